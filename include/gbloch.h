@@ -1,0 +1,192 @@
+/*
+ * gbloch.h -- C ABI of the grouped-isochromat Bloch simulator for gfx950.
+ *
+ * The library simulates K static isochromats under a block-structured pulse
+ * sequence, after H. Takeshima, "Fast Magnetic Resonance Simulation Using
+ * Combined Update with Grouped Isochromats":
+ *
+ *   - per raster step dt every isochromat's homogeneous state
+ *     (Mx, My, Mz, M0) is multiplied by U = D R (Eq. 2; Appendix A, Eq. A1
+ *     and Eq. A2): R rotates about u = B/|B| by theta = -gamma |B| dt with
+ *     B = (Re B1, Im B1, G . r + dB0) held constant over the step, D applies
+ *     T2 decay and T1 recovery toward M0;
+ *   - relaxation blocks (no RF, no ADC) use the closed forms Eq. (4), (5);
+ *   - ADC sample n adds Mx + i My of all isochromats at its raster boundary
+ *     (Eq. 6, one receive coil of unit sensitivity);
+ *   - GBS_PLAIN steps every isochromat individually (the conventional
+ *     method, Sec. 2.2); GBS_GROUPED uses the paper's combined update with
+ *     grouped isochromats (Sec. 2.3, 2.4): isochromats sharing
+ *     (r_a, T1, T2, dB0) share one combined transition T (Eq. 7) for an
+ *     a-only subsequence, and with-ADC subsequences evolve per-group sums
+ *     (Eq. 8-10) instead of every member.  Both modes give the same result up
+ *     to floating-point rounding.
+ *
+ * Units: metres, seconds, tesla, T/m, T*s/m; off-resonance in Hz
+ * (B_z gains df / (gamma/2pi)); gamma/2pi = 42.577478518 MHz/T.
+ *
+ * Memory: "device" pointers are HIP device memory of the context's device
+ * (e.g. torch CUDA tensors); "host" pointers are ordinary host memory.
+ * Every function returns GBS_OK (0) or a negative status; on failure
+ * gbs_last_error(ctx) holds a message.  A context is not thread-safe.
+ */
+#ifndef GBLOCH_H
+#define GBLOCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define GBS_OK 0
+#define GBS_E_INVALID (-1) /* bad argument: null pointer, K <= 0, T1/T2 <= 0 or NaN, bad block */
+#define GBS_E_STATE (-2)   /* call order: no phantom / sequence, groups missing or stale */
+#define GBS_E_HIP (-3)     /* a HIP runtime call or kernel launch failed */
+#define GBS_E_NOMEM (-4)   /* device or host allocation failed */
+
+/* ---- block types (Sec. 2.1, Fig. 1) ---------------------------------- */
+#define GBS_BLOCK_RF 1    /* with-RF subsequence: stepped, samples not allowed */
+#define GBS_BLOCK_ADC 2   /* with-ADC subsequence: stepped, n_samples >= 0 */
+#define GBS_BLOCK_RELAX 3 /* relaxation subsequence: closed form over tau with moment */
+
+/* ---- grouping axes (Sec. 2.4) ---------------------------------------- */
+#define GBS_AX_X 1u
+#define GBS_AX_Y 2u
+#define GBS_AX_Z 4u
+
+/* ---- simulation modes and flags -------------------------------------- */
+#define GBS_PLAIN 0
+#define GBS_GROUPED 1
+#define GBS_ASYNC 1u /* enqueue on the context stream and return; no final synchronize */
+
+/*
+ * One subsequence.  RF/ADC blocks cover raster steps
+ * [step_offset, step_offset + n_steps) of the waveform arrays; an ADC block's
+ * samples are entries [sample_offset, sample_offset + n_samples) of
+ * adc_idx (raster boundaries counted from the block start, 0..n_steps,
+ * non-decreasing) and of the output signal.  A RELAX block uses tau (s) and
+ * moment = int G dt (T*s/m) and ignores the step/sample fields.
+ */
+typedef struct gbs_block {
+    int32_t type;
+    int32_t n_samples;
+    int64_t step_offset;
+    int64_t n_steps;
+    int64_t sample_offset;
+    double tau;
+    double moment[3];
+} gbs_block;
+
+typedef struct gbs_info {
+    int64_t K;             /* isochromats of the current phantom (0 if none) */
+    int64_t n_blocks;      /* blocks of the current sequence */
+    int64_t total_steps;   /* raster steps in the waveform arrays */
+    int64_t total_samples; /* ADC samples = signal length */
+    int64_t stepped_steps; /* raster steps inside RF and ADC blocks */
+    int64_t n_groups[3];   /* groups per axis x, y, z; -1 when not built */
+    int32_t groups_valid;  /* 1 when groups match the current phantom */
+    int32_t device;
+} gbs_info;
+
+/* Filled by gbs_simulate when non-null.  Times come from HIP events. */
+typedef struct gbs_stats {
+    double ms_total;       /* whole simulate call on the device */
+    double ms_prepare;     /* grouped: combined transitions and map tables */
+    double ms_passes;      /* grouped: streaming passes over all isochromats */
+    double ms_adc_eval;    /* grouped: ADC samples from group sums (Eq. 8, 10) */
+    double ms_stepped;     /* plain stepping (PLAIN mode, or fallback blocks) */
+    int64_t n_passes;      /* grouped streaming passes (incl. emission-only) */
+    int64_t n_emit_only;   /* passes that only reduce group sums */
+    int64_t n_rf_grouped;  /* with-RF blocks applied as group transitions */
+    int64_t n_adc_grouped; /* with-ADC blocks evaluated from group sums */
+    int64_t n_fallback;    /* RF/ADC blocks stepped per isochromat */
+    int64_t n_distinct_rf; /* distinct (waveform, axis) combined transitions composed */
+    int64_t n_b1zero;      /* RF-typed blocks with B1 == 0 folded into closed forms */
+    double pass_bytes;     /* algorithmic HBM bytes of the streaming passes */
+    double pass_ms_max;    /* (reserved) */
+} gbs_stats;
+
+typedef struct gbs_ctx gbs_ctx;
+
+/*
+ * Create a context on HIP `device`; all work is enqueued on `stream`
+ * (a hipStream_t; NULL = the default stream).  *out receives the context.
+ * Errors: GBS_E_INVALID (out null, bad device), GBS_E_HIP.
+ */
+int gbs_create(gbs_ctx **out, int device, void *stream);
+
+/* Release the context and every device buffer it owns.  NULL is a no-op. */
+int gbs_destroy(gbs_ctx *ctx);
+
+/*
+ * Phantom: K isochromats as device float arrays of length K (Sec. 2.1,
+ * Eq. 1): position x, y, z (m), T1, T2 (s, > 0, may be +inf), off-resonance
+ * df_hz (Hz) and M0.  The context keeps these pointers (views, no copy) until
+ * the next gbs_set_phantom or gbs_destroy; the caller keeps them alive and
+ * unchanged.  Validates on the device (NaN, T <= 0 -> GBS_E_INVALID).
+ * Invalidates groups.
+ */
+int gbs_set_phantom(gbs_ctx *ctx, int64_t K, const float *x, const float *y, const float *z,
+                    const float *t1, const float *t2, const float *df_hz, const float *m0);
+
+/*
+ * Sequence (Sec. 2.1, Fig. 1): `blocks` (host, n_blocks entries) over a
+ * uniform raster `dt` (s).  Per-step waveforms are host arrays of length
+ * total_steps: rf_re, rf_im (B1 in T), gx, gy, gz (T/m); adc_idx is a host
+ * int32 array of length total_samples.  Everything is copied; the caller's
+ * arrays may be freed after the call.  Validation failures -> GBS_E_INVALID.
+ */
+int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, const float *rf_re,
+                     const float *rf_im, const float *gx, const float *gy, const float *gz,
+                     int64_t total_steps, const int32_t *adc_idx, int64_t total_samples, double dt);
+
+/*
+ * Group the isochromats once (Sec. 2.4, Fig. 2): for each requested axis a
+ * (GBS_AX_X | GBS_AX_Y | GBS_AX_Z) the key (r_a, T1, T2, dB0) is compared by
+ * exact bit pattern (-0 == +0); equal keys form one group, numbered densely
+ * in lexicographic key order.  GBS_GROUPED needs GBS_AX_X; blocks whose type
+ * needs an axis that was not built are stepped per isochromat.  The context
+ * stores a copy of the phantom in group-sorted order (about 13 float/int32
+ * words per isochromat).  Synchronizes the stream.
+ * Errors: GBS_E_STATE (no phantom), GBS_E_INVALID (axes == 0), GBS_E_NOMEM.
+ */
+int gbs_build_groups(gbs_ctx *ctx, uint32_t axes);
+
+/*
+ * Run the sequence on the phantom.  mode = GBS_PLAIN or GBS_GROUPED.
+ * m_init: device float[3*K] SoA (Mx, My, Mz) or NULL for (0, 0, M0).
+ * m_out: device float[3*K] SoA final magnetization (may alias m_init).
+ * sig_out: device double[2*total_samples], interleaved (re, im), Eq. (6).
+ * stats: host, nullable.  Without GBS_ASYNC the call synchronizes the stream.
+ * Errors: GBS_E_STATE (no phantom/sequence; GROUPED without valid X groups),
+ * GBS_E_INVALID (null outputs, bad mode), GBS_E_NOMEM, GBS_E_HIP.
+ */
+int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float *m_init, float *m_out,
+                 double *sig_out, gbs_stats *stats);
+
+/* Sizes and group counts of the current state. */
+int gbs_get_info(gbs_ctx *ctx, gbs_info *info);
+
+/* Last error message of ctx (never NULL); gbs_strerror maps a status code. */
+const char *gbs_last_error(const gbs_ctx *ctx);
+const char *gbs_strerror(int status);
+
+/*
+ * Host-only planning summary (no device needed): classifies the blocks of a
+ * sequence (Sec. 2.1, 2.4, 3.1) and counts what GBS_GROUPED would run when
+ * groups for `axes` exist.  out[0..7] = grouped RF blocks, grouped ADC
+ * blocks, fallback blocks, B1 == 0 RF blocks, streaming passes,
+ * emission-only passes, distinct combined transitions, relaxation blocks.
+ * Same validation as gbs_set_sequence.
+ */
+int gbs_plan_summary(const gbs_block *blocks, int64_t n_blocks, const float *rf_re,
+                     const float *rf_im, const float *gx, const float *gy, const float *gz,
+                     int64_t total_steps, const int32_t *adc_idx, int64_t total_samples, double dt,
+                     uint32_t axes, int64_t out[8]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GBLOCH_H */

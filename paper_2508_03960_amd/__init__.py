@@ -1,0 +1,207 @@
+"""Python binding of libgbloch (include/gbloch.h): grouped-isochromat Bloch
+simulation on gfx950.
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of ``libgbloch.so``.  PyTorch provides device memory and the stream.
+The library must be built (``python -m paper_2508_03960_amd.build``); there is
+no CPU fallback, and importing this package fails loudly without it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgbloch.so")
+
+GBS_OK, GBS_E_INVALID, GBS_E_STATE, GBS_E_HIP, GBS_E_NOMEM = 0, -1, -2, -3, -4
+GBS_BLOCK_RF, GBS_BLOCK_ADC, GBS_BLOCK_RELAX = 1, 2, 3
+GBS_AX_X, GBS_AX_Y, GBS_AX_Z = 1, 2, 4
+GBS_PLAIN, GBS_GROUPED = 0, 1
+GBS_ASYNC = 1
+
+EXPORTED = ("gbs_create", "gbs_destroy", "gbs_set_phantom", "gbs_set_sequence", "gbs_build_groups",
+            "gbs_simulate", "gbs_get_info", "gbs_last_error", "gbs_strerror", "gbs_plan_summary")
+
+
+class gbs_block(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("n_samples", ctypes.c_int32),
+                ("step_offset", ctypes.c_int64), ("n_steps", ctypes.c_int64),
+                ("sample_offset", ctypes.c_int64), ("tau", ctypes.c_double),
+                ("moment", ctypes.c_double * 3)]
+
+
+class gbs_info(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int64), ("n_blocks", ctypes.c_int64), ("total_steps", ctypes.c_int64),
+                ("total_samples", ctypes.c_int64), ("stepped_steps", ctypes.c_int64),
+                ("n_groups", ctypes.c_int64 * 3), ("groups_valid", ctypes.c_int32),
+                ("device", ctypes.c_int32)]
+
+
+class gbs_stats(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_double), ("ms_prepare", ctypes.c_double),
+                ("ms_passes", ctypes.c_double), ("ms_adc_eval", ctypes.c_double),
+                ("ms_stepped", ctypes.c_double), ("n_passes", ctypes.c_int64),
+                ("n_emit_only", ctypes.c_int64), ("n_rf_grouped", ctypes.c_int64),
+                ("n_adc_grouped", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
+                ("n_distinct_rf", ctypes.c_int64), ("n_b1zero", ctypes.c_int64),
+                ("pass_bytes", ctypes.c_double), ("pass_ms_max", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2508_03960_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I64, I32, U32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
+    sig = {
+        "gbs_create": ([ctypes.POINTER(P), ctypes.c_int, P], ctypes.c_int),
+        "gbs_destroy": ([P], ctypes.c_int),
+        "gbs_set_phantom": ([P, I64] + [P] * 7, ctypes.c_int),
+        "gbs_set_sequence": ([P, P, I64, P, P, P, P, P, I64, P, I64, D], ctypes.c_int),
+        "gbs_build_groups": ([P, U32], ctypes.c_int),
+        "gbs_simulate": ([P, ctypes.c_int, U32, P, P, P, P], ctypes.c_int),
+        "gbs_get_info": ([P, P], ctypes.c_int),
+        "gbs_last_error": ([P], ctypes.c_char_p),
+        "gbs_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "gbs_plan_summary": ([P, I64, P, P, P, P, P, I64, P, I64, D, U32, P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+class GbsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{lib.gbs_strerror(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    import numpy as np
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def sequence_blocks(seq):
+    """gbs_block array for a synth.Sequence-like object (host)."""
+    nb = seq.n_blocks
+    arr = (gbs_block * max(nb, 1))()
+    for b in range(nb):
+        k = arr[b]
+        k.type = int(seq.btype[b])
+        k.n_samples = int(seq.n_samples[b])
+        k.step_offset = int(seq.step_offset[b])
+        k.n_steps = int(seq.n_steps[b])
+        k.sample_offset = int(seq.sample_offset[b])
+        k.tau = float(seq.tau[b])
+        for i in range(3):
+            k.moment[i] = float(seq.moment[b][i])
+    return arr
+
+
+def gbs_plan_summary(seq, axes=GBS_AX_X | GBS_AX_Y | GBS_AX_Z):
+    """Host-only classification counts (see gbloch.h)."""
+    import numpy as np
+    blocks = sequence_blocks(seq)
+    w = [_host(a, np.float32) for a in (seq.rf_re, seq.rf_im, seq.gx, seq.gy, seq.gz)]
+    adc = _host(seq.adc_idx, np.int32)
+    out = (ctypes.c_int64 * 8)()
+    rc = lib.gbs_plan_summary(blocks, seq.n_blocks, *(a.ctypes.data for a in w), seq.total_steps,
+                              adc.ctypes.data, seq.total_samples, float(seq.dt), axes, out)
+    if rc != GBS_OK:
+        raise GbsError(rc, "gbs_plan_summary rejected the sequence")
+    keys = ("rf_grouped", "adc_grouped", "fallback", "b1zero", "passes", "emit_only", "distinct_rf", "relax")
+    return dict(zip(keys, list(out)))
+
+
+class Simulator:
+    """One gbs context on a CUDA (HIP) device; thin wrapper over the C ABI."""
+
+    def __init__(self, device=0, stream=None):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = lib.gbs_create(ctypes.byref(h), self.device.index or 0, ctypes.c_void_p(stream.cuda_stream))
+        if rc != GBS_OK:
+            raise GbsError(rc, "gbs_create failed")
+        self._h = h
+        self._keep = ()
+        self.K = 0
+        self.n_samples = 0
+
+    def _check(self, rc):
+        if rc != GBS_OK:
+            raise GbsError(rc, lib.gbs_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.gbs_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def gbs_set_phantom(self, x, y, z, t1, t2, df_hz, m0):
+        ts = [t.to(self.device, torch.float32).contiguous() for t in (x, y, z, t1, t2, df_hz, m0)]
+        self._keep = ts  # the library keeps views of these tensors
+        self._check(lib.gbs_set_phantom(self._h, ts[0].numel(), *(_ptr(t) for t in ts)))
+        self.K = ts[0].numel()
+
+    def set_phantom(self, ph):
+        """From a synth.Phantom (host numpy arrays)."""
+        self.gbs_set_phantom(*(torch.from_numpy(a) for a in ph.arrays()))
+
+    def gbs_set_sequence(self, seq):
+        import numpy as np
+        blocks = sequence_blocks(seq)
+        w = [_host(a, np.float32) for a in (seq.rf_re, seq.rf_im, seq.gx, seq.gy, seq.gz)]
+        adc = _host(seq.adc_idx, np.int32)
+        self._check(lib.gbs_set_sequence(self._h, blocks, seq.n_blocks, *(a.ctypes.data for a in w),
+                                         seq.total_steps, adc.ctypes.data, seq.total_samples, float(seq.dt)))
+        self.n_samples = seq.total_samples
+
+    set_sequence = gbs_set_sequence
+
+    def gbs_build_groups(self, axes=GBS_AX_X | GBS_AX_Y | GBS_AX_Z):
+        self._check(lib.gbs_build_groups(self._h, axes))
+
+    build_groups = gbs_build_groups
+
+    def gbs_get_info(self):
+        info = gbs_info()
+        self._check(lib.gbs_get_info(self._h, ctypes.byref(info)))
+        return {"K": info.K, "n_blocks": info.n_blocks, "total_steps": info.total_steps,
+                "total_samples": info.total_samples, "stepped_steps": info.stepped_steps,
+                "n_groups": list(info.n_groups), "groups_valid": bool(info.groups_valid)}
+
+    info = gbs_get_info
+
+    def gbs_simulate(self, mode=GBS_GROUPED, m_init=None, m_out=None, sig_out=None, flags=0,
+                     stats=False):
+        """Returns (M (3, K) float32 device tensor, signal complex128 device tensor[, stats])."""
+        if m_out is None:
+            m_out = torch.empty(3, self.K, device=self.device, dtype=torch.float32)
+        if sig_out is None:
+            sig_out = torch.empty(max(self.n_samples, 1), 2, device=self.device, dtype=torch.float64)
+        mi = None if m_init is None else m_init.to(self.device, torch.float32).contiguous()
+        st = gbs_stats() if stats else None
+        self._check(lib.gbs_simulate(self._h, mode, flags, _ptr(mi), _ptr(m_out), _ptr(sig_out),
+                                     ctypes.byref(st) if st is not None else None))
+        sig = torch.view_as_complex(sig_out)[: self.n_samples]
+        return (m_out, sig, st.as_dict()) if stats else (m_out, sig)
+
+    simulate = gbs_simulate

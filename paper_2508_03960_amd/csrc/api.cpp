@@ -1,0 +1,653 @@
+// C ABI of the grouped-isochromat Bloch simulator (include/gbloch.h).
+//
+// The context owns: a device copy of the sequence waveform, and after
+// gbs_build_groups a group-sorted copy of the phantom (sorted by the x-group
+// key, so every x-group is one contiguous run), per-axis group ids and group
+// tables, and the magnetization state in that order.  Per simulate call it
+// owns the combined-transition tables, the map tables, the group sums and the
+// per-sample tables.  The caller owns the phantom arrays and the outputs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "consts.hpp"
+#include "gbloch.h"
+#include "groups.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace gbs;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t n) {
+        if (n == 0) n = 256;
+        if (p && n <= cap) return hipSuccess;
+        release();
+        hipError_t e = hipMalloc(&p, n);
+        if (e == hipSuccess) cap = n;
+        else p = nullptr;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <class T>
+    T *as() const {
+        return (T *)p;
+    }
+};
+
+}  // namespace
+
+struct gbs_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // phantom (caller-owned views, natural order)
+    int64_t K = 0;
+    PhantomPtrs ph{};
+    bool has_ph = false;
+    // sequence
+    HostSeq seq;
+    bool has_seq = false;
+    std::vector<BlockClass> cls;
+    DevBuf d_wave, d_adc;
+    // groups and the group-sorted copy
+    uint32_t axes = 0;
+    bool groups_valid = false;
+    int64_t ng[3] = {-1, -1, -1};
+    int64_t Kpad = 0;
+    DevBuf perm, xi, yi, zi, t1i, t2i, dfi, m0i, gid[3], gtab[3], gcount[3], ms[3];
+    // per-simulate buffers
+    DevBuf tabs, gsum, partial, jobs, samp, flag;
+    std::vector<char> host_jobs;  // kept alive until the next call
+    std::vector<double2> host_samp;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+
+static int fail(gbs_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? GBS_E_NOMEM : GBS_E_HIP,              \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+    } while (0)
+
+#define ALLOC(buf, bytes)                                                                      \
+    do {                                                                                       \
+        hipError_t e_ = (buf).ensure(bytes);                                                   \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(ctx, GBS_E_NOMEM, std::string("device allocation of ") +               \
+                                              std::to_string((size_t)(bytes)) + " bytes failed"); \
+    } while (0)
+
+static const char *status_text(int s) {
+    switch (s) {
+        case GBS_OK: return "ok";
+        case GBS_E_INVALID: return "invalid argument";
+        case GBS_E_STATE: return "invalid call order or stale state";
+        case GBS_E_HIP: return "HIP runtime error";
+        case GBS_E_NOMEM: return "out of memory";
+        default: return "unknown status";
+    }
+}
+
+extern "C" {
+
+const char *gbs_strerror(int status) { return status_text(status); }
+
+const char *gbs_last_error(const gbs_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int gbs_create(gbs_ctx **out, int device, void *stream) {
+    if (!out) return GBS_E_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return GBS_E_INVALID;
+    if (hipSetDevice(device) != hipSuccess) return GBS_E_HIP;
+    gbs_ctx *ctx = new (std::nothrow) gbs_ctx();
+    if (!ctx) return GBS_E_NOMEM;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)stream;
+    for (auto &e : ctx->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            gbs_destroy(ctx);
+            return GBS_E_HIP;
+        }
+    }
+    *out = ctx;
+    return GBS_OK;
+}
+
+int gbs_destroy(gbs_ctx *ctx) {
+    if (!ctx) return GBS_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    DevBuf *bufs[] = {&ctx->d_wave, &ctx->d_adc, &ctx->perm, &ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i,
+                      &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->tabs, &ctx->gsum, &ctx->partial, &ctx->jobs,
+                      &ctx->samp, &ctx->flag};
+    for (DevBuf *b : bufs) b->release();
+    for (int a = 0; a < 3; ++a) {
+        ctx->gid[a].release();
+        ctx->gtab[a].release();
+        ctx->gcount[a].release();
+        ctx->ms[a].release();
+    }
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+    return GBS_OK;
+}
+
+int gbs_set_phantom(gbs_ctx *ctx, int64_t K, const float *x, const float *y, const float *z,
+                    const float *t1, const float *t2, const float *df_hz, const float *m0) {
+    if (!ctx) return GBS_E_INVALID;
+    if (K <= 0 || K > (int64_t)INT32_MAX - 4096)
+        return fail(ctx, GBS_E_INVALID, "K must be in [1, 2^31 - 4096]");
+    if (!x || !y || !z || !t1 || !t2 || !df_hz || !m0) return fail(ctx, GBS_E_INVALID, "null phantom array");
+    HIPCHK(hipSetDevice(ctx->device));
+    ctx->has_ph = false;
+    ctx->groups_valid = false;
+    PhantomPtrs ph{x, y, z, t1, t2, df_hz, m0};
+    ALLOC(ctx->flag, 256);
+    HIPCHK(launch_fill_f64(ctx->flag.as<double>(), 1, ctx->stream));
+    HIPCHK(launch_validate_phantom(K, ph, ctx->flag.as<int>(), ctx->stream));
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, ctx->flag.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (bad) return fail(ctx, GBS_E_INVALID, "phantom has NaN/inf values or T1/T2 <= 0");
+    ctx->K = K;
+    ctx->ph = ph;
+    ctx->has_ph = true;
+    return GBS_OK;
+}
+
+int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, const float *rf_re,
+                     const float *rf_im, const float *gx, const float *gy, const float *gz,
+                     int64_t total_steps, const int32_t *adc_idx, int64_t total_samples, double dt) {
+    if (!ctx) return GBS_E_INVALID;
+    std::string err;
+    int rc = validate_sequence(blocks, n_blocks, total_steps, adc_idx, total_samples, dt, err);
+    if (rc != GBS_OK) return fail(ctx, rc, err);
+    if (total_steps > 0 && (!rf_re || !rf_im || !gx || !gy || !gz))
+        return fail(ctx, GBS_E_INVALID, "null waveform array");
+    for (int64_t j = 0; j < total_steps; ++j)
+        if (!std::isfinite(rf_re[j]) || !std::isfinite(rf_im[j]) || !std::isfinite(gx[j]) ||
+            !std::isfinite(gy[j]) || !std::isfinite(gz[j]))
+            return fail(ctx, GBS_E_INVALID, "non-finite waveform sample at step " + std::to_string(j));
+    HIPCHK(hipSetDevice(ctx->device));
+    ctx->has_seq = false;
+    copy_sequence(ctx->seq, blocks, n_blocks, rf_re, rf_im, gx, gy, gz, total_steps, adc_idx, total_samples, dt);
+    ctx->cls = classify(ctx->seq);
+    std::vector<StepW> w((size_t)total_steps);
+    for (int64_t j = 0; j < total_steps; ++j) {
+        const double re = rf_re[j], im = rf_im[j];
+        w[j] = StepW{rf_re[j], rf_im[j], (float)(re * re + im * im), gx[j], gy[j], gz[j], 0.f, 0.f};
+    }
+    ALLOC(ctx->d_wave, sizeof(StepW) * (size_t)total_steps);
+    ALLOC(ctx->d_adc, sizeof(int32_t) * (size_t)total_samples);
+    if (total_steps)
+        HIPCHK(hipMemcpy(ctx->d_wave.p, w.data(), sizeof(StepW) * (size_t)total_steps, hipMemcpyHostToDevice));
+    if (total_samples)
+        HIPCHK(hipMemcpy(ctx->d_adc.p, adc_idx, sizeof(int32_t) * (size_t)total_samples, hipMemcpyHostToDevice));
+    ctx->has_seq = true;
+    return GBS_OK;
+}
+
+int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
+    if (!ctx) return GBS_E_INVALID;
+    if (!ctx->has_ph) return fail(ctx, GBS_E_STATE, "gbs_build_groups before gbs_set_phantom");
+    if (!(axes & GBS_AX_X) || (axes & ~7u)) return fail(ctx, GBS_E_INVALID, "axes must include GBS_AX_X and only X|Y|Z");
+    HIPCHK(hipSetDevice(ctx->device));
+    ctx->groups_valid = false;
+    const int64_t K = ctx->K;
+    const int64_t Kpad = (K + 1023) / 1024 * 1024;
+    const size_t scratch_bytes = group_scratch_bytes(K) + 4096;
+    DevBuf scratch, gid_nat, order;
+    auto cleanup = [&]() {
+        scratch.release();
+        gid_nat.release();
+        order.release();
+    };
+    if (scratch.ensure(scratch_bytes) != hipSuccess || gid_nat.ensure(4 * K) != hipSuccess ||
+        order.ensure(4 * K) != hipSuccess) {
+        cleanup();
+        return fail(ctx, GBS_E_NOMEM, "grouping scratch allocation failed");
+    }
+    const float *coord[3] = {ctx->ph.x, ctx->ph.y, ctx->ph.z};
+    ALLOC(ctx->perm, 4 * Kpad);
+    for (int a = 0; a < 3; ++a) {
+        ctx->ng[a] = -1;
+        if (!(axes & (1u << a))) {
+            ctx->gid[a].release();
+            ctx->gtab[a].release();
+            ctx->gcount[a].release();
+            continue;
+        }
+        ALLOC(ctx->gtab[a], sizeof(float4) * K);
+        ALLOC(ctx->gcount[a], sizeof(int32_t) * K);
+        ALLOC(ctx->gid[a], sizeof(int32_t) * Kpad);
+        int32_t *ord = a == 0 ? ctx->perm.as<int32_t>() : order.as<int32_t>();
+        int64_t G = 0;
+        hipError_t e = group_axis(K, coord[a], ctx->ph.t1, ctx->ph.t2, ctx->ph.df, scratch.p, scratch_bytes,
+                                  gid_nat.as<int32_t>(), ctx->gtab[a].as<float4>(),
+                                  ctx->gcount[a].as<int32_t>(), ord, &G, ctx->stream);
+        if (e != hipSuccess) {
+            cleanup();
+            return fail(ctx, GBS_E_HIP, std::string("grouping failed: ") + hipGetErrorString(e));
+        }
+        ctx->ng[a] = G;
+        // ids in group-sorted order (the order comes from the x axis, built first)
+        e = launch_gather_i32(K, Kpad, ctx->perm.as<int32_t>(), gid_nat.as<int32_t>(), ctx->gid[a].as<int32_t>(),
+                              ctx->stream);
+        if (e != hipSuccess) {
+            cleanup();
+            return fail(ctx, GBS_E_HIP, hipGetErrorString(e));
+        }
+    }
+    DevBuf *dst[7] = {&ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i, &ctx->t2i, &ctx->dfi, &ctx->m0i};
+    const float *src[7] = {ctx->ph.x, ctx->ph.y, ctx->ph.z, ctx->ph.t1, ctx->ph.t2, ctx->ph.df, ctx->ph.m0};
+    for (int i = 0; i < 7; ++i) {
+        ALLOC(*dst[i], 4 * Kpad);
+        HIPCHK(launch_gather_f32(K, Kpad, ctx->perm.as<int32_t>(), src[i], dst[i]->as<float>(), ctx->stream));
+    }
+    for (int a = 0; a < 3; ++a) ALLOC(ctx->ms[a], 4 * Kpad);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    cleanup();
+    ctx->axes = axes;
+    ctx->Kpad = Kpad;
+    ctx->groups_valid = true;
+    return GBS_OK;
+}
+
+int gbs_get_info(gbs_ctx *ctx, gbs_info *info) {
+    if (!ctx || !info) return GBS_E_INVALID;
+    std::memset(info, 0, sizeof(*info));
+    info->K = ctx->has_ph ? ctx->K : 0;
+    info->n_blocks = ctx->has_seq ? (int64_t)ctx->seq.blocks.size() : 0;
+    info->total_steps = ctx->has_seq ? ctx->seq.total_steps : 0;
+    info->total_samples = ctx->has_seq ? ctx->seq.total_samples : 0;
+    info->stepped_steps = ctx->has_seq ? ctx->seq.stepped_steps : 0;
+    for (int a = 0; a < 3; ++a) info->n_groups[a] = ctx->groups_valid ? ctx->ng[a] : -1;
+    info->groups_valid = ctx->groups_valid ? 1 : 0;
+    info->device = ctx->device;
+    return GBS_OK;
+}
+
+int gbs_plan_summary(const gbs_block *blocks, int64_t n_blocks, const float *rf_re, const float *rf_im,
+                     const float *gx, const float *gy, const float *gz, int64_t total_steps,
+                     const int32_t *adc_idx, int64_t total_samples, double dt, uint32_t axes, int64_t out[8]) {
+    if (!out) return GBS_E_INVALID;
+    std::string err;
+    int rc = validate_sequence(blocks, n_blocks, total_steps, adc_idx, total_samples, dt, err);
+    if (rc != GBS_OK) return rc;
+    if (total_steps > 0 && (!rf_re || !rf_im || !gx || !gy || !gz)) return GBS_E_INVALID;
+    HostSeq s;
+    copy_sequence(s, blocks, n_blocks, rf_re, rf_im, gx, gy, gz, total_steps, adc_idx, total_samples, dt);
+    Plan p = plan_grouped(s, classify(s), axes);
+    out[0] = p.n_rf_grouped;
+    out[1] = p.n_adc_grouped;
+    out[2] = p.n_fallback;
+    out[3] = p.n_b1zero;
+    out[4] = p.n_passes + (p.final_pass ? 1 : 0);
+    out[5] = p.n_emit_only;
+    out[6] = (int64_t)p.rf.size();
+    out[7] = p.n_relax;
+    return GBS_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------- simulate
+namespace {
+
+PlainArgs step_args(gbs_ctx *ctx, const StepOp &op, const PhantomPtrs &ph, int64_t K, const float *in_x,
+                    const float *in_y, const float *in_z, float *ox, float *oy, float *oz) {
+    PlainArgs a{};
+    a.K = K;
+    a.ph = ph;
+    a.min_x = in_x;
+    a.min_y = in_y;
+    a.min_z = in_z;
+    a.mout_x = ox;
+    a.mout_y = oy;
+    a.mout_z = oz;
+    a.dt = ctx->seq.dt;
+    a.gdt = (float)(kTwoPi * kGammaBar * ctx->seq.dt);
+    a.has_pre = op.has_pre ? 1 : 0;
+    a.pre_tau = op.pre.tau;
+    for (int i = 0; i < 3; ++i) a.pre_cyc[i] = kGammaBar * op.pre.m[i];
+    if (op.block >= 0) {
+        const gbs_block &b = ctx->seq.blocks[op.block];
+        a.wave = ctx->d_wave.as<StepW>() + b.step_offset + op.step_lo;
+        a.n_steps = (int32_t)(op.step_hi - op.step_lo);
+        a.sidx = ctx->d_adc.as<int32_t>() + b.sample_offset + op.sample_lo;
+        a.step_base = (int32_t)op.step_lo;
+        a.n_samples = op.sample_hi - op.sample_lo;
+    } else {
+        a.wave = ctx->d_wave.as<StepW>();
+        a.n_steps = 0;
+        a.sidx = ctx->d_adc.as<int32_t>();
+        a.step_base = 0;
+        a.n_samples = 0;
+    }
+    a.partial = ctx->partial.as<double2>();
+    return a;
+}
+
+}  // namespace
+
+static int run_plain(gbs_ctx *ctx, const float *m_init, float *m_out, double *sig_out, gbs_stats *st) {
+    const int64_t K = ctx->K;
+    Plan plan = plan_plain(ctx->seq);
+    if (plan.ops.empty()) {
+        Op op;
+        op.kind = 1;
+        op.step = StepOp{};
+        plan.ops.push_back(op);
+    }
+    const int grid = plain_grid(K);
+    ALLOC(ctx->partial, sizeof(double2) * (size_t)grid * kMaxSamplesPerLaunch);
+    float *ox = m_out, *oy = m_out + K, *oz = m_out + 2 * K;
+    bool first = true;
+    for (const Op &op : plan.ops) {
+        const float *ix = first && m_init ? m_init : (first ? nullptr : ox);
+        const float *iy = first && m_init ? m_init + K : (first ? nullptr : oy);
+        const float *iz = first && m_init ? m_init + 2 * K : (first ? nullptr : oz);
+        PlainArgs a = step_args(ctx, op.step, ctx->ph, K, ix, iy, iz, ox, oy, oz);
+        const bool b1 = op.step.block >= 0 && ctx->cls[op.step.block].has_b1;
+        HIPCHK(launch_plain(a, b1, grid, ctx->stream));
+        if (a.n_samples > 0) {
+            const gbs_block &b = ctx->seq.blocks[op.step.block];
+            HIPCHK(launch_plain_finalize(ctx->partial.as<double2>(), grid, a.n_samples,
+                                         sig_out + 2 * (b.sample_offset + op.step.sample_lo), ctx->stream));
+        }
+        first = false;
+    }
+    if (st) st->n_fallback = 0;
+    return GBS_OK;
+}
+
+namespace {
+
+// Device pointers of the tables of one B1 = 0 map.
+struct MapAlloc {
+    size_t x_off = 0, z_off = 0;
+    bool has_z = false;
+};
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+static double pass_bytes(const PassArgs &a) {
+    // algorithmic HBM bytes per isochromat of one pass (mirrors k_pass's loads and stores)
+    const bool need_mz = a.write_m && (a.has_pre || a.rf_axis >= 0);
+    const bool need_gx = a.has_pre || a.emit_axis >= 0 || a.rf_axis == 0;
+    const bool need_gz = a.rf_axis == 2 || a.emit_axis == 2 || (a.has_pre && a.pre.ztab) ||
+                         (a.emit_axis >= 0 && a.emit.ztab);
+    const bool need_gy = a.rf_axis == 1 || a.emit_axis == 1;
+    const bool need_y = (a.has_pre && a.pre.cy != 0.0) || (a.emit_axis >= 0 && a.emit.cy != 0.0);
+    const bool need_z = (a.has_pre && a.pre.cz != 0.0) || (a.emit_axis >= 0 && a.emit.cz != 0.0);
+    double b = 8.0;  // Mx, My read
+    if (need_mz) b += 8.0;
+    if (a.write_m) b += need_mz ? 12.0 : 8.0;
+    b += 4.0 * (need_gx + need_gy + need_gz + need_y + need_z);
+    return b;
+}
+
+static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *sig_out, gbs_stats *st) {
+    const int64_t K = ctx->K;
+    const HostSeq &s = ctx->seq;
+    Plan plan = plan_grouped(s, ctx->cls, ctx->axes);
+    const bool zbuilt = (ctx->axes & GBS_AX_Z) != 0;
+    const int64_t Gx = ctx->ng[0], Gz = zbuilt ? ctx->ng[2] : 0;
+
+    // ---- arena layout -------------------------------------------------------
+    size_t off = 0;
+    std::vector<size_t> rf_off(plan.rf.size());
+    int64_t max_rf_groups = 0;
+    for (size_t i = 0; i < plan.rf.size(); ++i) {
+        rf_off[i] = off;
+        const int64_t G = ctx->ng[plan.rf[i].axis];
+        max_rf_groups = std::max(max_rf_groups, G);
+        off = align256(off + sizeof(float4) * 3 * (size_t)G);
+    }
+    std::vector<TabJob> tjobs;
+    auto alloc_map = [&](const Map &m) {
+        MapAlloc r;
+        r.x_off = off;
+        off = align256(off + sizeof(float4) * (size_t)Gx);
+        tjobs.push_back(TabJob{0, (int32_t)Gx, m.tau, kGammaBar * m.m[0], (void *)r.x_off});
+        if (zbuilt && m.m[2] != 0.0) {
+            r.has_z = true;
+            r.z_off = off;
+            off = align256(off + sizeof(float2) * (size_t)Gz);
+            tjobs.push_back(TabJob{1, (int32_t)Gz, 0.0, kGammaBar * m.m[2], (void *)r.z_off});
+        }
+        return r;
+    };
+    std::vector<MapAlloc> pre_tab(plan.ops.size()), emit_tab(plan.ops.size());
+    for (size_t i = 0; i < plan.ops.size(); ++i) {
+        const Op &op = plan.ops[i];
+        if (op.kind != 0) continue;
+        if (op.pass.has_pre) pre_tab[i] = alloc_map(op.pass.pre);
+        if (op.pass.emit_axis >= 0) emit_tab[i] = alloc_map(op.pass.emit);
+    }
+    MapAlloc final_tab;
+    if (plan.final_pass) final_tab = alloc_map(plan.final_map);
+    const size_t tab_bytes = off;
+
+    size_t goff = 0;
+    std::vector<size_t> gsum_off(plan.adc.size()), samp_off(plan.adc.size());
+    size_t soff = 0;
+    int max_adc_groups = 0, max_adc_samples = 0;
+    for (size_t i = 0; i < plan.adc.size(); ++i) {
+        const AdcJob &j = plan.adc[i];
+        gsum_off[i] = goff;
+        goff += (size_t)ctx->ng[j.axis];
+        samp_off[i] = soff;
+        soff += (size_t)s.blocks[j.block].n_samples;
+        max_adc_groups = std::max(max_adc_groups, (int)ctx->ng[j.axis]);
+        max_adc_samples = std::max(max_adc_samples, (int)s.blocks[j.block].n_samples);
+    }
+    ALLOC(ctx->tabs, tab_bytes);
+    ALLOC(ctx->gsum, sizeof(double2) * goff);
+    ALLOC(ctx->samp, sizeof(double2) * soff);
+    const int grid = plain_grid(K);
+    if (plan.n_fallback) ALLOC(ctx->partial, sizeof(double2) * (size_t)grid * kMaxSamplesPerLaunch);
+    char *tb = ctx->tabs.as<char>();
+    for (auto &t : tjobs) t.out = tb + (size_t)t.out;
+
+    // per-sample tables (tau_n, gamma_bar m_n) of the grouped with-ADC blocks (Eq. 10)
+    std::vector<double2> &hs = ctx->host_samp;
+    hs.assign(soff, double2{0.0, 0.0});
+    for (size_t i = 0; i < plan.adc.size(); ++i) {
+        const AdcJob &j = plan.adc[i];
+        const gbs_block &b = s.blocks[j.block];
+        const std::vector<float> &g = j.axis == 0 ? s.gx : j.axis == 1 ? s.gy : s.gz;
+        double m = 0.0;
+        int64_t step = 0;
+        for (int32_t n = 0; n < b.n_samples; ++n) {
+            const int32_t tgt = s.adc_idx[b.sample_offset + n];
+            for (; step < tgt; ++step) m += (double)g[b.step_offset + step] * s.dt;
+            hs[samp_off[i] + n] = double2{(double)tgt * s.dt, kGammaBar * m};
+        }
+    }
+
+    // job arrays: rf | tables | adc, one upload
+    std::vector<RfJobDev> rj(plan.rf.size());
+    for (size_t i = 0; i < plan.rf.size(); ++i) {
+        const RfJob &r = plan.rf[i];
+        rj[i] = RfJobDev{r.axis, (int32_t)r.n_steps, ctx->ng[r.axis], ctx->d_wave.as<StepW>() + r.step_offset,
+                         ctx->gtab[r.axis].as<float4>(), (float4 *)(tb + rf_off[i])};
+    }
+    std::vector<AdcJobDev> aj(plan.adc.size());
+    for (size_t i = 0; i < plan.adc.size(); ++i) {
+        const AdcJob &j = plan.adc[i];
+        const gbs_block &b = s.blocks[j.block];
+        aj[i] = AdcJobDev{b.n_samples, (int32_t)ctx->ng[j.axis], ctx->gsum.as<double2>() + gsum_off[i],
+                          ctx->gtab[j.axis].as<float4>(), ctx->samp.as<double2>() + samp_off[i],
+                          sig_out + 2 * b.sample_offset};
+    }
+    const size_t o_rf = 0, o_tab = align256(sizeof(RfJobDev) * rj.size());
+    const size_t o_adc = o_tab + align256(sizeof(TabJob) * tjobs.size());
+    const size_t jbytes = o_adc + sizeof(AdcJobDev) * aj.size();
+    ctx->host_jobs.assign(jbytes, 0);
+    if (!rj.empty()) std::memcpy(ctx->host_jobs.data() + o_rf, rj.data(), sizeof(RfJobDev) * rj.size());
+    if (!tjobs.empty()) std::memcpy(ctx->host_jobs.data() + o_tab, tjobs.data(), sizeof(TabJob) * tjobs.size());
+    if (!aj.empty()) std::memcpy(ctx->host_jobs.data() + o_adc, aj.data(), sizeof(AdcJobDev) * aj.size());
+    ALLOC(ctx->jobs, jbytes);
+    HIPCHK(hipMemcpyAsync(ctx->jobs.p, ctx->host_jobs.data(), jbytes, hipMemcpyHostToDevice, ctx->stream));
+    if (soff)
+        HIPCHK(hipMemcpyAsync(ctx->samp.p, hs.data(), sizeof(double2) * soff, hipMemcpyHostToDevice, ctx->stream));
+    char *jb = ctx->jobs.as<char>();
+
+    // ---- prepare: combined transitions (Eq. 7) and map tables --------------
+    HIPCHK(launch_fill_f64((double *)ctx->gsum.p, 2 * (int64_t)goff, ctx->stream));
+    HIPCHK(launch_compose((const RfJobDev *)(jb + o_rf), (int)rj.size(), max_rf_groups, s.dt, ctx->stream));
+    int64_t max_tab = std::max<int64_t>(Gx, Gz);
+    HIPCHK(launch_tables((const TabJob *)(jb + o_tab), (int)tjobs.size(), (int)max_tab,
+                         ctx->gtab[0].as<float4>(), zbuilt ? ctx->gtab[2].as<float4>() : nullptr, ctx->stream));
+    if (st) HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
+
+    // ---- streaming passes ---------------------------------------------------
+    float *mx = ctx->ms[0].as<float>(), *my = ctx->ms[1].as<float>(), *mz = ctx->ms[2].as<float>();
+    HIPCHK(launch_init_state(K, ctx->Kpad, ctx->perm.as<int32_t>(), m_init, m_init ? m_init + K : nullptr,
+                             m_init ? m_init + 2 * K : nullptr, ctx->m0i.as<float>(), mx, my, mz, ctx->stream));
+    auto map_tabs = [&](const Map &m, const MapAlloc &al) {
+        MapTabs t{};
+        t.xtab = (const float4 *)(tb + al.x_off);
+        t.ztab = al.has_z ? (const float2 *)(tb + al.z_off) : nullptr;
+        t.cy = kGammaBar * m.m[1];
+        t.cz = (!zbuilt) ? kGammaBar * m.m[2] : 0.0;
+        return t;
+    };
+    PassArgs base{};
+    base.n4 = (K + 3) / 4;
+    base.mx = (float4 *)mx;
+    base.my = (float4 *)my;
+    base.mz = (float4 *)mz;
+    base.m0 = ctx->m0i.as<float4>();
+    base.gid_x = ctx->gid[0].as<int4>();
+    base.gid_y = ctx->gid[1].as<int4>();
+    base.gid_z = ctx->gid[2].as<int4>();
+    base.yv = ctx->yi.as<float4>();
+    base.zv = ctx->zi.as<float4>();
+    base.rf_axis = -1;
+    base.emit_axis = -1;
+    const PhantomPtrs iph{ctx->xi.as<float>(), ctx->yi.as<float>(), ctx->zi.as<float>(), ctx->t1i.as<float>(),
+                          ctx->t2i.as<float>(), ctx->dfi.as<float>(), ctx->m0i.as<float>()};
+    double bytes = 0.0;
+    for (size_t i = 0; i < plan.ops.size(); ++i) {
+        const Op &op = plan.ops[i];
+        if (op.kind == 0) {
+            PassArgs a = base;
+            a.has_pre = op.pass.has_pre ? 1 : 0;
+            if (op.pass.has_pre) a.pre = map_tabs(op.pass.pre, pre_tab[i]);
+            a.rf_axis = op.pass.rf_axis;
+            a.ttab = op.pass.rf_axis >= 0 ? (const float4 *)(tb + rf_off[op.pass.rf_id]) : nullptr;
+            a.write_m = op.pass.write_m ? 1 : 0;
+            a.emit_axis = op.pass.emit_axis;
+            if (op.pass.emit_axis >= 0) {
+                a.emit = map_tabs(op.pass.emit, emit_tab[i]);
+                a.gsum = ctx->gsum.as<double2>() + gsum_off[op.pass.adc_job];
+            }
+            bytes += pass_bytes(a) * (double)K;
+            HIPCHK(launch_pass(a, ctx->stream));
+        } else {
+            PlainArgs a = step_args(ctx, op.step, iph, K, mx, my, mz, mx, my, mz);
+            const bool b1 = op.step.block >= 0 && ctx->cls[op.step.block].has_b1;
+            HIPCHK(launch_plain(a, b1, grid, ctx->stream));
+            if (a.n_samples > 0) {
+                const gbs_block &b = s.blocks[op.step.block];
+                HIPCHK(launch_plain_finalize(ctx->partial.as<double2>(), grid, a.n_samples,
+                                             sig_out + 2 * (b.sample_offset + op.step.sample_lo), ctx->stream));
+            }
+        }
+    }
+    if (plan.final_pass) {
+        PassArgs a = base;
+        a.has_pre = 1;
+        a.pre = map_tabs(plan.final_map, final_tab);
+        a.write_m = 1;
+        bytes += pass_bytes(a) * (double)K;
+        HIPCHK(launch_pass(a, ctx->stream));
+    }
+    if (st) HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
+
+    // ---- ADC samples from the group sums (Eq. 8, Eq. 10) --------------------
+    HIPCHK(launch_adc_eval((const AdcJobDev *)(jb + o_adc), (int)aj.size(), max_adc_groups, max_adc_samples,
+                           ctx->stream));
+    if (st) HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
+    HIPCHK(launch_scatter_state(K, ctx->perm.as<int32_t>(), mx, my, mz, m_out, m_out + K, m_out + 2 * K,
+                                ctx->stream));
+    if (st) {
+        st->n_passes = plan.n_passes + (plan.final_pass ? 1 : 0);
+        st->n_emit_only = plan.n_emit_only;
+        st->n_rf_grouped = plan.n_rf_grouped;
+        st->n_adc_grouped = plan.n_adc_grouped;
+        st->n_fallback = plan.n_fallback;
+        st->n_distinct_rf = (int64_t)plan.rf.size();
+        st->n_b1zero = plan.n_b1zero;
+        st->pass_bytes = bytes;
+    }
+    return GBS_OK;
+}
+
+extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float *m_init, float *m_out,
+                            double *sig_out, gbs_stats *stats) {
+    if (!ctx) return GBS_E_INVALID;
+    if (!ctx->has_ph) return fail(ctx, GBS_E_STATE, "gbs_simulate before gbs_set_phantom");
+    if (!ctx->has_seq) return fail(ctx, GBS_E_STATE, "gbs_simulate before gbs_set_sequence");
+    if (mode != GBS_PLAIN && mode != GBS_GROUPED) return fail(ctx, GBS_E_INVALID, "mode must be GBS_PLAIN or GBS_GROUPED");
+    if (!m_out || (ctx->seq.total_samples > 0 && !sig_out)) return fail(ctx, GBS_E_INVALID, "null output");
+    if (mode == GBS_GROUPED && !ctx->groups_valid)
+        return fail(ctx, GBS_E_STATE, "GBS_GROUPED needs gbs_build_groups on the current phantom");
+    if (flags & ~GBS_ASYNC) return fail(ctx, GBS_E_INVALID, "unknown flags");
+    HIPCHK(hipSetDevice(ctx->device));
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        HIPCHK(hipEventRecord(ctx->ev[0], ctx->stream));
+    }
+    if (ctx->seq.total_samples > 0)
+        HIPCHK(launch_fill_f64(sig_out, 2 * ctx->seq.total_samples, ctx->stream));
+    int rc = mode == GBS_PLAIN ? run_plain(ctx, m_init, m_out, sig_out, stats)
+                               : run_grouped(ctx, m_init, m_out, sig_out, stats);
+    if (rc != GBS_OK) return rc;
+    if (stats) HIPCHK(hipEventRecord(ctx->ev[4], ctx->stream));
+    if (!(flags & GBS_ASYNC) || stats) {
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        HIPCHK(hipGetLastError());
+    }
+    if (stats) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[4]));
+        stats->ms_total = ms;
+        if (mode == GBS_PLAIN) {
+            stats->ms_stepped = ms;
+        } else {
+            HIPCHK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+            stats->ms_prepare = ms;
+            HIPCHK(hipEventElapsedTime(&ms, ctx->ev[1], ctx->ev[2]));
+            stats->ms_passes = ms;
+            HIPCHK(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
+            stats->ms_adc_eval = ms;
+        }
+    }
+    return GBS_OK;
+}

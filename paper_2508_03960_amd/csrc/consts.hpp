@@ -1,0 +1,10 @@
+// Physical constants of the simulator (host and device).
+#pragma once
+
+namespace gbs {
+
+// gamma/2pi of the proton, Hz/T (CODATA 2018).
+constexpr double kGammaBar = 42.577478518e6;
+constexpr double kTwoPi = 6.283185307179586476925286766559005768;
+
+}  // namespace gbs

@@ -1,0 +1,19 @@
+// Device grouping helpers (k_groups.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace gbs {
+
+size_t group_scratch_bytes(int64_t K);
+hipError_t group_axis(int64_t K, const float *coord, const float *t1, const float *t2, const float *df,
+                      void *scratch, size_t scratch_bytes, int32_t *gid_nat, float4 *gtab,
+                      int32_t *gcount, int32_t *order, int64_t *n_groups, hipStream_t st);
+hipError_t launch_gather_f32(int64_t K, int64_t Kpad, const int32_t *perm, const float *src, float *dst,
+                             hipStream_t st);
+hipError_t launch_gather_i32(int64_t K, int64_t Kpad, const int32_t *perm, const int32_t *src,
+                             int32_t *dst, hipStream_t st);
+
+}  // namespace gbs

@@ -1,0 +1,169 @@
+// Grouping of isochromats (Sec. 2.4, Fig. 2) on the device.
+//
+// For an axis a the key of isochromat k is (r_a, T1, T2, dB0), compared by
+// exact bit pattern with -0 folded onto +0.  Keys are made order-preserving
+// 32-bit words, packed as two 64-bit halves and sorted with two stable LSD
+// radix passes (low half, then high half), carrying the isochromat index.
+// Equal neighbours share a group id; ids are dense in lexicographic key order.
+#include <hipcub/hipcub.hpp>
+
+#include "groups.hpp"
+#include "kernels.hpp"
+
+namespace gbs {
+
+__device__ __forceinline__ uint32_t ordered_bits(float f) {
+    const uint32_t u = __float_as_uint(f + 0.0f);  // -0 -> +0
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ void k_keys(int64_t K, const float *__restrict__ c, const float *__restrict__ t1,
+                       const float *__restrict__ t2, const float *__restrict__ df, uint64_t *hi,
+                       uint64_t *lo, int32_t *idx) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
+        hi[i] = ((uint64_t)ordered_bits(c[i]) << 32) | ordered_bits(t1[i]);
+        lo[i] = ((uint64_t)ordered_bits(t2[i]) << 32) | ordered_bits(df[i]);
+        idx[i] = (int32_t)i;
+    }
+}
+
+__global__ void k_gather_u64(int64_t K, const uint64_t *__restrict__ src, const int32_t *__restrict__ idx,
+                             uint64_t *__restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[idx[i]];
+}
+
+__global__ void k_heads(int64_t K, const uint64_t *__restrict__ hi, const uint64_t *__restrict__ lo,
+                        int32_t *__restrict__ flag) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x)
+        flag[i] = (i == 0 || hi[i] != hi[i - 1] || lo[i] != lo[i - 1]) ? 1 : 0;
+}
+
+// ids = inclusive scan of the head flags (1-based).
+__global__ void k_assign(int64_t K, const int32_t *__restrict__ ids, const int32_t *__restrict__ order,
+                         const float *__restrict__ c, const float *__restrict__ t1,
+                         const float *__restrict__ t2, const float *__restrict__ df,
+                         int32_t *__restrict__ gid_nat, float4 *__restrict__ gtab,
+                         int32_t *__restrict__ gstart) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t g = ids[i] - 1;
+        const int32_t k = order[i];
+        gid_nat[k] = g;
+        if (i == 0 || ids[i - 1] != ids[i]) {
+            gtab[g] = make_float4(c[k], t1[k], t2[k], df[k]);
+            gstart[g] = (int32_t)i;
+        }
+    }
+}
+
+__global__ void k_counts(int64_t G, int64_t K, const int32_t *__restrict__ gstart, int32_t *__restrict__ gcount) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < G; g += (int64_t)gridDim.x * blockDim.x)
+        gcount[g] = (int32_t)((g + 1 < G ? gstart[g + 1] : K) - gstart[g]);
+}
+
+__global__ void k_gather_f32(int64_t K, int64_t Kpad, const int32_t *__restrict__ perm,
+                             const float *__restrict__ src, float *__restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < Kpad; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = i < K ? src[perm[i]] : 0.0f;
+}
+
+__global__ void k_gather_i32(int64_t K, int64_t Kpad, const int32_t *__restrict__ perm,
+                             const int32_t *__restrict__ src, int32_t *__restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < Kpad; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = i < K ? src[perm[i]] : 0;
+}
+
+__global__ void k_validate(int64_t K, PhantomPtrs ph, int *bad) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
+        const float t1 = ph.t1[i], t2 = ph.t2[i];
+        const bool ok = (t1 > 0.f) && (t2 > 0.f) && isfinite(ph.x[i]) && isfinite(ph.y[i]) &&
+                        isfinite(ph.z[i]) && isfinite(ph.df[i]) && isfinite(ph.m0[i]);
+        if (!ok) atomicOr(bad, 1);
+    }
+}
+
+static dim3 grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return dim3((unsigned)g);
+}
+
+hipError_t launch_validate_phantom(int64_t K, const PhantomPtrs &ph, int *bad, hipStream_t st) {
+    hipLaunchKernelGGL(k_validate, grid_for(K), dim3(256), 0, st, K, ph, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_f32(int64_t K, int64_t Kpad, const int32_t *perm, const float *src, float *dst,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_f32, grid_for(Kpad), dim3(256), 0, st, K, Kpad, perm, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_i32(int64_t K, int64_t Kpad, const int32_t *perm, const int32_t *src,
+                             int32_t *dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_i32, grid_for(Kpad), dim3(256), 0, st, K, Kpad, perm, src, dst);
+    return hipGetLastError();
+}
+
+size_t group_scratch_bytes(int64_t K) {
+    size_t sort_tmp = 0, scan_tmp = 0;
+    hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                       (const int32_t *)nullptr, (int32_t *)nullptr, (int)K, 0, 64);
+    hipcub::DeviceScan::InclusiveSum(nullptr, scan_tmp, (const int32_t *)nullptr, (int32_t *)nullptr, (int)K);
+    const size_t tmp = sort_tmp > scan_tmp ? sort_tmp : scan_tmp;
+    // 4 u64 key arrays, 3 i32 arrays, tmp
+    return 4 * sizeof(uint64_t) * K + 3 * sizeof(int32_t) * K + tmp + 8 * 256;
+}
+
+// Group one axis.  coord = r_a of every isochromat (natural order).  Writes
+// gid_nat[K] (natural order), gtab[n_groups] = (coord, T1, T2, df) and
+// gcount[n_groups] (gtab and gcount need room for K entries), order[K] =
+// isochromat indices sorted by key (stable), and returns the group count
+// through *n_groups (synchronizes the stream).
+hipError_t group_axis(int64_t K, const float *coord, const float *t1, const float *t2, const float *df,
+                      void *scratch, size_t scratch_bytes, int32_t *gid_nat, float4 *gtab,
+                      int32_t *gcount, int32_t *order, int64_t *n_groups, hipStream_t st) {
+    char *p = (char *)scratch;
+    auto take = [&](size_t n) {
+        char *r = p;
+        p += (n + 255) & ~(size_t)255;
+        return (void *)r;
+    };
+    uint64_t *hi = (uint64_t *)take(8 * K), *lo = (uint64_t *)take(8 * K);
+    uint64_t *k2 = (uint64_t *)take(8 * K), *k3 = (uint64_t *)take(8 * K);
+    int32_t *idx0 = (int32_t *)take(4 * K), *idx1 = (int32_t *)take(4 * K), *flag = (int32_t *)take(4 * K);
+    const size_t used = (size_t)(p - (char *)scratch);
+    if (used > scratch_bytes) return hipErrorInvalidValue;
+    void *tmp = p;
+    size_t tmp_bytes = scratch_bytes - used;
+    const dim3 g = grid_for(K);
+    hipError_t e;
+    hipLaunchKernelGGL(k_keys, g, dim3(256), 0, st, K, coord, t1, t2, df, hi, lo, idx0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // LSD: low half first (carry indices), then the high half of the same records.
+    if ((e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, lo, k2, idx0, idx1, (int)K, 0, 64, st)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_gather_u64, g, dim3(256), 0, st, K, hi, idx1, k3);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, k3, hi, idx1, order, (int)K, 0, 64, st)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_gather_u64, g, dim3(256), 0, st, K, lo, order, k2);  // low half in final order
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_heads, g, dim3(256), 0, st, K, hi, k2, flag);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, flag, idx0, (int)K, st)) != hipSuccess) return e;
+    int32_t *gstart = idx1;  // the first sort's payload is no longer needed
+    hipLaunchKernelGGL(k_assign, g, dim3(256), 0, st, K, idx0, order, coord, t1, t2, df, gid_nat, gtab, gstart);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int32_t last = 0;
+    if ((e = hipMemcpyAsync(&last, idx0 + (K - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_counts, grid_for(last), dim3(256), 0, st, (int64_t)last, K, gstart, gcount);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    *n_groups = last;
+    return hipSuccess;
+}
+
+}  // namespace gbs

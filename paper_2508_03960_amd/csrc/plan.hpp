@@ -1,0 +1,108 @@
+// Host-side planning of a simulation: subsequence classification (Sec. 2.1,
+// 2.4, 3.1) and the schedule of device passes for both modes.  Pure C++; no
+// HIP dependency, so it is unit-testable without a GPU.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "gbloch.h"
+
+namespace gbs {
+
+// Gradient type of a with-RF / with-ADC subsequence (Sec. 2.4).
+enum GradType { GT_X = 0, GT_Y = 1, GT_Z = 2, GT_NONE = 3, GT_MIXED = 4 };
+
+struct HostSeq {
+    std::vector<gbs_block> blocks;
+    std::vector<float> rf_re, rf_im, gx, gy, gz;
+    std::vector<int32_t> adc_idx;
+    double dt = 0.0;
+    int64_t total_steps = 0, total_samples = 0, stepped_steps = 0;
+};
+
+struct BlockClass {
+    bool has_b1 = false;   // any nonzero B1 sample in the block
+    int gtype = GT_NONE;   // exact-zero test per axis over the whole block
+    double moment[3] = {0, 0, 0};  // sum_j G_j dt over the block (FP64)
+};
+
+// A B1 = 0 closed-form map (Eq. 4, 5) over total duration tau with total
+// gradient moment m.  All such maps commute, so consecutive ones add.
+struct Map {
+    double tau = 0.0;
+    double m[3] = {0.0, 0.0, 0.0};
+    bool any() const { return tau != 0.0 || m[0] != 0.0 || m[1] != 0.0 || m[2] != 0.0; }
+    void add(double t, const double *mm) {
+        tau += t;
+        m[0] += mm[0];
+        m[1] += mm[1];
+        m[2] += mm[2];
+    }
+};
+
+// One streaming pass over all isochromats in group-sorted order:
+//   M <- [RF group transition] o [pre map] (M), written back if write_m;
+//   then, if emit_axis >= 0, the group sums of emit-map(Mxy) for ADC job adc_job.
+struct PassOp {
+    bool has_pre = false;
+    Map pre;
+    int rf_axis = -1;  // -1: none
+    int rf_id = -1;    // index into Plan::rf
+    bool write_m = true;
+    int emit_axis = -1;
+    Map emit;
+    int adc_job = -1;
+};
+
+// Per-isochromat stepping of steps [step_lo, step_hi) of a block, with the
+// samples [sample_lo, sample_hi) of that block (the plain method, or the
+// fallback for a subsequence the grouped method cannot classify).
+struct StepOp {
+    int64_t block = -1;  // -1: no steps (closed-form pre map only)
+    bool has_pre = false;
+    Map pre;
+    int64_t step_lo = 0, step_hi = 0;
+    int32_t sample_lo = 0, sample_hi = 0;
+};
+
+struct Op {
+    int kind = 0;  // 0 = pass, 1 = step
+    PassOp pass;
+    StepOp step;
+};
+
+struct RfJob {  // one distinct combined transition (Eq. 7) per group of `axis`
+    int axis;
+    int64_t step_offset, n_steps;
+};
+
+struct AdcJob {  // one grouped with-ADC subsequence (Eq. 8-10)
+    int axis;
+    int64_t block;
+};
+
+struct Plan {
+    std::vector<Op> ops;
+    std::vector<RfJob> rf;
+    std::vector<AdcJob> adc;
+    bool final_pass = false;  // materialize the trailing map before output
+    Map final_map;
+    int64_t n_rf_grouped = 0, n_adc_grouped = 0, n_fallback = 0, n_b1zero = 0, n_relax = 0;
+    int64_t n_passes = 0, n_emit_only = 0;
+};
+
+// Largest number of ADC samples one stepping launch accumulates (LDS bound).
+constexpr int32_t kMaxSamplesPerLaunch = 256;
+
+int validate_sequence(const gbs_block *blocks, int64_t n_blocks, int64_t total_steps,
+                      const int32_t *adc_idx, int64_t total_samples, double dt, std::string &err);
+void copy_sequence(HostSeq &s, const gbs_block *blocks, int64_t n_blocks, const float *rf_re,
+                   const float *rf_im, const float *gx, const float *gy, const float *gz,
+                   int64_t total_steps, const int32_t *adc_idx, int64_t total_samples, double dt);
+std::vector<BlockClass> classify(const HostSeq &s);
+Plan plan_plain(const HostSeq &s);
+Plan plan_grouped(const HostSeq &s, const std::vector<BlockClass> &cls, uint32_t axes_built);
+
+}  // namespace gbs
