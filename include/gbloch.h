@@ -59,7 +59,8 @@ extern "C" {
 /* ---- simulation modes and flags -------------------------------------- */
 #define GBS_PLAIN 0
 #define GBS_GROUPED 1
-#define GBS_ASYNC 1u /* enqueue on the context stream and return; no final synchronize */
+#define GBS_ASYNC 1u      /* enqueue on the context stream and return; no final synchronize */
+#define GBS_PLAIN_FP32 2u /* GBS_PLAIN: step in FP32 instead of FP64 (faster to state, less exact) */
 
 /*
  * One subsequence.  RF/ADC blocks cover raster steps
@@ -146,11 +147,13 @@ int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, co
  * Group the isochromats once (Sec. 2.4, Fig. 2): for each requested axis a
  * (GBS_AX_X | GBS_AX_Y | GBS_AX_Z) the key (r_a, T1, T2, dB0) is compared by
  * exact bit pattern (-0 == +0); equal keys form one group, numbered densely
- * in lexicographic key order.  GBS_GROUPED needs GBS_AX_X; blocks whose type
- * needs an axis that was not built are stepped per isochromat.  The context
+ * in lexicographic key order.  `axes` must include GBS_AX_X (the x groups
+ * order the stored copy); blocks whose type needs an axis that was not built
+ * are stepped per isochromat.  The context
  * stores a copy of the phantom in group-sorted order (about 13 float/int32
  * words per isochromat).  Synchronizes the stream.
- * Errors: GBS_E_STATE (no phantom), GBS_E_INVALID (axes == 0), GBS_E_NOMEM.
+ * Errors: GBS_E_STATE (no phantom), GBS_E_INVALID (no GBS_AX_X, unknown bits),
+ * GBS_E_NOMEM, GBS_E_HIP.
  */
 int gbs_build_groups(gbs_ctx *ctx, uint32_t axes);
 

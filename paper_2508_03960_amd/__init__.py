@@ -21,6 +21,7 @@ GBS_BLOCK_RF, GBS_BLOCK_ADC, GBS_BLOCK_RELAX = 1, 2, 3
 GBS_AX_X, GBS_AX_Y, GBS_AX_Z = 1, 2, 4
 GBS_PLAIN, GBS_GROUPED = 0, 1
 GBS_ASYNC = 1
+GBS_PLAIN_FP32 = 2
 
 EXPORTED = ("gbs_create", "gbs_destroy", "gbs_set_phantom", "gbs_set_sequence", "gbs_build_groups",
             "gbs_simulate", "gbs_get_info", "gbs_last_error", "gbs_strerror", "gbs_plan_summary")

@@ -327,7 +327,7 @@ PlainArgs step_args(gbs_ctx *ctx, const StepOp &op, const PhantomPtrs &ph, int64
     a.mout_y = oy;
     a.mout_z = oz;
     a.dt = ctx->seq.dt;
-    a.gdt = (float)(kTwoPi * kGammaBar * ctx->seq.dt);
+    a.gdt = kTwoPi * kGammaBar * ctx->seq.dt;
     a.has_pre = op.has_pre ? 1 : 0;
     a.pre_tau = op.pre.tau;
     for (int i = 0; i < 3; ++i) a.pre_cyc[i] = kGammaBar * op.pre.m[i];
@@ -351,7 +351,8 @@ PlainArgs step_args(gbs_ctx *ctx, const StepOp &op, const PhantomPtrs &ph, int64
 
 }  // namespace
 
-static int run_plain(gbs_ctx *ctx, const float *m_init, float *m_out, double *sig_out, gbs_stats *st) {
+static int run_plain(gbs_ctx *ctx, const float *m_init, float *m_out, double *sig_out, bool fp32,
+                     gbs_stats *st) {
     const int64_t K = ctx->K;
     Plan plan = plan_plain(ctx->seq);
     if (plan.ops.empty()) {
@@ -370,7 +371,7 @@ static int run_plain(gbs_ctx *ctx, const float *m_init, float *m_out, double *si
         const float *iz = first && m_init ? m_init + 2 * K : (first ? nullptr : oz);
         PlainArgs a = step_args(ctx, op.step, ctx->ph, K, ix, iy, iz, ox, oy, oz);
         const bool b1 = op.step.block >= 0 && ctx->cls[op.step.block].has_b1;
-        HIPCHK(launch_plain(a, b1, grid, ctx->stream));
+        HIPCHK(launch_plain(a, b1, fp32, grid, ctx->stream));
         if (a.n_samples > 0) {
             const gbs_block &b = ctx->seq.blocks[op.step.block];
             HIPCHK(launch_plain_finalize(ctx->partial.as<double2>(), grid, a.n_samples,
@@ -572,7 +573,7 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
         } else {
             PlainArgs a = step_args(ctx, op.step, iph, K, mx, my, mz, mx, my, mz);
             const bool b1 = op.step.block >= 0 && ctx->cls[op.step.block].has_b1;
-            HIPCHK(launch_plain(a, b1, grid, ctx->stream));
+            HIPCHK(launch_plain(a, b1, false, grid, ctx->stream));
             if (a.n_samples > 0) {
                 const gbs_block &b = s.blocks[op.step.block];
                 HIPCHK(launch_plain_finalize(ctx->partial.as<double2>(), grid, a.n_samples,
@@ -618,7 +619,7 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
     if (!m_out || (ctx->seq.total_samples > 0 && !sig_out)) return fail(ctx, GBS_E_INVALID, "null output");
     if (mode == GBS_GROUPED && !ctx->groups_valid)
         return fail(ctx, GBS_E_STATE, "GBS_GROUPED needs gbs_build_groups on the current phantom");
-    if (flags & ~GBS_ASYNC) return fail(ctx, GBS_E_INVALID, "unknown flags");
+    if (flags & ~(GBS_ASYNC | GBS_PLAIN_FP32)) return fail(ctx, GBS_E_INVALID, "unknown flags");
     HIPCHK(hipSetDevice(ctx->device));
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
@@ -626,7 +627,7 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
     }
     if (ctx->seq.total_samples > 0)
         HIPCHK(launch_fill_f64(sig_out, 2 * ctx->seq.total_samples, ctx->stream));
-    int rc = mode == GBS_PLAIN ? run_plain(ctx, m_init, m_out, sig_out, stats)
+    int rc = mode == GBS_PLAIN ? run_plain(ctx, m_init, m_out, sig_out, (flags & GBS_PLAIN_FP32) != 0, stats)
                                : run_grouped(ctx, m_init, m_out, sig_out, stats);
     if (rc != GBS_OK) return rc;
     if (stats) HIPCHK(hipEventRecord(ctx->ev[4], ctx->stream));

@@ -51,7 +51,22 @@ __device__ __forceinline__ float wave_sum_lane63(float v) {
     return v;
 }
 
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum_lane63_f64(double v) {
+    v += dpp_f64<0xb1>(v);
+    v += dpp_f64<0x4e>(v);
+    v += dpp_f64<0x114>(v);
+    v += dpp_f64<0x118>(v);
+    v += dpp_f64<0x142>(v);
+    v += dpp_f64<0x143>(v);
+    return v;
+}
 
 // Compensated (Kahan) accumulation of x into (sum, comp).
 __device__ __forceinline__ void kahan_add(float &sum, float &comp, float x) {

@@ -5,17 +5,23 @@
 // of a block: U = D R (Eq. 2, Eq. A1, Eq. A2).  The waveform value of a step
 // is the same for every lane, so it is one scalar load per step.
 //
-// FP32 is used in increment form so that rounding does not bias the state:
+// The step is applied in increment form:
 //   R M = M + a (B x M) + b (B (B . M) - |B|^2 M),
 //   a = sin(theta)/|B|,  b = (1 - cos theta)/|B|^2,  theta = -gamma |B| dt,
 // with a, b from their power series in q = theta^2 (no sqrt, no division, and
 // R = I falls out at B = 0); relaxation as M -= (1 - E) M with
 // 1 - E = -expm1(-dt/T) computed once per isochromat.
 //
+// The arithmetic type R is double by default and float on request.  In float
+// the rounded per-step coefficients bias every step of a constant-gradient
+// readout the same way (about 1e-8 per step), which over tens of thousands of
+// steps exceeds 1e-5; the double version keeps the state exact to ~1e-12 at
+// the same FMA rate (packed FP32 is not used on this target).
+//
 // ADC samples (Eq. 6): at each sample boundary a wavefront sums its lanes with
-// DPP, lane 63 adds the wave total into a per-wave compensated (Kahan) FP32
-// accumulator in LDS; at the end each workgroup writes one FP64 partial per
-// sample, and a finalize kernel adds the partials in a fixed order.
+// DPP, lane 63 adds the wave total into a per-wave LDS accumulator
+// (compensated FP32, or FP64); at the end each workgroup writes one FP64
+// partial per sample, and a finalize kernel adds the partials in a fixed order.
 #include "device_math.hpp"
 #include "kernels.hpp"
 
@@ -24,89 +30,175 @@ namespace gbs {
 constexpr int kPlainBlock = 256;
 constexpr int kIso = 2;
 constexpr int kTile = kPlainBlock * kIso;
-constexpr float kQMax = 1.0f;  // series used while theta^2 <= 1
 
-// a = sin(theta)/|B| = -gdt * S(q), b = (1 - cos theta)/|B|^2 = gdt^2 * C(q),
-// S(q) = sum (-q)^n / (2n+1)!, C(q) = sum (-q)^n / (2n+2)!, n = 0..5.
-__device__ __forceinline__ void rot_coeffs(float B2, float gdt, float k2, float &a, float &b) {
-    const float q = k2 * B2;
-    if (q <= kQMax) {
-        float S = fmaf(q, -2.5052108385441719e-8f, 2.7557319223985891e-6f);
+// Rotation coefficients of one step:
+//   a = sin(theta)/|B| = -gdt * S(q),  b = (1 - cos theta)/|B|^2 = gdt^2 * C(q),
+//   S(q) = sum_n (-q)^n / (2n+1)!,  C(q) = sum_n (-q)^n / (2n+2)!,  q = theta^2.
+// For q <= 1 the series is truncated where the next term is below the
+// precision of R (n <= 5 for float, n <= 8 for double); larger angles use
+// sqrt and sincos.
+template <typename R>
+struct Series;
+
+template <>
+struct Series<float> {
+    static __device__ __forceinline__ void coeffs(float q, float &S, float &C) {
+        S = fmaf(q, -2.5052108385441719e-8f, 2.7557319223985891e-6f);
         S = fmaf(q, S, -1.9841269841269841e-4f);
         S = fmaf(q, S, 8.3333333333333333e-3f);
         S = fmaf(q, S, -1.6666666666666667e-1f);
         S = fmaf(q, S, 1.0f);
-        float C = fmaf(q, -2.0876756987868099e-9f, 2.7557319223985891e-7f);
+        C = fmaf(q, -2.0876756987868099e-9f, 2.7557319223985891e-7f);
         C = fmaf(q, C, -2.4801587301587302e-5f);
         C = fmaf(q, C, 1.3888888888888889e-3f);
         C = fmaf(q, C, -4.1666666666666667e-2f);
         C = fmaf(q, C, 0.5f);
-        a = -gdt * S;
-        b = k2 * C;
-    } else {
+    }
+    static __device__ __forceinline__ void big(float B2, float gdt, float &a, float &b) {
         const float nb = sqrtf(B2);
         float sh, ch;
         sincosf(0.5f * gdt * nb, &sh, &ch);
         a = -2.0f * sh * ch / nb;
         b = 2.0f * sh * sh / B2;
     }
+};
+
+template <>
+struct Series<double> {
+    static __device__ __forceinline__ void coeffs(double q, double &S, double &C) {
+        S = fma(q, 8.2206352466243297e-18, -2.8114572543455208e-15);  // 1/19!, -1/17!
+        S = fma(q, S, 7.6471637318198164e-13);                         // 1/15!
+        S = fma(q, S, -1.6059043836821613e-10);                        // -1/13!
+        S = fma(q, S, 2.5052108385441719e-8);                          // 1/11!
+        S = fma(q, S, -2.7557319223985891e-6);                         // -1/9!
+        S = fma(q, S, 1.9841269841269841e-4);                          // 1/7!
+        S = fma(q, S, -8.3333333333333333e-3);                         // -1/5!
+        S = fma(q, S, 1.6666666666666667e-1);                          // 1/3!
+        S = fma(-q, S, 1.0);
+        C = fma(q, 4.1103176233121648e-19, -1.5619206968586226e-16);   // 1/20!, -1/18!
+        C = fma(q, C, 4.7794773323873853e-14);                         // 1/16!
+        C = fma(q, C, -1.1470745597729725e-11);                        // -1/14!
+        C = fma(q, C, 2.0876756987868099e-9);                          // 1/12!
+        C = fma(q, C, -2.7557319223985891e-7);                         // -1/10!
+        C = fma(q, C, 2.4801587301587302e-5);                          // 1/8!
+        C = fma(q, C, -1.3888888888888889e-3);                         // -1/6!
+        C = fma(q, C, 4.1666666666666667e-2);                          // 1/4!
+        C = fma(-q, C, 0.5);
+    }
+    static __device__ __forceinline__ void big(double B2, double gdt, double &a, double &b) {
+        const double nb = sqrt(B2);
+        double sh, ch;
+        sincos(0.5 * gdt * nb, &sh, &ch);
+        a = -2.0 * sh * ch / nb;
+        b = 2.0 * sh * sh / B2;
+    }
+};
+
+template <typename R>
+__device__ __forceinline__ void rot_coeffs(R B2, R gdt, R k2, R &a, R &b) {
+    const R q = k2 * B2;
+    if (q <= R(1)) {
+        R S, C;
+        Series<R>::coeffs(q, S, C);
+        a = -gdt * S;
+        b = k2 * C;
+    } else {
+        Series<R>::big(B2, gdt, a, b);
+    }
 }
 
-template <bool HAS_B1>
+// Per-wave ADC accumulator in LDS: compensated FP32, or plain FP64.
+template <typename R>
+struct SampleAcc;
+
+template <>
+struct SampleAcc<float> {
+    float4 v;  // (sum re, comp re, sum im, comp im)
+    static __device__ __forceinline__ void add(SampleAcc &a, float x, float y) {
+        kahan_add(a.v.x, a.v.y, x);
+        kahan_add(a.v.z, a.v.w, y);
+    }
+    __device__ __forceinline__ double re() const { return (double)v.x - (double)v.y; }
+    __device__ __forceinline__ double im() const { return (double)v.z - (double)v.w; }
+    static __device__ __forceinline__ float wave_sum(float x) { return wave_sum_lane63(x); }
+};
+
+template <>
+struct SampleAcc<double> {
+    double2 v;
+    static __device__ __forceinline__ void add(SampleAcc &a, double x, double y) {
+        a.v.x += x;
+        a.v.y += y;
+    }
+    __device__ __forceinline__ double re() const { return v.x; }
+    __device__ __forceinline__ double im() const { return v.y; }
+    static __device__ __forceinline__ double wave_sum(double x) { return wave_sum_lane63_f64(x); }
+};
+
+template <typename R>
+__device__ __forceinline__ R fmaR(R a, R b, R c);
+template <>
+__device__ __forceinline__ float fmaR<float>(float a, float b, float c) { return fmaf(a, b, c); }
+template <>
+__device__ __forceinline__ double fmaR<double>(double a, double b, double c) { return fma(a, b, c); }
+
+template <typename R, bool HAS_B1>
 __global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a) {
-    extern __shared__ float4 acc[];  // [4 waves][n_samples]: (sum re, comp re, sum im, comp im)
+    using Acc = SampleAcc<R>;
+    extern __shared__ char lds_raw[];
+    Acc *acc = reinterpret_cast<Acc *>(lds_raw);  // [4 waves][n_samples]
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
     const int ns = a.n_samples;
-    for (int i = tid; i < 4 * ns; i += kPlainBlock) acc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = tid; i < 4 * ns; i += kPlainBlock) acc[i] = Acc{};
     __syncthreads();
-    const float gdt = a.gdt;
-    const float k2 = gdt * gdt;
+    const R gdt = (R)a.gdt;
+    const R k2 = gdt * gdt;
     const StepW *__restrict__ wave_ptr = a.wave;
     const int32_t *__restrict__ sidx = a.sidx;
 
     for (int64_t base = (int64_t)blockIdx.x * kTile; base < a.K; base += (int64_t)gridDim.x * kTile) {
-        float X[kIso], Y[kIso], Z[kIso], boff[kIso], e1m[kIso], e2m[kIso], M0[kIso];
-        float mx[kIso], my[kIso], mz[kIso];
+        R X[kIso], Y[kIso], Z[kIso], boff[kIso], e1m[kIso], e2m[kIso], M0[kIso];
+        R mx[kIso], my[kIso], mz[kIso];
 #pragma unroll
         for (int i = 0; i < kIso; ++i) {
             const int64_t k = base + (int64_t)i * kPlainBlock + tid;
             if (k < a.K) {
-                X[i] = a.ph.x[k];
-                Y[i] = a.ph.y[k];
-                Z[i] = a.ph.z[k];
+                const double x = a.ph.x[k], y = a.ph.y[k], z = a.ph.z[k];
                 const double t1 = a.ph.t1[k], t2 = a.ph.t2[k], df = a.ph.df[k];
-                M0[i] = a.ph.m0[k];
-                boff[i] = (float)(df / kGammaBar);
-                e1m[i] = (float)(-expm1(-a.dt / t1));
-                e2m[i] = (float)(-expm1(-a.dt / t2));
+                const double m0 = a.ph.m0[k];
+                double vx = 0.0, vy = 0.0, vz = m0;
                 if (a.min_x) {
-                    mx[i] = a.min_x[k];
-                    my[i] = a.min_y[k];
-                    mz[i] = a.min_z[k];
-                } else {
-                    mx[i] = 0.f;
-                    my[i] = 0.f;
-                    mz[i] = M0[i];
+                    vx = a.min_x[k];
+                    vy = a.min_y[k];
+                    vz = a.min_z[k];
                 }
-                if (a.has_pre) {  // Eq. (4), (5) with the phase reduced in FP64
-                    const double cyc = a.pre_cyc[0] * X[i] + a.pre_cyc[1] * Y[i] + a.pre_cyc[2] * Z[i] +
-                                       df * a.pre_tau;
-                    float s, c;
-                    sincos_rev(cyc, &s, &c);
-                    const float e2 = (float)exp(-a.pre_tau / t2);
-                    const float e1 = (float)exp(-a.pre_tau / t1);
-                    const float nx = e2 * (mx[i] * c + my[i] * s);
-                    const float ny = e2 * (my[i] * c - mx[i] * s);
-                    mx[i] = nx;
-                    my[i] = ny;
-                    mz[i] = fmaf(e1, mz[i] - M0[i], M0[i]);
+                if (a.has_pre) {  // Eq. (4), (5); phase reduced modulo one cycle in FP64
+                    const double cyc = a.pre_cyc[0] * x + a.pre_cyc[1] * y + a.pre_cyc[2] * z + df * a.pre_tau;
+                    double sn, cs;
+                    sincos(kTwoPi * (cyc - rint(cyc)), &sn, &cs);
+                    const double e2 = exp(-a.pre_tau / t2), e1 = exp(-a.pre_tau / t1);
+                    const double nx = e2 * (vx * cs + vy * sn);
+                    const double ny = e2 * (vy * cs - vx * sn);
+                    vx = nx;
+                    vy = ny;
+                    vz = m0 + (vz - m0) * e1;
                 }
+                X[i] = (R)x;
+                Y[i] = (R)y;
+                Z[i] = (R)z;
+                M0[i] = (R)m0;
+                boff[i] = (R)(df / kGammaBar);
+                e1m[i] = (R)(-expm1(-a.dt / t1));
+                e2m[i] = (R)(-expm1(-a.dt / t2));
+                mx[i] = (R)vx;
+                my[i] = (R)vy;
+                mz[i] = (R)vz;
             } else {
-                X[i] = Y[i] = Z[i] = 0.f;
-                boff[i] = e1m[i] = e2m[i] = M0[i] = 0.f;
-                mx[i] = my[i] = mz[i] = 0.f;
+                X[i] = Y[i] = Z[i] = R(0);
+                boff[i] = e1m[i] = e2m[i] = M0[i] = R(0);
+                mx[i] = my[i] = mz[i] = R(0);
             }
         }
 
@@ -116,61 +208,58 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a) {
 #pragma unroll 2
             for (; j < jend; ++j) {
                 const StepW w = wave_ptr[j];
+                const R b1r = (R)w.b1r, b1i = (R)w.b1i, b1sq = (R)w.b1sq;
+                const R gx = (R)w.gx, gy = (R)w.gy, gz = (R)w.gz;
 #pragma unroll
                 for (int i = 0; i < kIso; ++i) {
-                    const float bz = fmaf(w.gx, X[i], fmaf(w.gy, Y[i], fmaf(w.gz, Z[i], boff[i])));
-                    float ca, cb;
+                    const R bz = fmaR(gx, X[i], fmaR(gy, Y[i], fmaR(gz, Z[i], boff[i])));
+                    R ca, cb;
                     if (HAS_B1) {
-                        const float B2 = fmaf(bz, bz, w.b1sq);
-                        rot_coeffs(B2, gdt, k2, ca, cb);
-                        const float cx = w.b1i * mz[i] - bz * my[i];
-                        const float cy = bz * mx[i] - w.b1r * mz[i];
-                        const float cz = w.b1r * my[i] - w.b1i * mx[i];
-                        const float d = fmaf(w.b1r, mx[i], fmaf(w.b1i, my[i], bz * mz[i]));
-                        const float dx = fmaf(ca, cx, cb * fmaf(w.b1r, d, -B2 * mx[i]));
-                        const float dy = fmaf(ca, cy, cb * fmaf(w.b1i, d, -B2 * my[i]));
-                        const float dz = fmaf(ca, cz, cb * fmaf(bz, d, -B2 * mz[i]));
+                        const R B2 = fmaR(bz, bz, b1sq);
+                        rot_coeffs<R>(B2, gdt, k2, ca, cb);
+                        const R cx = b1i * mz[i] - bz * my[i];
+                        const R cy = bz * mx[i] - b1r * mz[i];
+                        const R cz = b1r * my[i] - b1i * mx[i];
+                        const R d = fmaR(b1r, mx[i], fmaR(b1i, my[i], bz * mz[i]));
+                        const R dx = fmaR(ca, cx, cb * fmaR(b1r, d, -B2 * mx[i]));
+                        const R dy = fmaR(ca, cy, cb * fmaR(b1i, d, -B2 * my[i]));
+                        const R dz = fmaR(ca, cz, cb * fmaR(bz, d, -B2 * mz[i]));
                         mx[i] += dx;
                         my[i] += dy;
                         mz[i] += dz;
                     } else {  // B = (0, 0, bz): rotation about z
-                        const float B2 = bz * bz;
-                        rot_coeffs(B2, gdt, k2, ca, cb);
-                        const float p = ca * bz, r = cb * B2;
-                        const float nx = fmaf(-p, my[i], fmaf(-r, mx[i], mx[i]));
-                        const float ny = fmaf(p, mx[i], fmaf(-r, my[i], my[i]));
+                        const R B2 = bz * bz;
+                        rot_coeffs<R>(B2, gdt, k2, ca, cb);
+                        const R p = ca * bz, r = cb * B2;
+                        const R nx = fmaR(-p, my[i], fmaR(-r, mx[i], mx[i]));
+                        const R ny = fmaR(p, mx[i], fmaR(-r, my[i], my[i]));
                         mx[i] = nx;
                         my[i] = ny;
                     }
-                    mx[i] = fmaf(-e2m[i], mx[i], mx[i]);  // D: T2 decay, T1 recovery
-                    my[i] = fmaf(-e2m[i], my[i], my[i]);
-                    mz[i] = fmaf(e1m[i], M0[i] - mz[i], mz[i]);
+                    mx[i] = fmaR(-e2m[i], mx[i], mx[i]);  // D: T2 decay, T1 recovery
+                    my[i] = fmaR(-e2m[i], my[i], my[i]);
+                    mz[i] = fmaR(e1m[i], M0[i] - mz[i], mz[i]);
                 }
             }
             if (n < ns) {
-                float vx = mx[0], vy = my[0];
+                R vx = mx[0], vy = my[0];
 #pragma unroll
                 for (int i = 1; i < kIso; ++i) {
                     vx += mx[i];
                     vy += my[i];
                 }
-                vx = wave_sum_lane63(vx);
-                vy = wave_sum_lane63(vy);
-                if (lane == 63) {
-                    float4 t = acc[wave * ns + n];
-                    kahan_add(t.x, t.y, vx);
-                    kahan_add(t.z, t.w, vy);
-                    acc[wave * ns + n] = t;
-                }
+                vx = Acc::wave_sum(vx);
+                vy = Acc::wave_sum(vy);
+                if (lane == 63) Acc::add(acc[wave * ns + n], vx, vy);
             }
         }
 #pragma unroll
         for (int i = 0; i < kIso; ++i) {
             const int64_t k = base + (int64_t)i * kPlainBlock + tid;
             if (k < a.K) {
-                a.mout_x[k] = mx[i];
-                a.mout_y[k] = my[i];
-                a.mout_z[k] = mz[i];
+                a.mout_x[k] = (float)mx[i];
+                a.mout_y[k] = (float)my[i];
+                a.mout_z[k] = (float)mz[i];
             }
         }
     }
@@ -180,9 +269,8 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a) {
         double re = 0.0, im = 0.0;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-            const float4 t = acc[w * ns + n];
-            re += (double)t.x - (double)t.y;
-            im += (double)t.z - (double)t.w;
+            re += acc[w * ns + n].re();
+            im += acc[w * ns + n].im();
         }
         a.partial[(int64_t)blockIdx.x * ns + n] = make_double2(re, im);
     }
@@ -208,12 +296,19 @@ int plain_grid(int64_t K) {
     return (int)(tiles < cap ? (tiles > 0 ? tiles : 1) : cap);
 }
 
-hipError_t launch_plain(const PlainArgs &a, bool has_b1, int grid, hipStream_t st) {
-    const size_t lds = sizeof(float4) * 4 * (size_t)a.n_samples;
-    if (has_b1)
-        hipLaunchKernelGGL(k_plain<true>, dim3(grid), dim3(kPlainBlock), lds, st, a);
-    else
-        hipLaunchKernelGGL(k_plain<false>, dim3(grid), dim3(kPlainBlock), lds, st, a);
+hipError_t launch_plain(const PlainArgs &a, bool has_b1, bool fp32, int grid, hipStream_t st) {
+    const size_t lds = 16 * 4 * (size_t)a.n_samples;  // both accumulator types are 16 bytes
+    if (fp32) {
+        if (has_b1)
+            hipLaunchKernelGGL((k_plain<float, true>), dim3(grid), dim3(kPlainBlock), lds, st, a);
+        else
+            hipLaunchKernelGGL((k_plain<float, false>), dim3(grid), dim3(kPlainBlock), lds, st, a);
+    } else {
+        if (has_b1)
+            hipLaunchKernelGGL((k_plain<double, true>), dim3(grid), dim3(kPlainBlock), lds, st, a);
+        else
+            hipLaunchKernelGGL((k_plain<double, false>), dim3(grid), dim3(kPlainBlock), lds, st, a);
+    }
     return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ struct PlainArgs {
     double pre_tau;
     double pre_cyc[3];    // gamma_bar * moment (cycles per metre)
     double dt;
-    float gdt;            // gamma * dt (rad / T)
+    double gdt;           // gamma * dt (rad / T)
 };
 
 // ---- grouped streaming pass ---------------------------------------------
@@ -87,7 +87,7 @@ struct AdcJobDev {
 };
 
 // ---- launchers (all asynchronous on `st`) -----------------------------------
-hipError_t launch_plain(const PlainArgs &a, bool has_b1, int grid, hipStream_t st);
+hipError_t launch_plain(const PlainArgs &a, bool has_b1, bool fp32, int grid, hipStream_t st);
 hipError_t launch_plain_finalize(const double2 *partial, int nblk, int n_samples, double *sig,
                                  hipStream_t st);
 int plain_grid(int64_t K);

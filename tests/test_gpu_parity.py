@@ -15,6 +15,11 @@ pytestmark = pytest.mark.gpu
 
 DM_TOL = 1e-5
 SIG_TOL = 1e-4
+# GBS_PLAIN_FP32: every step multiplies by FP32-rounded rotation coefficients,
+# a bias of up to ~2 ulp (1e-7) per step that adds up coherently over a
+# constant-gradient readout; 1e-7 x ~1e4 steps -> 1e-3 is the bar derived for it.
+DM_TOL_FP32 = 2e-3
+SIG_TOL_FP32 = 1e-3
 
 
 @pytest.fixture(scope="module")
@@ -30,7 +35,7 @@ def say(msg):
     print(msg, flush=True)
 
 
-def run_gpu(gb, ph, seq, mode, axes=7, m_init=None):
+def run_gpu(gb, ph, seq, mode, axes=7, m_init=None, flags=0):
     import torch
     sim = gb.Simulator(0)
     sim.set_phantom(ph)
@@ -38,7 +43,7 @@ def run_gpu(gb, ph, seq, mode, axes=7, m_init=None):
     if mode == gb.GBS_GROUPED:
         sim.build_groups(axes)
     mi = None if m_init is None else torch.from_numpy(np.ascontiguousarray(m_init, np.float32))
-    M, sig, st = sim.simulate(mode, m_init=mi, stats=True)
+    M, sig, st = sim.simulate(mode, m_init=mi, stats=True, flags=flags)
     torch.cuda.synchronize()
     out = M.cpu().numpy().astype(np.float64), sig.cpu().numpy().copy(), st
     sim.close()
@@ -56,17 +61,19 @@ def check_case(gb, name, ph, seq, modes=("plain", "grouped"), axes=7, m_init=Non
     Mr, sr = ref if ref is not None else oracle.simulate(ph, seq, m_init=m_init)
     for mode in modes:
         say(f"[gpu] {name}: {mode} K={ph.K} blocks={seq.n_blocks} axes={axes}")
-        m = gb.GBS_PLAIN if mode == "plain" else gb.GBS_GROUPED
-        M, sig, st = run_gpu(gb, ph, seq, m, axes=axes, m_init=m_init)
+        m = gb.GBS_GROUPED if mode == "grouped" else gb.GBS_PLAIN
+        flags = gb.GBS_PLAIN_FP32 if mode == "plain32" else 0
+        M, sig, st = run_gpu(gb, ph, seq, m, axes=axes, m_init=m_init, flags=flags)
         dm, rel = errors(M, sig, Mr, sr)
         say(f"[gpu] {name}: {mode} max|dM|={dm:.3e} rel_sig={rel:.3e} stats={st}")
-        assert dm <= DM_TOL, (name, mode, dm)
-        assert rel <= SIG_TOL, (name, mode, rel)
+        dm_tol, sig_tol = (DM_TOL_FP32, SIG_TOL_FP32) if mode == "plain32" else (DM_TOL, SIG_TOL)
+        assert dm <= dm_tol, (name, mode, dm)
+        assert rel <= sig_tol, (name, mode, rel)
 
 
 def test_gre_4096(gb):
     ph, seq = synth.workload("gre")
-    check_case(gb, "gre", ph, seq)
+    check_case(gb, "gre", ph, seq, modes=("plain", "grouped", "plain32"))
 
 
 def test_fse_small(gb):
