@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Benchmark: grouped-isochromat vs plain Bloch simulation on one MI355X.
+
+Workload (timed step): one grouped simulation of the FSE sequence
+(16 shots x ETL 16, 256 phase lines x 256 readout samples, 90/180 sinc RF of
+3000 raster steps with Gz) on the 1024x1024x26 = 27,262,976-isochromat
+six-class phantom; inputs resident in HBM, groups built before timing.
+Throughput = K * (raster steps inside RF and ADC blocks) / time.
+
+Also reported: the EPI workload (grouped), the plain per-isochromat method
+on the same GPU (FSE: first shot of the sequence at full K; EPI: whole),
+the grouped-vs-plain speedup, the roofline of the dominant kernel (the
+streaming pass k_pass) and the FP64 CPU oracle timed on the host cores.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+COUNTERS = os.path.join(ROOT, "profiles", "k_pass_fse_27m_counters.json")
+PASS_SRC = os.path.join(ROOT, "paper_2508_03960_amd", "csrc", "k_grouped.hip")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def timed_runs(sim, gb, mode, steps, warmup, m_out, sig_out, flags=0):
+    import torch
+    for _ in range(warmup):
+        sim.simulate(mode, m_out=m_out, sig_out=sig_out, flags=flags)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, _, st = sim.simulate(mode, m_out=m_out, sig_out=sig_out, flags=flags, stats=True)
+        stats.append(st)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, stats
+
+
+def traffic_per_launch():
+    """HBM bytes per k_pass launch from the committed rocprofv3 counter runs,
+    scaled by the copy-kernel calibration; None if absent or stale."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+        with open(PASS_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if c.get("kernel_source_sha256") != sha:
+            return None
+        return float(c["hbm_bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def cpu_baseline(ph, seq, target_s=15.0):
+    """FP64 oracle on a seeded subset of isochromats, whole FSE sequence."""
+    import numpy as np
+
+    import oracle
+    import synth
+    nt = oracle.max_threads()
+    S = seq.stepped_count()
+    idx0 = synth.random_subset_indices(ph.K, nt, seed=7)
+    t = time.perf_counter()
+    oracle.simulate(ph.subset(idx0), seq)
+    t_one = time.perf_counter() - t
+    n = int(max(nt, min(64 * nt, nt * round(target_s / max(t_one, 1e-3)))))
+    idx = synth.random_subset_indices(ph.K, n, seed=7)
+    sub = ph.subset(idx)
+    t = time.perf_counter()
+    M, _ = oracle.simulate(sub, seq)
+    dt = time.perf_counter() - t
+    return {"value": n * S / dt, "unit": "isochromat-steps/s", "cores": nt, "kind": "oracle",
+            "sample": f"{n} seeded isochromats of the 27,262,976 x full FSE sequence "
+                      f"({S} stepped raster steps each), FP64, {dt:.1f} s"}, idx, M
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-method runs")
+    ap.add_argument("--no-epi", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (for counter calibration under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the simulator has no "
+              "multi-GPU path; isochromats would shard by index with one signal reduce.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2508_03960_amd as gb
+
+    dev = torch.device("cuda", 0)
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("copy calibration: 3 x 1 GiB device copy done")
+
+    t = time.perf_counter()
+    ph = synth.brain_like_phantom()
+    fse = synth.fse_sequence()
+    epi = synth.epi_sequence()
+    log(f"phantom K={ph.K} built in {time.perf_counter() - t:.1f} s")
+    sim = gb.Simulator(0)
+    sim.set_phantom(ph)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sim.build_groups()
+    torch.cuda.synchronize()
+    t_groups = time.perf_counter() - t
+    info = sim.info()
+    log(f"groups {info['n_groups']} in {t_groups:.2f} s")
+    K = ph.K
+    m_out = torch.empty(3, K, device=dev, dtype=torch.float32)
+
+    # ---- FSE grouped (the timed step) ------------------------------------------
+    sim.set_sequence(fse)
+    sig_fse = torch.empty(fse.total_samples, 2, device=dev, dtype=torch.float64)
+    S_fse = fse.stepped_count()
+    sec, stats = timed_runs(sim, gb, gb.GBS_GROUPED, args.steps, args.warmup, m_out, sig_fse,
+                            flags=gb.GBS_PROFILE)
+    value = K * S_fse / sec
+    log(f"FSE grouped: {sec * 1e3:.2f} ms/step, {value:.3e} iso-steps/s; stats {stats[-1]}")
+    n_pass = stats[-1]["n_passes"]
+    pass_ms = float(np.mean([s["pass_kernel_ms"] for s in stats])) / n_pass
+    bytes_launch = stats[-1]["pass_bytes"] / n_pass
+    achieved = bytes_launch / (pass_ms * 1e-3) / 1e9
+    M_fse = m_out.cpu().numpy()
+
+    out = {
+        "metric": "isochromat-steps/s grouped vs plain (same GPU); FSE/EPI sim time @27.3M isos",
+        "value": value, "unit": "isochromat-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "FSE grouped, 1024x1024x26 = 27,262,976 isochromats, 16 shots x ETL 16, "
+                               "256x256 samples @4us, 90/180 sinc 3000 steps with Gz, TR 3 s",
+                   "K": K, "stepped_steps": S_fse, "mode": "grouped", "n_groups_xyz": info["n_groups"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_per_launch(),
+                     "kernel": "k_pass", "bytes_per_launch": bytes_launch, "avg_launch_ms": pass_ms,
+                     "launches_per_step": n_pass},
+        "fse": {"grouped_ms": sec * 1e3, "phases_ms": {k: stats[-1][k] for k in
+                                                      ("ms_prepare", "ms_passes", "ms_adc_eval")},
+                "build_groups_s": t_groups},
+    }
+
+    # ---- EPI grouped --------------------------------------------------------------
+    if not args.no_epi:
+        sim.set_sequence(epi)
+        sig_epi = torch.empty(epi.total_samples, 2, device=dev, dtype=torch.float64)
+        S_epi = epi.stepped_count()
+        sec_e, st_e = timed_runs(sim, gb, gb.GBS_GROUPED, args.steps, args.warmup, m_out, sig_epi)
+        out["epi"] = {"grouped_ms": sec_e * 1e3, "grouped_iso_steps_per_s": K * S_epi / sec_e,
+                      "stepped_steps": S_epi, "phases_ms": {k: st_e[-1][k] for k in
+                                                            ("ms_prepare", "ms_passes", "ms_adc_eval")}}
+        log(f"EPI grouped: {sec_e * 1e3:.2f} ms/step")
+        if not args.no_plain:
+            sec_p, _ = timed_runs(sim, gb, gb.GBS_PLAIN, 1, 0, m_out, sig_epi)
+            out["epi"].update({"plain_ms": sec_p * 1e3, "plain_iso_steps_per_s": K * S_epi / sec_p,
+                               "speedup_grouped_vs_plain": sec_p / sec_e})
+            log(f"EPI plain: {sec_p * 1e3:.1f} ms")
+
+    # ---- plain FSE: first shot (1/16 of the sequence) at full K -------------------------
+    if not args.no_plain:
+        shot = fse.head(66, name="fse-shot1")
+        sim.set_sequence(shot)
+        sig_shot = torch.empty(shot.total_samples, 2, device=dev, dtype=torch.float64)
+        sec_p, _ = timed_runs(sim, gb, gb.GBS_PLAIN, 1, 1, m_out, sig_shot)
+        rate_p = K * shot.stepped_count() / sec_p
+        out["plain"] = {"workload": "FSE first shot (17 RF + 16 ADC blocks, 67,384 stepped steps) at full K, FP64",
+                        "ms": sec_p * 1e3, "iso_steps_per_s": rate_p,
+                        "fse_full_s_extrapolated": K * S_fse / rate_p}
+        out["fse"]["speedup_grouped_vs_plain"] = value / rate_p
+        log(f"FSE plain shot: {sec_p * 1e3:.1f} ms, {rate_p:.3e} iso-steps/s")
+
+    # ---- FP64 oracle on the host cores, and the sampled error of the timed run -----------
+    if not args.no_cpu:
+        cb, idx, M_ref = cpu_baseline(ph, fse)
+        out["cpu_baseline"] = cb
+        out["fse"]["max_abs_dM_vs_oracle_sampled"] = float(np.max(np.abs(M_fse[:, idx] - M_ref)))
+        out["fse"]["oracle_sample_isochromats"] = int(idx.size)
+        log(f"cpu baseline {cb}")
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

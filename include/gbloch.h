@@ -61,6 +61,7 @@ extern "C" {
 #define GBS_GROUPED 1
 #define GBS_ASYNC 1u      /* enqueue on the context stream and return; no final synchronize */
 #define GBS_PLAIN_FP32 2u /* GBS_PLAIN: step in FP32 instead of FP64 (faster to state, less exact) */
+#define GBS_PROFILE 4u    /* time every sweep launch with HIP events (gbs_stats.pass_kernel_ms) */
 
 /*
  * One subsequence.  RF/ADC blocks cover raster steps
@@ -98,15 +99,16 @@ typedef struct gbs_stats {
     double ms_passes;      /* grouped: streaming passes over all isochromats */
     double ms_adc_eval;    /* grouped: ADC samples from group sums (Eq. 8, 10) */
     double ms_stepped;     /* plain stepping (PLAIN mode, or fallback blocks) */
-    int64_t n_passes;      /* grouped streaming passes (incl. emission-only) */
-    int64_t n_emit_only;   /* passes that only reduce group sums */
+    int64_t n_passes;      /* grouped operations (group transition and/or group sums) */
+    int64_t n_emit_only;   /* operations that only reduce group sums */
     int64_t n_rf_grouped;  /* with-RF blocks applied as group transitions */
     int64_t n_adc_grouped; /* with-ADC blocks evaluated from group sums */
     int64_t n_fallback;    /* RF/ADC blocks stepped per isochromat */
     int64_t n_distinct_rf; /* distinct (waveform, axis) combined transitions composed */
     int64_t n_b1zero;      /* RF-typed blocks with B1 == 0 folded into closed forms */
-    double pass_bytes;     /* algorithmic HBM bytes of the streaming passes */
-    double pass_ms_max;    /* (reserved) */
+    double pass_bytes;     /* algorithmic HBM bytes of the sweeps over all isochromats */
+    double pass_kernel_ms; /* GBS_PROFILE: sum of the sweep kernel durations */
+    int64_t n_sweeps;      /* sweep launches: runs of grouped operations applied in one pass */
 } gbs_stats;
 
 typedef struct gbs_ctx gbs_ctx;

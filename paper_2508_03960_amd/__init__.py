@@ -22,6 +22,7 @@ GBS_AX_X, GBS_AX_Y, GBS_AX_Z = 1, 2, 4
 GBS_PLAIN, GBS_GROUPED = 0, 1
 GBS_ASYNC = 1
 GBS_PLAIN_FP32 = 2
+GBS_PROFILE = 4
 
 EXPORTED = ("gbs_create", "gbs_destroy", "gbs_set_phantom", "gbs_set_sequence", "gbs_build_groups",
             "gbs_simulate", "gbs_get_info", "gbs_last_error", "gbs_strerror", "gbs_plan_summary")
@@ -48,16 +49,17 @@ class gbs_stats(ctypes.Structure):
                 ("n_emit_only", ctypes.c_int64), ("n_rf_grouped", ctypes.c_int64),
                 ("n_adc_grouped", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
                 ("n_distinct_rf", ctypes.c_int64), ("n_b1zero", ctypes.c_int64),
-                ("pass_bytes", ctypes.c_double), ("pass_ms_max", ctypes.c_double)]
+                ("pass_bytes", ctypes.c_double), ("pass_kernel_ms", ctypes.c_double),
+                ("n_sweeps", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
-def _load():
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2508_03960_amd.build`")
-    lib = ctypes.CDLL(LIB_PATH)
+def _load(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_2508_03960_amd.build`")
+    lib = ctypes.CDLL(path)
     P, I64, I32, U32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
     sig = {
         "gbs_create": ([ctypes.POINTER(P), ctypes.c_int, P], ctypes.c_int),

@@ -47,6 +47,38 @@ struct DevBuf {
     }
 };
 
+// Tables of one B1 = 0 map inside the per-simulate table arena (byte offsets).
+struct MapAlloc {
+    size_t x_off = 0, z_off = 0;
+    bool has_z = false;
+};
+
+// Everything about a grouped simulation that depends only on the sequence and
+// the groups: the pass schedule, the arena layout, the per-sample tables and
+// the job arrays (uploaded once).  Rebuilt after set_sequence/build_groups.
+struct GroupedPlan {
+    bool valid = false;
+    Plan plan;
+    bool zbuilt = false;
+    std::vector<size_t> rf_off, gsum_off;
+    std::vector<MapAlloc> pre_tab, emit_tab;
+    MapAlloc final_tab;
+    size_t gsum_count = 0;
+    int64_t max_rf_groups = 0, max_tab = 0;
+    int max_adc_groups = 0, max_adc_samples = 0;
+    int n_rf = 0, n_tab = 0, n_adc = 0;
+    size_t o_rf = 0, o_tab = 0, o_adc = 0, o_sweep = 0;
+    // execution: runs of grouped ops fused into sweeps, plain steps between
+    struct Seg {
+        int op_begin, op_end, need;
+        bool write_m;
+        double bytes_per_iso;
+    };
+    std::vector<Seg> segs;
+    std::vector<std::pair<int, int>> exec;  // (0, segment) or (1, index into plan.ops)
+    int64_t n_ops = 0;
+};
+
 }  // namespace
 
 struct gbs_ctx {
@@ -73,6 +105,10 @@ struct gbs_ctx {
     std::vector<char> host_jobs;  // kept alive until the next call
     std::vector<double2> host_samp;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> pev;  // GBS_PROFILE: one (start, stop) pair per pass launch
+    GroupedPlan gp;
+    bool pplan_valid = false;
+    Plan pplan;  // plain schedule
 };
 
 static int fail(gbs_ctx *c, int code, const std::string &msg) {
@@ -149,6 +185,7 @@ int gbs_destroy(gbs_ctx *ctx) {
     }
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &e : ctx->pev) (void)hipEventDestroy(e);
     delete ctx;
     return GBS_OK;
 }
@@ -162,6 +199,7 @@ int gbs_set_phantom(gbs_ctx *ctx, int64_t K, const float *x, const float *y, con
     HIPCHK(hipSetDevice(ctx->device));
     ctx->has_ph = false;
     ctx->groups_valid = false;
+    ctx->gp.valid = false;
     PhantomPtrs ph{x, y, z, t1, t2, df_hz, m0};
     ALLOC(ctx->flag, 256);
     HIPCHK(launch_fill_f64(ctx->flag.as<double>(), 1, ctx->stream));
@@ -191,6 +229,8 @@ int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, co
             return fail(ctx, GBS_E_INVALID, "non-finite waveform sample at step " + std::to_string(j));
     HIPCHK(hipSetDevice(ctx->device));
     ctx->has_seq = false;
+    ctx->gp.valid = false;
+    ctx->pplan_valid = false;
     copy_sequence(ctx->seq, blocks, n_blocks, rf_re, rf_im, gx, gy, gz, total_steps, adc_idx, total_samples, dt);
     ctx->cls = classify(ctx->seq);
     std::vector<StepW> w((size_t)total_steps);
@@ -214,6 +254,7 @@ int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
     if (!(axes & GBS_AX_X) || (axes & ~7u)) return fail(ctx, GBS_E_INVALID, "axes must include GBS_AX_X and only X|Y|Z");
     HIPCHK(hipSetDevice(ctx->device));
     ctx->groups_valid = false;
+    ctx->gp.valid = false;
     const int64_t K = ctx->K;
     const int64_t Kpad = (K + 1023) / 1024 * 1024;
     const size_t scratch_bytes = group_scratch_bytes(K) + 4096;
@@ -354,13 +395,17 @@ PlainArgs step_args(gbs_ctx *ctx, const StepOp &op, const PhantomPtrs &ph, int64
 static int run_plain(gbs_ctx *ctx, const float *m_init, float *m_out, double *sig_out, bool fp32,
                      gbs_stats *st) {
     const int64_t K = ctx->K;
-    Plan plan = plan_plain(ctx->seq);
-    if (plan.ops.empty()) {
-        Op op;
-        op.kind = 1;
-        op.step = StepOp{};
-        plan.ops.push_back(op);
+    if (!ctx->pplan_valid) {
+        ctx->pplan = plan_plain(ctx->seq);
+        if (ctx->pplan.ops.empty()) {  // still write (0, 0, M0) or the initial state out
+            Op op;
+            op.kind = 1;
+            op.step = StepOp{};
+            ctx->pplan.ops.push_back(op);
+        }
+        ctx->pplan_valid = true;
     }
+    const Plan &plan = ctx->pplan;
     const int grid = plain_grid(K);
     ALLOC(ctx->partial, sizeof(double2) * (size_t)grid * kMaxSamplesPerLaunch);
     float *ox = m_out, *oy = m_out + K, *oz = m_out + 2 * K;
@@ -385,47 +430,27 @@ static int run_plain(gbs_ctx *ctx, const float *m_init, float *m_out, double *si
 
 namespace {
 
-// Device pointers of the tables of one B1 = 0 map.
-struct MapAlloc {
-    size_t x_off = 0, z_off = 0;
-    bool has_z = false;
-};
-
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 }  // namespace
 
-static double pass_bytes(const PassArgs &a) {
-    // algorithmic HBM bytes per isochromat of one pass (mirrors k_pass's loads and stores)
-    const bool need_mz = a.write_m && (a.has_pre || a.rf_axis >= 0);
-    const bool need_gx = a.has_pre || a.emit_axis >= 0 || a.rf_axis == 0;
-    const bool need_gz = a.rf_axis == 2 || a.emit_axis == 2 || (a.has_pre && a.pre.ztab) ||
-                         (a.emit_axis >= 0 && a.emit.ztab);
-    const bool need_gy = a.rf_axis == 1 || a.emit_axis == 1;
-    const bool need_y = (a.has_pre && a.pre.cy != 0.0) || (a.emit_axis >= 0 && a.emit.cy != 0.0);
-    const bool need_z = (a.has_pre && a.pre.cz != 0.0) || (a.emit_axis >= 0 && a.emit.cz != 0.0);
-    double b = 8.0;  // Mx, My read
-    if (need_mz) b += 8.0;
-    if (a.write_m) b += need_mz ? 12.0 : 8.0;
-    b += 4.0 * (need_gx + need_gy + need_gz + need_y + need_z);
-    return b;
-}
-
-static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *sig_out, gbs_stats *st) {
-    const int64_t K = ctx->K;
+// Build the cached grouped plan: schedule, arena layout, sample tables and
+// job arrays (device).  Host work only once per (sequence, groups).
+static int build_grouped_plan(gbs_ctx *ctx) {
+    GroupedPlan &g = ctx->gp;
     const HostSeq &s = ctx->seq;
-    Plan plan = plan_grouped(s, ctx->cls, ctx->axes);
-    const bool zbuilt = (ctx->axes & GBS_AX_Z) != 0;
-    const int64_t Gx = ctx->ng[0], Gz = zbuilt ? ctx->ng[2] : 0;
+    g = GroupedPlan{};
+    g.plan = plan_grouped(s, ctx->cls, ctx->axes);
+    const Plan &plan = g.plan;
+    g.zbuilt = (ctx->axes & GBS_AX_Z) != 0;
+    const int64_t Gx = ctx->ng[0], Gz = g.zbuilt ? ctx->ng[2] : 0;
 
-    // ---- arena layout -------------------------------------------------------
     size_t off = 0;
-    std::vector<size_t> rf_off(plan.rf.size());
-    int64_t max_rf_groups = 0;
+    g.rf_off.resize(plan.rf.size());
     for (size_t i = 0; i < plan.rf.size(); ++i) {
-        rf_off[i] = off;
+        g.rf_off[i] = off;
         const int64_t G = ctx->ng[plan.rf[i].axis];
-        max_rf_groups = std::max(max_rf_groups, G);
+        g.max_rf_groups = std::max(g.max_rf_groups, G);
         off = align256(off + sizeof(float4) * 3 * (size_t)G);
     }
     std::vector<TabJob> tjobs;
@@ -434,7 +459,7 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
         r.x_off = off;
         off = align256(off + sizeof(float4) * (size_t)Gx);
         tjobs.push_back(TabJob{0, (int32_t)Gx, m.tau, kGammaBar * m.m[0], (void *)r.x_off});
-        if (zbuilt && m.m[2] != 0.0) {
+        if (g.zbuilt && m.m[2] != 0.0) {
             r.has_z = true;
             r.z_off = off;
             off = align256(off + sizeof(float2) * (size_t)Gz);
@@ -442,35 +467,35 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
         }
         return r;
     };
-    std::vector<MapAlloc> pre_tab(plan.ops.size()), emit_tab(plan.ops.size());
+    g.pre_tab.assign(plan.ops.size(), MapAlloc{});
+    g.emit_tab.assign(plan.ops.size(), MapAlloc{});
     for (size_t i = 0; i < plan.ops.size(); ++i) {
         const Op &op = plan.ops[i];
         if (op.kind != 0) continue;
-        if (op.pass.has_pre) pre_tab[i] = alloc_map(op.pass.pre);
-        if (op.pass.emit_axis >= 0) emit_tab[i] = alloc_map(op.pass.emit);
+        if (op.pass.has_pre) g.pre_tab[i] = alloc_map(op.pass.pre);
+        if (op.pass.emit_axis >= 0) g.emit_tab[i] = alloc_map(op.pass.emit);
     }
-    MapAlloc final_tab;
-    if (plan.final_pass) final_tab = alloc_map(plan.final_map);
+    if (plan.final_pass) g.final_tab = alloc_map(plan.final_map);
     const size_t tab_bytes = off;
+    g.max_tab = std::max<int64_t>(Gx, Gz);
 
-    size_t goff = 0;
-    std::vector<size_t> gsum_off(plan.adc.size()), samp_off(plan.adc.size());
-    size_t soff = 0;
-    int max_adc_groups = 0, max_adc_samples = 0;
+    size_t goff = 0, soff = 0;
+    g.gsum_off.resize(plan.adc.size());
+    std::vector<size_t> samp_off(plan.adc.size());
     for (size_t i = 0; i < plan.adc.size(); ++i) {
         const AdcJob &j = plan.adc[i];
-        gsum_off[i] = goff;
+        g.gsum_off[i] = goff;
         goff += (size_t)ctx->ng[j.axis];
         samp_off[i] = soff;
         soff += (size_t)s.blocks[j.block].n_samples;
-        max_adc_groups = std::max(max_adc_groups, (int)ctx->ng[j.axis]);
-        max_adc_samples = std::max(max_adc_samples, (int)s.blocks[j.block].n_samples);
+        g.max_adc_groups = std::max(g.max_adc_groups, (int)ctx->ng[j.axis]);
+        g.max_adc_samples = std::max(g.max_adc_samples, (int)s.blocks[j.block].n_samples);
     }
+    g.gsum_count = goff;
     ALLOC(ctx->tabs, tab_bytes);
     ALLOC(ctx->gsum, sizeof(double2) * goff);
     ALLOC(ctx->samp, sizeof(double2) * soff);
-    const int grid = plain_grid(K);
-    if (plan.n_fallback) ALLOC(ctx->partial, sizeof(double2) * (size_t)grid * kMaxSamplesPerLaunch);
+    if (plan.n_fallback) ALLOC(ctx->partial, sizeof(double2) * (size_t)plain_grid(ctx->K) * kMaxSamplesPerLaunch);
     char *tb = ctx->tabs.as<char>();
     for (auto &t : tjobs) t.out = tb + (size_t)t.out;
 
@@ -480,12 +505,12 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     for (size_t i = 0; i < plan.adc.size(); ++i) {
         const AdcJob &j = plan.adc[i];
         const gbs_block &b = s.blocks[j.block];
-        const std::vector<float> &g = j.axis == 0 ? s.gx : j.axis == 1 ? s.gy : s.gz;
+        const std::vector<float> &gw = j.axis == 0 ? s.gx : j.axis == 1 ? s.gy : s.gz;
         double m = 0.0;
         int64_t step = 0;
         for (int32_t n = 0; n < b.n_samples; ++n) {
             const int32_t tgt = s.adc_idx[b.sample_offset + n];
-            for (; step < tgt; ++step) m += (double)g[b.step_offset + step] * s.dt;
+            for (; step < tgt; ++step) m += (double)gw[b.step_offset + step] * s.dt;
             hs[samp_off[i] + n] = double2{(double)tgt * s.dt, kGammaBar * m};
         }
     }
@@ -495,50 +520,129 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     for (size_t i = 0; i < plan.rf.size(); ++i) {
         const RfJob &r = plan.rf[i];
         rj[i] = RfJobDev{r.axis, (int32_t)r.n_steps, ctx->ng[r.axis], ctx->d_wave.as<StepW>() + r.step_offset,
-                         ctx->gtab[r.axis].as<float4>(), (float4 *)(tb + rf_off[i])};
+                         ctx->gtab[r.axis].as<float4>(), (float4 *)(tb + g.rf_off[i])};
     }
     std::vector<AdcJobDev> aj(plan.adc.size());
     for (size_t i = 0; i < plan.adc.size(); ++i) {
         const AdcJob &j = plan.adc[i];
         const gbs_block &b = s.blocks[j.block];
-        aj[i] = AdcJobDev{b.n_samples, (int32_t)ctx->ng[j.axis], ctx->gsum.as<double2>() + gsum_off[i],
-                          ctx->gtab[j.axis].as<float4>(), ctx->samp.as<double2>() + samp_off[i],
-                          sig_out + 2 * b.sample_offset};
+        aj[i] = AdcJobDev{b.n_samples, (int32_t)ctx->ng[j.axis], ctx->gsum.as<double2>() + g.gsum_off[i],
+                          ctx->gtab[j.axis].as<float4>(), ctx->samp.as<double2>() + samp_off[i], b.sample_offset};
     }
-    const size_t o_rf = 0, o_tab = align256(sizeof(RfJobDev) * rj.size());
-    const size_t o_adc = o_tab + align256(sizeof(TabJob) * tjobs.size());
-    const size_t jbytes = o_adc + sizeof(AdcJobDev) * aj.size();
-    ctx->host_jobs.assign(jbytes, 0);
-    if (!rj.empty()) std::memcpy(ctx->host_jobs.data() + o_rf, rj.data(), sizeof(RfJobDev) * rj.size());
-    if (!tjobs.empty()) std::memcpy(ctx->host_jobs.data() + o_tab, tjobs.data(), sizeof(TabJob) * tjobs.size());
-    if (!aj.empty()) std::memcpy(ctx->host_jobs.data() + o_adc, aj.data(), sizeof(AdcJobDev) * aj.size());
-    ALLOC(ctx->jobs, jbytes);
-    HIPCHK(hipMemcpyAsync(ctx->jobs.p, ctx->host_jobs.data(), jbytes, hipMemcpyHostToDevice, ctx->stream));
-    if (soff)
-        HIPCHK(hipMemcpyAsync(ctx->samp.p, hs.data(), sizeof(double2) * soff, hipMemcpyHostToDevice, ctx->stream));
-    char *jb = ctx->jobs.as<char>();
-
-    // ---- prepare: combined transitions (Eq. 7) and map tables --------------
-    HIPCHK(launch_fill_f64((double *)ctx->gsum.p, 2 * (int64_t)goff, ctx->stream));
-    HIPCHK(launch_compose((const RfJobDev *)(jb + o_rf), (int)rj.size(), max_rf_groups, s.dt, ctx->stream));
-    int64_t max_tab = std::max<int64_t>(Gx, Gz);
-    HIPCHK(launch_tables((const TabJob *)(jb + o_tab), (int)tjobs.size(), (int)max_tab,
-                         ctx->gtab[0].as<float4>(), zbuilt ? ctx->gtab[2].as<float4>() : nullptr, ctx->stream));
-    if (st) HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
-
-    // ---- streaming passes ---------------------------------------------------
-    float *mx = ctx->ms[0].as<float>(), *my = ctx->ms[1].as<float>(), *mz = ctx->ms[2].as<float>();
-    HIPCHK(launch_init_state(K, ctx->Kpad, ctx->perm.as<int32_t>(), m_init, m_init ? m_init + K : nullptr,
-                             m_init ? m_init + 2 * K : nullptr, ctx->m0i.as<float>(), mx, my, mz, ctx->stream));
+    // grouped ops in schedule order; consecutive ones fuse into one sweep
     auto map_tabs = [&](const Map &m, const MapAlloc &al) {
         MapTabs t{};
         t.xtab = (const float4 *)(tb + al.x_off);
         t.ztab = al.has_z ? (const float2 *)(tb + al.z_off) : nullptr;
         t.cy = kGammaBar * m.m[1];
-        t.cz = (!zbuilt) ? kGammaBar * m.m[2] : 0.0;
+        t.cz = g.zbuilt ? 0.0 : kGammaBar * m.m[2];
         return t;
     };
-    PassArgs base{};
+    std::vector<SweepOp> sops;
+    auto add_op = [&](const PassOp &p, const MapAlloc &pre_al, const MapAlloc &emit_al) {
+        SweepOp o{};
+        o.flags = (p.has_pre ? kOpPre : 0) | (p.rf_axis >= 0 ? kOpRf : 0) | (p.emit_axis >= 0 ? kOpEmit : 0);
+        o.rf_axis = p.rf_axis;
+        o.emit_axis = p.emit_axis;
+        if (p.has_pre) o.pre = map_tabs(p.pre, pre_al);
+        if (p.rf_axis >= 0) o.ttab = (const float4 *)(tb + g.rf_off[p.rf_id]);
+        if (p.emit_axis >= 0) {
+            o.emit = map_tabs(p.emit, emit_al);
+            o.gsum = ctx->gsum.as<double2>() + g.gsum_off[p.adc_job];
+        }
+        int need = 0;
+        if (p.has_pre || p.rf_axis >= 0) need |= kNeedMz;
+        if (p.has_pre || p.emit_axis >= 0 || p.rf_axis == 0) need |= kNeedGx;
+        if (p.rf_axis == 1 || p.emit_axis == 1) need |= kNeedGy;
+        if (p.rf_axis == 2 || p.emit_axis == 2 || (p.has_pre && o.pre.ztab) || (p.emit_axis >= 0 && o.emit.ztab))
+            need |= kNeedGz;
+        if ((p.has_pre && o.pre.cy != 0.0) || (p.emit_axis >= 0 && o.emit.cy != 0.0)) need |= kNeedY;
+        if ((p.has_pre && o.pre.cz != 0.0) || (p.emit_axis >= 0 && o.emit.cz != 0.0)) need |= kNeedZ;
+        if (g.segs.empty() || g.exec.empty() || g.exec.back().first != 0) {
+            g.segs.push_back(GroupedPlan::Seg{(int)sops.size(), (int)sops.size(), 0, false, 0.0});
+            g.exec.push_back({0, (int)g.segs.size() - 1});
+        }
+        GroupedPlan::Seg &sg = g.segs.back();
+        sg.op_end = (int)sops.size() + 1;
+        sg.need |= need;
+        sg.write_m = sg.write_m || (need & kNeedMz);
+        sops.push_back(o);
+    };
+    for (size_t i = 0; i < plan.ops.size(); ++i) {
+        const Op &op = plan.ops[i];
+        if (op.kind == 0)
+            add_op(op.pass, g.pre_tab[i], g.emit_tab[i]);
+        else
+            g.exec.push_back({1, (int)i});
+    }
+    if (plan.final_pass) {
+        PassOp f;
+        f.has_pre = true;
+        f.pre = plan.final_map;
+        f.write_m = true;
+        add_op(f, g.final_tab, MapAlloc{});
+    }
+    for (auto &sg : g.segs) {
+        const int n = sg.need;
+        double b = 8.0 + ((n & kNeedMz) ? 8.0 : 0.0);
+        b += 4.0 * (!!(n & kNeedGx) + !!(n & kNeedGy) + !!(n & kNeedGz) + !!(n & kNeedY) + !!(n & kNeedZ));
+        if (sg.write_m) b += (n & kNeedMz) ? 12.0 : 8.0;
+        sg.bytes_per_iso = b;
+    }
+    g.n_ops = (int64_t)sops.size();
+
+    g.n_rf = (int)rj.size();
+    g.n_tab = (int)tjobs.size();
+    g.n_adc = (int)aj.size();
+    g.o_rf = 0;
+    g.o_tab = align256(sizeof(RfJobDev) * rj.size());
+    g.o_adc = g.o_tab + align256(sizeof(TabJob) * tjobs.size());
+    g.o_sweep = g.o_adc + align256(sizeof(AdcJobDev) * aj.size());
+    const size_t jbytes = g.o_sweep + sizeof(SweepOp) * sops.size();
+    ctx->host_jobs.assign(jbytes, 0);
+    if (!rj.empty()) std::memcpy(ctx->host_jobs.data() + g.o_rf, rj.data(), sizeof(RfJobDev) * rj.size());
+    if (!tjobs.empty()) std::memcpy(ctx->host_jobs.data() + g.o_tab, tjobs.data(), sizeof(TabJob) * tjobs.size());
+    if (!aj.empty()) std::memcpy(ctx->host_jobs.data() + g.o_adc, aj.data(), sizeof(AdcJobDev) * aj.size());
+    if (!sops.empty()) std::memcpy(ctx->host_jobs.data() + g.o_sweep, sops.data(), sizeof(SweepOp) * sops.size());
+    ALLOC(ctx->jobs, jbytes);
+    HIPCHK(hipMemcpy(ctx->jobs.p, ctx->host_jobs.data(), jbytes, hipMemcpyHostToDevice));
+    if (soff) HIPCHK(hipMemcpy(ctx->samp.p, hs.data(), sizeof(double2) * soff, hipMemcpyHostToDevice));
+    g.valid = true;
+    return GBS_OK;
+}
+
+static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *sig_out, bool profile,
+                       gbs_stats *st, int *n_timed) {
+    const int64_t K = ctx->K;
+    const HostSeq &s = ctx->seq;
+    if (!ctx->gp.valid) {
+        int rc = build_grouped_plan(ctx);
+        if (rc != GBS_OK) return rc;
+    }
+    const GroupedPlan &g = ctx->gp;
+    const Plan &plan = g.plan;
+    const bool zbuilt = g.zbuilt;
+    const int grid = plain_grid(K);
+    char *tb = ctx->tabs.as<char>();
+    char *jb = ctx->jobs.as<char>();
+    const auto &rf_off = g.rf_off;
+    const auto &gsum_off = g.gsum_off;
+    const auto &pre_tab = g.pre_tab;
+    const auto &emit_tab = g.emit_tab;
+    const MapAlloc &final_tab = g.final_tab;
+
+    // ---- prepare: combined transitions (Eq. 7) and map tables --------------
+    HIPCHK(launch_fill_f64((double *)ctx->gsum.p, 2 * (int64_t)g.gsum_count, ctx->stream));
+    HIPCHK(launch_compose((const RfJobDev *)(jb + g.o_rf), g.n_rf, g.max_rf_groups, s.dt, ctx->stream));
+    HIPCHK(launch_tables((const TabJob *)(jb + g.o_tab), g.n_tab, (int)g.max_tab, ctx->gtab[0].as<float4>(),
+                         zbuilt ? ctx->gtab[2].as<float4>() : nullptr, ctx->stream));
+    if (st) HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
+
+    // ---- sweeps of grouped ops (plain stepping between them) ----------------
+    float *mx = ctx->ms[0].as<float>(), *my = ctx->ms[1].as<float>(), *mz = ctx->ms[2].as<float>();
+    HIPCHK(launch_init_state(K, ctx->Kpad, ctx->perm.as<int32_t>(), m_init, m_init ? m_init + K : nullptr,
+                             m_init ? m_init + 2 * K : nullptr, ctx->m0i.as<float>(), mx, my, mz, ctx->stream));
+    SweepArgs base{};
     base.n4 = (K + 3) / 4;
     base.mx = (float4 *)mx;
     base.my = (float4 *)my;
@@ -549,28 +653,33 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     base.gid_z = ctx->gid[2].as<int4>();
     base.yv = ctx->yi.as<float4>();
     base.zv = ctx->zi.as<float4>();
-    base.rf_axis = -1;
-    base.emit_axis = -1;
     const PhantomPtrs iph{ctx->xi.as<float>(), ctx->yi.as<float>(), ctx->zi.as<float>(), ctx->t1i.as<float>(),
                           ctx->t2i.as<float>(), ctx->dfi.as<float>(), ctx->m0i.as<float>()};
+    if (profile) {
+        const size_t need = 2 * (g.segs.size() + 1);
+        while (ctx->pev.size() < need) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            ctx->pev.push_back(e);
+        }
+    }
+    int timed = 0;
     double bytes = 0.0;
-    for (size_t i = 0; i < plan.ops.size(); ++i) {
-        const Op &op = plan.ops[i];
-        if (op.kind == 0) {
-            PassArgs a = base;
-            a.has_pre = op.pass.has_pre ? 1 : 0;
-            if (op.pass.has_pre) a.pre = map_tabs(op.pass.pre, pre_tab[i]);
-            a.rf_axis = op.pass.rf_axis;
-            a.ttab = op.pass.rf_axis >= 0 ? (const float4 *)(tb + rf_off[op.pass.rf_id]) : nullptr;
-            a.write_m = op.pass.write_m ? 1 : 0;
-            a.emit_axis = op.pass.emit_axis;
-            if (op.pass.emit_axis >= 0) {
-                a.emit = map_tabs(op.pass.emit, emit_tab[i]);
-                a.gsum = ctx->gsum.as<double2>() + gsum_off[op.pass.adc_job];
-            }
-            bytes += pass_bytes(a) * (double)K;
-            HIPCHK(launch_pass(a, ctx->stream));
+    const SweepOp *dev_ops = (const SweepOp *)(jb + g.o_sweep);
+    for (const auto &item : g.exec) {
+        if (item.first == 0) {
+            const GroupedPlan::Seg &sg = g.segs[item.second];
+            SweepArgs a = base;
+            a.ops = dev_ops + sg.op_begin;
+            a.n_ops = sg.op_end - sg.op_begin;
+            a.need = sg.need;
+            a.write_m = sg.write_m ? 1 : 0;
+            bytes += sg.bytes_per_iso * (double)K;
+            if (profile) HIPCHK(hipEventRecord(ctx->pev[2 * timed], ctx->stream));
+            HIPCHK(launch_sweep(a, ctx->stream));
+            if (profile) HIPCHK(hipEventRecord(ctx->pev[2 * timed++ + 1], ctx->stream));
         } else {
+            const Op &op = plan.ops[item.second];
             PlainArgs a = step_args(ctx, op.step, iph, K, mx, my, mz, mx, my, mz);
             const bool b1 = op.step.block >= 0 && ctx->cls[op.step.block].has_b1;
             HIPCHK(launch_plain(a, b1, false, grid, ctx->stream));
@@ -581,24 +690,18 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
             }
         }
     }
-    if (plan.final_pass) {
-        PassArgs a = base;
-        a.has_pre = 1;
-        a.pre = map_tabs(plan.final_map, final_tab);
-        a.write_m = 1;
-        bytes += pass_bytes(a) * (double)K;
-        HIPCHK(launch_pass(a, ctx->stream));
-    }
+    *n_timed = timed;
     if (st) HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
 
     // ---- ADC samples from the group sums (Eq. 8, Eq. 10) --------------------
-    HIPCHK(launch_adc_eval((const AdcJobDev *)(jb + o_adc), (int)aj.size(), max_adc_groups, max_adc_samples,
-                           ctx->stream));
+    HIPCHK(launch_adc_eval((const AdcJobDev *)(jb + g.o_adc), g.n_adc, g.max_adc_groups, g.max_adc_samples,
+                           sig_out, ctx->stream));
     if (st) HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
     HIPCHK(launch_scatter_state(K, ctx->perm.as<int32_t>(), mx, my, mz, m_out, m_out + K, m_out + 2 * K,
                                 ctx->stream));
     if (st) {
-        st->n_passes = plan.n_passes + (plan.final_pass ? 1 : 0);
+        st->n_passes = g.n_ops;
+        st->n_sweeps = (int64_t)g.segs.size();
         st->n_emit_only = plan.n_emit_only;
         st->n_rf_grouped = plan.n_rf_grouped;
         st->n_adc_grouped = plan.n_adc_grouped;
@@ -619,7 +722,7 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
     if (!m_out || (ctx->seq.total_samples > 0 && !sig_out)) return fail(ctx, GBS_E_INVALID, "null output");
     if (mode == GBS_GROUPED && !ctx->groups_valid)
         return fail(ctx, GBS_E_STATE, "GBS_GROUPED needs gbs_build_groups on the current phantom");
-    if (flags & ~(GBS_ASYNC | GBS_PLAIN_FP32)) return fail(ctx, GBS_E_INVALID, "unknown flags");
+    if (flags & ~(GBS_ASYNC | GBS_PLAIN_FP32 | GBS_PROFILE)) return fail(ctx, GBS_E_INVALID, "unknown flags");
     HIPCHK(hipSetDevice(ctx->device));
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
@@ -627,11 +730,13 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
     }
     if (ctx->seq.total_samples > 0)
         HIPCHK(launch_fill_f64(sig_out, 2 * ctx->seq.total_samples, ctx->stream));
+    const bool profile = (flags & GBS_PROFILE) != 0;
+    int n_timed = 0;
     int rc = mode == GBS_PLAIN ? run_plain(ctx, m_init, m_out, sig_out, (flags & GBS_PLAIN_FP32) != 0, stats)
-                               : run_grouped(ctx, m_init, m_out, sig_out, stats);
+                               : run_grouped(ctx, m_init, m_out, sig_out, profile, stats, &n_timed);
     if (rc != GBS_OK) return rc;
     if (stats) HIPCHK(hipEventRecord(ctx->ev[4], ctx->stream));
-    if (!(flags & GBS_ASYNC) || stats) {
+    if (!(flags & GBS_ASYNC) || stats || profile) {
         HIPCHK(hipStreamSynchronize(ctx->stream));
         HIPCHK(hipGetLastError());
     }
@@ -648,6 +753,12 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
             stats->ms_passes = ms;
             HIPCHK(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]));
             stats->ms_adc_eval = ms;
+            double sum = 0.0;
+            for (int i = 0; i < n_timed; ++i) {
+                HIPCHK(hipEventElapsedTime(&ms, ctx->pev[2 * i], ctx->pev[2 * i + 1]));
+                sum += ms;
+            }
+            stats->pass_kernel_ms = sum;
         }
     }
     return GBS_OK;

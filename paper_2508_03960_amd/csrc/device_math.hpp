@@ -9,30 +9,13 @@
 namespace gbs {
 
 // sin and cos of 2*pi*rev for a phase given in revolutions (cycles).  The
-// phase is reduced in FP64 to the nearest quarter turn, the remainder
-// |t| <= pi/4 is evaluated in FP32 with the Taylor series of sin (to t^9)
-// and cos (to t^10), whose truncation errors are below 2e-9 on that range.
+// phase is reduced modulo one turn in FP64, then evaluated by the hardware
+// V_SIN_F32 / V_COS_F32, whose input is in revolutions (measured maximum
+// absolute error on [-0.5, 0.5]: 1.24e-7).
 __device__ __forceinline__ void sincos_rev(double rev, float *s_out, float *c_out) {
-    const double q4 = 4.0 * (rev - rint(rev));  // quarter turns in [-2, 2]
-    const double q = rint(q4);
-    const float t = (float)((q4 - q) * 1.5707963267948966192313216916398);
-    const float t2 = t * t;
-    float sp = fmaf(t2, 2.7557319223985891e-6f, -1.9841269841269841e-4f);
-    sp = fmaf(t2, sp, 8.3333333333333333e-3f);
-    sp = fmaf(t2, sp, -1.6666666666666667e-1f);
-    sp = fmaf(t2 * t, sp, t);
-    float cp = fmaf(t2, -2.7557319223985891e-7f, 2.4801587301587302e-5f);
-    cp = fmaf(t2, cp, -1.3888888888888889e-3f);
-    cp = fmaf(t2, cp, 4.1666666666666667e-2f);
-    cp = fmaf(t2, cp, -0.5f);
-    cp = fmaf(t2, cp, 1.0f);
-    const int k = ((int)q) & 3;  // rotate (sin t, cos t) by k quarter turns
-    float s = sp, c = cp;
-    if (k == 1) { s = cp; c = -sp; }
-    else if (k == 2) { s = -sp; c = -cp; }
-    else if (k == 3) { s = -cp; c = sp; }
-    *s_out = s;
-    *c_out = c;
+    const float r = (float)(rev - rint(rev));
+    *s_out = __builtin_amdgcn_sinf(r);
+    *c_out = __builtin_amdgcn_cosf(r);
 }
 
 // ---- wavefront (64-lane) sums through DPP; the total lands in lane 63 ----

@@ -7,10 +7,11 @@
 //  k_tables    per-group factors of the closed-form B1 = 0 maps (Eq. 4, 5):
 //              x-groups carry decay, off-resonance and x phase; z-groups the
 //              z phase.
-//  k_pass      one coalesced streaming pass over the group-sorted isochromats:
-//              pre map, group transition, write back, and the group sums of
-//              the next with-ADC subsequence (Eq. 9) reduced per run of equal
-//              group ids, then across the wavefront, then FP64 atomics.
+//  k_sweep     one coalesced sweep over the group-sorted isochromats that
+//              applies a run of grouped operations with the state in
+//              registers: pre maps, group transitions, and the group sums of
+//              each with-ADC subsequence (Eq. 9) reduced across the wavefront
+//              (one group per wavefront in the common case), then FP64 atomics.
 //  k_adc_eval  every ADC sample from the group sums (Eq. 8 with Eq. 10), FP64
 //              phase reduced to a quarter turn, FP64 accumulation.
 #include "device_math.hpp"
@@ -180,29 +181,6 @@ __device__ __forceinline__ void cmul(float &ar, float &ai, float br, float bi) {
     ar = r;
 }
 
-// The factor a (Mxy <- a Mxy) of a B1 = 0 map for one isochromat.
-__device__ __forceinline__ void map_factor(const MapTabs &m, int gx, int gz, float y, float z,
-                                           float &ar, float &ai, float &e1) {
-    const float4 f = m.xtab[gx];
-    ar = f.x;
-    ai = f.y;
-    e1 = f.z;
-    if (m.ztab) {
-        const float2 zf = m.ztab[gz];
-        cmul(ar, ai, zf.x, zf.y);
-    }
-    if (m.cy != 0.0) {
-        float s, c;
-        sincos_rev(m.cy * (double)y, &s, &c);
-        cmul(ar, ai, c, -s);
-    }
-    if (m.cz != 0.0) {
-        float s, c;
-        sincos_rev(m.cz * (double)z, &s, &c);
-        cmul(ar, ai, c, -s);
-    }
-}
-
 __device__ __forceinline__ void ld4(const float4 *p, int64_t i, float v[4]) {
     const float4 t = p[i];
     v[0] = t.x;
@@ -218,6 +196,89 @@ __device__ __forceinline__ void ld4i(const int4 *p, int64_t i, int v[4]) {
     v[3] = t.w;
 }
 
+__device__ __forceinline__ bool same4(const int g[4]) { return g[0] == g[1] && g[0] == g[2] && g[0] == g[3]; }
+
+// Wave-uniform read of a table that no kernel writes while it runs: through
+// the constant address space, so a uniform index becomes one scalar load.
+// Table gathers and group-sum atomics through the global address space (the
+// pointers come out of op descriptors and would otherwise be flat accesses).
+typedef const __attribute__((address_space(1))) float *global_f32_ptr;
+__device__ __forceinline__ float4 gather_row(const float4 *tab, int g) {
+    global_f32_ptr p = (global_f32_ptr)(tab + g);
+    return make_float4(p[0], p[1], p[2], p[3]);
+}
+__device__ __forceinline__ float2 gather_row(const float2 *tab, int g) {
+    global_f32_ptr p = (global_f32_ptr)(tab + g);
+    return make_float2(p[0], p[1]);
+}
+__device__ __forceinline__ void group_add(double *p, double v) {
+    __builtin_amdgcn_global_atomic_fadd_f64((__attribute__((address_space(1))) double *)p, v);
+}
+
+typedef const __attribute__((address_space(4))) float *const_f32_ptr;
+__device__ __forceinline__ float4 uniform_row(const float4 *tab, int g) {
+    const_f32_ptr p = (const_f32_ptr)(tab + g);
+    return make_float4(p[0], p[1], p[2], p[3]);
+}
+__device__ __forceinline__ float2 uniform_row(const float2 *tab, int g) {
+    const_f32_ptr p = (const_f32_ptr)(tab + g);
+    return make_float2(p[0], p[1]);
+}
+
+// Table rows of the thread's 4 isochromats.  Group ids are sorted runs, so
+// the whole wavefront usually shares one x-group (one scalar load) and a
+// thread's 4 neighbours usually share their other groups (one gather).
+template <class T>
+__device__ __forceinline__ void rows4(const T *__restrict__ tab, const int g[4], bool wave_uniform, int g_uni,
+                                      T out[4]) {
+    if (wave_uniform) {
+        const T v = uniform_row(tab, g_uni);
+        out[0] = out[1] = out[2] = out[3] = v;
+    } else if (same4(g)) {
+        const T v = gather_row(tab, g[0]);
+        out[0] = out[1] = out[2] = out[3] = v;
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) out[c] = gather_row(tab, g[c]);
+    }
+}
+
+// Mxy factor a and E1 of a B1 = 0 map for the thread's 4 isochromats.
+__device__ __forceinline__ void map_factor4(const MapTabs &m, const int gx[4], bool gx_uni, int gx0,
+                                            const int gz[4], const float y[4], const float z[4],
+                                            float ar[4], float ai[4], float e1[4]) {
+    float4 xf[4];
+    rows4(m.xtab, gx, gx_uni, gx0, xf);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        ar[c] = xf[c].x;
+        ai[c] = xf[c].y;
+        e1[c] = xf[c].z;
+    }
+    if (m.ztab) {
+        float2 zf[4];
+        rows4(m.ztab, gz, false, 0, zf);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cmul(ar[c], ai[c], zf[c].x, zf[c].y);
+    }
+    if (m.cy != 0.0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            float s, co;
+            sincos_rev(m.cy * (double)y[c], &s, &co);
+            cmul(ar[c], ai[c], co, -s);
+        }
+    }
+    if (m.cz != 0.0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            float s, co;
+            sincos_rev(m.cz * (double)z[c], &s, &co);
+            cmul(ar[c], ai[c], co, -s);
+        }
+    }
+}
+
 // Sum (vr, vi) per run of equal keys: within the thread, then across the
 // wavefront with a segmented inclusive scan; segment ends add to gsum.
 __device__ __forceinline__ void emit_runs(const int key[4], const float vr[4], const float vi[4],
@@ -228,8 +289,8 @@ __device__ __forceinline__ void emit_runs(const int key[4], const float vr[4], c
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             if (key[c] != k) {
-                atomicAdd(&gsum[k].x, sr);
-                atomicAdd(&gsum[k].y, si);
+                group_add(&gsum[k].x, sr);
+                group_add(&gsum[k].y, si);
                 sr = si = 0.0;
                 k = key[c];
             }
@@ -256,95 +317,152 @@ __device__ __forceinline__ void emit_runs(const int key[4], const float vr[4], c
     const int kn = __shfl_down(k, 1);
     const bool tail = (lane == 63) || (kn != k);
     if (tail && k >= 0) {
-        atomicAdd(&gsum[k].x, sr);
-        atomicAdd(&gsum[k].y, si);
+        group_add(&gsum[k].x, sr);
+        group_add(&gsum[k].y, si);
     }
 }
 
-__global__ __launch_bounds__(256) void k_pass(PassArgs a) {
+typedef const __attribute__((address_space(4))) uint64_t *const_u64_ptr;
+static_assert(sizeof(SweepOp) % 8 == 0, "SweepOp is read as 64-bit words");
+
+// The op descriptor is the same for every lane: read it through the constant
+// address space so that it arrives in scalar registers.
+__device__ __forceinline__ SweepOp load_op(const SweepOp *ops, int o) {
+    uint64_t w[sizeof(SweepOp) / 8];
+    const_u64_ptr p = (const_u64_ptr)(ops + o);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(SweepOp) / 8); ++i) w[i] = p[i];
+    SweepOp r;
+    __builtin_memcpy(&r, w, sizeof(SweepOp));
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     const int64_t i4 = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool act = i4 < a.n4;
-    const bool need_mz = a.write_m && (a.has_pre || a.rf_axis >= 0);
-    const bool need_gx = a.has_pre || a.emit_axis >= 0 || a.rf_axis == 0;
-    const bool need_gz = a.rf_axis == 2 || a.emit_axis == 2 || (a.has_pre && a.pre.ztab) ||
-                         (a.emit_axis >= 0 && a.emit.ztab);
-    const bool need_gy = a.rf_axis == 1 || a.emit_axis == 1;
-    const bool need_y = (a.has_pre && a.pre.cy != 0.0) || (a.emit_axis >= 0 && a.emit.cy != 0.0);
-    const bool need_z = (a.has_pre && a.pre.cz != 0.0) || (a.emit_axis >= 0 && a.emit.cz != 0.0);
-
+    const int need = a.need;
     float mx[4] = {0, 0, 0, 0}, my[4] = {0, 0, 0, 0}, mz[4] = {0, 0, 0, 0}, m0[4] = {0, 0, 0, 0};
     float yv[4] = {0, 0, 0, 0}, zv[4] = {0, 0, 0, 0};
-    int gx[4] = {0, 0, 0, 0}, gy[4] = {0, 0, 0, 0}, gz[4] = {0, 0, 0, 0};
+    int gx[4] = {-1, -1, -1, -1}, gy[4] = {0, 0, 0, 0}, gz[4] = {0, 0, 0, 0};
     if (act) {
         ld4(a.mx, i4, mx);
         ld4(a.my, i4, my);
-        if (need_mz) {
+        if (need & kNeedMz) {
             ld4(a.mz, i4, mz);
             ld4(a.m0, i4, m0);
         }
-        if (need_gx) ld4i(a.gid_x, i4, gx);
-        if (need_gy) ld4i(a.gid_y, i4, gy);
-        if (need_gz) ld4i(a.gid_z, i4, gz);
-        if (need_y) ld4(a.yv, i4, yv);
-        if (need_z) ld4(a.zv, i4, zv);
+        if (need & kNeedGx) ld4i(a.gid_x, i4, gx);
+        if (need & kNeedGy) ld4i(a.gid_y, i4, gy);
+        if (need & kNeedGz) ld4i(a.gid_z, i4, gz);
+        if (need & kNeedY) ld4(a.yv, i4, yv);
+        if (need & kNeedZ) ld4(a.zv, i4, zv);
     }
-    if (a.has_pre) {
+    // x-groups are contiguous runs in this order: is the wavefront inside one?
+    const int gx0 = __builtin_amdgcn_readfirstlane(gx[0]);
+    const bool gx_uni = __all(act && same4(gx) && gx[0] == gx0) != 0;
+    const int gxs[4] = {act ? gx[0] : 0, act ? gx[1] : 0, act ? gx[2] : 0, act ? gx[3] : 0};
+
+    for (int o = 0; o < a.n_ops; ++o) {
+        const SweepOp op = load_op(a.ops, o);
+        if (op.flags & kOpPre) {
+            float ar[4], ai[4], e1[4];
+            map_factor4(op.pre, gxs, gx_uni, gx0, gz, yv, zv, ar, ai, e1);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            float ar, ai, e1;
-            map_factor(a.pre, gx[c], gz[c], yv[c], zv[c], ar, ai, e1);
-            const float nx = mx[c] * ar - my[c] * ai;
-            const float ny = mx[c] * ai + my[c] * ar;
-            mx[c] = nx;
-            my[c] = ny;
-            mz[c] = fmaf(e1, mz[c] - m0[c], m0[c]);
+            for (int c = 0; c < 4; ++c) {
+                const float nx = mx[c] * ar[c] - my[c] * ai[c];
+                const float ny = mx[c] * ai[c] + my[c] * ar[c];
+                mx[c] = nx;
+                my[c] = ny;
+                mz[c] = fmaf(e1[c], mz[c] - m0[c], m0[c]);
+            }
         }
-    }
-    if (a.rf_axis >= 0) {
+        if (op.flags & kOpRf) {
+            const int *grf = op.rf_axis == 0 ? gxs : (op.rf_axis == 1 ? gy : gz);
+            const float4 *__restrict__ tt = op.ttab;
+            float4 r0[4], r1[4], r2[4];
+            if (op.rf_axis == 0 && gx_uni) {
+                const float4 u0 = uniform_row(tt, 3 * gx0), u1 = uniform_row(tt, 3 * gx0 + 1),
+                             u2 = uniform_row(tt, 3 * gx0 + 2);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int g = a.rf_axis == 0 ? gx[c] : (a.rf_axis == 1 ? gy[c] : gz[c]);
-            const float4 r0 = a.ttab[3 * g], r1 = a.ttab[3 * g + 1], r2 = a.ttab[3 * g + 2];
-            const float nx = fmaf(r0.x, mx[c], fmaf(r0.y, my[c], fmaf(r0.z, mz[c], r0.w * m0[c])));
-            const float ny = fmaf(r1.x, mx[c], fmaf(r1.y, my[c], fmaf(r1.z, mz[c], r1.w * m0[c])));
-            const float nz = fmaf(r2.x, mx[c], fmaf(r2.y, my[c], fmaf(r2.z, mz[c], r2.w * m0[c])));
-            mx[c] = nx;
-            my[c] = ny;
-            mz[c] = nz;
+                for (int c = 0; c < 4; ++c) {
+                    r0[c] = u0;
+                    r1[c] = u1;
+                    r2[c] = u2;
+                }
+            } else if (same4(grf)) {
+                const int g = grf[0];
+                const float4 u0 = gather_row(tt, 3 * g), u1 = gather_row(tt, 3 * g + 1),
+                             u2 = gather_row(tt, 3 * g + 2);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    r0[c] = u0;
+                    r1[c] = u1;
+                    r2[c] = u2;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    r0[c] = gather_row(tt, 3 * grf[c]);
+                    r1[c] = gather_row(tt, 3 * grf[c] + 1);
+                    r2[c] = gather_row(tt, 3 * grf[c] + 2);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float nx = fmaf(r0[c].x, mx[c], fmaf(r0[c].y, my[c], fmaf(r0[c].z, mz[c], r0[c].w * m0[c])));
+                const float ny = fmaf(r1[c].x, mx[c], fmaf(r1[c].y, my[c], fmaf(r1[c].z, mz[c], r1[c].w * m0[c])));
+                const float nz = fmaf(r2[c].x, mx[c], fmaf(r2[c].y, my[c], fmaf(r2[c].z, mz[c], r2[c].w * m0[c])));
+                mx[c] = nx;
+                my[c] = ny;
+                mz[c] = nz;
+            }
+        }
+        if (op.flags & kOpEmit) {
+            float ar[4], ai[4], e1[4], vr[4], vi[4];
+            map_factor4(op.emit, gxs, gx_uni, gx0, gz, yv, zv, ar, ai, e1);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                vr[c] = act ? mx[c] * ar[c] - my[c] * ai[c] : 0.f;
+                vi[c] = act ? mx[c] * ai[c] + my[c] * ar[c] : 0.f;
+            }
+            if (op.emit_axis == 0 && gx_uni) {
+                // one group for the whole wavefront: DPP sum, one FP64 atomic pair
+                float sr = (vr[0] + vr[1]) + (vr[2] + vr[3]);
+                float si = (vi[0] + vi[1]) + (vi[2] + vi[3]);
+                sr = wave_sum_lane63(sr);
+                si = wave_sum_lane63(si);
+                if (__lane_id() == 63) {
+                    group_add(&op.gsum[gx0].x, (double)sr);
+                    group_add(&op.gsum[gx0].y, (double)si);
+                }
+            } else {
+                int key[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) key[c] = op.emit_axis == 0 ? gxs[c] : (op.emit_axis == 1 ? gy[c] : gz[c]);
+                emit_runs(key, vr, vi, act, op.gsum);
+            }
         }
     }
     if (act && a.write_m) {
         a.mx[i4] = make_float4(mx[0], mx[1], mx[2], mx[3]);
         a.my[i4] = make_float4(my[0], my[1], my[2], my[3]);
-        if (need_mz) a.mz[i4] = make_float4(mz[0], mz[1], mz[2], mz[3]);
-    }
-    if (a.emit_axis >= 0) {
-        float vr[4], vi[4];
-        int key[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            float ar, ai, e1;
-            map_factor(a.emit, gx[c], gz[c], yv[c], zv[c], ar, ai, e1);
-            vr[c] = mx[c] * ar - my[c] * ai;
-            vi[c] = mx[c] * ai + my[c] * ar;
-            key[c] = a.emit_axis == 0 ? gx[c] : (a.emit_axis == 1 ? gy[c] : gz[c]);
-        }
-        emit_runs(key, vr, vi, act, a.gsum);
+        if (need & kNeedMz) a.mz[i4] = make_float4(mz[0], mz[1], mz[2], mz[3]);
     }
 }
 
-hipError_t launch_pass(const PassArgs &a, hipStream_t st) {
-    if (a.n4 <= 0) return hipSuccess;
+hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
+    if (a.n4 <= 0 || a.n_ops <= 0) return hipSuccess;
     const int64_t grid = (a.n4 + 255) / 256;
-    hipLaunchKernelGGL(k_pass, dim3((unsigned)grid), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_sweep, dim3((unsigned)grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- k_adc_eval
 constexpr int kAdcChunk = 1024;  // groups per workgroup
 
-__global__ void k_adc_eval(const AdcJobDev *__restrict__ jobs) {
+__global__ void k_adc_eval(const AdcJobDev *__restrict__ jobs, double *__restrict__ sig_base) {
     const AdcJobDev j = jobs[blockIdx.y];
+    double *sig = sig_base + 2 * j.sig_offset;
     const int g0 = blockIdx.x * kAdcChunk;
     if (g0 >= j.n_groups) return;
     const int g1 = min(g0 + kAdcChunk, j.n_groups);
@@ -363,18 +481,18 @@ __global__ void k_adc_eval(const AdcJobDev *__restrict__ jobs) {
             ar = fma(tr, S.x, fma(-ti, S.y, ar));
             ai = fma(tr, S.y, fma(ti, S.x, ai));
         }
-        atomicAdd(&j.sig[2 * n], ar);
-        atomicAdd(&j.sig[2 * n + 1], ai);
+        atomicAdd(&sig[2 * n], ar);
+        atomicAdd(&sig[2 * n + 1], ai);
     }
 }
 
 hipError_t launch_adc_eval(const AdcJobDev *jobs, int n_jobs, int max_groups, int max_samples,
-                           hipStream_t st) {
+                           double *sig, hipStream_t st) {
     if (n_jobs <= 0 || max_groups <= 0 || max_samples <= 0) return hipSuccess;
     int bs = ((max_samples + 63) / 64) * 64;
     if (bs > 256) bs = 256;
     dim3 grid((max_groups + kAdcChunk - 1) / kAdcChunk, n_jobs);
-    hipLaunchKernelGGL(k_adc_eval, grid, dim3(bs), 0, st, jobs);
+    hipLaunchKernelGGL(k_adc_eval, grid, dim3(bs), 0, st, jobs, sig);
     return hipGetLastError();
 }
 

@@ -43,20 +43,37 @@ struct MapTabs {
     double cz;           // gamma_bar * m_z for the direct z phase; 0 -> none
 };
 
-struct PassArgs {
+// One grouped operation (Sec. 2.3) inside a sweep:
+//   M <- [RF group transition] o [pre map] (M); then, if emitting, the group
+//   sums of emit-map(Mxy) for one with-ADC subsequence (Eq. 9).
+// Read by every wavefront with scalar loads.
+enum { kOpPre = 1, kOpRf = 2, kOpEmit = 4 };
+struct SweepOp {
+    int32_t flags;
+    int32_t rf_axis;
+    int32_t emit_axis;
+    int32_t pad;
+    MapTabs pre;
+    const float4 *ttab;  // 3 float4 rows (A_r0, A_r1, A_r2, b_r) per group
+    MapTabs emit;
+    double2 *gsum;
+};
+
+// Per-isochromat arrays a sweep reads.
+enum { kNeedMz = 1, kNeedGx = 2, kNeedGy = 4, kNeedGz = 8, kNeedY = 16, kNeedZ = 32 };
+
+// A sweep applies ops[0 .. n_ops) in order to every isochromat while its
+// state stays in registers: one read and at most one write of M per launch.
+struct SweepArgs {
     int64_t n4;  // number of 4-isochromat chunks
     float4 *mx, *my, *mz;
     const float4 *m0;
     const int4 *gid_x, *gid_y, *gid_z;
     const float4 *yv, *zv;
-    int32_t has_pre;
-    MapTabs pre;
-    int32_t rf_axis;     // -1: no RF transition
-    const float4 *ttab;  // 3 float4 rows (A_r0, A_r1, A_r2, b_r) per group
+    const SweepOp *ops;
+    int32_t n_ops;
+    int32_t need;
     int32_t write_m;
-    int32_t emit_axis;   // -1: no emission
-    MapTabs emit;
-    double2 *gsum;       // group sums of the emission
 };
 
 // ---- tables ---------------------------------------------------------------
@@ -83,7 +100,7 @@ struct AdcJobDev {
     const double2 *gsum;
     const float4 *gtab;
     const double2 *samp;  // (tau_n, gamma_bar * m_n) per sample, from the block start
-    double *sig;          // 2 * n_samples doubles at this block's sample offset
+    int64_t sig_offset;   // first output sample of this block
 };
 
 // ---- launchers (all asynchronous on `st`) -----------------------------------
@@ -92,13 +109,13 @@ hipError_t launch_plain_finalize(const double2 *partial, int nblk, int n_samples
                                  hipStream_t st);
 int plain_grid(int64_t K);
 
-hipError_t launch_pass(const PassArgs &a, hipStream_t st);
+hipError_t launch_sweep(const SweepArgs &a, hipStream_t st);
 hipError_t launch_tables(const TabJob *jobs, int n_jobs, int max_n, const float4 *gtab_x,
                          const float4 *gtab_z, hipStream_t st);
 hipError_t launch_compose(const RfJobDev *jobs, int n_jobs, int64_t max_groups, double dt,
                           hipStream_t st);
 hipError_t launch_adc_eval(const AdcJobDev *jobs, int n_jobs, int max_groups, int max_samples,
-                           hipStream_t st);
+                           double *sig, hipStream_t st);
 hipError_t launch_fill_f64(double *p, int64_t n, hipStream_t st);
 hipError_t launch_init_state(int64_t K, int64_t Kpad, const int32_t *perm, const float *mi_x,
                              const float *mi_y, const float *mi_z, const float *m0i, float *mx,

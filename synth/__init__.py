@@ -191,6 +191,20 @@ class Sequence:
         m = (self.btype == BLOCK_RF) | (self.btype == BLOCK_ADC)
         return int(self.n_steps[m].sum())
 
+    def head(self, n_blocks: int, name: str | None = None) -> "Sequence":
+        """The first n_blocks blocks as a sequence of their own."""
+        nb = int(n_blocks)
+        stepped = self.btype[:nb] != BLOCK_RELAX
+        s_end = int((self.step_offset[:nb] + self.n_steps[:nb])[stepped].max()) if stepped.any() else 0
+        q_end = int((self.sample_offset[:nb] + self.n_samples[:nb]).max()) if nb else 0
+        return Sequence(dt=self.dt, btype=self.btype[:nb].copy(), step_offset=self.step_offset[:nb].copy(),
+                        n_steps=self.n_steps[:nb].copy(), n_samples=self.n_samples[:nb].copy(),
+                        sample_offset=self.sample_offset[:nb].copy(), tau=self.tau[:nb].copy(),
+                        moment=self.moment[:nb].copy(), rf_re=self.rf_re[:s_end].copy(),
+                        rf_im=self.rf_im[:s_end].copy(), gx=self.gx[:s_end].copy(), gy=self.gy[:s_end].copy(),
+                        gz=self.gz[:s_end].copy(), adc_idx=self.adc_idx[:q_end].copy(),
+                        name=name or f"{self.name}[:{nb}]", meta=dict(self.meta))
+
 
 class SeqBuilder:
     def __init__(self, dt=1e-6, name=""):
