@@ -109,6 +109,7 @@ typedef struct gbs_stats {
     double pass_bytes;     /* algorithmic HBM bytes of the sweeps over all isochromats */
     double pass_kernel_ms; /* GBS_PROFILE: sum of the sweep kernel durations */
     int64_t n_sweeps;      /* sweep launches: runs of grouped operations applied in one pass */
+    double pass_flops;     /* algorithmic FP32 flops of the sweeps (factor products, maps, transitions, sums) */
 } gbs_stats;
 
 typedef struct gbs_ctx gbs_ctx;

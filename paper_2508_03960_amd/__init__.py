@@ -50,7 +50,7 @@ class gbs_stats(ctypes.Structure):
                 ("n_adc_grouped", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
                 ("n_distinct_rf", ctypes.c_int64), ("n_b1zero", ctypes.c_int64),
                 ("pass_bytes", ctypes.c_double), ("pass_kernel_ms", ctypes.c_double),
-                ("n_sweeps", ctypes.c_int64)]
+                ("n_sweeps", ctypes.c_int64), ("pass_flops", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

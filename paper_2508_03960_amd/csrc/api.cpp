@@ -72,7 +72,7 @@ struct GroupedPlan {
     struct Seg {
         int op_begin, op_end, need;
         bool write_m;
-        double bytes_per_iso;
+        double bytes_per_iso, flops_per_iso;
     };
     std::vector<Seg> segs;
     std::vector<std::pair<int, int>> exec;  // (0, segment) or (1, index into plan.ops)
@@ -550,6 +550,14 @@ static int build_grouped_plan(gbs_ctx *ctx) {
             o.emit = map_tabs(p.emit, emit_al);
             o.gsum = ctx->gsum.as<double2>() + g.gsum_off[p.adc_job];
         }
+        // algorithmic FP32 flops per isochromat: each complex factor beyond the
+        // first costs a complex product (6); applying a map 6 + 3 (Mz); a
+        // transition 12 FMA (24); an emission a product (6) and a sum (2)
+        auto factors = [](const MapTabs &t) { return (t.ztab ? 1 : 0) + (t.cy != 0.0) + (t.cz != 0.0); };
+        double fl = 0.0;
+        if (p.has_pre) fl += 9.0 + 6.0 * factors(o.pre);
+        if (p.rf_axis >= 0) fl += 24.0;
+        if (p.emit_axis >= 0) fl += 8.0 + 6.0 * factors(o.emit);
         int need = 0;
         if (p.has_pre || p.rf_axis >= 0) need |= kNeedMz;
         if (p.has_pre || p.emit_axis >= 0 || p.rf_axis == 0) need |= kNeedGx;
@@ -559,13 +567,14 @@ static int build_grouped_plan(gbs_ctx *ctx) {
         if ((p.has_pre && o.pre.cy != 0.0) || (p.emit_axis >= 0 && o.emit.cy != 0.0)) need |= kNeedY;
         if ((p.has_pre && o.pre.cz != 0.0) || (p.emit_axis >= 0 && o.emit.cz != 0.0)) need |= kNeedZ;
         if (g.segs.empty() || g.exec.empty() || g.exec.back().first != 0) {
-            g.segs.push_back(GroupedPlan::Seg{(int)sops.size(), (int)sops.size(), 0, false, 0.0});
+            g.segs.push_back(GroupedPlan::Seg{(int)sops.size(), (int)sops.size(), 0, false, 0.0, 0.0});
             g.exec.push_back({0, (int)g.segs.size() - 1});
         }
         GroupedPlan::Seg &sg = g.segs.back();
         sg.op_end = (int)sops.size() + 1;
         sg.need |= need;
         sg.write_m = sg.write_m || (need & kNeedMz);
+        sg.flops_per_iso += fl;
         sops.push_back(o);
     };
     for (size_t i = 0; i < plan.ops.size(); ++i) {
@@ -664,7 +673,7 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
         }
     }
     int timed = 0;
-    double bytes = 0.0;
+    double bytes = 0.0, flops = 0.0;
     const SweepOp *dev_ops = (const SweepOp *)(jb + g.o_sweep);
     for (const auto &item : g.exec) {
         if (item.first == 0) {
@@ -675,6 +684,7 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
             a.need = sg.need;
             a.write_m = sg.write_m ? 1 : 0;
             bytes += sg.bytes_per_iso * (double)K;
+            flops += sg.flops_per_iso * (double)K;
             if (profile) HIPCHK(hipEventRecord(ctx->pev[2 * timed], ctx->stream));
             HIPCHK(launch_sweep(a, ctx->stream));
             if (profile) HIPCHK(hipEventRecord(ctx->pev[2 * timed++ + 1], ctx->stream));
@@ -709,6 +719,7 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
         st->n_distinct_rf = (int64_t)plan.rf.size();
         st->n_b1zero = plan.n_b1zero;
         st->pass_bytes = bytes;
+        st->pass_flops = flops;
     }
     return GBS_OK;
 }
