@@ -47,12 +47,6 @@ struct DevBuf {
     }
 };
 
-// Tables of one B1 = 0 map inside the per-simulate table arena (byte offsets).
-struct MapAlloc {
-    size_t x_off = 0, z_off = 0;
-    bool has_z = false;
-};
-
 // Everything about a grouped simulation that depends only on the sequence and
 // the groups: the pass schedule, the arena layout, the per-sample tables and
 // the job arrays (uploaded once).  Rebuilt after set_sequence/build_groups.
@@ -61,13 +55,12 @@ struct GroupedPlan {
     Plan plan;
     bool zbuilt = false;
     std::vector<size_t> rf_off, gsum_off;
-    std::vector<MapAlloc> pre_tab, emit_tab;
-    MapAlloc final_tab;
     size_t gsum_count = 0;
     int64_t max_rf_groups = 0, max_tab = 0;
     int max_adc_groups = 0, max_adc_samples = 0;
-    int n_rf = 0, n_tab = 0, n_adc = 0;
-    size_t o_rf = 0, o_tab = 0, o_adc = 0, o_sweep = 0;
+    int n_rf = 0, n_fold = 0, n_tab = 0, n_adc = 0;
+    int64_t max_fold_groups = 0;
+    size_t o_rf = 0, o_fold = 0, o_tab = 0, o_adc = 0, o_sweep = 0;
     // execution: runs of grouped ops fused into sweeps, plain steps between
     struct Seg {
         int op_begin, op_end, need;
@@ -98,6 +91,7 @@ struct gbs_ctx {
     uint32_t axes = 0;
     bool groups_valid = false;
     int64_t ng[3] = {-1, -1, -1};
+    int64_t Kint = 0;  // isochromats in the padded group-sorted layout (multiple of 4)
     int64_t Kpad = 0;
     DevBuf perm, xi, yi, zi, t1i, t2i, dfi, m0i, gid[3], gtab[3], gcount[3], ms[3];
     // per-simulate buffers
@@ -256,21 +250,28 @@ int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
     ctx->groups_valid = false;
     ctx->gp.valid = false;
     const int64_t K = ctx->K;
-    const int64_t Kpad = (K + 1023) / 1024 * 1024;
+    const int64_t cap = (4 * K + 1023) / 1024 * 1024;  // padded layout is at most 4 K long
     const size_t scratch_bytes = group_scratch_bytes(K) + 4096;
-    DevBuf scratch, gid_nat, order;
+    DevBuf scratch, gid_nat[3], order, perm_tmp, src_tmp;
     auto cleanup = [&]() {
         scratch.release();
-        gid_nat.release();
+        for (auto &g : gid_nat) g.release();
         order.release();
+        perm_tmp.release();
+        src_tmp.release();
     };
-    if (scratch.ensure(scratch_bytes) != hipSuccess || gid_nat.ensure(4 * K) != hipSuccess ||
-        order.ensure(4 * K) != hipSuccess) {
+    auto fail_hip = [&](hipError_t e, const char *what) {
+        cleanup();
+        return fail(ctx, e == hipErrorOutOfMemory ? GBS_E_NOMEM : GBS_E_HIP,
+                    std::string(what) + ": " + hipGetErrorString(e));
+    };
+    if (scratch.ensure(scratch_bytes) != hipSuccess || order.ensure(4 * K) != hipSuccess ||
+        perm_tmp.ensure(4 * cap) != hipSuccess || src_tmp.ensure(4 * cap) != hipSuccess) {
         cleanup();
         return fail(ctx, GBS_E_NOMEM, "grouping scratch allocation failed");
     }
+    // 1. group every requested axis by its key (r_a, T1, T2, dB0)
     const float *coord[3] = {ctx->ph.x, ctx->ph.y, ctx->ph.z};
-    ALLOC(ctx->perm, 4 * Kpad);
     for (int a = 0; a < 3; ++a) {
         ctx->ng[a] = -1;
         if (!(axes & (1u << a))) {
@@ -279,37 +280,46 @@ int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
             ctx->gcount[a].release();
             continue;
         }
+        if (gid_nat[a].ensure(4 * K) != hipSuccess) {
+            cleanup();
+            return fail(ctx, GBS_E_NOMEM, "grouping scratch allocation failed");
+        }
         ALLOC(ctx->gtab[a], sizeof(float4) * K);
         ALLOC(ctx->gcount[a], sizeof(int32_t) * K);
-        ALLOC(ctx->gid[a], sizeof(int32_t) * Kpad);
-        int32_t *ord = a == 0 ? ctx->perm.as<int32_t>() : order.as<int32_t>();
         int64_t G = 0;
         hipError_t e = group_axis(K, coord[a], ctx->ph.t1, ctx->ph.t2, ctx->ph.df, scratch.p, scratch_bytes,
-                                  gid_nat.as<int32_t>(), ctx->gtab[a].as<float4>(),
-                                  ctx->gcount[a].as<int32_t>(), ord, &G, ctx->stream);
-        if (e != hipSuccess) {
-            cleanup();
-            return fail(ctx, GBS_E_HIP, std::string("grouping failed: ") + hipGetErrorString(e));
-        }
+                                  gid_nat[a].as<int32_t>(), ctx->gtab[a].as<float4>(), ctx->gcount[a].as<int32_t>(),
+                                  order.as<int32_t>(), &G, ctx->stream);
+        if (e != hipSuccess) return fail_hip(e, "grouping failed");
         ctx->ng[a] = G;
-        // ids in group-sorted order (the order comes from the x axis, built first)
-        e = launch_gather_i32(K, Kpad, ctx->perm.as<int32_t>(), gid_nat.as<int32_t>(), ctx->gid[a].as<int32_t>(),
-                              ctx->stream);
-        if (e != hipSuccess) {
-            cleanup();
-            return fail(ctx, GBS_E_HIP, hipGetErrorString(e));
-        }
+    }
+    // 2. the padded group-sorted layout: (x-group, z-group) runs of multiples of 4
+    int64_t kint = 0;
+    hipError_t e = build_layout(K, gid_nat[0].as<int32_t>(), (axes & GBS_AX_Z) ? gid_nat[2].as<int32_t>() : nullptr,
+                                scratch.p, scratch_bytes, perm_tmp.as<int32_t>(), src_tmp.as<int32_t>(), cap, &kint,
+                                ctx->stream);
+    if (e != hipSuccess) return fail_hip(e, "layout failed");
+    const int64_t Kpad = (kint + 1023) / 1024 * 1024;
+    ALLOC(ctx->perm, 4 * Kpad);
+    HIPCHK(hipMemcpyAsync(ctx->perm.p, perm_tmp.p, 4 * Kpad, hipMemcpyDeviceToDevice, ctx->stream));
+    const int32_t *src = src_tmp.as<int32_t>();
+    for (int a = 0; a < 3; ++a) {
+        if (!(axes & (1u << a))) continue;
+        ALLOC(ctx->gid[a], sizeof(int32_t) * Kpad);
+        HIPCHK(launch_gather_i32(Kpad, Kpad, src, gid_nat[a].as<int32_t>(), ctx->gid[a].as<int32_t>(), ctx->stream));
     }
     DevBuf *dst[7] = {&ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i, &ctx->t2i, &ctx->dfi, &ctx->m0i};
-    const float *src[7] = {ctx->ph.x, ctx->ph.y, ctx->ph.z, ctx->ph.t1, ctx->ph.t2, ctx->ph.df, ctx->ph.m0};
+    const float *from[7] = {ctx->ph.x, ctx->ph.y, ctx->ph.z, ctx->ph.t1, ctx->ph.t2, ctx->ph.df, ctx->ph.m0};
     for (int i = 0; i < 7; ++i) {
         ALLOC(*dst[i], 4 * Kpad);
-        HIPCHK(launch_gather_f32(K, Kpad, ctx->perm.as<int32_t>(), src[i], dst[i]->as<float>(), ctx->stream));
+        HIPCHK(launch_gather_f32(Kpad, Kpad, src, from[i], dst[i]->as<float>(), ctx->stream));
     }
+    HIPCHK(launch_zero_padding(Kpad, ctx->perm.as<int32_t>(), ctx->m0i.as<float>(), ctx->stream));
     for (int a = 0; a < 3; ++a) ALLOC(ctx->ms[a], 4 * Kpad);
     HIPCHK(hipStreamSynchronize(ctx->stream));
     cleanup();
     ctx->axes = axes;
+    ctx->Kint = kint;
     ctx->Kpad = Kpad;
     ctx->groups_valid = true;
     return GBS_OK;
@@ -445,37 +455,74 @@ static int build_grouped_plan(gbs_ctx *ctx) {
     g.zbuilt = (ctx->axes & GBS_AX_Z) != 0;
     const int64_t Gx = ctx->ng[0], Gz = g.zbuilt ? ctx->ng[2] : 0;
 
+    // ---- arena: FP64 combined transitions, folded transitions, map tables
     size_t off = 0;
     g.rf_off.resize(plan.rf.size());
     for (size_t i = 0; i < plan.rf.size(); ++i) {
         g.rf_off[i] = off;
         const int64_t G = ctx->ng[plan.rf[i].axis];
         g.max_rf_groups = std::max(g.max_rf_groups, G);
-        off = align256(off + sizeof(float4) * 3 * (size_t)G);
+        off = align256(off + sizeof(double) * 12 * (size_t)G);
     }
     std::vector<TabJob> tjobs;
-    auto alloc_map = [&](const Map &m) {
-        MapAlloc r;
-        r.x_off = off;
+    auto x_table = [&](int kind, double tau, double cyc) {
+        const size_t o = off;
         off = align256(off + sizeof(float4) * (size_t)Gx);
-        tjobs.push_back(TabJob{0, (int32_t)Gx, m.tau, kGammaBar * m.m[0], (void *)r.x_off});
-        if (g.zbuilt && m.m[2] != 0.0) {
-            r.has_z = true;
-            r.z_off = off;
-            off = align256(off + sizeof(float2) * (size_t)Gz);
-            tjobs.push_back(TabJob{1, (int32_t)Gz, 0.0, kGammaBar * m.m[2], (void *)r.z_off});
-        }
-        return r;
+        tjobs.push_back(TabJob{kind, (int32_t)Gx, tau, cyc, (void *)o});
+        return o;
     };
-    g.pre_tab.assign(plan.ops.size(), MapAlloc{});
-    g.emit_tab.assign(plan.ops.size(), MapAlloc{});
-    for (size_t i = 0; i < plan.ops.size(); ++i) {
-        const Op &op = plan.ops[i];
-        if (op.kind != 0) continue;
-        if (op.pass.has_pre) g.pre_tab[i] = alloc_map(op.pass.pre);
-        if (op.pass.emit_axis >= 0) g.emit_tab[i] = alloc_map(op.pass.emit);
+    auto z_table = [&](double cyc) {
+        const size_t o = off;
+        off = align256(off + sizeof(float2) * (size_t)Gz);
+        tjobs.push_back(TabJob{1, (int32_t)Gz, 0.0, cyc, (void *)o});
+        return o;
+    };
+    struct FoldPlan {
+        size_t out_off;
+        int axis, rf_id, has_pre;
+        double tau, cyc;
+    };
+    std::vector<FoldPlan> folds;
+    const size_t kNone = ~(size_t)0;
+    struct OpTabs {  // arena offsets of one op's tables
+        size_t pre_x = kNone, pre_z = kNone, ttab = kNone, emit_x = kNone, emit_z = kNone;
+    };
+    std::vector<PassOp> passes;  // grouped ops in schedule order, final map last
+    std::vector<int> pass_of_op(plan.ops.size(), -1);
+    for (size_t i = 0; i < plan.ops.size(); ++i)
+        if (plan.ops[i].kind == 0) {
+            pass_of_op[i] = (int)passes.size();
+            passes.push_back(plan.ops[i].pass);
+        }
+    if (plan.final_pass) {
+        PassOp f;
+        f.has_pre = true;
+        f.pre = plan.final_map;
+        f.write_m = true;
+        passes.push_back(f);
     }
-    if (plan.final_pass) g.final_tab = alloc_map(plan.final_map);
+    std::vector<OpTabs> ot(passes.size());
+    for (size_t i = 0; i < passes.size(); ++i) {
+        const PassOp &p = passes[i];
+        if (p.rf_axis >= 0) {
+            // the tissue part and the own-axis phase of the pre map fold into T'
+            const int A = p.rf_axis;
+            ot[i].ttab = off;
+            off = align256(off + sizeof(float4) * 3 * (size_t)ctx->ng[A]);
+            folds.push_back(FoldPlan{ot[i].ttab, A, p.rf_id, p.has_pre ? 1 : 0, p.pre.tau, kGammaBar * p.pre.m[A]});
+            if (p.has_pre) {
+                if (A != 0 && p.pre.m[0] != 0.0) ot[i].pre_x = x_table(2, 0.0, kGammaBar * p.pre.m[0]);
+                if (A != 2 && g.zbuilt && p.pre.m[2] != 0.0) ot[i].pre_z = z_table(kGammaBar * p.pre.m[2]);
+            }
+        } else if (p.has_pre) {
+            ot[i].pre_x = x_table(0, p.pre.tau, kGammaBar * p.pre.m[0]);
+            if (g.zbuilt && p.pre.m[2] != 0.0) ot[i].pre_z = z_table(kGammaBar * p.pre.m[2]);
+        }
+        if (p.emit_axis >= 0) {
+            ot[i].emit_x = x_table(0, p.emit.tau, kGammaBar * p.emit.m[0]);
+            if (g.zbuilt && p.emit.m[2] != 0.0) ot[i].emit_z = z_table(kGammaBar * p.emit.m[2]);
+        }
+    }
     const size_t tab_bytes = off;
     g.max_tab = std::max<int64_t>(Gx, Gz);
 
@@ -495,7 +542,7 @@ static int build_grouped_plan(gbs_ctx *ctx) {
     ALLOC(ctx->tabs, tab_bytes);
     ALLOC(ctx->gsum, sizeof(double2) * goff);
     ALLOC(ctx->samp, sizeof(double2) * soff);
-    if (plan.n_fallback) ALLOC(ctx->partial, sizeof(double2) * (size_t)plain_grid(ctx->K) * kMaxSamplesPerLaunch);
+    if (plan.n_fallback) ALLOC(ctx->partial, sizeof(double2) * (size_t)plain_grid(ctx->Kint) * kMaxSamplesPerLaunch);
     char *tb = ctx->tabs.as<char>();
     for (auto &t : tjobs) t.out = tb + (size_t)t.out;
 
@@ -515,12 +562,19 @@ static int build_grouped_plan(gbs_ctx *ctx) {
         }
     }
 
-    // job arrays: rf | tables | adc, one upload
+    // ---- job arrays
     std::vector<RfJobDev> rj(plan.rf.size());
     for (size_t i = 0; i < plan.rf.size(); ++i) {
         const RfJob &r = plan.rf[i];
         rj[i] = RfJobDev{r.axis, (int32_t)r.n_steps, ctx->ng[r.axis], ctx->d_wave.as<StepW>() + r.step_offset,
-                         ctx->gtab[r.axis].as<float4>(), (float4 *)(tb + g.rf_off[i])};
+                         ctx->gtab[r.axis].as<float4>(), (double *)(tb + g.rf_off[i])};
+    }
+    std::vector<FoldJob> fj(folds.size());
+    for (size_t i = 0; i < folds.size(); ++i) {
+        const FoldPlan &f = folds[i];
+        fj[i] = FoldJob{f.axis, f.has_pre, ctx->ng[f.axis], (const double *)(tb + g.rf_off[f.rf_id]),
+                        ctx->gtab[f.axis].as<float4>(), f.tau, f.cyc, (float4 *)(tb + f.out_off)};
+        g.max_fold_groups = std::max(g.max_fold_groups, ctx->ng[f.axis]);
     }
     std::vector<AdcJobDev> aj(plan.adc.size());
     for (size_t i = 0; i < plan.adc.size(); ++i) {
@@ -529,43 +583,55 @@ static int build_grouped_plan(gbs_ctx *ctx) {
         aj[i] = AdcJobDev{b.n_samples, (int32_t)ctx->ng[j.axis], ctx->gsum.as<double2>() + g.gsum_off[i],
                           ctx->gtab[j.axis].as<float4>(), ctx->samp.as<double2>() + samp_off[i], b.sample_offset};
     }
-    // grouped ops in schedule order; consecutive ones fuse into one sweep
-    auto map_tabs = [&](const Map &m, const MapAlloc &al) {
-        MapTabs t{};
-        t.xtab = (const float4 *)(tb + al.x_off);
-        t.ztab = al.has_z ? (const float2 *)(tb + al.z_off) : nullptr;
-        t.cy = kGammaBar * m.m[1];
-        t.cz = g.zbuilt ? 0.0 : kGammaBar * m.m[2];
-        return t;
-    };
+
+    // ---- sweep ops: grouped ops in schedule order; consecutive ones fuse
+    auto ptr4 = [&](size_t o) { return o == kNone ? (const float4 *)nullptr : (const float4 *)(tb + o); };
+    auto ptr2 = [&](size_t o) { return o == kNone ? (const float2 *)nullptr : (const float2 *)(tb + o); };
     std::vector<SweepOp> sops;
-    auto add_op = [&](const PassOp &p, const MapAlloc &pre_al, const MapAlloc &emit_al) {
+    auto add_op = [&](int pi) {
+        const PassOp &p = passes[pi];
+        const OpTabs &t = ot[pi];
         SweepOp o{};
-        o.flags = (p.has_pre ? kOpPre : 0) | (p.rf_axis >= 0 ? kOpRf : 0) | (p.emit_axis >= 0 ? kOpEmit : 0);
         o.rf_axis = p.rf_axis;
         o.emit_axis = p.emit_axis;
-        if (p.has_pre) o.pre = map_tabs(p.pre, pre_al);
-        if (p.rf_axis >= 0) o.ttab = (const float4 *)(tb + g.rf_off[p.rf_id]);
-        if (p.emit_axis >= 0) {
-            o.emit = map_tabs(p.emit, emit_al);
-            o.gsum = ctx->gsum.as<double2>() + g.gsum_off[p.adc_job];
-        }
-        // algorithmic FP32 flops per isochromat: each complex factor beyond the
-        // first costs a complex product (6); applying a map 6 + 3 (Mz); a
-        // transition 12 FMA (24); an emission a product (6) and a sum (2)
-        auto factors = [](const MapTabs &t) { return (t.ztab ? 1 : 0) + (t.cy != 0.0) + (t.cz != 0.0); };
         double fl = 0.0;
-        if (p.has_pre) fl += 9.0 + 6.0 * factors(o.pre);
-        if (p.rf_axis >= 0) fl += 24.0;
-        if (p.emit_axis >= 0) fl += 8.0 + 6.0 * factors(o.emit);
+        if (p.has_pre) {
+            const int A = p.rf_axis;  // -1: nothing folded
+            o.pre_xtab = ptr4(t.pre_x);
+            o.pre_ztab = ptr2(t.pre_z);
+            o.pre_cy = (A != 1) ? kGammaBar * p.pre.m[1] : 0.0;
+            o.pre_cz = (A != 2 && !g.zbuilt) ? kGammaBar * p.pre.m[2] : 0.0;
+            const int nf = (o.pre_xtab != nullptr) + (o.pre_ztab != nullptr) + (o.pre_cy != 0.0) + (o.pre_cz != 0.0);
+            if (nf) {
+                o.flags |= kOpPre;
+                fl += 6.0 * nf;
+            }
+            if (A < 0) {
+                o.flags |= kPreMz;
+                fl += 3.0;
+            }
+        }
+        if (p.rf_axis >= 0) {
+            o.flags |= kOpRf;
+            o.ttab = ptr4(t.ttab);
+            fl += 24.0;
+        }
+        if (p.emit_axis >= 0) {
+            o.flags |= kOpEmit;
+            o.emit_xtab = ptr4(t.emit_x);
+            o.emit_ztab = ptr2(t.emit_z);
+            o.emit_cy = kGammaBar * p.emit.m[1];
+            o.emit_cz = g.zbuilt ? 0.0 : kGammaBar * p.emit.m[2];
+            o.gsum = ctx->gsum.as<double2>() + g.gsum_off[p.adc_job];
+            fl += 8.0 + 6.0 * ((o.emit_ztab != nullptr) + (o.emit_cy != 0.0) + (o.emit_cz != 0.0));
+        }
         int need = 0;
-        if (p.has_pre || p.rf_axis >= 0) need |= kNeedMz;
-        if (p.has_pre || p.emit_axis >= 0 || p.rf_axis == 0) need |= kNeedGx;
+        if ((o.flags & kOpRf) || (o.flags & kPreMz)) need |= kNeedMz;
+        if (o.pre_xtab || (o.flags & kOpEmit) || p.rf_axis == 0) need |= kNeedGx;
         if (p.rf_axis == 1 || p.emit_axis == 1) need |= kNeedGy;
-        if (p.rf_axis == 2 || p.emit_axis == 2 || (p.has_pre && o.pre.ztab) || (p.emit_axis >= 0 && o.emit.ztab))
-            need |= kNeedGz;
-        if ((p.has_pre && o.pre.cy != 0.0) || (p.emit_axis >= 0 && o.emit.cy != 0.0)) need |= kNeedY;
-        if ((p.has_pre && o.pre.cz != 0.0) || (p.emit_axis >= 0 && o.emit.cz != 0.0)) need |= kNeedZ;
+        if (o.pre_ztab || o.emit_ztab || p.rf_axis == 2 || p.emit_axis == 2) need |= kNeedGz;
+        if (o.pre_cy != 0.0 || o.emit_cy != 0.0) need |= kNeedY;
+        if (o.pre_cz != 0.0 || o.emit_cz != 0.0) need |= kNeedZ;
         if (g.segs.empty() || g.exec.empty() || g.exec.back().first != 0) {
             g.segs.push_back(GroupedPlan::Seg{(int)sops.size(), (int)sops.size(), 0, false, 0.0, 0.0});
             g.exec.push_back({0, (int)g.segs.size() - 1});
@@ -573,23 +639,54 @@ static int build_grouped_plan(gbs_ctx *ctx) {
         GroupedPlan::Seg &sg = g.segs.back();
         sg.op_end = (int)sops.size() + 1;
         sg.need |= need;
-        sg.write_m = sg.write_m || (need & kNeedMz);
+        sg.write_m = sg.write_m || (o.flags & (kOpPre | kOpRf));
         sg.flops_per_iso += fl;
         sops.push_back(o);
     };
     for (size_t i = 0; i < plan.ops.size(); ++i) {
-        const Op &op = plan.ops[i];
-        if (op.kind == 0)
-            add_op(op.pass, g.pre_tab[i], g.emit_tab[i]);
+        if (plan.ops[i].kind == 0)
+            add_op(pass_of_op[i]);
         else
             g.exec.push_back({1, (int)i});
     }
-    if (plan.final_pass) {
-        PassOp f;
-        f.has_pre = true;
-        f.pre = plan.final_map;
-        f.write_m = true;
-        add_op(f, g.final_tab, MapAlloc{});
+    if (plan.final_pass) add_op((int)passes.size() - 1);
+
+    // y phases of consecutive emissions inside a sweep: direct evaluation, or
+    // a complex recurrence when the coefficients step evenly (restarted every
+    // 16 emissions to bound FP32 drift)
+    for (const auto &sg : g.segs) {
+        double prev = 0.0, step = 0.0;
+        bool have_prev = false, have_step = false;
+        int chain = 0;
+        std::vector<int> em;
+        for (int o = sg.op_begin; o < sg.op_end; ++o)
+            if (sops[o].flags & kOpEmit) em.push_back(o);
+        for (size_t e = 0; e < em.size(); ++e) {
+            SweepOp &o = sops[em[e]];
+            const double c = o.emit_cy;
+            if (c == 0.0) {
+                have_prev = have_step = false;
+                continue;
+            }
+            const bool stepped = have_prev && have_step && chain < 15 &&
+                                 std::fabs(c - prev - step) <= 1e-12 * std::max(std::fabs(step), std::fabs(c));
+            if (stepped) {
+                o.flags |= kYStep;
+                ++chain;
+            } else {
+                o.flags |= kYDirect;
+                chain = 0;
+                have_step = false;
+                if (e + 1 < em.size() && sops[em[e + 1]].emit_cy != 0.0) {
+                    o.flags |= kYSetR;
+                    o.emit_dcy = sops[em[e + 1]].emit_cy - c;
+                    step = o.emit_dcy;
+                    have_step = true;
+                }
+            }
+            prev = c;
+            have_prev = true;
+        }
     }
     for (auto &sg : g.segs) {
         const int n = sg.need;
@@ -601,18 +698,24 @@ static int build_grouped_plan(gbs_ctx *ctx) {
     g.n_ops = (int64_t)sops.size();
 
     g.n_rf = (int)rj.size();
+    g.n_fold = (int)fj.size();
     g.n_tab = (int)tjobs.size();
     g.n_adc = (int)aj.size();
     g.o_rf = 0;
-    g.o_tab = align256(sizeof(RfJobDev) * rj.size());
+    g.o_fold = align256(sizeof(RfJobDev) * rj.size());
+    g.o_tab = g.o_fold + align256(sizeof(FoldJob) * fj.size());
     g.o_adc = g.o_tab + align256(sizeof(TabJob) * tjobs.size());
     g.o_sweep = g.o_adc + align256(sizeof(AdcJobDev) * aj.size());
     const size_t jbytes = g.o_sweep + sizeof(SweepOp) * sops.size();
     ctx->host_jobs.assign(jbytes, 0);
-    if (!rj.empty()) std::memcpy(ctx->host_jobs.data() + g.o_rf, rj.data(), sizeof(RfJobDev) * rj.size());
-    if (!tjobs.empty()) std::memcpy(ctx->host_jobs.data() + g.o_tab, tjobs.data(), sizeof(TabJob) * tjobs.size());
-    if (!aj.empty()) std::memcpy(ctx->host_jobs.data() + g.o_adc, aj.data(), sizeof(AdcJobDev) * aj.size());
-    if (!sops.empty()) std::memcpy(ctx->host_jobs.data() + g.o_sweep, sops.data(), sizeof(SweepOp) * sops.size());
+    auto put = [&](size_t o, const void *src, size_t n) {
+        if (n) std::memcpy(ctx->host_jobs.data() + o, src, n);
+    };
+    put(g.o_rf, rj.data(), sizeof(RfJobDev) * rj.size());
+    put(g.o_fold, fj.data(), sizeof(FoldJob) * fj.size());
+    put(g.o_tab, tjobs.data(), sizeof(TabJob) * tjobs.size());
+    put(g.o_adc, aj.data(), sizeof(AdcJobDev) * aj.size());
+    put(g.o_sweep, sops.data(), sizeof(SweepOp) * sops.size());
     ALLOC(ctx->jobs, jbytes);
     HIPCHK(hipMemcpy(ctx->jobs.p, ctx->host_jobs.data(), jbytes, hipMemcpyHostToDevice));
     if (soff) HIPCHK(hipMemcpy(ctx->samp.p, hs.data(), sizeof(double2) * soff, hipMemcpyHostToDevice));
@@ -631,28 +734,25 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     const GroupedPlan &g = ctx->gp;
     const Plan &plan = g.plan;
     const bool zbuilt = g.zbuilt;
-    const int grid = plain_grid(K);
+    const int grid = plain_grid(ctx->Kint);
     char *tb = ctx->tabs.as<char>();
     char *jb = ctx->jobs.as<char>();
-    const auto &rf_off = g.rf_off;
-    const auto &gsum_off = g.gsum_off;
-    const auto &pre_tab = g.pre_tab;
-    const auto &emit_tab = g.emit_tab;
-    const MapAlloc &final_tab = g.final_tab;
 
     // ---- prepare: combined transitions (Eq. 7) and map tables --------------
     HIPCHK(launch_fill_f64((double *)ctx->gsum.p, 2 * (int64_t)g.gsum_count, ctx->stream));
     HIPCHK(launch_compose((const RfJobDev *)(jb + g.o_rf), g.n_rf, g.max_rf_groups, s.dt, ctx->stream));
+    HIPCHK(launch_fold((const FoldJob *)(jb + g.o_fold), g.n_fold, g.max_fold_groups, ctx->stream));
     HIPCHK(launch_tables((const TabJob *)(jb + g.o_tab), g.n_tab, (int)g.max_tab, ctx->gtab[0].as<float4>(),
                          zbuilt ? ctx->gtab[2].as<float4>() : nullptr, ctx->stream));
     if (st) HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
 
     // ---- sweeps of grouped ops (plain stepping between them) ----------------
     float *mx = ctx->ms[0].as<float>(), *my = ctx->ms[1].as<float>(), *mz = ctx->ms[2].as<float>();
-    HIPCHK(launch_init_state(K, ctx->Kpad, ctx->perm.as<int32_t>(), m_init, m_init ? m_init + K : nullptr,
+    const int64_t Kint = ctx->Kint;
+    HIPCHK(launch_init_state(Kint, ctx->Kpad, ctx->perm.as<int32_t>(), m_init, m_init ? m_init + K : nullptr,
                              m_init ? m_init + 2 * K : nullptr, ctx->m0i.as<float>(), mx, my, mz, ctx->stream));
     SweepArgs base{};
-    base.n4 = (K + 3) / 4;
+    base.n4 = Kint / 4;
     base.mx = (float4 *)mx;
     base.my = (float4 *)my;
     base.mz = (float4 *)mz;
@@ -690,7 +790,7 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
             if (profile) HIPCHK(hipEventRecord(ctx->pev[2 * timed++ + 1], ctx->stream));
         } else {
             const Op &op = plan.ops[item.second];
-            PlainArgs a = step_args(ctx, op.step, iph, K, mx, my, mz, mx, my, mz);
+            PlainArgs a = step_args(ctx, op.step, iph, Kint, mx, my, mz, mx, my, mz);
             const bool b1 = op.step.block >= 0 && ctx->cls[op.step.block].has_b1;
             HIPCHK(launch_plain(a, b1, false, grid, ctx->stream));
             if (a.n_samples > 0) {
@@ -707,7 +807,7 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     HIPCHK(launch_adc_eval((const AdcJobDev *)(jb + g.o_adc), g.n_adc, g.max_adc_groups, g.max_adc_samples,
                            sig_out, ctx->stream));
     if (st) HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
-    HIPCHK(launch_scatter_state(K, ctx->perm.as<int32_t>(), mx, my, mz, m_out, m_out + K, m_out + 2 * K,
+    HIPCHK(launch_scatter_state(Kint, ctx->perm.as<int32_t>(), mx, my, mz, m_out, m_out + K, m_out + 2 * K,
                                 ctx->stream));
     if (st) {
         st->n_passes = g.n_ops;

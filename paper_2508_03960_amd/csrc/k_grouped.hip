@@ -4,16 +4,18 @@
 //              FP64.  One wavefront per group: each lane composes a contiguous
 //              chunk of steps, then the 64 partial products are combined in a
 //              log2 tree through LDS (later chunk on the left).
-//  k_tables    per-group factors of the closed-form B1 = 0 maps (Eq. 4, 5):
-//              x-groups carry decay, off-resonance and x phase; z-groups the
-//              z phase.
+//  k_fold      per operation, T' = T o P with the tissue part and the
+//              own-axis phase of the preceding B1 = 0 map P (Eq. 4, 5), FP64,
+//              rounded once to FP32.
+//  k_tables    per-group factors of the remaining B1 = 0 map parts.
 //  k_sweep     one coalesced sweep over the group-sorted isochromats that
 //              applies a run of grouped operations with the state in
-//              registers: pre maps, group transitions, and the group sums of
-//              each with-ADC subsequence (Eq. 9) reduced across the wavefront
-//              (one group per wavefront in the common case), then FP64 atomics.
+//              registers: pre-map phases, group transitions, and the group
+//              sums of each with-ADC subsequence (Eq. 9) reduced across the
+//              wavefront (one group per wavefront in the common case), then
+//              FP64 atomics.
 //  k_adc_eval  every ADC sample from the group sums (Eq. 8 with Eq. 10), FP64
-//              phase reduced to a quarter turn, FP64 accumulation.
+//              phase reduced modulo one turn, FP64 accumulation.
 #include "device_math.hpp"
 #include "kernels.hpp"
 
@@ -125,11 +127,7 @@ __global__ __launch_bounds__(256) void k_compose(const RfJobDev *__restrict__ jo
         }
         __syncthreads();
     }
-    if (act && lane < 3) {
-        const double *row = &lds[wave][0][0];
-        j.out[3 * g + lane] = make_float4((float)row[3 * lane], (float)row[3 * lane + 1],
-                                          (float)row[3 * lane + 2], (float)row[9 + lane]);
-    }
+    if (act && lane < 12) j.out[12 * g + lane] = lds[wave][0][lane];
 }
 
 hipError_t launch_compose(const RfJobDev *jobs, int n_jobs, int64_t max_groups, double dt,
@@ -140,26 +138,73 @@ hipError_t launch_compose(const RfJobDev *jobs, int n_jobs, int64_t max_groups, 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- k_fold
+__global__ __launch_bounds__(256) void k_fold(const FoldJob *__restrict__ jobs) {
+    const FoldJob j = jobs[blockIdx.y];
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < j.n_groups; g += (int64_t)gridDim.x * 256) {
+        Aff T;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) T.a[i] = j.t64[12 * g + i];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) T.b[i] = j.t64[12 * g + 9 + i];
+        Aff r = T;
+        if (j.has_pre) {
+            // P: Mxy <- E2 exp(-i phi) Mxy, Mz <- E1 Mz + (1 - E1) M0 (Eq. 4, 5)
+            const float4 p = j.gtab[g];  // (coord, T1, T2, df)
+            const double cyc = j.cyc * (double)p.x + (double)p.w * j.tau;
+            double sn, cs;
+            sincos(kTwoPi * (cyc - rint(cyc)), &sn, &cs);
+            const double e2 = exp(-j.tau / (double)p.z), e1 = exp(-j.tau / (double)p.y);
+            Aff P;
+            P.a[0] = e2 * cs;
+            P.a[1] = e2 * sn;
+            P.a[2] = 0.0;
+            P.a[3] = -e2 * sn;
+            P.a[4] = e2 * cs;
+            P.a[5] = 0.0;
+            P.a[6] = 0.0;
+            P.a[7] = 0.0;
+            P.a[8] = e1;
+            P.b[0] = 0.0;
+            P.b[1] = 0.0;
+            P.b[2] = 1.0 - e1;
+            aff_compose(T, P, r);
+        }
+#pragma unroll
+        for (int row = 0; row < 3; ++row)
+            j.out[3 * g + row] = make_float4((float)r.a[3 * row], (float)r.a[3 * row + 1], (float)r.a[3 * row + 2],
+                                             (float)r.b[row]);
+    }
+}
+
+hipError_t launch_fold(const FoldJob *jobs, int n_jobs, int64_t max_groups, hipStream_t st) {
+    if (n_jobs <= 0 || max_groups <= 0) return hipSuccess;
+    int64_t gx = (max_groups + 255) / 256;
+    if (gx > 64) gx = 64;
+    hipLaunchKernelGGL(k_fold, dim3((unsigned)gx, n_jobs), dim3(256), 0, st, jobs);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- k_tables
 __global__ __launch_bounds__(256) void k_tables(const TabJob *__restrict__ jobs,
                                                 const float4 *__restrict__ gtab_x,
                                                 const float4 *__restrict__ gtab_z) {
     const TabJob j = jobs[blockIdx.y];
     for (int g = blockIdx.x * 256 + threadIdx.x; g < j.n; g += gridDim.x * 256) {
-        if (j.kind == 0) {
+        if (j.kind == 0 || j.kind == 2) {
             const float4 p = gtab_x[g];  // (x, T1, T2, df)
-            const double cyc = j.cyc * (double)p.x + (double)p.w * j.tau;
-            const double ph = kTwoPi * (cyc - rint(cyc));
+            const bool tissue = j.kind == 0;
+            const double cyc = j.cyc * (double)p.x + (tissue ? (double)p.w * j.tau : 0.0);
             double sn, cs;
-            sincos(ph, &sn, &cs);
-            const double e2 = exp(-j.tau / (double)p.z), e1 = exp(-j.tau / (double)p.y);
+            sincos(kTwoPi * (cyc - rint(cyc)), &sn, &cs);
+            const double e2 = tissue ? exp(-j.tau / (double)p.z) : 1.0;
+            const double e1 = tissue ? exp(-j.tau / (double)p.y) : 1.0;
             ((float4 *)j.out)[g] = make_float4((float)(e2 * cs), (float)(-e2 * sn), (float)e1, 0.f);
         } else {
             const float4 p = gtab_z[g];
             const double cyc = j.cyc * (double)p.x;
-            const double ph = kTwoPi * (cyc - rint(cyc));
             double sn, cs;
-            sincos(ph, &sn, &cs);
+            sincos(kTwoPi * (cyc - rint(cyc)), &sn, &cs);
             ((float2 *)j.out)[g] = make_float2((float)cs, (float)-sn);
         }
     }
@@ -174,7 +219,14 @@ hipError_t launch_tables(const TabJob *jobs, int n_jobs, int max_n, const float4
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- k_pass
+// ---------------------------------------------------------------- k_sweep
+// Waves per SIMD the register budgets are sized for: the specialized sweep
+// fits without spills at this occupancy; the general one only at 3.
+#ifndef SWEEP_WAVES_FAST
+#define SWEEP_WAVES_FAST 6
+#endif
+#define SWEEP_WAVES_GENERAL 3
+
 __device__ __forceinline__ void cmul(float &ar, float &ai, float br, float bi) {
     const float r = ar * br - ai * bi;
     ai = ar * bi + ai * br;
@@ -196,10 +248,6 @@ __device__ __forceinline__ void ld4i(const int4 *p, int64_t i, int v[4]) {
     v[3] = t.w;
 }
 
-__device__ __forceinline__ bool same4(const int g[4]) { return g[0] == g[1] && g[0] == g[2] && g[0] == g[3]; }
-
-// Wave-uniform read of a table that no kernel writes while it runs: through
-// the constant address space, so a uniform index becomes one scalar load.
 // Table gathers and group-sum atomics through the global address space (the
 // pointers come out of op descriptors and would otherwise be flat accesses).
 typedef const __attribute__((address_space(1))) float *global_f32_ptr;
@@ -215,111 +263,12 @@ __device__ __forceinline__ void group_add(double *p, double v) {
     __builtin_amdgcn_global_atomic_fadd_f64((__attribute__((address_space(1))) double *)p, v);
 }
 
+// Wave-uniform read of a table that no kernel writes while it runs: through
+// the constant address space, so a uniform index becomes one scalar load.
 typedef const __attribute__((address_space(4))) float *const_f32_ptr;
 __device__ __forceinline__ float4 uniform_row(const float4 *tab, int g) {
     const_f32_ptr p = (const_f32_ptr)(tab + g);
     return make_float4(p[0], p[1], p[2], p[3]);
-}
-__device__ __forceinline__ float2 uniform_row(const float2 *tab, int g) {
-    const_f32_ptr p = (const_f32_ptr)(tab + g);
-    return make_float2(p[0], p[1]);
-}
-
-// Table rows of the thread's 4 isochromats.  Group ids are sorted runs, so
-// the whole wavefront usually shares one x-group (one scalar load) and a
-// thread's 4 neighbours usually share their other groups (one gather).
-template <class T>
-__device__ __forceinline__ void rows4(const T *__restrict__ tab, const int g[4], bool wave_uniform, int g_uni,
-                                      T out[4]) {
-    if (wave_uniform) {
-        const T v = uniform_row(tab, g_uni);
-        out[0] = out[1] = out[2] = out[3] = v;
-    } else if (same4(g)) {
-        const T v = gather_row(tab, g[0]);
-        out[0] = out[1] = out[2] = out[3] = v;
-    } else {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) out[c] = gather_row(tab, g[c]);
-    }
-}
-
-// Mxy factor a and E1 of a B1 = 0 map for the thread's 4 isochromats.
-__device__ __forceinline__ void map_factor4(const MapTabs &m, const int gx[4], bool gx_uni, int gx0,
-                                            const int gz[4], const float y[4], const float z[4],
-                                            float ar[4], float ai[4], float e1[4]) {
-    float4 xf[4];
-    rows4(m.xtab, gx, gx_uni, gx0, xf);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        ar[c] = xf[c].x;
-        ai[c] = xf[c].y;
-        e1[c] = xf[c].z;
-    }
-    if (m.ztab) {
-        float2 zf[4];
-        rows4(m.ztab, gz, false, 0, zf);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) cmul(ar[c], ai[c], zf[c].x, zf[c].y);
-    }
-    if (m.cy != 0.0) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            float s, co;
-            sincos_rev(m.cy * (double)y[c], &s, &co);
-            cmul(ar[c], ai[c], co, -s);
-        }
-    }
-    if (m.cz != 0.0) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            float s, co;
-            sincos_rev(m.cz * (double)z[c], &s, &co);
-            cmul(ar[c], ai[c], co, -s);
-        }
-    }
-}
-
-// Sum (vr, vi) per run of equal keys: within the thread, then across the
-// wavefront with a segmented inclusive scan; segment ends add to gsum.
-__device__ __forceinline__ void emit_runs(const int key[4], const float vr[4], const float vi[4],
-                                          bool act, double2 *__restrict__ gsum) {
-    int k = act ? key[0] : -1;
-    double sr = 0.0, si = 0.0;
-    if (act) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            if (key[c] != k) {
-                group_add(&gsum[k].x, sr);
-                group_add(&gsum[k].y, si);
-                sr = si = 0.0;
-                k = key[c];
-            }
-            sr += (double)vr[c];
-            si += (double)vi[c];
-        }
-    }
-    const int lane = __lane_id();
-    const int kp = __shfl_up(k, 1);
-    int head = (lane == 0) || (kp != k);
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double orr = __shfl_up(sr, d);
-        const double oi = __shfl_up(si, d);
-        const int oh = __shfl_up(head, d);
-        if (lane >= d) {
-            if (!head) {
-                sr += orr;
-                si += oi;
-            }
-            head |= oh;
-        }
-    }
-    const int kn = __shfl_down(k, 1);
-    const bool tail = (lane == 63) || (kn != k);
-    if (tail && k >= 0) {
-        group_add(&gsum[k].x, sr);
-        group_add(&gsum[k].y, si);
-    }
 }
 
 typedef const __attribute__((address_space(4))) uint64_t *const_u64_ptr;
@@ -337,13 +286,71 @@ __device__ __forceinline__ SweepOp load_op(const SweepOp *ops, int o) {
     return r;
 }
 
-__global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
+// x-group row: one scalar load when the wavefront sits inside one x-group.
+__device__ __forceinline__ float4 x_row(const float4 *tab, bool gx_uni, int gx0, int gx) {
+    return gx_uni ? uniform_row(tab, gx0) : gather_row(tab, gx);
+}
+
+// Group sums of (vr, vi) keyed by the thread's group id: one DPP-reduced
+// atomic pair when the wavefront has one key, else a segmented scan over
+// the lanes (keys are sorted runs) and one atomic pair per run end.
+__device__ __forceinline__ void emit_thread(int key, bool uni, float vr, float vi, bool act,
+                                            double2 *__restrict__ gsum) {
+    if (uni) {
+        vr = wave_sum_lane63(vr);
+        vi = wave_sum_lane63(vi);
+        if (__lane_id() == 63) {
+            group_add(&gsum[key].x, (double)vr);
+            group_add(&gsum[key].y, (double)vi);
+        }
+        return;
+    }
+    const int k = act ? key : -1;
+    const int lane = __lane_id();
+    const int kp = __shfl_up(k, 1);
+    int head = (lane == 0) || (kp != k);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const float orr = __shfl_up(vr, d);
+        const float oi = __shfl_up(vi, d);
+        const int oh = __shfl_up(head, d);
+        if (lane >= d) {
+            if (!head) {
+                vr += orr;
+                vi += oi;
+            }
+            head |= oh;
+        }
+    }
+    const int kn = __shfl_down(k, 1);
+    if (((lane == 63) || (kn != k)) && k >= 0) {
+        group_add(&gsum[k].x, (double)vr);
+        group_add(&gsum[k].y, (double)vi);
+    }
+}
+
+// Per-isochromat keys (the y axis is not part of the layout's runs).
+__device__ __forceinline__ void emit_items(const int key[4], const float vr[4], const float vi[4], bool act,
+                                           double2 *__restrict__ gsum) {
+    if (!act) return;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        group_add(&gsum[key[c]].x, (double)vr[c]);
+        group_add(&gsum[key[c]].y, (double)vi[c]);
+    }
+}
+
+// GENERAL = false drops what only y-group transitions/emissions and direct z
+// phases (no z groups) need, which frees registers for occupancy.
+template <bool GENERAL>
+__device__ __forceinline__ void sweep_body(const SweepArgs &a) {
     const int64_t i4 = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool act = i4 < a.n4;
-    const int need = a.need;
+    const int need = GENERAL ? a.need : (a.need & ~(kNeedGy | kNeedZ));
     float mx[4] = {0, 0, 0, 0}, my[4] = {0, 0, 0, 0}, mz[4] = {0, 0, 0, 0}, m0[4] = {0, 0, 0, 0};
     float yv[4] = {0, 0, 0, 0}, zv[4] = {0, 0, 0, 0};
-    int gx[4] = {-1, -1, -1, -1}, gy[4] = {0, 0, 0, 0}, gz[4] = {0, 0, 0, 0};
+    int gy[4] = {0, 0, 0, 0};
+    int gx = 0, gz = 0;  // the thread's 4 isochromats share their x- and z-groups
     if (act) {
         ld4(a.mx, i4, mx);
         ld4(a.my, i4, my);
@@ -351,95 +358,132 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
             ld4(a.mz, i4, mz);
             ld4(a.m0, i4, m0);
         }
-        if (need & kNeedGx) ld4i(a.gid_x, i4, gx);
+        if (need & kNeedGx) gx = a.gid_x[i4].x;
         if (need & kNeedGy) ld4i(a.gid_y, i4, gy);
-        if (need & kNeedGz) ld4i(a.gid_z, i4, gz);
+        if (need & kNeedGz) gz = a.gid_z[i4].x;
         if (need & kNeedY) ld4(a.yv, i4, yv);
         if (need & kNeedZ) ld4(a.zv, i4, zv);
     }
     // x-groups are contiguous runs in this order: is the wavefront inside one?
-    const int gx0 = __builtin_amdgcn_readfirstlane(gx[0]);
-    const bool gx_uni = __all(act && same4(gx) && gx[0] == gx0) != 0;
-    const int gxs[4] = {act ? gx[0] : 0, act ? gx[1] : 0, act ? gx[2] : 0, act ? gx[3] : 0};
+    const int gx0 = __builtin_amdgcn_readfirstlane(gx);
+    const bool gx_uni = __all(!act || gx == gx0) != 0;
+    float wr[4] = {1, 1, 1, 1}, wi[4] = {0, 0, 0, 0};  // y phase of the last emission
+    float rr[4] = {1, 1, 1, 1}, ri[4] = {0, 0, 0, 0};  // its per-step factor
 
     for (int o = 0; o < a.n_ops; ++o) {
         const SweepOp op = load_op(a.ops, o);
         if (op.flags & kOpPre) {
-            float ar[4], ai[4], e1[4];
-            map_factor4(op.pre, gxs, gx_uni, gx0, gz, yv, zv, ar, ai, e1);
+            float fr = 1.f, fi = 0.f, e1 = 1.f;
+            if (op.pre_xtab) {
+                const float4 v = x_row(op.pre_xtab, gx_uni, gx0, gx);
+                fr = v.x;
+                fi = v.y;
+                e1 = v.z;
+            }
+            if (op.pre_ztab) {
+                const float2 v = gather_row(op.pre_ztab, gz);
+                cmul(fr, fi, v.x, v.y);
+            }
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const float nx = mx[c] * ar[c] - my[c] * ai[c];
-                const float ny = mx[c] * ai[c] + my[c] * ar[c];
+                float ar = fr, ai = fi;
+                if (op.pre_cy != 0.0) {
+                    float s, co;
+                    sincos_rev(op.pre_cy * (double)yv[c], &s, &co);
+                    cmul(ar, ai, co, -s);
+                }
+                if (GENERAL && op.pre_cz != 0.0) {
+                    float s, co;
+                    sincos_rev(op.pre_cz * (double)zv[c], &s, &co);
+                    cmul(ar, ai, co, -s);
+                }
+                const float nx = mx[c] * ar - my[c] * ai;
+                const float ny = mx[c] * ai + my[c] * ar;
                 mx[c] = nx;
                 my[c] = ny;
-                mz[c] = fmaf(e1[c], mz[c] - m0[c], m0[c]);
+                if (op.flags & kPreMz) mz[c] = fmaf(e1, mz[c] - m0[c], m0[c]);
             }
         }
         if (op.flags & kOpRf) {
-            const int *grf = op.rf_axis == 0 ? gxs : (op.rf_axis == 1 ? gy : gz);
             const float4 *__restrict__ tt = op.ttab;
-            float4 r0[4], r1[4], r2[4];
-            if (op.rf_axis == 0 && gx_uni) {
-                const float4 u0 = uniform_row(tt, 3 * gx0), u1 = uniform_row(tt, 3 * gx0 + 1),
-                             u2 = uniform_row(tt, 3 * gx0 + 2);
+            if (GENERAL && op.rf_axis == 1) {  // y groups: rows per isochromat
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    r0[c] = u0;
-                    r1[c] = u1;
-                    r2[c] = u2;
-                }
-            } else if (same4(grf)) {
-                const int g = grf[0];
-                const float4 u0 = gather_row(tt, 3 * g), u1 = gather_row(tt, 3 * g + 1),
-                             u2 = gather_row(tt, 3 * g + 2);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    r0[c] = u0;
-                    r1[c] = u1;
-                    r2[c] = u2;
+                    const float4 r0 = gather_row(tt, 3 * gy[c]), r1 = gather_row(tt, 3 * gy[c] + 1),
+                                 r2 = gather_row(tt, 3 * gy[c] + 2);
+                    const float nx = fmaf(r0.x, mx[c], fmaf(r0.y, my[c], fmaf(r0.z, mz[c], r0.w * m0[c])));
+                    const float ny = fmaf(r1.x, mx[c], fmaf(r1.y, my[c], fmaf(r1.z, mz[c], r1.w * m0[c])));
+                    const float nz = fmaf(r2.x, mx[c], fmaf(r2.y, my[c], fmaf(r2.z, mz[c], r2.w * m0[c])));
+                    mx[c] = nx;
+                    my[c] = ny;
+                    mz[c] = nz;
                 }
             } else {
+                float4 r0, r1, r2;
+                if (op.rf_axis == 0 && gx_uni) {
+                    r0 = uniform_row(tt, 3 * gx0);
+                    r1 = uniform_row(tt, 3 * gx0 + 1);
+                    r2 = uniform_row(tt, 3 * gx0 + 2);
+                } else {
+                    const int g = op.rf_axis == 0 ? gx : gz;
+                    r0 = gather_row(tt, 3 * g);
+                    r1 = gather_row(tt, 3 * g + 1);
+                    r2 = gather_row(tt, 3 * g + 2);
+                }
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    r0[c] = gather_row(tt, 3 * grf[c]);
-                    r1[c] = gather_row(tt, 3 * grf[c] + 1);
-                    r2[c] = gather_row(tt, 3 * grf[c] + 2);
+                    const float nx = fmaf(r0.x, mx[c], fmaf(r0.y, my[c], fmaf(r0.z, mz[c], r0.w * m0[c])));
+                    const float ny = fmaf(r1.x, mx[c], fmaf(r1.y, my[c], fmaf(r1.z, mz[c], r1.w * m0[c])));
+                    const float nz = fmaf(r2.x, mx[c], fmaf(r2.y, my[c], fmaf(r2.z, mz[c], r2.w * m0[c])));
+                    mx[c] = nx;
+                    my[c] = ny;
+                    mz[c] = nz;
                 }
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const float nx = fmaf(r0[c].x, mx[c], fmaf(r0[c].y, my[c], fmaf(r0[c].z, mz[c], r0[c].w * m0[c])));
-                const float ny = fmaf(r1[c].x, mx[c], fmaf(r1[c].y, my[c], fmaf(r1[c].z, mz[c], r1[c].w * m0[c])));
-                const float nz = fmaf(r2[c].x, mx[c], fmaf(r2[c].y, my[c], fmaf(r2[c].z, mz[c], r2[c].w * m0[c])));
-                mx[c] = nx;
-                my[c] = ny;
-                mz[c] = nz;
             }
         }
         if (op.flags & kOpEmit) {
-            float ar[4], ai[4], e1[4], vr[4], vi[4];
-            map_factor4(op.emit, gxs, gx_uni, gx0, gz, yv, zv, ar, ai, e1);
+            const float4 xv = x_row(op.emit_xtab, gx_uni, gx0, gx);
+            float fr = xv.x, fi = xv.y;
+            if (op.emit_ztab) {
+                const float2 v = gather_row(op.emit_ztab, gz);
+                cmul(fr, fi, v.x, v.y);
+            }
+            float vr[4], vi[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                vr[c] = act ? mx[c] * ar[c] - my[c] * ai[c] : 0.f;
-                vi[c] = act ? mx[c] * ai[c] + my[c] * ar[c] : 0.f;
-            }
-            if (op.emit_axis == 0 && gx_uni) {
-                // one group for the whole wavefront: DPP sum, one FP64 atomic pair
-                float sr = (vr[0] + vr[1]) + (vr[2] + vr[3]);
-                float si = (vi[0] + vi[1]) + (vi[2] + vi[3]);
-                sr = wave_sum_lane63(sr);
-                si = wave_sum_lane63(si);
-                if (__lane_id() == 63) {
-                    group_add(&op.gsum[gx0].x, (double)sr);
-                    group_add(&op.gsum[gx0].y, (double)si);
+                if (op.flags & kYDirect) {
+                    float s, co;
+                    sincos_rev(op.emit_cy * (double)yv[c], &s, &co);
+                    wr[c] = co;
+                    wi[c] = -s;
+                } else if (op.flags & kYStep) {
+                    cmul(wr[c], wi[c], rr[c], ri[c]);
                 }
+                if (op.flags & kYSetR) {
+                    float s, co;
+                    sincos_rev(op.emit_dcy * (double)yv[c], &s, &co);
+                    rr[c] = co;
+                    ri[c] = -s;
+                }
+                float ar = fr, ai = fi;
+                if (op.flags & (kYDirect | kYStep)) cmul(ar, ai, wr[c], wi[c]);
+                if (GENERAL && op.emit_cz != 0.0) {
+                    float s, co;
+                    sincos_rev(op.emit_cz * (double)zv[c], &s, &co);
+                    cmul(ar, ai, co, -s);
+                }
+                vr[c] = mx[c] * ar - my[c] * ai;
+                vi[c] = mx[c] * ai + my[c] * ar;
+            }
+            if (GENERAL && op.emit_axis == 1) {
+                emit_items(gy, vr, vi, act, op.gsum);
             } else {
-                int key[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) key[c] = op.emit_axis == 0 ? gxs[c] : (op.emit_axis == 1 ? gy[c] : gz[c]);
-                emit_runs(key, vr, vi, act, op.gsum);
+                const float sr = (vr[0] + vr[1]) + (vr[2] + vr[3]);
+                const float si = (vi[0] + vi[1]) + (vi[2] + vi[3]);
+                if (op.emit_axis == 0)
+                    emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
+                else
+                    emit_thread(gz, false, sr, si, act, op.gsum);
             }
         }
     }
@@ -450,10 +494,22 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
     }
 }
 
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES_FAST))) void k_sweep(SweepArgs a) {
+    sweep_body<false>(a);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES_GENERAL))) void k_sweep_general(
+    SweepArgs a) {
+    sweep_body<true>(a);
+}
+
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
     if (a.n4 <= 0 || a.n_ops <= 0) return hipSuccess;
     const int64_t grid = (a.n4 + 255) / 256;
-    hipLaunchKernelGGL(k_sweep, dim3((unsigned)grid), dim3(256), 0, st, a);
+    if (a.need & (kNeedGy | kNeedZ))
+        hipLaunchKernelGGL(k_sweep_general, dim3((unsigned)grid), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_sweep, dim3((unsigned)grid), dim3(256), 0, st, a);
     return hipGetLastError();
 }
 
@@ -516,9 +572,9 @@ __global__ void k_init_state(int64_t K, int64_t Kpad, const int32_t *__restrict_
                              float *__restrict__ mx, float *__restrict__ my, float *__restrict__ mz) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < Kpad; i += (int64_t)gridDim.x * blockDim.x) {
         float x = 0.f, y = 0.f, z = 0.f;
-        if (i < K) {
+        const int32_t k = i < K ? perm[i] : -1;  // -1: padding of the group-sorted layout
+        if (k >= 0) {
             if (ix) {
-                const int32_t k = perm[i];
                 x = ix[k];
                 y = iy[k];
                 z = iz[k];
@@ -547,6 +603,7 @@ __global__ void k_scatter_state(int64_t K, const int32_t *__restrict__ perm, con
                                 float *ox, float *oy, float *oz) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t k = perm[i];
+        if (k < 0) continue;  // padding
         ox[k] = mx[i];
         oy[k] = my[i];
         oz[k] = mz[i];

@@ -82,6 +82,72 @@ __global__ void k_validate(int64_t K, PhantomPtrs ph, int *bad) {
     }
 }
 
+// ---- padded group-sorted layout ---------------------------------------------
+// Isochromats are ordered by (x-group, z-group, index) and every run of equal
+// (x-group, z-group) is padded to a multiple of 4 with copies of its first
+// member carrying M0 = 0.  A thread's 4 consecutive isochromats then always
+// share both groups.
+__global__ void k_pair_keys(int64_t K, const int32_t *__restrict__ gx, const int32_t *__restrict__ gz,
+                            uint64_t *__restrict__ key, int32_t *__restrict__ idx) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
+        key[i] = ((uint64_t)(uint32_t)gx[i] << 32) | (gz ? (uint32_t)gz[i] : 0u);
+        idx[i] = (int32_t)i;
+    }
+}
+
+__global__ void k_key_heads(int64_t K, const uint64_t *__restrict__ key, int32_t *__restrict__ flag) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x)
+        flag[i] = (i == 0 || key[i] != key[i - 1]) ? 1 : 0;
+}
+
+__global__ void k_run_start(int64_t K, const int32_t *__restrict__ rid, int32_t *__restrict__ rstart) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x)
+        if (i == 0 || rid[i] != rid[i - 1]) rstart[rid[i] - 1] = (int32_t)i;
+}
+
+__global__ void k_run_plen(int64_t R, int64_t K, const int32_t *__restrict__ rstart, int32_t *__restrict__ plen) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t L = (int32_t)((r + 1 < R ? rstart[r + 1] : K) - rstart[r]);
+        plen[r] = (L + 3) & ~3;
+    }
+}
+
+__global__ void k_place(int64_t K, const int32_t *__restrict__ rid, const int32_t *__restrict__ rstart,
+                        const int32_t *__restrict__ pstart, const int32_t *__restrict__ order,
+                        int32_t *__restrict__ perm, int32_t *__restrict__ src) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = rid[i] - 1;
+        const int64_t pos = (int64_t)pstart[r] + (i - rstart[r]);
+        perm[pos] = order[i];
+        src[pos] = order[i];
+    }
+}
+
+__global__ void k_pad(int64_t R, int64_t K, const int32_t *__restrict__ rstart, const int32_t *__restrict__ pstart,
+                      const int32_t *__restrict__ plen, const int32_t *__restrict__ order, int32_t *__restrict__ perm,
+                      int32_t *__restrict__ src) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t L = (int32_t)((r + 1 < R ? rstart[r + 1] : K) - rstart[r]);
+        const int32_t first = order[rstart[r]];
+        for (int32_t j = L; j < plen[r]; ++j) {
+            perm[pstart[r] + j] = -1;
+            src[pstart[r] + j] = first;
+        }
+    }
+}
+
+__global__ void k_fill_tail(int64_t from, int64_t to, int32_t *__restrict__ perm, int32_t *__restrict__ src) {
+    for (int64_t i = from + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < to; i += (int64_t)gridDim.x * blockDim.x) {
+        perm[i] = -1;
+        src[i] = 0;
+    }
+}
+
+__global__ void k_zero_padding(int64_t n, const int32_t *__restrict__ perm, float *__restrict__ m0) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (perm[i] < 0) m0[i] = 0.0f;
+}
+
 static dim3 grid_for(int64_t n) {
     int64_t g = (n + 255) / 256;
     if (g > 8192) g = 8192;
@@ -106,14 +172,71 @@ hipError_t launch_gather_i32(int64_t K, int64_t Kpad, const int32_t *perm, const
     return hipGetLastError();
 }
 
+// Build the padded layout from natural-order x (and optional z) group ids.
+// perm[pos] = isochromat at internal position pos or -1 (padding); src[pos] =
+// the isochromat whose parameters the position copies.  perm/src need room
+// for Kpad_cap entries; *kint receives the padded count (a multiple of 4).
+hipError_t build_layout(int64_t K, const int32_t *gid_x, const int32_t *gid_z, void *scratch, size_t scratch_bytes,
+                        int32_t *perm, int32_t *src, int64_t Kpad_cap, int64_t *kint, hipStream_t st) {
+    char *p = (char *)scratch;
+    auto take = [&](size_t n) {
+        char *r = p;
+        p += (n + 255) & ~(size_t)255;
+        return (void *)r;
+    };
+    uint64_t *key = (uint64_t *)take(8 * K), *key2 = (uint64_t *)take(8 * K);
+    int32_t *idx = (int32_t *)take(4 * K), *order = (int32_t *)take(4 * K), *flag = (int32_t *)take(4 * K);
+    int32_t *rid = (int32_t *)take(4 * K), *rstart = (int32_t *)take(4 * K), *plen = (int32_t *)take(4 * K);
+    int32_t *pstart = (int32_t *)take(4 * K);
+    const size_t used = (size_t)(p - (char *)scratch);
+    if (used > scratch_bytes) return hipErrorInvalidValue;
+    void *tmp = p;
+    size_t tmp_bytes = scratch_bytes - used;
+    const dim3 g = grid_for(K);
+    hipError_t e;
+    hipLaunchKernelGGL(k_pair_keys, g, dim3(256), 0, st, K, gid_x, gid_z, key, idx);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key, key2, idx, order, (int)K, 0, 64, st)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_key_heads, g, dim3(256), 0, st, K, key2, flag);
+    if ((e = hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, flag, rid, (int)K, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_run_start, g, dim3(256), 0, st, K, rid, rstart);
+    int32_t R = 0;
+    if ((e = hipMemcpyAsync(&R, rid + (K - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_run_plen, grid_for(R), dim3(256), 0, st, (int64_t)R, K, rstart, plen);
+    if ((e = hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, plen, pstart, (int)R, st)) != hipSuccess) return e;
+    int32_t last[2] = {0, 0};
+    if ((e = hipMemcpyAsync(&last[0], pstart + (R - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return e;
+    if ((e = hipMemcpyAsync(&last[1], plen + (R - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    const int64_t n = (int64_t)last[0] + last[1];
+    if (n > Kpad_cap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_place, g, dim3(256), 0, st, K, rid, rstart, pstart, order, perm, src);
+    hipLaunchKernelGGL(k_pad, grid_for(R), dim3(256), 0, st, (int64_t)R, K, rstart, pstart, plen, order, perm, src);
+    if (Kpad_cap > n) hipLaunchKernelGGL(k_fill_tail, grid_for(Kpad_cap - n), dim3(256), 0, st, n, Kpad_cap, perm, src);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    *kint = n;
+    return hipSuccess;
+}
+
+hipError_t launch_zero_padding(int64_t n, const int32_t *perm, float *m0, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_padding, grid_for(n), dim3(256), 0, st, n, perm, m0);
+    return hipGetLastError();
+}
+
 size_t group_scratch_bytes(int64_t K) {
-    size_t sort_tmp = 0, scan_tmp = 0;
+    size_t sort_tmp = 0, scan_tmp = 0, escan_tmp = 0;
     hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, (const uint64_t *)nullptr, (uint64_t *)nullptr,
                                        (const int32_t *)nullptr, (int32_t *)nullptr, (int)K, 0, 64);
     hipcub::DeviceScan::InclusiveSum(nullptr, scan_tmp, (const int32_t *)nullptr, (int32_t *)nullptr, (int)K);
-    const size_t tmp = sort_tmp > scan_tmp ? sort_tmp : scan_tmp;
-    // 4 u64 key arrays, 3 i32 arrays, tmp
-    return 4 * sizeof(uint64_t) * K + 3 * sizeof(int32_t) * K + tmp + 8 * 256;
+    hipcub::DeviceScan::ExclusiveSum(nullptr, escan_tmp, (const int32_t *)nullptr, (int32_t *)nullptr, (int)K);
+    size_t tmp = sort_tmp > scan_tmp ? sort_tmp : scan_tmp;
+    if (escan_tmp > tmp) tmp = escan_tmp;
+    // the larger of group_axis (4 u64 + 3 i32 arrays) and build_layout (2 u64 + 7 i32), plus tmp
+    return 4 * sizeof(uint64_t) * K + 7 * sizeof(int32_t) * K + tmp + 16 * 256;
 }
 
 // Group one axis.  coord = r_a of every isochromat (natural order).  Writes

@@ -35,27 +35,31 @@ struct PlainArgs {
     double gdt;           // gamma * dt (rad / T)
 };
 
-// ---- grouped streaming pass ---------------------------------------------
-struct MapTabs {
-    const float4 *xtab;  // per x-group: (Re a, Im a, E1, 0)
-    const float2 *ztab;  // per z-group phase factor; null -> direct z phase via cz
-    double cy;           // gamma_bar * m_y; 0 -> no y phase
-    double cz;           // gamma_bar * m_z for the direct z phase; 0 -> none
-};
-
+// ---- grouped sweep -------------------------------------------------------
 // One grouped operation (Sec. 2.3) inside a sweep:
-//   M <- [RF group transition] o [pre map] (M); then, if emitting, the group
-//   sums of emit-map(Mxy) for one with-ADC subsequence (Eq. 9).
-// Read by every wavefront with scalar loads.
-enum { kOpPre = 1, kOpRf = 2, kOpEmit = 4 };
+//   M <- T'_g o [remaining pre-map phases] (M), where T' is the group
+//   transition with the tissue and own-axis part of the preceding B1 = 0 map
+//   folded in; then, if emitting, the group sums of emit-map(Mxy) for one
+//   with-ADC subsequence (Eq. 9).  An operation without a transition applies
+//   its whole pre map per isochromat (kPreMz: with T1 recovery).
+// y phases of consecutive emissions follow a recurrence when their
+// coefficients step evenly (kYDirect starts it, kYSetR sets the step, kYStep
+// advances it).  Every wavefront reads the descriptor with scalar loads.
+enum { kOpPre = 1, kOpRf = 2, kOpEmit = 4, kPreMz = 8, kYDirect = 16, kYStep = 32, kYSetR = 64 };
 struct SweepOp {
     int32_t flags;
     int32_t rf_axis;
     int32_t emit_axis;
     int32_t pad;
-    MapTabs pre;
-    const float4 *ttab;  // 3 float4 rows (A_r0, A_r1, A_r2, b_r) per group
-    MapTabs emit;
+    const float4 *pre_xtab;  // per x-group (Re a, Im a, E1, 0); null: no x factor
+    const float2 *pre_ztab;  // per z-group phase; null: none
+    double pre_cy, pre_cz;   // direct y / z phase coefficients (cycles per metre); 0: none
+    const float4 *ttab;      // 3 float4 rows (A_r0, A_r1, A_r2, b_r) per group of rf_axis
+    const float4 *emit_xtab; // per x-group: decay, off-resonance and x phase
+    const float2 *emit_ztab; // per z-group phase; null: none
+    double emit_cy;          // y phase coefficient (cycles per metre)
+    double emit_dcy;         // recurrence step of emit_cy (kYSetR)
+    double emit_cz;          // direct z phase coefficient (no z groups)
     double2 *gsum;
 };
 
@@ -64,6 +68,8 @@ enum { kNeedMz = 1, kNeedGx = 2, kNeedGy = 4, kNeedGz = 8, kNeedY = 16, kNeedZ =
 
 // A sweep applies ops[0 .. n_ops) in order to every isochromat while its
 // state stays in registers: one read and at most one write of M per launch.
+// The layout guarantees that the 4 isochromats of a thread share their x- and
+// z-groups.
 struct SweepArgs {
     int64_t n4;  // number of 4-isochromat chunks
     float4 *mx, *my, *mz;
@@ -78,7 +84,8 @@ struct SweepArgs {
 
 // ---- tables ---------------------------------------------------------------
 struct TabJob {
-    int32_t kind;  // 0: x-group map factor (float4), 1: z-group phase (float2)
+    int32_t kind;  // 0: x-group decay, off-resonance, x phase, E1 (float4); 1: z-group phase (float2);
+                   // 2: x-group x phase only (float4, E1 = 1)
     int32_t n;     // groups
     double tau;    // duration (kind 0)
     double cyc;    // gamma_bar * moment along the table's axis
@@ -91,7 +98,20 @@ struct RfJobDev {
     int64_t n_groups;
     const StepW *wave;
     const float4 *gtab;  // (coord, T1, T2, df) per group
-    float4 *out;         // 3 float4 per group
+    double *out;         // 12 doubles (A row-major, b) per group
+};
+
+// T' = T o P for one operation: P is the tissue part (decay, off-resonance,
+// T1 recovery) and the own-axis phase of its pre map (identity if none).
+struct FoldJob {
+    int32_t axis;
+    int32_t has_pre;
+    int64_t n_groups;
+    const double *t64;
+    const float4 *gtab;
+    double tau;
+    double cyc;  // gamma_bar * moment along `axis`
+    float4 *out;
 };
 
 struct AdcJobDev {
@@ -114,6 +134,7 @@ hipError_t launch_tables(const TabJob *jobs, int n_jobs, int max_n, const float4
                          const float4 *gtab_z, hipStream_t st);
 hipError_t launch_compose(const RfJobDev *jobs, int n_jobs, int64_t max_groups, double dt,
                           hipStream_t st);
+hipError_t launch_fold(const FoldJob *jobs, int n_jobs, int64_t max_groups, hipStream_t st);
 hipError_t launch_adc_eval(const AdcJobDev *jobs, int n_jobs, int max_groups, int max_samples,
                            double *sig, hipStream_t st);
 hipError_t launch_fill_f64(double *p, int64_t n, hipStream_t st);
