@@ -93,7 +93,7 @@ struct gbs_ctx {
     int64_t ng[3] = {-1, -1, -1};
     int64_t Kint = 0;  // isochromats in the padded group-sorted layout (multiple of 4)
     int64_t Kpad = 0;
-    DevBuf perm, xi, yi, zi, t1i, t2i, dfi, m0i, gid[3], gtab[3], gcount[3], ms[3];
+    DevBuf perm, inv, xi, yi, zi, t1i, t2i, dfi, m0i, gid[3], gtab[3], gcount[3], ms[3];
     // per-simulate buffers
     DevBuf tabs, gsum, partial, jobs, samp, flag;
     std::vector<char> host_jobs;  // kept alive until the next call
@@ -167,7 +167,7 @@ int gbs_destroy(gbs_ctx *ctx) {
     if (!ctx) return GBS_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
-    DevBuf *bufs[] = {&ctx->d_wave, &ctx->d_adc, &ctx->perm, &ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i,
+    DevBuf *bufs[] = {&ctx->d_wave, &ctx->d_adc, &ctx->perm, &ctx->inv, &ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i,
                       &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->tabs, &ctx->gsum, &ctx->partial, &ctx->jobs,
                       &ctx->samp, &ctx->flag};
     for (DevBuf *b : bufs) b->release();
@@ -302,6 +302,8 @@ int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
     const int64_t Kpad = (kint + 1023) / 1024 * 1024;
     ALLOC(ctx->perm, 4 * Kpad);
     HIPCHK(hipMemcpyAsync(ctx->perm.p, perm_tmp.p, 4 * Kpad, hipMemcpyDeviceToDevice, ctx->stream));
+    ALLOC(ctx->inv, 4 * K);
+    HIPCHK(launch_invert(Kpad, ctx->perm.as<int32_t>(), ctx->inv.as<int32_t>(), ctx->stream));
     const int32_t *src = src_tmp.as<int32_t>();
     for (int a = 0; a < 3; ++a) {
         if (!(axes & (1u << a))) continue;
@@ -807,7 +809,7 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     HIPCHK(launch_adc_eval((const AdcJobDev *)(jb + g.o_adc), g.n_adc, g.max_adc_groups, g.max_adc_samples,
                            sig_out, ctx->stream));
     if (st) HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
-    HIPCHK(launch_scatter_state(Kint, ctx->perm.as<int32_t>(), mx, my, mz, m_out, m_out + K, m_out + 2 * K,
+    HIPCHK(launch_gather_state(K, ctx->inv.as<int32_t>(), mx, my, mz, m_out, m_out + K, m_out + 2 * K,
                                 ctx->stream));
     if (st) {
         st->n_passes = g.n_ops;

@@ -13,6 +13,7 @@ hipError_t group_axis(int64_t K, const float *coord, const float *t1, const floa
                       int32_t *gcount, int32_t *order, int64_t *n_groups, hipStream_t st);
 hipError_t build_layout(int64_t K, const int32_t *gid_x, const int32_t *gid_z, void *scratch, size_t scratch_bytes,
                         int32_t *perm, int32_t *src, int64_t Kpad_cap, int64_t *kint, hipStream_t st);
+hipError_t launch_invert(int64_t n, const int32_t *perm, int32_t *inv, hipStream_t st);
 hipError_t launch_zero_padding(int64_t n, const int32_t *perm, float *m0, hipStream_t st);
 hipError_t launch_gather_f32(int64_t K, int64_t Kpad, const int32_t *perm, const float *src, float *dst,
                              hipStream_t st);

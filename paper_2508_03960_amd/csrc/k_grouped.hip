@@ -598,24 +598,25 @@ hipError_t launch_init_state(int64_t K, int64_t Kpad, const int32_t *perm, const
     return hipGetLastError();
 }
 
-__global__ void k_scatter_state(int64_t K, const int32_t *__restrict__ perm, const float *__restrict__ mx,
-                                const float *__restrict__ my, const float *__restrict__ mz,
-                                float *ox, float *oy, float *oz) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t k = perm[i];
-        if (k < 0) continue;  // padding
+// Final state in the caller's order: coalesced writes, reads through the
+// inverse permutation (neighbouring caller indices usually sit in nearby
+// rows of the group-sorted layout, so the reads hit L2).
+__global__ void k_gather_state(int64_t K, const int32_t *__restrict__ inv, const float *__restrict__ mx,
+                               const float *__restrict__ my, const float *__restrict__ mz, float *ox, float *oy,
+                               float *oz) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t i = inv[k];
         ox[k] = mx[i];
         oy[k] = my[i];
         oz[k] = mz[i];
     }
 }
 
-hipError_t launch_scatter_state(int64_t K, const int32_t *perm, const float *mx, const float *my,
-                                const float *mz, float *ox, float *oy, float *oz, hipStream_t st) {
+hipError_t launch_gather_state(int64_t K, const int32_t *inv, const float *mx, const float *my, const float *mz,
+                               float *ox, float *oy, float *oz, hipStream_t st) {
     int64_t g = (K + 255) / 256;
-    if (g > 8192) g = 8192;
-    hipLaunchKernelGGL(k_scatter_state, dim3((unsigned)g), dim3(256), 0, st, K, perm, mx, my, mz, ox,
-                       oy, oz);
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(k_gather_state, dim3((unsigned)g), dim3(256), 0, st, K, inv, mx, my, mz, ox, oy, oz);
     return hipGetLastError();
 }
 

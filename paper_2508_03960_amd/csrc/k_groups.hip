@@ -222,6 +222,16 @@ hipError_t build_layout(int64_t K, const int32_t *gid_x, const int32_t *gid_z, v
     return hipSuccess;
 }
 
+__global__ void k_invert(int64_t n, const int32_t *__restrict__ perm, int32_t *__restrict__ inv) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (perm[i] >= 0) inv[perm[i]] = (int32_t)i;
+}
+
+hipError_t launch_invert(int64_t n, const int32_t *perm, int32_t *inv, hipStream_t st) {
+    hipLaunchKernelGGL(k_invert, grid_for(n), dim3(256), 0, st, n, perm, inv);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_padding(int64_t n, const int32_t *perm, float *m0, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_padding, grid_for(n), dim3(256), 0, st, n, perm, m0);
     return hipGetLastError();

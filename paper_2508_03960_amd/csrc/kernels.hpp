@@ -141,8 +141,8 @@ hipError_t launch_fill_f64(double *p, int64_t n, hipStream_t st);
 hipError_t launch_init_state(int64_t K, int64_t Kpad, const int32_t *perm, const float *mi_x,
                              const float *mi_y, const float *mi_z, const float *m0i, float *mx,
                              float *my, float *mz, hipStream_t st);
-hipError_t launch_scatter_state(int64_t K, const int32_t *perm, const float *mx, const float *my,
-                                const float *mz, float *ox, float *oy, float *oz, hipStream_t st);
+hipError_t launch_gather_state(int64_t K, const int32_t *inv, const float *mx, const float *my, const float *mz,
+                               float *ox, float *oy, float *oz, hipStream_t st);
 
 // ---- grouping ---------------------------------------------------------------
 hipError_t launch_validate_phantom(int64_t K, const PhantomPtrs &ph, int *bad, hipStream_t st);
