@@ -10,7 +10,8 @@ Throughput = K * (raster steps inside RF and ADC blocks) / time.
 Also reported: the EPI workload (grouped), the plain per-isochromat method
 on the same GPU (FSE: first shot of the sequence at full K; EPI: whole),
 the grouped-vs-plain speedup, the roofline of the dominant kernel (the
-streaming pass k_pass) and the FP64 CPU oracle timed on the host cores.
+fused grouped sweep k_sweep: algorithmic FP32 flops per launch over its
+HIP-event-timed duration) and the FP64 CPU oracle timed on the host cores.
 
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1]
 """
