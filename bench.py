@@ -96,6 +96,75 @@ def cpu_baseline(ph, seq, target_s=15.0):
                       f"({S} stepped raster steps each), FP64, {dt:.1f} s"}, idx, M
 
 
+MLP_MACS = 5 * 128 + 128 * 128 * 2 + 128 * 12  # multiply-adds per network evaluation
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
+
+
+def surrogate_leg(sim, gb, ph, fse, sig_exact, m_out, steps):
+    """Learned RF-transition surrogate of the FSE 180-degree pulse: training on
+    2M simulator-generated transitions, per-transition speed and accuracy,
+    and the FSE run with the network in place of the exact composition."""
+    import numpy as np
+    import torch
+
+    import synth
+    rf, gz, dt = synth.fse_refocusing_pulse()
+    m = gb.Mlp(0, seed=7)
+    m.set_pulse(rf, gz, dt)
+    m.set_params(synth.mlp_init_params(seed=7))
+    tup = torch.from_numpy(synth.surrogate_tuples(1 << 21, seed=36)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T = m.exact(tup)
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    hist = m.train(tup, T, epochs=32, batch=1024, lr_max=3e-3, lr_min=1e-6, seed=2)
+    t_train = time.perf_counter() - t0
+    del tup, T
+    # per-isochromat transitions of the whole phantom (what a plain, per-isochromat path needs)
+    g_ref = float(np.max(np.abs(np.float32(gz))))
+    pt = np.stack([synth.GAMMA_BAR * g_ref * ph.z, ph.df, ph.t1, ph.t2, np.ones(ph.K)], 1).astype(np.float32)
+    pt = torch.from_numpy(pt).cuda()
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for _ in range(2):  # second pass timed warm
+        ev[0].record(st)
+        Tm = m.infer(pt)
+        ev[1].record(st)
+        Te = m.exact(pt)
+        ev[2].record(st)
+        torch.cuda.synchronize()
+    ms_inf, ms_ex = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    err = (Tm.double() - Te).abs().max(dim=1).values
+    err_q = torch.quantile(err[:: -(-ph.K // (1 << 24))].float(), torch.tensor([0.5, 0.99], device=err.device))
+    res = {"training": {"samples": 1 << 21, "exact_data_s": t_data, "epochs": 32, "batch": 1024,
+                        "steps": int(hist.size), "train_s": t_train, "us_per_step": t_train / hist.size * 1e6,
+                        "final_loss": float(hist[-1])},
+           "per_isochromat_transitions": {
+               "count": ph.K, "network_ms": ms_inf, "exact_fp64_ms": ms_ex, "speedup": ms_ex / ms_inf,
+               "max_abs_err": float(err.max()), "median_abs_err": float(err_q[0]),
+               "p99_abs_err": float(err_q[1]),
+               "mfma_roofline": {"kernel": "k_mlp_infer", "bound": "mfma",
+                                 "achieved": 2 * MLP_MACS * ph.K / (ms_inf * 1e-3) / 1e12,
+                                 "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": 2 * MLP_MACS * ph.K / (ms_inf * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+                                 "issued_over_algorithmic": 2.0}}}
+    del Tm, Te, pt, err
+    sig = torch.empty_like(torch.view_as_real(sig_exact))
+    ref = sig_exact.cpu().numpy()
+    for name, tol in (("spot_checked_tol_1e-3", 1e-3), ("forced", 1e9)):
+        gb.set_surrogate(sim, m, tol=tol, n_check=32, seed=11)
+        sec, sts = timed_runs(sim, gb, gb.GBS_GROUPED, steps, 1, m_out, sig, flags=gb.GBS_SURROGATE)
+        s_np = torch.view_as_complex(sig).cpu().numpy()
+        res["fse_" + name] = {"ms": sec * 1e3, "fallback": bool(sts[-1]["n_surrogate_fallback"]),
+                              "spot_check_residual": sts[-1]["surrogate_residual"],
+                              "signal_rel_err_vs_grouped_exact": float(np.linalg.norm(s_np - ref) /
+                                                                       np.linalg.norm(ref))}
+    gb.set_surrogate(sim, None)
+    m.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +173,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-method runs")
     ap.add_argument("--no-epi", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -159,6 +229,7 @@ def main():
     flops_launch = stats[-1]["pass_flops"] / n_sw
     achieved = flops_launch / (sweep_ms * 1e-3) / 1e12
     M_fse = m_out.cpu().numpy()
+    sig_fse_exact = torch.view_as_complex(sig_fse).clone()
 
     out = {
         "metric": "isochromat-steps/s grouped vs plain (same GPU); FSE/EPI sim time @27.3M isos",
@@ -179,6 +250,12 @@ def main():
                                                       ("ms_prepare", "ms_passes", "ms_adc_eval")},
                 "build_groups_s": t_groups},
     }
+
+    # ---- learned RF-transition surrogate (FSE 180-degree pulse) --------------------
+    if not args.no_surrogate:
+        sim.set_sequence(fse)
+        out["surrogate"] = surrogate_leg(sim, gb, ph, fse, sig_fse_exact, m_out, args.steps)
+        log(f"surrogate: {out['surrogate']}")
 
     # ---- EPI grouped --------------------------------------------------------------
     if not args.no_epi:

@@ -62,6 +62,8 @@ extern "C" {
 #define GBS_ASYNC 1u      /* enqueue on the context stream and return; no final synchronize */
 #define GBS_PLAIN_FP32 2u /* GBS_PLAIN: step in FP32 instead of FP64 (faster to state, less exact) */
 #define GBS_PROFILE 4u    /* time every sweep launch with HIP events (gbs_stats.pass_kernel_ms) */
+#define GBS_SURROGATE 8u  /* GBS_GROUPED: transitions of RF blocks that match the attached surrogate's
+                             pulse come from the network, with the spot-check fallback (gbs_set_surrogate) */
 
 /*
  * One subsequence.  RF/ADC blocks cover raster steps
@@ -110,6 +112,9 @@ typedef struct gbs_stats {
     double pass_kernel_ms; /* GBS_PROFILE: sum of the sweep kernel durations */
     int64_t n_sweeps;      /* sweep launches: runs of grouped operations applied in one pass */
     double pass_flops;     /* algorithmic FP32 flops of the sweeps (factor products, maps, transitions, sums) */
+    int64_t n_surrogate;   /* GBS_SURROGATE: distinct RF transitions taken from the network */
+    int64_t n_surrogate_fallback; /* ... of which failed the spot check and were composed exactly */
+    double surrogate_residual;    /* largest spot-check residual max|T_mlp - T_exact| (0 if none) */
 } gbs_stats;
 
 typedef struct gbs_ctx gbs_ctx;
@@ -191,6 +196,95 @@ int gbs_plan_summary(const gbs_block *blocks, int64_t n_blocks, const float *rf_
                      const float *rf_im, const float *gx, const float *gy, const float *gz,
                      int64_t total_steps, const int32_t *adc_idx, int64_t total_samples, double dt,
                      uint32_t axes, int64_t out[8]);
+
+
+/* ==== learned RF-transition surrogate ==================================
+ *
+ * A 5-128-128-128-12 network with SiLU activations that maps the parameters
+ * of one isochromat group to the 3x4 combined transition T (Eq. 7) of one
+ * fixed with-RF, Gz-only subsequence (the "pulse"): T replaces the exact
+ * composition when it passes a spot check.  Inputs per tuple, float[5]:
+ *   f_z  = gamma_bar * g_ref * z   (Hz; g_ref = peak |Gz| of the pulse),
+ *   f_B0 = dB0 off-resonance (Hz), T1 (s), T2 (s), B1 scale (multiplies B1).
+ * Features: f_z, f_B0, ln T1, ln T2, B1 scale, each mapped affinely by
+ * (v - center) / scale.  Weights enter the matrix cores as BF16
+ * (v_mfma_f32_16x16x32_bf16) with FP32 accumulation and FP32 biases;
+ * activations are carried as BF16 hi + lo pairs.  The outputs are the
+ * transition in a frame without the free precession of each half of the
+ * pulse, K = P(-a) T P(-a) with P the z rotation of Eq. A2 and
+ * a = -2 pi (f_z + f_B0) n_steps dt / 2; T = P(a) K P(a) is returned.
+ * Training minimises the mean over samples and the 12 entries of
+ * (K_mlp - K_exact)^2 with Adam on the GPU.
+ *
+ * Parameter vector (GBS_MLP_PARAMS floats): W1[128][5] b1[128] W2[128][128]
+ * b2[128] W3[128][128] b3[128] W4[12][128] b4[12]; layer l computes
+ * z = W_l h + b_l.  Transitions are float/double[12] per tuple: A row-major
+ * (3x3), then b (M' = A M + b M0).
+ */
+#define GBS_MLP_PARAMS 35340
+
+typedef struct gbs_mlp gbs_mlp;
+
+typedef struct gbs_train_cfg {
+    int32_t epochs;
+    int32_t batch;        /* samples per Adam step, multiple of 256 */
+    float lr_max, lr_min; /* cosine schedule from lr_max to lr_min over all steps */
+    float beta1, beta2, eps;
+    uint64_t seed;        /* per-epoch sample order */
+} gbs_train_cfg;
+
+/* New network on `device`/`stream` with weights and biases drawn uniformly
+ * from +-1/sqrt(fan_in) (seeded); feature normalization defaults to the
+ * ranges f_z +-1400 Hz, f_B0 +-100 Hz, T1 0.25-2.5 s, T2 0.03-0.3 s, B1 scale
+ * 0.8-1.2.  Errors: GBS_E_INVALID, GBS_E_HIP, GBS_E_NOMEM. */
+int gbs_mlp_create(gbs_mlp **out, int device, void *stream, uint64_t seed);
+int gbs_mlp_destroy(gbs_mlp *m);
+const char *gbs_mlp_last_error(const gbs_mlp *m);
+
+/* The pulse this network models: host waveforms of n_steps raster steps of
+ * dt (B1 in T, gradients in T/m).  gx and gy must be zero and gz not all zero
+ * (a Gz-only with-RF subsequence, Sec. 2.4).  Copied. */
+int gbs_mlp_set_pulse(gbs_mlp *m, const float *rf_re, const float *rf_im, const float *gx,
+                      const float *gy, const float *gz, int64_t n_steps, double dt);
+
+/* Feature normalization, host float[5] each (scale != 0). */
+int gbs_mlp_set_norm(gbs_mlp *m, const float center[5], const float scale[5]);
+
+/* FP32 master parameters, host float[n], n = GBS_MLP_PARAMS.  set_params
+ * also clears the Adam state and step count. */
+int gbs_mlp_get_params(gbs_mlp *m, float *params, int64_t n);
+int gbs_mlp_set_params(gbs_mlp *m, const float *params, int64_t n);
+
+/* Exact transitions of the pulse (Eq. 7, Eq. A1, A2), FP64: device tuples
+ * float[n][5] -> device T double[n][12].  Synchronizes. */
+int gbs_mlp_exact(gbs_mlp *m, const float *tuples, int64_t n, double *T);
+
+/* Network transitions: device tuples float[n][5] -> device T float[n][12].
+ * Synchronizes. */
+int gbs_mlp_infer(gbs_mlp *m, const float *tuples, int64_t n, float *T);
+
+/* Loss and gradient of one batch without an update: n samples (multiple of
+ * 64, in order), device T_exact double[n][12]; device grad float[GBS_MLP_PARAMS]
+ * in the parameter order above, host *loss.  Synchronizes. */
+int gbs_mlp_loss_grad(gbs_mlp *m, const float *tuples, const double *T_exact, int64_t n,
+                      float *grad, float *loss);
+
+/* Train with Adam on n samples (n >= cfg->batch): epochs x floor(n / batch)
+ * steps, a new seeded sample order every epoch.  loss_hist (host, nullable)
+ * receives the batch loss of each step, up to hist_len entries.
+ * Synchronizes. */
+int gbs_mlp_train(gbs_mlp *m, const float *tuples, const double *T_exact, int64_t n,
+                  const gbs_train_cfg *cfg, float *loss_hist, int64_t hist_len);
+
+/* Attach a surrogate to a simulator context (NULL detaches).  Used by
+ * gbs_simulate(GBS_GROUPED, flags | GBS_SURROGATE) for every distinct
+ * with-RF, Gz-only subsequence whose waveform equals the network's pulse
+ * bit for bit: the network gives T for every z group, then the exact T is
+ * composed for n_check seeded groups (all if fewer); if any entry differs by
+ * more than tol, the exact T of every group is used instead.  The network
+ * object must outlive its use.  Errors: GBS_E_INVALID (tol <= 0, n_check < 1,
+ * device mismatch). */
+int gbs_set_surrogate(gbs_ctx *ctx, gbs_mlp *m, float tol, int32_t n_check, uint64_t seed);
 
 #ifdef __cplusplus
 }

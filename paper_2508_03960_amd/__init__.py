@@ -23,9 +23,14 @@ GBS_PLAIN, GBS_GROUPED = 0, 1
 GBS_ASYNC = 1
 GBS_PLAIN_FP32 = 2
 GBS_PROFILE = 4
+GBS_SURROGATE = 8
+GBS_MLP_PARAMS = 35340
 
 EXPORTED = ("gbs_create", "gbs_destroy", "gbs_set_phantom", "gbs_set_sequence", "gbs_build_groups",
-            "gbs_simulate", "gbs_get_info", "gbs_last_error", "gbs_strerror", "gbs_plan_summary")
+            "gbs_simulate", "gbs_get_info", "gbs_last_error", "gbs_strerror", "gbs_plan_summary",
+            "gbs_mlp_create", "gbs_mlp_destroy", "gbs_mlp_last_error", "gbs_mlp_set_pulse",
+            "gbs_mlp_set_norm", "gbs_mlp_get_params", "gbs_mlp_set_params", "gbs_mlp_exact",
+            "gbs_mlp_infer", "gbs_mlp_loss_grad", "gbs_mlp_train", "gbs_set_surrogate")
 
 
 class gbs_block(ctypes.Structure):
@@ -50,10 +55,18 @@ class gbs_stats(ctypes.Structure):
                 ("n_adc_grouped", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
                 ("n_distinct_rf", ctypes.c_int64), ("n_b1zero", ctypes.c_int64),
                 ("pass_bytes", ctypes.c_double), ("pass_kernel_ms", ctypes.c_double),
-                ("n_sweeps", ctypes.c_int64), ("pass_flops", ctypes.c_double)]
+                ("n_sweeps", ctypes.c_int64), ("pass_flops", ctypes.c_double),
+                ("n_surrogate", ctypes.c_int64), ("n_surrogate_fallback", ctypes.c_int64),
+                ("surrogate_residual", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class gbs_train_cfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr_max", ctypes.c_float),
+                ("lr_min", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("seed", ctypes.c_uint64)]
 
 
 def _load(path=LIB_PATH):
@@ -72,6 +85,18 @@ def _load(path=LIB_PATH):
         "gbs_last_error": ([P], ctypes.c_char_p),
         "gbs_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "gbs_plan_summary": ([P, I64, P, P, P, P, P, I64, P, I64, D, U32, P], ctypes.c_int),
+        "gbs_mlp_create": ([ctypes.POINTER(P), ctypes.c_int, P, ctypes.c_uint64], ctypes.c_int),
+        "gbs_mlp_destroy": ([P], ctypes.c_int),
+        "gbs_mlp_last_error": ([P], ctypes.c_char_p),
+        "gbs_mlp_set_pulse": ([P, P, P, P, P, P, I64, D], ctypes.c_int),
+        "gbs_mlp_set_norm": ([P, P, P], ctypes.c_int),
+        "gbs_mlp_get_params": ([P, P, I64], ctypes.c_int),
+        "gbs_mlp_set_params": ([P, P, I64], ctypes.c_int),
+        "gbs_mlp_exact": ([P, P, I64, P], ctypes.c_int),
+        "gbs_mlp_infer": ([P, P, I64, P], ctypes.c_int),
+        "gbs_mlp_loss_grad": ([P, P, P, I64, P, P], ctypes.c_int),
+        "gbs_mlp_train": ([P, P, P, I64, P, P, I64], ctypes.c_int),
+        "gbs_set_surrogate": ([P, P, ctypes.c_float, I32, ctypes.c_uint64], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -143,6 +168,7 @@ class Simulator:
         if rc != GBS_OK:
             raise GbsError(rc, "gbs_create failed")
         self._h = h
+        self._destroy = lib.gbs_destroy  # still reachable while the interpreter shuts down
         self._keep = ()
         self.K = 0
         self.n_samples = 0
@@ -153,7 +179,7 @@ class Simulator:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib.gbs_destroy(self._h)
+            self._destroy(self._h)
             self._h = None
 
     __del__ = close
@@ -208,3 +234,102 @@ class Simulator:
         return (m_out, sig, st.as_dict()) if stats else (m_out, sig)
 
     simulate = gbs_simulate
+
+
+class Mlp:
+    """A gbs_mlp network (learned RF-transition surrogate) on a HIP device."""
+
+    def __init__(self, device=0, seed=0, stream=None):
+        self.device = torch.device("cuda", device) if isinstance(device, int) else torch.device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        rc = lib.gbs_mlp_create(ctypes.byref(h), self.device.index or 0, ctypes.c_void_p(stream.cuda_stream),
+                                int(seed))
+        if rc != GBS_OK:
+            raise GbsError(rc, "gbs_mlp_create failed")
+        self._h = h
+        self._destroy = lib.gbs_mlp_destroy
+
+    def _check(self, rc):
+        if rc != GBS_OK:
+            raise GbsError(rc, lib.gbs_mlp_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def set_pulse(self, rf, gz, dt, gx=None, gy=None):
+        """rf: complex host array (T), gz: host array (T/m) of the same length."""
+        import numpy as np
+        rf = np.asarray(rf)
+        n = rf.size
+        w = [_host(a, np.float32) for a in (rf.real, rf.imag,
+                                            np.zeros(n) if gx is None else gx,
+                                            np.zeros(n) if gy is None else gy, gz)]
+        self._check(lib.gbs_mlp_set_pulse(self._h, *(a.ctypes.data for a in w), n, float(dt)))
+
+    def set_norm(self, center, scale):
+        import numpy as np
+        c, sc = _host(center, np.float32), _host(scale, np.float32)
+        self._check(lib.gbs_mlp_set_norm(self._h, c.ctypes.data, sc.ctypes.data))
+
+    def get_params(self):
+        import numpy as np
+        p = np.empty(GBS_MLP_PARAMS, np.float32)
+        self._check(lib.gbs_mlp_get_params(self._h, p.ctypes.data, p.size))
+        return p
+
+    def set_params(self, p):
+        import numpy as np
+        p = _host(p, np.float32)
+        self._check(lib.gbs_mlp_set_params(self._h, p.ctypes.data, p.size))
+
+    def _tuples(self, tuples):
+        return tuples.to(self.device, torch.float32).contiguous()
+
+    def exact(self, tuples):
+        """Exact FP64 transitions (n, 12) of the pulse for device/host tuples (n, 5)."""
+        t = self._tuples(tuples)
+        out = torch.empty(t.shape[0], 12, device=self.device, dtype=torch.float64)
+        self._check(lib.gbs_mlp_exact(self._h, _ptr(t), t.shape[0], _ptr(out)))
+        return out
+
+    def infer(self, tuples):
+        t = self._tuples(tuples)
+        out = torch.empty(t.shape[0], 12, device=self.device, dtype=torch.float32)
+        self._check(lib.gbs_mlp_infer(self._h, _ptr(t), t.shape[0], _ptr(out)))
+        return out
+
+    def loss_grad(self, tuples, T_exact):
+        t = self._tuples(tuples)
+        T = T_exact.to(self.device, torch.float64).contiguous()
+        g = torch.empty(GBS_MLP_PARAMS, device=self.device, dtype=torch.float32)
+        loss = ctypes.c_float()
+        self._check(lib.gbs_mlp_loss_grad(self._h, _ptr(t), _ptr(T), t.shape[0], _ptr(g), ctypes.byref(loss)))
+        return float(loss.value), g
+
+    def train(self, tuples, T_exact, epochs=10, batch=4096, lr_max=2e-3, lr_min=1e-5, beta1=0.9,
+              beta2=0.999, eps=1e-8, seed=0):
+        """Adam on the GPU; returns the per-step batch losses (numpy)."""
+        import numpy as np
+        t = self._tuples(tuples)
+        T = T_exact.to(self.device, torch.float64).contiguous()
+        cfg = gbs_train_cfg(int(epochs), int(batch), float(lr_max), float(lr_min), float(beta1), float(beta2),
+                            float(eps), int(seed))
+        steps = int(epochs) * (t.shape[0] // int(batch))
+        hist = np.zeros(max(steps, 1), np.float32)
+        self._check(lib.gbs_mlp_train(self._h, _ptr(t), _ptr(T), t.shape[0], ctypes.byref(cfg),
+                                      hist.ctypes.data, hist.size))
+        return hist[:steps]
+
+
+def set_surrogate(sim, mlp, tol=1e-3, n_check=32, seed=0):
+    """Attach (or with mlp=None detach) a trained surrogate to a Simulator."""
+    sim._mlp = mlp  # keep the network alive while attached
+    sim._check(lib.gbs_set_surrogate(sim._h, None if mlp is None else mlp._h, float(tol), int(n_check),
+                                     int(seed)))

@@ -18,6 +18,8 @@
 #include "gbloch.h"
 #include "groups.hpp"
 #include "kernels.hpp"
+#include "mlp.hpp"
+#include "mlp_api.hpp"
 #include "plan.hpp"
 
 using namespace gbs;
@@ -70,6 +72,12 @@ struct GroupedPlan {
     std::vector<Seg> segs;
     std::vector<std::pair<int, int>> exec;  // (0, segment) or (1, index into plan.ops)
     int64_t n_ops = 0;
+    // learned surrogate for one distinct RF transition (surr_rf >= 0)
+    bool surr_on = false;
+    int surr_rf = -1;
+    int64_t surr_groups = 0;
+    int surr_n_check = 0;
+    size_t s_tuples = 0, s_T32 = 0, s_idx = 0, s_exact = 0, s_res = 0, s_fb = 0;
 };
 
 }  // namespace
@@ -101,6 +109,12 @@ struct gbs_ctx {
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     std::vector<hipEvent_t> pev;  // GBS_PROFILE: one (start, stop) pair per pass launch
     GroupedPlan gp;
+    // learned surrogate (not owned)
+    gbs_mlp *mlp = nullptr;
+    float surr_tol = 1e-3f;
+    int32_t surr_check = 32;
+    uint64_t surr_seed = 0;
+    DevBuf surr;
     bool pplan_valid = false;
     Plan pplan;  // plain schedule
 };
@@ -169,7 +183,7 @@ int gbs_destroy(gbs_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     DevBuf *bufs[] = {&ctx->d_wave, &ctx->d_adc, &ctx->perm, &ctx->inv, &ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i,
                       &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->tabs, &ctx->gsum, &ctx->partial, &ctx->jobs,
-                      &ctx->samp, &ctx->flag};
+                      &ctx->samp, &ctx->flag, &ctx->surr};
     for (DevBuf *b : bufs) b->release();
     for (int a = 0; a < 3; ++a) {
         ctx->gid[a].release();
@@ -448,13 +462,34 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Build the cached grouped plan: schedule, arena layout, sample tables and
 // job arrays (device).  Host work only once per (sequence, groups).
-static int build_grouped_plan(gbs_ctx *ctx) {
+// Does distinct RF transition r have exactly the surrogate's pulse?
+static bool matches_pulse(const gbs_ctx *ctx, const RfJob &r) {
+    const gbs_mlp *m = ctx->mlp;
+    const HostSeq &s = ctx->seq;
+    if (!m || !m->has_pulse || r.axis != 2 || r.n_steps != m->n_steps || s.dt != m->dt) return false;
+    const size_t o = (size_t)r.step_offset, n = (size_t)r.n_steps;
+    for (size_t i = 0; i < n; ++i)
+        if (s.gx[o + i] != 0.f || s.gy[o + i] != 0.f) return false;
+    return std::memcmp(&s.rf_re[o], m->rf_re.data(), n * sizeof(float)) == 0 &&
+           std::memcmp(&s.rf_im[o], m->rf_im.data(), n * sizeof(float)) == 0 &&
+           std::memcmp(&s.gz[o], m->gz.data(), n * sizeof(float)) == 0;
+}
+
+static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
     GroupedPlan &g = ctx->gp;
     const HostSeq &s = ctx->seq;
     g = GroupedPlan{};
     g.plan = plan_grouped(s, ctx->cls, ctx->axes);
     const Plan &plan = g.plan;
     g.zbuilt = (ctx->axes & GBS_AX_Z) != 0;
+    g.surr_on = want_surr;
+    if (want_surr && ctx->mlp && ctx->mlp->device == ctx->device) {
+        for (size_t i = 0; i < plan.rf.size(); ++i)
+            if (matches_pulse(ctx, plan.rf[i])) {
+                g.surr_rf = (int)i;
+                break;
+            }
+    }
     const int64_t Gx = ctx->ng[0], Gz = g.zbuilt ? ctx->ng[2] : 0;
 
     // ---- arena: FP64 combined transitions, folded transitions, map tables
@@ -568,8 +603,39 @@ static int build_grouped_plan(gbs_ctx *ctx) {
     std::vector<RfJobDev> rj(plan.rf.size());
     for (size_t i = 0; i < plan.rf.size(); ++i) {
         const RfJob &r = plan.rf[i];
-        rj[i] = RfJobDev{r.axis, (int32_t)r.n_steps, ctx->ng[r.axis], ctx->d_wave.as<StepW>() + r.step_offset,
+        // the surrogate's transition is not composed here (n_groups = 0 skips it)
+        const int64_t ng = (int)i == g.surr_rf ? 0 : ctx->ng[r.axis];
+        rj[i] = RfJobDev{r.axis, (int32_t)r.n_steps, ng, ctx->d_wave.as<StepW>() + r.step_offset,
                          ctx->gtab[r.axis].as<float4>(), (double *)(tb + g.rf_off[i])};
+    }
+    if (g.surr_rf >= 0) {
+        // tuples, network output, spot-check indices (seeded, distinct) and exact values
+        const int64_t G = ctx->ng[2];
+        g.surr_groups = G;
+        g.surr_n_check = (int)std::min<int64_t>(ctx->surr_check, G);
+        size_t so = 0;
+        auto take = [&](size_t bytes) {
+            const size_t o = so;
+            so = align256(so + bytes);
+            return o;
+        };
+        g.s_tuples = take(sizeof(float) * 5 * (size_t)G);
+        g.s_T32 = take(sizeof(float) * 12 * (size_t)G);
+        g.s_idx = take(sizeof(int32_t) * (size_t)g.surr_n_check);
+        g.s_exact = take(sizeof(double) * 12 * (size_t)g.surr_n_check);
+        g.s_res = take(sizeof(float));
+        g.s_fb = take(sizeof(int32_t));
+        std::vector<int32_t> all((size_t)G);
+        for (int64_t i = 0; i < G; ++i) all[i] = (int32_t)i;
+        uint64_t rs = ctx->surr_seed ^ 0x5DEECE66Dull;
+        for (int k = 0; k < g.surr_n_check; ++k) {  // partial Fisher-Yates
+            rs = rs * 6364136223846793005ull + 1442695040888963407ull;
+            const int64_t j = k + (int64_t)((rs >> 33) % (uint64_t)(G - k));
+            std::swap(all[k], all[j]);
+        }
+        ALLOC(ctx->surr, so);
+        HIPCHK(hipMemcpy((char *)ctx->surr.p + g.s_idx, all.data(), sizeof(int32_t) * g.surr_n_check,
+                         hipMemcpyHostToDevice));
     }
     std::vector<FoldJob> fj(folds.size());
     for (size_t i = 0; i < folds.size(); ++i) {
@@ -726,11 +792,11 @@ static int build_grouped_plan(gbs_ctx *ctx) {
 }
 
 static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *sig_out, bool profile,
-                       gbs_stats *st, int *n_timed) {
+                       bool use_surr, gbs_stats *st, int *n_timed) {
     const int64_t K = ctx->K;
     const HostSeq &s = ctx->seq;
-    if (!ctx->gp.valid) {
-        int rc = build_grouped_plan(ctx);
+    if (!ctx->gp.valid || ctx->gp.surr_on != use_surr) {
+        int rc = build_grouped_plan(ctx, use_surr);
         if (rc != GBS_OK) return rc;
     }
     const GroupedPlan &g = ctx->gp;
@@ -742,6 +808,24 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
 
     // ---- prepare: combined transitions (Eq. 7) and map tables --------------
     HIPCHK(launch_fill_f64((double *)ctx->gsum.p, 2 * (int64_t)g.gsum_count, ctx->stream));
+    if (g.surr_rf >= 0) {
+        // network transitions for every z group, exact ones for the checked groups,
+        // then exact for all groups only if the check failed (gated on the device)
+        char *sb = ctx->surr.as<char>();
+        const gbs_mlp *m = ctx->mlp;
+        float *tuples = (float *)(sb + g.s_tuples), *T32 = (float *)(sb + g.s_T32);
+        const int32_t *cidx = (const int32_t *)(sb + g.s_idx);
+        int32_t *fb = (int32_t *)(sb + g.s_fb);
+        double *T64 = (double *)(tb + g.rf_off[g.surr_rf]);
+        HIPCHK(launch_surr_tuples(ctx->gtab[2].as<float4>(), g.surr_groups, kGammaBar * m->g_ref, tuples,
+                                  ctx->stream));
+        HIPCHK(mlp_infer_async(m, tuples, nullptr, g.surr_groups, T32, ctx->stream));
+        HIPCHK(launch_surr_store(T32, g.surr_groups, T64, ctx->stream));
+        HIPCHK(mlp_exact_async(m, tuples, cidx, g.surr_n_check, nullptr, (double *)(sb + g.s_exact), ctx->stream));
+        HIPCHK(launch_surr_check(T32, cidx, (const double *)(sb + g.s_exact), g.surr_n_check, ctx->surr_tol,
+                                 (float *)(sb + g.s_res), fb, ctx->stream));
+        HIPCHK(mlp_exact_async(m, tuples, nullptr, g.surr_groups, fb, T64, ctx->stream));
+    }
     HIPCHK(launch_compose((const RfJobDev *)(jb + g.o_rf), g.n_rf, g.max_rf_groups, s.dt, ctx->stream));
     HIPCHK(launch_fold((const FoldJob *)(jb + g.o_fold), g.n_fold, g.max_fold_groups, ctx->stream));
     HIPCHK(launch_tables((const TabJob *)(jb + g.o_tab), g.n_tab, (int)g.max_tab, ctx->gtab[0].as<float4>(),
@@ -835,7 +919,11 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
     if (!m_out || (ctx->seq.total_samples > 0 && !sig_out)) return fail(ctx, GBS_E_INVALID, "null output");
     if (mode == GBS_GROUPED && !ctx->groups_valid)
         return fail(ctx, GBS_E_STATE, "GBS_GROUPED needs gbs_build_groups on the current phantom");
-    if (flags & ~(GBS_ASYNC | GBS_PLAIN_FP32 | GBS_PROFILE)) return fail(ctx, GBS_E_INVALID, "unknown flags");
+    if (flags & ~(GBS_ASYNC | GBS_PLAIN_FP32 | GBS_PROFILE | GBS_SURROGATE))
+        return fail(ctx, GBS_E_INVALID, "unknown flags");
+    const bool use_surr = (flags & GBS_SURROGATE) != 0;
+    if (use_surr && (mode != GBS_GROUPED || !ctx->mlp))
+        return fail(ctx, GBS_E_INVALID, "GBS_SURROGATE needs GBS_GROUPED and gbs_set_surrogate");
     HIPCHK(hipSetDevice(ctx->device));
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
@@ -846,7 +934,7 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
     const bool profile = (flags & GBS_PROFILE) != 0;
     int n_timed = 0;
     int rc = mode == GBS_PLAIN ? run_plain(ctx, m_init, m_out, sig_out, (flags & GBS_PLAIN_FP32) != 0, stats)
-                               : run_grouped(ctx, m_init, m_out, sig_out, profile, stats, &n_timed);
+                               : run_grouped(ctx, m_init, m_out, sig_out, profile, use_surr, stats, &n_timed);
     if (rc != GBS_OK) return rc;
     if (stats) HIPCHK(hipEventRecord(ctx->ev[4], ctx->stream));
     if (!(flags & GBS_ASYNC) || stats || profile) {
@@ -872,7 +960,33 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
                 sum += ms;
             }
             stats->pass_kernel_ms = sum;
+            const GroupedPlan &g = ctx->gp;
+            if (g.surr_rf >= 0) {
+                float res = 0.f;
+                int32_t fb = 0;
+                HIPCHK(hipMemcpy(&res, ctx->surr.as<char>() + g.s_res, sizeof(float), hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(&fb, ctx->surr.as<char>() + g.s_fb, sizeof(int32_t), hipMemcpyDeviceToHost));
+                stats->n_surrogate = 1;
+                stats->n_surrogate_fallback = fb ? 1 : 0;
+                stats->surrogate_residual = res;
+            }
         }
     }
+    return GBS_OK;
+}
+
+extern "C" int gbs_set_surrogate(gbs_ctx *ctx, gbs_mlp *m, float tol, int32_t n_check, uint64_t seed) {
+    if (!ctx) return GBS_E_INVALID;
+    if (m) {
+        if (!(tol > 0.f) || !std::isfinite(tol)) return fail(ctx, GBS_E_INVALID, "tol must be positive");
+        if (n_check < 1) return fail(ctx, GBS_E_INVALID, "n_check must be >= 1");
+        if (m->device != ctx->device) return fail(ctx, GBS_E_INVALID, "network lives on another device");
+        if (!m->has_pulse) return fail(ctx, GBS_E_STATE, "network has no pulse (gbs_mlp_set_pulse)");
+    }
+    ctx->mlp = m;
+    ctx->surr_tol = tol;
+    ctx->surr_check = n_check;
+    ctx->surr_seed = seed;
+    ctx->gp.valid = false;
     return GBS_OK;
 }

@@ -1,0 +1,116 @@
+// Learned RF-transition surrogate: a 5-128-128-128-12 SiLU network that maps
+// (slice-gradient off-resonance, dB0 off-resonance, T1, T2, B1 scale) to the
+// 3x4 affine transition of one RF subsequence (Eq. 7).  Device-side layouts
+// shared by k_mlp.hip and api_mlp.cpp.
+//
+// Parameters (FP32 master copy, flat): W1[128][5] b1[128] W2[128][128] b2[128]
+// W3[128][128] b3[128] W4[12][128] b4[12].  Weights enter the matrix cores as
+// BF16 (v_mfma_f32_16x16x32_bf16, FP32 accumulation); biases stay FP32.
+// Activations are carried as a BF16 pair (hi + lo) so that only the weights
+// are rounded to BF16.
+//
+// The network predicts K = P(-a) T P(-a), the transition with the free
+// precession of each half of the pulse removed; P(a) is the z rotation of
+// Eq. A2 and a = -2 pi (f_z + f_B0) tau/2.  T is recovered exactly as
+// P(a) K P(a) (b column: P(a) k_b).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace gbs {
+
+constexpr int kMlpIn = 5, kMlpH = 128, kMlpOut = 12;
+constexpr int kOffW1 = 0, kOffB1 = 640, kOffW2 = 768, kOffB2 = 17152, kOffW3 = 17280,
+              kOffB3 = 33664, kOffW4 = 33792, kOffB4 = 35328, kMlpParams = 35340;
+
+// Packed MFMA A-operand fragments: 64 lanes x 8 BF16 (1 KiB) each.
+// Forward (rows = output neuron, k = input neuron): L1 8 tiles x 1 chunk,
+// L2 and L3 8 x 4, L4 1 x 4.  Backward (W^T: rows = input neuron, k = output
+// neuron): L2 and L3 8 x 4, L4 8 x 1.
+constexpr int kFragFwdL1 = 0, kFragFwdL2 = 8, kFragFwdL3 = 40, kFragFwdL4 = 72, kFragFwd = 76;
+constexpr int kFragBwdL2 = 0, kFragBwdL3 = 32, kFragBwdL4 = 64, kFragBwd = 72;
+
+// Weight-gradient tiles (16 x 16, contraction over the batch): L1 8 x 2,
+// L2 and L3 8 x 9, L4 1 x 9; the last input tile of each layer is the bias.
+constexpr int kGradTiles = 169;
+
+// Training activations, one row per neuron, B samples per row.
+constexpr int kActRows = 400;  // H0 (16: 5 inputs + zeros), H1, H2, H3
+constexpr int kDzRows = 400;   // dZ1, dZ2, dZ3, dZ4 (16: 12 outputs + zeros)
+constexpr int kSpRows = 384;   // SiLU'(Z1..Z3)
+
+struct MlpNorm {
+    float center[5];     // features: f_z [Hz], f_B0 [Hz], ln T1, ln T2, B1 scale
+    float inv_scale[5];  // u_k = (feature_k - center_k) * inv_scale_k
+    double half;         // tau/2 of the modelled pulse [s]
+};
+
+struct MlpTrainArgs {
+    const float *tuples;   // [N][5]: f_z, f_B0, T1, T2, B1 scale
+    const float *targets;  // [N][12]: K (precession-removed transition)
+    int64_t N;
+    uint64_t pa, pc;  // sample j of the epoch is (pa * j + pc) mod N
+    int64_t j0;       // first sample of this batch within the epoch
+    int32_t B;        // batch size (multiple of 64)
+    const uint4 *wf, *wb;
+    const float *params;
+    MlpNorm norm;
+    uint16_t *act_h, *act_l, *dz_h, *dz_l;
+    float *sp;
+    float *loss;  // += mean squared error of this batch
+};
+
+struct MlpGradArgs {
+    const uint16_t *act_h, *act_l, *dz_h, *dz_l;
+    int32_t B;
+    int32_t slice;  // samples per split-K slice (multiple of 32)
+    float *part;    // [B / slice][kGradTiles][16][16]
+};
+
+struct MlpAdamArgs {
+    const float *part;
+    int32_t n_slices;
+    float *w, *m, *v;
+    uint16_t *wf, *wb;
+    float lr, beta1, beta2, eps, corr1, corr2;  // corr = 1 / (1 - beta^t)
+    float *grad_out;  // if set: write the gradient and do not update
+};
+
+struct MlpInferArgs {
+    const float *tuples;
+    const int32_t *idx;  // optional gather
+    int64_t N;
+    const uint4 *wf;
+    const float *params;
+    MlpNorm norm;
+    float *out;  // [N][12] transition T (A row-major, b)
+};
+
+struct MlpExactArgs {
+    const float *tuples;
+    const int32_t *idx;  // optional gather
+    int64_t N;
+    const float4 *wave;  // per step: B1 re, B1 im [T], Gz [T/m], 0
+    int32_t n_steps;
+    double dt;
+    double g_ref;       // f_z = gamma_bar * g_ref * z
+    const int32_t *gate;  // optional: run only if *gate != 0
+    double *out;        // [N][12]
+};
+
+hipError_t launch_mlp_train_fb(const MlpTrainArgs &a, hipStream_t st);
+hipError_t launch_mlp_wgrad(const MlpGradArgs &a, hipStream_t st);
+hipError_t launch_mlp_adam(const MlpAdamArgs &a, hipStream_t st);
+hipError_t launch_mlp_pack(const float *w, uint16_t *wf, uint16_t *wb, hipStream_t st);
+hipError_t launch_mlp_infer(const MlpInferArgs &a, hipStream_t st);
+hipError_t launch_mlp_exact(const MlpExactArgs &a, hipStream_t st);
+hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
+hipError_t launch_mlp_targets(const float *tuples, const double *T, int64_t N, double half,
+                              float *K, hipStream_t st);
+hipError_t launch_surr_tuples(const float4 *gtab, int64_t n, double fz_per_m, float *tuples,
+                              hipStream_t st);
+hipError_t launch_surr_store(const float *T32, int64_t n, double *T64, hipStream_t st);
+hipError_t launch_surr_check(const float *T32, const int32_t *idx, const double *exact, int n_check,
+                             float tol, float *residual, int32_t *fallback, hipStream_t st);
+
+}  // namespace gbs

@@ -390,6 +390,47 @@ def epi_sequence(n_lines=128, n_read=128, dwell_steps=4, fov=(0.256, 0.256), thk
     return sb.build(kind="epi", n_lines=n_lines, n_read=n_read, fov=fov)
 
 
+# ---- learned RF-transition surrogate: the modelled pulse and its inputs ----
+def fse_refocusing_pulse(rf_steps=3000, dt=1e-6, thk=0.010, tbw=4.0):
+    """The FSE 180-degree refocusing pulse (about y) with its slice gradient:
+    (complex B1 per step [T], Gz per step [T/m], dt)."""
+    b180 = sinc_pulse(rf_steps, dt, np.pi, tbw, phase=np.pi / 2)
+    gz = np.full(rf_steps, slice_gradient(rf_steps, dt, thk, tbw))
+    return b180, gz, dt
+
+
+SURROGATE_RANGES = {  # training domain of the surrogate inputs
+    "f_z": (-1400.0, 1400.0),   # Hz, gamma_bar * Gz * z (slice +-10 mm covers +-1333 Hz)
+    "f_b0": (-100.0, 100.0),    # Hz
+    "t1": (0.25, 2.5),          # s, log-uniform
+    "t2": (0.03, 0.3),          # s, log-uniform
+    "b1": (0.8, 1.2),           # B1 scale
+}
+
+
+def surrogate_tuples(n, seed=2024):
+    """Seeded random surrogate inputs, float32 (n, 5): f_z, f_B0, T1, T2, B1 scale."""
+    r = SURROGATE_RANGES
+    rng = np.random.default_rng(seed)
+    out = np.empty((n, 5), np.float32)
+    out[:, 0] = rng.uniform(*r["f_z"], n)
+    out[:, 1] = rng.uniform(*r["f_b0"], n)
+    out[:, 2] = np.exp(rng.uniform(np.log(r["t1"][0]), np.log(r["t1"][1]), n))
+    out[:, 3] = np.exp(rng.uniform(np.log(r["t2"][0]), np.log(r["t2"][1]), n))
+    out[:, 4] = rng.uniform(*r["b1"], n)
+    return out
+
+
+def mlp_init_params(seed=0):
+    """Seeded parameters of the 5-128-128-128-12 network in the flat order
+    W1 b1 W2 b2 W3 b3 W4 b4, each drawn from U(-1/sqrt(fan_in), 1/sqrt(fan_in))."""
+    rng = np.random.default_rng(seed)
+    shapes = [((128, 5), 5), ((128,), 5), ((128, 128), 128), ((128,), 128),
+              ((128, 128), 128), ((128,), 128), ((12, 128), 128), ((12,), 128)]
+    parts = [rng.uniform(-1, 1, int(np.prod(s))) / np.sqrt(f) for s, f in shapes]
+    return np.concatenate(parts).astype(np.float32)
+
+
 # Workload registry: the sizes used by the benchmark and the parity tests.
 def workload(name: str):
     """Return (phantom, sequence) for a named workload."""

@@ -1,0 +1,212 @@
+"""GPU parity of the learned RF-transition surrogate against its FP64 oracle
+(oracle/surrogate.py), through the C ABI.
+
+Bars:
+* exact transitions (FP64 on both sides, different summation order over
+  3000 steps): max |dT| <= 1e-9;
+* network outputs: the GPU rounds weights to BF16 exactly as the oracle does;
+  activations travel as BF16 hi + lo pairs (relative error <= 2^-17 each)
+  with FP32 accumulation, so outputs of size O(1) agree to ~1e-5; bar 1e-4;
+* loss and gradient: relative 1e-4 (loss) and 1e-3 (gradient, L2), from the
+  same per-operand error carried through the backward pass and the FP32
+  sums over the batch;
+* inside a simulation the usual parity bar (|dM| <= 1e-5, relative signal
+  <= 1e-4) holds whenever the spot check falls back to the exact transition.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import surrogate as so
+
+pytestmark = pytest.mark.gpu
+
+DM_TOL = 1e-5
+SIG_TOL = 1e-4
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2508_03960_amd as gb
+    pulse = synth.fse_refocusing_pulse()
+    return gb, torch, pulse
+
+
+def make_mlp(gb, pulse, seed=3):
+    m = gb.Mlp(0)
+    rf, gz, dt = pulse
+    m.set_pulse(rf, gz, dt)
+    m.set_params(synth.mlp_init_params(seed=seed))
+    return m
+
+
+def test_exact_transitions_vs_oracle(env):
+    gb, torch, pulse = env
+    m = make_mlp(gb, pulse)
+    tup = synth.surrogate_tuples(13, seed=31)
+    tup[0] = [0.0, 0.0, 1.0, 0.1, 1.0]
+    say("[gpu] surrogate: exact transitions, 13 tuples")
+    T = m.exact(torch.from_numpy(tup)).cpu().numpy()
+    Tr = so.transition(pulse, tup)
+    err = float(np.max(np.abs(T - Tr)))
+    say(f"[gpu] surrogate: exact max|dT| = {err:.3e}")
+    assert err <= 1e-9
+    m.close()
+
+
+def test_infer_vs_oracle_forward(env):
+    gb, torch, pulse = env
+    m = make_mlp(gb, pulse)
+    tup = synth.surrogate_tuples(2021, seed=32)  # not a multiple of the 32-sample tile
+    say("[gpu] surrogate: inference, 2021 tuples")
+    T = m.infer(torch.from_numpy(tup)).cpu().numpy().astype(np.float64)
+    Tr = so.mlp_transition(synth.mlp_init_params(seed=3), tup, pulse[2] * len(pulse[0]) / 2)
+    err = float(np.max(np.abs(T - Tr)))
+    say(f"[gpu] surrogate: inference max|dT| = {err:.3e} (outputs up to {np.max(np.abs(Tr)):.2f})")
+    assert err <= 1e-4
+    m.close()
+
+
+def _targets(n, seed):
+    tup = synth.surrogate_tuples(n, seed=seed)
+    return tup, so.transition(synth.fse_refocusing_pulse(), tup)
+
+
+@pytest.fixture(scope="module")
+def batch512():
+    return _targets(512, 33)
+
+
+def test_loss_grad_vs_oracle(env, batch512):
+    gb, torch, pulse = env
+    m = make_mlp(gb, pulse)
+    tup, T = batch512
+    say("[gpu] surrogate: loss and gradient, 512 samples")
+    loss, g = m.loss_grad(torch.from_numpy(tup), torch.from_numpy(T))
+    g = g.cpu().numpy().astype(np.float64)
+    half = pulse[2] * len(pulse[0]) / 2
+    lr_, gr = so.loss_grad(synth.mlp_init_params(seed=3), so.features(tup), so.frame(T, tup, half))
+    rel_l = abs(loss - lr_) / lr_
+    rel_g = float(np.linalg.norm(g - gr) / np.linalg.norm(gr))
+    say(f"[gpu] surrogate: loss {loss:.6e} vs {lr_:.6e} (rel {rel_l:.2e}); grad rel L2 {rel_g:.2e}")
+    assert rel_l <= 1e-4
+    assert rel_g <= 1e-3
+    assert float(np.max(np.abs(g - gr))) <= 1e-3 * float(np.max(np.abs(gr)))
+    m.close()
+
+
+def test_adam_step_and_repack_vs_oracle(env, batch512):
+    gb, torch, pulse = env
+    m = make_mlp(gb, pulse)
+    tup, T = batch512
+    tup, T = tup[:256], T[:256]
+    p0 = synth.mlp_init_params(seed=3).astype(np.float64)
+    half = pulse[2] * len(pulse[0]) / 2
+    _, gr = so.loss_grad(p0, so.features(tup), so.frame(T, tup, half))
+    say("[gpu] surrogate: one Adam step, batch 256")
+    m.train(torch.from_numpy(tup), torch.from_numpy(T), epochs=1, batch=256, lr_max=1e-3, lr_min=0.0)
+    p1 = m.get_params().astype(np.float64)
+    want, _, _ = so.adam(p0, np.zeros_like(p0), np.zeros_like(p0), gr, 1, 1e-3)
+    sel = np.abs(gr) > 1e-3 * np.max(np.abs(gr))  # first Adam step is lr*sign(g): compare where g is clear
+    err = float(np.max(np.abs(p1 - want)[sel]))
+    say(f"[gpu] surrogate: Adam step max|dw| = {err:.3e} over {int(sel.sum())} parameters")
+    assert err <= 1e-6
+    assert float(np.max(np.abs(p1 - p0))) <= 1e-3 * (1 + 1e-5)
+    # the BF16 fragments were repacked from the updated master weights
+    probe = synth.surrogate_tuples(100, seed=34)
+    Tm = m.infer(torch.from_numpy(probe)).cpu().numpy().astype(np.float64)
+    err2 = float(np.max(np.abs(Tm - so.mlp_transition(p1, probe, half))))
+    say(f"[gpu] surrogate: inference after the step max|dT| = {err2:.3e}")
+    assert err2 <= 1e-4
+    m.close()
+
+
+def test_training_reduces_loss(env):
+    gb, torch, pulse = env
+    m = make_mlp(gb, pulse)
+    n = 65536
+    tup = torch.from_numpy(synth.surrogate_tuples(n, seed=35)).cuda()
+    say("[gpu] surrogate: exact targets for 65536 tuples, then 6 epochs of batch 1024")
+    T = m.exact(tup)
+    hist = m.train(tup, T, epochs=6, batch=1024, lr_max=2e-3, lr_min=1e-4, seed=1)
+    say(f"[gpu] surrogate: loss {hist[0]:.3e} -> {hist[-1]:.3e} over {hist.size} steps")
+    assert np.all(np.isfinite(hist))
+    assert hist[-1] < hist[0] / 10
+    m.close()
+
+
+def _fse_small_run(gb, torch, m, tol, flags_extra):
+    ph, seq = synth.workload("fse-small")
+    sim = gb.Simulator(0)
+    sim.set_phantom(ph)
+    sim.set_sequence(seq)
+    sim.build_groups()
+    gb.set_surrogate(sim, m, tol=tol, n_check=16, seed=5)
+    M, sig, st = sim.simulate(gb.GBS_GROUPED, flags=flags_extra, stats=True)
+    torch.cuda.synchronize()
+    out = M.cpu().numpy().astype(np.float64), sig.cpu().numpy().copy(), st
+    sim.close()
+    return out
+
+
+def test_surrogate_in_grouped_fse_falls_back(env):
+    gb, torch, pulse = env
+    m = make_mlp(gb, pulse)  # untrained: its transitions are far from exact
+    ph, seq = synth.workload("fse-small")
+    Mr, sr = oracle.simulate(ph, seq)
+    say("[gpu] surrogate: FSE-small grouped with an untrained network, tol 1e-3")
+    M, sig, st = _fse_small_run(gb, torch, m, 1e-3, gb.GBS_SURROGATE)
+    dm = float(np.max(np.abs(M - Mr)))
+    rel = float(np.linalg.norm(sig - sr) / np.linalg.norm(sr))
+    say(f"[gpu] surrogate: stats n={st['n_surrogate']} fallback={st['n_surrogate_fallback']} "
+        f"residual={st['surrogate_residual']:.3e}; max|dM|={dm:.3e} rel_sig={rel:.3e}")
+    assert st["n_surrogate"] == 1 and st["n_surrogate_fallback"] == 1
+    assert st["surrogate_residual"] > 1e-3
+    assert dm <= DM_TOL and rel <= SIG_TOL
+    say("[gpu] surrogate: same with tol 1e9 (network accepted)")
+    M2, sig2, st2 = _fse_small_run(gb, torch, m, 1e9, gb.GBS_SURROGATE)
+    assert st2["n_surrogate_fallback"] == 0
+    assert float(np.linalg.norm(sig2 - sr) / np.linalg.norm(sr)) > 1e-3  # the network's T was used
+    m.close()
+
+
+def test_trained_surrogate_gain(env):
+    """What the network buys: one transition costs an MLP evaluation instead of
+    a 3000-step FP64 composition.  Trained on 2M transitions of the 180-degree
+    pulse; reports speed and accuracy per transition on 1M held-out tuples."""
+    gb, torch, pulse = env
+    m = make_mlp(gb, pulse, seed=7)
+    tup = torch.from_numpy(synth.surrogate_tuples(1 << 21, seed=36)).cuda()
+    say("[gpu] surrogate gain: exact targets for 2,097,152 tuples, train 32 epochs of batch 1024")
+    T = m.exact(tup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = m.train(tup, T, epochs=32, batch=1024, lr_max=3e-3, lr_min=1e-6, seed=2)
+    t_train = time.perf_counter() - t0
+    test = torch.from_numpy(synth.surrogate_tuples(1 << 20, seed=37)).cuda()
+    for _ in range(2):  # second pass timed warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Tm = m.infer(test)
+        t_inf = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Te = m.exact(test)
+        t_ex = time.perf_counter() - t0
+    err = (Tm.double() - Te).abs().max(dim=1).values.cpu().numpy()
+    say(f"[gpu] surrogate gain: {hist.size} Adam steps in {t_train:.2f} s, final loss {hist[-1]:.3e}; "
+        f"1,048,576 transitions: network {t_inf * 1e3:.2f} ms, exact {t_ex * 1e3:.2f} ms (x{t_ex / t_inf:.1f}); "
+        f"max|dT| {err.max():.3e}, p99 {np.quantile(err, 0.99):.3e}, median {np.median(err):.3e}, "
+        f"within 1e-3: {np.mean(err <= 1e-3) * 100:.1f} %")
+    assert t_inf * 5 < t_ex
+    assert np.median(err) < 2e-3 and np.quantile(err, 0.99) < 5e-3
+    m.close()
