@@ -22,6 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "bloch_oracle.c")
+ADJ_PATH = os.path.join(_HERE, "bloch_adjoint.c")
 
 _lib = None
 
@@ -31,7 +32,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-               SRC_PATH, "-o", tmp, "-lm"]
+               SRC_PATH, ADJ_PATH, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -47,13 +48,20 @@ def bind(path: str):
         [ctypes.c_int64] + [P] * 8 + [ctypes.c_int64] + [P] * 7 + [ctypes.c_int64] + [P] * 5
         + [ctypes.c_int64, P, ctypes.c_double, ctypes.c_int, P, P])
     lib.oracle_max_threads.restype = ctypes.c_int
+    if hasattr(lib, "oracle_adjoint"):
+        lib.oracle_adjoint.restype = ctypes.c_int
+        lib.oracle_adjoint.argtypes = (
+            [ctypes.c_int64] + [P] * 6 + [ctypes.c_int32, P, P, ctypes.c_int64] + [P] * 7
+            + [ctypes.c_int64] + [P] * 5 + [ctypes.c_int64, P, ctypes.c_double, ctypes.c_int64, P,
+                                             ctypes.c_int32, P, P, ctypes.c_int, P, P, P, P])
     return lib
 
 
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(
+                os.path.getmtime(SRC_PATH), os.path.getmtime(ADJ_PATH)):
             build()
         _lib = bind(LIB_PATH)
     return _lib
@@ -97,3 +105,43 @@ def simulate(ph, seq, m_init=None, nthreads: int = 0, lib=None):
     if rc != 0:
         raise ValueError(f"oracle_simulate rejected its inputs (code {rc})")
     return m_out, sig[0::2] + 1j * sig[1::2]
+
+
+def adjoint(ph, cls, t1c, t2c, seq, rf_param, param_blocks, w, nthreads: int = 0, lib=None):
+    """FP64 signal and gradient of L = sum_n (w_re Re A_n + w_im Im A_n)
+    (``bloch_adjoint.c``).
+
+    ph: phantom (its t1/t2 are ignored: isochromat k has T1 = t1c[cls[k]],
+    T2 = t2c[cls[k]]); rf_param: complex (n_rf,), the B1 of every block in
+    ``param_blocks``; w: complex (total_samples,).  Returns
+    (sig complex, g_rf complex (n_rf,) = dL/dRe + i dL/dIm, g_t1, g_t2)."""
+    lib = lib or _load()
+    K = ph.K
+    x, y, z, _, _, df, m0 = (_f64(a) for a in ph.arrays())
+    cls = np.ascontiguousarray(cls, dtype=np.int32)
+    t1c, t2c = _f64(t1c), _f64(t2c)
+    C = t1c.size
+    rf_re, rf_im, gx, gy, gz = (_f64(a) for a in (seq.rf_re, seq.rf_im, seq.gx, seq.gy, seq.gz))
+    btype = np.ascontiguousarray(seq.btype, dtype=np.int32)
+    i64 = [np.ascontiguousarray(a, dtype=np.int64) for a in (seq.step_offset, seq.n_steps, seq.n_samples,
+                                                            seq.sample_offset)]
+    tau, mom = _f64(seq.tau), _f64(np.asarray(seq.moment).reshape(-1, 3))
+    adc = np.ascontiguousarray(seq.adc_idx, dtype=np.int32)
+    rp = np.asarray(rf_param, dtype=np.complex128)
+    n_rf = rp.size
+    rpi = _f64(np.stack([rp.real, rp.imag], 1).ravel())
+    pb = np.ascontiguousarray(param_blocks, dtype=np.int32)
+    wv = np.asarray(w, dtype=np.complex128)
+    wi = _f64(np.stack([wv.real, wv.imag], 1).ravel())
+    N = seq.total_samples
+    sig = np.zeros(2 * max(N, 1))
+    g_rf = np.zeros(2 * max(n_rf, 1))
+    g1, g2 = np.zeros(C), np.zeros(C)
+    d = lambda a: a.ctypes.data
+    rc = lib.oracle_adjoint(K, d(x), d(y), d(z), d(df), d(m0), d(cls), C, d(t1c), d(t2c), seq.n_blocks,
+                            d(btype), *(d(a) for a in i64), d(tau), d(mom), seq.total_steps,
+                            d(rf_re), d(rf_im), d(gx), d(gy), d(gz), N, d(adc), float(seq.dt), n_rf,
+                            d(pb), pb.size, d(rpi), d(wi), nthreads, d(sig), d(g_rf), d(g1), d(g2))
+    if rc != 0:
+        raise ValueError(f"oracle_adjoint rejected its input ({rc})")
+    return (sig[0:2 * N:2] + 1j * sig[1:2 * N:2], g_rf[0:2 * n_rf:2] + 1j * g_rf[1:2 * n_rf:2], g1, g2)

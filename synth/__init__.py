@@ -45,6 +45,7 @@ class Phantom:
     m0: np.ndarray
     shape: tuple | None = None  # (nz, ny, nx) for grid phantoms
     name: str = ""
+    labels: np.ndarray | None = None  # tissue class per isochromat (int32), when known
 
     @property
     def K(self) -> int:
@@ -56,7 +57,8 @@ class Phantom:
     def subset(self, idx: np.ndarray, name: str | None = None) -> "Phantom":
         idx = np.asarray(idx)
         return Phantom(*(a[idx].copy() for a in self.arrays()), shape=None,
-                       name=name or (self.name + f"[{idx.size}]"))
+                       name=name or (self.name + f"[{idx.size}]"),
+                       labels=None if self.labels is None else self.labels[idx].copy())
 
 
 def _grid(n, extent):
@@ -111,8 +113,9 @@ def ellipse_phantom(nx, ny, nz, fov, t1s, t2s, pds, df_range, df_levels,
     Y = np.broadcast_to(ys[None, :, None], shp)
     X = np.broadcast_to(xs[None, None, :], shp)
     f32 = lambda a: np.ascontiguousarray(np.broadcast_to(a, shp), dtype=np.float32).ravel()
+    labels = np.ascontiguousarray(np.broadcast_to(cls[None], shp), dtype=np.int32).ravel()
     return Phantom(f32(X), f32(Y), f32(Z), f32(t1[None]), f32(t2[None]), f32(df),
-                   f32(pd[None]), shape=shp, name=name)
+                   f32(pd[None]), shape=shp, name=name, labels=labels)
 
 
 def gre_phantom(nx=32, ny=32, nz=4, seed=1000):
@@ -429,6 +432,23 @@ def mlp_init_params(seed=0):
               ((128, 128), 128), ((128,), 128), ((12, 128), 128), ((12,), 128)]
     parts = [rng.uniform(-1, 1, int(np.prod(s))) / np.sqrt(f) for s, f in shapes]
     return np.concatenate(parts).astype(np.float32)
+
+
+# ---- adjoint (gradient of the signal) workload ----------------------------
+def adjoint_workload(nx=256, ny=256, nz=16, n_lines=8, n_read=64, rf_steps=3000, seed=1002):
+    """GRE for the signal gradient: a (nx, ny, nz) six-class phantom over
+    256x256x10 mm, 8 B0 levels in +-50 Hz; n_lines TRs of a 3 ms sinc 30-degree
+    RF with Gz (5 mm slice), n_read samples at 10 us, TE 5 ms, TR 10 ms.
+
+    Returns (phantom, class T1, class T2, sequence, rf_param, param_blocks):
+    the RF blocks listed in param_blocks all play the complex pulse rf_param."""
+    ph = ellipse_phantom(nx, ny, nz, (0.256, 0.256, 0.010), SIX_T1, SIX_T2, SIX_PD,
+                         df_range=50.0, df_levels=8, seed=seed, name=f"adjoint {nx}x{ny}x{nz}")
+    seq = gre_sequence(n_lines=n_lines, n_read=n_read, dwell_steps=10, fov=(0.256, 0.256), thk=0.005,
+                       rf_steps=rf_steps, te=5e-3, tr=10e-3)
+    rf = sinc_pulse(rf_steps, 1e-6, np.deg2rad(30.0), 4.0)
+    blocks = np.nonzero(np.asarray(seq.btype) == BLOCK_RF)[0].astype(np.int32)
+    return ph, np.array(SIX_T1), np.array(SIX_T2), seq, rf.astype(np.complex128), blocks
 
 
 # Workload registry: the sizes used by the benchmark and the parity tests.
