@@ -165,6 +165,49 @@ def surrogate_leg(sim, gb, ph, fse, sig_exact, m_out, steps):
     return res
 
 
+def adjoint_leg(gb, steps):
+    """Gradient of the GRE signal (3000 complex RF samples, 6 tissue T1/T2
+    pairs) on the 256x256x16 phantom: forward with checkpoints every 256 ops,
+    then the backward pass, FP32 state and FP64 sums."""
+    import numpy as np
+    import torch
+
+    import synth
+    ph, t1c, t2c, seq, rf, pb = synth.adjoint_workload()
+    sim = gb.Simulator(0)
+    sim.set_phantom(ph)
+    sim.set_sequence(seq)
+    adj = gb.Adjoint(sim, ph.labels, pb, every=256)
+    rng = np.random.default_rng(12)
+    w = rng.standard_normal(seq.total_samples) + 1j * rng.standard_normal(seq.total_samples)
+    W = torch.tensor(np.stack([w.real, w.imag], 1), dtype=torch.float64, device="cuda")
+    rft = torch.tensor(np.stack([rf.real, rf.imag], 1), dtype=torch.float32, device="cuda")
+    t1 = torch.tensor(t1c, dtype=torch.float32, device="cuda")
+    t2 = torch.tensor(t2c, dtype=torch.float32, device="cuda")
+    fwd, bwd = [], []
+    for i in range(steps + 1):  # first pass warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        adj.forward(rft, t1, t2)
+        t_f = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        adj.backward(W)
+        t_b = time.perf_counter() - t0
+        if i:
+            fwd.append(t_f)
+            bwd.append(t_b)
+    S = seq.stepped_count()
+    n_ops = S + int(np.sum(np.asarray(seq.btype) == synth.BLOCK_RELAX))
+    f, b = float(np.mean(fwd)), float(np.mean(bwd))
+    sim.close()
+    return {"workload": f"GRE {ph.K} isochromats (256x256x16), {len(pb)} TRs of a 3000-sample complex sinc RF, "
+                        f"{seq.total_samples} samples; gradient wrt 3000 complex RF samples + 6 (T1, T2) pairs",
+            "forward_ms": f * 1e3, "backward_ms": b * 1e3, "backward_over_forward": b / f,
+            "forward_iso_steps_per_s": ph.K * S / f, "backward_iso_steps_per_s": ph.K * S / b,
+            "checkpoint_every": 256, "checkpoint_bytes": 12 * ph.K * -(-n_ops // 256),
+            "precision": "FP32 state, FP64 sums over isochromats"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +217,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-method runs")
     ap.add_argument("--no-epi", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the signal-gradient leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -256,6 +300,11 @@ def main():
         sim.set_sequence(fse)
         out["surrogate"] = surrogate_leg(sim, gb, ph, fse, sig_fse_exact, m_out, args.steps)
         log(f"surrogate: {out['surrogate']}")
+
+    # ---- gradient of the signal (adjoint) -------------------------------------------
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(gb, max(1, min(args.steps, 3)))
+        log(f"adjoint: {out['adjoint']}")
 
     # ---- EPI grouped --------------------------------------------------------------
     if not args.no_epi:

@@ -286,6 +286,43 @@ int gbs_mlp_train(gbs_mlp *m, const float *tuples, const double *T_exact, int64_
  * device mismatch). */
 int gbs_set_surrogate(gbs_ctx *ctx, gbs_mlp *m, float tol, int32_t n_check, uint64_t seed);
 
+/* ==== gradient of the signal (adjoint Bloch simulation) ===================
+ *
+ * Reverse-mode differentiation of the plain simulation (Eq. 2 with U = D R
+ * of Eq. A1, A2 per raster step; Eq. 4, 5 for relaxation blocks; Eq. 6) of
+ * the context's phantom and sequence, in FP32 with FP64 sums over
+ * isochromats.  Parameters: a complex "parameter pulse" of n_rf samples,
+ * played by every listed RF block in place of its own B1, and per-class T1
+ * and T2 (isochromat k has class cls[k]; the phantom's own T1/T2 arrays are
+ * not used).  For a cotangent w of the signal the backward pass returns the
+ * gradient of L = sum_n (w_re[n] Re A_n + w_im[n] Im A_n).
+ *
+ * The forward pass stores the state every `every` ops (one op = one raster
+ * step or one relaxation block; 3 * K floats per checkpoint, owned by the
+ * context); the backward pass steps each segment again from its checkpoint.
+ */
+
+/* Forward pass.  cls: device int32[K] in [0, n_classes), n_classes <= 64;
+ * t1c, t2c: device float[n_classes] (s, > 0); rf_param: device float[2*n_rf]
+ * interleaved (re, im) in T, n_rf <= 3072; param_blocks: host int32 list of
+ * RF block indices whose n_steps equals n_rf; every: multiple of 16 in
+ * [16, 256].  sig_out: device double[2*total_samples] (re, im).  The context
+ * keeps cls, t1c, t2c and rf_param (views) for the backward pass: keep them
+ * alive and unchanged until then.  Synchronizes.
+ * Errors: GBS_E_STATE (no phantom/sequence), GBS_E_INVALID (limits, block
+ * list, class index out of range, T <= 0), GBS_E_NOMEM, GBS_E_HIP. */
+int gbs_adj_forward(gbs_ctx *ctx, const int32_t *cls, int32_t n_classes, const float *t1c, const float *t2c,
+                    const float *rf_param, int64_t n_rf, const int32_t *param_blocks, int32_t n_param_blocks,
+                    int32_t every, double *sig_out);
+
+/* Backward pass of the last gbs_adj_forward: grad_sig device
+ * double[2*total_samples] (dL/dRe A_n, dL/dIm A_n); outputs device
+ * grad_rf float[2*n_rf] (dL/dRe B1, dL/dIm B1 per sample), grad_t1 and
+ * grad_t2 double[n_classes].  May be called repeatedly with different
+ * cotangents.  Synchronizes.  Errors: GBS_E_STATE (no forward since the last
+ * change of phantom or sequence), GBS_E_INVALID, GBS_E_HIP. */
+int gbs_adj_backward(gbs_ctx *ctx, const double *grad_sig, float *grad_rf, double *grad_t1, double *grad_t2);
+
 #ifdef __cplusplus
 }
 #endif

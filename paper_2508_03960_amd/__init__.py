@@ -30,7 +30,8 @@ EXPORTED = ("gbs_create", "gbs_destroy", "gbs_set_phantom", "gbs_set_sequence", 
             "gbs_simulate", "gbs_get_info", "gbs_last_error", "gbs_strerror", "gbs_plan_summary",
             "gbs_mlp_create", "gbs_mlp_destroy", "gbs_mlp_last_error", "gbs_mlp_set_pulse",
             "gbs_mlp_set_norm", "gbs_mlp_get_params", "gbs_mlp_set_params", "gbs_mlp_exact",
-            "gbs_mlp_infer", "gbs_mlp_loss_grad", "gbs_mlp_train", "gbs_set_surrogate")
+            "gbs_mlp_infer", "gbs_mlp_loss_grad", "gbs_mlp_train", "gbs_set_surrogate",
+            "gbs_adj_forward", "gbs_adj_backward")
 
 
 class gbs_block(ctypes.Structure):
@@ -97,6 +98,8 @@ def _load(path=LIB_PATH):
         "gbs_mlp_loss_grad": ([P, P, P, I64, P, P], ctypes.c_int),
         "gbs_mlp_train": ([P, P, P, I64, P, P, I64], ctypes.c_int),
         "gbs_set_surrogate": ([P, P, ctypes.c_float, I32, ctypes.c_uint64], ctypes.c_int),
+        "gbs_adj_forward": ([P, P, I32, P, P, P, I64, P, I32, I32, P], ctypes.c_int),
+        "gbs_adj_backward": ([P, P, P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -333,3 +336,69 @@ def set_surrogate(sim, mlp, tol=1e-3, n_check=32, seed=0):
     sim._mlp = mlp  # keep the network alive while attached
     sim._check(lib.gbs_set_surrogate(sim._h, None if mlp is None else mlp._h, float(tol), int(n_check),
                                      int(seed)))
+
+
+class Adjoint:
+    """Gradient of the signal of a Simulator's phantom and sequence with
+    respect to a complex parameter pulse and per-class T1/T2 (gbs_adj_*)."""
+
+    def __init__(self, sim, labels, param_blocks, every=256):
+        import numpy as np
+        self.sim = sim
+        self.cls = torch.as_tensor(np.asarray(labels, np.int32)).to(sim.device).contiguous()
+        self.param_blocks = np.ascontiguousarray(param_blocks, dtype=np.int32)
+        self.every = int(every)
+        self._held = None
+        self.generation = 0
+
+    def forward(self, rf, t1c, t2c):
+        """rf: (n_rf, 2) float32 (re, im) in T; t1c, t2c: (C,) float32.  Returns
+        the signal as a (N, 2) float64 device tensor."""
+        dev = self.sim.device
+        rf = rf.detach().to(dev, torch.float32).contiguous()
+        t1c = t1c.detach().to(dev, torch.float32).contiguous()
+        t2c = t2c.detach().to(dev, torch.float32).contiguous()
+        sig = torch.empty(max(self.sim.n_samples, 1), 2, device=dev, dtype=torch.float64)
+        self._held = (rf, t1c, t2c)  # the library reads these again in backward
+        self.sim._check(lib.gbs_adj_forward(self.sim._h, _ptr(self.cls), t1c.numel(), _ptr(t1c), _ptr(t2c),
+                                            _ptr(rf), rf.shape[0], self.param_blocks.ctypes.data,
+                                            self.param_blocks.size, self.every, _ptr(sig)))
+        self.generation += 1
+        return sig[: self.sim.n_samples]
+
+    def backward(self, grad_sig):
+        """grad_sig: (N, 2) cotangent of the signal.  Returns (grad_rf (n_rf, 2)
+        float32, grad_t1 (C,) float64, grad_t2 (C,) float64)."""
+        rf, t1c, _ = self._held
+        dev = self.sim.device
+        g = grad_sig.detach().to(dev, torch.float64).contiguous()
+        grf = torch.empty_like(rf)
+        g1 = torch.empty(t1c.numel(), device=dev, dtype=torch.float64)
+        g2 = torch.empty_like(g1)
+        self.sim._check(lib.gbs_adj_backward(self.sim._h, _ptr(g), _ptr(grf), _ptr(g1), _ptr(g2)))
+        return grf, g1, g2
+
+
+class BlochSignal(torch.autograd.Function):
+    """signal = BlochSignal.apply(rf, t1c, t2c, adjoint): differentiable with
+    respect to the parameter pulse rf (n_rf, 2) and the class T1/T2."""
+
+    @staticmethod
+    def forward(ctx, rf, t1c, t2c, adj):
+        sig = adj.forward(rf, t1c, t2c)
+        ctx.adj = adj
+        ctx.generation = adj.generation
+        ctx.dtypes = (rf.dtype, t1c.dtype, t2c.dtype)
+        return sig
+
+    @staticmethod
+    def backward(ctx, grad_sig):
+        adj = ctx.adj
+        if adj.generation != ctx.generation:
+            raise RuntimeError("the adjoint's checkpoints belong to a later forward pass")
+        grf, g1, g2 = adj.backward(grad_sig)
+        return grf.to(ctx.dtypes[0]), g1.to(ctx.dtypes[1]), g2.to(ctx.dtypes[2]), None
+
+
+def bloch_signal(adj, rf, t1c, t2c):
+    return BlochSignal.apply(rf, t1c, t2c, adj)

@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "adj.hpp"
 #include "consts.hpp"
 #include "gbloch.h"
 #include "groups.hpp"
@@ -115,6 +116,10 @@ struct gbs_ctx {
     int32_t surr_check = 32;
     uint64_t surr_seed = 0;
     DevBuf surr;
+    // gradient of the signal (adjoint): flattened ops, checkpoints, partials
+    DevBuf adj_ops, adj_samp, adj_ckpt, adj_sig, adj_grf, adj_gt;
+    AdjArgs adj{};
+    bool adj_ready = false;
     bool pplan_valid = false;
     Plan pplan;  // plain schedule
 };
@@ -183,7 +188,8 @@ int gbs_destroy(gbs_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     DevBuf *bufs[] = {&ctx->d_wave, &ctx->d_adc, &ctx->perm, &ctx->inv, &ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i,
                       &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->tabs, &ctx->gsum, &ctx->partial, &ctx->jobs,
-                      &ctx->samp, &ctx->flag, &ctx->surr};
+                      &ctx->samp, &ctx->flag, &ctx->surr, &ctx->adj_ops, &ctx->adj_samp, &ctx->adj_ckpt,
+                      &ctx->adj_sig, &ctx->adj_grf, &ctx->adj_gt};
     for (DevBuf *b : bufs) b->release();
     for (int a = 0; a < 3; ++a) {
         ctx->gid[a].release();
@@ -208,6 +214,7 @@ int gbs_set_phantom(gbs_ctx *ctx, int64_t K, const float *x, const float *y, con
     ctx->has_ph = false;
     ctx->groups_valid = false;
     ctx->gp.valid = false;
+    ctx->adj_ready = false;
     PhantomPtrs ph{x, y, z, t1, t2, df_hz, m0};
     ALLOC(ctx->flag, 256);
     HIPCHK(launch_fill_f64(ctx->flag.as<double>(), 1, ctx->stream));
@@ -239,6 +246,7 @@ int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, co
     ctx->has_seq = false;
     ctx->gp.valid = false;
     ctx->pplan_valid = false;
+    ctx->adj_ready = false;
     copy_sequence(ctx->seq, blocks, n_blocks, rf_re, rf_im, gx, gy, gz, total_steps, adc_idx, total_samples, dt);
     ctx->cls = classify(ctx->seq);
     std::vector<StepW> w((size_t)total_steps);
@@ -988,5 +996,141 @@ extern "C" int gbs_set_surrogate(gbs_ctx *ctx, gbs_mlp *m, float tol, int32_t n_
     ctx->surr_check = n_check;
     ctx->surr_seed = seed;
     ctx->gp.valid = false;
+    return GBS_OK;
+}
+
+// ------------------------------------------------------------------ adjoint
+extern "C" int gbs_adj_forward(gbs_ctx *ctx, const int32_t *cls, int32_t n_classes, const float *t1c,
+                               const float *t2c, const float *rf_param, int64_t n_rf, const int32_t *param_blocks,
+                               int32_t n_param_blocks, int32_t every, double *sig_out) {
+    if (!ctx) return GBS_E_INVALID;
+    ctx->adj_ready = false;
+    if (!ctx->has_ph) return fail(ctx, GBS_E_STATE, "gbs_adj_forward before gbs_set_phantom");
+    if (!ctx->has_seq) return fail(ctx, GBS_E_STATE, "gbs_adj_forward before gbs_set_sequence");
+    if (!cls || !t1c || !t2c || !rf_param || (ctx->seq.total_samples > 0 && !sig_out))
+        return fail(ctx, GBS_E_INVALID, "null argument");
+    if (n_classes < 1 || n_classes > kAdjMaxClasses)
+        return fail(ctx, GBS_E_INVALID, "n_classes must be in [1, 64]");
+    if (n_rf < 1 || n_rf > kAdjMaxRf) return fail(ctx, GBS_E_INVALID, "n_rf must be in [1, 3072]");
+    if (every < kAdjSub || every > kAdjMaxEvery || every % kAdjSub)
+        return fail(ctx, GBS_E_INVALID, "checkpoint interval must be a multiple of 16 in [16, 256]");
+    if (n_param_blocks < 0 || (n_param_blocks > 0 && !param_blocks))
+        return fail(ctx, GBS_E_INVALID, "bad parameter block list");
+    const HostSeq &s = ctx->seq;
+    const int64_t nb = (int64_t)s.blocks.size();
+    std::vector<char> is_par(nb, 0);
+    for (int32_t i = 0; i < n_param_blocks; ++i) {
+        const int32_t b = param_blocks[i];
+        if (b < 0 || b >= nb || s.blocks[b].type != GBS_BLOCK_RF || s.blocks[b].n_steps != n_rf)
+            return fail(ctx, GBS_E_INVALID, "parameter blocks must be RF blocks of n_rf steps");
+        is_par[b] = 1;
+    }
+    // flatten the sequence: one op per raster step or relaxation block; samples by boundary
+    int64_t n_ops = 0;
+    for (const gbs_block &b : s.blocks) n_ops += b.type == GBS_BLOCK_RELAX ? 1 : b.n_steps;
+    if (n_ops > (int64_t)INT32_MAX - 2) return fail(ctx, GBS_E_INVALID, "sequence too long for the adjoint");
+    std::vector<AdjOp> ops((size_t)n_ops);
+    std::vector<int32_t> spos((size_t)s.total_samples);
+    int64_t o = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        const gbs_block &bk = s.blocks[b];
+        if (bk.type == GBS_BLOCK_RELAX) {
+            AdjOp &op = ops[o++];
+            op = AdjOp{};
+            op.kind = 1;
+            op.param = -1;
+            op.tau = bk.tau;
+            for (int i = 0; i < 3; ++i) op.cyc[i] = kGammaBar * bk.moment[i];
+            continue;
+        }
+        for (int32_t n = 0; n < bk.n_samples; ++n)
+            spos[bk.sample_offset + n] = (int32_t)(o + s.adc_idx[bk.sample_offset + n]);
+        for (int64_t j = 0; j < bk.n_steps; ++j) {
+            const size_t w = (size_t)(bk.step_offset + j);
+            AdjOp &op = ops[o++];
+            op = AdjOp{};
+            op.kind = 0;
+            op.b1r = s.rf_re[w];
+            op.b1i = s.rf_im[w];
+            op.gx = s.gx[w];
+            op.gy = s.gy[w];
+            op.gz = s.gz[w];
+            op.param = is_par[b] ? (int32_t)j : -1;
+        }
+    }
+    const int64_t N = s.total_samples;
+    std::vector<int32_t> samp((size_t)(n_ops + 2 + N), 0);  // sstart[n_ops + 2], then sid[N]
+    for (int64_t n = 0; n < N; ++n) samp[spos[n] + 1]++;
+    for (int64_t p = 0; p <= n_ops; ++p) samp[p + 1] += samp[p];
+    {
+        std::vector<int32_t> fill((size_t)(n_ops + 1), 0);
+        for (int64_t n = 0; n < N; ++n) samp[n_ops + 2 + samp[spos[n]] + fill[spos[n]]++] = (int32_t)n;
+    }
+    HIPCHK(hipSetDevice(ctx->device));
+    const int64_t K = ctx->K;
+    const int grid = (int)((K + kAdjWG - 1) / kAdjWG);
+    const int64_t n_ckpt = (n_ops + every - 1) / every;
+    ALLOC(ctx->adj_ops, sizeof(AdjOp) * (size_t)std::max<int64_t>(n_ops, 1));
+    ALLOC(ctx->adj_samp, sizeof(int32_t) * samp.size());
+    ALLOC(ctx->adj_ckpt, sizeof(float) * 3 * (size_t)K * (size_t)std::max<int64_t>(n_ckpt, 1));
+    ALLOC(ctx->adj_sig, sizeof(double2) * (size_t)grid * (size_t)std::max<int64_t>(N, 1));
+    ALLOC(ctx->adj_grf, sizeof(float2) * (size_t)grid * (size_t)n_rf);
+    ALLOC(ctx->adj_gt, sizeof(double2) * (size_t)grid * (size_t)n_classes);
+    ALLOC(ctx->flag, 256);
+    // inputs: class indices in range, T1/T2 > 0 (checked on the device)
+    HIPCHK(launch_fill_f64(ctx->flag.as<double>(), 1, ctx->stream));
+    HIPCHK(launch_adj_validate(K, cls, n_classes, t1c, t2c, ctx->flag.as<int>(), ctx->stream));
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, ctx->flag.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (bad) return fail(ctx, GBS_E_INVALID, "class index out of range or T1/T2 <= 0");
+    if (n_ops > 0) HIPCHK(hipMemcpy(ctx->adj_ops.p, ops.data(), sizeof(AdjOp) * (size_t)n_ops, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(ctx->adj_samp.p, samp.data(), sizeof(int32_t) * samp.size(), hipMemcpyHostToDevice));
+    AdjArgs a{};
+    a.K = K;
+    a.x = ctx->ph.x;
+    a.y = ctx->ph.y;
+    a.z = ctx->ph.z;
+    a.df = ctx->ph.df;
+    a.m0 = ctx->ph.m0;
+    a.cls = cls;
+    a.t1c = t1c;
+    a.t2c = t2c;
+    a.n_classes = n_classes;
+    a.ops = ctx->adj_ops.as<AdjOp>();
+    a.n_ops = (int32_t)n_ops;
+    a.rfp = (const float2 *)rf_param;
+    a.n_rf = (int32_t)n_rf;
+    a.sstart = ctx->adj_samp.as<int32_t>();
+    a.sid = ctx->adj_samp.as<int32_t>() + n_ops + 2;
+    a.dt = s.dt;
+    a.every = every;
+    a.ckpt = ctx->adj_ckpt.as<float>();
+    a.N = (int32_t)N;
+    a.sig_part = ctx->adj_sig.as<double2>();
+    a.grf_part = ctx->adj_grf.as<float2>();
+    a.gt_part = ctx->adj_gt.as<double2>();
+    HIPCHK(launch_adj_forward(a, ctx->stream));
+    HIPCHK(launch_adj_finalize(a, sig_out, nullptr, nullptr, nullptr, true, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipGetLastError());
+    ctx->adj = a;
+    ctx->adj_ready = true;
+    return GBS_OK;
+}
+
+extern "C" int gbs_adj_backward(gbs_ctx *ctx, const double *grad_sig, float *grad_rf, double *grad_t1,
+                                double *grad_t2) {
+    if (!ctx) return GBS_E_INVALID;
+    if (!ctx->adj_ready) return fail(ctx, GBS_E_STATE, "gbs_adj_backward without a preceding gbs_adj_forward");
+    if ((ctx->adj.N > 0 && !grad_sig) || !grad_rf || !grad_t1 || !grad_t2)
+        return fail(ctx, GBS_E_INVALID, "null argument");
+    HIPCHK(hipSetDevice(ctx->device));
+    AdjArgs a = ctx->adj;
+    a.w = (const double2 *)grad_sig;
+    HIPCHK(launch_adj_backward(a, ctx->stream));
+    HIPCHK(launch_adj_finalize(a, nullptr, grad_rf, grad_t1, grad_t2, false, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipGetLastError());
     return GBS_OK;
 }

@@ -1,0 +1,395 @@
+// Reverse-mode (adjoint) Bloch simulation for gfx950: the gradient of
+// L = sum_n (w_re[n] Re A_n + w_im[n] Im A_n) with respect to the samples of
+// a parameter RF pulse and per-class T1, T2.  One isochromat per thread,
+// FP32 state, FP64 accumulation of sums over isochromats.
+//
+//  k_adj_forward   plain stepping (Eq. 2 with U = D R of Eq. A1, A2; Eq. 4, 5
+//                  for relaxation blocks), the samples of Eq. 6, and the state
+//                  at every `every`-th op boundary (checkpoints, SoA in HBM).
+//  k_adj_backward  segments in reverse: from each checkpoint the segment is
+//                  stepped again, keeping a sub-checkpoint every 16 ops in
+//                  LDS; each 16-op sub-segment is stepped once more with its
+//                  rotated states in registers and then walked backward:
+//                      lambda_p = (D_p R_p)^T lambda_{p+1} + cotangent at p.
+//  k_adj_finalize  sums the per-workgroup partials in FP64.
+//
+// Derivatives of one raster step M' = D R(w) M + (1 - E1) M0 e_z, with the
+// rotation vector w = -2 pi gamma_bar dt B (R = exp([w]x), Eq. A2), v = R M
+// and mu = D lambda':
+//   dL/dw = J^T (v x mu),  J^T = I - C [w]x + D3 [w]x^2        (SO(3) Jacobian)
+//   dL/dB1x = -2 pi gamma_bar dt (dL/dw)_x,   dL/dB1y likewise,
+//   dL/dT2 += (lambda'_x M'_x + lambda'_y M'_y) dt / T2^2,
+//   dL/dT1 += lambda'_z (M'_z - M0) dt / T1^2,
+// with S = sin t / t, C = (1 - cos t) / t^2, D3 = (t - sin t) / t^3, t = |w|.
+// A relaxation block is a z rotation by the phase of Eq. 4 and the decay of
+// Eq. 4, 5 over tau: the same T1, T2 terms with dt -> tau.
+#include "adj.hpp"
+#include "consts.hpp"
+#include "device_math.hpp"
+
+namespace gbs {
+
+// S, C, D3 of t = sqrt(q).  Taylor series below q = 4: the first dropped
+// terms are 4^9 / 19!, 4^9 / 20!, 4^9 / 21! (< 3e-12).
+__device__ __forceinline__ void rot_coeffs(float q, float &S, float &C, float &D3) {
+    if (q < 4.f) {
+        // 1/k! for k = 1 .. 21
+        constexpr float f[22] = {1.f, 1.f, 5.0e-1f, 1.6666666666666666e-1f, 4.1666666666666664e-2f,
+                                 8.3333333333333332e-3f, 1.3888888888888889e-3f, 1.9841269841269841e-4f,
+                                 2.4801587301587302e-5f, 2.7557319223985893e-6f, 2.7557319223985888e-7f,
+                                 2.5052108385441720e-8f, 2.0876756987868100e-9f, 1.6059043836821613e-10f,
+                                 1.1470745597729725e-11f, 7.6471637318198164e-13f, 4.7794773323873853e-14f,
+                                 2.8114572543455206e-15f, 1.5619206968586225e-16f, 8.2206352466243295e-18f,
+                                 4.1103176233121648e-19f, 1.9572941063391263e-20f};
+        float s = f[19], c = f[20], d = f[21];
+#pragma unroll
+        for (int n = 8; n >= 1; --n) {
+            s = f[2 * n - 1] - q * s;
+            c = f[2 * n] - q * c;
+            d = f[2 * n + 1] - q * d;
+        }
+        S = s;
+        C = c;
+        D3 = d;
+    } else {
+        const float t = sqrtf(q);
+        float sn, cs;
+        sincosf(t, &sn, &cs);
+        S = sn / t;
+        C = (1.f - cs) / q;
+        D3 = (t - sn) / (q * t);
+    }
+}
+
+struct Iso {
+    float x, y, z, m0;
+    double df;
+    float om1, om2;  // 1 - exp(-dt/T), accurate for small dt/T
+    float kap, ofs;  // 2 pi gamma_bar dt, 2 pi df dt
+    double t1, t2;
+    int cls;
+};
+
+__device__ __forceinline__ Iso load_iso(const AdjArgs &a, int64_t k, bool act) {
+    Iso s;
+    s.x = act ? a.x[k] : 0.f;
+    s.y = act ? a.y[k] : 0.f;
+    s.z = act ? a.z[k] : 0.f;
+    s.m0 = act ? a.m0[k] : 0.f;
+    const float df = act ? a.df[k] : 0.f;
+    s.df = df;
+    s.cls = act ? a.cls[k] : 0;
+    s.t1 = act ? (double)a.t1c[s.cls] : 1.0;
+    s.t2 = act ? (double)a.t2c[s.cls] : 1.0;
+    s.om1 = (float)(-expm1(-a.dt / s.t1));
+    s.om2 = (float)(-expm1(-a.dt / s.t2));
+    s.kap = (float)(kTwoPi * kGammaBar * a.dt);
+    s.ofs = (float)(kTwoPi * (double)df * a.dt);
+    return s;
+}
+
+struct StepCoef {
+    float wx, wy, wz, S, C, D3;
+};
+
+__device__ __forceinline__ StepCoef raster_coef(const AdjOp &op, const AdjArgs &a, const Iso &s, bool need_d3) {
+    StepCoef r;
+    float bx = op.b1r, by = op.b1i;
+    if (op.param >= 0) {
+        const float2 p = a.rfp[op.param];
+        bx = p.x;
+        by = p.y;
+    }
+    r.wx = -s.kap * bx;
+    r.wy = -s.kap * by;
+    r.wz = -(s.kap * (op.gx * s.x + op.gy * s.y + op.gz * s.z) + s.ofs);
+    const float q = r.wx * r.wx + r.wy * r.wy + r.wz * r.wz;
+    rot_coeffs(q, r.S, r.C, r.D3);
+    (void)need_d3;
+    return r;
+}
+
+// out = v + S (w x v) + sgn... : R v = v + S (w x v) + C (w x (w x v));
+// the transpose uses -S.
+__device__ __forceinline__ void rotate(const StepCoef &c, float S, const float *v, float *out) {
+    const float ax = c.wy * v[2] - c.wz * v[1], ay = c.wz * v[0] - c.wx * v[2], az = c.wx * v[1] - c.wy * v[0];
+    const float bx = c.wy * az - c.wz * ay, by = c.wz * ax - c.wx * az, bz = c.wx * ay - c.wy * ax;
+    out[0] = v[0] + S * ax + c.C * bx;
+    out[1] = v[1] + S * ay + c.C * by;
+    out[2] = v[2] + S * az + c.C * bz;
+}
+
+struct RelaxCoef {
+    float c, s, e2, om1;
+};
+
+__device__ __forceinline__ RelaxCoef relax_coef(const AdjOp &op, const Iso &s) {
+    RelaxCoef r;
+    const double cyc = op.cyc[0] * s.x + op.cyc[1] * s.y + op.cyc[2] * s.z + s.df * op.tau;
+    sincos_rev(cyc, &r.s, &r.c);
+    r.e2 = (float)exp(-op.tau / s.t2);
+    r.om1 = (float)(-expm1(-op.tau / s.t1));
+    return r;
+}
+
+// One op on M; v receives the rotated state before relaxation.
+__device__ __forceinline__ void step(const AdjOp &op, const AdjArgs &a, const Iso &s, float *M, float *v) {
+    if (op.kind == 0) {
+        const StepCoef c = raster_coef(op, a, s, false);
+        rotate(c, c.S, M, v);
+        M[0] = v[0] - s.om2 * v[0];
+        M[1] = v[1] - s.om2 * v[1];
+        M[2] = v[2] + s.om1 * (s.m0 - v[2]);
+    } else {
+        const RelaxCoef r = relax_coef(op, s);
+        v[0] = M[0] * r.c + M[1] * r.s;  // (Mx + i My) e^{-i phase}
+        v[1] = M[1] * r.c - M[0] * r.s;
+        v[2] = M[2];
+        M[0] = r.e2 * v[0];
+        M[1] = r.e2 * v[1];
+        M[2] = v[2] + r.om1 * (s.m0 - v[2]);
+    }
+}
+
+// --------------------------------------------------------------- forward
+__global__ __launch_bounds__(kAdjWG) void k_adj_forward(AdjArgs a) {
+    __shared__ float ws[kAdjWG / 64][2];
+    const int64_t k = (int64_t)blockIdx.x * kAdjWG + threadIdx.x;
+    const bool act = k < a.K;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const Iso s = load_iso(a, k, act);
+    float M[3] = {0.f, 0.f, s.m0}, v[3];
+    for (int p = 0;; ++p) {
+        if (p % a.every == 0 && p < a.n_ops && act) {
+            float *c = a.ckpt + (int64_t)(p / a.every) * 3 * a.K + k;
+            c[0] = M[0];
+            c[a.K] = M[1];
+            c[2 * a.K] = M[2];
+        }
+        const int q1 = a.sstart[p + 1];
+        for (int q = a.sstart[p]; q < q1; ++q) {  // samples at this boundary (Eq. 6)
+            const float sx = wave_sum_lane63(M[0]), sy = wave_sum_lane63(M[1]);
+            if (lane == 63) {
+                ws[wave][0] = sx;
+                ws[wave][1] = sy;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double re = 0.0, im = 0.0;
+#pragma unroll
+                for (int w = 0; w < kAdjWG / 64; ++w) {
+                    re += ws[w][0];
+                    im += ws[w][1];
+                }
+                a.sig_part[(int64_t)blockIdx.x * a.N + a.sid[q]] = make_double2(re, im);
+            }
+            __syncthreads();
+        }
+        if (p == a.n_ops) break;
+        step(a.ops[p], a, s, M, v);
+    }
+}
+
+// -------------------------------------------------------------- backward
+__device__ __forceinline__ void add_cotangent(const AdjArgs &a, int p, float *lam) {
+    const int q1 = a.sstart[p + 1];
+    for (int q = a.sstart[p]; q < q1; ++q) {
+        const double2 w = a.w[a.sid[q]];
+        lam[0] += (float)w.x;
+        lam[1] += (float)w.y;
+    }
+}
+
+struct TAcc {
+    double r1, r2;  // raster steps: sum of lambda'_z (M'_z - M0), lambda'_xy . M'_xy
+    double x1, x2;  // relaxation blocks: the same terms times tau
+};
+
+// Back through op `op` whose rotated state is v; lam = lambda' on entry, lambda on exit.
+__device__ __forceinline__ void back_step(const AdjOp &op, const AdjArgs &a, const Iso &s, const float *v, float *lam,
+                                          TAcc &t, float2 *rfg, int lane) {
+    if (op.kind == 0) {
+        const float Mx = v[0] - s.om2 * v[0], My = v[1] - s.om2 * v[1], Mz = v[2] + s.om1 * (s.m0 - v[2]);
+        t.r2 += (double)(lam[0] * Mx + lam[1] * My);
+        t.r1 += (double)(lam[2] * (Mz - s.m0));
+        const float e2 = 1.f - s.om2, e1 = 1.f - s.om1;
+        const float mu[3] = {e2 * lam[0], e2 * lam[1], e1 * lam[2]};
+        const StepCoef c = raster_coef(op, a, s, true);
+        if (op.param >= 0) {  // wave-uniform
+            const float wv[3] = {v[1] * mu[2] - v[2] * mu[1], v[2] * mu[0] - v[0] * mu[2], v[0] * mu[1] - v[1] * mu[0]};
+            const float ax = c.wy * wv[2] - c.wz * wv[1], ay = c.wz * wv[0] - c.wx * wv[2],
+                        az = c.wx * wv[1] - c.wy * wv[0];
+            const float bx = c.wy * az - c.wz * ay, by = c.wz * ax - c.wx * az;
+            const float gx = -s.kap * (wv[0] - c.C * ax + c.D3 * bx);
+            const float gy = -s.kap * (wv[1] - c.C * ay + c.D3 * by);
+            const float sx = wave_sum_lane63(gx), sy = wave_sum_lane63(gy);
+            if (lane == 63) {
+                atomicAdd(&rfg[op.param].x, sx);
+                atomicAdd(&rfg[op.param].y, sy);
+            }
+        }
+        rotate(c, -c.S, mu, lam);  // R^T mu
+    } else {
+        const RelaxCoef r = relax_coef(op, s);
+        const float Mx = r.e2 * v[0], My = r.e2 * v[1], Mz = v[2] + r.om1 * (s.m0 - v[2]);
+        t.x2 += (double)(lam[0] * Mx + lam[1] * My) * op.tau;
+        t.x1 += (double)(lam[2] * (Mz - s.m0)) * op.tau;
+        const float mux = r.e2 * lam[0], muy = r.e2 * lam[1];
+        lam[0] = r.c * mux - r.s * muy;
+        lam[1] = r.s * mux + r.c * muy;
+        lam[2] = (1.f - r.om1) * lam[2];
+    }
+}
+
+__global__ __launch_bounds__(kAdjWG) void k_adj_backward(AdjArgs a) {
+    __shared__ float sub[kAdjMaxEvery / kAdjSub][3][kAdjWG];
+    __shared__ double tg[kAdjMaxClasses][2];
+    __shared__ float2 rfg[kAdjMaxRf];
+    const int64_t k = (int64_t)blockIdx.x * kAdjWG + threadIdx.x;
+    const bool act = k < a.K;
+    const int lane = threadIdx.x & 63, tid = threadIdx.x;
+    for (int j = tid; j < a.n_rf; j += kAdjWG) rfg[j] = make_float2(0.f, 0.f);
+    for (int j = tid; j < kAdjMaxClasses * 2; j += kAdjWG) tg[j >> 1][j & 1] = 0.0;
+    __syncthreads();
+    const Iso s = load_iso(a, k, act);
+    float lam[3] = {0.f, 0.f, 0.f};
+    TAcc t = {0.0, 0.0, 0.0, 0.0};
+    add_cotangent(a, a.n_ops, lam);
+    const int n_seg = (a.n_ops + a.every - 1) / a.every;
+    for (int seg = n_seg - 1; seg >= 0; --seg) {
+        const int p0 = seg * a.every, p1 = min(p0 + a.every, a.n_ops);
+        float M[3] = {0.f, 0.f, 0.f}, v[3];
+        if (act) {
+            const float *c = a.ckpt + (int64_t)seg * 3 * a.K + k;
+            M[0] = c[0];
+            M[1] = c[a.K];
+            M[2] = c[2 * a.K];
+        }
+        for (int p = p0; p < p1; ++p) {  // each thread touches only its own LDS column
+            if (((p - p0) & (kAdjSub - 1)) == 0) {
+                const int j = (p - p0) / kAdjSub;
+                sub[j][0][tid] = M[0];
+                sub[j][1][tid] = M[1];
+                sub[j][2][tid] = M[2];
+            }
+            step(a.ops[p], a, s, M, v);
+        }
+        const int n_sub = (p1 - p0 + kAdjSub - 1) / kAdjSub;
+        for (int sb = n_sub - 1; sb >= 0; --sb) {
+            const int q0 = p0 + sb * kAdjSub, cnt = min(kAdjSub, p1 - q0);
+            M[0] = sub[sb][0][tid];
+            M[1] = sub[sb][1][tid];
+            M[2] = sub[sb][2][tid];
+            float V[kAdjSub][3];
+#pragma unroll
+            for (int i = 0; i < kAdjSub; ++i)
+                if (i < cnt) step(a.ops[q0 + i], a, s, M, V[i]);
+#pragma unroll
+            for (int i = kAdjSub - 1; i >= 0; --i) {
+                if (i < cnt) {
+                    back_step(a.ops[q0 + i], a, s, V[i], lam, t, rfg, lane);
+                    add_cotangent(a, q0 + i, lam);
+                }
+            }
+        }
+    }
+    if (act) {
+        atomicAdd(&tg[s.cls][0], (t.r1 * a.dt + t.x1) / (s.t1 * s.t1));
+        atomicAdd(&tg[s.cls][1], (t.r2 * a.dt + t.x2) / (s.t2 * s.t2));
+    }
+    __syncthreads();
+    for (int j = tid; j < a.n_rf; j += kAdjWG) a.grf_part[(int64_t)blockIdx.x * a.n_rf + j] = rfg[j];
+    for (int c = tid; c < a.n_classes; c += kAdjWG)
+        a.gt_part[(int64_t)blockIdx.x * a.n_classes + c] = make_double2(tg[c][0], tg[c][1]);
+}
+
+// -------------------------------------------------------------- finalize
+__global__ __launch_bounds__(256) void k_adj_sum_sig(const double2 *part, int grid, int N, double *sig) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= N) return;
+    double re = 0.0, im = 0.0;
+    for (int g = 0; g < grid; ++g) {
+        const double2 p = part[(int64_t)g * N + n];
+        re += p.x;
+        im += p.y;
+    }
+    sig[2 * n] = re;
+    sig[2 * n + 1] = im;
+}
+
+__global__ __launch_bounds__(256) void k_adj_sum_grad(const float2 *grf, const double2 *gt, int grid, int n_rf, int C,
+                                                      float *grad_rf, double *g1, double *g2) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j < n_rf) {
+        double re = 0.0, im = 0.0;
+        for (int g = 0; g < grid; ++g) {
+            const float2 p = grf[(int64_t)g * n_rf + j];
+            re += p.x;
+            im += p.y;
+        }
+        grad_rf[2 * j] = (float)re;
+        grad_rf[2 * j + 1] = (float)im;
+    }
+    if (j < C) {
+        double a = 0.0, b = 0.0;
+        for (int g = 0; g < grid; ++g) {
+            const double2 p = gt[(int64_t)g * C + j];
+            a += p.x;
+            b += p.y;
+        }
+        g1[j] = a;
+        g2[j] = b;
+    }
+}
+
+static int adj_grid(const AdjArgs &a) { return (int)((a.K + kAdjWG - 1) / kAdjWG); }
+
+hipError_t launch_adj_forward(const AdjArgs &a, hipStream_t st) {
+    if (a.K <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_forward, dim3(adj_grid(a)), dim3(kAdjWG), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_backward(const AdjArgs &a, hipStream_t st) {
+    if (a.K <= 0) return hipSuccess;
+    if (a.n_rf > kAdjMaxRf || a.every > kAdjMaxEvery || a.every % kAdjSub || a.n_classes > kAdjMaxClasses)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adj_backward, dim3(adj_grid(a)), dim3(kAdjWG), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_finalize(const AdjArgs &a, double *sig, float *grad_rf, double *grad_t1, double *grad_t2,
+                               bool forward, hipStream_t st) {
+    const int grid = adj_grid(a);
+    if (forward) {
+        if (a.N > 0)
+            hipLaunchKernelGGL(k_adj_sum_sig, dim3((a.N + 255) / 256), dim3(256), 0, st, a.sig_part, grid, a.N, sig);
+    } else {
+        const int n = a.n_rf > a.n_classes ? a.n_rf : a.n_classes;
+        hipLaunchKernelGGL(k_adj_sum_grad, dim3((n + 255) / 256), dim3(256), 0, st, a.grf_part, a.gt_part, grid,
+                           a.n_rf, a.n_classes, grad_rf, grad_t1, grad_t2);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gbs
+
+namespace gbs {
+
+// Flags bad inputs of a gradient run: class index out of range, T1/T2 not > 0.
+__global__ __launch_bounds__(256) void k_adj_validate(int64_t K, const int32_t *cls, int n_classes, const float *t1c,
+                                                      const float *t2c, int *flag) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < n_classes && !(t1c[k] > 0.f && t2c[k] > 0.f)) atomicOr(flag, 2);
+    if (k < K && (cls[k] < 0 || cls[k] >= n_classes)) atomicOr(flag, 1);
+}
+
+hipError_t launch_adj_validate(int64_t K, const int32_t *cls, int n_classes, const float *t1c, const float *t2c,
+                               int *flag, hipStream_t st) {
+    const int64_t n = K > n_classes ? K : n_classes;
+    hipLaunchKernelGGL(k_adj_validate, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, K, cls, n_classes, t1c,
+                       t2c, flag);
+    return hipGetLastError();
+}
+
+}  // namespace gbs
