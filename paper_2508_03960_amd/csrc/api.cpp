@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "adc.hpp"
 #include "adj.hpp"
 #include "consts.hpp"
 #include "gbloch.h"
@@ -61,9 +62,9 @@ struct GroupedPlan {
     size_t gsum_count = 0;
     int64_t max_rf_groups = 0, max_tab = 0;
     int max_adc_groups = 0, max_adc_samples = 0;
-    int n_rf = 0, n_fold = 0, n_tab = 0, n_adc = 0;
+    int n_rf = 0, n_fold = 0, n_tab = 0, n_adc = 0, n_adclin = 0, max_adclin_groups = 0;
     int64_t max_fold_groups = 0;
-    size_t o_rf = 0, o_fold = 0, o_tab = 0, o_adc = 0, o_sweep = 0;
+    size_t o_rf = 0, o_fold = 0, o_tab = 0, o_adc = 0, o_adclin = 0, o_sweep = 0;
     // execution: runs of grouped ops fused into sweeps, plain steps between
     struct Seg {
         int op_begin, op_end, need;
@@ -652,12 +653,39 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
                         ctx->gtab[f.axis].as<float4>(), f.tau, f.cyc, (float4 *)(tb + f.out_off)};
         g.max_fold_groups = std::max(g.max_fold_groups, ctx->ng[f.axis]);
     }
-    std::vector<AdcJobDev> aj(plan.adc.size());
+    // readouts whose sample times and moments are arithmetic in the sample index take the
+    // geometric-sequence evaluation; the rest the direct one
+    std::vector<AdcJobDev> aj;
+    std::vector<AdcLinJob> lj;
+    g.max_adc_groups = 0;
+    g.max_adc_samples = 0;
     for (size_t i = 0; i < plan.adc.size(); ++i) {
         const AdcJob &j = plan.adc[i];
         const gbs_block &b = s.blocks[j.block];
-        aj[i] = AdcJobDev{b.n_samples, (int32_t)ctx->ng[j.axis], ctx->gsum.as<double2>() + g.gsum_off[i],
-                          ctx->gtab[j.axis].as<float4>(), ctx->samp.as<double2>() + samp_off[i], b.sample_offset};
+        const int ns = b.n_samples;
+        const double2 *h = hs.data() + samp_off[i];
+        bool lin = ns >= 1;
+        double dtau = 0.0, dcyc = 0.0;
+        if (ns >= 2) {
+            dtau = (h[ns - 1].x - h[0].x) / (ns - 1);
+            dcyc = (h[ns - 1].y - h[0].y) / (ns - 1);
+            for (int n = 0; n < ns && lin; ++n) {
+                // phase error of the linear model below 1e-9 cycles per metre and 1e-15 s
+                lin = std::fabs(h[n].x - (h[0].x + n * dtau)) <= 1e-15 &&
+                      std::fabs(h[n].y - (h[0].y + n * dcyc)) <= 1e-9;
+            }
+        }
+        if (lin) {
+            lj.push_back(AdcLinJob{ns, (int32_t)ctx->ng[j.axis], ctx->gsum.as<double2>() + g.gsum_off[i],
+                                   ctx->gtab[j.axis].as<float4>(), h[0].x, dtau, h[0].y, dcyc, b.sample_offset});
+            g.max_adclin_groups = std::max(g.max_adclin_groups, (int)ctx->ng[j.axis]);
+        } else {
+            aj.push_back(AdcJobDev{ns, (int32_t)ctx->ng[j.axis], ctx->gsum.as<double2>() + g.gsum_off[i],
+                                   ctx->gtab[j.axis].as<float4>(), ctx->samp.as<double2>() + samp_off[i],
+                                   b.sample_offset});
+            g.max_adc_groups = std::max(g.max_adc_groups, (int)ctx->ng[j.axis]);
+            g.max_adc_samples = std::max(g.max_adc_samples, ns);
+        }
     }
 
     // ---- sweep ops: grouped ops in schedule order; consecutive ones fuse
@@ -777,11 +805,13 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
     g.n_fold = (int)fj.size();
     g.n_tab = (int)tjobs.size();
     g.n_adc = (int)aj.size();
+    g.n_adclin = (int)lj.size();
     g.o_rf = 0;
     g.o_fold = align256(sizeof(RfJobDev) * rj.size());
     g.o_tab = g.o_fold + align256(sizeof(FoldJob) * fj.size());
     g.o_adc = g.o_tab + align256(sizeof(TabJob) * tjobs.size());
-    g.o_sweep = g.o_adc + align256(sizeof(AdcJobDev) * aj.size());
+    g.o_adclin = g.o_adc + align256(sizeof(AdcJobDev) * aj.size());
+    g.o_sweep = g.o_adclin + align256(sizeof(AdcLinJob) * lj.size());
     const size_t jbytes = g.o_sweep + sizeof(SweepOp) * sops.size();
     ctx->host_jobs.assign(jbytes, 0);
     auto put = [&](size_t o, const void *src, size_t n) {
@@ -791,6 +821,7 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
     put(g.o_fold, fj.data(), sizeof(FoldJob) * fj.size());
     put(g.o_tab, tjobs.data(), sizeof(TabJob) * tjobs.size());
     put(g.o_adc, aj.data(), sizeof(AdcJobDev) * aj.size());
+    put(g.o_adclin, lj.data(), sizeof(AdcLinJob) * lj.size());
     put(g.o_sweep, sops.data(), sizeof(SweepOp) * sops.size());
     ALLOC(ctx->jobs, jbytes);
     HIPCHK(hipMemcpy(ctx->jobs.p, ctx->host_jobs.data(), jbytes, hipMemcpyHostToDevice));
@@ -900,6 +931,8 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     // ---- ADC samples from the group sums (Eq. 8, Eq. 10) --------------------
     HIPCHK(launch_adc_eval((const AdcJobDev *)(jb + g.o_adc), g.n_adc, g.max_adc_groups, g.max_adc_samples,
                            sig_out, ctx->stream));
+    HIPCHK(launch_adc_lin((const AdcLinJob *)(jb + g.o_adclin), g.n_adclin, g.max_adclin_groups, sig_out,
+                          ctx->stream));
     if (st) HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
     HIPCHK(launch_gather_state(K, ctx->inv.as<int32_t>(), mx, my, mz, m_out, m_out + K, m_out + 2 * K,
                                 ctx->stream));
