@@ -384,24 +384,37 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 const float2 v = gather_row(op.pre_ztab, gz);
                 cmul(fr, fi, v.x, v.y);
             }
+            if (op.pre_cy != 0.0 || (GENERAL && op.pre_cz != 0.0)) {  // per-isochromat phases
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                float ar = fr, ai = fi;
-                if (op.pre_cy != 0.0) {
-                    float s, co;
-                    sincos_rev(op.pre_cy * (double)yv[c], &s, &co);
-                    cmul(ar, ai, co, -s);
+                for (int c = 0; c < 4; ++c) {
+                    float ar = fr, ai = fi;
+                    if (op.pre_cy != 0.0) {
+                        float s, co;
+                        sincos_rev(op.pre_cy * (double)yv[c], &s, &co);
+                        cmul(ar, ai, co, -s);
+                    }
+                    if (GENERAL && op.pre_cz != 0.0) {
+                        float s, co;
+                        sincos_rev(op.pre_cz * (double)zv[c], &s, &co);
+                        cmul(ar, ai, co, -s);
+                    }
+                    const float nx = mx[c] * ar - my[c] * ai;
+                    const float ny = mx[c] * ai + my[c] * ar;
+                    mx[c] = nx;
+                    my[c] = ny;
                 }
-                if (GENERAL && op.pre_cz != 0.0) {
-                    float s, co;
-                    sincos_rev(op.pre_cz * (double)zv[c], &s, &co);
-                    cmul(ar, ai, co, -s);
+            } else {  // one factor for the thread's 4 isochromats
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const float nx = mx[c] * fr - my[c] * fi;
+                    const float ny = mx[c] * fi + my[c] * fr;
+                    mx[c] = nx;
+                    my[c] = ny;
                 }
-                const float nx = mx[c] * ar - my[c] * ai;
-                const float ny = mx[c] * ai + my[c] * ar;
-                mx[c] = nx;
-                my[c] = ny;
-                if (op.flags & kPreMz) mz[c] = fmaf(e1, mz[c] - m0[c], m0[c]);
+            }
+            if (op.flags & kPreMz) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) mz[c] = fmaf(e1, mz[c] - m0[c], m0[c]);
             }
         }
         if (op.flags & kOpRf) {
@@ -448,38 +461,67 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 const float2 v = gather_row(op.emit_ztab, gz);
                 cmul(fr, fi, v.x, v.y);
             }
-            float vr[4], vi[4];
+            // y phase of this emission: evaluated, or stepped from the last one
+            if (op.flags & kYDirect) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                if (op.flags & kYDirect) {
+                for (int c = 0; c < 4; ++c) {
                     float s, co;
                     sincos_rev(op.emit_cy * (double)yv[c], &s, &co);
                     wr[c] = co;
                     wi[c] = -s;
-                } else if (op.flags & kYStep) {
-                    cmul(wr[c], wi[c], rr[c], ri[c]);
                 }
-                if (op.flags & kYSetR) {
+            } else if (op.flags & kYStep) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) cmul(wr[c], wi[c], rr[c], ri[c]);
+            }
+            if (op.flags & kYSetR) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
                     float s, co;
                     sincos_rev(op.emit_dcy * (double)yv[c], &s, &co);
                     rr[c] = co;
                     ri[c] = -s;
                 }
-                float ar = fr, ai = fi;
-                if (op.flags & (kYDirect | kYStep)) cmul(ar, ai, wr[c], wi[c]);
-                if (GENERAL && op.emit_cz != 0.0) {
-                    float s, co;
-                    sincos_rev(op.emit_cz * (double)zv[c], &s, &co);
-                    cmul(ar, ai, co, -s);
-                }
-                vr[c] = mx[c] * ar - my[c] * ai;
-                vi[c] = mx[c] * ai + my[c] * ar;
             }
-            if (GENERAL && op.emit_axis == 1) {
-                emit_items(gy, vr, vi, act, op.gsum);
+            const bool yph = (op.flags & (kYDirect | kYStep)) != 0;
+            if (GENERAL && (op.emit_cz != 0.0 || op.emit_axis == 1)) {
+                float vr[4], vi[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    float ar = fr, ai = fi;
+                    if (yph) cmul(ar, ai, wr[c], wi[c]);
+                    if (op.emit_cz != 0.0) {
+                        float s, co;
+                        sincos_rev(op.emit_cz * (double)zv[c], &s, &co);
+                        cmul(ar, ai, co, -s);
+                    }
+                    vr[c] = mx[c] * ar - my[c] * ai;
+                    vi[c] = mx[c] * ai + my[c] * ar;
+                }
+                if (op.emit_axis == 1) {
+                    emit_items(gy, vr, vi, act, op.gsum);
+                } else {
+                    const float sr = (vr[0] + vr[1]) + (vr[2] + vr[3]);
+                    const float si = (vi[0] + vi[1]) + (vi[2] + vi[3]);
+                    if (op.emit_axis == 0)
+                        emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
+                    else
+                        emit_thread(gz, false, sr, si, act, op.gsum);
+                }
             } else {
-                const float sr = (vr[0] + vr[1]) + (vr[2] + vr[3]);
-                const float si = (vi[0] + vi[1]) + (vi[2] + vi[3]);
+                // the factor of the x and z groups is common to the thread's 4
+                // isochromats: sum (M_c w_c) first, multiply once
+                float pr, pi;
+                if (yph) {
+                    pr = (mx[0] * wr[0] - my[0] * wi[0]) + (mx[1] * wr[1] - my[1] * wi[1]) +
+                         ((mx[2] * wr[2] - my[2] * wi[2]) + (mx[3] * wr[3] - my[3] * wi[3]));
+                    pi = (mx[0] * wi[0] + my[0] * wr[0]) + (mx[1] * wi[1] + my[1] * wr[1]) +
+                         ((mx[2] * wi[2] + my[2] * wr[2]) + (mx[3] * wi[3] + my[3] * wr[3]));
+                } else {
+                    pr = (mx[0] + mx[1]) + (mx[2] + mx[3]);
+                    pi = (my[0] + my[1]) + (my[2] + my[3]);
+                }
+                const float sr = fr * pr - fi * pi, si = fr * pi + fi * pr;
                 if (op.emit_axis == 0)
                     emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
                 else
