@@ -101,7 +101,7 @@ struct gbs_ctx {
     uint32_t axes = 0;
     bool groups_valid = false;
     int64_t ng[3] = {-1, -1, -1};
-    int64_t Kint = 0;  // isochromats in the padded group-sorted layout (multiple of 4)
+    int64_t Kint = 0;  // isochromats in the padded group-sorted layout (multiple of 8)
     int64_t Kpad = 0;
     DevBuf perm, inv, xi, yi, zi, t1i, t2i, dfi, m0i, gid[3], gtab[3], gcount[3], ms[3];
     // per-simulate buffers
@@ -273,7 +273,7 @@ int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
     ctx->groups_valid = false;
     ctx->gp.valid = false;
     const int64_t K = ctx->K;
-    const int64_t cap = (4 * K + 1023) / 1024 * 1024;  // padded layout is at most 4 K long
+    const int64_t cap = (8 * K + 1023) / 1024 * 1024;  // padded layout is at most 8 K long
     const size_t scratch_bytes = group_scratch_bytes(K) + 4096;
     DevBuf scratch, gid_nat[3], order, perm_tmp, src_tmp;
     auto cleanup = [&]() {
@@ -316,7 +316,7 @@ int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
         if (e != hipSuccess) return fail_hip(e, "grouping failed");
         ctx->ng[a] = G;
     }
-    // 2. the padded group-sorted layout: (x-group, z-group) runs of multiples of 4
+    // 2. the padded group-sorted layout: (x-group, z-group) runs of multiples of 8
     int64_t kint = 0;
     hipError_t e = build_layout(K, gid_nat[0].as<int32_t>(), (axes & GBS_AX_Z) ? gid_nat[2].as<int32_t>() : nullptr,
                                 scratch.p, scratch_bytes, perm_tmp.as<int32_t>(), src_tmp.as<int32_t>(), cap, &kint,

@@ -222,8 +222,11 @@ hipError_t launch_tables(const TabJob *jobs, int n_jobs, int max_n, const float4
 // ---------------------------------------------------------------- k_sweep
 // Waves per SIMD the register budgets are sized for: the specialized sweep
 // fits without spills at this occupancy; the general one only at 3.
+#ifndef SWEEP_NI_FAST
+#define SWEEP_NI_FAST 8  // isochromats per thread in the fast sweep
+#endif
 #ifndef SWEEP_WAVES_FAST
-#define SWEEP_WAVES_FAST 6
+#define SWEEP_WAVES_FAST 4  // the largest occupancy without spills at 8 isochromats per thread
 #endif
 #define SWEEP_WAVES_GENERAL 3
 
@@ -329,46 +332,84 @@ __device__ __forceinline__ void emit_thread(int key, bool uni, float vr, float v
     }
 }
 
+// FP64 copy of a coordinate for a phase evaluation.  The empty asm keeps the
+// compiler from hoisting the conversion out of the op loop, which would hold
+// two registers per isochromat for the whole sweep.
+__device__ __forceinline__ double coord64(float v) {
+    asm volatile("" : "+v"(v));
+    return (double)v;
+}
+
+// Pairwise sum of N values (N a power of two).
+template <int N>
+__device__ __forceinline__ float tree_sum(const float *v) {
+    float t[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) t[c] = v[c];
+#pragma unroll
+    for (int w = N / 2; w >= 1; w /= 2)
+#pragma unroll
+        for (int c = 0; c < w; ++c) t[c] += t[c + w];
+    return t[0];
+}
+
 // Per-isochromat keys (the y axis is not part of the layout's runs).
-__device__ __forceinline__ void emit_items(const int key[4], const float vr[4], const float vi[4], bool act,
+template <int NI>
+__device__ __forceinline__ void emit_items(const int *key, const float *vr, const float *vi, bool act,
                                            double2 *__restrict__ gsum) {
     if (!act) return;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < NI; ++c) {
         group_add(&gsum[key[c]].x, (double)vr[c]);
         group_add(&gsum[key[c]].y, (double)vi[c]);
     }
 }
 
-// GENERAL = false drops what only y-group transitions/emissions and direct z
-// phases (no z groups) need, which frees registers for occupancy.
-template <bool GENERAL>
+// Each thread owns NI consecutive isochromats of the layout (NI = 4 or 8;
+// runs of equal (x-group, z-group) are padded to multiples of 8, so they
+// share their x- and z-groups).  GENERAL = false drops what only y-group
+// transitions/emissions and direct z phases (no z groups) need, which frees
+// registers for occupancy.
+template <bool GENERAL, int NI>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
-    const int64_t i4 = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool act = i4 < a.n4;
+    constexpr int NQ = NI / 4;  // float4 words per array and thread
+    const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool act = it < a.n4 / NQ;
+    const int64_t i4 = it * NQ;
     const int need = GENERAL ? a.need : (a.need & ~(kNeedGy | kNeedZ));
-    float mx[4] = {0, 0, 0, 0}, my[4] = {0, 0, 0, 0}, mz[4] = {0, 0, 0, 0}, m0[4] = {0, 0, 0, 0};
-    float yv[4] = {0, 0, 0, 0}, zv[4] = {0, 0, 0, 0};
-    int gy[4] = {0, 0, 0, 0};
-    int gx = 0, gz = 0;  // the thread's 4 isochromats share their x- and z-groups
+    float mx[NI], my[NI], mz[NI], m0[NI], yv[NI], zv[NI];
+    int gy[NI];
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+        mx[c] = my[c] = mz[c] = m0[c] = yv[c] = zv[c] = 0.f;
+        gy[c] = 0;
+    }
+    int gx = 0, gz = 0;
     if (act) {
-        ld4(a.mx, i4, mx);
-        ld4(a.my, i4, my);
-        if (need & kNeedMz) {
-            ld4(a.mz, i4, mz);
-            ld4(a.m0, i4, m0);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            ld4(a.mx, i4 + q, mx + 4 * q);
+            ld4(a.my, i4 + q, my + 4 * q);
+            if (need & kNeedMz) {
+                ld4(a.mz, i4 + q, mz + 4 * q);
+                ld4(a.m0, i4 + q, m0 + 4 * q);
+            }
+            if (need & kNeedGy) ld4i(a.gid_y, i4 + q, gy + 4 * q);
+            if (need & kNeedY) ld4(a.yv, i4 + q, yv + 4 * q);
+            if (need & kNeedZ) ld4(a.zv, i4 + q, zv + 4 * q);
         }
         if (need & kNeedGx) gx = a.gid_x[i4].x;
-        if (need & kNeedGy) ld4i(a.gid_y, i4, gy);
         if (need & kNeedGz) gz = a.gid_z[i4].x;
-        if (need & kNeedY) ld4(a.yv, i4, yv);
-        if (need & kNeedZ) ld4(a.zv, i4, zv);
     }
     // x-groups are contiguous runs in this order: is the wavefront inside one?
     const int gx0 = __builtin_amdgcn_readfirstlane(gx);
     const bool gx_uni = __all(!act || gx == gx0) != 0;
-    float wr[4] = {1, 1, 1, 1}, wi[4] = {0, 0, 0, 0};  // y phase of the last emission
-    float rr[4] = {1, 1, 1, 1}, ri[4] = {0, 0, 0, 0};  // its per-step factor
+    float wr[NI], wi[NI], rr[NI], ri[NI];  // y phase of the last emission and its per-step factor
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+        wr[c] = rr[c] = 1.f;
+        wi[c] = ri[c] = 0.f;
+    }
 
     for (int o = 0; o < a.n_ops; ++o) {
         const SweepOp op = load_op(a.ops, o);
@@ -386,16 +427,16 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
             }
             if (op.pre_cy != 0.0 || (GENERAL && op.pre_cz != 0.0)) {  // per-isochromat phases
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
+                for (int c = 0; c < NI; ++c) {
                     float ar = fr, ai = fi;
                     if (op.pre_cy != 0.0) {
                         float s, co;
-                        sincos_rev(op.pre_cy * (double)yv[c], &s, &co);
+                        sincos_rev(op.pre_cy * coord64(yv[c]), &s, &co);
                         cmul(ar, ai, co, -s);
                     }
                     if (GENERAL && op.pre_cz != 0.0) {
                         float s, co;
-                        sincos_rev(op.pre_cz * (double)zv[c], &s, &co);
+                        sincos_rev(op.pre_cz * coord64(zv[c]), &s, &co);
                         cmul(ar, ai, co, -s);
                     }
                     const float nx = mx[c] * ar - my[c] * ai;
@@ -403,9 +444,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     mx[c] = nx;
                     my[c] = ny;
                 }
-            } else {  // one factor for the thread's 4 isochromats
+            } else {  // one factor for all the thread's isochromats
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
+                for (int c = 0; c < NI; ++c) {
                     const float nx = mx[c] * fr - my[c] * fi;
                     const float ny = mx[c] * fi + my[c] * fr;
                     mx[c] = nx;
@@ -414,14 +455,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
             }
             if (op.flags & kPreMz) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) mz[c] = fmaf(e1, mz[c] - m0[c], m0[c]);
+                for (int c = 0; c < NI; ++c) mz[c] = fmaf(e1, mz[c] - m0[c], m0[c]);
             }
         }
         if (op.flags & kOpRf) {
             const float4 *__restrict__ tt = op.ttab;
             if (GENERAL && op.rf_axis == 1) {  // y groups: rows per isochromat
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
+                for (int c = 0; c < NI; ++c) {
                     const float4 r0 = gather_row(tt, 3 * gy[c]), r1 = gather_row(tt, 3 * gy[c] + 1),
                                  r2 = gather_row(tt, 3 * gy[c] + 2);
                     const float nx = fmaf(r0.x, mx[c], fmaf(r0.y, my[c], fmaf(r0.z, mz[c], r0.w * m0[c])));
@@ -444,7 +485,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     r2 = gather_row(tt, 3 * g + 2);
                 }
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
+                for (int c = 0; c < NI; ++c) {
                     const float nx = fmaf(r0.x, mx[c], fmaf(r0.y, my[c], fmaf(r0.z, mz[c], r0.w * m0[c])));
                     const float ny = fmaf(r1.x, mx[c], fmaf(r1.y, my[c], fmaf(r1.z, mz[c], r1.w * m0[c])));
                     const float nz = fmaf(r2.x, mx[c], fmaf(r2.y, my[c], fmaf(r2.z, mz[c], r2.w * m0[c])));
@@ -464,45 +505,44 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
             // y phase of this emission: evaluated, or stepped from the last one
             if (op.flags & kYDirect) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
+                for (int c = 0; c < NI; ++c) {
                     float s, co;
-                    sincos_rev(op.emit_cy * (double)yv[c], &s, &co);
+                    sincos_rev(op.emit_cy * coord64(yv[c]), &s, &co);
                     wr[c] = co;
                     wi[c] = -s;
                 }
             } else if (op.flags & kYStep) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) cmul(wr[c], wi[c], rr[c], ri[c]);
+                for (int c = 0; c < NI; ++c) cmul(wr[c], wi[c], rr[c], ri[c]);
             }
             if (op.flags & kYSetR) {
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
+                for (int c = 0; c < NI; ++c) {
                     float s, co;
-                    sincos_rev(op.emit_dcy * (double)yv[c], &s, &co);
+                    sincos_rev(op.emit_dcy * coord64(yv[c]), &s, &co);
                     rr[c] = co;
                     ri[c] = -s;
                 }
             }
             const bool yph = (op.flags & (kYDirect | kYStep)) != 0;
             if (GENERAL && (op.emit_cz != 0.0 || op.emit_axis == 1)) {
-                float vr[4], vi[4];
+                float vr[NI], vi[NI];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
+                for (int c = 0; c < NI; ++c) {
                     float ar = fr, ai = fi;
                     if (yph) cmul(ar, ai, wr[c], wi[c]);
                     if (op.emit_cz != 0.0) {
                         float s, co;
-                        sincos_rev(op.emit_cz * (double)zv[c], &s, &co);
+                        sincos_rev(op.emit_cz * coord64(zv[c]), &s, &co);
                         cmul(ar, ai, co, -s);
                     }
                     vr[c] = mx[c] * ar - my[c] * ai;
                     vi[c] = mx[c] * ai + my[c] * ar;
                 }
                 if (op.emit_axis == 1) {
-                    emit_items(gy, vr, vi, act, op.gsum);
+                    emit_items<NI>(gy, vr, vi, act, op.gsum);
                 } else {
-                    const float sr = (vr[0] + vr[1]) + (vr[2] + vr[3]);
-                    const float si = (vi[0] + vi[1]) + (vi[2] + vi[3]);
+                    const float sr = tree_sum<NI>(vr), si = tree_sum<NI>(vi);
                     if (op.emit_axis == 0)
                         emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
                     else
@@ -511,16 +551,13 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
             } else {
                 // the factor of the x and z groups is common to the thread's 4
                 // isochromats: sum (M_c w_c) first, multiply once
-                float pr, pi;
-                if (yph) {
-                    pr = (mx[0] * wr[0] - my[0] * wi[0]) + (mx[1] * wr[1] - my[1] * wi[1]) +
-                         ((mx[2] * wr[2] - my[2] * wi[2]) + (mx[3] * wr[3] - my[3] * wi[3]));
-                    pi = (mx[0] * wi[0] + my[0] * wr[0]) + (mx[1] * wi[1] + my[1] * wr[1]) +
-                         ((mx[2] * wi[2] + my[2] * wr[2]) + (mx[3] * wi[3] + my[3] * wr[3]));
-                } else {
-                    pr = (mx[0] + mx[1]) + (mx[2] + mx[3]);
-                    pi = (my[0] + my[1]) + (my[2] + my[3]);
+                float tr[NI], ti[NI];
+#pragma unroll
+                for (int c = 0; c < NI; ++c) {
+                    tr[c] = yph ? mx[c] * wr[c] - my[c] * wi[c] : mx[c];
+                    ti[c] = yph ? mx[c] * wi[c] + my[c] * wr[c] : my[c];
                 }
+                const float pr = tree_sum<NI>(tr), pi = tree_sum<NI>(ti);
                 const float sr = fr * pr - fi * pi, si = fr * pi + fi * pr;
                 if (op.emit_axis == 0)
                     emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
@@ -530,28 +567,33 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
         }
     }
     if (act && a.write_m) {
-        a.mx[i4] = make_float4(mx[0], mx[1], mx[2], mx[3]);
-        a.my[i4] = make_float4(my[0], my[1], my[2], my[3]);
-        if (need & kNeedMz) a.mz[i4] = make_float4(mz[0], mz[1], mz[2], mz[3]);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            a.mx[i4 + q] = make_float4(mx[4 * q], mx[4 * q + 1], mx[4 * q + 2], mx[4 * q + 3]);
+            a.my[i4 + q] = make_float4(my[4 * q], my[4 * q + 1], my[4 * q + 2], my[4 * q + 3]);
+            if (need & kNeedMz) a.mz[i4 + q] = make_float4(mz[4 * q], mz[4 * q + 1], mz[4 * q + 2], mz[4 * q + 3]);
+        }
     }
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES_FAST))) void k_sweep(SweepArgs a) {
-    sweep_body<false>(a);
+    sweep_body<false, SWEEP_NI_FAST>(a);
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES_GENERAL))) void k_sweep_general(
     SweepArgs a) {
-    sweep_body<true>(a);
+    sweep_body<true, 4>(a);
 }
 
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
     if (a.n4 <= 0 || a.n_ops <= 0) return hipSuccess;
-    const int64_t grid = (a.n4 + 255) / 256;
-    if (a.need & (kNeedGy | kNeedZ))
-        hipLaunchKernelGGL(k_sweep_general, dim3((unsigned)grid), dim3(256), 0, st, a);
-    else
-        hipLaunchKernelGGL(k_sweep, dim3((unsigned)grid), dim3(256), 0, st, a);
+    if (a.n4 % (SWEEP_NI_FAST / 4)) return hipErrorInvalidValue;  // the layout pads runs to multiples of 8
+    if (a.need & (kNeedGy | kNeedZ)) {
+        hipLaunchKernelGGL(k_sweep_general, dim3((unsigned)((a.n4 + 255) / 256)), dim3(256), 0, st, a);
+    } else {
+        const int64_t n = a.n4 / (SWEEP_NI_FAST / 4);
+        hipLaunchKernelGGL(k_sweep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+    }
     return hipGetLastError();
 }
 

@@ -84,8 +84,8 @@ __global__ void k_validate(int64_t K, PhantomPtrs ph, int *bad) {
 
 // ---- padded group-sorted layout ---------------------------------------------
 // Isochromats are ordered by (x-group, z-group, index) and every run of equal
-// (x-group, z-group) is padded to a multiple of 4 with copies of its first
-// member carrying M0 = 0.  A thread's 4 consecutive isochromats then always
+// (x-group, z-group) is padded to a multiple of 8 with copies of its first
+// member carrying M0 = 0.  A thread's 8 (or 4) consecutive isochromats then always
 // share both groups.
 __global__ void k_pair_keys(int64_t K, const int32_t *__restrict__ gx, const int32_t *__restrict__ gz,
                             uint64_t *__restrict__ key, int32_t *__restrict__ idx) {
@@ -108,7 +108,7 @@ __global__ void k_run_start(int64_t K, const int32_t *__restrict__ rid, int32_t 
 __global__ void k_run_plen(int64_t R, int64_t K, const int32_t *__restrict__ rstart, int32_t *__restrict__ plen) {
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
         const int32_t L = (int32_t)((r + 1 < R ? rstart[r + 1] : K) - rstart[r]);
-        plen[r] = (L + 3) & ~3;
+        plen[r] = (L + 7) & ~7;  // 8-isochromat sweep threads never straddle a run
     }
 }
 
@@ -175,7 +175,7 @@ hipError_t launch_gather_i32(int64_t K, int64_t Kpad, const int32_t *perm, const
 // Build the padded layout from natural-order x (and optional z) group ids.
 // perm[pos] = isochromat at internal position pos or -1 (padding); src[pos] =
 // the isochromat whose parameters the position copies.  perm/src need room
-// for Kpad_cap entries; *kint receives the padded count (a multiple of 4).
+// for Kpad_cap entries; *kint receives the padded count (a multiple of 8).
 hipError_t build_layout(int64_t K, const int32_t *gid_x, const int32_t *gid_z, void *scratch, size_t scratch_bytes,
                         int32_t *perm, int32_t *src, int64_t Kpad_cap, int64_t *kint, hipStream_t st) {
     char *p = (char *)scratch;
