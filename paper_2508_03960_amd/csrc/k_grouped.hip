@@ -551,13 +551,20 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
             } else {
                 // the factor of the x and z groups is common to the thread's 4
                 // isochromats: sum (M_c w_c) first, multiply once
-                float tr[NI], ti[NI];
+                float pr, pi;
+                if (yph) {
+                    float tr[NI], ti[NI];
 #pragma unroll
-                for (int c = 0; c < NI; ++c) {
-                    tr[c] = yph ? mx[c] * wr[c] - my[c] * wi[c] : mx[c];
-                    ti[c] = yph ? mx[c] * wi[c] + my[c] * wr[c] : my[c];
+                    for (int c = 0; c < NI; ++c) {
+                        tr[c] = mx[c] * wr[c] - my[c] * wi[c];
+                        ti[c] = mx[c] * wi[c] + my[c] * wr[c];
+                    }
+                    pr = tree_sum<NI>(tr);
+                    pi = tree_sum<NI>(ti);
+                } else {
+                    pr = tree_sum<NI>(mx);
+                    pi = tree_sum<NI>(my);
                 }
-                const float pr = tree_sum<NI>(tr), pi = tree_sum<NI>(ti);
                 const float sr = fr * pr - fi * pi, si = fr * pi + fi * pr;
                 if (op.emit_axis == 0)
                     emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
