@@ -105,7 +105,7 @@ struct gbs_ctx {
     int64_t Kpad = 0;
     DevBuf perm, inv, xi, yi, zi, t1i, t2i, dfi, m0i, gid[3], gtab[3], gcount[3], ms[3];
     // per-simulate buffers
-    DevBuf tabs, gsum, partial, jobs, samp, flag;
+    DevBuf tabs, gsum, partial, jobs, samp, flag, state64;
     std::vector<char> host_jobs;  // kept alive until the next call
     std::vector<double2> host_samp;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -190,7 +190,7 @@ int gbs_destroy(gbs_ctx *ctx) {
     DevBuf *bufs[] = {&ctx->d_wave, &ctx->d_adc, &ctx->perm, &ctx->inv, &ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i,
                       &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->tabs, &ctx->gsum, &ctx->partial, &ctx->jobs,
                       &ctx->samp, &ctx->flag, &ctx->surr, &ctx->adj_ops, &ctx->adj_samp, &ctx->adj_ckpt,
-                      &ctx->adj_sig, &ctx->adj_grf, &ctx->adj_gt};
+                      &ctx->adj_sig, &ctx->adj_grf, &ctx->adj_gt, &ctx->state64};
     for (DevBuf *b : bufs) b->release();
     for (int a = 0; a < 3; ++a) {
         ctx->gid[a].release();
@@ -444,12 +444,37 @@ static int run_plain(gbs_ctx *ctx, const float *m_init, float *m_out, double *si
     const int grid = plain_grid(K);
     ALLOC(ctx->partial, sizeof(double2) * (size_t)grid * kMaxSamplesPerLaunch);
     float *ox = m_out, *oy = m_out + K, *oz = m_out + 2 * K;
+    // the FP64 stepper keeps its state in FP64 between launches and rounds
+    // to the FP32 output once, in the last launch
+    double *sx = nullptr, *sy = nullptr, *sz = nullptr;
+    if (!fp32 && plan.ops.size() > 1) {
+        ALLOC(ctx->state64, sizeof(double) * 3 * (size_t)K);
+        sx = ctx->state64.as<double>();
+        sy = sx + K;
+        sz = sx + 2 * K;
+    }
     bool first = true;
-    for (const Op &op : plan.ops) {
+    for (size_t oi = 0; oi < plan.ops.size(); ++oi) {
+        const Op &op = plan.ops[oi];
+        const bool last = oi + 1 == plan.ops.size();
         const float *ix = first && m_init ? m_init : (first ? nullptr : ox);
         const float *iy = first && m_init ? m_init + K : (first ? nullptr : oy);
         const float *iz = first && m_init ? m_init + 2 * K : (first ? nullptr : oz);
         PlainArgs a = step_args(ctx, op.step, ctx->ph, K, ix, iy, iz, ox, oy, oz);
+        if (sx) {
+            if (!first) {
+                a.min_x = a.min_y = a.min_z = nullptr;
+                a.min64_x = sx;
+                a.min64_y = sy;
+                a.min64_z = sz;
+            }
+            if (!last) {
+                a.mout_x = a.mout_y = a.mout_z = nullptr;
+                a.mout64_x = sx;
+                a.mout64_y = sy;
+                a.mout64_z = sz;
+            }
+        }
         const bool b1 = op.step.block >= 0 && ctx->cls[op.step.block].has_b1;
         HIPCHK(launch_plain(a, b1, fp32, grid, ctx->stream));
         if (a.n_samples > 0) {

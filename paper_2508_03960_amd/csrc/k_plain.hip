@@ -169,7 +169,11 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a) {
                 const double t1 = a.ph.t1[k], t2 = a.ph.t2[k], df = a.ph.df[k];
                 const double m0 = a.ph.m0[k];
                 double vx = 0.0, vy = 0.0, vz = m0;
-                if (a.min_x) {
+                if (a.min64_x) {
+                    vx = a.min64_x[k];
+                    vy = a.min64_y[k];
+                    vz = a.min64_z[k];
+                } else if (a.min_x) {
                     vx = a.min_x[k];
                     vy = a.min_y[k];
                     vz = a.min_z[k];
@@ -257,9 +261,16 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a) {
         for (int i = 0; i < kIso; ++i) {
             const int64_t k = base + (int64_t)i * kPlainBlock + tid;
             if (k < a.K) {
-                a.mout_x[k] = (float)mx[i];
-                a.mout_y[k] = (float)my[i];
-                a.mout_z[k] = (float)mz[i];
+                if (a.mout_x) {
+                    a.mout_x[k] = (float)mx[i];
+                    a.mout_y[k] = (float)my[i];
+                    a.mout_z[k] = (float)mz[i];
+                }
+                if (a.mout64_x) {
+                    a.mout64_x[k] = (double)mx[i];
+                    a.mout64_y[k] = (double)my[i];
+                    a.mout64_z[k] = (double)mz[i];
+                }
             }
         }
     }

@@ -21,7 +21,11 @@ struct PlainArgs {
     int64_t K;
     PhantomPtrs ph;
     const float *min_x, *min_y, *min_z;  // state in; null: (0, 0, M0)
-    float *mout_x, *mout_y, *mout_z;     // state out (may alias state in)
+    float *mout_x, *mout_y, *mout_z;     // state out (may alias state in; null: not written)
+    // FP64 state carried between launches of the FP64 stepper (null: unused);
+    // when min64_x is set it replaces min_*
+    const double *min64_x, *min64_y, *min64_z;
+    double *mout64_x, *mout64_y, *mout64_z;
     const StepW *wave;                   // first raster step of this launch
     int32_t n_steps;
     const int32_t *sidx;  // sample boundaries, counted from the block start
