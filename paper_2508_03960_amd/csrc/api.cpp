@@ -782,9 +782,10 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
 
     // y phases of consecutive emissions inside a sweep: direct evaluation, or
     // a complex recurrence when the coefficients step evenly (restarted every
-    // 16 emissions to bound FP32 drift)
+    // 16 emissions to bound FP32 drift).  The kernel keeps the step factor
+    // between chains, so a chain with the step of the last one reuses it.
     for (const auto &sg : g.segs) {
-        double prev = 0.0, step = 0.0;
+        double prev = 0.0, step = 0.0, held = 0.0;  // held: step the kernel's factor holds (starts at 1)
         bool have_prev = false, have_step = false;
         int chain = 0;
         std::vector<int> em;
@@ -807,14 +808,39 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
                 chain = 0;
                 have_step = false;
                 if (e + 1 < em.size() && sops[em[e + 1]].emit_cy != 0.0) {
-                    o.flags |= kYSetR;
-                    o.emit_dcy = sops[em[e + 1]].emit_cy - c;
-                    step = o.emit_dcy;
+                    step = sops[em[e + 1]].emit_cy - c;
                     have_step = true;
+                    if (std::fabs(step - held) > 1e-12 * std::fabs(step)) {
+                        o.flags |= kYSetR;
+                        o.emit_dcy = step;
+                        held = step;
+                    } else {
+                        step = held;
+                    }
                 }
             }
             prev = c;
             have_prev = true;
+        }
+    }
+    // a sweep whose emissions need no recurrence holds a repeated pre-map y
+    // phase in the recurrence's factor instead of evaluating it per op
+    for (const auto &sg : g.segs) {
+        bool free_factor = true;
+        for (int o = sg.op_begin; o < sg.op_end; ++o) free_factor = free_factor && !(sops[o].flags & kYSetR);
+        if (!free_factor) continue;
+        double held = 0.0;
+        bool have = false;
+        for (int o = sg.op_begin; o < sg.op_end; ++o) {
+            SweepOp &op = sops[o];
+            if (!(op.flags & kOpPre) || op.pre_cy == 0.0) continue;
+            if (have && std::fabs(op.pre_cy - held) <= 1e-12 * std::fabs(op.pre_cy)) {
+                op.flags |= kPreYHold;
+            } else {
+                op.flags |= kPreYSet;
+                held = op.pre_cy;
+                have = true;
+            }
         }
     }
     for (auto &sg : g.segs) {

@@ -332,6 +332,58 @@ __device__ __forceinline__ void emit_thread(int key, bool uni, float vr, float v
     }
 }
 
+// v = v * a + b, the result in v's own register.  The compiler's accumulating
+// FMA form would land it in b's register instead, and the state then needs a
+// copy back on every pass of the op loop.
+__device__ __forceinline__ void fma_inplace(float &v, float a, float b) {
+    asm("v_fma_f32 %0, %0, %1, %2" : "+v"(v) : "v"(a), "v"(b));
+}
+
+// M <- T (M, m0) for one isochromat.  Each output's partial sum leaves out
+// the diagonal term, so that the last step updates the component in place
+// and no copies of the state are needed.
+__device__ __forceinline__ void rf_apply(const float4 &r0, const float4 &r1, const float4 &r2, float m0, float &mx,
+                                         float &my, float &mz) {
+    const float px = fmaf(r0.y, my, fmaf(r0.z, mz, r0.w * m0));
+    const float py = fmaf(r1.x, mx, fmaf(r1.z, mz, r1.w * m0));
+    const float pz = fmaf(r2.x, mx, fmaf(r2.y, my, r2.w * m0));
+    fma_inplace(mx, r0.x, px);
+    fma_inplace(my, r1.y, py);
+    fma_inplace(mz, r2.z, pz);
+}
+
+// Row of T applied after the transverse factor f = fr + i fi: the row acting
+// on (f (mx + i my)) equals the folded row acting on (mx + i my).
+__device__ __forceinline__ float4 fold_row(float4 r, float fr, float fi) {
+    return make_float4(fmaf(r.x, fr, r.y * fi), fmaf(r.y, fr, -(r.x * fi)), r.z, r.w);
+}
+
+// Real and imaginary parts of sum_c (mx_c + i my_c)(wr_c + i wi_c) as two
+// FMA chains per part.
+template <int NI>
+__device__ __forceinline__ void dot_phase(const float *mx, const float *my, const float *wr, const float *wi,
+                                          float &pr, float &pi) {
+    float a0 = mx[0] * wr[0], a1 = mx[1] * wr[1];
+    float b0 = mx[0] * wi[0], b1 = mx[1] * wi[1];
+    a0 = fmaf(-my[0], wi[0], a0);
+    a1 = fmaf(-my[1], wi[1], a1);
+    b0 = fmaf(my[0], wr[0], b0);
+    b1 = fmaf(my[1], wr[1], b1);
+#pragma unroll
+    for (int c = 2; c < NI; c += 2) {
+        a0 = fmaf(mx[c], wr[c], a0);
+        a1 = fmaf(mx[c + 1], wr[c + 1], a1);
+        b0 = fmaf(mx[c], wi[c], b0);
+        b1 = fmaf(mx[c + 1], wi[c + 1], b1);
+        a0 = fmaf(-my[c], wi[c], a0);
+        a1 = fmaf(-my[c + 1], wi[c + 1], a1);
+        b0 = fmaf(my[c], wr[c], b0);
+        b1 = fmaf(my[c + 1], wr[c + 1], b1);
+    }
+    pr = a0 + a1;
+    pi = b0 + b1;
+}
+
 // FP64 copy of a coordinate for a phase evaluation.  The empty asm keeps the
 // compiler from hoisting the conversion out of the op loop, which would hold
 // two registers per isochromat for the whole sweep.
@@ -413,8 +465,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
 
     for (int o = 0; o < a.n_ops; ++o) {
         const SweepOp op = load_op(a.ops, o);
+        // a factor common to the thread's isochromats followed by a transition
+        // is folded into the thread's rows of T
+        bool fold = false;
+        float fr = 1.f, fi = 0.f;
         if (op.flags & kOpPre) {
-            float fr = 1.f, fi = 0.f, e1 = 1.f;
+            float e1 = 1.f;
             if (op.pre_xtab) {
                 const float4 v = x_row(op.pre_xtab, gx_uni, gx0, gx);
                 fr = v.x;
@@ -426,10 +482,22 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 cmul(fr, fi, v.x, v.y);
             }
             if (op.pre_cy != 0.0 || (GENERAL && op.pre_cz != 0.0)) {  // per-isochromat phases
+                const bool held = (op.flags & (kPreYSet | kPreYHold)) != 0;
+                if (op.flags & kPreYSet) {
+#pragma unroll
+                    for (int c = 0; c < NI; ++c) {
+                        float s, co;
+                        sincos_rev(op.pre_cy * coord64(yv[c]), &s, &co);
+                        rr[c] = co;
+                        ri[c] = -s;
+                    }
+                }
 #pragma unroll
                 for (int c = 0; c < NI; ++c) {
                     float ar = fr, ai = fi;
-                    if (op.pre_cy != 0.0) {
+                    if (held) {
+                        cmul(ar, ai, rr[c], ri[c]);
+                    } else if (op.pre_cy != 0.0) {
                         float s, co;
                         sincos_rev(op.pre_cy * coord64(yv[c]), &s, &co);
                         cmul(ar, ai, co, -s);
@@ -444,6 +512,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     mx[c] = nx;
                     my[c] = ny;
                 }
+            } else if ((op.flags & kOpRf) && !(GENERAL && op.rf_axis == 1)) {
+                fold = true;
             } else {  // one factor for all the thread's isochromats
 #pragma unroll
                 for (int c = 0; c < NI; ++c) {
@@ -484,23 +554,21 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     r1 = gather_row(tt, 3 * g + 1);
                     r2 = gather_row(tt, 3 * g + 2);
                 }
-#pragma unroll
-                for (int c = 0; c < NI; ++c) {
-                    const float nx = fmaf(r0.x, mx[c], fmaf(r0.y, my[c], fmaf(r0.z, mz[c], r0.w * m0[c])));
-                    const float ny = fmaf(r1.x, mx[c], fmaf(r1.y, my[c], fmaf(r1.z, mz[c], r1.w * m0[c])));
-                    const float nz = fmaf(r2.x, mx[c], fmaf(r2.y, my[c], fmaf(r2.z, mz[c], r2.w * m0[c])));
-                    mx[c] = nx;
-                    my[c] = ny;
-                    mz[c] = nz;
+                if (fold) {
+                    r0 = fold_row(r0, fr, fi);
+                    r1 = fold_row(r1, fr, fi);
+                    r2 = fold_row(r2, fr, fi);
                 }
+#pragma unroll
+                for (int c = 0; c < NI; ++c) rf_apply(r0, r1, r2, m0[c], mx[c], my[c], mz[c]);
             }
         }
         if (op.flags & kOpEmit) {
             const float4 xv = x_row(op.emit_xtab, gx_uni, gx0, gx);
-            float fr = xv.x, fi = xv.y;
+            float er = xv.x, ei = xv.y;
             if (op.emit_ztab) {
                 const float2 v = gather_row(op.emit_ztab, gz);
-                cmul(fr, fi, v.x, v.y);
+                cmul(er, ei, v.x, v.y);
             }
             // y phase of this emission: evaluated, or stepped from the last one
             if (op.flags & kYDirect) {
@@ -529,7 +597,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 float vr[NI], vi[NI];
 #pragma unroll
                 for (int c = 0; c < NI; ++c) {
-                    float ar = fr, ai = fi;
+                    float ar = er, ai = ei;
                     if (yph) cmul(ar, ai, wr[c], wi[c]);
                     if (op.emit_cz != 0.0) {
                         float s, co;
@@ -549,23 +617,16 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                         emit_thread(gz, false, sr, si, act, op.gsum);
                 }
             } else {
-                // the factor of the x and z groups is common to the thread's 4
+                // the factor of the x and z groups is common to the thread's
                 // isochromats: sum (M_c w_c) first, multiply once
                 float pr, pi;
                 if (yph) {
-                    float tr[NI], ti[NI];
-#pragma unroll
-                    for (int c = 0; c < NI; ++c) {
-                        tr[c] = mx[c] * wr[c] - my[c] * wi[c];
-                        ti[c] = mx[c] * wi[c] + my[c] * wr[c];
-                    }
-                    pr = tree_sum<NI>(tr);
-                    pi = tree_sum<NI>(ti);
+                    dot_phase<NI>(mx, my, wr, wi, pr, pi);
                 } else {
                     pr = tree_sum<NI>(mx);
                     pi = tree_sum<NI>(my);
                 }
-                const float sr = fr * pr - fi * pi, si = fr * pi + fi * pr;
+                const float sr = er * pr - ei * pi, si = er * pi + ei * pr;
                 if (op.emit_axis == 0)
                     emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
                 else

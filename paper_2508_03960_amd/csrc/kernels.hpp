@@ -48,8 +48,21 @@ struct PlainArgs {
 //   its whole pre map per isochromat (kPreMz: with T1 recovery).
 // y phases of consecutive emissions follow a recurrence when their
 // coefficients step evenly (kYDirect starts it, kYSetR sets the step, kYStep
-// advances it).  Every wavefront reads the descriptor with scalar loads.
-enum { kOpPre = 1, kOpRf = 2, kOpEmit = 4, kPreMz = 8, kYDirect = 16, kYStep = 32, kYSetR = 64 };
+// advances it).  In a sweep without such recurrences the same per-isochromat
+// factor holds a repeated y phase of the pre maps instead (kPreYSet evaluates
+// it, kPreYHold reuses it).  Every wavefront reads the descriptor with scalar
+// loads.
+enum {
+    kOpPre = 1,
+    kOpRf = 2,
+    kOpEmit = 4,
+    kPreMz = 8,
+    kYDirect = 16,
+    kYStep = 32,
+    kYSetR = 64,
+    kPreYSet = 128,
+    kPreYHold = 256
+};
 struct SweepOp {
     int32_t flags;
     int32_t rf_axis;
@@ -72,8 +85,8 @@ enum { kNeedMz = 1, kNeedGx = 2, kNeedGy = 4, kNeedGz = 8, kNeedY = 16, kNeedZ =
 
 // A sweep applies ops[0 .. n_ops) in order to every isochromat while its
 // state stays in registers: one read and at most one write of M per launch.
-// The layout guarantees that the 4 isochromats of a thread share their x- and
-// z-groups.
+// The layout pads runs of equal (x-group, z-group) to multiples of 8, so the
+// 4 or 8 consecutive isochromats of a thread share their x- and z-groups.
 struct SweepArgs {
     int64_t n4;  // number of 4-isochromat chunks
     float4 *mx, *my, *mz;
