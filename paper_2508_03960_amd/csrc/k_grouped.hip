@@ -221,12 +221,13 @@ hipError_t launch_tables(const TabJob *jobs, int n_jobs, int max_n, const float4
 
 // ---------------------------------------------------------------- k_sweep
 // Waves per SIMD the register budgets are sized for: the specialized sweep
-// fits without spills at this occupancy; the general one only at 3.
+// fits its op loop without spills at 5 (96 VGPRs, with the y phases in LDS);
+// the general one at 3.
 #ifndef SWEEP_NI_FAST
 #define SWEEP_NI_FAST 8  // isochromats per thread in the fast sweep
 #endif
 #ifndef SWEEP_WAVES_FAST
-#define SWEEP_WAVES_FAST 4  // the largest occupancy without spills at 8 isochromats per thread
+#define SWEEP_WAVES_FAST 5
 #endif
 #define SWEEP_WAVES_GENERAL 3
 
@@ -456,11 +457,16 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
     // x-groups are contiguous runs in this order: is the wavefront inside one?
     const int gx0 = __builtin_amdgcn_readfirstlane(gx);
     const bool gx_uni = __all(!act || gx == gx0) != 0;
-    float wr[NI], wi[NI], rr[NI], ri[NI];  // y phase of the last emission and its per-step factor
+    // y phase of the last emission per isochromat: it changes only at
+    // emissions, so it waits in LDS (slot [c][thread]) rather than in registers
+    // that would be copied around the op loop.  (rr, ri): its per-step factor.
+    __shared__ float2 wsh[NI][256];
+    float rr[NI], ri[NI];
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
-        wr[c] = rr[c] = 1.f;
-        wi[c] = ri[c] = 0.f;
+        wsh[c][threadIdx.x] = make_float2(1.f, 0.f);
+        rr[c] = 1.f;
+        ri[c] = 0.f;
     }
 
     for (int o = 0; o < a.n_ops; ++o) {
@@ -571,6 +577,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 cmul(er, ei, v.x, v.y);
             }
             // y phase of this emission: evaluated, or stepped from the last one
+            float wr[NI], wi[NI];
             if (op.flags & kYDirect) {
 #pragma unroll
                 for (int c = 0; c < NI; ++c) {
@@ -578,10 +585,20 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     sincos_rev(op.emit_cy * coord64(yv[c]), &s, &co);
                     wr[c] = co;
                     wi[c] = -s;
+                    wsh[c][threadIdx.x] = make_float2(co, -s);
                 }
             } else if (op.flags & kYStep) {
 #pragma unroll
-                for (int c = 0; c < NI; ++c) cmul(wr[c], wi[c], rr[c], ri[c]);
+                for (int c = 0; c < NI; ++c) {
+                    const float2 w = wsh[c][threadIdx.x];
+                    wr[c] = w.x;
+                    wi[c] = w.y;
+                    cmul(wr[c], wi[c], rr[c], ri[c]);
+                    wsh[c][threadIdx.x] = make_float2(wr[c], wi[c]);
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < NI; ++c) wr[c] = wi[c] = 0.f;
             }
             if (op.flags & kYSetR) {
 #pragma unroll
