@@ -340,6 +340,11 @@ __device__ __forceinline__ void fma_inplace(float &v, float a, float b) {
     asm("v_fma_f32 %0, %0, %1, %2" : "+v"(v) : "v"(a), "v"(b));
 }
 
+// v = v * a - b in v's own register.
+__device__ __forceinline__ void fms_inplace(float &v, float a, float b) {
+    asm("v_fma_f32 %0, %0, %1, -%2" : "+v"(v) : "v"(a), "v"(b));
+}
+
 // M <- T (M, m0) for one isochromat.  Each output's partial sum leaves out
 // the diagonal term, so that the last step updates the component in place
 // and no copies of the state are needed.
@@ -355,8 +360,10 @@ __device__ __forceinline__ void rf_apply(const float4 &r0, const float4 &r1, con
 
 // Row of T applied after the transverse factor f = fr + i fi: the row acting
 // on (f (mx + i my)) equals the folded row acting on (mx + i my).
-__device__ __forceinline__ float4 fold_row(float4 r, float fr, float fi) {
-    return make_float4(fmaf(r.x, fr, r.y * fi), fmaf(r.y, fr, -(r.x * fi)), r.z, r.w);
+__device__ __forceinline__ void fold_row(float4 &r, float fr, float fi) {
+    const float t = r.y * fi, u = r.x * fi;
+    fma_inplace(r.x, fr, t);
+    fms_inplace(r.y, fr, u);
 }
 
 // Real and imaginary parts of sum_c (mx_c + i my_c)(wr_c + i wi_c) as two
@@ -518,8 +525,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     mx[c] = nx;
                     my[c] = ny;
                 }
-            } else if ((op.flags & kOpRf) && !(GENERAL && op.rf_axis == 1)) {
-                fold = true;
+            } else if (!(GENERAL && (op.flags & kOpRf) && op.rf_axis == 1)) {
+                fold = true;  // into the transition's rows, or into identity rows without one
             } else {  // one factor for all the thread's isochromats
 #pragma unroll
                 for (int c = 0; c < NI; ++c) {
@@ -534,9 +541,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 for (int c = 0; c < NI; ++c) mz[c] = fmaf(e1, mz[c] - m0[c], m0[c]);
             }
         }
-        if (op.flags & kOpRf) {
+        if ((op.flags & kOpRf) || fold) {
             const float4 *__restrict__ tt = op.ttab;
-            if (GENERAL && op.rf_axis == 1) {  // y groups: rows per isochromat
+            if (GENERAL && (op.flags & kOpRf) && op.rf_axis == 1) {  // y groups: rows per isochromat
 #pragma unroll
                 for (int c = 0; c < NI; ++c) {
                     const float4 r0 = gather_row(tt, 3 * gy[c]), r1 = gather_row(tt, 3 * gy[c] + 1),
@@ -550,7 +557,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 }
             } else {
                 float4 r0, r1, r2;
-                if (op.rf_axis == 0 && gx_uni) {
+                if (!(op.flags & kOpRf)) {
+                    r0 = make_float4(1.f, 0.f, 0.f, 0.f);
+                    r1 = make_float4(0.f, 1.f, 0.f, 0.f);
+                    r2 = make_float4(0.f, 0.f, 1.f, 0.f);
+                } else if (op.rf_axis == 0 && gx_uni) {
                     r0 = uniform_row(tt, 3 * gx0);
                     r1 = uniform_row(tt, 3 * gx0 + 1);
                     r2 = uniform_row(tt, 3 * gx0 + 2);
@@ -561,9 +572,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     r2 = gather_row(tt, 3 * g + 2);
                 }
                 if (fold) {
-                    r0 = fold_row(r0, fr, fi);
-                    r1 = fold_row(r1, fr, fi);
-                    r2 = fold_row(r2, fr, fi);
+                    fold_row(r0, fr, fi);
+                    fold_row(r1, fr, fi);
+                    fold_row(r2, fr, fi);
                 }
 #pragma unroll
                 for (int c = 0; c < NI; ++c) rf_apply(r0, r1, r2, m0[c], mx[c], my[c], mz[c]);
@@ -577,41 +588,31 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 cmul(er, ei, v.x, v.y);
             }
             // y phase of this emission: evaluated, or stepped from the last one
-            float wr[NI], wi[NI];
-            if (op.flags & kYDirect) {
-#pragma unroll
-                for (int c = 0; c < NI; ++c) {
-                    float s, co;
-                    sincos_rev(op.emit_cy * coord64(yv[c]), &s, &co);
-                    wr[c] = co;
-                    wi[c] = -s;
-                    wsh[c][threadIdx.x] = make_float2(co, -s);
-                }
-            } else if (op.flags & kYStep) {
-#pragma unroll
-                for (int c = 0; c < NI; ++c) {
-                    const float2 w = wsh[c][threadIdx.x];
-                    wr[c] = w.x;
-                    wi[c] = w.y;
-                    cmul(wr[c], wi[c], rr[c], ri[c]);
-                    wsh[c][threadIdx.x] = make_float2(wr[c], wi[c]);
-                }
-            } else {
-#pragma unroll
-                for (int c = 0; c < NI; ++c) wr[c] = wi[c] = 0.f;
-            }
-            if (op.flags & kYSetR) {
-#pragma unroll
-                for (int c = 0; c < NI; ++c) {
-                    float s, co;
-                    sincos_rev(op.emit_dcy * coord64(yv[c]), &s, &co);
-                    rr[c] = co;
-                    ri[c] = -s;
-                }
-            }
             const bool yph = (op.flags & (kYDirect | kYStep)) != 0;
+            auto y_phase = [&](float *wr, float *wi) {
+                if (op.flags & kYDirect) {
+#pragma unroll
+                    for (int c = 0; c < NI; ++c) {
+                        float s, co;
+                        sincos_rev(op.emit_cy * coord64(yv[c]), &s, &co);
+                        wr[c] = co;
+                        wi[c] = -s;
+                        wsh[c][threadIdx.x] = make_float2(co, -s);
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < NI; ++c) {
+                        const float2 w = wsh[c][threadIdx.x];
+                        wr[c] = w.x;
+                        wi[c] = w.y;
+                        cmul(wr[c], wi[c], rr[c], ri[c]);
+                        wsh[c][threadIdx.x] = make_float2(wr[c], wi[c]);
+                    }
+                }
+            };
             if (GENERAL && (op.emit_cz != 0.0 || op.emit_axis == 1)) {
-                float vr[NI], vi[NI];
+                float wr[NI], wi[NI], vr[NI], vi[NI];
+                if (yph) y_phase(wr, wi);
 #pragma unroll
                 for (int c = 0; c < NI; ++c) {
                     float ar = er, ai = ei;
@@ -638,6 +639,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 // isochromats: sum (M_c w_c) first, multiply once
                 float pr, pi;
                 if (yph) {
+                    float wr[NI], wi[NI];
+                    y_phase(wr, wi);
                     dot_phase<NI>(mx, my, wr, wi, pr, pi);
                 } else {
                     pr = tree_sum<NI>(mx);
@@ -648,6 +651,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
                 else
                     emit_thread(gz, false, sr, si, act, op.gsum);
+            }
+            if (op.flags & kYSetR) {  // step factor of the chain this emission starts
+#pragma unroll
+                for (int c = 0; c < NI; ++c) {
+                    float s, co;
+                    sincos_rev(op.emit_dcy * coord64(yv[c]), &s, &co);
+                    rr[c] = co;
+                    ri[c] = -s;
+                }
             }
         }
     }
