@@ -32,6 +32,12 @@ COMMON = [
 ]
 
 
+# Per-source flags.  The sweep's group-sum atomics are issued by one lane after
+# a DPP reduction (or by run-end lanes at distinct addresses); the compiler's
+# wave-level atomic combining would only add a loop around each of them.
+EXTRA = {"k_grouped.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]}
+
+
 def hipcc() -> str:
     for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if c and os.path.exists(c):
@@ -42,7 +48,7 @@ def hipcc() -> str:
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [hipcc()] + lang + COMMON + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc()] + lang + COMMON + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile of {src} failed:\n{r.stdout}\n{r.stderr}")
