@@ -104,6 +104,7 @@ struct gbs_ctx {
     int64_t Kint = 0;  // isochromats in the padded group-sorted layout (multiple of 8)
     int64_t Kpad = 0;
     DevBuf perm, inv, xi, yi, zi, t1i, t2i, dfi, m0i, gid[3], gtab[3], gcount[3], ms[3];
+    DevBuf m_final;  // (mx, my, mz, 0) per layout slot, written by the last sweep of a run
     // per-simulate buffers
     DevBuf tabs, gsum, partial, jobs, samp, flag, state64;
     std::vector<char> host_jobs;  // kept alive until the next call
@@ -190,7 +191,7 @@ int gbs_destroy(gbs_ctx *ctx) {
     DevBuf *bufs[] = {&ctx->d_wave, &ctx->d_adc, &ctx->perm, &ctx->inv, &ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i,
                       &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->tabs, &ctx->gsum, &ctx->partial, &ctx->jobs,
                       &ctx->samp, &ctx->flag, &ctx->surr, &ctx->adj_ops, &ctx->adj_samp, &ctx->adj_ckpt,
-                      &ctx->adj_sig, &ctx->adj_grf, &ctx->adj_gt, &ctx->state64};
+                      &ctx->adj_sig, &ctx->adj_grf, &ctx->adj_gt, &ctx->state64, &ctx->m_final};
     for (DevBuf *b : bufs) b->release();
     for (int a = 0; a < 3; ++a) {
         ctx->gid[a].release();
@@ -341,6 +342,7 @@ int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
     }
     HIPCHK(launch_zero_padding(Kpad, ctx->perm.as<int32_t>(), ctx->m0i.as<float>(), ctx->stream));
     for (int a = 0; a < 3; ++a) ALLOC(ctx->ms[a], 4 * Kpad);
+    ALLOC(ctx->m_final, 16 * Kpad);
     HIPCHK(hipStreamSynchronize(ctx->stream));
     cleanup();
     ctx->axes = axes;
@@ -925,8 +927,11 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     // ---- sweeps of grouped ops (plain stepping between them) ----------------
     float *mx = ctx->ms[0].as<float>(), *my = ctx->ms[1].as<float>(), *mz = ctx->ms[2].as<float>();
     const int64_t Kint = ctx->Kint;
-    HIPCHK(launch_init_state(Kint, ctx->Kpad, ctx->perm.as<int32_t>(), m_init, m_init ? m_init + K : nullptr,
-                             m_init ? m_init + 2 * K : nullptr, ctx->m0i.as<float>(), mx, my, mz, ctx->stream));
+    // the default initial state (0, 0, M0) is made by the first sweep itself
+    const bool fresh = !m_init && !g.exec.empty() && g.exec.front().first == 0;
+    if (!fresh)
+        HIPCHK(launch_init_state(Kint, ctx->Kpad, ctx->perm.as<int32_t>(), m_init, m_init ? m_init + K : nullptr,
+                                 m_init ? m_init + 2 * K : nullptr, ctx->m0i.as<float>(), mx, my, mz, ctx->stream));
     SweepArgs base{};
     base.n4 = Kint / 4;
     base.mx = (float4 *)mx;
@@ -951,7 +956,10 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     int timed = 0;
     double bytes = 0.0, flops = 0.0;
     const SweepOp *dev_ops = (const SweepOp *)(jb + g.o_sweep);
-    for (const auto &item : g.exec) {
+    // a run that ends with a state-writing sweep leaves its state in m_final
+    const bool final4 = !g.exec.empty() && g.exec.back().first == 0 && g.segs[g.exec.back().second].write_m;
+    for (size_t e = 0; e < g.exec.size(); ++e) {
+        const auto &item = g.exec[e];
         if (item.first == 0) {
             const GroupedPlan::Seg &sg = g.segs[item.second];
             SweepArgs a = base;
@@ -959,6 +967,12 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
             a.n_ops = sg.op_end - sg.op_begin;
             a.need = sg.need;
             a.write_m = sg.write_m ? 1 : 0;
+            a.m_final = (final4 && e + 1 == g.exec.size()) ? ctx->m_final.as<float4>() : nullptr;
+            a.fresh = (fresh && e == 0) ? 1 : 0;
+            if (a.m_final || a.fresh) {  // the whole state is written, so all of it is held
+                a.need |= kNeedMz;
+                a.write_m = 1;
+            }
             bytes += sg.bytes_per_iso * (double)K;
             flops += sg.flops_per_iso * (double)K;
             if (profile) HIPCHK(hipEventRecord(ctx->pev[2 * timed], ctx->stream));
@@ -985,8 +999,12 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     HIPCHK(launch_adc_lin((const AdcLinJob *)(jb + g.o_adclin), g.n_adclin, g.max_adclin_groups, sig_out,
                           ctx->stream));
     if (st) HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
-    HIPCHK(launch_gather_state(K, ctx->inv.as<int32_t>(), mx, my, mz, m_out, m_out + K, m_out + 2 * K,
-                                ctx->stream));
+    if (final4)
+        HIPCHK(launch_gather_state4(K, ctx->inv.as<int32_t>(), ctx->m_final.as<float4>(), m_out, m_out + K,
+                                    m_out + 2 * K, ctx->stream));
+    else
+        HIPCHK(launch_gather_state(K, ctx->inv.as<int32_t>(), mx, my, mz, m_out, m_out + K, m_out + 2 * K,
+                                    ctx->stream));
     if (st) {
         st->n_passes = g.n_ops;
         st->n_sweeps = (int64_t)g.segs.size();

@@ -448,11 +448,18 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
     if (act) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            ld4(a.mx, i4 + q, mx + 4 * q);
-            ld4(a.my, i4 + q, my + 4 * q);
+            if (!a.fresh) {
+                ld4(a.mx, i4 + q, mx + 4 * q);
+                ld4(a.my, i4 + q, my + 4 * q);
+            }
             if (need & kNeedMz) {
-                ld4(a.mz, i4 + q, mz + 4 * q);
                 ld4(a.m0, i4 + q, m0 + 4 * q);
+                if (a.fresh) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) mz[4 * q + c] = m0[4 * q + c];
+                } else {
+                    ld4(a.mz, i4 + q, mz + 4 * q);
+                }
             }
             if (need & kNeedGy) ld4i(a.gid_y, i4 + q, gy + 4 * q);
             if (need & kNeedY) ld4(a.yv, i4 + q, yv + 4 * q);
@@ -663,7 +670,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
             }
         }
     }
-    if (act && a.write_m) {
+    if (act && a.write_m && a.m_final) {
+#pragma unroll
+        for (int c = 0; c < NI; ++c) a.m_final[4 * i4 + c] = make_float4(mx[c], my[c], mz[c], 0.f);
+    } else if (act && a.write_m) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             a.mx[i4 + q] = make_float4(mx[4 * q], mx[4 * q + 1], mx[4 * q + 2], mx[4 * q + 3]);
@@ -791,6 +801,27 @@ __global__ void k_gather_state(int64_t K, const int32_t *__restrict__ inv, const
         oy[k] = my[i];
         oz[k] = mz[i];
     }
+}
+
+__global__ __launch_bounds__(256) void k_gather_state4(int64_t K, const int32_t *__restrict__ inv,
+                                                      const float4 *__restrict__ m4, float *ox, float *oy,
+                                                      float *oz) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < K) {
+        const float4 v = m4[inv[k]];
+        ox[k] = v.x;
+        oy[k] = v.y;
+        oz[k] = v.z;
+    }
+}
+
+hipError_t launch_gather_state4(int64_t K, const int32_t *inv, const float4 *m4, float *ox, float *oy, float *oz,
+                                hipStream_t st) {
+    const int64_t g = (K + 255) / 256;  // one index per thread
+    if (g > 0x7fffffff) return hipErrorInvalidValue;
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_state4, dim3((unsigned)g), dim3(256), 0, st, K, inv, m4, ox, oy, oz);
+    return hipGetLastError();
 }
 
 hipError_t launch_gather_state(int64_t K, const int32_t *inv, const float *mx, const float *my, const float *mz,

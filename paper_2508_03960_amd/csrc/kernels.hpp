@@ -97,6 +97,13 @@ struct SweepArgs {
     int32_t n_ops;
     int32_t need;
     int32_t write_m;
+    // Final sweep of a run: when set, the state is written here as
+    // (mx, my, mz, 0) per layout slot instead of into mx / my / mz, so that
+    // the copy into the caller's order reads one 16-byte row per isochromat.
+    float4 *m_final;
+    // First sweep of a run from the default state (0, 0, M0): nothing is read
+    // from mx / my / mz.
+    int32_t fresh;
 };
 
 // ---- tables ---------------------------------------------------------------
@@ -160,6 +167,8 @@ hipError_t launch_init_state(int64_t K, int64_t Kpad, const int32_t *perm, const
                              float *my, float *mz, hipStream_t st);
 hipError_t launch_gather_state(int64_t K, const int32_t *inv, const float *mx, const float *my, const float *mz,
                                float *ox, float *oy, float *oz, hipStream_t st);
+hipError_t launch_gather_state4(int64_t K, const int32_t *inv, const float4 *m4, float *ox, float *oy, float *oz,
+                                hipStream_t st);
 
 // ---- grouping ---------------------------------------------------------------
 hipError_t launch_validate_phantom(int64_t K, const PhantomPtrs &ph, int *bad, hipStream_t st);
