@@ -511,6 +511,18 @@ static bool matches_pulse(const gbs_ctx *ctx, const RfJob &r) {
            std::memcmp(&s.gz[o], m->gz.data(), n * sizeof(float)) == 0;
 }
 
+// Algorithmic HBM bytes per isochromat of one sweep launch: the state it
+// reads (none when it starts from (0, 0, M0)), M0 and the per-isochromat
+// arrays its ops need, and the state it writes (a 16-byte row in the last
+// launch of a run).
+static double sweep_bytes_per_iso(int need, bool write_m, bool fresh, bool final_rows) {
+    double b = fresh ? 0.0 : 8.0;
+    if (need & kNeedMz) b += fresh ? 4.0 : 8.0;
+    b += 4.0 * (!!(need & kNeedGx) + !!(need & kNeedGy) + !!(need & kNeedGz) + !!(need & kNeedY) + !!(need & kNeedZ));
+    if (write_m) b += final_rows ? 16.0 : ((need & kNeedMz) ? 12.0 : 8.0);
+    return b;
+}
+
 static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
     GroupedPlan &g = ctx->gp;
     const HostSeq &s = ctx->seq;
@@ -845,13 +857,7 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
             }
         }
     }
-    for (auto &sg : g.segs) {
-        const int n = sg.need;
-        double b = 8.0 + ((n & kNeedMz) ? 8.0 : 0.0);
-        b += 4.0 * (!!(n & kNeedGx) + !!(n & kNeedGy) + !!(n & kNeedGz) + !!(n & kNeedY) + !!(n & kNeedZ));
-        if (sg.write_m) b += (n & kNeedMz) ? 12.0 : 8.0;
-        sg.bytes_per_iso = b;
-    }
+    for (auto &sg : g.segs) sg.bytes_per_iso = sweep_bytes_per_iso(sg.need, sg.write_m, false, false);
     g.n_ops = (int64_t)sops.size();
 
     g.n_rf = (int)rj.size();
@@ -973,7 +979,7 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
                 a.need |= kNeedMz;
                 a.write_m = 1;
             }
-            bytes += sg.bytes_per_iso * (double)K;
+            bytes += sweep_bytes_per_iso(a.need, a.write_m != 0, a.fresh != 0, a.m_final != nullptr) * (double)K;
             flops += sg.flops_per_iso * (double)K;
             if (profile) HIPCHK(hipEventRecord(ctx->pev[2 * timed], ctx->stream));
             HIPCHK(launch_sweep(a, ctx->stream));
