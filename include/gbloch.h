@@ -299,14 +299,16 @@ int gbs_set_surrogate(gbs_ctx *ctx, gbs_mlp *m, float tol, int32_t n_check, uint
  *
  * The forward pass stores the state every `every` ops (one op = one raster
  * step or one relaxation block; 3 * K floats per checkpoint, owned by the
- * context); the backward pass steps each segment again from its checkpoint.
+ * context); the backward pass steps each segment again from its checkpoint,
+ * keeping the state every 8 ops of the segment (3 * K * every / 8 floats,
+ * also owned by the context).
  */
 
 /* Forward pass.  cls: device int32[K] in [0, n_classes), n_classes <= 64;
  * t1c, t2c: device float[n_classes] (s, > 0); rf_param: device float[2*n_rf]
  * interleaved (re, im) in T, n_rf <= 3072; param_blocks: host int32 list of
- * RF block indices whose n_steps equals n_rf; every: multiple of 16 in
- * [16, 256].  sig_out: device double[2*total_samples] (re, im).  The context
+ * RF block indices whose n_steps equals n_rf; every: multiple of 8 in
+ * [8, 256].  sig_out: device double[2*total_samples] (re, im).  The context
  * keeps cls, t1c, t2c and rf_param (views) for the backward pass: keep them
  * alive and unchanged until then.  Synchronizes.
  * Errors: GBS_E_STATE (no phantom/sequence), GBS_E_INVALID (limits, block

@@ -7,8 +7,8 @@
 namespace gbs {
 
 constexpr int kAdjWG = 256;          // isochromats per workgroup (one per thread)
-constexpr int kAdjSub = 16;          // ops per recomputed sub-segment (states in registers)
-constexpr int kAdjMaxEvery = 256;    // largest checkpoint interval (16 sub-checkpoints in LDS)
+constexpr int kAdjSub = 8;           // ops per recomputed sub-segment (states in registers)
+constexpr int kAdjMaxEvery = 256;    // largest checkpoint interval
 constexpr int kAdjMaxClasses = 64;
 constexpr int kAdjMaxRf = 3072;      // parameter-pulse samples (gradient accumulated in LDS, 24 KiB)
 
@@ -38,6 +38,7 @@ struct AdjArgs {
     double dt;
     int32_t every;       // checkpoint interval in ops (multiple of kAdjSub, <= kAdjMaxEvery)
     float *ckpt;         // [n_ckpt][3][K]: state at boundaries 0, every, 2 every, ...
+    float *sub;          // backward: [every / kAdjSub][3][K] sub-checkpoints of the current segment
     int32_t N;           // samples
     double2 *sig_part;   // forward: [grid][N] per-workgroup sums
     const double2 *w;    // backward: cotangent of the signal, [N] (d/dRe, d/dIm)

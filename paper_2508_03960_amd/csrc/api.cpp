@@ -119,7 +119,7 @@ struct gbs_ctx {
     uint64_t surr_seed = 0;
     DevBuf surr;
     // gradient of the signal (adjoint): flattened ops, checkpoints, partials
-    DevBuf adj_ops, adj_samp, adj_ckpt, adj_sig, adj_grf, adj_gt;
+    DevBuf adj_ops, adj_samp, adj_ckpt, adj_sub, adj_sig, adj_grf, adj_gt;
     AdjArgs adj{};
     bool adj_ready = false;
     bool pplan_valid = false;
@@ -190,7 +190,7 @@ int gbs_destroy(gbs_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     DevBuf *bufs[] = {&ctx->d_wave, &ctx->d_adc, &ctx->perm, &ctx->inv, &ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i,
                       &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->tabs, &ctx->gsum, &ctx->partial, &ctx->jobs,
-                      &ctx->samp, &ctx->flag, &ctx->surr, &ctx->adj_ops, &ctx->adj_samp, &ctx->adj_ckpt,
+                      &ctx->samp, &ctx->flag, &ctx->surr, &ctx->adj_ops, &ctx->adj_samp, &ctx->adj_ckpt, &ctx->adj_sub,
                       &ctx->adj_sig, &ctx->adj_grf, &ctx->adj_gt, &ctx->state64, &ctx->m_final};
     for (DevBuf *b : bufs) b->release();
     for (int a = 0; a < 3; ++a) {
@@ -1121,7 +1121,7 @@ extern "C" int gbs_adj_forward(gbs_ctx *ctx, const int32_t *cls, int32_t n_class
         return fail(ctx, GBS_E_INVALID, "n_classes must be in [1, 64]");
     if (n_rf < 1 || n_rf > kAdjMaxRf) return fail(ctx, GBS_E_INVALID, "n_rf must be in [1, 3072]");
     if (every < kAdjSub || every > kAdjMaxEvery || every % kAdjSub)
-        return fail(ctx, GBS_E_INVALID, "checkpoint interval must be a multiple of 16 in [16, 256]");
+        return fail(ctx, GBS_E_INVALID, "checkpoint interval must be a multiple of 8 in [8, 256]");
     if (n_param_blocks < 0 || (n_param_blocks > 0 && !param_blocks))
         return fail(ctx, GBS_E_INVALID, "bad parameter block list");
     const HostSeq &s = ctx->seq;
@@ -1181,6 +1181,7 @@ extern "C" int gbs_adj_forward(gbs_ctx *ctx, const int32_t *cls, int32_t n_class
     ALLOC(ctx->adj_ops, sizeof(AdjOp) * (size_t)std::max<int64_t>(n_ops, 1));
     ALLOC(ctx->adj_samp, sizeof(int32_t) * samp.size());
     ALLOC(ctx->adj_ckpt, sizeof(float) * 3 * (size_t)K * (size_t)std::max<int64_t>(n_ckpt, 1));
+    ALLOC(ctx->adj_sub, sizeof(float) * 3 * (size_t)K * (size_t)(every / kAdjSub));
     ALLOC(ctx->adj_sig, sizeof(double2) * (size_t)grid * (size_t)std::max<int64_t>(N, 1));
     ALLOC(ctx->adj_grf, sizeof(float2) * (size_t)grid * (size_t)n_rf);
     ALLOC(ctx->adj_gt, sizeof(double2) * (size_t)grid * (size_t)n_classes);
@@ -1214,6 +1215,7 @@ extern "C" int gbs_adj_forward(gbs_ctx *ctx, const int32_t *cls, int32_t n_class
     a.dt = s.dt;
     a.every = every;
     a.ckpt = ctx->adj_ckpt.as<float>();
+    a.sub = ctx->adj_sub.as<float>();
     a.N = (int32_t)N;
     a.sig_part = ctx->adj_sig.as<double2>();
     a.grf_part = ctx->adj_grf.as<float2>();

@@ -241,8 +241,9 @@ __device__ __forceinline__ void back_step(const AdjOp &op, const AdjArgs &a, con
     }
 }
 
-__global__ __launch_bounds__(kAdjWG) void k_adj_backward(AdjArgs a) {
-    __shared__ float sub[kAdjMaxEvery / kAdjSub][3][kAdjWG];
+// 4 waves per SIMD: 128 VGPRs (a few spills outside the op loops).  LDS holds
+// 25 KiB of accumulators per workgroup, so registers set the occupancy.
+__global__ __launch_bounds__(kAdjWG) __attribute__((amdgpu_waves_per_eu(4))) void k_adj_backward(AdjArgs a) {
     __shared__ double tg[kAdjMaxClasses][2];
     __shared__ float2 rfg[kAdjMaxRf];
     const int64_t k = (int64_t)blockIdx.x * kAdjWG + threadIdx.x;
@@ -265,21 +266,27 @@ __global__ __launch_bounds__(kAdjWG) void k_adj_backward(AdjArgs a) {
             M[1] = c[a.K];
             M[2] = c[2 * a.K];
         }
-        for (int p = p0; p < p1; ++p) {  // each thread touches only its own LDS column
-            if (((p - p0) & (kAdjSub - 1)) == 0) {
-                const int j = (p - p0) / kAdjSub;
-                sub[j][0][tid] = M[0];
-                sub[j][1][tid] = M[1];
-                sub[j][2][tid] = M[2];
+        // sub-checkpoints in HBM, one column per thread (coalesced), so that
+        // LDS holds only the gradient accumulators and occupancy is set by
+        // registers
+        for (int p = p0; p < p1; ++p) {
+            if (act && ((p - p0) & (kAdjSub - 1)) == 0) {
+                float *c = a.sub + (int64_t)((p - p0) / kAdjSub) * 3 * a.K + k;
+                c[0] = M[0];
+                c[a.K] = M[1];
+                c[2 * a.K] = M[2];
             }
             step(a.ops[p], a, s, M, v);
         }
         const int n_sub = (p1 - p0 + kAdjSub - 1) / kAdjSub;
         for (int sb = n_sub - 1; sb >= 0; --sb) {
             const int q0 = p0 + sb * kAdjSub, cnt = min(kAdjSub, p1 - q0);
-            M[0] = sub[sb][0][tid];
-            M[1] = sub[sb][1][tid];
-            M[2] = sub[sb][2][tid];
+            if (act) {
+                const float *c = a.sub + (int64_t)sb * 3 * a.K + k;
+                M[0] = c[0];
+                M[1] = c[a.K];
+                M[2] = c[2 * a.K];
+            }
             float V[kAdjSub][3];
 #pragma unroll
             for (int i = 0; i < kAdjSub; ++i)

@@ -121,6 +121,26 @@ def test_edge_cases(gb):
     check_case(gb, "empty", ph, empty)
 
 
+def test_run_boundaries(gb):
+    """Grouped runs that start and end with per-isochromat stepping (a
+    mixed-gradient RF block first, an ADC-with-RF block last): the layout
+    state is initialised by its own kernel and copied out from the
+    per-component arrays, instead of by the first and last sweeps."""
+    ph = synth.tiny_phantom(nx=7, ny=6, nz=3, n_classes=2, df_levels=2)
+    sb = SeqBuilder(1e-6, "plain-ends")
+    sb.rf(synth.sinc_pulse(40, 1e-6, 0.5), (0.004, 0, 0.01))
+    sb.relax(5e-4, (2e-6, -1e-6, 3e-6))
+    sb.rf(synth.sinc_pulse(60, 1e-6, 1.0), (0, 0, 0.012))
+    sb.adc(24, (0.01, 0, 0), 3 * np.arange(8) + 1)
+    sb.adc(20, (0.01, 0, 0), [0, 5, 19], b1=np.full(20, 1e-6 + 0j))
+    seq = sb.build()
+    check_case(gb, "plain-ends", ph, seq)
+    _, _, st = run_gpu(gb, ph, seq, gb.GBS_GROUPED)
+    assert st["n_fallback"] >= 2 and st["n_sweeps"] >= 1, st
+    rng = np.random.default_rng(5)
+    check_case(gb, "plain-ends+m_init", ph, seq, modes=("grouped",), m_init=rng.uniform(-0.5, 0.5, (3, ph.K)))
+
+
 def test_grouped_is_repeatable(gb):
     ph, seq = synth.workload("fse-small")
     M1, s1, _ = run_gpu(gb, ph, seq, gb.GBS_GROUPED)
