@@ -7,8 +7,8 @@
 //                  for relaxation blocks), the samples of Eq. 6, and the state
 //                  at every `every`-th op boundary (checkpoints, SoA in HBM).
 //  k_adj_backward  segments in reverse: from each checkpoint the segment is
-//                  stepped again, keeping a sub-checkpoint every 16 ops in
-//                  LDS; each 16-op sub-segment is stepped once more with its
+//                  stepped again, keeping a sub-checkpoint every 8 ops in
+//                  HBM; each 8-op sub-segment is stepped once more with its
 //                  rotated states in registers and then walked backward:
 //                      lambda_p = (D_p R_p)^T lambda_{p+1} + cotangent at p.
 //  k_adj_finalize  sums the per-workgroup partials in FP64.
@@ -61,6 +61,41 @@ __device__ __forceinline__ void rot_coeffs(float q, float &S, float &C, float &D
     }
 }
 
+// Op descriptors, the parameter pulse, the sample lists and the signal
+// cotangent are read-only during a launch and indexed by wave-uniform values:
+// they are read through the constant address space, so that they arrive in
+// scalar registers instead of through vector loads the op loop must wait for.
+typedef const __attribute__((address_space(4))) uint64_t *const_u64_ptr;
+static_assert(sizeof(AdjOp) % 8 == 0, "AdjOp is read as 64-bit words");
+
+__device__ __forceinline__ AdjOp load_op(const AdjOp *ops, int p) {
+    uint64_t w[sizeof(AdjOp) / 8];
+    const const_u64_ptr q = (const_u64_ptr)(ops + p);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(AdjOp) / 8); ++i) w[i] = q[i];
+    AdjOp r;
+    __builtin_memcpy(&r, w, sizeof(AdjOp));
+    return r;
+}
+
+// Plain-old-data element i of p, as 64-bit (or one 32-bit) scalar words.
+template <typename T>
+__device__ __forceinline__ T uniform_load(const T *p, int64_t i) {
+    T r;
+    if constexpr (sizeof(T) % 8 == 0) {
+        uint64_t w[sizeof(T) / 8];
+        const const_u64_ptr q = (const_u64_ptr)(p + i);
+#pragma unroll
+        for (int j = 0; j < (int)(sizeof(T) / 8); ++j) w[j] = q[j];
+        __builtin_memcpy(&r, w, sizeof(T));
+    } else {
+        static_assert(sizeof(T) == 4, "32-bit or multiple-of-64-bit elements");
+        const uint32_t w = ((const __attribute__((address_space(4))) uint32_t *)(p + i))[0];
+        __builtin_memcpy(&r, &w, sizeof(T));
+    }
+    return r;
+}
+
 struct Iso {
     float x, y, z, m0;
     double df;
@@ -96,7 +131,7 @@ __device__ __forceinline__ StepCoef raster_coef(const AdjOp &op, const AdjArgs &
     StepCoef r;
     float bx = op.b1r, by = op.b1i;
     if (op.param >= 0) {
-        const float2 p = a.rfp[op.param];
+        const float2 p = uniform_load(a.rfp, op.param);
         bx = p.x;
         by = p.y;
     }
@@ -166,8 +201,8 @@ __global__ __launch_bounds__(kAdjWG) void k_adj_forward(AdjArgs a) {
             c[a.K] = M[1];
             c[2 * a.K] = M[2];
         }
-        const int q1 = a.sstart[p + 1];
-        for (int q = a.sstart[p]; q < q1; ++q) {  // samples at this boundary (Eq. 6)
+        const int q1 = uniform_load(a.sstart, p + 1);
+        for (int q = uniform_load(a.sstart, p); q < q1; ++q) {  // samples at this boundary (Eq. 6)
             const float sx = wave_sum_lane63(M[0]), sy = wave_sum_lane63(M[1]);
             if (lane == 63) {
                 ws[wave][0] = sx;
@@ -181,20 +216,20 @@ __global__ __launch_bounds__(kAdjWG) void k_adj_forward(AdjArgs a) {
                     re += ws[w][0];
                     im += ws[w][1];
                 }
-                a.sig_part[(int64_t)blockIdx.x * a.N + a.sid[q]] = make_double2(re, im);
+                a.sig_part[(int64_t)blockIdx.x * a.N + uniform_load(a.sid, q)] = make_double2(re, im);
             }
             __syncthreads();
         }
         if (p == a.n_ops) break;
-        step(a.ops[p], a, s, M, v);
+        step(load_op(a.ops, p), a, s, M, v);
     }
 }
 
 // -------------------------------------------------------------- backward
 __device__ __forceinline__ void add_cotangent(const AdjArgs &a, int p, float *lam) {
-    const int q1 = a.sstart[p + 1];
-    for (int q = a.sstart[p]; q < q1; ++q) {
-        const double2 w = a.w[a.sid[q]];
+    const int q1 = uniform_load(a.sstart, p + 1);
+    for (int q = uniform_load(a.sstart, p); q < q1; ++q) {
+        const double2 w = uniform_load(a.w, uniform_load(a.sid, q));
         lam[0] += (float)w.x;
         lam[1] += (float)w.y;
     }
@@ -276,7 +311,7 @@ __global__ __launch_bounds__(kAdjWG) __attribute__((amdgpu_waves_per_eu(4))) voi
                 c[a.K] = M[1];
                 c[2 * a.K] = M[2];
             }
-            step(a.ops[p], a, s, M, v);
+            step(load_op(a.ops, p), a, s, M, v);
         }
         const int n_sub = (p1 - p0 + kAdjSub - 1) / kAdjSub;
         for (int sb = n_sub - 1; sb >= 0; --sb) {
@@ -290,11 +325,11 @@ __global__ __launch_bounds__(kAdjWG) __attribute__((amdgpu_waves_per_eu(4))) voi
             float V[kAdjSub][3];
 #pragma unroll
             for (int i = 0; i < kAdjSub; ++i)
-                if (i < cnt) step(a.ops[q0 + i], a, s, M, V[i]);
+                if (i < cnt) step(load_op(a.ops, q0 + i), a, s, M, V[i]);
 #pragma unroll
             for (int i = kAdjSub - 1; i >= 0; --i) {
                 if (i < cnt) {
-                    back_step(a.ops[q0 + i], a, s, V[i], lam, t, rfg, lane);
+                    back_step(load_op(a.ops, q0 + i), a, s, V[i], lam, t, rfg, lane);
                     add_cotangent(a, q0 + i, lam);
                 }
             }
