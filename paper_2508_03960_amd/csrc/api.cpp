@@ -110,6 +110,10 @@ struct gbs_ctx {
     std::vector<char> host_jobs;  // kept alive until the next call
     std::vector<double2> host_samp;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    // second stream of the context (default priority): the copy of the final
+    // state into the caller's order runs on it beside the ADC evaluation
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     std::vector<hipEvent_t> pev;  // GBS_PROFILE: one (start, stop) pair per pass launch
     GroupedPlan gp;
     // learned surrogate (not owned)
@@ -180,6 +184,12 @@ int gbs_create(gbs_ctx **out, int device, void *stream) {
             return GBS_E_HIP;
         }
     }
+    if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming) != hipSuccess) {
+        gbs_destroy(ctx);
+        return GBS_E_HIP;
+    }
     *out = ctx;
     return GBS_OK;
 }
@@ -202,6 +212,12 @@ int gbs_destroy(gbs_ctx *ctx) {
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : ctx->pev) (void)hipEventDestroy(e);
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->join) (void)hipEventDestroy(ctx->join);
+    if (ctx->side) {
+        (void)hipStreamSynchronize(ctx->side);
+        (void)hipStreamDestroy(ctx->side);
+    }
     delete ctx;
     return GBS_OK;
 }
@@ -999,18 +1015,24 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     *n_timed = timed;
     if (st) HIPCHK(hipEventRecord(ctx->ev[2], ctx->stream));
 
+    // ---- final state into the caller's order, on the side stream ------------
+    HIPCHK(hipEventRecord(ctx->fork, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+    if (final4)
+        HIPCHK(launch_gather_state4(K, ctx->inv.as<int32_t>(), ctx->m_final.as<float4>(), m_out, m_out + K,
+                                    m_out + 2 * K, ctx->side));
+    else
+        HIPCHK(launch_gather_state(K, ctx->inv.as<int32_t>(), mx, my, mz, m_out, m_out + K, m_out + 2 * K,
+                                    ctx->side));
+    HIPCHK(hipEventRecord(ctx->join, ctx->side));
+
     // ---- ADC samples from the group sums (Eq. 8, Eq. 10) --------------------
     HIPCHK(launch_adc_eval((const AdcJobDev *)(jb + g.o_adc), g.n_adc, g.max_adc_groups, g.max_adc_samples,
                            sig_out, ctx->stream));
     HIPCHK(launch_adc_lin((const AdcLinJob *)(jb + g.o_adclin), g.n_adclin, g.max_adclin_groups, sig_out,
                           ctx->stream));
     if (st) HIPCHK(hipEventRecord(ctx->ev[3], ctx->stream));
-    if (final4)
-        HIPCHK(launch_gather_state4(K, ctx->inv.as<int32_t>(), ctx->m_final.as<float4>(), m_out, m_out + K,
-                                    m_out + 2 * K, ctx->stream));
-    else
-        HIPCHK(launch_gather_state(K, ctx->inv.as<int32_t>(), mx, my, mz, m_out, m_out + K, m_out + 2 * K,
-                                    ctx->stream));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->join, 0));
     if (st) {
         st->n_passes = g.n_ops;
         st->n_sweeps = (int64_t)g.segs.size();
