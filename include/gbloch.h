@@ -120,8 +120,12 @@ typedef struct gbs_stats {
 typedef struct gbs_ctx gbs_ctx;
 
 /*
- * Create a context on HIP `device`; all work is enqueued on `stream`
+ * Create a context on HIP `device`; work is enqueued on `stream`
  * (a hipStream_t; NULL = the default stream).  *out receives the context.
+ * The context also owns one stream of its own at the default priority.  A
+ * grouped simulation forks the copy of the final state onto it with an event
+ * and makes `stream` wait for it, so work enqueued later on `stream` sees
+ * every result.
  * Errors: GBS_E_INVALID (out null, bad device), GBS_E_HIP.
  */
 int gbs_create(gbs_ctx **out, int device, void *stream);
