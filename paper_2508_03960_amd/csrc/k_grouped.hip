@@ -16,6 +16,11 @@
 //              FP64 atomics.
 //  k_adc_eval  every ADC sample from the group sums (Eq. 8 with Eq. 10), FP64
 //              phase reduced modulo one turn, FP64 accumulation.
+//  k_init_state, k_gather_state4, k_gather_state
+//              the state into the group-sorted layout (when the first sweep
+//              does not start it from (0, 0, M0) itself) and back into the
+//              caller's order (from the last sweep's 16-byte rows, or from the
+//              per-component arrays after plain stepping).
 #include "device_math.hpp"
 #include "kernels.hpp"
 
@@ -296,8 +301,10 @@ __device__ __forceinline__ float4 x_row(const float4 *tab, bool gx_uni, int gx0,
 }
 
 // Group sums of (vr, vi) keyed by the thread's group id: one DPP-reduced
-// atomic pair when the wavefront has one key, else a segmented scan over
-// the lanes (keys are sorted runs) and one atomic pair per run end.
+// atomic pair when the wavefront has one key, two masked DPP reductions when
+// it has two (about a third of the wavefronts straddle one run boundary),
+// else a segmented scan over the lanes (keys are sorted runs) and one atomic
+// pair per run end.
 __device__ __forceinline__ void emit_thread(int key, bool uni, float vr, float vi, bool act,
                                             double2 *__restrict__ gsum) {
     if (uni) {
@@ -310,6 +317,25 @@ __device__ __forceinline__ void emit_thread(int key, bool uni, float vr, float v
         return;
     }
     const int k = act ? key : -1;
+    // Two runs in the wavefront (or one run and the grid's inactive tail):
+    // two masked DPP reductions instead of the segmented scan.
+    const int k0 = __builtin_amdgcn_readfirstlane(k), k1 = __builtin_amdgcn_readlane(k, 63);
+    if (__all(k == k0 || k == k1)) {
+        const bool in0 = k == k0;
+        const float ar = wave_sum_lane63(in0 ? vr : 0.f), ai = wave_sum_lane63(in0 ? vi : 0.f);
+        const float br = wave_sum_lane63(in0 ? 0.f : vr), bi = wave_sum_lane63(in0 ? 0.f : vi);
+        if (__lane_id() == 63) {
+            if (k0 >= 0) {
+                group_add(&gsum[k0].x, (double)ar);
+                group_add(&gsum[k0].y, (double)ai);
+            }
+            if (k1 >= 0 && k1 != k0) {
+                group_add(&gsum[k1].x, (double)br);
+                group_add(&gsum[k1].y, (double)bi);
+            }
+        }
+        return;
+    }
     const int lane = __lane_id();
     const int kp = __shfl_up(k, 1);
     int head = (lane == 0) || (kp != k);
