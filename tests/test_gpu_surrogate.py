@@ -180,6 +180,31 @@ def test_surrogate_in_grouped_fse_falls_back(env):
     m.close()
 
 
+def test_surrogate_without_matching_pulse(env):
+    """A sequence none of whose RF waveforms is the network's pulse (EPI
+    plays only a 90-degree excitation) keeps every exact transition: the
+    surrogate flag changes nothing, bit for bit."""
+    gb, torch, pulse = env
+    m = make_mlp(gb, pulse)
+    ph, seq = synth.workload("epi-small")
+    out = []
+    for flags in (0, gb.GBS_SURROGATE):
+        sim = gb.Simulator(0)
+        sim.set_phantom(ph)
+        sim.set_sequence(seq)
+        sim.build_groups()
+        gb.set_surrogate(sim, m, tol=1e9, n_check=16, seed=5)
+        M, sig, st = sim.simulate(gb.GBS_GROUPED, flags=flags, stats=True)
+        torch.cuda.synchronize()
+        out.append((M.cpu().numpy(), sig.cpu().numpy().copy(), st))
+        sim.close()
+    m.close()
+    say(f"[gpu] surrogate: EPI-small with no matching pulse: n_surrogate={out[1][2]['n_surrogate']}")
+    assert out[1][2]["n_surrogate"] == 0 and out[1][2]["n_surrogate_fallback"] == 0
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.allclose(out[0][1], out[1][1], rtol=0, atol=1e-12 * np.max(np.abs(out[0][1])))
+
+
 def test_trained_surrogate_gain(env):
     """What the network buys: one transition costs an MLP evaluation instead of
     a 3000-step FP64 composition.  Trained on 2M transitions of the 180-degree
