@@ -369,6 +369,8 @@ class Adjoint:
     def backward(self, grad_sig):
         """grad_sig: (N, 2) cotangent of the signal.  Returns (grad_rf (n_rf, 2)
         float32, grad_t1 (C,) float64, grad_t2 (C,) float64)."""
+        if self._held is None:  # no forward pass yet: the library reports the call order
+            self.sim._check(lib.gbs_adj_backward(self.sim._h, None, None, None, None))
         rf, t1c, _ = self._held
         dev = self.sim.device
         g = grad_sig.detach().to(dev, torch.float64).contiguous()
