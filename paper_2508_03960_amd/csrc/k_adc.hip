@@ -39,10 +39,17 @@ __global__ __launch_bounds__(kAdcLinWG) void k_adc_lin(const AdcLinJob *__restri
         double ar[kAdcLinChunk], ai[kAdcLinChunk];
 #pragma unroll
         for (int k = 0; k < kAdcLinChunk; ++k) ar[k] = ai[k] = 0.0;
-        if (cnt > 0) {
+        if (cnt > 0 && g0 + slice < g1) {
+            // the next group's table row and sum are loaded one iteration ahead
+            float4 p_next = j.gtab[g0 + slice];  // (coord, T1, T2, df)
+            double2 S_next = j.gsum[g0 + slice];
             for (int g = g0 + slice; g < g1; g += n_slices) {
-                const float4 p = j.gtab[g];  // (coord, T1, T2, df)
-                const double2 S = j.gsum[g];
+                const float4 p = p_next;
+                const double2 S = S_next;
+                if (g + n_slices < g1) {
+                    p_next = j.gtab[g + n_slices];
+                    S_next = j.gsum[g + n_slices];
+                }
                 float s0, c0, sd, cd;
                 sincos_rev(cyc_n0 * (double)p.x + (double)p.w * tau_n0, &s0, &c0);
                 sincos_rev(j.dcyc * (double)p.x + (double)p.w * j.dtau, &sd, &cd);
