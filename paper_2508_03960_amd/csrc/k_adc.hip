@@ -20,7 +20,9 @@ constexpr int kAdcLinChunk = 16;      // samples per thread
 constexpr int kAdcLinGroups = 1024;   // groups per workgroup
 
 __global__ __launch_bounds__(kAdcLinWG) void k_adc_lin(const AdcLinJob *__restrict__ jobs, double *__restrict__ sig_base) {
-    __shared__ double2 red[kAdcLinWG * kAdcLinChunk];  // [slice][sample]: 64 KiB
+    // [slice][sample] for the lower half of the slices (32 KiB): the upper
+    // half adds into it, so that the LDS allows 4 workgroups per CU
+    __shared__ double2 red[kAdcLinWG * kAdcLinChunk / 2];
     const AdcLinJob j = jobs[blockIdx.y];
     const int g0 = blockIdx.x * kAdcLinGroups;
     if (g0 >= j.n_groups) return;  // uniform over the workgroup
@@ -70,13 +72,25 @@ __global__ __launch_bounds__(kAdcLinWG) void k_adc_lin(const AdcLinJob *__restri
                 }
             }
         }
+        const int half = n_slices / 2;
+        double2 *mine = red + (slice % half) * per_pass + chunk * kAdcLinChunk;
+        if (slice < half) {
 #pragma unroll
-        for (int k = 0; k < kAdcLinChunk; ++k) red[slice * per_pass + chunk * kAdcLinChunk + k] = make_double2(ar[k], ai[k]);
+            for (int k = 0; k < kAdcLinChunk; ++k) mine[k] = make_double2(ar[k], ai[k]);
+        }
+        __syncthreads();
+        if (slice >= half) {  // each slot has exactly one adding thread
+#pragma unroll
+            for (int k = 0; k < kAdcLinChunk; ++k) {
+                const double2 v = mine[k];
+                mine[k] = make_double2(v.x + ar[k], v.y + ai[k]);
+            }
+        }
         __syncthreads();
         for (int n = threadIdx.x; n < per_pass; n += kAdcLinWG) {
             if (base + n < j.n_samples) {
                 double sr = 0.0, si = 0.0;
-                for (int sl = 0; sl < n_slices; ++sl) {
+                for (int sl = 0; sl < half; ++sl) {
                     const double2 v = red[sl * per_pass + n];
                     sr += v.x;
                     si += v.y;
