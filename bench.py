@@ -316,11 +316,17 @@ def main():
                       "stepped_steps": S_epi, "phases_ms": {k: st_e[-1][k] for k in
                                                             ("ms_prepare", "ms_passes", "ms_adc_eval")}}
         log(f"EPI grouped: {sec_e * 1e3:.2f} ms/step")
+        M_epi = m_out.cpu().numpy()
+        s_epi = sig_epi.cpu().numpy()
         if not args.no_plain:
             sec_p, _ = timed_runs(sim, gb, gb.GBS_PLAIN, 1, 0, m_out, sig_epi)
+            s_pl = sig_epi.cpu().numpy()
             out["epi"].update({"plain_ms": sec_p * 1e3, "plain_iso_steps_per_s": K * S_epi / sec_p,
-                               "speedup_grouped_vs_plain": sec_p / sec_e})
-            log(f"EPI plain: {sec_p * 1e3:.1f} ms")
+                               "speedup_grouped_vs_plain": sec_p / sec_e,
+                               "grouped_vs_plain_fp64": {
+                                   "max_abs_dM": float(np.max(np.abs(M_epi - m_out.cpu().numpy()))),
+                                   "rel_signal": float(np.linalg.norm(s_epi - s_pl) / np.linalg.norm(s_pl))}})
+            log(f"EPI plain: {sec_p * 1e3:.1f} ms; grouped vs plain {out['epi']['grouped_vs_plain_fp64']}")
 
     # ---- plain FSE: first shot (1/16 of the sequence) at full K -------------------------
     if not args.no_plain:
@@ -342,6 +348,13 @@ def main():
         out["fse"]["max_abs_dM_vs_oracle_sampled"] = float(np.max(np.abs(M_fse[:, idx] - M_ref)))
         out["fse"]["oracle_sample_isochromats"] = int(idx.size)
         log(f"cpu baseline {cb}")
+        if not args.no_epi:  # the EPI run's sampled error as well (256 isochromats)
+            import oracle
+            import synth
+            idx_e = synth.random_subset_indices(K, 256, seed=8)
+            M_ref_e, _ = oracle.simulate(ph.subset(idx_e), epi)
+            out["epi"]["max_abs_dM_vs_oracle_sampled"] = float(np.max(np.abs(M_epi[:, idx_e] - M_ref_e)))
+            out["epi"]["oracle_sample_isochromats"] = int(idx_e.size)
     print(json.dumps(out), flush=True)
     sim.close()
 
