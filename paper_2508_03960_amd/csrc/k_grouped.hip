@@ -616,10 +616,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
         if (op.flags & kOpEmit) {
             const float4 xv = x_row(op.emit_xtab, gx_uni, gx0, gx);
             float er = xv.x, ei = xv.y;
-            if (op.emit_ztab) {
-                const float2 v = gather_row(op.emit_ztab, gz);
-                cmul(er, ei, v.x, v.y);
-            }
+            // the z row is gathered first and used last, so that the gather's
+            // latency overlaps the y phase and the sum (fast sweep)
+            float2 zf = make_float2(1.f, 0.f);
+            if (op.emit_ztab) zf = gather_row(op.emit_ztab, gz);
+            if (GENERAL && op.emit_ztab) cmul(er, ei, zf.x, zf.y);
             // y phase of this emission: evaluated, or stepped from the last one
             const bool yph = (op.flags & (kYDirect | kYStep)) != 0;
             auto y_phase = [&](float *wr, float *wi) {
@@ -679,6 +680,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     pr = tree_sum<NI>(mx);
                     pi = tree_sum<NI>(my);
                 }
+                if (!GENERAL && op.emit_ztab) cmul(er, ei, zf.x, zf.y);
                 const float sr = er * pr - ei * pi, si = er * pi + ei * pr;
                 if (op.emit_axis == 0)
                     emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
