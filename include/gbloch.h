@@ -18,8 +18,14 @@
  *     grouped isochromats (Sec. 2.3, 2.4): isochromats sharing
  *     (r_a, T1, T2, dB0) share one combined transition T (Eq. 7) for an
  *     a-only subsequence, and with-ADC subsequences evolve per-group sums
- *     (Eq. 8-10) instead of every member.  Both modes give the same result up
- *     to floating-point rounding.
+ *     (Eq. 8-10) instead of every member;
+ *   - GBS_CACHED is the conventional accelerated method of Sec. 2.2 that the
+ *     grouped update is compared with: every isochromat gets its own combined
+ *     transition T_k (Eq. 7) per distinct with-RF waveform, composed at its
+ *     first occurrence and cached (dynamic caching) for the later ones, and
+ *     with-ADC subsequences without RF are evaluated at every sample directly
+ *     from the block-start state by Eq. (4), (5), (6).
+ *   All modes give the same result up to floating-point rounding.
  *
  * Units: metres, seconds, tesla, T/m, T*s/m; off-resonance in Hz
  * (B_z gains df / (gamma/2pi)); gamma/2pi = 42.577478518 MHz/T.
@@ -59,6 +65,7 @@ extern "C" {
 /* ---- simulation modes and flags -------------------------------------- */
 #define GBS_PLAIN 0
 #define GBS_GROUPED 1
+#define GBS_CACHED 2
 #define GBS_ASYNC 1u      /* enqueue on the context stream and return; no final synchronize */
 #define GBS_PLAIN_FP32 2u /* GBS_PLAIN: step in FP32 instead of FP64 (faster to state, less exact) */
 #define GBS_PROFILE 4u    /* time every sweep launch with HIP events (gbs_stats.pass_kernel_ms) */
@@ -115,6 +122,13 @@ typedef struct gbs_stats {
     int64_t n_surrogate;   /* GBS_SURROGATE: distinct RF transitions taken from the network */
     int64_t n_surrogate_fallback; /* ... of which failed the spot check and were composed exactly */
     double surrogate_residual;    /* largest spot-check residual max|T_mlp - T_exact| (0 if none) */
+    int64_t n_rf_cached;   /* GBS_CACHED: with-RF blocks applied as per-isochromat transitions
+                              (n_distinct_rf of them composed, the rest read from the cache) */
+    int64_t n_adc_direct;  /* GBS_CACHED: with-ADC blocks evaluated per isochromat and sample */
+    double cache_bytes;    /* GBS_CACHED: device bytes of the transition cache (48 per isochromat and entry) */
+    double ms_compose;     /* GBS_CACHED + GBS_PROFILE: launches composing and caching transitions */
+    double ms_apply;       /* ... launches applying cached transitions or closed-form maps */
+    double ms_adc_direct;  /* ... direct ADC launches (with their sample finalize) */
 } gbs_stats;
 
 typedef struct gbs_ctx gbs_ctx;
@@ -170,11 +184,19 @@ int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, co
 int gbs_build_groups(gbs_ctx *ctx, uint32_t axes);
 
 /*
- * Run the sequence on the phantom.  mode = GBS_PLAIN or GBS_GROUPED.
+ * Run the sequence on the phantom.  mode = GBS_PLAIN, GBS_GROUPED or
+ * GBS_CACHED (GBS_CACHED needs no groups).
  * m_init: device float[3*K] SoA (Mx, My, Mz) or NULL for (0, 0, M0).
  * m_out: device float[3*K] SoA final magnetization (may alias m_init).
  * sig_out: device double[2*total_samples], interleaved (re, im), Eq. (6).
  * stats: host, nullable.  Without GBS_ASYNC the call synchronizes the stream.
+ * GBS_PLAIN and GBS_CACHED keep the state between launches in FP64 (3 * K
+ * doubles owned by the context).  GBS_CACHED also owns the transition cache:
+ * 3 float4 rows (A_i0, A_i1, A_i2, b_i) of K per distinct with-RF waveform
+ * (bit-identical B1 and gradients), 48 * K bytes each, recomposed by every
+ * call; the state and cache allocations fail with GBS_E_NOMEM when they do
+ * not fit.  With-ADC blocks that play RF are stepped per isochromat in every
+ * mode.
  * Errors: GBS_E_STATE (no phantom/sequence; GROUPED without valid X groups),
  * GBS_E_INVALID (null outputs, bad mode), GBS_E_NOMEM, GBS_E_HIP.
  */
@@ -200,6 +222,19 @@ int gbs_plan_summary(const gbs_block *blocks, int64_t n_blocks, const float *rf_
                      const float *rf_im, const float *gx, const float *gy, const float *gz,
                      int64_t total_steps, const int32_t *adc_idx, int64_t total_samples, double dt,
                      uint32_t axes, int64_t out[8]);
+
+/*
+ * Host-only planning summary of GBS_CACHED (no device needed):
+ * out[0..5] = with-RF blocks applied as per-isochromat transitions, distinct
+ * transitions composed (cache entries), with-ADC blocks evaluated directly,
+ * direct-ADC launches (at most 256 samples each), blocks stepped per
+ * isochromat (RF during ADC), RF blocks with B1 == 0 folded into closed forms.
+ * Same validation as gbs_set_sequence.
+ */
+int gbs_plan_cached_summary(const gbs_block *blocks, int64_t n_blocks, const float *rf_re,
+                            const float *rf_im, const float *gx, const float *gy, const float *gz,
+                            int64_t total_steps, const int32_t *adc_idx, int64_t total_samples,
+                            double dt, int64_t out[6]);
 
 
 /* ==== learned RF-transition surrogate ==================================

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libgbloch.so")
 GBS_OK, GBS_E_INVALID, GBS_E_STATE, GBS_E_HIP, GBS_E_NOMEM = 0, -1, -2, -3, -4
 GBS_BLOCK_RF, GBS_BLOCK_ADC, GBS_BLOCK_RELAX = 1, 2, 3
 GBS_AX_X, GBS_AX_Y, GBS_AX_Z = 1, 2, 4
-GBS_PLAIN, GBS_GROUPED = 0, 1
+GBS_PLAIN, GBS_GROUPED, GBS_CACHED = 0, 1, 2
 GBS_ASYNC = 1
 GBS_PLAIN_FP32 = 2
 GBS_PROFILE = 4
@@ -28,6 +28,7 @@ GBS_MLP_PARAMS = 35340
 
 EXPORTED = ("gbs_create", "gbs_destroy", "gbs_set_phantom", "gbs_set_sequence", "gbs_build_groups",
             "gbs_simulate", "gbs_get_info", "gbs_last_error", "gbs_strerror", "gbs_plan_summary",
+            "gbs_plan_cached_summary",
             "gbs_mlp_create", "gbs_mlp_destroy", "gbs_mlp_last_error", "gbs_mlp_set_pulse",
             "gbs_mlp_set_norm", "gbs_mlp_get_params", "gbs_mlp_set_params", "gbs_mlp_exact",
             "gbs_mlp_infer", "gbs_mlp_loss_grad", "gbs_mlp_train", "gbs_set_surrogate",
@@ -58,7 +59,10 @@ class gbs_stats(ctypes.Structure):
                 ("pass_bytes", ctypes.c_double), ("pass_kernel_ms", ctypes.c_double),
                 ("n_sweeps", ctypes.c_int64), ("pass_flops", ctypes.c_double),
                 ("n_surrogate", ctypes.c_int64), ("n_surrogate_fallback", ctypes.c_int64),
-                ("surrogate_residual", ctypes.c_double)]
+                ("surrogate_residual", ctypes.c_double), ("n_rf_cached", ctypes.c_int64),
+                ("n_adc_direct", ctypes.c_int64), ("cache_bytes", ctypes.c_double),
+                ("ms_compose", ctypes.c_double), ("ms_apply", ctypes.c_double),
+                ("ms_adc_direct", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -86,6 +90,7 @@ def _load(path=LIB_PATH):
         "gbs_last_error": ([P], ctypes.c_char_p),
         "gbs_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "gbs_plan_summary": ([P, I64, P, P, P, P, P, I64, P, I64, D, U32, P], ctypes.c_int),
+        "gbs_plan_cached_summary": ([P, I64, P, P, P, P, P, I64, P, I64, D, P], ctypes.c_int),
         "gbs_mlp_create": ([ctypes.POINTER(P), ctypes.c_int, P, ctypes.c_uint64], ctypes.c_int),
         "gbs_mlp_destroy": ([P], ctypes.c_int),
         "gbs_mlp_last_error": ([P], ctypes.c_char_p),
@@ -155,6 +160,21 @@ def gbs_plan_summary(seq, axes=GBS_AX_X | GBS_AX_Y | GBS_AX_Z):
     if rc != GBS_OK:
         raise GbsError(rc, "gbs_plan_summary rejected the sequence")
     keys = ("rf_grouped", "adc_grouped", "fallback", "b1zero", "passes", "emit_only", "distinct_rf", "relax")
+    return dict(zip(keys, list(out)))
+
+
+def gbs_plan_cached_summary(seq):
+    """Host-only counts of what GBS_CACHED runs (see gbloch.h)."""
+    import numpy as np
+    blocks = sequence_blocks(seq)
+    w = [_host(a, np.float32) for a in (seq.rf_re, seq.rf_im, seq.gx, seq.gy, seq.gz)]
+    adc = _host(seq.adc_idx, np.int32)
+    out = (ctypes.c_int64 * 6)()
+    rc = lib.gbs_plan_cached_summary(blocks, seq.n_blocks, *(a.ctypes.data for a in w), seq.total_steps,
+                                     adc.ctypes.data, seq.total_samples, float(seq.dt), out)
+    if rc != GBS_OK:
+        raise GbsError(rc, "gbs_plan_cached_summary rejected the sequence")
+    keys = ("rf_cached", "entries", "adc_direct", "adc_launches", "fallback", "b1zero")
     return dict(zip(keys, list(out)))
 
 

@@ -16,6 +16,7 @@
 
 #include "adc.hpp"
 #include "adj.hpp"
+#include "cached.hpp"
 #include "consts.hpp"
 #include "gbloch.h"
 #include "groups.hpp"
@@ -128,6 +129,15 @@ struct gbs_ctx {
     bool adj_ready = false;
     bool pplan_valid = false;
     Plan pplan;  // plain schedule
+    // conventional method with per-isochromat transition caching (GBS_CACHED):
+    // schedule, per-sample tables of its direct ADC operations (row offset per
+    // operation), the cache itself (3 float4 rows of K per entry) and, with
+    // GBS_PROFILE, the kind of each timed launch
+    bool cplan_valid = false;
+    Plan cplan;
+    std::vector<int64_t> csamp_off;
+    DevBuf csamp, cache;
+    std::vector<int> cprof_kind;
 };
 
 static int fail(gbs_ctx *c, int code, const std::string &msg) {
@@ -202,7 +212,8 @@ int gbs_destroy(gbs_ctx *ctx) {
     DevBuf *bufs[] = {&ctx->d_wave, &ctx->d_adc, &ctx->perm, &ctx->inv, &ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i,
                       &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->tabs, &ctx->gsum, &ctx->partial, &ctx->jobs,
                       &ctx->samp, &ctx->flag, &ctx->surr, &ctx->adj_ops, &ctx->adj_samp, &ctx->adj_ckpt, &ctx->adj_sub,
-                      &ctx->adj_sig, &ctx->adj_grf, &ctx->adj_gt, &ctx->state64, &ctx->m_final};
+                      &ctx->adj_sig, &ctx->adj_grf, &ctx->adj_gt, &ctx->state64, &ctx->m_final,
+                      &ctx->csamp, &ctx->cache};
     for (DevBuf *b : bufs) b->release();
     for (int a = 0; a < 3; ++a) {
         ctx->gid[a].release();
@@ -262,6 +273,7 @@ int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, co
     ctx->has_seq = false;
     ctx->gp.valid = false;
     ctx->pplan_valid = false;
+    ctx->cplan_valid = false;
     ctx->adj_ready = false;
     copy_sequence(ctx->seq, blocks, n_blocks, rf_re, rf_im, gx, gy, gz, total_steps, adc_idx, total_samples, dt);
     ctx->cls = classify(ctx->seq);
@@ -399,6 +411,29 @@ int gbs_plan_summary(const gbs_block *blocks, int64_t n_blocks, const float *rf_
     out[5] = p.n_emit_only;
     out[6] = (int64_t)p.rf.size();
     out[7] = p.n_relax;
+    return GBS_OK;
+}
+
+int gbs_plan_cached_summary(const gbs_block *blocks, int64_t n_blocks, const float *rf_re, const float *rf_im,
+                            const float *gx, const float *gy, const float *gz, int64_t total_steps,
+                            const int32_t *adc_idx, int64_t total_samples, double dt, int64_t out[6]) {
+    if (!out) return GBS_E_INVALID;
+    std::string err;
+    int rc = validate_sequence(blocks, n_blocks, total_steps, adc_idx, total_samples, dt, err);
+    if (rc != GBS_OK) return rc;
+    if (total_steps > 0 && (!rf_re || !rf_im || !gx || !gy || !gz)) return GBS_E_INVALID;
+    HostSeq s;
+    copy_sequence(s, blocks, n_blocks, rf_re, rf_im, gx, gy, gz, total_steps, adc_idx, total_samples, dt);
+    Plan p = plan_cached(s, classify(s));
+    int64_t adc_launches = 0;
+    for (const Op &op : p.ops)
+        if (op.kind == 3) ++adc_launches;
+    out[0] = p.n_rf_cached;
+    out[1] = (int64_t)p.rf.size();
+    out[2] = p.n_adc_direct;
+    out[3] = adc_launches;
+    out[4] = p.n_fallback;
+    out[5] = p.n_b1zero;
     return GBS_OK;
 }
 
@@ -1046,12 +1081,170 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     return GBS_OK;
 }
 
+// The conventional accelerated method (Sec. 2.2): per-isochromat combined
+// transitions with dynamic caching, direct evaluation of with-ADC blocks.
+// The state lives in FP64 (state64) from the first operation that writes it;
+// until then operations read m_init or (0, 0, M0).  The last operation always
+// writes m_out.
+static int run_cached(gbs_ctx *ctx, const float *m_init, float *m_out, double *sig_out, bool profile,
+                      gbs_stats *st, int *n_timed) {
+    const int64_t K = ctx->K;
+    const double dt = ctx->seq.dt;
+    if (!ctx->cplan_valid) {
+        ctx->cplan = plan_cached(ctx->seq, ctx->cls);
+        const Plan &plan = ctx->cplan;
+        // sample n of a direct ADC operation: c_n = gamma_bar (m_pre + m(s_n)),
+        // tau_n = tau_pre + s_n dt, with m(s) the block's gradient moment over
+        // its first s raster steps
+        std::vector<double4> tab;
+        ctx->csamp_off.assign(plan.ops.size(), -1);
+        int64_t mom_block = -1;
+        std::vector<double> mom[3];
+        for (size_t oi = 0; oi < plan.ops.size(); ++oi) {
+            const Op &op = plan.ops[oi];
+            if (op.kind != 3) continue;
+            const CachedOp &c = op.cached;
+            const gbs_block &b = ctx->seq.blocks[c.block];
+            if (c.block != mom_block) {
+                const std::vector<float> *g[3] = {&ctx->seq.gx, &ctx->seq.gy, &ctx->seq.gz};
+                for (int a = 0; a < 3; ++a) {
+                    mom[a].assign((size_t)b.n_steps + 1, 0.0);
+                    for (int64_t j = 0; j < b.n_steps; ++j)
+                        mom[a][j + 1] = mom[a][j] + (double)(*g[a])[b.step_offset + j] * dt;
+                }
+                mom_block = c.block;
+            }
+            ctx->csamp_off[oi] = (int64_t)tab.size();
+            for (int32_t n = c.sample_lo; n < c.sample_hi; ++n) {
+                const int32_t sn = ctx->seq.adc_idx[b.sample_offset + n];
+                tab.push_back(make_double4(kGammaBar * (c.pre.m[0] + mom[0][sn]), kGammaBar * (c.pre.m[1] + mom[1][sn]),
+                                           kGammaBar * (c.pre.m[2] + mom[2][sn]), c.pre.tau + (double)sn * dt));
+            }
+        }
+        ALLOC(ctx->csamp, sizeof(double4) * std::max<size_t>(tab.size(), 1));
+        if (!tab.empty())
+            HIPCHK(hipMemcpy(ctx->csamp.p, tab.data(), sizeof(double4) * tab.size(), hipMemcpyHostToDevice));
+        ctx->cplan_valid = true;
+    }
+    const Plan &plan = ctx->cplan;
+    const size_t n_entries = plan.rf.size();
+    ALLOC(ctx->state64, sizeof(double) * 3 * (size_t)K);
+    if (n_entries) ALLOC(ctx->cache, sizeof(float4) * 3 * (size_t)K * n_entries);
+    const int pgrid = plain_grid(K), agrid = direct_adc_grid(K);
+    ALLOC(ctx->partial, sizeof(double2) * (size_t)std::max(pgrid, agrid) * kMaxSamplesPerLaunch);
+    if (profile) {
+        const size_t need = 2 * plan.ops.size();
+        while (ctx->pev.size() < need) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            ctx->pev.push_back(e);
+        }
+    }
+    ctx->cprof_kind.clear();
+    double *s64 = ctx->state64.as<double>();
+    const float *mi_x = m_init, *mi_y = m_init ? m_init + K : nullptr, *mi_z = m_init ? m_init + 2 * K : nullptr;
+    bool from_init = true;
+    int timed = 0;
+    for (size_t oi = 0; oi < plan.ops.size(); ++oi) {
+        const Op &op = plan.ops[oi];
+        if (profile) HIPCHK(hipEventRecord(ctx->pev[2 * timed], ctx->stream));
+        if (op.kind == 1) {  // RF during ADC: plain FP64 stepping
+            PlainArgs a = step_args(ctx, op.step, ctx->ph, K, from_init ? mi_x : nullptr, from_init ? mi_y : nullptr,
+                                    from_init ? mi_z : nullptr, nullptr, nullptr, nullptr);
+            if (!from_init) {
+                a.min64_x = s64;
+                a.min64_y = s64 + K;
+                a.min64_z = s64 + 2 * K;
+            }
+            a.mout64_x = s64;
+            a.mout64_y = s64 + K;
+            a.mout64_z = s64 + 2 * K;
+            HIPCHK(launch_plain(a, ctx->cls[op.step.block].has_b1, false, pgrid, ctx->stream));
+            if (a.n_samples > 0) {
+                const gbs_block &b = ctx->seq.blocks[op.step.block];
+                HIPCHK(launch_plain_finalize(ctx->partial.as<double2>(), pgrid, a.n_samples,
+                                             sig_out + 2 * (b.sample_offset + op.step.sample_lo), ctx->stream));
+            }
+            from_init = false;
+        } else if (op.kind == 3) {  // direct ADC: reads the state, writes samples
+            const CachedOp &c = op.cached;
+            const gbs_block &b = ctx->seq.blocks[c.block];
+            DirectAdcArgs a{};
+            a.K = K;
+            a.ph = ctx->ph;
+            if (from_init) {
+                a.min_x = mi_x;
+                a.min_y = mi_y;
+            } else {
+                a.s64_in = s64;
+            }
+            a.samp = ctx->csamp.as<double4>() + ctx->csamp_off[oi];
+            a.n_samples = c.sample_hi - c.sample_lo;
+            a.partial = ctx->partial.as<double2>();
+            HIPCHK(launch_direct_adc(a, agrid, ctx->stream));
+            HIPCHK(launch_plain_finalize(ctx->partial.as<double2>(), agrid, a.n_samples,
+                                         sig_out + 2 * (b.sample_offset + c.sample_lo), ctx->stream));
+        } else {  // 2: cached transition (composed at first use); 4: final map
+            const CachedOp &c = op.cached;
+            CachedArgs a{};
+            a.K = K;
+            a.ph = ctx->ph;
+            if (from_init) {
+                a.min_x = mi_x;
+                a.min_y = mi_y;
+                a.min_z = mi_z;
+            } else {
+                a.s64_in = s64;
+            }
+            if (op.kind == 4) {
+                a.mout_x = m_out;
+                a.mout_y = m_out + K;
+                a.mout_z = m_out + 2 * K;
+            } else {
+                a.s64_out = s64;
+            }
+            a.has_pre = c.has_pre ? 1 : 0;
+            a.pre_tau = c.pre.tau;
+            for (int i = 0; i < 3; ++i) a.pre_cyc[i] = kGammaBar * c.pre.m[i];
+            a.dt = dt;
+            a.gdt = kTwoPi * kGammaBar * dt;
+            int mode = kCacheMap;
+            if (op.kind == 2) {
+                const gbs_block &b = ctx->seq.blocks[c.block];
+                a.cache = ctx->cache.as<float4>() + 3 * (size_t)K * (size_t)c.entry;
+                mode = c.compose ? kCacheCompose : kCacheApply;
+                a.wave = ctx->d_wave.as<StepW>() + b.step_offset;
+                a.n_steps = (int32_t)b.n_steps;
+            }
+            HIPCHK(launch_cached(a, mode, ctx->stream));
+            from_init = false;
+        }
+        if (profile) {
+            HIPCHK(hipEventRecord(ctx->pev[2 * timed + 1], ctx->stream));
+            ++timed;
+            // 0: compose, 1: cached transition or map, 2: direct ADC, 3: stepped
+            ctx->cprof_kind.push_back(op.kind == 1 ? 3 : op.kind == 3 ? 2 : (op.kind == 2 && op.cached.compose) ? 0 : 1);
+        }
+    }
+    *n_timed = timed;
+    if (st) {
+        st->n_rf_cached = plan.n_rf_cached;
+        st->n_adc_direct = plan.n_adc_direct;
+        st->n_fallback = plan.n_fallback;
+        st->n_distinct_rf = (int64_t)n_entries;
+        st->n_b1zero = plan.n_b1zero;
+        st->cache_bytes = (double)(sizeof(float4) * 3 * (size_t)K * n_entries);
+    }
+    return GBS_OK;
+}
+
 extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float *m_init, float *m_out,
                             double *sig_out, gbs_stats *stats) {
     if (!ctx) return GBS_E_INVALID;
     if (!ctx->has_ph) return fail(ctx, GBS_E_STATE, "gbs_simulate before gbs_set_phantom");
     if (!ctx->has_seq) return fail(ctx, GBS_E_STATE, "gbs_simulate before gbs_set_sequence");
-    if (mode != GBS_PLAIN && mode != GBS_GROUPED) return fail(ctx, GBS_E_INVALID, "mode must be GBS_PLAIN or GBS_GROUPED");
+    if (mode != GBS_PLAIN && mode != GBS_GROUPED && mode != GBS_CACHED)
+        return fail(ctx, GBS_E_INVALID, "mode must be GBS_PLAIN, GBS_GROUPED or GBS_CACHED");
     if (!m_out || (ctx->seq.total_samples > 0 && !sig_out)) return fail(ctx, GBS_E_INVALID, "null output");
     if (mode == GBS_GROUPED && !ctx->groups_valid)
         return fail(ctx, GBS_E_STATE, "GBS_GROUPED needs gbs_build_groups on the current phantom");
@@ -1069,8 +1262,9 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
         HIPCHK(launch_fill_f64(sig_out, 2 * ctx->seq.total_samples, ctx->stream));
     const bool profile = (flags & GBS_PROFILE) != 0;
     int n_timed = 0;
-    int rc = mode == GBS_PLAIN ? run_plain(ctx, m_init, m_out, sig_out, (flags & GBS_PLAIN_FP32) != 0, stats)
-                               : run_grouped(ctx, m_init, m_out, sig_out, profile, use_surr, stats, &n_timed);
+    int rc = mode == GBS_PLAIN    ? run_plain(ctx, m_init, m_out, sig_out, (flags & GBS_PLAIN_FP32) != 0, stats)
+             : mode == GBS_CACHED ? run_cached(ctx, m_init, m_out, sig_out, profile, stats, &n_timed)
+                                  : run_grouped(ctx, m_init, m_out, sig_out, profile, use_surr, stats, &n_timed);
     if (rc != GBS_OK) return rc;
     if (stats) HIPCHK(hipEventRecord(ctx->ev[4], ctx->stream));
     if (!(flags & GBS_ASYNC) || stats || profile) {
@@ -1083,6 +1277,16 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
         stats->ms_total = ms;
         if (mode == GBS_PLAIN) {
             stats->ms_stepped = ms;
+        } else if (mode == GBS_CACHED) {
+            double sum[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int i = 0; i < n_timed; ++i) {
+                HIPCHK(hipEventElapsedTime(&ms, ctx->pev[2 * i], ctx->pev[2 * i + 1]));
+                sum[ctx->cprof_kind[i]] += ms;
+            }
+            stats->ms_compose = sum[0];
+            stats->ms_apply = sum[1];
+            stats->ms_adc_direct = sum[2];
+            stats->ms_stepped = sum[3];
         } else {
             HIPCHK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
             stats->ms_prepare = ms;

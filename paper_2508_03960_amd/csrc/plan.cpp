@@ -179,8 +179,9 @@ static uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
     return h;
 }
 
-// Index of the combined transition for RF block b applied per group of `axis`;
-// identical waveforms (B1 and the active gradient, bit for bit) share one.
+// Index of the combined transition for RF block b applied per group of `axis`
+// (-1: per isochromat); identical waveforms (B1 and all three gradients, bit
+// for bit; the hash covers B1 and the active gradient) share one.
 static int rf_lookup(Plan &p, std::vector<uint64_t> &hashes, const HostSeq &s, int64_t b, int axis,
                      int gtype) {
     const gbs_block &k = s.blocks[b];
@@ -288,6 +289,67 @@ Plan plan_grouped(const HostSeq &s, const std::vector<BlockClass> &cls, uint32_t
     flush();
     p.final_pass = P.any();
     p.final_map = P;
+    return p;
+}
+
+Plan plan_cached(const HostSeq &s, const std::vector<BlockClass> &cls) {
+    Plan p;
+    std::vector<uint64_t> hashes;
+    Map P;  // B1 = 0 maps not yet applied to the stored state
+    for (size_t bi = 0; bi < s.blocks.size(); ++bi) {
+        const int64_t b = (int64_t)bi;
+        const gbs_block &k = s.blocks[bi];
+        const BlockClass &c = cls[bi];
+        if (k.type == GBS_BLOCK_RELAX) {
+            P.add(k.tau, k.moment);
+            ++p.n_relax;
+            continue;
+        }
+        const double dur = (double)k.n_steps * s.dt;
+        if (!c.has_b1) {
+            if (k.type == GBS_BLOCK_RF) {
+                ++p.n_b1zero;
+            } else {
+                // static isochromats, no RF: every sample from the block-start state
+                for (int32_t a = 0; a < k.n_samples; a += kMaxSamplesPerLaunch) {
+                    Op op;
+                    op.kind = 3;
+                    op.cached.block = b;
+                    op.cached.has_pre = P.any();
+                    op.cached.pre = P;
+                    op.cached.sample_lo = a;
+                    op.cached.sample_hi = std::min(k.n_samples, a + kMaxSamplesPerLaunch);
+                    p.ops.push_back(op);
+                }
+                ++p.n_adc_direct;
+            }
+            P.add(dur, c.moment);
+            continue;
+        }
+        if (k.type == GBS_BLOCK_RF) {
+            const size_t before = p.rf.size();
+            Op op;
+            op.kind = 2;
+            op.cached.block = b;
+            op.cached.has_pre = P.any();
+            op.cached.pre = P;
+            op.cached.entry = rf_lookup(p, hashes, s, b, -1, GT_MIXED);
+            op.cached.compose = p.rf.size() > before;
+            p.ops.push_back(op);
+            P = Map{};
+            ++p.n_rf_cached;
+            continue;
+        }
+        // RF during an ADC block: stepped per isochromat
+        add_step_ops(p, s, b, P, P.any());
+        P = Map{};
+        ++p.n_fallback;
+    }
+    Op op;
+    op.kind = 4;
+    op.cached.has_pre = P.any();
+    op.cached.pre = P;
+    p.ops.push_back(op);
     return p;
 }
 

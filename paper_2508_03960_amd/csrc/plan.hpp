@@ -67,10 +67,29 @@ struct StepOp {
     int32_t sample_lo = 0, sample_hi = 0;
 };
 
+// One operation of the conventional accelerated method (Sec. 2.2), per
+// isochromat, after the pending closed-form map `pre`:
+//   kind 2: with-RF block through its combined transition T_k (Eq. 7), which
+//           the first occurrence of the waveform composes and caches;
+//   kind 3: samples [sample_lo, sample_hi) of a with-ADC block without RF,
+//           evaluated directly from the state at the block start by Eq. (4),
+//           (5), (6); the state itself is not written (the block's map joins
+//           the pending one);
+//   kind 4: the pending map alone (always the last operation: writes the output).
+struct CachedOp {
+    int64_t block = -1;
+    bool has_pre = false;
+    Map pre;
+    int entry = -1;        // kind 2: cache entry, index into Plan::rf (axis -1)
+    bool compose = false;  // kind 2: first occurrence of the waveform
+    int32_t sample_lo = 0, sample_hi = 0;  // kind 3
+};
+
 struct Op {
-    int kind = 0;  // 0 = pass, 1 = step
+    int kind = 0;  // 0 = pass, 1 = step, 2-4 = CachedOp kinds
     PassOp pass;
     StepOp step;
+    CachedOp cached;
 };
 
 struct RfJob {  // one distinct combined transition (Eq. 7) per group of `axis`
@@ -91,6 +110,7 @@ struct Plan {
     Map final_map;
     int64_t n_rf_grouped = 0, n_adc_grouped = 0, n_fallback = 0, n_b1zero = 0, n_relax = 0;
     int64_t n_passes = 0, n_emit_only = 0;
+    int64_t n_rf_cached = 0, n_adc_direct = 0;  // plan_cached
 };
 
 // Largest number of ADC samples one stepping launch accumulates (LDS bound).
@@ -104,5 +124,9 @@ void copy_sequence(HostSeq &s, const gbs_block *blocks, int64_t n_blocks, const 
 std::vector<BlockClass> classify(const HostSeq &s);
 Plan plan_plain(const HostSeq &s);
 Plan plan_grouped(const HostSeq &s, const std::vector<BlockClass> &cls, uint32_t axes_built);
+// Schedule of the conventional accelerated method with dynamic caching of
+// per-isochromat transitions (Sec. 2.2).  Plan::rf lists the cache entries
+// (axis -1: bit-identical B1 and all three gradients).
+Plan plan_cached(const HostSeq &s, const std::vector<BlockClass> &cls);
 
 }  // namespace gbs

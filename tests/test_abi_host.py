@@ -114,6 +114,47 @@ def test_identical_rf_waveforms_share_one_transition(gb):
     assert gb.gbs_plan_summary(sb.build())["distinct_rf"] == 2
 
 
+# ------------------------------------------------ conventional method with caching (Sec. 2.2)
+def test_cached_plan_fse(gb):
+    # 16 x (90 + 16 x 180) RF blocks, two distinct waveforms composed once each;
+    # 256 readouts of 256 samples, one direct-ADC launch each
+    s = gb.gbs_plan_cached_summary(synth.fse_sequence())
+    assert s == {"rf_cached": 272, "entries": 2, "adc_direct": 256, "adc_launches": 256, "fallback": 0,
+                 "b1zero": 0}
+
+
+def test_cached_plan_epi(gb):
+    s = gb.gbs_plan_cached_summary(synth.epi_sequence())
+    assert (s["rf_cached"], s["entries"], s["adc_direct"], s["fallback"]) == (1, 1, 128, 0)
+
+
+def test_cached_plan_any_gradient(gb):
+    # per-isochromat transitions need no grouping axis: the mixed-gradient RF
+    # block is cached as well; only RF played during an ADC block is stepped
+    s = gb.gbs_plan_cached_summary(_misc_seq())
+    assert s == {"rf_cached": 3, "entries": 3, "adc_direct": 1, "adc_launches": 1, "fallback": 1, "b1zero": 1}
+
+
+def test_cached_plan_splits_long_readouts(gb):
+    sb = SeqBuilder(1e-6)
+    sb.rf(synth.sinc_pulse(40, 1e-6, 0.5), (0, 0, 0.01))
+    sb.adc(700, (0.01, 0, 0), np.arange(0, 700, 1))   # 700 samples: 3 launches
+    sb.adc(10, (0.01, 0, 0), [])                      # no samples: no launch
+    s = gb.gbs_plan_cached_summary(sb.build())
+    assert (s["adc_direct"], s["adc_launches"]) == (2, 3)
+
+
+def test_cached_plan_reuses_identical_waveforms(gb):
+    sb = SeqBuilder(1e-6)
+    b1 = synth.sinc_pulse(50, 1e-6, 1.0)
+    for _ in range(5):
+        sb.rf(b1, (0, 0, 0.01))
+        sb.relax(1e-3)
+    sb.rf(b1, (0, 0.01, 0))  # same B1, other gradient: its own entry
+    s = gb.gbs_plan_cached_summary(sb.build())
+    assert (s["rf_cached"], s["entries"]) == (6, 2)
+
+
 @pytest.mark.parametrize("case", ["unsorted", "outside", "negative_tau", "rf_with_samples"])
 def test_plan_rejects_bad_sequences(gb, case):
     sb = SeqBuilder(1e-6)

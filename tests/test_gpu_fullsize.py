@@ -8,7 +8,9 @@ The FP64 oracle cannot run 27M isochromats through 1.08M raster steps, so:
   against the oracle on smaller workloads) where that path is affordable: the
   whole EPI and the first FSE shot;
 * superposition (the signal is a sum over isochromats, Eq. 6) is checked for
-  the whole FSE: phantom = A + B gives signal(A) + signal(B).
+  the whole FSE: phantom = A + B gives signal(A) + signal(B);
+* the whole FSE and EPI are compared between the grouped update and the
+  conventional method with per-isochromat transition caching.
 """
 import numpy as np
 import pytest
@@ -92,6 +94,24 @@ def test_fse_first_shot_fullsize_vs_plain_fp64(big):
     dm, r = float(np.max(np.abs(Mg - Mp))), rel(sg, sp)
     say(f"[gpu] FSE shot 1 full: grouped vs plain max|dM|={dm:.3e} rel_sig={r:.3e}")
     assert dm <= DM_TOL and r <= SIG_TOL
+
+
+@pytest.mark.parametrize("name", ["fse", "epi"])
+def test_cached_fullsize_vs_grouped(big, name):
+    """The conventional method with per-isochromat caching (GBS_CACHED) and the
+    grouped update are independent algorithms for the same discrete model:
+    at full size they must agree to the parity bar, and sampled isochromats of
+    the cached result must match the oracle."""
+    gb, ph, sim = big
+    seq = synth.fse_sequence() if name == "fse" else synth.epi_sequence()
+    say(f"[gpu] {name} full K={ph.K}: cached")
+    Mc, sc = run(sim, gb, seq, gb.GBS_CACHED)
+    say(f"[gpu] {name} full: grouped")
+    Mg, sg = run(sim, gb, seq, gb.GBS_GROUPED)
+    dm, r = float(np.max(np.abs(Mc - Mg))), rel(sc, sg)
+    dmo = sampled_error(ph, seq, Mc, n=32, seed=13)
+    say(f"[gpu] {name} full: cached vs grouped max|dM|={dm:.3e} rel_sig={r:.3e}; sampled vs oracle {dmo:.3e}")
+    assert dm <= DM_TOL and r <= SIG_TOL and dmo <= DM_TOL
 
 
 def test_fse_fullsize_superposition(big):

@@ -2,7 +2,8 @@
 
 Bar (FP32 path vs FP64 oracle): max_k,c |M_gpu - M_oracle| <= 1e-5 on the
 final magnetization (M0 <= 1) and ||A_gpu - A_oracle||_2 / ||A_oracle||_2 <=
-1e-4 over all samples, for both the plain and the grouped mode.
+1e-4 over all samples, for the plain and the grouped mode (the cached mode
+has its own file, with the same bar).
 """
 import numpy as np
 import pytest
@@ -61,7 +62,7 @@ def check_case(gb, name, ph, seq, modes=("plain", "grouped"), axes=7, m_init=Non
     Mr, sr = ref if ref is not None else oracle.simulate(ph, seq, m_init=m_init)
     for mode in modes:
         say(f"[gpu] {name}: {mode} K={ph.K} blocks={seq.n_blocks} axes={axes}")
-        m = gb.GBS_GROUPED if mode == "grouped" else gb.GBS_PLAIN
+        m = {"grouped": gb.GBS_GROUPED, "cached": gb.GBS_CACHED}.get(mode, gb.GBS_PLAIN)
         flags = gb.GBS_PLAIN_FP32 if mode == "plain32" else 0
         M, sig, st = run_gpu(gb, ph, seq, m, axes=axes, m_init=m_init, flags=flags)
         dm, rel = errors(M, sig, Mr, sr)
