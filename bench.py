@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the signal-gradient leg")
     ap.add_argument("--no-cached", action="store_true",
                     help="skip the conventional method with per-isochromat transition caching")
+    ap.add_argument("--no-table2", action="store_true",
+                    help="skip the four sequences of the paper's Table 2 (grouped vs cached)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -402,6 +404,25 @@ def main():
             out["cached"]["epi"] = cached_leg(sim, gb, epi, m_out, sig_c, n_c, M_epi, s_epi[:, 0] + 1j * s_epi[:, 1])
             out["epi"]["speedup_grouped_vs_cached"] = out["cached"]["epi"]["ms"] / out["epi"]["grouped_ms"]
             log(f"EPI cached: {out['cached']['epi']}")
+
+    # ---- the paper's Table 2 sequences: grouped vs the cached conventional method ----------
+    if not args.no_table2:
+        out["table2"] = {}
+        for name, seq in synth.table2_sequences().items():
+            sim.set_sequence(seq)
+            sig_t = torch.empty(seq.total_samples, 2, device=dev, dtype=torch.float64)
+            sec_g, _ = timed_runs(sim, gb, gb.GBS_GROUPED, max(1, min(args.steps, 3)), 1, m_out, sig_t)
+            M_g = m_out.cpu().numpy()
+            s_g = torch.view_as_complex(sig_t).cpu().numpy()
+            sec_c, _ = timed_runs(sim, gb, gb.GBS_CACHED, 1, 1, m_out, sig_t)
+            s_c = torch.view_as_complex(sig_t).cpu().numpy()
+            S_t = seq.stepped_count()
+            out["table2"][name] = {
+                "grouped_ms": sec_g * 1e3, "cached_ms": sec_c * 1e3, "speedup_grouped_vs_cached": sec_c / sec_g,
+                "grouped_iso_steps_per_s": K * S_t / sec_g, "stepped_steps": S_t,
+                "cached_vs_grouped": {"max_abs_dM": float(np.max(np.abs(m_out.cpu().numpy() - M_g))),
+                                      "rel_signal": float(np.linalg.norm(s_c - s_g) / np.linalg.norm(s_g))}}
+            log(f"table2 {name}: {out['table2'][name]}")
 
     # ---- plain FSE: first shot (1/16 of the sequence) at full K -------------------------
     if not args.no_plain:

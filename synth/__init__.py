@@ -393,6 +393,104 @@ def epi_sequence(n_lines=128, n_read=128, dwell_steps=4, fov=(0.256, 0.256), thk
     return sb.build(kind="epi", n_lines=n_lines, n_read=n_read, fov=fov)
 
 
+# ---- the four pulse sequences of the paper's Table 2 --------------------------
+# Hamming-windowed sinc pulses of 4000 us at 1 us per sample (90 and 180
+# degrees), FOV 256 mm x 256 mm, one 10 mm slice, 256 readout samples (128 for
+# the EPI).  Timing the table leaves open (gaps, crushers, ramps) is ours.
+def se_sequence(n_lines=256, n_read=256, dwell_steps=5, fov=(0.256, 0.256), thk=0.010, rf_steps=4000,
+                te=10e-3, tr=500e-3, dt=1e-6, tbw=4.0):
+    """2D spin echo: per TR a 90x and a 180y sinc with Gz, one Gx readout whose
+    centre sample is at TE after the centre of the 90; readout prephaser and
+    phase encode before the 180, crushers on both sides of it, spoiling to TR.
+    Table 2: T1W is TE 10 ms, TR 500 ms, 5 us/sample; T2W is TE 100 ms,
+    TR 4500 ms, 50 us/sample."""
+    sb = SeqBuilder(dt, name=f"se{n_lines}x{n_read}")
+    b90 = sinc_pulse(rf_steps, dt, np.pi / 2, tbw, phase=0.0)
+    b180 = sinc_pulse(rf_steps, dt, np.pi, tbw, phase=np.pi / 2)
+    gz = slice_gradient(rf_steps, dt, thk, tbw)
+    g_ro = readout_gradient(dwell_steps * dt, fov[0])
+    ro_steps = n_read * dwell_steps
+    samples = dwell_steps * np.arange(n_read) + dwell_steps // 2
+    echo_step = int(samples[n_read // 2])
+    half_rf = rf_steps * dt / 2
+    crush = 2.0 / (GAMMA_BAR * thk)
+    tau_1 = te / 2 - 2 * half_rf                  # end of the 90 to the start of the 180
+    tau_2 = te / 2 - half_rf - echo_step * dt     # end of the 180 to the start of the readout
+    tau_end = tr - (4 * half_rf + tau_1 + tau_2 + ro_steps * dt)
+    assert min(tau_1, tau_2, tau_end) > 0
+    spoil_z = 4.0 / (GAMMA_BAR * thk)
+    for line in range(n_lines):
+        my = (line - n_lines // 2) / (GAMMA_BAR * fov[1])
+        sb.rf(b90, (0.0, 0.0, gz))
+        # the 180 negates the phase of everything before it, so the prephaser
+        # has the readout's sign
+        sb.relax(tau_1, (g_ro * echo_step * dt, my, -0.5 * gz * rf_steps * dt + crush))
+        sb.rf(b180, (0.0, 0.0, gz))
+        sb.relax(tau_2, (0.0, 0.0, crush))
+        sb.adc(ro_steps, (g_ro, 0.0, 0.0), samples)
+        sb.relax(tau_end, (2.0 * g_ro * ro_steps * dt, 0.0, spoil_z))
+    return sb.build(kind="se", n_lines=n_lines, n_read=n_read, fov=fov, te=te, tr=tr)
+
+
+def se_epi_sequence(n_lines=96, n_full=128, n_read=128, dwell_steps=3, fov=(0.256, 0.256), thk=0.010,
+                    rf_steps=4000, te=70e-3, ramp=120e-6, blip=100e-6, dt=1e-6, tbw=4.0):
+    """Single-shot spin-echo EPI with partial Fourier: 90x and 180y sinc with
+    Gz, then n_lines of the n_full phase-encode lines (from
+    n_full/2 - n_lines to n_full/2 - 1 about the centre), alternating Gx flat
+    tops (ADC) with trapezoid ramps and Gy blips as relaxation blocks.  The
+    centre sample of the centre line is at TE after the centre of the 90.
+    Table 2: 96 of 128 lines, 128 samples at 3 us, TE 70 ms."""
+    sb = SeqBuilder(dt, name=f"seepi{n_lines}of{n_full}x{n_read}")
+    b90 = sinc_pulse(rf_steps, dt, np.pi / 2, tbw, phase=0.0)
+    b180 = sinc_pulse(rf_steps, dt, np.pi, tbw, phase=np.pi / 2)
+    gz = slice_gradient(rf_steps, dt, thk, tbw)
+    g_ro = readout_gradient(dwell_steps * dt, fov[0])
+    ro_steps = n_read * dwell_steps
+    samples = dwell_steps * np.arange(n_read) + dwell_steps // 2
+    echo_step = int(samples[n_read // 2])
+    half_rf = rf_steps * dt / 2
+    ramp_m = 0.5 * g_ro * ramp
+    blip_m = 1.0 / (GAMMA_BAR * fov[1])
+    crush = 2.0 / (GAMMA_BAR * thk)
+    first = n_full // 2 - n_lines  # phase-encode index of the first line (centre = 0)
+    c = -first                     # acquisition index of the centre line
+    period = ro_steps * dt + 2 * ramp + blip
+    tau_a = te / 2 - 2 * half_rf
+    tau_b = te - (te / 2 + half_rf) - (c * period + ramp + echo_step * dt)
+    assert n_lines <= n_full and first <= 0 and tau_a > 0 and tau_b > 0
+    sb.rf(b90, (0.0, 0.0, gz))
+    sb.relax(tau_a, (0.0, 0.0, -0.5 * gz * rf_steps * dt + crush))
+    sb.rf(b180, (0.0, 0.0, gz))
+    sb.relax(tau_b, (-(ramp_m + echo_step * g_ro * dt), first * blip_m, crush))
+    for line in range(n_lines):
+        s = 1.0 if line % 2 == 0 else -1.0
+        sb.relax(ramp, (s * ramp_m, 0.0, 0.0))
+        sb.adc(ro_steps, (s * g_ro, 0.0, 0.0), samples)
+        sb.relax(ramp, (s * ramp_m, 0.0, 0.0))
+        if line + 1 < n_lines:
+            sb.relax(blip, (0.0, blip_m, 0.0))
+    return sb.build(kind="se-epi", n_lines=n_lines, n_full=n_full, n_read=n_read, fov=fov, te=te)
+
+
+def table2_sequences(small=False):
+    """The four Table 2 sequences by name (full size, or a reduced version of
+    the same structure for oracle-checked parity runs)."""
+    if small:
+        return {
+            "t1w-se": se_sequence(n_lines=3, n_read=16, dwell_steps=5, rf_steps=400, te=10e-3, tr=30e-3),
+            "t2w-se": se_sequence(n_lines=2, n_read=16, dwell_steps=50, rf_steps=400, te=100e-3, tr=0.3),
+            "se-epi": se_epi_sequence(n_lines=12, n_full=16, n_read=16, rf_steps=400, te=20e-3),
+            "fse-etl5": fse_sequence(n_shots=2, etl=5, n_read=16, dwell_steps=8, rf_steps=400, esp=12e-3,
+                                     tr=0.2),
+        }
+    return {
+        "t1w-se": se_sequence(te=10e-3, tr=500e-3, dwell_steps=5),
+        "t2w-se": se_sequence(te=100e-3, tr=4500e-3, dwell_steps=50),
+        "se-epi": se_epi_sequence(),
+        "fse-etl5": fse_sequence(n_shots=52, etl=5, n_read=256, dwell_steps=8, rf_steps=4000, esp=12e-3, tr=1.5),
+    }
+
+
 # ---- learned RF-transition surrogate: the modelled pulse and its inputs ----
 def fse_refocusing_pulse(rf_steps=3000, dt=1e-6, thk=0.010, tbw=4.0):
     """The FSE 180-degree refocusing pulse (about y) with its slice gradient:
