@@ -61,6 +61,7 @@ extern "C" {
 #define GBS_AX_X 1u
 #define GBS_AX_Y 2u
 #define GBS_AX_Z 4u
+#define GBS_AX_N 8u /* no-grads groups: key (T1, T2, dB0) alone */
 
 /* ---- simulation modes and flags -------------------------------------- */
 #define GBS_PLAIN 0
@@ -99,6 +100,7 @@ typedef struct gbs_info {
     int64_t n_groups[3];   /* groups per axis x, y, z; -1 when not built */
     int32_t groups_valid;  /* 1 when groups match the current phantom */
     int32_t device;
+    int64_t n_tissue_groups; /* no-grads groups (GBS_AX_N); -1 when not built */
 } gbs_info;
 
 /* Filled by gbs_simulate when non-null.  Times come from HIP events. */
@@ -173,9 +175,13 @@ int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, co
  * Group the isochromats once (Sec. 2.4, Fig. 2): for each requested axis a
  * (GBS_AX_X | GBS_AX_Y | GBS_AX_Z) the key (r_a, T1, T2, dB0) is compared by
  * exact bit pattern (-0 == +0); equal keys form one group, numbered densely
- * in lexicographic key order.  `axes` must include GBS_AX_X (the x groups
- * order the stored copy); blocks whose type needs an axis that was not built
- * are stepped per isochromat.  The context
+ * in lexicographic key order.  GBS_AX_N adds the no-grads groups of key
+ * (T1, T2, dB0), numbered in ascending (T1, T2, dB0) order: a with-RF
+ * subsequence without gradients then composes one transition per such group
+ * instead of one per x-group (the result is the same).  `axes` must include
+ * GBS_AX_X (the x groups order the stored copy); blocks whose type needs an
+ * axis that was not built are stepped per isochromat, except that no-grads
+ * blocks use the x groups when GBS_AX_N is absent.  The context
  * stores a copy of the phantom in group-sorted order (about 13 float/int32
  * words per isochromat).  Synchronizes the stream.
  * Errors: GBS_E_STATE (no phantom), GBS_E_INVALID (no GBS_AX_X, unknown bits),

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -60,6 +61,8 @@ struct GroupedPlan {
     Plan plan;
     bool zbuilt = false;
     std::vector<size_t> rf_off, gsum_off;
+    // no-grads transitions composed per tissue group: (composed rows, x-group rows)
+    std::vector<std::pair<size_t, size_t>> expand;
     size_t gsum_count = 0;
     int64_t max_rf_groups = 0, max_tab = 0;
     int max_adc_groups = 0, max_adc_samples = 0;
@@ -106,6 +109,9 @@ struct gbs_ctx {
     int64_t Kpad = 0;
     DevBuf perm, inv, xi, yi, zi, t1i, t2i, dfi, m0i, gid[3], gtab[3], gcount[3], ms[3];
     DevBuf m_final;  // (mx, my, mz, 0) per layout slot, written by the last sweep of a run
+    // no-grads groups (GBS_AX_N): (0, T1, T2, df) per group, and the group of each x-group
+    int64_t n_tissue = -1;
+    DevBuf ttab, tmap;
     // per-simulate buffers
     DevBuf tabs, gsum, partial, jobs, samp, flag, state64;
     std::vector<char> host_jobs;  // kept alive until the next call
@@ -213,7 +219,7 @@ int gbs_destroy(gbs_ctx *ctx) {
                       &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->tabs, &ctx->gsum, &ctx->partial, &ctx->jobs,
                       &ctx->samp, &ctx->flag, &ctx->surr, &ctx->adj_ops, &ctx->adj_samp, &ctx->adj_ckpt, &ctx->adj_sub,
                       &ctx->adj_sig, &ctx->adj_grf, &ctx->adj_gt, &ctx->state64, &ctx->m_final,
-                      &ctx->csamp, &ctx->cache};
+                      &ctx->csamp, &ctx->cache, &ctx->ttab, &ctx->tmap};
     for (DevBuf *b : bufs) b->release();
     for (int a = 0; a < 3; ++a) {
         ctx->gid[a].release();
@@ -295,7 +301,8 @@ int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, co
 int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
     if (!ctx) return GBS_E_INVALID;
     if (!ctx->has_ph) return fail(ctx, GBS_E_STATE, "gbs_build_groups before gbs_set_phantom");
-    if (!(axes & GBS_AX_X) || (axes & ~7u)) return fail(ctx, GBS_E_INVALID, "axes must include GBS_AX_X and only X|Y|Z");
+    if (!(axes & GBS_AX_X) || (axes & ~15u))
+        return fail(ctx, GBS_E_INVALID, "axes must include GBS_AX_X and only X|Y|Z|N");
     HIPCHK(hipSetDevice(ctx->device));
     ctx->groups_valid = false;
     ctx->gp.valid = false;
@@ -343,6 +350,35 @@ int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
         if (e != hipSuccess) return fail_hip(e, "grouping failed");
         ctx->ng[a] = G;
     }
+    // no-grads groups: the distinct (T1, T2, dB0) of the x-group keys, each x
+    // group mapped to its own (every x-group key contains exactly one)
+    ctx->n_tissue = -1;
+    if (axes & GBS_AX_N) {
+        const int64_t Gx = ctx->ng[0];
+        std::vector<float4> xt((size_t)Gx);
+        HIPCHK(hipMemcpyAsync(xt.data(), ctx->gtab[0].p, sizeof(float4) * (size_t)Gx, hipMemcpyDeviceToHost,
+                              ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        auto canon = [](float v) { return v == 0.0f ? 0.0f : v; };  // -0 == +0
+        std::vector<std::array<float, 3>> keys((size_t)Gx);
+        for (int64_t g = 0; g < Gx; ++g) keys[g] = {canon(xt[g].y), canon(xt[g].z), canon(xt[g].w)};
+        std::vector<std::array<float, 3>> uniq(keys);
+        std::sort(uniq.begin(), uniq.end());
+        uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+        std::vector<int32_t> map((size_t)Gx);
+        for (int64_t g = 0; g < Gx; ++g)
+            map[g] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), keys[g]) - uniq.begin());
+        std::vector<float4> tt(uniq.size());
+        for (size_t i = 0; i < uniq.size(); ++i) tt[i] = make_float4(0.0f, uniq[i][0], uniq[i][1], uniq[i][2]);
+        ALLOC(ctx->ttab, sizeof(float4) * tt.size());
+        ALLOC(ctx->tmap, sizeof(int32_t) * map.size());
+        HIPCHK(hipMemcpy(ctx->ttab.p, tt.data(), sizeof(float4) * tt.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(ctx->tmap.p, map.data(), sizeof(int32_t) * map.size(), hipMemcpyHostToDevice));
+        ctx->n_tissue = (int64_t)uniq.size();
+    } else {
+        ctx->ttab.release();
+        ctx->tmap.release();
+    }
     // 2. the padded group-sorted layout: (x-group, z-group) runs of multiples of 8
     int64_t kint = 0;
     hipError_t e = build_layout(K, gid_nat[0].as<int32_t>(), (axes & GBS_AX_Z) ? gid_nat[2].as<int32_t>() : nullptr,
@@ -389,6 +425,7 @@ int gbs_get_info(gbs_ctx *ctx, gbs_info *info) {
     for (int a = 0; a < 3; ++a) info->n_groups[a] = ctx->groups_valid ? ctx->ng[a] : -1;
     info->groups_valid = ctx->groups_valid ? 1 : 0;
     info->device = ctx->device;
+    info->n_tissue_groups = ctx->groups_valid ? ctx->n_tissue : -1;
     return GBS_OK;
 }
 
@@ -592,11 +629,20 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
     // ---- arena: FP64 combined transitions, folded transitions, map tables
     size_t off = 0;
     g.rf_off.resize(plan.rf.size());
+    g.expand.clear();
+    std::vector<size_t> comp_off(plan.rf.size());
     for (size_t i = 0; i < plan.rf.size(); ++i) {
-        g.rf_off[i] = off;
-        const int64_t G = ctx->ng[plan.rf[i].axis];
+        const bool tissue = plan.rf[i].axis == kTissueAxis;
+        const int64_t G = tissue ? ctx->n_tissue : ctx->ng[plan.rf[i].axis];
+        comp_off[i] = off;
         g.max_rf_groups = std::max(g.max_rf_groups, G);
         off = align256(off + sizeof(double) * 12 * (size_t)G);
+        g.rf_off[i] = comp_off[i];
+        if (tissue) {  // expanded to x-group rows for the fold
+            g.rf_off[i] = off;
+            off = align256(off + sizeof(double) * 12 * (size_t)Gx);
+            g.expand.emplace_back(comp_off[i], g.rf_off[i]);
+        }
     }
     std::vector<TabJob> tjobs;
     auto x_table = [&](int kind, double tau, double cyc) {
@@ -701,6 +747,11 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
     for (size_t i = 0; i < plan.rf.size(); ++i) {
         const RfJob &r = plan.rf[i];
         // the surrogate's transition is not composed here (n_groups = 0 skips it)
+        if (r.axis == kTissueAxis) {  // no gradients: the coordinate column of the table is unused
+            rj[i] = RfJobDev{0, (int32_t)r.n_steps, ctx->n_tissue, ctx->d_wave.as<StepW>() + r.step_offset,
+                             ctx->ttab.as<float4>(), (double *)(tb + comp_off[i])};
+            continue;
+        }
         const int64_t ng = (int)i == g.surr_rf ? 0 : ctx->ng[r.axis];
         rj[i] = RfJobDev{r.axis, (int32_t)r.n_steps, ng, ctx->d_wave.as<StepW>() + r.step_offset,
                          ctx->gtab[r.axis].as<float4>(), (double *)(tb + g.rf_off[i])};
@@ -974,6 +1025,9 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
         HIPCHK(mlp_exact_async(m, tuples, nullptr, g.surr_groups, fb, T64, ctx->stream));
     }
     HIPCHK(launch_compose((const RfJobDev *)(jb + g.o_rf), g.n_rf, g.max_rf_groups, s.dt, ctx->stream));
+    for (const auto &e : g.expand)
+        HIPCHK(launch_expand_rows((const double *)(tb + e.first), ctx->tmap.as<int32_t>(), ctx->ng[0],
+                                  (double *)(tb + e.second), ctx->stream));
     HIPCHK(launch_fold((const FoldJob *)(jb + g.o_fold), g.n_fold, g.max_fold_groups, ctx->stream));
     HIPCHK(launch_tables((const TabJob *)(jb + g.o_tab), g.n_tab, (int)g.max_tab, ctx->gtab[0].as<float4>(),
                          zbuilt ? ctx->gtab[2].as<float4>() : nullptr, ctx->stream));

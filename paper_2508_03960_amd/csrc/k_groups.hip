@@ -172,6 +172,20 @@ hipError_t launch_gather_i32(int64_t K, int64_t Kpad, const int32_t *perm, const
     return hipGetLastError();
 }
 
+__global__ void k_expand_rows(const double *__restrict__ src, const int32_t *__restrict__ map, int64_t n,
+                              double *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= 12 * n) return;
+    const int64_t g = i / 12;
+    dst[i] = src[12 * (int64_t)map[g] + (i - 12 * g)];
+}
+
+hipError_t launch_expand_rows(const double *src, const int32_t *map, int64_t n, double *dst, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_expand_rows, dim3((unsigned)((12 * n + 255) / 256)), dim3(256), 0, st, src, map, n, dst);
+    return hipGetLastError();
+}
+
 // Build the padded layout from natural-order x (and optional z) group ids.
 // perm[pos] = isochromat at internal position pos or -1 (padding); src[pos] =
 // the isochromat whose parameters the position copies.  perm/src need room

@@ -248,7 +248,10 @@ Plan plan_grouped(const HostSeq &s, const std::vector<BlockClass> &cls, uint32_t
             cur.has_pre = P.any();
             cur.pre = P;
             cur.rf_axis = axis;
-            cur.rf_id = rf_lookup(p, hashes, s, b, axis, c.gtype);
+            // no-grads: one composition per tissue group when those exist (the
+            // sweep still applies it through the x-group rows)
+            const int job_axis = c.gtype == GT_NONE && (axes_built & GBS_AX_N) ? kTissueAxis : axis;
+            cur.rf_id = rf_lookup(p, hashes, s, b, job_axis, c.gtype);
             cur.write_m = true;
             have_cur = true;
             P = Map{};

@@ -14,6 +14,10 @@ namespace gbs {
 // Gradient type of a with-RF / with-ADC subsequence (Sec. 2.4).
 enum GradType { GT_X = 0, GT_Y = 1, GT_Z = 2, GT_NONE = 3, GT_MIXED = 4 };
 
+// RfJob::axis of a no-grads transition composed per tissue group (key T1, T2,
+// dB0; built with GBS_AX_N) and applied through the x-group rows.
+constexpr int kTissueAxis = 3;
+
 struct HostSeq {
     std::vector<gbs_block> blocks;
     std::vector<float> rf_re, rf_im, gx, gy, gz;
@@ -92,7 +96,7 @@ struct Op {
     CachedOp cached;
 };
 
-struct RfJob {  // one distinct combined transition (Eq. 7) per group of `axis`
+struct RfJob {  // one distinct combined transition (Eq. 7) per group of `axis` (or kTissueAxis)
     int axis;
     int64_t step_offset, n_steps;
 };

@@ -289,6 +289,13 @@ def sinc_pulse(n_steps, dt, flip_rad, tbw=4.0, phase=0.0):
     return amp * env * np.exp(1j * phase)
 
 
+def chess_pulse(n_steps, dt, flip_rad, offset_hz, tbw=2.0):
+    """Frequency-selective (CHESS) pulse without gradients: a sinc whose
+    centre frequency is moved by offset_hz (fat saturation: about -440 Hz at 3 T)."""
+    t = (np.arange(n_steps) + 0.5 - n_steps / 2) * dt
+    return sinc_pulse(n_steps, dt, flip_rad, tbw) * np.exp(2j * np.pi * offset_hz * t)
+
+
 def slice_gradient(n_steps, dt, thk, tbw=4.0):
     return tbw / (n_steps * dt * GAMMA_BAR * thk)
 
@@ -322,11 +329,16 @@ def gre_sequence(n_lines=32, n_read=64, dwell_steps=10, fov=(0.200, 0.200), thk=
 
 
 def fse_sequence(n_shots=16, etl=16, n_read=256, dwell_steps=4, fov=(0.256, 0.256), thk=0.010,
-                 rf_steps=3000, esp=8e-3, tr=3.0, dt=1e-6, tbw=4.0):
+                 rf_steps=3000, esp=8e-3, tr=3.0, dt=1e-6, tbw=4.0, fat_sat=False):
     """CPMG fast spin echo: 90x then `etl` 180y refocusing pulses (sinc with Gz),
     each echo read out with Gx; phase-encode line = etl_index*n_shots + shot.
-    Crushers bracket every refocusing pulse; relaxation to TR ends each shot."""
-    sb = SeqBuilder(dt, name=f"fse{n_shots}x{etl}x{n_read}")
+    Crushers bracket every refocusing pulse; relaxation to TR ends each shot.
+    fat_sat: every shot starts with a 2 ms CHESS 90-degree pulse at -440 Hz
+    (a no-grads with-RF subsequence) and a 1 ms spoiler, taken from the end
+    of the TR."""
+    sb = SeqBuilder(dt, name=f"fse{n_shots}x{etl}x{n_read}" + ("fs" if fat_sat else ""))
+    chess = chess_pulse(2000, dt, np.pi / 2, -440.0) if fat_sat else None
+    fs_time = 3e-3 if fat_sat else 0.0
     b90 = sinc_pulse(rf_steps, dt, np.pi / 2, tbw, phase=0.0)
     b180 = sinc_pulse(rf_steps, dt, np.pi, tbw, phase=np.pi / 2)
     gz = slice_gradient(rf_steps, dt, thk, tbw)
@@ -343,13 +355,16 @@ def fse_sequence(n_shots=16, etl=16, n_read=256, dwell_steps=4, fov=(0.256, 0.25
     tau_post = esp / 2 - (ro_steps - echo_step) * dt - half_rf
     assert min(tau_90_180, tau_pre, tau_post) > 0
     shot_len = 2 * half_rf + tau_90_180 + etl * (2 * half_rf + tau_pre + ro_steps * dt + tau_post)
-    tau_end = tr - shot_len + tau_post
+    tau_end = tr - shot_len + tau_post - fs_time
     assert tau_end > 0
     # x-moments: prephaser P, pre-readout Q, post-readout R = 0 such that every
     # echo centre (sample n_read//2) sees zero net x-moment.
     P = (ro_steps - echo_step) * a
     Q = P - echo_step * a
     for shot in range(n_shots):
+        if fat_sat:
+            sb.rf(chess, (0.0, 0.0, 0.0))
+            sb.relax(1e-3, (8.0 / (GAMMA_BAR * fov[0]), 8.0 / (GAMMA_BAR * fov[1]), 8.0 / (GAMMA_BAR * thk)))
         sb.rf(b90, (0.0, 0.0, gz))
         sb.relax(tau_90_180, (P, 0.0, -0.5 * gz * rf_steps * dt + crush))
         for e in range(etl):

@@ -104,6 +104,16 @@ def test_plan_classification(gb):
     assert s["fallback"] == 3 and s["adc_grouped"] == 0
 
 
+def test_plan_no_grads_groups(gb):
+    # GBS_AX_N changes where a no-grads transition is composed, not the counts
+    a = gb.gbs_plan_summary(_misc_seq(), axes=gb.GBS_AX_ALL)
+    b = gb.gbs_plan_summary(_misc_seq(), axes=gb.GBS_AX_X | gb.GBS_AX_Y | gb.GBS_AX_Z)
+    assert a == b
+    fs = synth.fse_sequence(n_shots=2, etl=2, n_read=16, fat_sat=True)
+    s = gb.gbs_plan_summary(fs)
+    assert (s["rf_grouped"], s["distinct_rf"], s["fallback"]) == (8, 3, 0)
+
+
 def test_identical_rf_waveforms_share_one_transition(gb):
     sb = SeqBuilder(1e-6)
     b1 = synth.sinc_pulse(50, 1e-6, 1.0)

@@ -95,10 +95,11 @@ def test_ragged_k_and_initial_state(gb):
     check_case(gb, "ragged+m_init", ph, seq, m_init=m_init)
 
 
-@pytest.mark.parametrize("axes", [7, 5, 1])
+@pytest.mark.parametrize("axes", [15, 7, 5, 1])
 def test_classification_paths(gb, axes):
     """Gx/Gy/no-grads RF, Gy/Gz readouts with ramps, mixed-gradient RF and ADC
-    with RF (stepped per isochromat); fewer axes force more fallbacks."""
+    with RF (stepped per isochromat); fewer axes force more fallbacks; with
+    GBS_AX_N (15) the no-grads RF is composed per tissue group."""
     from tests.test_oracle_pins import _mini_sequences
     ph = synth.tiny_phantom(nx=9, ny=7, nz=3, n_classes=3, df_levels=3)
     for seq in _mini_sequences():
@@ -120,6 +121,41 @@ def test_edge_cases(gb):
     check_case(gb, "b1zero", ph, sb.build())
     empty = SeqBuilder(1e-6, "empty").build()
     check_case(gb, "empty", ph, empty)
+
+
+def test_no_grads_groups(gb):
+    """No-grads with-RF subsequences (Sec. 2.4): with GBS_AX_N the transition is
+    composed once per (T1, T2, dB0) group and expanded to the x-group rows;
+    the count of those groups is the number of distinct tissue keys, and the
+    result matches the oracle and the x-group composition."""
+    import torch
+    ph = synth.tiny_phantom(nx=9, ny=7, nz=3, n_classes=3, df_levels=3)
+    keys = np.stack([ph.t1.astype(np.float32), ph.t2.astype(np.float32), ph.df.astype(np.float32)], 1)
+    n_tissue = len(np.unique(keys + 0.0, axis=0))  # + 0.0 maps -0 to +0
+    sb = SeqBuilder(1e-6, "chess")
+    chess = synth.chess_pulse(300, 1e-6, np.pi / 2, -60.0)
+    for i in range(2):  # the second CHESS pulse reuses the first transition
+        sb.rf(chess, (0, 0, 0))
+        sb.relax(5e-4, (3e-6, -2e-6, 4e-6))
+        sb.rf(synth.sinc_pulse(120, 1e-6, 0.6), (0, 0, 0.01))
+        sb.relax(3e-4, (-1e-6, 0, -5e-7))
+        sb.adc(48, (0.008, 0, 0), 4 * np.arange(12) + 2)
+    seq = sb.build()
+    ref = oracle.simulate(ph, seq)
+    sim = gb.Simulator(0)
+    sim.set_phantom(ph)
+    sim.build_groups(gb.GBS_AX_ALL)
+    info = sim.info()
+    sim.close()
+    say(f"[gpu] no-grads: {info['n_tissue_groups']} tissue groups (expected {n_tissue}), x-groups {info['n_groups'][0]}")
+    assert info["n_tissue_groups"] == n_tissue < info["n_groups"][0]
+    check_case(gb, "chess", ph, seq, modes=("grouped",), axes=15, ref=ref)
+    check_case(gb, "chess/x-groups", ph, seq, modes=("grouped",), axes=7, ref=ref)
+    M15, s15, st = run_gpu(gb, ph, seq, gb.GBS_GROUPED, axes=15)
+    M7, s7, _ = run_gpu(gb, ph, seq, gb.GBS_GROUPED, axes=7)
+    assert st["n_distinct_rf"] == 2 and st["n_fallback"] == 0, st
+    dm, rel = errors(M15, s15, M7, s7)
+    assert dm <= 1e-6 and rel <= 1e-6, (dm, rel)
 
 
 def test_run_boundaries(gb):
