@@ -8,6 +8,10 @@ code with the GPU library; both sides only read the same seeded inputs from
 * ``simulate`` wraps the plain per-isochromat C oracle (``bloch_oracle.c``):
   raster stepping with U = D*R (Eq. 2, Eq. A1, Eq. A2), closed-form
   relaxation blocks (Eq. 4, Eq. 5) and the k-space sum (Eq. 6).
+* ``simulate_coils`` gives the signal of P receive coils (Eq. 6 with
+  S(k, p)): every isochromat is simulated on its own by ``simulate`` (its
+  signal is its Mxy at the sample instants) and the coil signals are the
+  S-weighted sums of those.  For tiny phantoms only.
 * ``oracle.grouped.simulate_grouped`` is a brute-force FP64 transcription of
   the grouped method (Sec. 2.3 and 2.4) for tiny phantoms.
 """
@@ -145,3 +149,23 @@ def adjoint(ph, cls, t1c, t2c, seq, rf_param, param_blocks, w, nthreads: int = 0
     if rc != 0:
         raise ValueError(f"oracle_adjoint rejected its input ({rc})")
     return (sig[0:2 * N:2] + 1j * sig[1:2 * N:2], g_rf[0:2 * n_rf:2] + 1j * g_rf[1:2 * n_rf:2], g1, g2)
+
+
+def simulate_coils(ph, seq, sens, m_init=None):
+    """Signals of P receive coils, Eq. (6): A(p, t_n) = sum_k S(k, p) Mxy(k, t_n).
+
+    ``sens`` is complex (P, K).  Each isochromat k is simulated alone, which
+    gives Mxy(k, t_n) at every sample; the coil signals weight and add those.
+    Returns ``(M, sig)`` with M float64 (3, K) and sig complex128 (P, N).
+    """
+    sens = np.asarray(sens, np.complex128)
+    K = ph.K
+    assert sens.ndim == 2 and sens.shape[1] == K
+    mi = None if m_init is None else np.asarray(m_init, np.float64).reshape(3, K)
+    M = np.zeros((3, K))
+    sig = np.zeros((sens.shape[0], seq.total_samples), np.complex128)
+    for k in range(K):
+        Mk, sk = simulate(ph.subset(np.array([k])), seq, m_init=None if mi is None else mi[:, k:k + 1], nthreads=1)
+        M[:, k] = Mk[:, 0]
+        sig += sens[:, k:k + 1] * sk[None, :]
+    return M, sig
