@@ -12,7 +12,8 @@
  *     T2 decay and T1 recovery toward M0;
  *   - relaxation blocks (no RF, no ADC) use the closed forms Eq. (4), (5);
  *   - ADC sample n adds Mx + i My of all isochromats at its raster boundary
- *     (Eq. 6, one receive coil of unit sensitivity);
+ *     (Eq. 6): one receive coil of unit sensitivity, or P coils with
+ *     per-isochromat sensitivities S(k, p) (gbs_set_coils);
  *   - GBS_PLAIN steps every isochromat individually (the conventional
  *     method, Sec. 2.2); GBS_GROUPED uses the paper's combined update with
  *     grouped isochromats (Sec. 2.3, 2.4): isochromats sharing
@@ -101,6 +102,7 @@ typedef struct gbs_info {
     int32_t groups_valid;  /* 1 when groups match the current phantom */
     int32_t device;
     int64_t n_tissue_groups; /* no-grads groups (GBS_AX_N); -1 when not built */
+    int64_t n_coils;         /* receive coils of the signal (1 unless gbs_set_coils set more) */
 } gbs_info;
 
 /* Filled by gbs_simulate when non-null.  Times come from HIP events. */
@@ -161,6 +163,23 @@ int gbs_set_phantom(gbs_ctx *ctx, int64_t K, const float *x, const float *y, con
                     const float *t1, const float *t2, const float *df_hz, const float *m0);
 
 /*
+ * Receive coils (Eq. 6 and Eq. 9 with P = n_coils): sens_re, sens_im are
+ * device float arrays [n_coils][K] holding S(k, p) of isochromat k (in the
+ * phantom's order) for coil p, kept as views until the next gbs_set_coils or
+ * gbs_set_phantom (which returns to one coil of unit sensitivity).  Both null
+ * with n_coils = 1 selects that default.  With sensitivities the signal of
+ * gbs_simulate has n_coils rows, and every emission of GBS_GROUPED weights
+ * its members by S before the group sums of each coil (the general sweep
+ * kernel; S is read from the context's group-sorted copy at every emission).
+ * GBS_PLAIN, and readouts that are stepped per isochromat in any mode (RF
+ * during an ADC block, unclassified blocks), are rejected with sensitivities.
+ * Errors: GBS_E_STATE (no phantom), GBS_E_INVALID (n_coils outside
+ * [1, GBS_MAX_COILS], one pointer null, NaN/inf values), GBS_E_HIP.
+ */
+#define GBS_MAX_COILS 8
+int gbs_set_coils(gbs_ctx *ctx, int32_t n_coils, const float *sens_re, const float *sens_im);
+
+/*
  * Sequence (Sec. 2.1, Fig. 1): `blocks` (host, n_blocks entries) over a
  * uniform raster `dt` (s).  Per-step waveforms are host arrays of length
  * total_steps: rf_re, rf_im (B1 in T), gx, gy, gz (T/m); adc_idx is a host
@@ -194,7 +213,8 @@ int gbs_build_groups(gbs_ctx *ctx, uint32_t axes);
  * GBS_CACHED (GBS_CACHED needs no groups).
  * m_init: device float[3*K] SoA (Mx, My, Mz) or NULL for (0, 0, M0).
  * m_out: device float[3*K] SoA final magnetization (may alias m_init).
- * sig_out: device double[2*total_samples], interleaved (re, im), Eq. (6).
+ * sig_out: device double[2*n_coils*total_samples], interleaved (re, im), Eq. (6),
+ *          coil-major (row p holds coil p; n_coils = 1 without gbs_set_coils).
  * stats: host, nullable.  Without GBS_ASYNC the call synchronizes the stream.
  * GBS_PLAIN and GBS_CACHED keep the state between launches in FP64 (3 * K
  * doubles owned by the context).  GBS_CACHED also owns the transition cache:

@@ -29,7 +29,7 @@ GBS_MLP_PARAMS = 35340
 
 EXPORTED = ("gbs_create", "gbs_destroy", "gbs_set_phantom", "gbs_set_sequence", "gbs_build_groups",
             "gbs_simulate", "gbs_get_info", "gbs_last_error", "gbs_strerror", "gbs_plan_summary",
-            "gbs_plan_cached_summary",
+            "gbs_plan_cached_summary", "gbs_set_coils",
             "gbs_mlp_create", "gbs_mlp_destroy", "gbs_mlp_last_error", "gbs_mlp_set_pulse",
             "gbs_mlp_set_norm", "gbs_mlp_get_params", "gbs_mlp_set_params", "gbs_mlp_exact",
             "gbs_mlp_infer", "gbs_mlp_loss_grad", "gbs_mlp_train", "gbs_set_surrogate",
@@ -47,7 +47,7 @@ class gbs_info(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int64), ("n_blocks", ctypes.c_int64), ("total_steps", ctypes.c_int64),
                 ("total_samples", ctypes.c_int64), ("stepped_steps", ctypes.c_int64),
                 ("n_groups", ctypes.c_int64 * 3), ("groups_valid", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("n_tissue_groups", ctypes.c_int64)]
+                ("device", ctypes.c_int32), ("n_tissue_groups", ctypes.c_int64), ("n_coils", ctypes.c_int64)]
 
 
 class gbs_stats(ctypes.Structure):
@@ -84,6 +84,7 @@ def _load(path=LIB_PATH):
         "gbs_create": ([ctypes.POINTER(P), ctypes.c_int, P], ctypes.c_int),
         "gbs_destroy": ([P], ctypes.c_int),
         "gbs_set_phantom": ([P, I64] + [P] * 7, ctypes.c_int),
+        "gbs_set_coils": ([P, I32, P, P], ctypes.c_int),
         "gbs_set_sequence": ([P, P, I64, P, P, P, P, P, I64, P, I64, D], ctypes.c_int),
         "gbs_build_groups": ([P, U32], ctypes.c_int),
         "gbs_simulate": ([P, ctypes.c_int, U32, P, P, P, P], ctypes.c_int),
@@ -194,8 +195,10 @@ class Simulator:
         self._h = h
         self._destroy = lib.gbs_destroy  # still reachable while the interpreter shuts down
         self._keep = ()
+        self._coils = ()
         self.K = 0
         self.n_samples = 0
+        self.n_coils = 1
 
     def _check(self, rc):
         if rc != GBS_OK:
@@ -213,10 +216,29 @@ class Simulator:
         self._keep = ts  # the library keeps views of these tensors
         self._check(lib.gbs_set_phantom(self._h, ts[0].numel(), *(_ptr(t) for t in ts)))
         self.K = ts[0].numel()
+        self._coils = ()
+        self.n_coils = 1
 
     def set_phantom(self, ph):
         """From a synth.Phantom (host numpy arrays)."""
         self.gbs_set_phantom(*(torch.from_numpy(a) for a in ph.arrays()))
+
+    def gbs_set_coils(self, sens):
+        """Receive-coil sensitivities S(k, p): complex (P, K) array or tensor
+        (None: one coil of unit sensitivity).  Signals then have P rows."""
+        if sens is None:
+            self._check(lib.gbs_set_coils(self._h, 1, None, None))
+            self._coils, self.n_coils = (), 1
+            return
+        st = torch.as_tensor(sens)
+        if st.dim() != 2 or st.shape[1] != self.K:
+            raise ValueError(f"sensitivities must be (P, K={self.K}), got {tuple(st.shape)}")
+        re = st.real.to(self.device, torch.float32).contiguous()
+        im = (st.imag if st.is_complex() else torch.zeros_like(st.real)).to(self.device, torch.float32).contiguous()
+        self._check(lib.gbs_set_coils(self._h, st.shape[0], _ptr(re), _ptr(im)))
+        self._coils, self.n_coils = (re, im), st.shape[0]  # the library keeps views
+
+    set_coils = gbs_set_coils
 
     def gbs_set_sequence(self, seq):
         import numpy as np
@@ -240,22 +262,25 @@ class Simulator:
         return {"K": info.K, "n_blocks": info.n_blocks, "total_steps": info.total_steps,
                 "total_samples": info.total_samples, "stepped_steps": info.stepped_steps,
                 "n_groups": list(info.n_groups), "groups_valid": bool(info.groups_valid),
-                "n_tissue_groups": info.n_tissue_groups}
+                "n_tissue_groups": info.n_tissue_groups, "n_coils": info.n_coils}
 
     info = gbs_get_info
 
     def gbs_simulate(self, mode=GBS_GROUPED, m_init=None, m_out=None, sig_out=None, flags=0,
                      stats=False):
-        """Returns (M (3, K) float32 device tensor, signal complex128 device tensor[, stats])."""
+        """Returns (M (3, K) float32 device tensor, signal complex128 device tensor[, stats]).
+        The signal is (N,) for one coil and (P, N) after set_coils with P rows."""
         if m_out is None:
             m_out = torch.empty(3, self.K, device=self.device, dtype=torch.float32)
         if sig_out is None:
-            sig_out = torch.empty(max(self.n_samples, 1), 2, device=self.device, dtype=torch.float64)
+            sig_out = torch.empty(max(self.n_coils * self.n_samples, 1), 2, device=self.device, dtype=torch.float64)
         mi = None if m_init is None else m_init.to(self.device, torch.float32).contiguous()
         st = gbs_stats() if stats else None
         self._check(lib.gbs_simulate(self._h, mode, flags, _ptr(mi), _ptr(m_out), _ptr(sig_out),
                                      ctypes.byref(st) if st is not None else None))
-        sig = torch.view_as_complex(sig_out)[: self.n_samples]
+        sig = torch.view_as_complex(sig_out)[: self.n_coils * self.n_samples]
+        if self.n_coils > 1:
+            sig = sig.view(self.n_coils, self.n_samples)
         return (m_out, sig, st.as_dict()) if stats else (m_out, sig)
 
     simulate = gbs_simulate

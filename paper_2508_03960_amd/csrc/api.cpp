@@ -112,6 +112,12 @@ struct gbs_ctx {
     // no-grads groups (GBS_AX_N): (0, T1, T2, df) per group, and the group of each x-group
     int64_t n_tissue = -1;
     DevBuf ttab, tmap;
+    // receive coils (gbs_set_coils; caller-owned views [n_coils][K] in natural
+    // order) and their group-sorted copy (planes re, im per coil, Kpad each)
+    int32_t n_coils = 1;
+    const float *coil_re = nullptr, *coil_im = nullptr;
+    DevBuf coil_l;
+    bool coil_l_valid = false;
     // per-simulate buffers
     DevBuf tabs, gsum, partial, jobs, samp, flag, state64;
     std::vector<char> host_jobs;  // kept alive until the next call
@@ -219,7 +225,7 @@ int gbs_destroy(gbs_ctx *ctx) {
                       &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->tabs, &ctx->gsum, &ctx->partial, &ctx->jobs,
                       &ctx->samp, &ctx->flag, &ctx->surr, &ctx->adj_ops, &ctx->adj_samp, &ctx->adj_ckpt, &ctx->adj_sub,
                       &ctx->adj_sig, &ctx->adj_grf, &ctx->adj_gt, &ctx->state64, &ctx->m_final,
-                      &ctx->csamp, &ctx->cache, &ctx->ttab, &ctx->tmap};
+                      &ctx->csamp, &ctx->cache, &ctx->ttab, &ctx->tmap, &ctx->coil_l};
     for (DevBuf *b : bufs) b->release();
     for (int a = 0; a < 3; ++a) {
         ctx->gid[a].release();
@@ -248,6 +254,9 @@ int gbs_set_phantom(gbs_ctx *ctx, int64_t K, const float *x, const float *y, con
     ctx->groups_valid = false;
     ctx->gp.valid = false;
     ctx->adj_ready = false;
+    ctx->n_coils = 1;  // sensitivities belong to the previous phantom
+    ctx->coil_re = ctx->coil_im = nullptr;
+    ctx->coil_l_valid = false;
     PhantomPtrs ph{x, y, z, t1, t2, df_hz, m0};
     ALLOC(ctx->flag, 256);
     HIPCHK(launch_fill_f64(ctx->flag.as<double>(), 1, ctx->stream));
@@ -259,6 +268,33 @@ int gbs_set_phantom(gbs_ctx *ctx, int64_t K, const float *x, const float *y, con
     ctx->K = K;
     ctx->ph = ph;
     ctx->has_ph = true;
+    return GBS_OK;
+}
+
+int gbs_set_coils(gbs_ctx *ctx, int32_t n_coils, const float *sens_re, const float *sens_im) {
+    if (!ctx) return GBS_E_INVALID;
+    if (!ctx->has_ph) return fail(ctx, GBS_E_STATE, "gbs_set_coils before gbs_set_phantom");
+    if (n_coils < 1 || n_coils > GBS_MAX_COILS)
+        return fail(ctx, GBS_E_INVALID, "n_coils must be in [1, " + std::to_string(GBS_MAX_COILS) + "]");
+    if (!sens_re != !sens_im) return fail(ctx, GBS_E_INVALID, "sens_re and sens_im must both be set or both null");
+    if (!sens_re && n_coils != 1) return fail(ctx, GBS_E_INVALID, "null sensitivities need n_coils = 1");
+    HIPCHK(hipSetDevice(ctx->device));
+    if (sens_re) {
+        ALLOC(ctx->flag, 256);
+        HIPCHK(launch_fill_f64(ctx->flag.as<double>(), 1, ctx->stream));
+        const int64_t n = (int64_t)n_coils * ctx->K;
+        HIPCHK(launch_check_finite(n, sens_re, ctx->flag.as<int>(), ctx->stream));
+        HIPCHK(launch_check_finite(n, sens_im, ctx->flag.as<int>(), ctx->stream));
+        int bad = 0;
+        HIPCHK(hipMemcpyAsync(&bad, ctx->flag.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (bad) return fail(ctx, GBS_E_INVALID, "coil sensitivities have NaN/inf values");
+    }
+    ctx->n_coils = n_coils;
+    ctx->coil_re = sens_re;
+    ctx->coil_im = sens_im;
+    ctx->coil_l_valid = false;
+    ctx->gp.valid = false;
     return GBS_OK;
 }
 
@@ -306,6 +342,7 @@ int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
     HIPCHK(hipSetDevice(ctx->device));
     ctx->groups_valid = false;
     ctx->gp.valid = false;
+    ctx->coil_l_valid = false;
     const int64_t K = ctx->K;
     const int64_t cap = (8 * K + 1023) / 1024 * 1024;  // padded layout is at most 8 K long
     const size_t scratch_bytes = group_scratch_bytes(K) + 4096;
@@ -426,6 +463,7 @@ int gbs_get_info(gbs_ctx *ctx, gbs_info *info) {
     info->groups_valid = ctx->groups_valid ? 1 : 0;
     info->device = ctx->device;
     info->n_tissue_groups = ctx->groups_valid ? ctx->n_tissue : -1;
+    info->n_coils = ctx->n_coils;
     return GBS_OK;
 }
 
@@ -514,6 +552,18 @@ PlainArgs step_args(gbs_ctx *ctx, const StepOp &op, const PhantomPtrs &ph, int64
 }
 
 }  // namespace
+
+// Readout samples taken by per-isochromat stepping (RF during an ADC block, or a
+// block the grouped plan cannot classify) carry no coil weights.
+static int check_coil_plan(gbs_ctx *ctx, const Plan &plan) {
+    if (!ctx->coil_re) return GBS_OK;
+    for (const Op &op : plan.ops)
+        if (op.kind == 1 && op.step.sample_hi > op.step.sample_lo)
+            return fail(ctx, GBS_E_INVALID,
+                        "coil sensitivities with a readout that is stepped per isochromat (block " +
+                            std::to_string(op.step.block) + ")");
+    return GBS_OK;
+}
 
 static int run_plain(gbs_ctx *ctx, const float *m_init, float *m_out, double *sig_out, bool fp32,
                      gbs_stats *st) {
@@ -712,7 +762,7 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
     for (size_t i = 0; i < plan.adc.size(); ++i) {
         const AdcJob &j = plan.adc[i];
         g.gsum_off[i] = goff;
-        goff += (size_t)ctx->ng[j.axis];
+        goff += (size_t)ctx->ng[j.axis] * (size_t)ctx->n_coils;  // one block of sums per coil
         samp_off[i] = soff;
         soff += (size_t)s.blocks[j.block].n_samples;
         g.max_adc_groups = std::max(g.max_adc_groups, (int)ctx->ng[j.axis]);
@@ -814,16 +864,20 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
                       std::fabs(h[n].y - (h[0].y + n * dcyc)) <= 1e-9;
             }
         }
-        if (lin) {
-            lj.push_back(AdcLinJob{ns, (int32_t)ctx->ng[j.axis], ctx->gsum.as<double2>() + g.gsum_off[i],
-                                   ctx->gtab[j.axis].as<float4>(), h[0].x, dtau, h[0].y, dcyc, b.sample_offset});
-            g.max_adclin_groups = std::max(g.max_adclin_groups, (int)ctx->ng[j.axis]);
-        } else {
-            aj.push_back(AdcJobDev{ns, (int32_t)ctx->ng[j.axis], ctx->gsum.as<double2>() + g.gsum_off[i],
-                                   ctx->gtab[j.axis].as<float4>(), ctx->samp.as<double2>() + samp_off[i],
-                                   b.sample_offset});
-            g.max_adc_groups = std::max(g.max_adc_groups, (int)ctx->ng[j.axis]);
-            g.max_adc_samples = std::max(g.max_adc_samples, ns);
+        // coil p: its own block of group sums, its own row of the signal
+        for (int32_t p = 0; p < ctx->n_coils; ++p) {
+            const double2 *gs = ctx->gsum.as<double2>() + g.gsum_off[i] + (size_t)p * (size_t)ctx->ng[j.axis];
+            const int64_t so = (int64_t)p * s.total_samples + b.sample_offset;
+            if (lin) {
+                lj.push_back(AdcLinJob{ns, (int32_t)ctx->ng[j.axis], gs, ctx->gtab[j.axis].as<float4>(), h[0].x,
+                                       dtau, h[0].y, dcyc, so});
+                g.max_adclin_groups = std::max(g.max_adclin_groups, (int)ctx->ng[j.axis]);
+            } else {
+                aj.push_back(AdcJobDev{ns, (int32_t)ctx->ng[j.axis], gs, ctx->gtab[j.axis].as<float4>(),
+                                       ctx->samp.as<double2>() + samp_off[i], so});
+                g.max_adc_groups = std::max(g.max_adc_groups, (int)ctx->ng[j.axis]);
+                g.max_adc_samples = std::max(g.max_adc_samples, ns);
+            }
         }
     }
 
@@ -866,6 +920,7 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
             o.emit_cy = kGammaBar * p.emit.m[1];
             o.emit_cz = g.zbuilt ? 0.0 : kGammaBar * p.emit.m[2];
             o.gsum = ctx->gsum.as<double2>() + g.gsum_off[p.adc_job];
+            o.gsum_stride = (int32_t)ctx->ng[p.emit_axis];
             fl += 8.0 + 6.0 * ((o.emit_ztab != nullptr) + (o.emit_cy != 0.0) + (o.emit_cz != 0.0));
         }
         int need = 0;
@@ -999,6 +1054,7 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     }
     const GroupedPlan &g = ctx->gp;
     const Plan &plan = g.plan;
+    if (int rc = check_coil_plan(ctx, plan)) return rc;
     const bool zbuilt = g.zbuilt;
     const int grid = plain_grid(ctx->Kint);
     char *tb = ctx->tabs.as<char>();
@@ -1054,6 +1110,23 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     base.zv = ctx->zi.as<float4>();
     const PhantomPtrs iph{ctx->xi.as<float>(), ctx->yi.as<float>(), ctx->zi.as<float>(), ctx->t1i.as<float>(),
                           ctx->t2i.as<float>(), ctx->dfi.as<float>(), ctx->m0i.as<float>()};
+    if (ctx->coil_re) {  // sensitivities in layout order (padding slots: 0)
+        const int64_t Kp = ctx->Kpad;
+        if (!ctx->coil_l_valid) {
+            ALLOC(ctx->coil_l, sizeof(float) * 2 * (size_t)ctx->n_coils * (size_t)Kp);
+            float *cl = ctx->coil_l.as<float>();
+            for (int32_t p = 0; p < ctx->n_coils; ++p) {
+                HIPCHK(launch_gather_padded(Kp, ctx->perm.as<int32_t>(), ctx->coil_re + (size_t)p * K,
+                                            cl + (size_t)(2 * p) * Kp, ctx->stream));
+                HIPCHK(launch_gather_padded(Kp, ctx->perm.as<int32_t>(), ctx->coil_im + (size_t)p * K,
+                                            cl + (size_t)(2 * p + 1) * Kp, ctx->stream));
+            }
+            ctx->coil_l_valid = true;
+        }
+        base.coil = ctx->coil_l.as<float4>();
+        base.n_coils = ctx->n_coils;
+        base.coil_plane = Kp / 4;
+    }
     if (profile) {
         const size_t need = 2 * (g.segs.size() + 1);
         while (ctx->pev.size() < need) {
@@ -1181,11 +1254,13 @@ static int run_cached(gbs_ctx *ctx, const float *m_init, float *m_out, double *s
         ctx->cplan_valid = true;
     }
     const Plan &plan = ctx->cplan;
+    if (int rc = check_coil_plan(ctx, plan)) return rc;
     const size_t n_entries = plan.rf.size();
     ALLOC(ctx->state64, sizeof(double) * 3 * (size_t)K);
     if (n_entries) ALLOC(ctx->cache, sizeof(float4) * 3 * (size_t)K * n_entries);
     const int pgrid = plain_grid(K), agrid = direct_adc_grid(K);
-    ALLOC(ctx->partial, sizeof(double2) * (size_t)std::max(pgrid, agrid) * kMaxSamplesPerLaunch);
+    ALLOC(ctx->partial,
+          sizeof(double2) * (size_t)std::max(pgrid, agrid) * kMaxSamplesPerLaunch * (size_t)ctx->n_coils);
     if (profile) {
         const size_t need = 2 * plan.ops.size();
         while (ctx->pev.size() < need) {
@@ -1235,9 +1310,14 @@ static int run_cached(gbs_ctx *ctx, const float *m_init, float *m_out, double *s
             a.samp = ctx->csamp.as<double4>() + ctx->csamp_off[oi];
             a.n_samples = c.sample_hi - c.sample_lo;
             a.partial = ctx->partial.as<double2>();
+            a.coil_re = ctx->coil_re;
+            a.coil_im = ctx->coil_im;
+            a.n_coils = ctx->coil_re ? ctx->n_coils : 1;
             HIPCHK(launch_direct_adc(a, agrid, ctx->stream));
-            HIPCHK(launch_plain_finalize(ctx->partial.as<double2>(), agrid, a.n_samples,
-                                         sig_out + 2 * (b.sample_offset + c.sample_lo), ctx->stream));
+            for (int32_t p = 0; p < a.n_coils; ++p)  // partials of coil p: [grid][n_samples] block p
+                HIPCHK(launch_plain_finalize(
+                    ctx->partial.as<double2>() + (size_t)p * agrid * a.n_samples, agrid, a.n_samples,
+                    sig_out + 2 * ((int64_t)p * ctx->seq.total_samples + b.sample_offset + c.sample_lo), ctx->stream));
         } else {  // 2: cached transition (composed at first use); 4: final map
             const CachedOp &c = op.cached;
             CachedArgs a{};
@@ -1312,8 +1392,10 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
         std::memset(stats, 0, sizeof(*stats));
         HIPCHK(hipEventRecord(ctx->ev[0], ctx->stream));
     }
+    if (ctx->coil_re && mode == GBS_PLAIN)
+        return fail(ctx, GBS_E_INVALID, "coil sensitivities need GBS_GROUPED or GBS_CACHED");
     if (ctx->seq.total_samples > 0)
-        HIPCHK(launch_fill_f64(sig_out, 2 * ctx->seq.total_samples, ctx->stream));
+        HIPCHK(launch_fill_f64(sig_out, 2 * (int64_t)ctx->n_coils * ctx->seq.total_samples, ctx->stream));
     const bool profile = (flags & GBS_PROFILE) != 0;
     int n_timed = 0;
     int rc = mode == GBS_PLAIN    ? run_plain(ctx, m_init, m_out, sig_out, (flags & GBS_PLAIN_FP32) != 0, stats)

@@ -53,8 +53,14 @@ struct DirectAdcArgs {
     const float *min_x, *min_y;
     const double4 *samp;
     int32_t n_samples;  // 1 .. 256
-    double2 *partial;   // [gridDim.x][n_samples] per-workgroup sums
+    // Receive coils (Eq. 6 with S(k, p)): sensitivities [n_coils][K] in the
+    // caller's order, or null for one coil of unit sensitivity
+    const float *coil_re, *coil_im;
+    int32_t n_coils;     // 1 .. kMaxCoils
+    double2 *partial;    // [n_coils][gridDim.x][n_samples] per-workgroup sums
 };
+
+constexpr int kMaxCoils = 8;
 
 hipError_t launch_cached(const CachedArgs &a, int mode, hipStream_t st);
 int direct_adc_grid(int64_t K);

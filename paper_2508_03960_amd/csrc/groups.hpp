@@ -17,6 +17,10 @@ hipError_t launch_invert(int64_t n, const int32_t *perm, int32_t *inv, hipStream
 hipError_t launch_zero_padding(int64_t n, const int32_t *perm, float *m0, hipStream_t st);
 hipError_t launch_gather_f32(int64_t K, int64_t Kpad, const int32_t *perm, const float *src, float *dst,
                              hipStream_t st);
+// dst[i] <- src[perm[i]], 0 where perm[i] < 0 (layout padding), for i < n
+hipError_t launch_gather_padded(int64_t n, const int32_t *perm, const float *src, float *dst, hipStream_t st);
+// *bad <- 1 if any of a[0 .. n) is NaN or infinite (*bad is not cleared)
+hipError_t launch_check_finite(int64_t n, const float *a, int *bad, hipStream_t st);
 // dst row g (12 doubles) <- src row map[g], for g < n
 hipError_t launch_expand_rows(const double *src, const int32_t *map, int64_t n, double *dst, hipStream_t st);
 hipError_t launch_gather_i32(int64_t K, int64_t Kpad, const int32_t *perm, const int32_t *src,

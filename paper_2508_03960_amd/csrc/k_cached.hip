@@ -125,12 +125,16 @@ __global__ __launch_bounds__(kCachedBlock) void k_cached(CachedArgs a) {
     }
 }
 
+template <bool COILS>
 __global__ __launch_bounds__(kAdcBlock) void k_direct_adc(DirectAdcArgs a) {
+    constexpr int MC = COILS ? kMaxCoils : 1;
     __shared__ double4 pos[kAdcBlock];  // x, y, z, df
     __shared__ float4 mag[kAdcBlock];   // Mx, My, -log2(e) / T2, 0
+    __shared__ float2 sen[MC][kAdcBlock];  // S(k, p) of the chunk (coils only)
     __shared__ double2 red[kAdcBlock];
     const int t = threadIdx.x;
     const int ns = a.n_samples;
+    const int P = COILS ? a.n_coils : 1;
     const int G = kAdcBlock / ns;  // isochromat slices per chunk
     const int cnt = kAdcBlock / G;
     const int n = t % ns, g = t / ns;
@@ -138,13 +142,15 @@ __global__ __launch_bounds__(kAdcBlock) void k_direct_adc(DirectAdcArgs a) {
     const double4 c = active ? a.samp[n] : make_double4(0.0, 0.0, 0.0, 0.0);
     const float tau = (float)c.w;
     const int64_t K = a.K;
-    double acc_re = 0.0, acc_im = 0.0;
+    double acc_re[MC], acc_im[MC];
+#pragma unroll
+    for (int p = 0; p < MC; ++p) acc_re[p] = acc_im[p] = 0.0;
     for (int64_t base = (int64_t)blockIdx.x * kAdcBlock; base < K; base += (int64_t)gridDim.x * kAdcBlock) {
         const int64_t k = base + t;
-        double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
+        double4 q0 = make_double4(0.0, 0.0, 0.0, 0.0);
         float4 m = make_float4(0.f, 0.f, 0.f, 0.f);  // padding slots add nothing
         if (k < K) {
-            p = make_double4(a.ph.x[k], a.ph.y[k], a.ph.z[k], a.ph.df[k]);
+            q0 = make_double4(a.ph.x[k], a.ph.y[k], a.ph.z[k], a.ph.df[k]);
             float mx = 0.f, my = 0.f;
             if (a.s64_in) {
                 mx = (float)a.s64_in[k];
@@ -156,11 +162,19 @@ __global__ __launch_bounds__(kAdcBlock) void k_direct_adc(DirectAdcArgs a) {
             m = make_float4(mx, my, (float)(-kLog2e / (double)a.ph.t2[k]), 0.f);
         }
         __syncthreads();  // the previous chunk has been read
-        pos[t] = p;
+        pos[t] = q0;
         mag[t] = m;
+        if (COILS) {
+#pragma unroll
+            for (int p = 0; p < MC; ++p)
+                if (p < P) sen[p][t] = k < K ? make_float2(a.coil_re[p * K + k], a.coil_im[p * K + k])
+                                             : make_float2(0.f, 0.f);
+        }
         __syncthreads();
         if (active) {
-            float sr = 0.f, si = 0.f;
+            float sr[MC], si[MC];
+#pragma unroll
+            for (int p = 0; p < MC; ++p) sr[p] = si[p] = 0.f;
             auto add = [&](int j) {
                 const double4 q = pos[j];
                 const float4 v = mag[j];
@@ -169,27 +183,46 @@ __global__ __launch_bounds__(kAdcBlock) void k_direct_adc(DirectAdcArgs a) {
                 sincos_rev(cyc, &s, &co);
                 const float e = __builtin_amdgcn_exp2f(tau * v.z);  // exp(-tau / T2)
                 // (Mx + i My) exp(-i 2 pi cyc)
-                sr = fmaf(e, fmaf(v.x, co, v.y * s), sr);
-                si = fmaf(e, fmaf(v.y, co, -v.x * s), si);
+                const float tr = e * fmaf(v.x, co, v.y * s), ti = e * fmaf(v.y, co, -v.x * s);
+                if (COILS) {
+#pragma unroll
+                    for (int p = 0; p < MC; ++p)
+                        if (p < P) {
+                            const float2 w = sen[p][j];
+                            sr[p] = fmaf(tr, w.x, fmaf(-ti, w.y, sr[p]));
+                            si[p] = fmaf(tr, w.y, fmaf(ti, w.x, si[p]));
+                        }
+                } else {
+                    sr[0] += tr;
+                    si[0] += ti;
+                }
             };
             // slice g takes chunk entries g, g + G, ...: cnt of them (a
             // wave-uniform count), and one more when 256 is not a multiple of G
 #pragma unroll 4
             for (int i = 0; i < cnt; ++i) add(g + i * G);
             if (g + cnt * G < kAdcBlock) add(g + cnt * G);
-            acc_re += sr;
-            acc_im += si;
+#pragma unroll
+            for (int p = 0; p < MC; ++p) {
+                acc_re[p] += sr[p];
+                acc_im[p] += si[p];
+            }
         }
     }
-    red[t] = make_double2(acc_re, acc_im);
-    __syncthreads();
-    if (t < ns) {
-        double re = 0.0, im = 0.0;
-        for (int q = 0; q < G; ++q) {
-            re += red[q * ns + t].x;
-            im += red[q * ns + t].y;
+#pragma unroll
+    for (int p = 0; p < MC; ++p) {
+        if (p >= P) break;
+        if (p > 0) __syncthreads();  // the previous coil's sums have been read
+        red[t] = make_double2(acc_re[p], acc_im[p]);
+        __syncthreads();
+        if (t < ns) {
+            double re = 0.0, im = 0.0;
+            for (int q = 0; q < G; ++q) {
+                re += red[q * ns + t].x;
+                im += red[q * ns + t].y;
+            }
+            a.partial[((int64_t)p * gridDim.x + blockIdx.x) * ns + t] = make_double2(re, im);
         }
-        a.partial[(int64_t)blockIdx.x * ns + t] = make_double2(re, im);
     }
 }
 
@@ -214,7 +247,12 @@ int direct_adc_grid(int64_t K) {
 
 hipError_t launch_direct_adc(const DirectAdcArgs &a, int grid, hipStream_t st) {
     if (a.n_samples < 1 || a.n_samples > kAdcBlock || grid < 1 || grid > kAdcMaxGrid) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_direct_adc, dim3(grid), dim3(kAdcBlock), 0, st, a);
+    if (a.coil_re) {
+        if (!a.coil_im || a.n_coils < 1 || a.n_coils > kMaxCoils) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_direct_adc<true>, dim3(grid), dim3(kAdcBlock), 0, st, a);
+    } else {
+        hipLaunchKernelGGL(k_direct_adc<false>, dim3(grid), dim3(kAdcBlock), 0, st, a);
+    }
     return hipGetLastError();
 }
 

@@ -644,7 +644,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     }
                 }
             };
-            if (GENERAL && (op.emit_cz != 0.0 || op.emit_axis == 1)) {
+            if (GENERAL && (a.coil || op.emit_cz != 0.0 || op.emit_axis == 1)) {
                 float wr[NI], wi[NI], vr[NI], vi[NI];
                 if (yph) y_phase(wr, wi);
 #pragma unroll
@@ -659,7 +659,36 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     vr[c] = mx[c] * ar - my[c] * ai;
                     vi[c] = mx[c] * ai + my[c] * ar;
                 }
-                if (op.emit_axis == 1) {
+                if (a.coil) {  // every coil: members weighted by S(k, p), then its own group sums
+#pragma unroll 1
+                    for (int p = 0; p < a.n_coils; ++p) {
+                        float sre[NI], sim[NI], ur[NI], ui[NI];
+#pragma unroll
+                        for (int c = 0; c < NI; ++c) sre[c] = sim[c] = 0.f;
+                        if (act) {
+#pragma unroll
+                            for (int q = 0; q < NQ; ++q) {
+                                ld4(a.coil + 2 * p * a.coil_plane, i4 + q, sre + 4 * q);
+                                ld4(a.coil + (2 * p + 1) * a.coil_plane, i4 + q, sim + 4 * q);
+                            }
+                        }
+#pragma unroll
+                        for (int c = 0; c < NI; ++c) {
+                            ur[c] = vr[c] * sre[c] - vi[c] * sim[c];
+                            ui[c] = vr[c] * sim[c] + vi[c] * sre[c];
+                        }
+                        double2 *gs = op.gsum + (int64_t)p * op.gsum_stride;
+                        if (op.emit_axis == 1) {
+                            emit_items<NI>(gy, ur, ui, act, gs);
+                        } else {
+                            const float sr = tree_sum<NI>(ur), si = tree_sum<NI>(ui);
+                            if (op.emit_axis == 0)
+                                emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, gs);
+                            else
+                                emit_thread(gz, false, sr, si, act, gs);
+                        }
+                    }
+                } else if (op.emit_axis == 1) {
                     emit_items<NI>(gy, vr, vi, act, op.gsum);
                 } else {
                     const float sr = tree_sum<NI>(vr), si = tree_sum<NI>(vi);
@@ -723,7 +752,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
     if (a.n4 <= 0 || a.n_ops <= 0) return hipSuccess;
     if (a.n4 % (SWEEP_NI_FAST / 4)) return hipErrorInvalidValue;  // the layout pads runs to multiples of 8
-    if (a.need & (kNeedGy | kNeedZ)) {
+    if ((a.need & (kNeedGy | kNeedZ)) || a.coil) {
         hipLaunchKernelGGL(k_sweep_general, dim3((unsigned)((a.n4 + 255) / 256)), dim3(256), 0, st, a);
     } else {
         const int64_t n = a.n4 / (SWEEP_NI_FAST / 4);

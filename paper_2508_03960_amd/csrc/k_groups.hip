@@ -172,12 +172,37 @@ hipError_t launch_gather_i32(int64_t K, int64_t Kpad, const int32_t *perm, const
     return hipGetLastError();
 }
 
+__global__ void k_gather_padded(int64_t n, const int32_t *__restrict__ perm, const float *__restrict__ src,
+                                float *__restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = perm[i];
+        dst[i] = k >= 0 ? src[k] : 0.0f;
+    }
+}
+
+__global__ void k_check_finite(int64_t n, const float *__restrict__ a, int *__restrict__ bad) {
+    bool ok = true;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        ok = ok && isfinite(a[i]);
+    if (!ok) *bad = 1;
+}
+
 __global__ void k_expand_rows(const double *__restrict__ src, const int32_t *__restrict__ map, int64_t n,
                               double *__restrict__ dst) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= 12 * n) return;
     const int64_t g = i / 12;
     dst[i] = src[12 * (int64_t)map[g] + (i - 12 * g)];
+}
+
+hipError_t launch_gather_padded(int64_t n, const int32_t *perm, const float *src, float *dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather_padded, grid_for(n), dim3(256), 0, st, n, perm, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite(int64_t n, const float *a, int *bad, hipStream_t st) {
+    hipLaunchKernelGGL(k_check_finite, grid_for(n), dim3(256), 0, st, n, a, bad);
+    return hipGetLastError();
 }
 
 hipError_t launch_expand_rows(const double *src, const int32_t *map, int64_t n, double *dst, hipStream_t st) {

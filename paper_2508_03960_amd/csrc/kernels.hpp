@@ -67,7 +67,7 @@ struct SweepOp {
     int32_t flags;
     int32_t rf_axis;
     int32_t emit_axis;
-    int32_t pad;
+    int32_t gsum_stride;     // groups of the emission axis: coil p sums at gsum + p * gsum_stride
     const float4 *pre_xtab;  // per x-group (Re a, Im a, E1, 0); null: no x factor
     const float2 *pre_ztab;  // per z-group phase; null: none
     double pre_cy, pre_cz;   // direct y / z phase coefficients (cycles per metre); 0: none
@@ -104,6 +104,13 @@ struct SweepArgs {
     // First sweep of a run from the default state (0, 0, M0): nothing is read
     // from mx / my / mz.
     int32_t fresh;
+    // Receive-coil sensitivities (Eq. 6 with S(k, p)), or null for one coil of
+    // unit sensitivity: planes re, im of coil 0, re, im of coil 1, ... of
+    // coil_plane float4 words each in layout order.  Every emission weights
+    // its members by S(k, p) before the group sums of coil p (general sweep).
+    const float4 *coil;
+    int32_t n_coils;
+    int64_t coil_plane;
 };
 
 // ---- tables ---------------------------------------------------------------

@@ -155,6 +155,18 @@ def random_subset_indices(K, n, seed=7):
     return np.sort(rng.choice(K, size=n, replace=False)).astype(np.int64)
 
 
+def coil_maps(ph: "Phantom", n_coils: int, radius=0.16, width=0.12, seed=31) -> np.ndarray:
+    """Receive-coil sensitivities S(k, p), complex (n_coils, K): coils on a
+    circle of `radius` (m) around the z axis, Gaussian magnitude of `width`
+    (m) about each coil's centre and a seeded constant phase per coil."""
+    rng = np.random.default_rng(seed)
+    ang = 2 * np.pi * np.arange(n_coils) / n_coils
+    phase = rng.uniform(-np.pi, np.pi, n_coils)
+    x, y = ph.x.astype(np.float64), ph.y.astype(np.float64)
+    d2 = (x[None, :] - radius * np.cos(ang)[:, None]) ** 2 + (y[None, :] - radius * np.sin(ang)[:, None]) ** 2
+    return np.exp(-d2 / (2 * width ** 2)) * np.exp(1j * phase)[:, None]
+
+
 # --------------------------------------------------------------------------
 # sequences
 # --------------------------------------------------------------------------
