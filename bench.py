@@ -277,6 +277,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the signal-gradient leg")
     ap.add_argument("--no-cached", action="store_true",
                     help="skip the conventional method with per-isochromat transition caching")
+    ap.add_argument("--no-coils", action="store_true",
+                    help="skip the multi-coil FSE (4 and 8 receive coils, grouped)")
     ap.add_argument("--no-nograds", action="store_true",
                     help="skip the fat-saturated FSE (no-grads groups vs x-groups)")
     ap.add_argument("--no-table2", action="store_true",
@@ -406,6 +408,21 @@ def main():
             out["cached"]["epi"] = cached_leg(sim, gb, epi, m_out, sig_c, n_c, M_epi, s_epi[:, 0] + 1j * s_epi[:, 1])
             out["epi"]["speedup_grouped_vs_cached"] = out["cached"]["epi"]["ms"] / out["epi"]["grouped_ms"]
             log(f"EPI cached: {out['cached']['epi']}")
+
+    # ---- receive coils: the grouped FSE with 4 and 8 coil sensitivities ------------------
+    if not args.no_coils:
+        sim.set_sequence(fse)
+        res = {"single_coil_ms": sec * 1e3}
+        for P in (4, 8):
+            sim.set_coils(synth.coil_maps(ph, P))
+            sig_c = torch.empty(P * fse.total_samples, 2, device=dev, dtype=torch.float64)
+            sec_c, _ = timed_runs(sim, gb, gb.GBS_GROUPED, max(1, min(args.steps, 3)), 1, m_out, sig_c)
+            res[f"coils_{P}_ms"] = sec_c * 1e3
+        sim.set_coils(None)
+        # the sensitivities stream from HBM at every emission: 8 bytes per isochromat, coil and readout
+        res["coil_bytes_per_step_P8"] = 8.0 * 8 * K * int((fse.btype == 2).sum())
+        out["coils_fse"] = res
+        log(f"coils: {res}")
 
     # ---- no-grads groups: the FSE with a CHESS fat-saturation pulse per shot -------------
     if not args.no_nograds:

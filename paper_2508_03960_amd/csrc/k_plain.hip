@@ -21,7 +21,8 @@
 // ADC samples (Eq. 6): at each sample boundary a wavefront sums its lanes with
 // DPP, lane 63 adds the wave total into a per-wave LDS accumulator
 // (compensated FP32, or FP64); at the end each workgroup writes one FP64
-// partial per sample, and a finalize kernel adds the partials in a fixed order.
+// partial per sample, and a finalize kernel (one workgroup per sample) adds
+// the partials in a fixed order.
 #include "device_math.hpp"
 #include "kernels.hpp"
 #include "rotation.hpp"
@@ -212,18 +213,32 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a) {
     }
 }
 
-__global__ void k_plain_finalize(const double2 *__restrict__ partial, int nblk, int ns,
-                                 double *__restrict__ sig) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= ns) return;
+// One workgroup per sample: thread t adds partials t, t + 256, ... in order,
+// then a fixed LDS tree adds the 256 thread sums (the same order every run).
+__global__ __launch_bounds__(256) void k_plain_finalize(const double2 *__restrict__ partial, int nblk, int ns,
+                                                        double *__restrict__ sig) {
+    __shared__ double2 red[256];
+    const int n = blockIdx.x, t = threadIdx.x;
     double re = 0.0, im = 0.0;
-    for (int b = 0; b < nblk; ++b) {
+    for (int b = t; b < nblk; b += 256) {
         const double2 p = partial[(int64_t)b * ns + n];
         re += p.x;
         im += p.y;
     }
-    sig[2 * n] += re;
-    sig[2 * n + 1] += im;
+    red[t] = make_double2(re, im);
+    __syncthreads();
+#pragma unroll
+    for (int w = 128; w >= 1; w /= 2) {
+        if (t < w) {
+            red[t].x += red[t + w].x;
+            red[t].y += red[t + w].y;
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        sig[2 * n] += red[0].x;
+        sig[2 * n + 1] += red[0].y;
+    }
 }
 
 int plain_grid(int64_t K) {
@@ -251,8 +266,7 @@ hipError_t launch_plain(const PlainArgs &a, bool has_b1, bool fp32, int grid, hi
 hipError_t launch_plain_finalize(const double2 *partial, int nblk, int n_samples, double *sig,
                                  hipStream_t st) {
     if (n_samples <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_plain_finalize, dim3((n_samples + 255) / 256), dim3(256), 0, st, partial,
-                       nblk, n_samples, sig);
+    hipLaunchKernelGGL(k_plain_finalize, dim3(n_samples), dim3(256), 0, st, partial, nblk, n_samples, sig);
     return hipGetLastError();
 }
 
