@@ -62,7 +62,8 @@ extern "C" {
 #define GBS_AX_X 1u
 #define GBS_AX_Y 2u
 #define GBS_AX_Z 4u
-#define GBS_AX_N 8u /* no-grads groups: key (T1, T2, dB0) alone */
+#define GBS_AX_N 8u   /* no-grads groups: key (T1, T2, dB0) alone */
+#define GBS_AX_XZ 16u /* two-axis groups: key (x, z, T1, T2, dB0), for Gx+Gz with-RF subsequences */
 
 /* ---- simulation modes and flags -------------------------------------- */
 #define GBS_PLAIN 0
@@ -103,6 +104,7 @@ typedef struct gbs_info {
     int32_t device;
     int64_t n_tissue_groups; /* no-grads groups (GBS_AX_N); -1 when not built */
     int64_t n_coils;         /* receive coils of the signal (1 unless gbs_set_coils set more) */
+    int64_t n_xz_groups;     /* two-axis (x, z) groups (GBS_AX_XZ); -1 when not built */
 } gbs_info;
 
 /* Filled by gbs_simulate when non-null.  Times come from HIP events. */
@@ -197,13 +199,20 @@ int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, co
  * in lexicographic key order.  GBS_AX_N adds the no-grads groups of key
  * (T1, T2, dB0), numbered in ascending (T1, T2, dB0) order: a with-RF
  * subsequence without gradients then composes one transition per such group
- * instead of one per x-group (the result is the same).  `axes` must include
- * GBS_AX_X (the x groups order the stored copy); blocks whose type needs an
- * axis that was not built are stepped per isochromat, except that no-grads
- * blocks use the x groups when GBS_AX_N is absent.  The context
+ * instead of one per x-group (the result is the same).  GBS_AX_XZ (with
+ * GBS_AX_X and GBS_AX_Z) adds the two-axis groups of key (x, z, T1, T2,
+ * dB0), which are the runs of equal (x-group, z-group) in the stored copy: a
+ * with-RF subsequence whose only gradients are Gx and Gz (an oblique slice)
+ * then composes one transition per such group instead of being stepped per
+ * isochromat (with-ADC subsequences with two gradients are still stepped).
+ * `axes` must include GBS_AX_X (the x groups order the stored copy); blocks
+ * whose type needs an axis that was not built are stepped per isochromat,
+ * except that no-grads blocks use the x groups when GBS_AX_N is absent.  The
+ * context
  * stores a copy of the phantom in group-sorted order (about 13 float/int32
  * words per isochromat).  Synchronizes the stream.
- * Errors: GBS_E_STATE (no phantom), GBS_E_INVALID (no GBS_AX_X, unknown bits),
+ * Errors: GBS_E_STATE (no phantom), GBS_E_INVALID (no GBS_AX_X, unknown bits,
+ * GBS_AX_XZ without GBS_AX_Z),
  * GBS_E_NOMEM, GBS_E_HIP.
  */
 int gbs_build_groups(gbs_ctx *ctx, uint32_t axes);

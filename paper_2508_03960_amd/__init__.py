@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libgbloch.so")
 
 GBS_OK, GBS_E_INVALID, GBS_E_STATE, GBS_E_HIP, GBS_E_NOMEM = 0, -1, -2, -3, -4
 GBS_BLOCK_RF, GBS_BLOCK_ADC, GBS_BLOCK_RELAX = 1, 2, 3
-GBS_AX_X, GBS_AX_Y, GBS_AX_Z, GBS_AX_N = 1, 2, 4, 8
-GBS_AX_ALL = GBS_AX_X | GBS_AX_Y | GBS_AX_Z | GBS_AX_N
+GBS_AX_X, GBS_AX_Y, GBS_AX_Z, GBS_AX_N, GBS_AX_XZ = 1, 2, 4, 8, 16
+GBS_AX_ALL = GBS_AX_X | GBS_AX_Y | GBS_AX_Z | GBS_AX_N | GBS_AX_XZ
 GBS_PLAIN, GBS_GROUPED, GBS_CACHED = 0, 1, 2
 GBS_ASYNC = 1
 GBS_PLAIN_FP32 = 2
@@ -47,7 +47,8 @@ class gbs_info(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int64), ("n_blocks", ctypes.c_int64), ("total_steps", ctypes.c_int64),
                 ("total_samples", ctypes.c_int64), ("stepped_steps", ctypes.c_int64),
                 ("n_groups", ctypes.c_int64 * 3), ("groups_valid", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("n_tissue_groups", ctypes.c_int64), ("n_coils", ctypes.c_int64)]
+                ("device", ctypes.c_int32), ("n_tissue_groups", ctypes.c_int64), ("n_coils", ctypes.c_int64),
+                ("n_xz_groups", ctypes.c_int64)]
 
 
 class gbs_stats(ctypes.Structure):
@@ -262,7 +263,8 @@ class Simulator:
         return {"K": info.K, "n_blocks": info.n_blocks, "total_steps": info.total_steps,
                 "total_samples": info.total_samples, "stepped_steps": info.stepped_steps,
                 "n_groups": list(info.n_groups), "groups_valid": bool(info.groups_valid),
-                "n_tissue_groups": info.n_tissue_groups, "n_coils": info.n_coils}
+                "n_tissue_groups": info.n_tissue_groups, "n_coils": info.n_coils,
+                "n_xz_groups": info.n_xz_groups}
 
     info = gbs_get_info
 

@@ -24,6 +24,7 @@
 #include "kernels.hpp"
 #include "mlp.hpp"
 #include "mlp_api.hpp"
+#include "pairs.hpp"
 #include "plan.hpp"
 
 using namespace gbs;
@@ -63,6 +64,8 @@ struct GroupedPlan {
     std::vector<size_t> rf_off, gsum_off;
     // no-grads transitions composed per tissue group: (composed rows, x-group rows)
     std::vector<std::pair<size_t, size_t>> expand;
+    // Gx+Gz transitions composed per two-axis group: (arena offset, RF job)
+    std::vector<std::pair<size_t, int>> pair_jobs;
     size_t gsum_count = 0;
     int64_t max_rf_groups = 0, max_tab = 0;
     int max_adc_groups = 0, max_adc_samples = 0;
@@ -112,6 +115,10 @@ struct gbs_ctx {
     // no-grads groups (GBS_AX_N): (0, T1, T2, df) per group, and the group of each x-group
     int64_t n_tissue = -1;
     DevBuf ttab, tmap;
+    // two-axis groups (GBS_AX_XZ): the layout's runs of equal (x-group,
+    // z-group); run of every 4-slot quad, and (x, T1, T2, df), z per run
+    int64_t n_runs = -1;
+    DevBuf run_of4, rtab, rz;
     // receive coils (gbs_set_coils; caller-owned views [n_coils][K] in natural
     // order) and their group-sorted copy (planes re, im per coil, Kpad each)
     int32_t n_coils = 1;
@@ -225,7 +232,8 @@ int gbs_destroy(gbs_ctx *ctx) {
                       &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->tabs, &ctx->gsum, &ctx->partial, &ctx->jobs,
                       &ctx->samp, &ctx->flag, &ctx->surr, &ctx->adj_ops, &ctx->adj_samp, &ctx->adj_ckpt, &ctx->adj_sub,
                       &ctx->adj_sig, &ctx->adj_grf, &ctx->adj_gt, &ctx->state64, &ctx->m_final,
-                      &ctx->csamp, &ctx->cache, &ctx->ttab, &ctx->tmap, &ctx->coil_l};
+                      &ctx->csamp, &ctx->cache, &ctx->ttab, &ctx->tmap, &ctx->coil_l, &ctx->run_of4,
+                      &ctx->rtab, &ctx->rz};
     for (DevBuf *b : bufs) b->release();
     for (int a = 0; a < 3; ++a) {
         ctx->gid[a].release();
@@ -337,8 +345,10 @@ int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, co
 int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
     if (!ctx) return GBS_E_INVALID;
     if (!ctx->has_ph) return fail(ctx, GBS_E_STATE, "gbs_build_groups before gbs_set_phantom");
-    if (!(axes & GBS_AX_X) || (axes & ~15u))
-        return fail(ctx, GBS_E_INVALID, "axes must include GBS_AX_X and only X|Y|Z|N");
+    if (!(axes & GBS_AX_X) || (axes & ~31u))
+        return fail(ctx, GBS_E_INVALID, "axes must include GBS_AX_X and only X|Y|Z|N|XZ");
+    if ((axes & GBS_AX_XZ) && !(axes & GBS_AX_Z))
+        return fail(ctx, GBS_E_INVALID, "GBS_AX_XZ needs GBS_AX_Z");
     HIPCHK(hipSetDevice(ctx->device));
     ctx->groups_valid = false;
     ctx->gp.valid = false;
@@ -440,6 +450,48 @@ int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
         HIPCHK(launch_gather_f32(Kpad, Kpad, src, from[i], dst[i]->as<float>(), ctx->stream));
     }
     HIPCHK(launch_zero_padding(Kpad, ctx->perm.as<int32_t>(), ctx->m0i.as<float>(), ctx->stream));
+    // two-axis groups: the runs of equal (x-group, z-group) in the layout
+    ctx->n_runs = -1;
+    if (axes & GBS_AX_XZ) {
+        const int64_t n4 = kint / 4;
+        DevBuf flags;
+        if (flags.ensure((size_t)n4) != hipSuccess) {
+            cleanup();
+            return fail(ctx, GBS_E_NOMEM, "run flag allocation failed");
+        }
+        HIPCHK(launch_run_flags(n4, ctx->gid[0].as<int32_t>(), ctx->gid[2].as<int32_t>(), flags.as<uint8_t>(),
+                                ctx->stream));
+        std::vector<uint8_t> hf((size_t)n4);
+        HIPCHK(hipMemcpyAsync(hf.data(), flags.p, (size_t)n4, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        flags.release();
+        std::vector<int32_t> run_of((size_t)n4), first;
+        int32_t r = -1;
+        for (int64_t q = 0; q < n4; ++q) {
+            if (hf[q]) {
+                ++r;
+                first.push_back((int32_t)q);
+            }
+            run_of[q] = r;
+        }
+        const int64_t R = (int64_t)first.size();
+        DevBuf dfirst;
+        ALLOC(ctx->run_of4, sizeof(int32_t) * (size_t)n4);
+        ALLOC(ctx->rtab, sizeof(float4) * (size_t)R);
+        ALLOC(ctx->rz, sizeof(float) * (size_t)R);
+        ALLOC(dfirst, sizeof(int32_t) * (size_t)R);
+        HIPCHK(hipMemcpy(ctx->run_of4.p, run_of.data(), sizeof(int32_t) * (size_t)n4, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(dfirst.p, first.data(), sizeof(int32_t) * (size_t)R, hipMemcpyHostToDevice));
+        HIPCHK(launch_run_table(R, dfirst.as<int32_t>(), ctx->xi.as<float>(), ctx->zi.as<float>(), ctx->t1i.as<float>(),
+                                ctx->t2i.as<float>(), ctx->dfi.as<float>(), ctx->rtab.as<float4>(), ctx->rz.as<float>(),
+                                ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        ctx->n_runs = R;
+    } else {
+        ctx->run_of4.release();
+        ctx->rtab.release();
+        ctx->rz.release();
+    }
     for (int a = 0; a < 3; ++a) ALLOC(ctx->ms[a], 4 * Kpad);
     ALLOC(ctx->m_final, 16 * Kpad);
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -464,6 +516,7 @@ int gbs_get_info(gbs_ctx *ctx, gbs_info *info) {
     info->device = ctx->device;
     info->n_tissue_groups = ctx->groups_valid ? ctx->n_tissue : -1;
     info->n_coils = ctx->n_coils;
+    info->n_xz_groups = ctx->groups_valid ? ctx->n_runs : -1;
     return GBS_OK;
 }
 
@@ -654,6 +707,7 @@ static bool matches_pulse(const gbs_ctx *ctx, const RfJob &r) {
 static double sweep_bytes_per_iso(int need, bool write_m, bool fresh, bool final_rows) {
     double b = fresh ? 0.0 : 8.0;
     if (need & kNeedMz) b += fresh ? 4.0 : 8.0;
+    if (need & kNeedRun) b += 1.0;  // one int32 per 4 isochromats
     b += 4.0 * (!!(need & kNeedGx) + !!(need & kNeedGy) + !!(need & kNeedGz) + !!(need & kNeedY) + !!(need & kNeedZ));
     if (write_m) b += final_rows ? 16.0 : ((need & kNeedMz) ? 12.0 : 8.0);
     return b;
@@ -680,14 +734,19 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
     size_t off = 0;
     g.rf_off.resize(plan.rf.size());
     g.expand.clear();
+    g.pair_jobs.clear();
+    // groups behind the transition rows of an op's rf_axis (kPairRows: two-axis groups)
+    auto rows_groups = [&](int A) { return A == kPairRows ? ctx->n_runs : ctx->ng[A]; };
+    auto rows_table = [&](int A) { return A == kPairRows ? ctx->rtab.as<float4>() : ctx->gtab[A].as<float4>(); };
     std::vector<size_t> comp_off(plan.rf.size());
     for (size_t i = 0; i < plan.rf.size(); ++i) {
         const bool tissue = plan.rf[i].axis == kTissueAxis;
-        const int64_t G = tissue ? ctx->n_tissue : ctx->ng[plan.rf[i].axis];
+        const int64_t G = tissue ? ctx->n_tissue : plan.rf[i].axis == kPairAxis ? ctx->n_runs : ctx->ng[plan.rf[i].axis];
         comp_off[i] = off;
-        g.max_rf_groups = std::max(g.max_rf_groups, G);
+        if (plan.rf[i].axis != kPairAxis) g.max_rf_groups = std::max(g.max_rf_groups, G);  // k_compose's grid
         off = align256(off + sizeof(double) * 12 * (size_t)G);
         g.rf_off[i] = comp_off[i];
+        if (plan.rf[i].axis == kPairAxis) g.pair_jobs.emplace_back(comp_off[i], (int)i);
         if (tissue) {  // expanded to x-group rows for the fold
             g.rf_off[i] = off;
             off = align256(off + sizeof(double) * 12 * (size_t)Gx);
@@ -737,11 +796,13 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
         if (p.rf_axis >= 0) {
             // the tissue part and the own-axis phase of the pre map fold into T'
             const int A = p.rf_axis;
+            // (two-axis groups fold the x phase; their z phase stays a z-group table)
             ot[i].ttab = off;
-            off = align256(off + sizeof(float4) * 3 * (size_t)ctx->ng[A]);
-            folds.push_back(FoldPlan{ot[i].ttab, A, p.rf_id, p.has_pre ? 1 : 0, p.pre.tau, kGammaBar * p.pre.m[A]});
+            off = align256(off + sizeof(float4) * 3 * (size_t)rows_groups(A));
+            const double cyc = kGammaBar * p.pre.m[A == kPairRows ? 0 : A];
+            folds.push_back(FoldPlan{ot[i].ttab, A, p.rf_id, p.has_pre ? 1 : 0, p.pre.tau, cyc});
             if (p.has_pre) {
-                if (A != 0 && p.pre.m[0] != 0.0) ot[i].pre_x = x_table(2, 0.0, kGammaBar * p.pre.m[0]);
+                if (A != 0 && A != kPairRows && p.pre.m[0] != 0.0) ot[i].pre_x = x_table(2, 0.0, kGammaBar * p.pre.m[0]);
                 if (A != 2 && g.zbuilt && p.pre.m[2] != 0.0) ot[i].pre_z = z_table(kGammaBar * p.pre.m[2]);
             }
         } else if (p.has_pre) {
@@ -797,6 +858,11 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
     for (size_t i = 0; i < plan.rf.size(); ++i) {
         const RfJob &r = plan.rf[i];
         // the surrogate's transition is not composed here (n_groups = 0 skips it)
+        if (r.axis == kPairAxis) {  // composed by its own kernel (k_compose_pair)
+            rj[i] = RfJobDev{0, (int32_t)r.n_steps, 0, ctx->d_wave.as<StepW>() + r.step_offset, nullptr,
+                             (double *)(tb + comp_off[i])};
+            continue;
+        }
         if (r.axis == kTissueAxis) {  // no gradients: the coordinate column of the table is unused
             rj[i] = RfJobDev{0, (int32_t)r.n_steps, ctx->n_tissue, ctx->d_wave.as<StepW>() + r.step_offset,
                              ctx->ttab.as<float4>(), (double *)(tb + comp_off[i])};
@@ -838,9 +904,9 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
     std::vector<FoldJob> fj(folds.size());
     for (size_t i = 0; i < folds.size(); ++i) {
         const FoldPlan &f = folds[i];
-        fj[i] = FoldJob{f.axis, f.has_pre, ctx->ng[f.axis], (const double *)(tb + g.rf_off[f.rf_id]),
-                        ctx->gtab[f.axis].as<float4>(), f.tau, f.cyc, (float4 *)(tb + f.out_off)};
-        g.max_fold_groups = std::max(g.max_fold_groups, ctx->ng[f.axis]);
+        fj[i] = FoldJob{f.axis, f.has_pre, rows_groups(f.axis), (const double *)(tb + g.rf_off[f.rf_id]),
+                        rows_table(f.axis), f.tau, f.cyc, (float4 *)(tb + f.out_off)};
+        g.max_fold_groups = std::max(g.max_fold_groups, rows_groups(f.axis));
     }
     // readouts whose sample times and moments are arithmetic in the sample index take the
     // geometric-sequence evaluation; the rest the direct one
@@ -927,6 +993,7 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
         if ((o.flags & kOpRf) || (o.flags & kPreMz)) need |= kNeedMz;
         if (o.pre_xtab || (o.flags & kOpEmit) || p.rf_axis == 0) need |= kNeedGx;
         if (p.rf_axis == 1 || p.emit_axis == 1) need |= kNeedGy;
+        if (p.rf_axis == kPairRows) need |= kNeedRun;
         if (o.pre_ztab || o.emit_ztab || p.rf_axis == 2 || p.emit_axis == 2) need |= kNeedGz;
         if (o.pre_cy != 0.0 || o.emit_cy != 0.0) need |= kNeedY;
         if (o.pre_cz != 0.0 || o.emit_cz != 0.0) need |= kNeedZ;
@@ -1081,6 +1148,12 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
         HIPCHK(mlp_exact_async(m, tuples, nullptr, g.surr_groups, fb, T64, ctx->stream));
     }
     HIPCHK(launch_compose((const RfJobDev *)(jb + g.o_rf), g.n_rf, g.max_rf_groups, s.dt, ctx->stream));
+    for (const auto &pj : g.pair_jobs) {
+        const RfJob &r = plan.rf[pj.second];
+        HIPCHK(launch_compose_pair(ctx->n_runs, ctx->rtab.as<float4>(), ctx->rz.as<float>(),
+                                   ctx->d_wave.as<StepW>() + r.step_offset, (int32_t)r.n_steps, s.dt,
+                                   (double *)(tb + pj.first), ctx->stream));
+    }
     for (const auto &e : g.expand)
         HIPCHK(launch_expand_rows((const double *)(tb + e.first), ctx->tmap.as<int32_t>(), ctx->ng[0],
                                   (double *)(tb + e.second), ctx->stream));
@@ -1108,6 +1181,7 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     base.gid_z = ctx->gid[2].as<int4>();
     base.yv = ctx->yi.as<float4>();
     base.zv = ctx->zi.as<float4>();
+    base.run_of4 = ctx->run_of4.as<int32_t>();
     const PhantomPtrs iph{ctx->xi.as<float>(), ctx->yi.as<float>(), ctx->zi.as<float>(), ctx->t1i.as<float>(),
                           ctx->t2i.as<float>(), ctx->dfi.as<float>(), ctx->m0i.as<float>()};
     if (ctx->coil_re) {  // sensitivities in layout order (padding slots: 0)

@@ -470,7 +470,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
         mx[c] = my[c] = mz[c] = m0[c] = yv[c] = zv[c] = 0.f;
         gy[c] = 0;
     }
-    int gx = 0, gz = 0;
+    int gx = 0, gz = 0, run = 0;
     if (act) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
@@ -493,6 +493,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
         }
         if (need & kNeedGx) gx = a.gid_x[i4].x;
         if (need & kNeedGz) gz = a.gid_z[i4].x;
+        if (GENERAL && (need & kNeedRun)) run = a.run_of4[i4];
     }
     // x-groups are contiguous runs in this order: is the wavefront inside one?
     const int gx0 = __builtin_amdgcn_readfirstlane(gx);
@@ -599,7 +600,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     r1 = uniform_row(tt, 3 * gx0 + 1);
                     r2 = uniform_row(tt, 3 * gx0 + 2);
                 } else {
-                    const int g = op.rf_axis == 0 ? gx : gz;
+                    const int g = op.rf_axis == 0 ? gx : (GENERAL && op.rf_axis == 3 ? run : gz);
                     r0 = gather_row(tt, 3 * g);
                     r1 = gather_row(tt, 3 * g + 1);
                     r2 = gather_row(tt, 3 * g + 2);
@@ -752,7 +753,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
     if (a.n4 <= 0 || a.n_ops <= 0) return hipSuccess;
     if (a.n4 % (SWEEP_NI_FAST / 4)) return hipErrorInvalidValue;  // the layout pads runs to multiples of 8
-    if ((a.need & (kNeedGy | kNeedZ)) || a.coil) {
+    if ((a.need & (kNeedGy | kNeedZ | kNeedRun)) || a.coil) {
         hipLaunchKernelGGL(k_sweep_general, dim3((unsigned)((a.n4 + 255) / 256)), dim3(256), 0, st, a);
     } else {
         const int64_t n = a.n4 / (SWEEP_NI_FAST / 4);

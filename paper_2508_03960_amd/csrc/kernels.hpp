@@ -81,7 +81,7 @@ struct SweepOp {
 };
 
 // Per-isochromat arrays a sweep reads.
-enum { kNeedMz = 1, kNeedGx = 2, kNeedGy = 4, kNeedGz = 8, kNeedY = 16, kNeedZ = 32 };
+enum { kNeedMz = 1, kNeedGx = 2, kNeedGy = 4, kNeedGz = 8, kNeedY = 16, kNeedZ = 32, kNeedRun = 64 };
 
 // A sweep applies ops[0 .. n_ops) in order to every isochromat while its
 // state stays in registers: one read and at most one write of M per launch.
@@ -111,6 +111,9 @@ struct SweepArgs {
     const float4 *coil;
     int32_t n_coils;
     int64_t coil_plane;
+    // Two-axis group (run of equal x- and z-group) of every 4-slot quad, for
+    // operations whose transition rows are per such group (rf_axis 3; general sweep)
+    const int32_t *run_of4;
 };
 
 // ---- tables ---------------------------------------------------------------

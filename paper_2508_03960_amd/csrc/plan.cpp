@@ -111,6 +111,7 @@ std::vector<BlockClass> classify(const HostSeq &s) {
                 c.moment[a] += (double)v * s.dt;
             }
         }
+        c.axes_mask = (act[0] ? 1 : 0) | (act[1] ? 2 : 0) | (act[2] ? 4 : 0);
         int na = act[0] + act[1] + act[2];
         if (na == 0)
             c.gtype = GT_NONE;
@@ -242,6 +243,20 @@ Plan plan_grouped(const HostSeq &s, const std::vector<BlockClass> &cls, uint32_t
         }
         const int axis = c.gtype == GT_NONE ? GT_X : c.gtype;
         const bool known = c.gtype != GT_MIXED && (axes_built & (1u << axis));
+        if (k.type == GBS_BLOCK_RF && c.gtype == GT_MIXED && c.axes_mask == 5 && (axes_built & GBS_AX_XZ)) {
+            // Gx and Gz together (an oblique slice): one transition per (x, z) group
+            flush();
+            cur = PassOp{};
+            cur.has_pre = P.any();
+            cur.pre = P;
+            cur.rf_axis = kPairRows;
+            cur.rf_id = rf_lookup(p, hashes, s, b, kPairAxis, c.gtype);
+            cur.write_m = true;
+            have_cur = true;
+            P = Map{};
+            ++p.n_rf_grouped;
+            continue;
+        }
         if (k.type == GBS_BLOCK_RF && known) {
             flush();
             cur = PassOp{};

@@ -17,6 +17,10 @@ enum GradType { GT_X = 0, GT_Y = 1, GT_Z = 2, GT_NONE = 3, GT_MIXED = 4 };
 // RfJob::axis of a no-grads transition composed per tissue group (key T1, T2,
 // dB0; built with GBS_AX_N) and applied through the x-group rows.
 constexpr int kTissueAxis = 3;
+// RfJob::axis of a Gx+Gz transition composed per two-axis group (key x, z,
+// T1, T2, dB0; built with GBS_AX_XZ), and PassOp::rf_axis of its rows.
+constexpr int kPairAxis = 4;
+constexpr int kPairRows = 3;
 
 struct HostSeq {
     std::vector<gbs_block> blocks;
@@ -29,6 +33,7 @@ struct HostSeq {
 struct BlockClass {
     bool has_b1 = false;   // any nonzero B1 sample in the block
     int gtype = GT_NONE;   // exact-zero test per axis over the whole block
+    int axes_mask = 0;     // bit a: gradient a is nonzero somewhere in the block
     double moment[3] = {0, 0, 0};  // sum_j G_j dt over the block (FP64)
 };
 

@@ -317,9 +317,12 @@ def readout_gradient(dwell, fov):
 
 
 def gre_sequence(n_lines=32, n_read=64, dwell_steps=10, fov=(0.200, 0.200), thk=0.005,
-                 flip_deg=30.0, rf_steps=2000, te=5e-3, tr=20e-3, dt=1e-6, tbw=4.0):
+                 flip_deg=30.0, rf_steps=2000, te=5e-3, tr=20e-3, dt=1e-6, tbw=4.0, tilt_deg=0.0):
     """Spoiled 2D gradient echo: sinc RF with Gz, rephase + prephase + phase
-    encode (relaxation), Gx readout (ADC), rewind + spoil to TR (relaxation)."""
+    encode (relaxation), Gx readout (ADC), rewind + spoil to TR (relaxation).
+    tilt_deg tilts the slice normal from z toward x (an oblique slice: the
+    slice-select gradient and its rephaser gain an x component)."""
+    sn, cs = np.sin(np.deg2rad(tilt_deg)), np.cos(np.deg2rad(tilt_deg))
     sb = SeqBuilder(dt, name=f"gre{n_lines}x{n_read}")
     b1 = sinc_pulse(rf_steps, dt, np.deg2rad(flip_deg), tbw)
     gz = slice_gradient(rf_steps, dt, thk, tbw)
@@ -333,21 +336,23 @@ def gre_sequence(n_lines=32, n_read=64, dwell_steps=10, fov=(0.200, 0.200), thk=
     spoil_z = 4.0 / (GAMMA_BAR * thk)
     for line in range(n_lines):
         my = (line - n_lines // 2) / (GAMMA_BAR * fov[1])
-        sb.rf(b1, (0.0, 0.0, gz))
-        sb.relax(tau_pre, (-g_ro * echo_step * dt, my, -0.5 * gz * rf_steps * dt))
+        sb.rf(b1, (sn * gz, 0.0, cs * gz))
+        sb.relax(tau_pre, (-g_ro * echo_step * dt - sn * 0.5 * gz * rf_steps * dt, my, -cs * 0.5 * gz * rf_steps * dt))
         sb.adc(ro_steps, (g_ro, 0.0, 0.0), samples)
         sb.relax(tau_post, (2.0 * g_ro * ro_steps * dt, -my, spoil_z))
     return sb.build(kind="gre", n_lines=n_lines, n_read=n_read, fov=fov)
 
 
 def fse_sequence(n_shots=16, etl=16, n_read=256, dwell_steps=4, fov=(0.256, 0.256), thk=0.010,
-                 rf_steps=3000, esp=8e-3, tr=3.0, dt=1e-6, tbw=4.0, fat_sat=False):
+                 rf_steps=3000, esp=8e-3, tr=3.0, dt=1e-6, tbw=4.0, fat_sat=False, tilt_deg=0.0):
     """CPMG fast spin echo: 90x then `etl` 180y refocusing pulses (sinc with Gz),
     each echo read out with Gx; phase-encode line = etl_index*n_shots + shot.
     Crushers bracket every refocusing pulse; relaxation to TR ends each shot.
     fat_sat: every shot starts with a 2 ms CHESS 90-degree pulse at -440 Hz
     (a no-grads with-RF subsequence) and a 1 ms spoiler, taken from the end
-    of the TR."""
+    of the TR.  tilt_deg tilts the slice normal from z toward x (an oblique
+    slice): slice selection, its rephaser and the crushers gain an x part."""
+    sn, cs = np.sin(np.deg2rad(tilt_deg)), np.cos(np.deg2rad(tilt_deg))
     sb = SeqBuilder(dt, name=f"fse{n_shots}x{etl}x{n_read}" + ("fs" if fat_sat else ""))
     chess = chess_pulse(2000, dt, np.pi / 2, -440.0) if fat_sat else None
     fs_time = 3e-3 if fat_sat else 0.0
@@ -377,18 +382,19 @@ def fse_sequence(n_shots=16, etl=16, n_read=256, dwell_steps=4, fov=(0.256, 0.25
         if fat_sat:
             sb.rf(chess, (0.0, 0.0, 0.0))
             sb.relax(1e-3, (8.0 / (GAMMA_BAR * fov[0]), 8.0 / (GAMMA_BAR * fov[1]), 8.0 / (GAMMA_BAR * thk)))
-        sb.rf(b90, (0.0, 0.0, gz))
-        sb.relax(tau_90_180, (P, 0.0, -0.5 * gz * rf_steps * dt + crush))
+        sb.rf(b90, (sn * gz, 0.0, cs * gz))
+        s_m = -0.5 * gz * rf_steps * dt + crush  # slice rephaser and crusher
+        sb.relax(tau_90_180, (P + sn * s_m, 0.0, cs * s_m))
         for e in range(etl):
             line = e * n_shots + shot
             my = (line - n_lines // 2) / (GAMMA_BAR * fov[1])
-            sb.rf(b180, (0.0, 0.0, gz))
-            sb.relax(tau_pre, (Q, my, crush))
+            sb.rf(b180, (sn * gz, 0.0, cs * gz))
+            sb.relax(tau_pre, (Q + sn * crush, my, cs * crush))
             sb.adc(ro_steps, (g_ro, 0.0, 0.0), samples)
             if e + 1 < etl:
-                sb.relax(tau_post, (0.0, -my, crush))
+                sb.relax(tau_post, (sn * crush, -my, cs * crush))
             else:
-                sb.relax(tau_end, (4.0 * g_ro * ro_steps * dt, -my, 4.0 * crush))
+                sb.relax(tau_end, (4.0 * g_ro * ro_steps * dt + sn * 4.0 * crush, -my, cs * 4.0 * crush))
     return sb.build(kind="fse", n_shots=n_shots, etl=etl, n_read=n_read, fov=fov)
 
 

@@ -96,9 +96,12 @@ def _misc_seq(dt=1e-6):
 
 
 def test_plan_classification(gb):
-    s = gb.gbs_plan_summary(_misc_seq())
+    s = gb.gbs_plan_summary(_misc_seq(), axes=gb.GBS_AX_X | gb.GBS_AX_Y | gb.GBS_AX_Z)
     assert s["fallback"] == 2 and s["b1zero"] == 1
     assert s["rf_grouped"] == 2 and s["adc_grouped"] == 1
+    # with two-axis groups the Gx+Gz RF block is grouped too; RF during ADC is still stepped
+    s = gb.gbs_plan_summary(_misc_seq())
+    assert s["fallback"] == 1 and s["rf_grouped"] == 3 and s["distinct_rf"] == 3
     # without y-groups the Gy-only readout is stepped per isochromat
     s = gb.gbs_plan_summary(_misc_seq(), axes=gb.GBS_AX_X | gb.GBS_AX_Z)
     assert s["fallback"] == 3 and s["adc_grouped"] == 0
@@ -106,7 +109,7 @@ def test_plan_classification(gb):
 
 def test_plan_no_grads_groups(gb):
     # GBS_AX_N changes where a no-grads transition is composed, not the counts
-    a = gb.gbs_plan_summary(_misc_seq(), axes=gb.GBS_AX_ALL)
+    a = gb.gbs_plan_summary(_misc_seq(), axes=gb.GBS_AX_X | gb.GBS_AX_Y | gb.GBS_AX_Z | gb.GBS_AX_N)
     b = gb.gbs_plan_summary(_misc_seq(), axes=gb.GBS_AX_X | gb.GBS_AX_Y | gb.GBS_AX_Z)
     assert a == b
     fs = synth.fse_sequence(n_shots=2, etl=2, n_read=16, fat_sat=True)

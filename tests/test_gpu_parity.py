@@ -95,11 +95,12 @@ def test_ragged_k_and_initial_state(gb):
     check_case(gb, "ragged+m_init", ph, seq, m_init=m_init)
 
 
-@pytest.mark.parametrize("axes", [15, 7, 5, 1])
+@pytest.mark.parametrize("axes", [31, 15, 7, 5, 1])
 def test_classification_paths(gb, axes):
     """Gx/Gy/no-grads RF, Gy/Gz readouts with ramps, mixed-gradient RF and ADC
     with RF (stepped per isochromat); fewer axes force more fallbacks; with
-    GBS_AX_N (15) the no-grads RF is composed per tissue group."""
+    GBS_AX_N (15) the no-grads RF is composed per tissue group, and with
+    GBS_AX_XZ (31) the Gx+Gz RF per two-axis group."""
     from tests.test_oracle_pins import _mini_sequences
     ph = synth.tiny_phantom(nx=9, ny=7, nz=3, n_classes=3, df_levels=3)
     for seq in _mini_sequences():
@@ -156,6 +157,36 @@ def test_no_grads_groups(gb):
     assert st["n_distinct_rf"] == 2 and st["n_fallback"] == 0, st
     dm, rel = errors(M15, s15, M7, s7)
     assert dm <= 1e-6 and rel <= 1e-6, (dm, rel)
+
+
+def test_two_axis_groups(gb):
+    """Gx+Gz with-RF subsequences (an oblique slice): with GBS_AX_XZ the
+    transition is composed once per (x, z, T1, T2, dB0) group, the runs of the
+    group-sorted layout; without it the block is stepped per isochromat.  Both
+    match the oracle; the group count is the number of distinct keys."""
+    ph = synth.tiny_phantom(nx=9, ny=7, nz=3, n_classes=3, df_levels=3)
+    keys = np.stack([ph.x, ph.z, ph.t1, ph.t2, ph.df], 1).astype(np.float32) + 0.0
+    n_xz = len(np.unique(keys, axis=0))
+    seq = synth.gre_sequence(n_lines=3, n_read=16, dwell_steps=4, rf_steps=400, te=2.5e-3, tr=6e-3, tilt_deg=30.0)
+    ref = oracle.simulate(ph, seq)
+    sim = gb.Simulator(0)
+    sim.set_phantom(ph)
+    sim.build_groups(gb.GBS_AX_ALL)
+    info = sim.info()
+    sim.close()
+    say(f"[gpu] two-axis: {info['n_xz_groups']} groups (expected {n_xz}) of K={ph.K}")
+    assert info["n_xz_groups"] == n_xz
+    check_case(gb, "oblique", ph, seq, modes=("grouped",), axes=31, ref=ref)
+    check_case(gb, "oblique/stepped", ph, seq, modes=("grouped",), axes=15, ref=ref)
+    M31, s31, st31 = run_gpu(gb, ph, seq, gb.GBS_GROUPED, axes=31)
+    M15, s15, st15 = run_gpu(gb, ph, seq, gb.GBS_GROUPED, axes=15)
+    assert st31["n_fallback"] == 0 and st15["n_fallback"] == 3, (st31, st15)
+    dm, rel = errors(M31, s31, M15, s15)
+    assert dm <= 1e-6 and rel <= 1e-6, (dm, rel)
+    # an oblique FSE: pending maps with x, y and z moments before every transition
+    ph2 = synth.brain_like_phantom(48, 40, 3)
+    fs = synth.fse_sequence(n_shots=2, etl=3, n_read=32, tilt_deg=20.0)
+    check_case(gb, "oblique fse", ph2, fs, modes=("grouped", "cached"), axes=31)
 
 
 def test_run_boundaries(gb):
