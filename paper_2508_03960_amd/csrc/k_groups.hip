@@ -278,12 +278,17 @@ hipError_t launch_zero_padding(int64_t n, const int32_t *perm, float *m0, hipStr
 
 size_t group_scratch_bytes(int64_t K) {
     size_t sort_tmp = 0, scan_tmp = 0, escan_tmp = 0;
-    hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, (const uint64_t *)nullptr, (uint64_t *)nullptr,
-                                       (const int32_t *)nullptr, (int32_t *)nullptr, (int)K, 0, 64);
-    hipcub::DeviceScan::InclusiveSum(nullptr, scan_tmp, (const int32_t *)nullptr, (int32_t *)nullptr, (int)K);
-    hipcub::DeviceScan::ExclusiveSum(nullptr, escan_tmp, (const int32_t *)nullptr, (int32_t *)nullptr, (int)K);
+    const bool sized =
+        hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                                           (const int32_t *)nullptr, (int32_t *)nullptr, (int)K, 0, 64) == hipSuccess &&
+        hipcub::DeviceScan::InclusiveSum(nullptr, scan_tmp, (const int32_t *)nullptr, (int32_t *)nullptr, (int)K) ==
+            hipSuccess &&
+        hipcub::DeviceScan::ExclusiveSum(nullptr, escan_tmp, (const int32_t *)nullptr, (int32_t *)nullptr, (int)K) ==
+            hipSuccess;
     size_t tmp = sort_tmp > scan_tmp ? sort_tmp : scan_tmp;
     if (escan_tmp > tmp) tmp = escan_tmp;
+    // a failed size query leaves generous room; the sorts and scans report their own errors
+    if (!sized) tmp = ((size_t)64 << 20) + 16 * (size_t)K;
     // the larger of group_axis (4 u64 + 3 i32 arrays) and build_layout (2 u64 + 7 i32), plus tmp
     return 4 * sizeof(uint64_t) * K + 7 * sizeof(int32_t) * K + tmp + 16 * 256;
 }

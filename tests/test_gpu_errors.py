@@ -57,6 +57,8 @@ def small():
 def test_call_order(gb):
     ph, seq = small()
     sim = gb.Simulator(0)
+    say("[gpu] errors: coils before a phantom")
+    assert code_of(gb, lambda: sim.set_coils(None)) == gb.GBS_E_STATE
     say("[gpu] errors: simulate / build_groups before their inputs")
     assert code_of(gb, lambda: sim.simulate(gb.GBS_PLAIN)) == gb.GBS_E_STATE
     assert code_of(gb, lambda: sim.build_groups()) == gb.GBS_E_STATE
@@ -69,6 +71,8 @@ def test_call_order(gb):
     assert code_of(gb, lambda: sim.simulate(gb.GBS_GROUPED)) == gb.GBS_E_STATE
     assert code_of(gb, lambda: sim.simulate(7)) == gb.GBS_E_INVALID  # no such mode
     assert code_of(gb, lambda: sim.build_groups(gb.GBS_AX_Y)) == gb.GBS_E_INVALID  # x axis is required
+    assert code_of(gb, lambda: sim.build_groups(gb.GBS_AX_X | gb.GBS_AX_XZ)) == gb.GBS_E_INVALID  # needs z
+    assert code_of(gb, lambda: sim.build_groups(gb.GBS_AX_ALL | 32)) == gb.GBS_E_INVALID  # unknown bit
     # GBS_SURROGATE without a network
     sim.build_groups()
     assert code_of(gb, lambda: sim.simulate(gb.GBS_GROUPED, flags=gb.GBS_SURROGATE)) == gb.GBS_E_INVALID
