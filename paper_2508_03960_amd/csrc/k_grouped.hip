@@ -235,6 +235,7 @@ hipError_t launch_tables(const TabJob *jobs, int n_jobs, int max_n, const float4
 #define SWEEP_WAVES_FAST 5
 #endif
 #define SWEEP_WAVES_GENERAL 3
+constexpr int kSweepMaxCoils = 8;  // receive coils one sweep launch weights (gbs_set_coils' limit)
 
 __device__ __forceinline__ void cmul(float &ar, float &ai, float br, float bi) {
     const float r = ar * br - ai * bi;
@@ -456,9 +457,10 @@ __device__ __forceinline__ void emit_items(const int *key, const float *vr, cons
 // share their x- and z-groups).  GENERAL = false drops what only y-group
 // transitions/emissions and direct z phases (no z groups) need, which frees
 // registers for occupancy.
-template <bool GENERAL, int NI>
+template <bool GENERAL, int NI, bool COILS = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
     constexpr int NQ = NI / 4;  // float4 words per array and thread
+    constexpr int MC = COILS ? kSweepMaxCoils : 1;
     const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool act = it < a.n4 / NQ;
     const int64_t i4 = it * NQ;
@@ -494,6 +496,20 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
         if (need & kNeedGx) gx = a.gid_x[i4].x;
         if (need & kNeedGz) gz = a.gid_z[i4].x;
         if (GENERAL && (need & kNeedRun)) run = a.run_of4[i4];
+    }
+    // receive-coil sensitivities of the thread's isochromats, held for the whole launch
+    float csr[MC][NI], csi[MC][NI];
+#pragma unroll
+    for (int p = 0; p < MC; ++p) {
+#pragma unroll
+        for (int c = 0; c < NI; ++c) csr[p][c] = csi[p][c] = 0.f;
+        if (COILS && act && p < a.n_coils) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                ld4(a.coil + 2 * p * a.coil_plane, i4 + q, csr[p] + 4 * q);
+                ld4(a.coil + (2 * p + 1) * a.coil_plane, i4 + q, csi[p] + 4 * q);
+            }
+        }
     }
     // x-groups are contiguous runs in this order: is the wavefront inside one?
     const int gx0 = __builtin_amdgcn_readfirstlane(gx);
@@ -645,7 +661,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     }
                 }
             };
-            if (GENERAL && (a.coil || op.emit_cz != 0.0 || op.emit_axis == 1)) {
+            if (GENERAL && (COILS || op.emit_cz != 0.0 || op.emit_axis == 1)) {
                 float wr[NI], wi[NI], vr[NI], vi[NI];
                 if (yph) y_phase(wr, wi);
 #pragma unroll
@@ -660,23 +676,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     vr[c] = mx[c] * ar - my[c] * ai;
                     vi[c] = mx[c] * ai + my[c] * ar;
                 }
-                if (a.coil) {  // every coil: members weighted by S(k, p), then its own group sums
-#pragma unroll 1
-                    for (int p = 0; p < a.n_coils; ++p) {
-                        float sre[NI], sim[NI], ur[NI], ui[NI];
+                if (COILS) {  // every coil: members weighted by S(k, p), then its own group sums
 #pragma unroll
-                        for (int c = 0; c < NI; ++c) sre[c] = sim[c] = 0.f;
-                        if (act) {
-#pragma unroll
-                            for (int q = 0; q < NQ; ++q) {
-                                ld4(a.coil + 2 * p * a.coil_plane, i4 + q, sre + 4 * q);
-                                ld4(a.coil + (2 * p + 1) * a.coil_plane, i4 + q, sim + 4 * q);
-                            }
-                        }
+                    for (int p = 0; p < MC; ++p) {
+                        if (p >= a.n_coils) break;
+                        float ur[NI], ui[NI];
 #pragma unroll
                         for (int c = 0; c < NI; ++c) {
-                            ur[c] = vr[c] * sre[c] - vi[c] * sim[c];
-                            ui[c] = vr[c] * sim[c] + vi[c] * sre[c];
+                            ur[c] = vr[c] * csr[p][c] - vi[c] * csi[p][c];
+                            ui[c] = vr[c] * csi[p][c] + vi[c] * csr[p][c];
                         }
                         double2 *gs = op.gsum + (int64_t)p * op.gsum_stride;
                         if (op.emit_axis == 1) {
@@ -750,10 +758,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES
     sweep_body<true, 4>(a);
 }
 
+// The general sweep with receive coils: the thread's sensitivities (up to
+// kSweepMaxCoils coils) stay in registers for the whole launch.
+__global__ __launch_bounds__(256) void k_sweep_coils(SweepArgs a) { sweep_body<true, 4, true>(a); }
+
 hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
     if (a.n4 <= 0 || a.n_ops <= 0) return hipSuccess;
     if (a.n4 % (SWEEP_NI_FAST / 4)) return hipErrorInvalidValue;  // the layout pads runs to multiples of 8
-    if ((a.need & (kNeedGy | kNeedZ | kNeedRun)) || a.coil) {
+    if (a.coil) {
+        if (a.n_coils < 1 || a.n_coils > kSweepMaxCoils) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_sweep_coils, dim3((unsigned)((a.n4 + 255) / 256)), dim3(256), 0, st, a);
+    } else if (a.need & (kNeedGy | kNeedZ | kNeedRun)) {
         hipLaunchKernelGGL(k_sweep_general, dim3((unsigned)((a.n4 + 255) / 256)), dim3(256), 0, st, a);
     } else {
         const int64_t n = a.n4 / (SWEEP_NI_FAST / 4);
