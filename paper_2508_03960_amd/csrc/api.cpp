@@ -796,11 +796,22 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
         if (p.rf_axis >= 0) {
             // the tissue part and the own-axis phase of the pre map fold into T'
             const int A = p.rf_axis;
-            // (two-axis groups fold the x phase; their z phase stays a z-group table)
-            ot[i].ttab = off;
-            off = align256(off + sizeof(float4) * 3 * (size_t)rows_groups(A));
+            // (two-axis groups fold the x phase; their z phase stays a z-group table).
+            // Ops with the same transition and the same folded part share one table.
             const double cyc = kGammaBar * p.pre.m[A == kPairRows ? 0 : A];
-            folds.push_back(FoldPlan{ot[i].ttab, A, p.rf_id, p.has_pre ? 1 : 0, p.pre.tau, cyc});
+            const int hp = p.has_pre ? 1 : 0;
+            const double tau = p.has_pre ? p.pre.tau : 0.0, fc = p.has_pre ? cyc : 0.0;
+            auto same = [&](const FoldPlan &f) {
+                return f.axis == A && f.rf_id == p.rf_id && f.has_pre == hp && f.tau == tau && f.cyc == fc;
+            };
+            const auto hit = std::find_if(folds.begin(), folds.end(), same);
+            if (hit != folds.end()) {
+                ot[i].ttab = hit->out_off;
+            } else {
+                ot[i].ttab = off;
+                off = align256(off + sizeof(float4) * 3 * (size_t)rows_groups(A));
+                folds.push_back(FoldPlan{ot[i].ttab, A, p.rf_id, hp, tau, fc});
+            }
             if (p.has_pre) {
                 if (A != 0 && A != kPairRows && p.pre.m[0] != 0.0) ot[i].pre_x = x_table(2, 0.0, kGammaBar * p.pre.m[0]);
                 if (A != 2 && g.zbuilt && p.pre.m[2] != 0.0) ot[i].pre_z = z_table(kGammaBar * p.pre.m[2]);

@@ -457,7 +457,7 @@ __device__ __forceinline__ void emit_items(const int *key, const float *vr, cons
 // share their x- and z-groups).  GENERAL = false drops what only y-group
 // transitions/emissions and direct z phases (no z groups) need, which frees
 // registers for occupancy.
-template <bool GENERAL, int NI, bool COILS = false>
+template <bool GENERAL, int NI, bool COILS = false, bool PAIRS = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
     constexpr int NQ = NI / 4;  // float4 words per array and thread
     constexpr int MC = COILS ? kSweepMaxCoils : 1;
@@ -495,7 +495,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
         }
         if (need & kNeedGx) gx = a.gid_x[i4].x;
         if (need & kNeedGz) gz = a.gid_z[i4].x;
-        if (GENERAL && (need & kNeedRun)) run = a.run_of4[i4];
+        if ((GENERAL || PAIRS) && (need & kNeedRun)) run = a.run_of4[i4];  // the thread's slots share a run
     }
     // receive-coil sensitivities of the thread's isochromats, held for the whole launch
     float csr[MC][NI], csi[MC][NI];
@@ -616,7 +616,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     r1 = uniform_row(tt, 3 * gx0 + 1);
                     r2 = uniform_row(tt, 3 * gx0 + 2);
                 } else {
-                    const int g = op.rf_axis == 0 ? gx : (GENERAL && op.rf_axis == 3 ? run : gz);
+                    const int g = op.rf_axis == 0 ? gx : ((GENERAL || PAIRS) && op.rf_axis == 3 ? run : gz);
                     r0 = gather_row(tt, 3 * g);
                     r1 = gather_row(tt, 3 * g + 1);
                     r2 = gather_row(tt, 3 * g + 2);
@@ -758,6 +758,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES
     sweep_body<true, 4>(a);
 }
 
+// The fast sweep for runs with two-axis (x, z) transitions: rows per run of
+// the layout (a thread's 8 slots lie in one run).  The run index is one
+// register more than the fast sweep holds at 5 waves per SIMD, so 4.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_pairs(
+    SweepArgs a) {
+    sweep_body<false, SWEEP_NI_FAST, false, true>(a);
+}
+
 // The general sweep with receive coils: the thread's sensitivities (up to
 // kSweepMaxCoils coils) stay in registers for the whole launch.
 __global__ __launch_bounds__(256) void k_sweep_coils(SweepArgs a) { sweep_body<true, 4, true>(a); }
@@ -768,11 +776,14 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
     if (a.coil) {
         if (a.n_coils < 1 || a.n_coils > kSweepMaxCoils) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_sweep_coils, dim3((unsigned)((a.n4 + 255) / 256)), dim3(256), 0, st, a);
-    } else if (a.need & (kNeedGy | kNeedZ | kNeedRun)) {
+    } else if (a.need & (kNeedGy | kNeedZ)) {
         hipLaunchKernelGGL(k_sweep_general, dim3((unsigned)((a.n4 + 255) / 256)), dim3(256), 0, st, a);
     } else {
         const int64_t n = a.n4 / (SWEEP_NI_FAST / 4);
-        hipLaunchKernelGGL(k_sweep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+        if (a.need & kNeedRun)
+            hipLaunchKernelGGL(k_sweep_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL(k_sweep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
     }
     return hipGetLastError();
 }
