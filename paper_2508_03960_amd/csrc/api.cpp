@@ -962,6 +962,8 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
     auto ptr4 = [&](size_t o) { return o == kNone ? (const float4 *)nullptr : (const float4 *)(tb + o); };
     auto ptr2 = [&](size_t o) { return o == kNone ? (const float2 *)nullptr : (const float2 *)(tb + o); };
     std::vector<SweepOp> sops;
+    std::vector<int> op_need;       // per sweep op: arrays it needs
+    std::vector<double> op_flops;   // per sweep op: algorithmic flops per isochromat
     auto add_op = [&](int pi) {
         const PassOp &p = passes[pi];
         const OpTabs &t = ot[pi];
@@ -1018,6 +1020,8 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
         sg.write_m = sg.write_m || (o.flags & (kOpPre | kOpRf));
         sg.flops_per_iso += fl;
         sops.push_back(o);
+        op_need.push_back(need);
+        op_flops.push_back(fl);
     };
     for (size_t i = 0; i < plan.ops.size(); ++i) {
         if (plan.ops[i].kind == 0)
@@ -1026,6 +1030,58 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
             g.exec.push_back({1, (int)i});
     }
     if (plan.final_pass) add_op((int)passes.size() - 1);
+
+    // Runs of at least kEmitRun emissions that leave the state alone (an EPI
+    // readout train) become sweeps of their own: the state is written once
+    // before them, and they run in the emission-only kernel, whose few live
+    // registers allow more waves per SIMD to hide the per-op load latency.
+    {
+        constexpr int kEmitRun = 16;
+        auto emit_only = [&](int o) {
+            return (sops[o].flags & kOpEmit) && !(sops[o].flags & (kOpPre | kOpRf | kPreMz));
+        };
+        std::vector<GroupedPlan::Seg> segs;
+        std::vector<int> remap(g.segs.size() + 1, 0);
+        std::vector<std::vector<int>> pieces(g.segs.size());
+        for (size_t si = 0; si < g.segs.size(); ++si) {
+            const GroupedPlan::Seg &sg = g.segs[si];
+            int o = sg.op_begin;
+            while (o < sg.op_end) {
+                int e = o;
+                while (e < sg.op_end && emit_only(e)) ++e;
+                const bool run = e - o >= kEmitRun;
+                if (!run) {  // up to the next long emission run
+                    e = o + 1;
+                    while (e < sg.op_end) {
+                        int f = e;
+                        while (f < sg.op_end && emit_only(f)) ++f;
+                        if (f - e >= kEmitRun) break;
+                        e = f > e ? f : e + 1;
+                    }
+                }
+                GroupedPlan::Seg piece{o, e, 0, false, 0.0, 0.0};
+                for (int q = o; q < e; ++q) {
+                    piece.need |= op_need[q];
+                    piece.write_m = piece.write_m || (sops[q].flags & (kOpPre | kOpRf));
+                    piece.flops_per_iso += op_flops[q];
+                }
+                if (run) piece.need |= kEmitOnly;
+                pieces[si].push_back((int)segs.size());
+                segs.push_back(piece);
+                o = e;
+            }
+        }
+        std::vector<std::pair<int, int>> exec;
+        for (const auto &it : g.exec) {
+            if (it.first != 0) {
+                exec.push_back(it);
+                continue;
+            }
+            for (int pi : pieces[it.second]) exec.push_back({0, pi});
+        }
+        g.segs.swap(segs);
+        g.exec.swap(exec);
+    }
 
     // y phases of consecutive emissions inside a sweep: direct evaluation, or
     // a complex recurrence when the coefficients step evenly (restarted every

@@ -235,6 +235,9 @@ hipError_t launch_tables(const TabJob *jobs, int n_jobs, int max_n, const float4
 #define SWEEP_WAVES_FAST 5
 #endif
 #define SWEEP_WAVES_GENERAL 3
+#ifndef SWEEP_WAVES_EMIT
+#define SWEEP_WAVES_EMIT 6
+#endif
 constexpr int kSweepMaxCoils = 8;  // receive coils one sweep launch weights (gbs_set_coils' limit)
 
 __device__ __forceinline__ void cmul(float &ar, float &ai, float br, float bi) {
@@ -457,7 +460,7 @@ __device__ __forceinline__ void emit_items(const int *key, const float *vr, cons
 // share their x- and z-groups).  GENERAL = false drops what only y-group
 // transitions/emissions and direct z phases (no z groups) need, which frees
 // registers for occupancy.
-template <bool GENERAL, int NI, bool COILS = false, bool PAIRS = false>
+template <bool GENERAL, int NI, bool COILS = false, bool PAIRS = false, bool EMIT = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
     constexpr int NQ = NI / 4;  // float4 words per array and thread
     constexpr int MC = COILS ? kSweepMaxCoils : 1;
@@ -480,7 +483,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 ld4(a.mx, i4 + q, mx + 4 * q);
                 ld4(a.my, i4 + q, my + 4 * q);
             }
-            if (need & kNeedMz) {
+            if (!EMIT && (need & kNeedMz)) {  // (an emitting-only sweep loads Mz at the end)
                 ld4(a.m0, i4 + q, m0 + 4 * q);
                 if (a.fresh) {
 #pragma unroll
@@ -532,7 +535,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
         // is folded into the thread's rows of T
         bool fold = false;
         float fr = 1.f, fi = 0.f;
-        if (op.flags & kOpPre) {
+        if (!EMIT && (op.flags & kOpPre)) {
             float e1 = 1.f;
             if (op.pre_xtab) {
                 const float4 v = x_row(op.pre_xtab, gx_uni, gx0, gx);
@@ -591,7 +594,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 for (int c = 0; c < NI; ++c) mz[c] = fmaf(e1, mz[c] - m0[c], m0[c]);
             }
         }
-        if ((op.flags & kOpRf) || fold) {
+        if (!EMIT && ((op.flags & kOpRf) || fold)) {
             const float4 *__restrict__ tt = op.ttab;
             if (GENERAL && (op.flags & kOpRf) && op.rf_axis == 1) {  // y groups: rows per isochromat
 #pragma unroll
@@ -736,6 +739,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
             }
         }
     }
+    if (EMIT && act && a.write_m && (need & kNeedMz)) {  // Mz is unchanged: (0, 0, M0) or as read
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) ld4(a.fresh ? a.m0 : a.mz, i4 + q, mz + 4 * q);
+    }
     if (act && a.write_m && a.m_final) {
 #pragma unroll
         for (int c = 0; c < NI; ++c) a.m_final[4 * i4 + c] = make_float4(mx[c], my[c], mz[c], 0.f);
@@ -766,6 +773,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     sweep_body<false, SWEEP_NI_FAST, false, true>(a);
 }
 
+// The fast sweep for segments whose ops only emit (an EPI readout train): no
+// pre maps and no transitions, so few registers stay live and more waves per
+// SIMD hide the latency of each op's descriptor and table loads.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES_EMIT))) void k_sweep_emit(
+    SweepArgs a) {
+    sweep_body<false, SWEEP_NI_FAST, false, false, true>(a);
+}
+
 // The general sweep with receive coils: the thread's sensitivities (up to
 // kSweepMaxCoils coils) stay in registers for the whole launch.
 __global__ __launch_bounds__(256) void k_sweep_coils(SweepArgs a) { sweep_body<true, 4, true>(a); }
@@ -780,7 +795,9 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
         hipLaunchKernelGGL(k_sweep_general, dim3((unsigned)((a.n4 + 255) / 256)), dim3(256), 0, st, a);
     } else {
         const int64_t n = a.n4 / (SWEEP_NI_FAST / 4);
-        if (a.need & kNeedRun)
+        if (a.need & kEmitOnly)
+            hipLaunchKernelGGL(k_sweep_emit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+        else if (a.need & kNeedRun)
             hipLaunchKernelGGL(k_sweep_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
         else
             hipLaunchKernelGGL(k_sweep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);

@@ -189,6 +189,27 @@ def test_two_axis_groups(gb):
     check_case(gb, "oblique fse", ph2, fs, modes=("grouped", "cached"), axes=31)
 
 
+def test_emission_runs(gb):
+    """Runs of 16 or more emissions that leave the state alone sweep on their
+    own (the emission-only kernel): an EPI with 24 lines, and readouts before
+    any RF, from (0, 0, M0) and from a given state."""
+    ph = synth.brain_like_phantom(48, 40, 3)
+    epi = synth.epi_sequence(n_lines=24, n_read=32, rf_steps=1000)
+    check_case(gb, "epi24", ph, epi, modes=("grouped",))
+    _, _, st = run_gpu(gb, ph, epi, gb.GBS_GROUPED)
+    assert st["n_sweeps"] >= 2, st
+    sb = SeqBuilder(1e-6, "readouts-first")
+    for i in range(20):
+        sb.adc(32, (0.01 * (-1) ** i, 0, 0), 4 * np.arange(8) + 2)
+        sb.relax(1e-4, (0, 2e-6, 0))
+    sb.rf(synth.sinc_pulse(200, 1e-6, 0.8), (0, 0, 0.012))
+    sb.adc(32, (0.01, 0, 0), 4 * np.arange(8) + 2)
+    seq = sb.build()
+    rng = np.random.default_rng(12)
+    check_case(gb, "readouts-first", ph, seq, modes=("grouped",))
+    check_case(gb, "readouts-first+m_init", ph, seq, modes=("grouped",), m_init=rng.uniform(-0.5, 0.5, (3, ph.K)))
+
+
 def test_run_boundaries(gb):
     """Grouped runs that start and end with per-isochromat stepping (a
     mixed-gradient RF block first, an ADC-with-RF block last): the layout
