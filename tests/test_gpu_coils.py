@@ -98,6 +98,20 @@ def test_coils_fse_epi_small(gb, name):
     check(gb, name, ph, seq, synth.coil_maps(ph, 2, radius=0.03, width=0.03))
 
 
+def test_coils_with_two_axis_and_emission_runs(gb):
+    """Coils together with an oblique slice (transition rows per two-axis group
+    in the coil sweep) and with an EPI readout train of more than 16
+    emission-only operations (coil runs keep the coil sweep)."""
+    ph = synth.tiny_phantom(nx=7, ny=6, nz=3, n_classes=3, df_levels=3)
+    S = synth.coil_maps(ph, 3, radius=0.012, width=0.01)
+    ob = synth.gre_sequence(n_lines=2, n_read=16, dwell_steps=4, rf_steps=300, te=2.5e-3, tr=6e-3, tilt_deg=25.0)
+    check(gb, "oblique", ph, ob, S)
+    _, _, st, info = run(gb, ph, ob, gb.GBS_GROUPED, S)
+    assert st["n_fallback"] == 0 and info["n_xz_groups"] > 0, (st, info)
+    epi = synth.epi_sequence(n_lines=20, n_read=16, rf_steps=400)
+    check(gb, "epi20", ph, epi, S[:2])
+
+
 def test_unit_sensitivity_equals_the_default(gb):
     """One coil of S = 1 through the coil path (general sweep) against the
     default single-coil run (fast sweep)."""

@@ -138,6 +138,25 @@ def test_coils_fullsize_grouped_vs_cached(big):
     assert dm <= DM_TOL and max(r) <= SIG_TOL
 
 
+@pytest.mark.parametrize("name", ["se-epi", "t2w-se", "oblique-fse", "fat-sat-fse"])
+def test_workloads_fullsize_sampled(big, name):
+    """The other full-size workloads the benchmark times (a Table 2 spin-echo
+    EPI and T2W spin echo, the oblique-slice FSE with two-axis groups, the
+    fat-saturated FSE with no-grads groups): sampled isochromats against the
+    oracle, in the benchmark's configuration (all group axes built)."""
+    gb, ph, sim = big
+    seq = {"se-epi": lambda: synth.table2_sequences()["se-epi"],
+           "t2w-se": lambda: synth.table2_sequences()["t2w-se"].head(40, name="t2w-se[:10 TR]"),
+           "oblique-fse": lambda: synth.fse_sequence(tilt_deg=20.0),
+           "fat-sat-fse": lambda: synth.fse_sequence(fat_sat=True)}[name]()
+    say(f"[gpu] {name} full K={ph.K}: grouped")
+    M, sig = run(sim, gb, seq, gb.GBS_GROUPED)
+    assert np.all(np.isfinite(M)) and np.all(np.isfinite(sig))
+    dm = sampled_error(ph, seq, M, n=32, seed=19)
+    say(f"[gpu] {name} full: sampled max|dM| = {dm:.3e}")
+    assert dm <= DM_TOL
+
+
 def test_fse_fullsize_superposition(big):
     import torch
     gb, ph, sim = big
