@@ -170,11 +170,13 @@ int gbs_set_phantom(gbs_ctx *ctx, int64_t K, const float *x, const float *y, con
  * phantom's order) for coil p, kept as views until the next gbs_set_coils or
  * gbs_set_phantom (which returns to one coil of unit sensitivity).  Both null
  * with n_coils = 1 selects that default.  With sensitivities the signal of
- * gbs_simulate has n_coils rows, and every emission of GBS_GROUPED weights
- * its members by S before the group sums of each coil (the general sweep
- * kernel; S is read from the context's group-sorted copy at every emission).
- * GBS_PLAIN, and readouts that are stepped per isochromat in any mode (RF
- * during an ADC block, unclassified blocks), are rejected with sensitivities.
+ * gbs_simulate has n_coils rows in every mode: GBS_GROUPED weights the
+ * members of every emission by S before the group sums of each coil (the
+ * coil sweep holds each thread's S in registers, read from the context's
+ * group-sorted copy), GBS_CACHED weights every directly evaluated term, and
+ * per-isochromat stepping (GBS_PLAIN, and stepped readouts in the other
+ * modes) adds one weighted sum per coil at every sample, taking at most
+ * 256 / n_coils samples per launch.
  * Errors: GBS_E_STATE (no phantom), GBS_E_INVALID (n_coils outside
  * [1, GBS_MAX_COILS], one pointer null, NaN/inf values), GBS_E_HIP.
  */

@@ -25,6 +25,7 @@
 #include "mlp.hpp"
 #include "mlp_api.hpp"
 #include "pairs.hpp"
+#include "plain_coils.hpp"
 #include "plan.hpp"
 
 using namespace gbs;
@@ -302,7 +303,9 @@ int gbs_set_coils(gbs_ctx *ctx, int32_t n_coils, const float *sens_re, const flo
     ctx->coil_re = sens_re;
     ctx->coil_im = sens_im;
     ctx->coil_l_valid = false;
-    ctx->gp.valid = false;
+    ctx->gp.valid = false;  // stepped launches are cut to 256 / n_coils samples
+    ctx->pplan_valid = false;
+    ctx->cplan_valid = false;
     return GBS_OK;
 }
 
@@ -606,15 +609,24 @@ PlainArgs step_args(gbs_ctx *ctx, const StepOp &op, const PhantomPtrs &ph, int64
 
 }  // namespace
 
-// Readout samples taken by per-isochromat stepping (RF during an ADC block, or a
-// block the grouped plan cannot classify) carry no coil weights.
-static int check_coil_plan(gbs_ctx *ctx, const Plan &plan) {
-    if (!ctx->coil_re) return GBS_OK;
-    for (const Op &op : plan.ops)
-        if (op.kind == 1 && op.step.sample_hi > op.step.sample_lo)
-            return fail(ctx, GBS_E_INVALID,
-                        "coil sensitivities with a readout that is stepped per isochromat (block " +
-                            std::to_string(op.step.block) + ")");
+// Samples per stepping launch: the coil sums share the launch's LDS accumulators.
+static int32_t step_samples(const gbs_ctx *ctx) {
+    return kMaxSamplesPerLaunch / (ctx->coil_re ? ctx->n_coils : 1);
+}
+
+// One stepping launch with its samples: the coil sums when the context has coil
+// maps (sensitivities of the launch's isochromats: re + p * stride), then one
+// finalize per coil into row p of the signal.
+static int launch_steps(gbs_ctx *ctx, const PlainArgs &a, bool b1, bool fp32, int grid, const float *cre,
+                        const float *cim, int64_t cstride, double *sig_out, int64_t first_sample) {
+    const int32_t P = ctx->coil_re ? ctx->n_coils : 1;
+    if (ctx->coil_re && a.n_samples > 0)
+        HIPCHK(launch_plain_coils(a, PlainCoils{cre, cim, cstride, P}, b1, fp32, grid, ctx->stream));
+    else
+        HIPCHK(launch_plain(a, b1, fp32, grid, ctx->stream));
+    for (int32_t p = 0; p < P && a.n_samples > 0; ++p)
+        HIPCHK(launch_plain_finalize(ctx->partial.as<double2>() + (size_t)p * grid * a.n_samples, grid, a.n_samples,
+                                     sig_out + 2 * ((int64_t)p * ctx->seq.total_samples + first_sample), ctx->stream));
     return GBS_OK;
 }
 
@@ -622,7 +634,7 @@ static int run_plain(gbs_ctx *ctx, const float *m_init, float *m_out, double *si
                      gbs_stats *st) {
     const int64_t K = ctx->K;
     if (!ctx->pplan_valid) {
-        ctx->pplan = plan_plain(ctx->seq);
+        ctx->pplan = plan_plain(ctx->seq, step_samples(ctx));
         if (ctx->pplan.ops.empty()) {  // still write (0, 0, M0) or the initial state out
             Op op;
             op.kind = 1;
@@ -667,12 +679,8 @@ static int run_plain(gbs_ctx *ctx, const float *m_init, float *m_out, double *si
             }
         }
         const bool b1 = op.step.block >= 0 && ctx->cls[op.step.block].has_b1;
-        HIPCHK(launch_plain(a, b1, fp32, grid, ctx->stream));
-        if (a.n_samples > 0) {
-            const gbs_block &b = ctx->seq.blocks[op.step.block];
-            HIPCHK(launch_plain_finalize(ctx->partial.as<double2>(), grid, a.n_samples,
-                                         sig_out + 2 * (b.sample_offset + op.step.sample_lo), ctx->stream));
-        }
+        const int64_t s0 = op.step.block >= 0 ? ctx->seq.blocks[op.step.block].sample_offset + op.step.sample_lo : 0;
+        if (int rc = launch_steps(ctx, a, b1, fp32, grid, ctx->coil_re, ctx->coil_im, K, sig_out, s0)) return rc;
         first = false;
     }
     if (st) st->n_fallback = 0;
@@ -717,7 +725,7 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
     GroupedPlan &g = ctx->gp;
     const HostSeq &s = ctx->seq;
     g = GroupedPlan{};
-    g.plan = plan_grouped(s, ctx->cls, ctx->axes);
+    g.plan = plan_grouped(s, ctx->cls, ctx->axes, step_samples(ctx));
     const Plan &plan = g.plan;
     g.zbuilt = (ctx->axes & GBS_AX_Z) != 0;
     g.surr_on = want_surr;
@@ -1188,7 +1196,6 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     }
     const GroupedPlan &g = ctx->gp;
     const Plan &plan = g.plan;
-    if (int rc = check_coil_plan(ctx, plan)) return rc;
     const bool zbuilt = g.zbuilt;
     const int grid = plain_grid(ctx->Kint);
     char *tb = ctx->tabs.as<char>();
@@ -1305,12 +1312,11 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
             const Op &op = plan.ops[item.second];
             PlainArgs a = step_args(ctx, op.step, iph, Kint, mx, my, mz, mx, my, mz);
             const bool b1 = op.step.block >= 0 && ctx->cls[op.step.block].has_b1;
-            HIPCHK(launch_plain(a, b1, false, grid, ctx->stream));
-            if (a.n_samples > 0) {
-                const gbs_block &b = s.blocks[op.step.block];
-                HIPCHK(launch_plain_finalize(ctx->partial.as<double2>(), grid, a.n_samples,
-                                             sig_out + 2 * (b.sample_offset + op.step.sample_lo), ctx->stream));
-            }
+            const int64_t s0 = op.step.block >= 0 ? s.blocks[op.step.block].sample_offset + op.step.sample_lo : 0;
+            const float *cl = ctx->coil_re ? ctx->coil_l.as<float>() : nullptr;  // planes re, im per coil
+            const int64_t Kp = ctx->Kpad;
+            if (int rc = launch_steps(ctx, a, b1, false, grid, cl, cl ? cl + Kp : nullptr, 2 * Kp, sig_out, s0))
+                return rc;
         }
     }
     *n_timed = timed;
@@ -1359,7 +1365,7 @@ static int run_cached(gbs_ctx *ctx, const float *m_init, float *m_out, double *s
     const int64_t K = ctx->K;
     const double dt = ctx->seq.dt;
     if (!ctx->cplan_valid) {
-        ctx->cplan = plan_cached(ctx->seq, ctx->cls);
+        ctx->cplan = plan_cached(ctx->seq, ctx->cls, step_samples(ctx));
         const Plan &plan = ctx->cplan;
         // sample n of a direct ADC operation: c_n = gamma_bar (m_pre + m(s_n)),
         // tau_n = tau_pre + s_n dt, with m(s) the block's gradient moment over
@@ -1395,7 +1401,6 @@ static int run_cached(gbs_ctx *ctx, const float *m_init, float *m_out, double *s
         ctx->cplan_valid = true;
     }
     const Plan &plan = ctx->cplan;
-    if (int rc = check_coil_plan(ctx, plan)) return rc;
     const size_t n_entries = plan.rf.size();
     ALLOC(ctx->state64, sizeof(double) * 3 * (size_t)K);
     if (n_entries) ALLOC(ctx->cache, sizeof(float4) * 3 * (size_t)K * n_entries);
@@ -1429,12 +1434,10 @@ static int run_cached(gbs_ctx *ctx, const float *m_init, float *m_out, double *s
             a.mout64_x = s64;
             a.mout64_y = s64 + K;
             a.mout64_z = s64 + 2 * K;
-            HIPCHK(launch_plain(a, ctx->cls[op.step.block].has_b1, false, pgrid, ctx->stream));
-            if (a.n_samples > 0) {
-                const gbs_block &b = ctx->seq.blocks[op.step.block];
-                HIPCHK(launch_plain_finalize(ctx->partial.as<double2>(), pgrid, a.n_samples,
-                                             sig_out + 2 * (b.sample_offset + op.step.sample_lo), ctx->stream));
-            }
+            const int64_t s0 = ctx->seq.blocks[op.step.block].sample_offset + op.step.sample_lo;
+            if (int rc = launch_steps(ctx, a, ctx->cls[op.step.block].has_b1, false, pgrid, ctx->coil_re, ctx->coil_im,
+                                      K, sig_out, s0))
+                return rc;
             from_init = false;
         } else if (op.kind == 3) {  // direct ADC: reads the state, writes samples
             const CachedOp &c = op.cached;
@@ -1533,8 +1536,6 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
         std::memset(stats, 0, sizeof(*stats));
         HIPCHK(hipEventRecord(ctx->ev[0], ctx->stream));
     }
-    if (ctx->coil_re && mode == GBS_PLAIN)
-        return fail(ctx, GBS_E_INVALID, "coil sensitivities need GBS_GROUPED or GBS_CACHED");
     if (ctx->seq.total_samples > 0)
         HIPCHK(launch_fill_f64(sig_out, 2 * (int64_t)ctx->n_coils * ctx->seq.total_samples, ctx->stream));
     const bool profile = (flags & GBS_PROFILE) != 0;

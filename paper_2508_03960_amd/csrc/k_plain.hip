@@ -25,6 +25,7 @@
 // the partials in a fixed order.
 #include "device_math.hpp"
 #include "kernels.hpp"
+#include "plain_coils.hpp"
 #include "rotation.hpp"
 
 namespace gbs {
@@ -68,16 +69,18 @@ __device__ __forceinline__ float fmaR<float>(float a, float b, float c) { return
 template <>
 __device__ __forceinline__ double fmaR<double>(double a, double b, double c) { return fma(a, b, c); }
 
-template <typename R, bool HAS_B1>
-__global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a) {
+template <typename R, bool HAS_B1, bool COILS>
+__global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a, PlainCoils cl) {
     using Acc = SampleAcc<R>;
+    constexpr int MC = COILS ? kPlainMaxCoils : 1;
     extern __shared__ char lds_raw[];
-    Acc *acc = reinterpret_cast<Acc *>(lds_raw);  // [4 waves][n_samples]
+    Acc *acc = reinterpret_cast<Acc *>(lds_raw);  // [4 waves][n_samples][coils]
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
     const int ns = a.n_samples;
-    for (int i = tid; i < 4 * ns; i += kPlainBlock) acc[i] = Acc{};
+    const int P = COILS ? cl.n : 1;
+    for (int i = tid; i < 4 * ns * P; i += kPlainBlock) acc[i] = Acc{};
     __syncthreads();
     const R gdt = (R)a.gdt;
     const R k2 = gdt * gdt;
@@ -87,6 +90,16 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a) {
     for (int64_t base = (int64_t)blockIdx.x * kTile; base < a.K; base += (int64_t)gridDim.x * kTile) {
         R X[kIso], Y[kIso], Z[kIso], boff[kIso], e1m[kIso], e2m[kIso], M0[kIso];
         R mx[kIso], my[kIso], mz[kIso];
+        float csr[MC][kIso], csi[MC][kIso];  // coil sensitivities of the thread's isochromats
+#pragma unroll
+        for (int p = 0; p < MC; ++p)
+#pragma unroll
+            for (int i = 0; i < kIso; ++i) {
+                const int64_t k = base + (int64_t)i * kPlainBlock + tid;
+                const bool use = COILS && p < P && k < a.K;
+                csr[p][i] = use ? cl.re[p * cl.stride + k] : 0.f;
+                csi[p][i] = use ? cl.im[p * cl.stride + k] : 0.f;
+            }
 #pragma unroll
         for (int i = 0; i < kIso; ++i) {
             const int64_t k = base + (int64_t)i * kPlainBlock + tid;
@@ -171,7 +184,22 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a) {
                     mz[i] = fmaR(e1m[i], M0[i] - mz[i], mz[i]);
                 }
             }
-            if (n < ns) {
+            if (n < ns && COILS) {  // one sum per coil: S(k, p) (Mx + i My)
+#pragma unroll
+                for (int p = 0; p < MC; ++p) {
+                    if (p >= P) break;
+                    R vx = R(0), vy = R(0);
+#pragma unroll
+                    for (int i = 0; i < kIso; ++i) {
+                        const R sr = (R)csr[p][i], si = (R)csi[p][i];
+                        vx += mx[i] * sr - my[i] * si;
+                        vy += mx[i] * si + my[i] * sr;
+                    }
+                    vx = Acc::wave_sum(vx);
+                    vy = Acc::wave_sum(vy);
+                    if (lane == 63) Acc::add(acc[(wave * ns + n) * P + p], vx, vy);
+                }
+            } else if (n < ns) {
                 R vx = mx[0], vy = my[0];
 #pragma unroll
                 for (int i = 1; i < kIso; ++i) {
@@ -202,14 +230,15 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a) {
     }
     if (ns == 0) return;
     __syncthreads();
-    for (int n = tid; n < ns; n += kPlainBlock) {
+    for (int idx = tid; idx < ns * P; idx += kPlainBlock) {  // partials [coil][workgroup][sample]
+        const int n = idx / P, p = idx - n * P;
         double re = 0.0, im = 0.0;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-            re += acc[w * ns + n].re();
-            im += acc[w * ns + n].im();
+            re += acc[(w * ns + n) * P + p].re();
+            im += acc[(w * ns + n) * P + p].im();
         }
-        a.partial[(int64_t)blockIdx.x * ns + n] = make_double2(re, im);
+        a.partial[((int64_t)p * gridDim.x + blockIdx.x) * ns + n] = make_double2(re, im);
     }
 }
 
@@ -249,16 +278,35 @@ int plain_grid(int64_t K) {
 
 hipError_t launch_plain(const PlainArgs &a, bool has_b1, bool fp32, int grid, hipStream_t st) {
     const size_t lds = 16 * 4 * (size_t)a.n_samples;  // both accumulator types are 16 bytes
+    const PlainCoils none{nullptr, nullptr, 0, 1};
     if (fp32) {
         if (has_b1)
-            hipLaunchKernelGGL((k_plain<float, true>), dim3(grid), dim3(kPlainBlock), lds, st, a);
+            hipLaunchKernelGGL((k_plain<float, true, false>), dim3(grid), dim3(kPlainBlock), lds, st, a, none);
         else
-            hipLaunchKernelGGL((k_plain<float, false>), dim3(grid), dim3(kPlainBlock), lds, st, a);
+            hipLaunchKernelGGL((k_plain<float, false, false>), dim3(grid), dim3(kPlainBlock), lds, st, a, none);
     } else {
         if (has_b1)
-            hipLaunchKernelGGL((k_plain<double, true>), dim3(grid), dim3(kPlainBlock), lds, st, a);
+            hipLaunchKernelGGL((k_plain<double, true, false>), dim3(grid), dim3(kPlainBlock), lds, st, a, none);
         else
-            hipLaunchKernelGGL((k_plain<double, false>), dim3(grid), dim3(kPlainBlock), lds, st, a);
+            hipLaunchKernelGGL((k_plain<double, false, false>), dim3(grid), dim3(kPlainBlock), lds, st, a, none);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_coils(const PlainArgs &a, const PlainCoils &c, bool has_b1, bool fp32, int grid,
+                              hipStream_t st) {
+    if (!c.re || !c.im || c.n < 1 || c.n > kPlainMaxCoils || a.n_samples * c.n > 256) return hipErrorInvalidValue;
+    const size_t lds = 16 * 4 * (size_t)a.n_samples * (size_t)c.n;
+    if (fp32) {
+        if (has_b1)
+            hipLaunchKernelGGL((k_plain<float, true, true>), dim3(grid), dim3(kPlainBlock), lds, st, a, c);
+        else
+            hipLaunchKernelGGL((k_plain<float, false, true>), dim3(grid), dim3(kPlainBlock), lds, st, a, c);
+    } else {
+        if (has_b1)
+            hipLaunchKernelGGL((k_plain<double, true, true>), dim3(grid), dim3(kPlainBlock), lds, st, a, c);
+        else
+            hipLaunchKernelGGL((k_plain<double, false, true>), dim3(grid), dim3(kPlainBlock), lds, st, a, c);
     }
     return hipGetLastError();
 }

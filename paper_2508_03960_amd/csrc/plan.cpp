@@ -123,8 +123,8 @@ std::vector<BlockClass> classify(const HostSeq &s) {
     return out;
 }
 
-// Split a stepped block into launches of at most kMaxSamplesPerLaunch samples.
-static void add_step_ops(Plan &p, const HostSeq &s, int64_t b, const Map &pre, bool has_pre) {
+// Split a stepped block into launches of at most max_samples samples.
+static void add_step_ops(Plan &p, const HostSeq &s, int64_t b, const Map &pre, bool has_pre, int32_t max_samples) {
     const gbs_block &k = s.blocks[b];
     const int32_t ns = k.n_samples;
     if (ns == 0) {
@@ -134,8 +134,8 @@ static void add_step_ops(Plan &p, const HostSeq &s, int64_t b, const Map &pre, b
         p.ops.push_back(op);
         return;
     }
-    for (int32_t a = 0; a < ns; a += kMaxSamplesPerLaunch) {
-        int32_t e = std::min(ns, a + kMaxSamplesPerLaunch);
+    for (int32_t a = 0; a < ns; a += max_samples) {
+        int32_t e = std::min(ns, a + max_samples);
         Op op;
         op.kind = 1;
         op.step.block = b;
@@ -149,7 +149,7 @@ static void add_step_ops(Plan &p, const HostSeq &s, int64_t b, const Map &pre, b
     }
 }
 
-Plan plan_plain(const HostSeq &s) {
+Plan plan_plain(const HostSeq &s, int32_t max_samples) {
     Plan p;
     Map P;
     for (size_t b = 0; b < s.blocks.size(); ++b) {
@@ -159,7 +159,7 @@ Plan plan_plain(const HostSeq &s) {
             ++p.n_relax;
             continue;
         }
-        add_step_ops(p, s, (int64_t)b, P, P.any());
+        add_step_ops(p, s, (int64_t)b, P, P.any(), max_samples);
         P = Map{};
     }
     if (P.any()) {
@@ -210,7 +210,7 @@ static int rf_lookup(Plan &p, std::vector<uint64_t> &hashes, const HostSeq &s, i
     return (int)p.rf.size() - 1;
 }
 
-Plan plan_grouped(const HostSeq &s, const std::vector<BlockClass> &cls, uint32_t axes_built) {
+Plan plan_grouped(const HostSeq &s, const std::vector<BlockClass> &cls, uint32_t axes_built, int32_t max_samples) {
     Plan p;
     std::vector<uint64_t> hashes;
     Map P;  // B1 = 0 maps since the state in memory (or the pending pass) was last advanced
@@ -300,7 +300,7 @@ Plan plan_grouped(const HostSeq &s, const std::vector<BlockClass> &cls, uint32_t
         // Unclassified, RF together with ADC, or an axis without groups:
         // the conventional per-isochromat stepping (Sec. 3.1).
         flush();
-        add_step_ops(p, s, b, P, P.any());
+        add_step_ops(p, s, b, P, P.any(), max_samples);
         P = Map{};
         ++p.n_fallback;
     }
@@ -310,7 +310,7 @@ Plan plan_grouped(const HostSeq &s, const std::vector<BlockClass> &cls, uint32_t
     return p;
 }
 
-Plan plan_cached(const HostSeq &s, const std::vector<BlockClass> &cls) {
+Plan plan_cached(const HostSeq &s, const std::vector<BlockClass> &cls, int32_t max_samples) {
     Plan p;
     std::vector<uint64_t> hashes;
     Map P;  // B1 = 0 maps not yet applied to the stored state
@@ -359,7 +359,7 @@ Plan plan_cached(const HostSeq &s, const std::vector<BlockClass> &cls) {
             continue;
         }
         // RF during an ADC block: stepped per isochromat
-        add_step_ops(p, s, b, P, P.any());
+        add_step_ops(p, s, b, P, P.any(), max_samples);
         P = Map{};
         ++p.n_fallback;
     }

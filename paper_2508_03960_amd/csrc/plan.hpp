@@ -131,11 +131,14 @@ void copy_sequence(HostSeq &s, const gbs_block *blocks, int64_t n_blocks, const 
                    const float *rf_im, const float *gx, const float *gy, const float *gz,
                    int64_t total_steps, const int32_t *adc_idx, int64_t total_samples, double dt);
 std::vector<BlockClass> classify(const HostSeq &s);
-Plan plan_plain(const HostSeq &s);
-Plan plan_grouped(const HostSeq &s, const std::vector<BlockClass> &cls, uint32_t axes_built);
+// max_samples: the most samples one stepping launch accumulates (kMaxSamplesPerLaunch
+// divided by the receive coils, whose sums share the launch's LDS)
+Plan plan_plain(const HostSeq &s, int32_t max_samples = kMaxSamplesPerLaunch);
+Plan plan_grouped(const HostSeq &s, const std::vector<BlockClass> &cls, uint32_t axes_built,
+                  int32_t max_samples = kMaxSamplesPerLaunch);
 // Schedule of the conventional accelerated method with dynamic caching of
 // per-isochromat transitions (Sec. 2.2).  Plan::rf lists the cache entries
 // (axis -1: bit-identical B1 and all three gradients).
-Plan plan_cached(const HostSeq &s, const std::vector<BlockClass> &cls);
+Plan plan_cached(const HostSeq &s, const std::vector<BlockClass> &cls, int32_t max_samples = kMaxSamplesPerLaunch);
 
 }  // namespace gbs

@@ -44,9 +44,10 @@ def run(gb, ph, seq, mode, sens, axes=None, m_init=None):
     return out
 
 
-def check(gb, name, ph, seq, sens, m_init=None, axes=None):
+def check(gb, name, ph, seq, sens, m_init=None, axes=None, plain=False):
     Mr, sr = oracle.simulate_coils(ph, seq, sens, m_init=m_init)
-    for mode, label in ((gb.GBS_GROUPED, "grouped"), (gb.GBS_CACHED, "cached")):
+    modes = ((gb.GBS_GROUPED, "grouped"), (gb.GBS_CACHED, "cached")) + (((gb.GBS_PLAIN, "plain"),) if plain else ())
+    for mode, label in modes:
         say(f"[gpu] coils {name}: {label} K={ph.K} P={sens.shape[0]}")
         M, sig, _, info = run(gb, ph, seq, mode, sens, axes=axes, m_init=m_init)
         sig = sig.reshape(sens.shape[0], -1)
@@ -77,7 +78,23 @@ def readouts_sequence():
 def test_coils_small_gre(gb):
     ph = synth.gre_phantom(8, 8, 2, seed=41)
     seq = synth.gre_sequence(n_lines=3, n_read=16, dwell_steps=4, rf_steps=400, te=2.5e-3, tr=6e-3)
-    check(gb, "gre", ph, seq, synth.coil_maps(ph, 3))
+    check(gb, "gre", ph, seq, synth.coil_maps(ph, 3), plain=True)
+
+
+def test_coils_with_stepped_readouts(gb):
+    """Readouts stepped per isochromat (RF during the ADC, a mixed-gradient
+    readout) carry one weighted sum per coil in every mode; 8 coils cut the
+    stepped launches to 32 samples, so a 100-sample readout takes four."""
+    ph = synth.tiny_phantom(nx=7, ny=6, nz=3, n_classes=3, df_levels=3)
+    sb = SeqBuilder(1e-6, "stepped-readouts")
+    sb.rf(synth.sinc_pulse(200, 1e-6, np.pi / 2), (0, 0, 0.012))
+    sb.relax(3e-4, (-1e-6, 2e-6, -1.2e-6))
+    sb.adc(40, (0.01, 0, 0), [0, 5, 19, 39], b1=np.full(40, 1e-6 + 0j))      # RF during the readout
+    sb.adc(200, (0.006, 0.004, 0), 2 * np.arange(100))                        # two gradients: stepped
+    sb.adc(64, (0.01, 0, 0), 4 * np.arange(16) + 2)                           # grouped
+    seq = sb.build()
+    check(gb, "stepped/3", ph, seq, synth.coil_maps(ph, 3, radius=0.012, width=0.01), plain=True)
+    check(gb, "stepped/8", ph, seq, synth.coil_maps(ph, 8, radius=0.012, width=0.01), plain=True)
 
 
 def test_coils_every_emission_axis(gb):
@@ -142,16 +159,7 @@ def test_coil_errors(gb):
         codes.append(e.value.code)
     assert codes == [gb.GBS_E_INVALID] * 2
     sim.set_coils(S)
-    with pytest.raises(gb.GbsError) as e:  # no coil weights in per-isochromat stepping
-        sim.simulate(gb.GBS_PLAIN)
-    assert e.value.code == gb.GBS_E_INVALID
-    sb = SeqBuilder(1e-6, "rf-in-adc")
-    sb.adc(20, (0.01, 0, 0), [0, 5, 19], b1=np.full(20, 1e-6 + 0j))
-    sim.set_sequence(sb.build())
-    for mode in (gb.GBS_GROUPED, gb.GBS_CACHED):
-        with pytest.raises(gb.GbsError) as e:
-            sim.simulate(mode)
-        assert e.value.code == gb.GBS_E_INVALID
+    assert sim.info()["n_coils"] == 2
     sim.set_phantom(ph)  # back to one coil of unit sensitivity
     assert sim.info()["n_coils"] == 1
     sim.set_sequence(seq)
