@@ -1,0 +1,91 @@
+"""FSE and EPI at 27.3M isochromats against the FP64 oracle on a seeded
+uniform subset of 2^20 = 1,048,576 isochromats (seed 7, sorted): the final M
+of the subset taken from the full-phantom grouped run, and the signal of the
+subset simulated as a phantom of its own.  Bar: max |dM| <= 1e-5 and relative
+signal error <= 1e-4.
+
+The oracle is slow at this size: about 4 minutes for the EPI and about an
+hour for the FSE on 16 host threads.  GBLOCH_SLOW_ORACLE=epi (or fse, or
+all) selects which case runs; without it both are skipped.  The GPU half and
+the oracle half are separate functions so that the oracle half can run on
+another host from saved GPU results.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+SUBSET = 1 << 20
+CHUNK = 1 << 16
+
+
+def sequence(name):
+    return {"epi": synth.epi_sequence, "fse": synth.fse_sequence}[name]()
+
+
+def gpu_subset(name):
+    """Grouped GPU path: (subset indices, subset M [3, 2^20] as float64,
+    subset-phantom signal)."""
+    import torch
+    import paper_2508_03960_amd as gb
+    ph, seq = synth.brain_like_phantom(), sequence(name)
+    idx = synth.random_subset_indices(ph.K, SUBSET, seed=7)
+    sim = gb.Simulator(0)
+    try:
+        sim.set_phantom(ph)
+        sim.build_groups()
+        sim.set_sequence(seq)
+        M, _ = sim.simulate(gb.GBS_GROUPED)
+        torch.cuda.synchronize()
+        M_sub = M.cpu().numpy()[:, idx].astype(np.float64)
+    finally:
+        sim.close()
+    sim = gb.Simulator(0)
+    try:
+        sim.set_phantom(ph.subset(idx))
+        sim.build_groups()
+        sim.set_sequence(seq)
+        _, s = sim.simulate(gb.GBS_GROUPED)
+        torch.cuda.synchronize()
+        s = s.cpu().numpy().astype(np.complex128)
+    finally:
+        sim.close()
+    return idx, M_sub, s
+
+
+def oracle_compare(name, idx, M_sub, s_gpu, log=print):
+    """Run the oracle over the subset in chunks; return (max |dM|, relative
+    signal error)."""
+    ph, seq = synth.brain_like_phantom(), sequence(name)
+    sub = ph.subset(idx)
+    dm, s_ref = 0.0, np.zeros(seq.total_samples, np.complex128)
+    for c in range(0, idx.size, CHUNK):
+        e = min(c + CHUNK, idx.size)
+        Mo, so = oracle.simulate(sub.subset(np.arange(c, e)), seq)
+        dm = max(dm, float(np.max(np.abs(M_sub[:, c:e] - Mo))))
+        s_ref += so
+        log(f"[subset] {name}: oracle {e} / {idx.size}, max|dM| so far {dm:.3e}")
+    rel = float(np.linalg.norm(s_gpu - s_ref) / np.linalg.norm(s_ref))
+    return dm, rel
+
+
+def _selected(name):
+    v = os.environ.get("GBLOCH_SLOW_ORACLE", "")
+    return v in (name, "all", "1" if name == "epi" else "")
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("name", ["epi", "fse"])
+def test_subset_1m_against_oracle(name):
+    if not _selected(name):
+        pytest.skip(f"slow oracle case: set GBLOCH_SLOW_ORACLE={name} or all")
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    idx, M_sub, s_gpu = gpu_subset(name)
+    dm, rel = oracle_compare(name, idx, M_sub, s_gpu, log=lambda m: print(m, flush=True))
+    print(f"[subset] {name} 1M: max|dM| = {dm:.3e}, relative signal error = {rel:.3e}", flush=True)
+    assert dm <= 1e-5 and rel <= 1e-4
