@@ -274,6 +274,47 @@ int gbs_plan_cached_summary(const gbs_block *blocks, int64_t n_blocks, const flo
                             double dt, int64_t out[6]);
 
 
+/* ==== Pulseq sequence files ============================================
+ *
+ * Reads the text of a Pulseq sequence file (format version 1.4; other
+ * versions -> GBS_E_INVALID) into the block form of gbs_set_sequence
+ * (Sec. 2.1, Fig. 1).  Host only, no context and no device.
+ *
+ * Each Pulseq block of non-zero duration becomes one subsequence: with an
+ * ADC event a GBS_BLOCK_ADC block (its RF, if any, stays in it), else with an
+ * RF event a GBS_BLOCK_RF block, else a GBS_BLOCK_RELAX block of tau = the
+ * block duration and moment = the exact integral of each gradient.  Blocks
+ * of zero duration without events (labels) are dropped.  Stepped blocks are
+ * sampled on the uniform raster dt (dt <= 0: the file's RF raster time):
+ * every step holds the exact mean over the step of the RF (piecewise
+ * constant on the RF raster) and of each gradient (piecewise linear:
+ * trapezoids, arbitrary gradients on the default timing with their first and
+ * last values, or on a time shape).  ADC sample j lies at
+ * delay + (j + 0.5) * dwell from the block start and must fall on a raster
+ * boundary.  Units: Hz and Hz/m become T and T/m through gamma/2pi.  The
+ * simulated signal ignores the receiver's phase; adc_phase returns it per
+ * sample (phase offset + 2 pi * frequency offset * time since the ADC
+ * delay, radians) so that a caller can demodulate by exp(-i adc_phase).
+ * RF events with a time shape are rejected.  [EXTENSIONS] is ignored.
+ *
+ * Two calls.  Query: blocks == NULL; sizes (host int64[3]) receives
+ * n_blocks, total_steps, total_samples, nothing else is written.  Fill: the
+ * caller passes buffers of at least those sizes in sizes[0..2] and host
+ * arrays blocks[n_blocks], rf_re, rf_im, gx, gy, gz [total_steps] (T, T/m),
+ * adc_idx[total_samples] (raster boundary from the block start); adc_phase
+ * (double[total_samples]) may be NULL; sizes then holds the sizes written.
+ * rasters (host double[4], nullable) receives the gradient, RF, ADC and
+ * block-duration raster times (s) of the file.  err (host, err_cap bytes,
+ * nullable) receives a NUL-terminated message, empty on success.
+ * Errors: GBS_E_INVALID (malformed file, unsupported version or event,
+ * block duration or ADC sample off the raster, events outlasting their
+ * block, buffers too small or null), GBS_E_NOMEM.
+ */
+int gbs_pulseq_load(const char *text, int64_t text_len, double dt, int64_t sizes[3],
+                    gbs_block *blocks, float *rf_re, float *rf_im, float *gx, float *gy,
+                    float *gz, int32_t *adc_idx, double *adc_phase, double rasters[4],
+                    char *err, int64_t err_cap);
+
 /* ==== learned RF-transition surrogate ==================================
  *
  * A 5-128-128-128-12 network with SiLU activations that maps the parameters

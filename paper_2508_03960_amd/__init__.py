@@ -3,7 +3,7 @@ simulation on gfx950.
 
 Argument marshalling only: every step of the simulation runs in the HIP
 kernels of ``libgbloch.so``.  PyTorch provides device memory and the stream.
-The library must be built (``python -m paper_2508_03960_amd.build``); there is
+The library must be built (``python paper_2508_03960_amd/build.py``); there is
 no CPU fallback, and importing this package fails loudly without it.
 """
 from __future__ import annotations
@@ -33,7 +33,7 @@ EXPORTED = ("gbs_create", "gbs_destroy", "gbs_set_phantom", "gbs_set_sequence", 
             "gbs_mlp_create", "gbs_mlp_destroy", "gbs_mlp_last_error", "gbs_mlp_set_pulse",
             "gbs_mlp_set_norm", "gbs_mlp_get_params", "gbs_mlp_set_params", "gbs_mlp_exact",
             "gbs_mlp_infer", "gbs_mlp_loss_grad", "gbs_mlp_train", "gbs_set_surrogate",
-            "gbs_adj_forward", "gbs_adj_backward")
+            "gbs_adj_forward", "gbs_adj_backward", "gbs_pulseq_load")
 
 
 class gbs_block(ctypes.Structure):
@@ -78,7 +78,7 @@ class gbs_train_cfg(ctypes.Structure):
 
 def _load(path=LIB_PATH):
     if not os.path.exists(path):
-        raise ImportError(f"{path} is not built; run `python -m paper_2508_03960_amd.build`")
+        raise ImportError(f"{path} is not built; run `python paper_2508_03960_amd/build.py`")
     lib = ctypes.CDLL(path)
     P, I64, I32, U32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_double
     sig = {
@@ -108,6 +108,7 @@ def _load(path=LIB_PATH):
         "gbs_set_surrogate": ([P, P, ctypes.c_float, I32, ctypes.c_uint64], ctypes.c_int),
         "gbs_adj_forward": ([P, P, I32, P, P, P, I64, P, I32, I32, P], ctypes.c_int),
         "gbs_adj_backward": ([P, P, P, P, P], ctypes.c_int),
+        "gbs_pulseq_load": ([ctypes.c_char_p, I64, D, P, P] + [P] * 9 + [I64], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -179,6 +180,76 @@ def gbs_plan_cached_summary(seq):
         raise GbsError(rc, "gbs_plan_cached_summary rejected the sequence")
     keys = ("rf_cached", "entries", "adc_direct", "adc_launches", "fallback", "b1zero")
     return dict(zip(keys, list(out)))
+
+
+class PulseqSequence:
+    """A sequence read from a Pulseq 1.4 file by gbs_pulseq_load: the block
+    form gbs_set_sequence takes (the same fields as the seeded generators'
+    sequences), plus ``adc_phase`` (receiver phase per sample, radians) and
+    ``rasters`` (gradient, RF, ADC and block-duration raster times, s)."""
+
+    def __init__(self, dt, blocks, rf_re, rf_im, gx, gy, gz, adc_idx, adc_phase, rasters, name=""):
+        import numpy as np
+        nb = len(blocks)
+        self.dt = float(dt)
+        self.btype = np.array([b.type for b in blocks], np.int32)
+        self.step_offset = np.array([b.step_offset for b in blocks], np.int64)
+        self.n_steps = np.array([b.n_steps for b in blocks], np.int64)
+        self.n_samples = np.array([b.n_samples for b in blocks], np.int32)
+        self.sample_offset = np.array([b.sample_offset for b in blocks], np.int64)
+        self.tau = np.array([b.tau for b in blocks], np.float64)
+        self.moment = np.array([list(b.moment) for b in blocks], np.float64).reshape(nb, 3)
+        self.rf_re, self.rf_im, self.gx, self.gy, self.gz = rf_re, rf_im, gx, gy, gz
+        self.adc_idx, self.adc_phase, self.rasters = adc_idx, adc_phase, rasters
+        self.name = name
+        self.meta = {"source": "pulseq"}
+
+    @property
+    def n_blocks(self):
+        return int(self.btype.shape[0])
+
+    @property
+    def total_steps(self):
+        return int(self.rf_re.shape[0])
+
+    @property
+    def total_samples(self):
+        return int(self.adc_idx.shape[0])
+
+
+def load_pulseq(source, dt=None, name=None):
+    """Read a Pulseq 1.4 sequence (a path, or the file's text as str/bytes)
+    into a PulseqSequence on the raster ``dt`` (s; None = the file's RF
+    raster time).  Raises GbsError with the parser's message on a bad file."""
+    import numpy as np
+    if isinstance(source, (bytes, bytearray)):
+        text = bytes(source)
+    elif isinstance(source, str) and "\n" not in source and os.path.exists(source):
+        with open(source, "rb") as fh:
+            text = fh.read()
+        name = name or os.path.basename(source)
+    else:
+        text = str(source).encode()
+    err = ctypes.create_string_buffer(512)
+    sizes = (ctypes.c_int64 * 3)()
+    rasters = (ctypes.c_double * 4)()
+    dtv = float(dt) if dt else 0.0
+    rc = lib.gbs_pulseq_load(text, len(text), dtv, sizes, None, None, None, None, None, None, None, None,
+                             rasters, err, len(err))
+    if rc != GBS_OK:
+        raise GbsError(rc, err.value.decode(errors="replace"))
+    nb, ns, nq = list(sizes)
+    blocks = (gbs_block * max(nb, 1))()
+    w = [np.zeros(max(ns, 1), np.float32) for _ in range(5)]
+    adc = np.zeros(max(nq, 1), np.int32)
+    ph = np.zeros(max(nq, 1), np.float64)
+    rc = lib.gbs_pulseq_load(text, len(text), dtv, sizes, blocks, *(a.ctypes.data for a in w), adc.ctypes.data,
+                             ph.ctypes.data, rasters, err, len(err))
+    if rc != GBS_OK:
+        raise GbsError(rc, err.value.decode(errors="replace"))
+    used_dt = dtv if dtv > 0 else rasters[1]
+    return PulseqSequence(used_dt, list(blocks)[:nb], *(a[:ns] for a in w), adc[:nq], ph[:nq], tuple(rasters),
+                          name=name or "pulseq")
 
 
 class Simulator:

@@ -1,8 +1,9 @@
 """Build libgbloch.so (HIP, gfx950) in-tree.
 
 Compiles every source under csrc/ with hipcc for gfx950 into _build/ and
-links paper_2508_03960_amd/libgbloch.so.  Run as ``python -m
-paper_2508_03960_amd.build`` or through ``__graft_entry__.build()``.
+links paper_2508_03960_amd/libgbloch.so.  Run as ``python
+paper_2508_03960_amd/build.py`` (by path: importing the package loads the
+library) or through ``__graft_entry__.build()``.
 """
 from __future__ import annotations
 
@@ -21,7 +22,7 @@ ARCH = os.environ.get("GBLOCH_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "api_mlp.cpp", "plan.cpp", "k_plain.hip", "k_grouped.hip", "k_groups.hip", "k_mlp.hip",
            "k_adjoint.hip", "k_adc.hip", "k_cached.hip",
-           "k_pairs.hip"]
+           "k_pairs.hip", "pulseq.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

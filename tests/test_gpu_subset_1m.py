@@ -73,8 +73,8 @@ def oracle_compare(name, idx, M_sub, s_gpu, log=print):
 
 
 def _selected(name):
-    v = os.environ.get("GBLOCH_SLOW_ORACLE", "")
-    return v in (name, "all", "1" if name == "epi" else "")
+    v = os.environ.get("GBLOCH_SLOW_ORACLE", "").strip().lower()
+    return bool(v) and (v in (name, "all") or (v == "1" and name == "epi"))
 
 
 @pytest.mark.gpu
