@@ -19,7 +19,7 @@ import oracle
 import synth
 
 SUBSET = 1 << 20
-CHUNK = 1 << 16
+CHUNK = 1 << 14  # about a minute of oracle time per FSE chunk on 16 threads
 
 
 def sequence(name):
