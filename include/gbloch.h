@@ -284,9 +284,10 @@ int gbs_plan_cached_summary(const gbs_block *blocks, int64_t n_blocks, const flo
  * ADC event a GBS_BLOCK_ADC block (its RF, if any, stays in it), else with an
  * RF event a GBS_BLOCK_RF block, else a GBS_BLOCK_RELAX block of tau = the
  * block duration and moment = the exact integral of each gradient.  Blocks
- * of zero duration without events (labels) are dropped.  Stepped blocks are
- * sampled on the uniform raster dt (dt <= 0: the file's RF raster time):
- * every step holds the exact mean over the step of the RF (piecewise
+ * of zero duration without events (labels) are dropped.  Stepped (RF or ADC)
+ * blocks last a whole number of steps of the uniform raster dt (dt <= 0: the
+ * file's RF raster time); relaxation blocks keep their exact duration.  In a
+ * stepped block every step holds the exact mean over the step of the RF (piecewise
  * constant on the RF raster) and of each gradient (piecewise linear:
  * trapezoids, arbitrary gradients on the default timing with their first and
  * last values, or on a time shape).  ADC sample j lies at
@@ -296,6 +297,8 @@ int gbs_plan_cached_summary(const gbs_block *blocks, int64_t n_blocks, const flo
  * sample (phase offset + 2 pi * frequency offset * time since the ADC
  * delay, radians) so that a caller can demodulate by exp(-i adc_phase).
  * RF events with a time shape are rejected.  [EXTENSIONS] is ignored.
+ * Limits: at most 2^28 stepped raster steps and 2^28 ADC samples per file,
+ * 2^26 samples per shape, ids and counts within int32.
  *
  * Two calls.  Query: blocks == NULL; sizes (host int64[3]) receives
  * n_blocks, total_steps, total_samples, nothing else is written.  Fill: the
@@ -307,7 +310,7 @@ int gbs_plan_cached_summary(const gbs_block *blocks, int64_t n_blocks, const flo
  * block-duration raster times (s) of the file.  err (host, err_cap bytes,
  * nullable) receives a NUL-terminated message, empty on success.
  * Errors: GBS_E_INVALID (malformed file, unsupported version or event,
- * block duration or ADC sample off the raster, events outlasting their
+ * stepped-block duration or ADC sample off the raster, events outlasting their
  * block, buffers too small or null), GBS_E_NOMEM.
  */
 int gbs_pulseq_load(const char *text, int64_t text_len, double dt, int64_t sizes[3],

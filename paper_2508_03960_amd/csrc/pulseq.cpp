@@ -22,6 +22,8 @@
 // tesla and T/m through gamma / 2 pi.
 #include <algorithm>
 #include <cctype>
+#include <cerrno>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -35,6 +37,13 @@
 #include "gbloch.h"
 
 namespace {
+
+// Limits on what one file may ask for: stepped raster steps and ADC samples
+// (2^28: 268 s of RF and ADC time on a 1 us raster, about 5.4 GB of
+// waveforms) and samples of one shape.
+constexpr int64_t kMaxSteps = int64_t(1) << 28;
+constexpr int64_t kMaxSamples = int64_t(1) << 28;
+constexpr long kMaxShape = 1L << 26;
 
 struct Fail {
     std::string msg;
@@ -98,8 +107,10 @@ double num(const std::string &s, long line) {
 
 long inum(const std::string &s, long line) {
     char *end = nullptr;
+    errno = 0;
     long v = std::strtol(s.c_str(), &end, 10);
-    if (end == s.c_str() || *end != '\0') fail("line " + std::to_string(line) + ": '" + s + "' is not an integer");
+    if (end == s.c_str() || *end != '\0' || errno == ERANGE || v > INT32_MAX || v < INT32_MIN)
+        fail("line " + std::to_string(line) + ": '" + s + "' is not a 32-bit integer");
     return v;
 }
 
@@ -119,14 +130,15 @@ std::vector<double> decode_shape(const std::vector<double> &packed, long n_sampl
         if (i + 1 < packed.size() && packed[i] == packed[i + 1]) {
             if (i + 2 >= packed.size()) fail("shape " + std::to_string(id) + ": run without a count");
             double r = packed[i + 2];
-            if (r < 0 || r != std::floor(r) || r > 1e9) fail("shape " + std::to_string(id) + ": bad run count");
+            if (r < 0 || r != std::floor(r)) fail("shape " + std::to_string(id) + ": bad run count");
+            if ((double)d.size() + r + 2 > (double)n_samples)
+                fail("shape " + std::to_string(id) + ": decodes to more than num_samples = " + std::to_string(n_samples));
             d.insert(d.end(), (size_t)r + 2, packed[i]);
             i += 3;
         } else {
             d.push_back(packed[i]);
             i += 1;
         }
-        if ((long)d.size() > n_samples) break;
     }
     if ((long)d.size() != n_samples)
         fail("shape " + std::to_string(id) + ": decodes to " + std::to_string(d.size()) + " samples, num_samples is " +
@@ -214,7 +226,8 @@ File parse(const char *text, int64_t len) {
             } else if (t[0] == "num_samples") {
                 if (t.size() != 2 || shape_id < 0) fail("line " + std::to_string(line_no) + ": bad num_samples row");
                 shape_n = inum(t[1], line_no);
-                if (shape_n < 1) fail("line " + std::to_string(line_no) + ": num_samples < 1");
+                if (shape_n < 1 || shape_n > kMaxShape)
+                    fail("line " + std::to_string(line_no) + ": num_samples outside [1, 2^26]");
             } else {
                 if (shape_id < 0 || shape_n < 0) fail("line " + std::to_string(line_no) + ": shape values before shape_id/num_samples");
                 for (auto &s : t) packed.push_back(num(s, line_no));
@@ -303,6 +316,12 @@ double integrate_linear(const Pts &p, double dt, double *acc, int64_t n) {
     return total;
 }
 
+float to_float(double v, const char *what) {
+    float f = (float)v;
+    if (!std::isfinite(f)) fail(std::string(what) + " value outside the float range");
+    return f;
+}
+
 struct Out {
     std::vector<gbs_block> blocks;
     std::vector<float> rf_re, rf_im, g[3];
@@ -316,15 +335,21 @@ void rasterize(const File &f, double dt, bool fill, Out &o, int64_t &steps, int6
     for (const BlockRow &b : f.blocks) {
         const std::string at = "block " + std::to_string(b.num) + ": ";
         double D = b.dur * f.block_raster;
-        double q = D / dt;
-        int64_t n = (int64_t)std::llround(q);
-        if (std::fabs(q - n) > 1e-6 * std::max<double>(1.0, n))
-            fail(at + "duration " + std::to_string(D) + " s is not a whole number of raster steps dt");
         bool has_rf = b.rf != 0, has_adc = b.adc != 0;
         bool has_g = b.g[0] != 0 || b.g[1] != 0 || b.g[2] != 0;
-        if (n == 0) {
+        if (D == 0.0) {
             if (has_rf || has_adc || has_g) fail(at + "events in a block of zero duration");
             continue;  // a label-only block
+        }
+        // only stepped blocks live on the raster; a relaxation block keeps
+        // its exact duration
+        int64_t n = 0;
+        if (has_rf || has_adc) {
+            double q = D / dt;
+            if (!(q <= (double)kMaxSteps)) fail(at + "longer than 2^28 raster steps");
+            n = (int64_t)std::llround(q);
+            if (n == 0 || std::fabs(q - n) > 1e-6 * std::max<double>(1.0, n))
+                fail(at + "duration " + std::to_string(D) + " s is not a whole number of raster steps dt");
         }
         Pts gp[3];
         for (int a = 0; a < 3; ++a) {
@@ -336,12 +361,16 @@ void rasterize(const File &f, double dt, bool fill, Out &o, int64_t &steps, int6
         if (!has_rf && !has_adc) {
             blk.type = GBS_BLOCK_RELAX;
             blk.tau = D;
-            for (int a = 0; a < 3; ++a) blk.moment[a] = b.g[a] ? integrate_linear(gp[a], dt, nullptr, 0) : 0.0;
+            for (int a = 0; a < 3; ++a) {
+                blk.moment[a] = b.g[a] ? integrate_linear(gp[a], dt, nullptr, 0) : 0.0;
+                if (!std::isfinite(blk.moment[a])) fail(at + "gradient moment is not finite");
+            }
             blk.step_offset = steps;
             blk.sample_offset = samples;
             o.blocks.push_back(blk);
             continue;
         }
+        if (steps + n > kMaxSteps) fail("more than 2^28 stepped raster steps");
         blk.type = has_adc ? GBS_BLOCK_ADC : GBS_BLOCK_RF;
         blk.step_offset = steps;
         blk.n_steps = n;
@@ -351,9 +380,13 @@ void rasterize(const File &f, double dt, bool fill, Out &o, int64_t &steps, int6
             if (it == f.adc.end()) fail(at + "missing ADC event " + std::to_string(b.adc));
             const AdcEv &e = it->second;
             if (e.num < 0 || e.dwell_ns <= 0 || e.delay_us < 0) fail(at + "bad ADC event");
+            // samples lie on distinct boundaries 0..n
+            if (e.num > n + 1) fail(at + "ADC samples outlast the block");
+            if (samples + e.num > kMaxSamples) fail("more than 2^28 ADC samples");
             for (long j = 0; j < e.num; ++j) {
                 double t = e.delay_us * 1e-6 + (j + 0.5) * e.dwell_ns * 1e-9;
                 double r = t / dt;
+                if (!(r <= n + 0.5)) fail(at + "ADC samples outlast the block");
                 int64_t k = (int64_t)std::llround(r);
                 if (std::fabs(r - k) > 1e-6 * std::max<double>(1.0, k))
                     fail(at + "ADC sample " + std::to_string(j) + " at " + std::to_string(t) +
@@ -364,7 +397,6 @@ void rasterize(const File &f, double dt, bool fill, Out &o, int64_t &steps, int6
                     o.adc_phase.push_back(e.phase + 2.0 * M_PI * e.freq * (t - e.delay_us * 1e-6));
                 }
             }
-            if (e.num > (int64_t)INT32_MAX) fail(at + "too many ADC samples");
             blk.n_samples = (int32_t)e.num;
             samples += e.num;
         }
@@ -373,7 +405,7 @@ void rasterize(const File &f, double dt, bool fill, Out &o, int64_t &steps, int6
             for (int a = 0; a < 3; ++a) {
                 std::fill(acc.begin(), acc.end(), 0.0);
                 if (b.g[a]) integrate_linear(gp[a], dt, acc.data(), n);
-                for (int64_t j = 0; j < n; ++j) o.g[a].push_back((float)(acc[j] / dt));
+                for (int64_t j = 0; j < n; ++j) o.g[a].push_back(to_float(acc[j] / dt, "gradient"));
             }
             if (has_rf) {
                 auto it = f.rf.find(b.rf);
@@ -402,8 +434,8 @@ void rasterize(const File &f, double dt, bool fill, Out &o, int64_t &steps, int6
                 }
             }
             for (int64_t j = 0; j < n; ++j) {
-                o.rf_re.push_back((float)(re[j] / dt));
-                o.rf_im.push_back((float)(im[j] / dt));
+                o.rf_re.push_back(to_float(re[j] / dt, "RF"));
+                o.rf_im.push_back(to_float(im[j] / dt, "RF"));
             }
             o.blocks.push_back(blk);
         } else {
@@ -457,7 +489,7 @@ extern "C" int gbs_pulseq_load(const char *text, int64_t text_len, double dt, in
             fail("output buffers smaller than the sizes of the sequence");
         if ((steps > 0 && (!rf_re || !rf_im || !gx || !gy || !gz)) || (samples > 0 && !adc_idx))
             fail("a needed output buffer is null");
-        std::memcpy(blocks, o.blocks.data(), o.blocks.size() * sizeof(gbs_block));
+        if (!o.blocks.empty()) std::memcpy(blocks, o.blocks.data(), o.blocks.size() * sizeof(gbs_block));
         if (steps > 0) {
             std::memcpy(rf_re, o.rf_re.data(), steps * sizeof(float));
             std::memcpy(rf_im, o.rf_im.data(), steps * sizeof(float));

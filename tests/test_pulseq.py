@@ -272,3 +272,61 @@ def test_spin_echo_refocuses_off_resonance_through_the_oracle():
     # the echo sample lies at 5.015 ms + 4.99 ms = 10.005 ms, the 90's centre plus TE
     assert echo == pytest.approx(np.exp(-te / 0.08), rel=2e-3)
     assert abs(sig[0]) / n < 0.2 and abs(sig[2]) / n < 0.2
+
+
+@pytest.mark.parametrize("bad,msg", [
+    (FIXTURE_A.replace("5 40 0 2 0 0 2 0", "5 300000000 0 2 0 0 2 0"), "longer than 2\\^28"),
+    (FIXTURE_A.replace("2 4 10000 0 0 0", "2 2000000000 10000 0 0 0"), "outlast the block"),
+    (FIXTURE_A.replace("0.25\n2\n", "0.25\n1000000000\n"), "more than num_samples"),
+    (FIXTURE_A.replace("num_samples 8", "num_samples 99999999"), "outside \\[1, 2\\^26\\]"),
+    (FIXTURE_A.replace("1 8 1 0 0 0 0 0", "1 99999999999 1 0 0 0 0 0"), "32-bit integer"),
+    (FIXTURE_A.replace("1 1000 3 2 3 1", "1 1e300 3 2 3 1"), "float range"),
+    (FIXTURE_A.replace("[RF]\n1 1000", "[RF]\n1 1e300"), "float range"),
+])
+def test_limits(bad, msg):
+    with pytest.raises(gb.GbsError, match=msg):
+        gb.load_pulseq(bad, dt=1e-6)
+
+
+def test_mutated_files_fail_cleanly():
+    """Seeded token, line and truncation mutations of valid files: every call
+    returns a sequence or raises GbsError (the parser reads untrusted text)."""
+    import random
+    from pulseq_text import gre_text
+    rng = random.Random(11)
+    bases = [FIXTURE_A, gre_text(n_lines=2, n_read=16)]
+    vals = ["0", "-1", "1e300", "2147483648", "1e-300", "nan", "inf", "0.5", "3", "", "x", "[BLOCKS]",
+            "shape_id", "num_samples", "268435457"]
+    ok = 0
+    for _ in range(400):
+        lines = rng.choice(bases).split("\n")
+        for _ in range(rng.randint(1, 5)):
+            j, r = rng.randrange(len(lines)), rng.random()
+            if r < 0.6:
+                toks = lines[j].split(" ")
+                toks[rng.randrange(len(toks))] = rng.choice(vals)
+                lines[j] = " ".join(toks)
+            elif r < 0.8:
+                del lines[j]
+            else:
+                lines.insert(j, lines[rng.randrange(len(lines))])
+        text = "\n".join(lines)
+        if rng.random() < 0.1:
+            text = text[:rng.randrange(len(text) + 1)]
+        try:
+            s = gb.load_pulseq(text, dt=rng.choice([None, 1e-6, 2e-6]))
+            assert np.isfinite(s.rf_re).all() and np.isfinite(s.gx).all() and np.isfinite(s.moment).all()
+            ok += 1
+        except gb.GbsError:
+            pass
+    assert ok > 0
+
+
+def test_relaxation_blocks_keep_their_exact_duration():
+    # a 2000 s delay is no raster work; a 7.5 us one need not lie on the raster
+    s = gb.load_pulseq(FIXTURE_A.replace("3 40 0 2 0 0 0 0", "3 2000000000 0 2 0 0 0 0"), dt=1e-6)
+    assert s.tau[2] == pytest.approx(2000.0, rel=1e-15) and s.total_steps == 66
+    t = SeqText(block_raster=0.5e-6)
+    t.block(15)
+    s = gb.load_pulseq(t.text(), dt=1e-6)
+    assert s.n_blocks == 1 and s.tau[0] == pytest.approx(7.5e-6, rel=1e-12)
