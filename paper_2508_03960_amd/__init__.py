@@ -218,18 +218,18 @@ class PulseqSequence:
 
 
 def load_pulseq(source, dt=None, name=None):
-    """Read a Pulseq 1.4 sequence (a path, or the file's text as str/bytes)
-    into a PulseqSequence on the raster ``dt`` (s; None = the file's RF
+    """Read a Pulseq 1.4 sequence (a path; or the file's text as bytes, or as
+    a str of several lines) into a PulseqSequence on the raster ``dt`` (s; None = the file's RF
     raster time).  Raises GbsError with the parser's message on a bad file."""
     import numpy as np
     if isinstance(source, (bytes, bytearray)):
         text = bytes(source)
-    elif isinstance(source, str) and "\n" not in source and os.path.exists(source):
-        with open(source, "rb") as fh:
+    elif isinstance(source, os.PathLike) or (isinstance(source, str) and "\n" not in source):
+        with open(source, "rb") as fh:  # a path (one line); file text has several
             text = fh.read()
-        name = name or os.path.basename(source)
+        name = name or os.path.basename(os.fspath(source))
     else:
-        text = str(source).encode()
+        text = source.encode()
     err = ctypes.create_string_buffer(512)
     sizes = (ctypes.c_int64 * 3)()
     rasters = (ctypes.c_double * 4)()

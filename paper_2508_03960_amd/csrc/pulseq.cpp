@@ -237,6 +237,7 @@ File parse(const char *text, int64_t len) {
         // simulation uses.
     }
     close_shape();
+    if (f.major < 0 || f.minor < 0) fail("no [VERSION] section with major and minor");
     if (f.major != 1 || f.minor != 4)
         fail("Pulseq format version " + std::to_string(f.major) + "." + std::to_string(f.minor) +
              " is not supported (format 1.4 only)");

@@ -314,7 +314,7 @@ def test_mutated_files_fail_cleanly():
         if rng.random() < 0.1:
             text = text[:rng.randrange(len(text) + 1)]
         try:
-            s = gb.load_pulseq(text, dt=rng.choice([None, 1e-6, 2e-6]))
+            s = gb.load_pulseq(text.encode(), dt=rng.choice([None, 1e-6, 2e-6]))
             assert np.isfinite(s.rf_re).all() and np.isfinite(s.gx).all() and np.isfinite(s.moment).all()
             ok += 1
         except gb.GbsError:
@@ -330,3 +330,14 @@ def test_relaxation_blocks_keep_their_exact_duration():
     t.block(15)
     s = gb.load_pulseq(t.text(), dt=1e-6)
     assert s.n_blocks == 1 and s.tau[0] == pytest.approx(7.5e-6, rel=1e-12)
+
+
+def test_paths_and_missing_version(tmp_path):
+    f = tmp_path / "a.seq"
+    f.write_text(FIXTURE_A)
+    assert gb.load_pulseq(str(f)).total_steps == 66
+    assert gb.load_pulseq(f).name == "a.seq"
+    with pytest.raises(FileNotFoundError):
+        gb.load_pulseq(str(tmp_path / "missing.seq"))
+    with pytest.raises(gb.GbsError, match="no \\[VERSION\\]"):
+        gb.load_pulseq(FIXTURE_A.replace("major 1\n", ""))
