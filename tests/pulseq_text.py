@@ -133,3 +133,49 @@ def gre_text(n_lines=4, n_read=32, flip_deg=30.0, thk=0.005, fov=0.2, te_fill=10
         t.block(30, gz=spoil)
         t.block(tr_fill)
     return t.text()
+
+
+def epi_text(n_lines=8, n_read=32, fov=0.2, thk=0.005):
+    """Single-shot EPI as Pulseq text: the sinc excitation under a slice
+    trapezoid, prephasers, then n_lines readouts of alternating polarity
+    (trapezoids with their ADC, 10 us dwell) separated by Gy blips."""
+    import numpy as np
+    t = SeqText()
+    n_rf = 400
+    x = (np.arange(n_rf) + 0.5) / n_rf - 0.5
+    env = np.sinc(4 * x) * (0.54 + 0.46 * np.cos(2 * np.pi * x))
+    env = env / env.max()
+    rf = t.rf(np.pi / 2 / (2 * np.pi * env.sum() * 1e-6), env, delay_us=100)
+    gz_amp = (4 / 400e-6) / thk
+    gz = t.trap(gz_amp, 100, 400, 100)
+    gz_reph = t.trap(-gz_amp * 250e-6 / 400e-6, 100, 300, 100)
+    dk = 1.0 / fov
+    g_read = dk / 10e-6
+    ro = [t.trap(s * g_read, 50, n_read * 10, 50) for s in (1, -1)]
+    gx_pre = t.trap(-g_read * (n_read * 10 / 2 + 30) / 400, 100, 300, 100)
+    gy_pre = t.trap(-(n_lines // 2) * dk / 400e-6, 100, 300, 100)
+    blip = t.trap(dk / 20e-6, 10, 10, 10)
+    adc = t.adc(n_read, 10000, 50)
+    t.block(60, rf=rf, gz=gz)
+    t.block(50, gx=gx_pre, gy=gy_pre, gz=gz_reph)
+    for line in range(n_lines):
+        t.block(10 + n_read, gx=ro[line % 2], adc=adc)
+        if line + 1 < n_lines:
+            t.block(3, gy=blip)
+    t.block(100)
+    return t.text()
+
+
+def rf_during_adc_text(n=200):
+    """A hard 30 degree pulse, then an ADC block that also plays weak RF
+    (a constant 50 Hz B1) under a readout gradient: RF during ADC."""
+    import numpy as np
+    t = SeqText()
+    p30 = t.rf(np.deg2rad(30) / (2 * np.pi * 100e-6), np.ones(100))
+    weak = t.rf(50.0, np.ones(n * 10), phase_off=0.3)
+    g = t.trap(2e5, 50, n * 10 - 100, 50)
+    adc = t.adc(n, 10000, 0)
+    t.block(10, rf=p30)
+    t.block(n, rf=weak, gx=g, adc=adc)
+    t.block(200)
+    return t.text()
