@@ -30,3 +30,16 @@ def test_random_case(gb, seed):
     m_init = rng.uniform(-0.6, 0.6, (3, K)) if seed % 2 else None
     check_case(gb, f"random{seed}:{'+'.join(kinds)}", ph, seq, modes=("plain", "grouped", "cached"),
                axes=31 if seed % 2 == 0 else 7, m_init=m_init)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_case_large_groups(gb, seed):
+    """K from 500 to 5000 on the same few key values: groups of hundreds of
+    members that span several tiles, with ragged padding."""
+    rng = np.random.default_rng(5000 + seed)
+    K = int(rng.integers(500, 5001))
+    kinds = list(rng.choice(rc.KINDS, size=int(rng.integers(2, 7))))
+    ph, seq = rc.phantom(rng, K), rc.sequence(rng, kinds)
+    m_init = rng.uniform(-0.6, 0.6, (3, K)) if seed % 2 else None
+    check_case(gb, f"random-large{seed}:{'+'.join(kinds)}", ph, seq, modes=("plain", "grouped", "cached"),
+               axes=31, m_init=m_init)
