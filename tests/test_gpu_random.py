@@ -43,3 +43,22 @@ def test_random_case_large_groups(gb, seed):
     m_init = rng.uniform(-0.6, 0.6, (3, K)) if seed % 2 else None
     check_case(gb, f"random-large{seed}:{'+'.join(kinds)}", ph, seq, modes=("plain", "grouped", "cached"),
                axes=31, m_init=m_init)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_random_case_coils(gb, seed):
+    """Random cases with 2 to 4 receive coils of random complex sensitivity,
+    from a random initial state: grouped, cached and plain against the
+    oracle's coil sums."""
+    from tests.test_gpu_coils import check as check_coils
+    rng = np.random.default_rng(9000 + seed)
+    while True:
+        K = int(rng.integers(1, 65))
+        kinds = list(rng.choice(rc.KINDS, size=int(rng.integers(1, 7))))
+        ph, seq = rc.phantom(rng, K), rc.sequence(rng, kinds)
+        if seq.total_samples > 0:
+            break
+    P = int(rng.integers(2, 5))
+    sens = (rng.uniform(0.2, 1.0, (P, K)) * np.exp(1j * rng.uniform(0, 2 * np.pi, (P, K)))).astype(np.complex64)
+    m_init = rng.uniform(-0.6, 0.6, (3, K))
+    check_coils(gb, f"random{seed}:{'+'.join(kinds)}", ph, seq, sens, m_init=m_init, plain=True)
