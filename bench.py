@@ -284,7 +284,7 @@ def main():
     ap.add_argument("--no-nograds", action="store_true",
                     help="skip the fat-saturated FSE (no-grads groups vs x-groups)")
     ap.add_argument("--no-table2", action="store_true",
-                    help="skip the four sequences of the paper's Table 2 (grouped vs cached)")
+                    help="skip the four sequences of the paper's Table 2 (grouped vs cached) and the EPI read from a Pulseq file")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -486,6 +486,22 @@ def main():
                 "cached_vs_grouped": {"max_abs_dM": float(np.max(np.abs(m_out.cpu().numpy() - M_g))),
                                       "rel_signal": float(np.linalg.norm(s_c - s_g) / np.linalg.norm(s_g))}}
             log(f"table2 {name}: {out['table2'][name]}")
+
+    # ---- the same EPI shape read from a Pulseq file: loader time and the grouped run -------
+    if not args.no_table2:
+        from synth.pulseq import epi_text
+        txt = epi_text(n_lines=128, n_read=128, fov=0.256, dwell_us=4, ramp_us=44).encode()
+        t0 = time.perf_counter()
+        pseq = gb.load_pulseq(txt)
+        t_load = time.perf_counter() - t0
+        sim.set_sequence(pseq)
+        sig_q = torch.empty(pseq.total_samples, 2, device=dev, dtype=torch.float64)
+        sec_q, _ = timed_runs(sim, gb, gb.GBS_GROUPED, max(1, min(args.steps, 3)), 1, m_out, sig_q)
+        S_q = int(pseq.n_steps[pseq.btype != gb.GBS_BLOCK_RELAX].sum())
+        out["pulseq_epi"] = {"grouped_ms": sec_q * 1e3, "grouped_iso_steps_per_s": K * S_q / sec_q,
+                             "stepped_steps": S_q, "load_ms": t_load * 1e3, "file_bytes": len(txt),
+                             "blocks": pseq.n_blocks, "plan": gb.gbs_plan_summary(pseq)}
+        log(f"Pulseq EPI: {out['pulseq_epi']}")
 
     # ---- plain FSE: first shot (1/16 of the sequence) at full K -------------------------
     if not args.no_plain:

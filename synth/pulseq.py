@@ -1,6 +1,8 @@
-"""Writes the text of Pulseq 1.4 sequence files for tests of the loader.
+"""Writes the text of Pulseq 1.4 sequence files: seeded-free workload
+generators for the Pulseq loader (inputs only, none of the simulation's
+arithmetic).
 
-Test helper only: the sections and columns of format 1.4 ([VERSION],
+The sections and columns of format 1.4 ([VERSION],
 [DEFINITIONS], [BLOCKS], [RF], [GRADIENTS], [TRAP], [ADC], [SHAPES]), and
 shapes in the compressed form (the derivative, with a run of r >= 2 equal
 values written as v, v, r - 2) or uncompressed.
@@ -135,11 +137,16 @@ def gre_text(n_lines=4, n_read=32, flip_deg=30.0, thk=0.005, fov=0.2, te_fill=10
     return t.text()
 
 
-def epi_text(n_lines=8, n_read=32, fov=0.2, thk=0.005):
+def epi_text(n_lines=8, n_read=32, fov=0.2, thk=0.005, dwell_us=10, ramp_us=50):
     """Single-shot EPI as Pulseq text: the sinc excitation under a slice
     trapezoid, prephasers, then n_lines readouts of alternating polarity
-    (trapezoids with their ADC, 10 us dwell) separated by Gy blips."""
+    (trapezoids with their ADC, one k-space step per dwell) separated by Gy
+    blips.  A readout block lasts 2 ramp_us + n_read dwell_us, a whole number
+    of 10 us block-raster units."""
     import numpy as np
+    ro_us = 2 * ramp_us + n_read * dwell_us
+    if ro_us % 10:
+        raise ValueError("readout duration must be a multiple of the 10 us block raster")
     t = SeqText()
     n_rf = 400
     x = (np.arange(n_rf) + 0.5) / n_rf - 0.5
@@ -150,16 +157,17 @@ def epi_text(n_lines=8, n_read=32, fov=0.2, thk=0.005):
     gz = t.trap(gz_amp, 100, 400, 100)
     gz_reph = t.trap(-gz_amp * 250e-6 / 400e-6, 100, 300, 100)
     dk = 1.0 / fov
-    g_read = dk / 10e-6
-    ro = [t.trap(s * g_read, 50, n_read * 10, 50) for s in (1, -1)]
-    gx_pre = t.trap(-g_read * (n_read * 10 / 2 + 30) / 400, 100, 300, 100)
+    g_read = dk / (dwell_us * 1e-6)
+    ro = [t.trap(s * g_read, ramp_us, n_read * dwell_us, ramp_us) for s in (1, -1)]
+    # k = 0 at sample n_read / 2 of the first readout
+    gx_pre = t.trap(-g_read * (n_read * dwell_us / 2 + ramp_us / 2 + dwell_us / 2) / 400, 100, 300, 100)
     gy_pre = t.trap(-(n_lines // 2) * dk / 400e-6, 100, 300, 100)
     blip = t.trap(dk / 20e-6, 10, 10, 10)
-    adc = t.adc(n_read, 10000, 50)
+    adc = t.adc(n_read, dwell_us * 1000, ramp_us)
     t.block(60, rf=rf, gz=gz)
     t.block(50, gx=gx_pre, gy=gy_pre, gz=gz_reph)
     for line in range(n_lines):
-        t.block(10 + n_read, gx=ro[line % 2], adc=adc)
+        t.block(ro_us // 10, gx=ro[line % 2], adc=adc)
         if line + 1 < n_lines:
             t.block(3, gy=blip)
     t.block(100)

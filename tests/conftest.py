@@ -6,7 +6,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
-HERE = os.path.dirname(os.path.abspath(__file__))  # test helpers (pulseq_text)
+HERE = os.path.dirname(os.path.abspath(__file__))  # test helpers (random_cases)
 if HERE not in sys.path:
     sys.path.insert(1, HERE)
 

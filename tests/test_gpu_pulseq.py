@@ -8,7 +8,7 @@ import pytest
 
 import oracle
 import synth
-from pulseq_text import epi_text, gre_text, rf_during_adc_text
+from synth.pulseq import epi_text, gre_text, rf_during_adc_text
 
 pytestmark = pytest.mark.gpu
 

@@ -15,7 +15,7 @@ import pytest
 import oracle
 import synth
 import paper_2508_03960_amd as gb
-from pulseq_text import SeqText, compress
+from synth.pulseq import SeqText, compress
 
 GB = 42.577478518e6  # gamma / 2 pi (Hz/T), as the library states it
 
@@ -292,7 +292,7 @@ def test_mutated_files_fail_cleanly():
     """Seeded token, line and truncation mutations of valid files: every call
     returns a sequence or raises GbsError (the parser reads untrusted text)."""
     import random
-    from pulseq_text import gre_text
+    from synth.pulseq import gre_text
     rng = random.Random(11)
     bases = [FIXTURE_A, gre_text(n_lines=2, n_read=16)]
     vals = ["0", "-1", "1e300", "2147483648", "1e-300", "nan", "inf", "0.5", "3", "", "x", "[BLOCKS]",
