@@ -1,4 +1,4 @@
-"""Writes the text of Pulseq 1.4 sequence files: seeded-free workload
+"""Writes the text of Pulseq 1.4 sequence files: deterministic workload
 generators for the Pulseq loader (inputs only, none of the simulation's
 arithmetic).
 
