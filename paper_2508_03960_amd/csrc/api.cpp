@@ -1135,10 +1135,14 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
         }
     }
     // a sweep whose emissions need no recurrence holds a repeated pre-map y
-    // phase in the recurrence's factor instead of evaluating it per op
+    // phase in the recurrence's factor instead of evaluating it per op.  A
+    // stepped emission needs the factor even without kYSetR: a chain whose
+    // step is zero (emissions at the same y moment) multiplies by the 1 the
+    // factor starts with.
     for (const auto &sg : g.segs) {
         bool free_factor = true;
-        for (int o = sg.op_begin; o < sg.op_end; ++o) free_factor = free_factor && !(sops[o].flags & kYSetR);
+        for (int o = sg.op_begin; o < sg.op_end; ++o)
+            free_factor = free_factor && !(sops[o].flags & (kYSetR | kYStep));
         if (!free_factor) continue;
         double held = 0.0;
         bool have = false;

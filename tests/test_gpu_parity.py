@@ -230,6 +230,37 @@ def test_run_boundaries(gb):
     check_case(gb, "plain-ends+m_init", ph, seq, modes=("grouped",), m_init=rng.uniform(-0.5, 0.5, (3, ph.K)))
 
 
+def multi_echo_gre(n_lines=6, n_echo=3, n_read=16, dwell_steps=4, rf_steps=400, fov=(0.05, 0.05), thk=0.005):
+    """Multi-echo GRE without a Gy rewinder: every TR adds its phase-encode
+    moment to the pending map of the next excitation, and the echoes of a line
+    share one y moment (Gx flybacks between them), so their y phases repeat."""
+    sb = SeqBuilder(1e-6, "multi-echo gre, no Gy rewinder")
+    b1 = synth.sinc_pulse(rf_steps, 1e-6, 0.5)
+    gz = synth.slice_gradient(rf_steps, 1e-6, thk)
+    g_ro = synth.readout_gradient(dwell_steps * 1e-6, fov[0])
+    ro = n_read * dwell_steps
+    samples = dwell_steps * np.arange(n_read) + dwell_steps // 2
+    for line in range(n_lines):
+        my = (line - n_lines // 2) / (synth.GAMMA_BAR * fov[1])
+        sb.rf(b1, (0.0, 0.0, gz))
+        sb.relax(4e-4, (-0.5 * g_ro * ro * 1e-6, my, -0.5 * gz * rf_steps * 1e-6))
+        for e in range(n_echo):
+            sb.adc(ro, (g_ro, 0.0, 0.0), samples)
+            if e + 1 < n_echo:
+                sb.relax(2e-4, (-g_ro * ro * 1e-6, 0.0, 0.0))
+        sb.relax(2e-3, (0.5 * g_ro * ro * 1e-6, 0.0, 4.0 / (synth.GAMMA_BAR * thk)))
+    return sb.build()
+
+
+def test_multi_echo_without_y_rewinder(gb):
+    """Echoes at one y moment after a pre map with a y phase: the stepped y
+    phase of a repeated emission must not take the pre map's held factor."""
+    ph = synth.gre_phantom(24, 20, 2, seed=8)
+    seq = multi_echo_gre()
+    check_case(gb, "multi-echo", ph, seq, modes=("plain", "grouped", "cached"))
+    check_case(gb, "multi-echo/xyz", ph, seq, modes=("grouped",), axes=31)
+
+
 def test_grouped_is_repeatable(gb):
     ph, seq = synth.workload("fse-small")
     M1, s1, _ = run_gpu(gb, ph, seq, gb.GBS_GROUPED)

@@ -62,3 +62,17 @@ def test_random_case_coils(gb, seed):
     sens = (rng.uniform(0.2, 1.0, (P, K)) * np.exp(1j * rng.uniform(0, 2 * np.pi, (P, K)))).astype(np.complex64)
     m_init = rng.uniform(-0.6, 0.6, (3, K))
     check_coils(gb, f"random{seed}:{'+'.join(kinds)}", ph, seq, sens, m_init=m_init, plain=True)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_repeated_emissions(gb, seed):
+    """relax -> RF -> relax -> ADC -> ADC: the pending map before the RF has a
+    y moment, and the two readouts share theirs, so the second emission's y
+    phase steps by a zero step after the pre map's y phase was evaluated."""
+    rng = np.random.default_rng(7000 + seed)
+    K = int(rng.integers(1, 65))
+    rf = str(rng.choice(["rf_x", "rf_z", "rf_none"]))
+    adc = str(rng.choice(["adc_x", "adc_z"]))
+    kinds = ["relax", rf, "relax", adc, adc] * int(rng.integers(1, 3))
+    ph, seq = rc.phantom(rng, K), rc.sequence(rng, kinds)
+    check_case(gb, f"repeat{seed}:{'+'.join(kinds)}", ph, seq, modes=("grouped",), axes=31 if seed % 2 else 7)
