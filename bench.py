@@ -74,7 +74,9 @@ def traffic_per_launch():
 
 
 def cpu_baseline(ph, seq, target_s=15.0):
-    """FP64 oracle on a seeded subset of isochromats, whole FSE sequence."""
+    """FP64 oracle on a seeded subset of isochromats, whole FSE sequence.
+    Returns the timing record, the subset's indices and the oracle's M and
+    signal of the subset as a phantom of its own."""
     import numpy as np
 
     import oracle
@@ -85,15 +87,36 @@ def cpu_baseline(ph, seq, target_s=15.0):
     t = time.perf_counter()
     oracle.simulate(ph.subset(idx0), seq)
     t_one = time.perf_counter() - t
-    n = int(max(nt, min(64 * nt, nt * round(target_s / max(t_one, 1e-3)))))
+    n = int(max(nt, min(512 * nt, nt * round(target_s / max(t_one, 1e-3)))))
     idx = synth.random_subset_indices(ph.K, n, seed=7)
     sub = ph.subset(idx)
     t = time.perf_counter()
-    M, _ = oracle.simulate(sub, seq)
+    M, sig = oracle.simulate(sub, seq)
     dt = time.perf_counter() - t
     return {"value": n * S / dt, "unit": "isochromat-steps/s", "cores": nt, "kind": "oracle",
             "sample": f"{n} seeded isochromats of the 27,262,976 x full FSE sequence "
-                      f"({S} stepped raster steps each), FP64, {dt:.1f} s"}, idx, M
+                      f"({S} stepped raster steps each), FP64, {dt:.1f} s"}, idx, M, sig
+
+
+def subset_errors(gb, ph, seq, M_full, idx, M_ref, sig_ref):
+    """Errors of the grouped path against the oracle on a subset: max |dM| of
+    the subset's rows of the full-phantom run, and the relative signal error
+    of the subset simulated (grouped) as a phantom of its own."""
+    import numpy as np
+    import torch
+    sim = gb.Simulator(0)
+    try:
+        sim.set_phantom(ph.subset(idx))
+        sim.build_groups()
+        sim.set_sequence(seq)
+        _, s = sim.simulate(gb.GBS_GROUPED)
+        torch.cuda.synchronize()
+        s = s.cpu().numpy()
+    finally:
+        sim.close()
+    return {"subset_isochromats": int(idx.size),
+            "max_abs_dM": float(np.max(np.abs(M_full[:, idx] - M_ref))),
+            "rel_signal": float(np.linalg.norm(s - sig_ref) / np.linalg.norm(sig_ref))}
 
 
 # FP64 flops of one raster step of the per-isochromat composition [A | b] <- D R [A | b]
@@ -518,18 +541,17 @@ def main():
 
     # ---- FP64 oracle on the host cores, and the sampled error of the timed run -----------
     if not args.no_cpu:
-        cb, idx, M_ref = cpu_baseline(ph, fse)
+        cb, idx, M_ref, s_ref = cpu_baseline(ph, fse)
         out["cpu_baseline"] = cb
-        out["fse"]["max_abs_dM_vs_oracle_sampled"] = float(np.max(np.abs(M_fse[:, idx] - M_ref)))
-        out["fse"]["oracle_sample_isochromats"] = int(idx.size)
-        log(f"cpu baseline {cb}")
-        if not args.no_epi:  # the EPI run's sampled error as well (256 isochromats)
+        out["fse"]["vs_oracle"] = subset_errors(gb, ph, fse, M_fse, idx, M_ref, s_ref)
+        log(f"cpu baseline {cb}; FSE vs oracle {out['fse']['vs_oracle']}")
+        if not args.no_epi:  # the EPI run's error on a 16,384-isochromat subset as well
             import oracle
             import synth
-            idx_e = synth.random_subset_indices(K, 256, seed=8)
-            M_ref_e, _ = oracle.simulate(ph.subset(idx_e), epi)
-            out["epi"]["max_abs_dM_vs_oracle_sampled"] = float(np.max(np.abs(M_epi[:, idx_e] - M_ref_e)))
-            out["epi"]["oracle_sample_isochromats"] = int(idx_e.size)
+            idx_e = synth.random_subset_indices(K, 1 << 14, seed=8)
+            M_ref_e, s_ref_e = oracle.simulate(ph.subset(idx_e), epi)
+            out["epi"]["vs_oracle"] = subset_errors(gb, ph, epi, M_epi, idx_e, M_ref_e, s_ref_e)
+            log(f"EPI vs oracle {out['epi']['vs_oracle']}")
     print(json.dumps(out), flush=True)
     sim.close()
 

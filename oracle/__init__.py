@@ -35,7 +35,7 @@ def build(force: bool = True) -> str:
     """Compile the C oracle with gcc + OpenMP into oracle/liboracle.so."""
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
+        cmd = ["gcc", "-O3", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
                SRC_PATH, ADJ_PATH, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, LIB_PATH)

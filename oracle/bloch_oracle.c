@@ -106,12 +106,13 @@ static void matvec4(double A[4][4], const double v[4], double w[4])
     }
 }
 
-/* Eq. (2): one raster step, U = D * R applied to the homogeneous vector. */
-static void oracle_step(double M[4], double bx, double by, double bz, double dt, double t1, double t2)
+/* Eq. (2): one raster step, U = D * R applied to the homogeneous vector.
+ * D depends on dt, T1 and T2 only, so the caller builds it once per
+ * isochromat. */
+static void oracle_step(double M[4], double bx, double by, double bz, double dt, double D[4][4])
 {
-    double R[4][4], D[4][4], U[4][4], out[4];
+    double R[4][4], U[4][4], out[4];
     rotation_matrix(bx, by, bz, dt, R);
-    relaxation_matrix(dt, t1, t2, D);
     matmul4(D, R, U);
     matvec4(U, M, out);
     memcpy(M, out, sizeof(out));
@@ -216,6 +217,8 @@ int oracle_simulate(int64_t K, const double *x, const double *y, const double *z
             }
             M[3] = m0[k];
             double bz_off = df[k] / OR_GAMMA_BAR; /* tesla */
+            double D[4][4];
+            relaxation_matrix(dt, t1[k], t2[k], D);
             for (int64_t b = 0; b < n_blocks; ++b) {
                 if (btype[b] == OR_BLOCK_RELAX) {
                     oracle_relax(M, tau[b], moment + 3 * b, x[k], y[k], z[k], df[k], t1[k], t2[k]);
@@ -234,7 +237,7 @@ int oracle_simulate(int64_t K, const double *x, const double *y, const double *z
                         break;
                     int64_t s = s0 + j;
                     double bz = gx[s] * x[k] + gy[s] * y[k] + gz[s] * z[k] + bz_off;
-                    oracle_step(M, rf_re[s], rf_im[s], bz, dt, t1[k], t2[k]);
+                    oracle_step(M, rf_re[s], rf_im[s], bz, dt, D);
                 }
             }
             m_out[k] = M[0];
