@@ -52,6 +52,7 @@ extern "C" {
 #define GBS_E_STATE (-2)   /* call order: no phantom / sequence, groups missing or stale */
 #define GBS_E_HIP (-3)     /* a HIP runtime call or kernel launch failed */
 #define GBS_E_NOMEM (-4)   /* device or host allocation failed */
+#define GBS_E_WORKSPACE (-5) /* gbs_simulate: workspace null, smaller than gbs_workspace_size, or not 256-byte aligned */
 
 /* ---- block types (Sec. 2.1, Fig. 1) ---------------------------------- */
 #define GBS_BLOCK_RF 1    /* with-RF subsequence: stepped, samples not allowed */
@@ -211,7 +212,7 @@ int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, co
  * whose type needs an axis that was not built are stepped per isochromat,
  * except that no-grads blocks use the x groups when GBS_AX_N is absent.  The
  * context
- * stores a copy of the phantom in group-sorted order (about 13 float/int32
+ * stores a copy of the phantom in group-sorted order (about 12 float/int32
  * words per isochromat).  Synchronizes the stream.
  * Errors: GBS_E_STATE (no phantom), GBS_E_INVALID (no GBS_AX_X, unknown bits,
  * GBS_AX_XZ without GBS_AX_Z),
@@ -220,25 +221,55 @@ int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, co
 int gbs_build_groups(gbs_ctx *ctx, uint32_t axes);
 
 /*
- * Run the sequence on the phantom.  mode = GBS_PLAIN, GBS_GROUPED or
- * GBS_CACHED (GBS_CACHED needs no groups).
+ * Device memory a gbs_simulate call of `mode` needs besides its inputs and
+ * outputs, for the current phantom, sequence, groups, coils and surrogate
+ * (the largest over the flags of that mode).  The caller allocates it and
+ * passes it to gbs_simulate; the library allocates nothing on that path.
+ *   GBS_GROUPED: the state in group-sorted order (28 bytes per slot of the
+ *     padded layout: three float planes and one (mx, my, mz, 0) row), the
+ *     combined-transition and map tables of every grouped subsequence
+ *     (Eq. 7, Eq. 4/5), the FP64 group sums of every with-ADC subsequence
+ *     (Eq. 9), partial sample sums when blocks are stepped, and the
+ *     surrogate's buffers when one is attached (gbs_set_surrogate).
+ *   GBS_CACHED: the FP64 state (24 bytes per isochromat), the transition
+ *     cache of Sec. 2.2 (48 bytes per isochromat and distinct with-RF
+ *     waveform) and partial sample sums.
+ *   GBS_PLAIN: partial sample sums, and the FP64 state between launches.
+ * Errors: GBS_E_INVALID (bytes null, bad mode), GBS_E_STATE (no phantom or
+ * sequence; GBS_GROUPED without groups).
+ */
+int gbs_workspace_size(gbs_ctx *ctx, int mode, size_t *bytes);
+
+/*
+ * Run the sequence on the phantom (Sec. 2.1: Eq. 2-6 per isochromat; the
+ * grouped method of Sec. 2.3-2.4, Eq. 7-10; the cached conventional method
+ * of Sec. 2.2).  mode = GBS_PLAIN, GBS_GROUPED or GBS_CACHED (GBS_CACHED
+ * needs no groups).
+ * workspace: device memory of at least gbs_workspace_size(ctx, mode) bytes,
+ *          256-byte aligned, owned by the caller.  Its contents are scratch:
+ *          nothing is kept in it from one call to the next, and the caller
+ *          may reuse it between calls; concurrent calls need separate
+ *          workspaces.  Passing the same workspace as the last call avoids
+ *          a small upload of the grouped schedule's descriptors.
+ * ws_bytes: its size.
  * m_init: device float[3*K] SoA (Mx, My, Mz) or NULL for (0, 0, M0).
  * m_out: device float[3*K] SoA final magnetization (may alias m_init).
  * sig_out: device double[2*n_coils*total_samples], interleaved (re, im), Eq. (6),
  *          coil-major (row p holds coil p; n_coils = 1 without gbs_set_coils).
  * stats: host, nullable.  Without GBS_ASYNC the call synchronizes the stream.
- * GBS_PLAIN and GBS_CACHED keep the state between launches in FP64 (3 * K
- * doubles owned by the context).  GBS_CACHED also owns the transition cache:
- * 3 float4 rows (A_i0, A_i1, A_i2, b_i) of K per distinct with-RF waveform
- * (bit-identical B1 and gradients), 48 * K bytes each, recomposed by every
- * call; the state and cache allocations fail with GBS_E_NOMEM when they do
- * not fit.  With-ADC blocks that play RF are stepped per isochromat in every
- * mode.
+ * GBS_PLAIN and GBS_CACHED keep the state between launches in FP64.
+ * GBS_CACHED recomposes its transition cache (3 float4 rows (A_i0, A_i1,
+ * A_i2, b_i) of K per distinct with-RF waveform: bit-identical B1 and
+ * gradients) in every call.  With-ADC blocks that play RF are stepped per
+ * isochromat in every mode.  The schedules this call runs were built by the
+ * setters (gbs_set_sequence, gbs_build_groups, gbs_set_coils,
+ * gbs_set_surrogate), which also hold their small device arrays.
  * Errors: GBS_E_STATE (no phantom/sequence; GROUPED without valid X groups),
- * GBS_E_INVALID (null outputs, bad mode), GBS_E_NOMEM, GBS_E_HIP.
+ * GBS_E_INVALID (null outputs, bad mode, unknown flags), GBS_E_WORKSPACE,
+ * GBS_E_HIP.
  */
-int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float *m_init, float *m_out,
-                 double *sig_out, gbs_stats *stats);
+int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, void *workspace, size_t ws_bytes,
+                 const float *m_init, float *m_out, double *sig_out, gbs_stats *stats);
 
 /* Sizes and group counts of the current state. */
 int gbs_get_info(gbs_ctx *ctx, gbs_info *info);

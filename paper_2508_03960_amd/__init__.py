@@ -16,7 +16,7 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgbloch.so")
 
-GBS_OK, GBS_E_INVALID, GBS_E_STATE, GBS_E_HIP, GBS_E_NOMEM = 0, -1, -2, -3, -4
+GBS_OK, GBS_E_INVALID, GBS_E_STATE, GBS_E_HIP, GBS_E_NOMEM, GBS_E_WORKSPACE = 0, -1, -2, -3, -4, -5
 GBS_BLOCK_RF, GBS_BLOCK_ADC, GBS_BLOCK_RELAX = 1, 2, 3
 GBS_AX_X, GBS_AX_Y, GBS_AX_Z, GBS_AX_N, GBS_AX_XZ = 1, 2, 4, 8, 16
 GBS_AX_ALL = GBS_AX_X | GBS_AX_Y | GBS_AX_Z | GBS_AX_N | GBS_AX_XZ
@@ -28,7 +28,7 @@ GBS_SURROGATE = 8
 GBS_MLP_PARAMS = 35340
 
 EXPORTED = ("gbs_create", "gbs_destroy", "gbs_set_phantom", "gbs_set_sequence", "gbs_build_groups",
-            "gbs_simulate", "gbs_get_info", "gbs_last_error", "gbs_strerror", "gbs_plan_summary",
+            "gbs_simulate", "gbs_workspace_size", "gbs_get_info", "gbs_last_error", "gbs_strerror", "gbs_plan_summary",
             "gbs_plan_cached_summary", "gbs_set_coils",
             "gbs_mlp_create", "gbs_mlp_destroy", "gbs_mlp_last_error", "gbs_mlp_set_pulse",
             "gbs_mlp_set_norm", "gbs_mlp_get_params", "gbs_mlp_set_params", "gbs_mlp_exact",
@@ -88,7 +88,8 @@ def _load(path=LIB_PATH):
         "gbs_set_coils": ([P, I32, P, P], ctypes.c_int),
         "gbs_set_sequence": ([P, P, I64, P, P, P, P, P, I64, P, I64, D], ctypes.c_int),
         "gbs_build_groups": ([P, U32], ctypes.c_int),
-        "gbs_simulate": ([P, ctypes.c_int, U32, P, P, P, P], ctypes.c_int),
+        "gbs_simulate": ([P, ctypes.c_int, U32, P, ctypes.c_size_t, P, P, P, P], ctypes.c_int),
+        "gbs_workspace_size": ([P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "gbs_get_info": ([P, P], ctypes.c_int),
         "gbs_last_error": ([P], ctypes.c_char_p),
         "gbs_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -268,6 +269,7 @@ class Simulator:
         self._destroy = lib.gbs_destroy  # still reachable while the interpreter shuts down
         self._keep = ()
         self._coils = ()
+        self._ws = None  # workspace tensor (uint8), grown on demand
         self.K = 0
         self.n_samples = 0
         self.n_coils = 1
@@ -339,18 +341,41 @@ class Simulator:
 
     info = gbs_get_info
 
+    def gbs_workspace_size(self, mode=GBS_GROUPED):
+        """Bytes of device workspace gbs_simulate needs in `mode`."""
+        n = ctypes.c_size_t()
+        self._check(lib.gbs_workspace_size(self._h, mode, ctypes.byref(n)))
+        return int(n.value)
+
+    workspace_size = gbs_workspace_size
+
+    def workspace(self, mode=GBS_GROUPED):
+        """A uint8 device tensor of at least the workspace size of `mode`,
+        kept by this object and reused (torch's allocator owns the memory)."""
+        n = self.gbs_workspace_size(mode)
+        if self._ws is None or self._ws.numel() < n:
+            self._ws = None
+            self._ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def release_workspace(self):
+        self._ws = None
+
     def gbs_simulate(self, mode=GBS_GROUPED, m_init=None, m_out=None, sig_out=None, flags=0,
-                     stats=False):
+                     stats=False, workspace=None):
         """Returns (M (3, K) float32 device tensor, signal complex128 device tensor[, stats]).
-        The signal is (N,) for one coil and (P, N) after set_coils with P rows."""
+        The signal is (N,) for one coil and (P, N) after set_coils with P rows.
+        workspace: a uint8 device tensor of at least gbs_workspace_size(mode)
+        bytes; None uses (and grows) the one this object keeps."""
+        ws = self.workspace(mode) if workspace is None else workspace
         if m_out is None:
             m_out = torch.empty(3, self.K, device=self.device, dtype=torch.float32)
         if sig_out is None:
             sig_out = torch.empty(max(self.n_coils * self.n_samples, 1), 2, device=self.device, dtype=torch.float64)
         mi = None if m_init is None else m_init.to(self.device, torch.float32).contiguous()
         st = gbs_stats() if stats else None
-        self._check(lib.gbs_simulate(self._h, mode, flags, _ptr(mi), _ptr(m_out), _ptr(sig_out),
-                                     ctypes.byref(st) if st is not None else None))
+        self._check(lib.gbs_simulate(self._h, mode, flags, _ptr(ws), ws.numel() * ws.element_size(), _ptr(mi),
+                                     _ptr(m_out), _ptr(sig_out), ctypes.byref(st) if st is not None else None))
         sig = torch.view_as_complex(sig_out)[: self.n_coils * self.n_samples]
         if self.n_coils > 1:
             sig = sig.view(self.n_coils, self.n_samples)

@@ -1,11 +1,15 @@
 // C ABI of the grouped-isochromat Bloch simulator (include/gbloch.h).
 //
-// The context owns: a device copy of the sequence waveform, and after
+// The context owns: a device copy of the sequence waveform, after
 // gbs_build_groups a group-sorted copy of the phantom (sorted by the x-group
-// key, so every x-group is one contiguous run), per-axis group ids and group
-// tables, and the magnetization state in that order.  Per simulate call it
-// owns the combined-transition tables, the map tables, the group sums and the
-// per-sample tables.  The caller owns the phantom arrays and the outputs.
+// key, so every x-group is one contiguous run) with per-axis group ids and
+// group tables, and the small device arrays of each mode's schedule (job
+// descriptors, per-sample tables), built by the setters.  Everything a
+// simulation writes besides its outputs (the magnetization state in layout
+// order, combined-transition and map tables, group sums, partial sums, the
+// FP64 state and the transition cache of the conventional method) lives in
+// the caller's workspace; gbs_simulate allocates nothing.  The caller owns
+// the phantom arrays, the workspace and the outputs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -55,12 +59,56 @@ struct DevBuf {
     }
 };
 
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Regions of a caller's workspace, carved in order.  The first 256 bytes are
+// never handed out, so a zero workspace offset stored in a job descriptor
+// means "no table".
+struct WsCarve {
+    size_t off = 256;
+    size_t take(size_t bytes) {
+        const size_t o = off;
+        off = align256(off + (bytes ? bytes : 1));
+        return o;
+    }
+};
+
+// A workspace-relative address: job descriptors are assembled with workspace
+// offsets in their table and sum pointers, and the offsets are turned into
+// device addresses once the workspace is known (relocate_jobs).
+template <class T>
+T *ws_rel(size_t off) {
+    return reinterpret_cast<T *>(static_cast<uintptr_t>(off));
+}
+
+// Record, for n consecutive structs of type T at byte offset arr in img, the
+// byte offsets of the given pointer fields that hold a workspace offset.
+template <class T>
+void add_relocs(std::vector<size_t> &slots, const std::vector<char> &img, size_t arr, size_t n,
+                std::initializer_list<size_t> fields) {
+    for (size_t i = 0; i < n; ++i)
+        for (size_t f : fields) {
+            const size_t at = arr + i * sizeof(T) + f;
+            uintptr_t v = 0;
+            std::memcpy(&v, img.data() + at, sizeof(v));
+            if (v) slots.push_back(at);
+        }
+}
+
 // Everything about a grouped simulation that depends only on the sequence and
 // the groups: the pass schedule, the arena layout, the per-sample tables and
 // the job arrays (uploaded once).  Rebuilt after set_sequence/build_groups.
 struct GroupedPlan {
     bool valid = false;
     Plan plan;
+    // workspace layout: state in layout order (mx, my, mz planes of Kpad
+    // floats, then the final (mx, my, mz, 0) rows), table arena, group sums,
+    // partial sums of stepped blocks, surrogate buffers
+    size_t w_state = 0, w_tabs = 0, w_gsum = 0, w_partial = 0, w_surr = 0, ws_bytes = 0;
+    // job image slots that hold workspace offsets, and the workspace the
+    // device copy of the jobs was relocated for (null: not uploaded)
+    std::vector<size_t> relocs;
+    const void *uploaded_ws = nullptr;
     bool zbuilt = false;
     std::vector<size_t> rf_off, gsum_off;
     // no-grads transitions composed per tissue group: (composed rows, x-group rows)
@@ -82,12 +130,14 @@ struct GroupedPlan {
     std::vector<Seg> segs;
     std::vector<std::pair<int, int>> exec;  // (0, segment) or (1, index into plan.ops)
     int64_t n_ops = 0;
-    // learned surrogate for one distinct RF transition (surr_rf >= 0)
-    bool surr_on = false;
+    // learned surrogate for one distinct RF transition (surr_rf >= 0); the
+    // RF jobs at o_rf_surr skip its exact composition.  s_* are offsets in
+    // the workspace's surrogate region.
     int surr_rf = -1;
     int64_t surr_groups = 0;
     int surr_n_check = 0;
-    size_t s_tuples = 0, s_T32 = 0, s_idx = 0, s_exact = 0, s_res = 0, s_fb = 0;
+    size_t o_rf_surr = 0;
+    size_t s_tuples = 0, s_T32 = 0, s_exact = 0, s_res = 0, s_fb = 0;
 };
 
 }  // namespace
@@ -111,8 +161,7 @@ struct gbs_ctx {
     int64_t ng[3] = {-1, -1, -1};
     int64_t Kint = 0;  // isochromats in the padded group-sorted layout (multiple of 8)
     int64_t Kpad = 0;
-    DevBuf perm, inv, xi, yi, zi, t1i, t2i, dfi, m0i, gid[3], gtab[3], gcount[3], ms[3];
-    DevBuf m_final;  // (mx, my, mz, 0) per layout slot, written by the last sweep of a run
+    DevBuf perm, inv, xi, yi, zi, t1i, t2i, dfi, m0i, gid[3], gtab[3], gcount[3];
     // no-grads groups (GBS_AX_N): (0, T1, T2, df) per group, and the group of each x-group
     int64_t n_tissue = -1;
     DevBuf ttab, tmap;
@@ -126,10 +175,12 @@ struct gbs_ctx {
     const float *coil_re = nullptr, *coil_im = nullptr;
     DevBuf coil_l;
     bool coil_l_valid = false;
-    // per-simulate buffers
-    DevBuf tabs, gsum, partial, jobs, samp, flag, state64;
-    std::vector<char> host_jobs;  // kept alive until the next call
+    // grouped schedule on the device: job descriptors (relocated to the
+    // workspace of the call) and per-sample tables; validation flag
+    DevBuf jobs, samp, flag;
+    std::vector<char> host_jobs, patched_jobs;
     std::vector<double2> host_samp;
+    double2 *partial = nullptr;  // per-workgroup sample sums of the current call (workspace)
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     // second stream of the context (default priority): the copy of the final
     // state into the caller's order runs on it beside the ADC evaluation
@@ -142,7 +193,7 @@ struct gbs_ctx {
     float surr_tol = 1e-3f;
     int32_t surr_check = 32;
     uint64_t surr_seed = 0;
-    DevBuf surr;
+    DevBuf surr_idx;  // seeded spot-check groups
     // gradient of the signal (adjoint): flattened ops, checkpoints, partials
     DevBuf adj_ops, adj_samp, adj_ckpt, adj_sub, adj_sig, adj_grf, adj_gt;
     AdjArgs adj{};
@@ -151,12 +202,12 @@ struct gbs_ctx {
     Plan pplan;  // plain schedule
     // conventional method with per-isochromat transition caching (GBS_CACHED):
     // schedule, per-sample tables of its direct ADC operations (row offset per
-    // operation), the cache itself (3 float4 rows of K per entry) and, with
-    // GBS_PROFILE, the kind of each timed launch
+    // operation) and, with GBS_PROFILE, the kind of each timed launch.  The
+    // cache itself (3 float4 rows of K per entry) is in the workspace.
     bool cplan_valid = false;
     Plan cplan;
     std::vector<int64_t> csamp_off;
-    DevBuf csamp, cache;
+    DevBuf csamp;
     std::vector<int> cprof_kind;
 };
 
@@ -164,6 +215,10 @@ static int fail(gbs_ctx *c, int code, const std::string &msg) {
     if (c) c->err = msg;
     return code;
 }
+
+static int refresh_plans(gbs_ctx *ctx);
+static int build_coil_layout(gbs_ctx *ctx);
+static int build_grouped_plan(gbs_ctx *ctx);
 
 #define HIPCHK(expr)                                                                           \
     do {                                                                                       \
@@ -188,6 +243,7 @@ static const char *status_text(int s) {
         case GBS_E_STATE: return "invalid call order or stale state";
         case GBS_E_HIP: return "HIP runtime error";
         case GBS_E_NOMEM: return "out of memory";
+        case GBS_E_WORKSPACE: return "workspace missing, too small or misaligned";
         default: return "unknown status";
     }
 }
@@ -230,17 +286,15 @@ int gbs_destroy(gbs_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->side) (void)hipStreamSynchronize(ctx->side);  // a failed call may have left work there
     DevBuf *bufs[] = {&ctx->d_wave, &ctx->d_adc, &ctx->perm, &ctx->inv, &ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i,
-                      &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->tabs, &ctx->gsum, &ctx->partial, &ctx->jobs,
-                      &ctx->samp, &ctx->flag, &ctx->surr, &ctx->adj_ops, &ctx->adj_samp, &ctx->adj_ckpt, &ctx->adj_sub,
-                      &ctx->adj_sig, &ctx->adj_grf, &ctx->adj_gt, &ctx->state64, &ctx->m_final,
-                      &ctx->csamp, &ctx->cache, &ctx->ttab, &ctx->tmap, &ctx->coil_l, &ctx->run_of4,
+                      &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->jobs, &ctx->samp, &ctx->flag, &ctx->surr_idx,
+                      &ctx->adj_ops, &ctx->adj_samp, &ctx->adj_ckpt, &ctx->adj_sub, &ctx->adj_sig, &ctx->adj_grf,
+                      &ctx->adj_gt, &ctx->csamp, &ctx->ttab, &ctx->tmap, &ctx->coil_l, &ctx->run_of4,
                       &ctx->rtab, &ctx->rz};
     for (DevBuf *b : bufs) b->release();
     for (int a = 0; a < 3; ++a) {
         ctx->gid[a].release();
         ctx->gtab[a].release();
         ctx->gcount[a].release();
-        ctx->ms[a].release();
     }
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
@@ -277,7 +331,7 @@ int gbs_set_phantom(gbs_ctx *ctx, int64_t K, const float *x, const float *y, con
     ctx->K = K;
     ctx->ph = ph;
     ctx->has_ph = true;
-    return GBS_OK;
+    return refresh_plans(ctx);  // one coil again: stepped launches take 256 samples
 }
 
 int gbs_set_coils(gbs_ctx *ctx, int32_t n_coils, const float *sens_re, const float *sens_im) {
@@ -303,10 +357,7 @@ int gbs_set_coils(gbs_ctx *ctx, int32_t n_coils, const float *sens_re, const flo
     ctx->coil_re = sens_re;
     ctx->coil_im = sens_im;
     ctx->coil_l_valid = false;
-    ctx->gp.valid = false;  // stepped launches are cut to 256 / n_coils samples
-    ctx->pplan_valid = false;
-    ctx->cplan_valid = false;
-    return GBS_OK;
+    return refresh_plans(ctx);  // stepped launches are cut to 256 / n_coils samples
 }
 
 int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, const float *rf_re,
@@ -342,7 +393,7 @@ int gbs_set_sequence(gbs_ctx *ctx, const gbs_block *blocks, int64_t n_blocks, co
     if (total_samples)
         HIPCHK(hipMemcpy(ctx->d_adc.p, adc_idx, sizeof(int32_t) * (size_t)total_samples, hipMemcpyHostToDevice));
     ctx->has_seq = true;
-    return GBS_OK;
+    return refresh_plans(ctx);
 }
 
 int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
@@ -495,15 +546,15 @@ int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
         ctx->rtab.release();
         ctx->rz.release();
     }
-    for (int a = 0; a < 3; ++a) ALLOC(ctx->ms[a], 4 * Kpad);
-    ALLOC(ctx->m_final, 16 * Kpad);
     HIPCHK(hipStreamSynchronize(ctx->stream));
     cleanup();
     ctx->axes = axes;
     ctx->Kint = kint;
     ctx->Kpad = Kpad;
     ctx->groups_valid = true;
-    return GBS_OK;
+    if (!ctx->has_seq) return GBS_OK;
+    if (int rc = build_coil_layout(ctx)) return rc;
+    return build_grouped_plan(ctx);
 }
 
 int gbs_get_info(gbs_ctx *ctx, gbs_info *info) {
@@ -603,7 +654,7 @@ PlainArgs step_args(gbs_ctx *ctx, const StepOp &op, const PhantomPtrs &ph, int64
         a.step_base = 0;
         a.n_samples = 0;
     }
-    a.partial = ctx->partial.as<double2>();
+    a.partial = ctx->partial;
     return a;
 }
 
@@ -625,34 +676,46 @@ static int launch_steps(gbs_ctx *ctx, const PlainArgs &a, bool b1, bool fp32, in
     else
         HIPCHK(launch_plain(a, b1, fp32, grid, ctx->stream));
     for (int32_t p = 0; p < P && a.n_samples > 0; ++p)
-        HIPCHK(launch_plain_finalize(ctx->partial.as<double2>() + (size_t)p * grid * a.n_samples, grid, a.n_samples,
+        HIPCHK(launch_plain_finalize(ctx->partial + (size_t)p * grid * a.n_samples, grid, a.n_samples,
                                      sig_out + 2 * ((int64_t)p * ctx->seq.total_samples + first_sample), ctx->stream));
     return GBS_OK;
 }
 
-static int run_plain(gbs_ctx *ctx, const float *m_init, float *m_out, double *sig_out, bool fp32,
+// Plain schedule (host only).
+static void build_plain_plan(gbs_ctx *ctx) {
+    ctx->pplan = plan_plain(ctx->seq, step_samples(ctx));
+    if (ctx->pplan.ops.empty()) {  // still write (0, 0, M0) or the initial state out
+        Op op;
+        op.kind = 1;
+        op.step = StepOp{};
+        ctx->pplan.ops.push_back(op);
+    }
+    ctx->pplan_valid = true;
+}
+
+// Workspace of GBS_PLAIN: per-workgroup sample sums, and the FP64 state
+// between launches when there is more than one.
+static size_t plain_ws(const gbs_ctx *ctx, size_t *o_partial, size_t *o_state) {
+    WsCarve w;
+    *o_partial = w.take(sizeof(double2) * (size_t)plain_grid(ctx->K) * kMaxSamplesPerLaunch);
+    *o_state = ctx->pplan.ops.size() > 1 ? w.take(sizeof(double) * 3 * (size_t)ctx->K) : 0;
+    return w.off;
+}
+
+static int run_plain(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out, double *sig_out, bool fp32,
                      gbs_stats *st) {
     const int64_t K = ctx->K;
-    if (!ctx->pplan_valid) {
-        ctx->pplan = plan_plain(ctx->seq, step_samples(ctx));
-        if (ctx->pplan.ops.empty()) {  // still write (0, 0, M0) or the initial state out
-            Op op;
-            op.kind = 1;
-            op.step = StepOp{};
-            ctx->pplan.ops.push_back(op);
-        }
-        ctx->pplan_valid = true;
-    }
     const Plan &plan = ctx->pplan;
     const int grid = plain_grid(K);
-    ALLOC(ctx->partial, sizeof(double2) * (size_t)grid * kMaxSamplesPerLaunch);
+    size_t o_partial = 0, o_state = 0;
+    plain_ws(ctx, &o_partial, &o_state);
+    ctx->partial = (double2 *)(ws + o_partial);
     float *ox = m_out, *oy = m_out + K, *oz = m_out + 2 * K;
     // the FP64 stepper keeps its state in FP64 between launches and rounds
     // to the FP32 output once, in the last launch
     double *sx = nullptr, *sy = nullptr, *sz = nullptr;
     if (!fp32 && plan.ops.size() > 1) {
-        ALLOC(ctx->state64, sizeof(double) * 3 * (size_t)K);
-        sx = ctx->state64.as<double>();
+        sx = (double *)(ws + o_state);
         sy = sx + K;
         sz = sx + 2 * K;
     }
@@ -687,12 +750,6 @@ static int run_plain(gbs_ctx *ctx, const float *m_init, float *m_out, double *si
     return GBS_OK;
 }
 
-namespace {
-
-size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-}  // namespace
-
 // Build the cached grouped plan: schedule, arena layout, sample tables and
 // job arrays (device).  Host work only once per (sequence, groups).
 // Does distinct RF transition r have exactly the surrogate's pulse?
@@ -721,15 +778,14 @@ static double sweep_bytes_per_iso(int need, bool write_m, bool fresh, bool final
     return b;
 }
 
-static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
+static int build_grouped_plan(gbs_ctx *ctx) {
     GroupedPlan &g = ctx->gp;
     const HostSeq &s = ctx->seq;
     g = GroupedPlan{};
     g.plan = plan_grouped(s, ctx->cls, ctx->axes, step_samples(ctx));
     const Plan &plan = g.plan;
     g.zbuilt = (ctx->axes & GBS_AX_Z) != 0;
-    g.surr_on = want_surr;
-    if (want_surr && ctx->mlp && ctx->mlp->device == ctx->device) {
+    if (ctx->mlp && ctx->mlp->device == ctx->device) {
         for (size_t i = 0; i < plan.rf.size(); ++i)
             if (matches_pulse(ctx, plan.rf[i])) {
                 g.surr_rf = (int)i;
@@ -849,12 +905,16 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
         g.max_adc_samples = std::max(g.max_adc_samples, (int)s.blocks[j.block].n_samples);
     }
     g.gsum_count = goff;
-    ALLOC(ctx->tabs, tab_bytes);
-    ALLOC(ctx->gsum, sizeof(double2) * goff);
-    ALLOC(ctx->samp, sizeof(double2) * soff);
-    if (plan.n_fallback) ALLOC(ctx->partial, sizeof(double2) * (size_t)plain_grid(ctx->Kint) * kMaxSamplesPerLaunch);
-    char *tb = ctx->tabs.as<char>();
-    for (auto &t : tjobs) t.out = tb + (size_t)t.out;
+    WsCarve w;
+    g.w_state = w.take(28 * (size_t)ctx->Kpad);  // mx, my, mz planes (4 B each), final rows (16 B)
+    g.w_tabs = w.take(tab_bytes);
+    g.w_gsum = w.take(sizeof(double2) * goff);
+    if (plan.n_fallback) g.w_partial = w.take(sizeof(double2) * (size_t)plain_grid(ctx->Kint) * kMaxSamplesPerLaunch);
+    ALLOC(ctx->samp, sizeof(double2) * std::max<size_t>(soff, 1));
+    // workspace-relative addresses in the table arena and the group sums
+    auto tb = [&](size_t o) { return ws_rel<char>(g.w_tabs + o); };
+    auto gsum_at = [&](size_t i) { return ws_rel<double2>(g.w_gsum + sizeof(double2) * i); };
+    for (auto &t : tjobs) t.out = tb((size_t)t.out);
 
     // per-sample tables (tau_n, gamma_bar m_n) of the grouped with-ADC blocks (Eq. 10)
     std::vector<double2> &hs = ctx->host_samp;
@@ -879,18 +939,19 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
         // the surrogate's transition is not composed here (n_groups = 0 skips it)
         if (r.axis == kPairAxis) {  // composed by its own kernel (k_compose_pair)
             rj[i] = RfJobDev{0, (int32_t)r.n_steps, 0, ctx->d_wave.as<StepW>() + r.step_offset, nullptr,
-                             (double *)(tb + comp_off[i])};
+                             (double *)tb(comp_off[i])};
             continue;
         }
         if (r.axis == kTissueAxis) {  // no gradients: the coordinate column of the table is unused
             rj[i] = RfJobDev{0, (int32_t)r.n_steps, ctx->n_tissue, ctx->d_wave.as<StepW>() + r.step_offset,
-                             ctx->ttab.as<float4>(), (double *)(tb + comp_off[i])};
+                             ctx->ttab.as<float4>(), (double *)tb(comp_off[i])};
             continue;
         }
-        const int64_t ng = (int)i == g.surr_rf ? 0 : ctx->ng[r.axis];
-        rj[i] = RfJobDev{r.axis, (int32_t)r.n_steps, ng, ctx->d_wave.as<StepW>() + r.step_offset,
-                         ctx->gtab[r.axis].as<float4>(), (double *)(tb + g.rf_off[i])};
+        rj[i] = RfJobDev{r.axis, (int32_t)r.n_steps, ctx->ng[r.axis], ctx->d_wave.as<StepW>() + r.step_offset,
+                         ctx->gtab[r.axis].as<float4>(), (double *)tb(g.rf_off[i])};
     }
+    std::vector<RfJobDev> rj_surr(rj);  // GBS_SURROGATE: the network's transition is not composed
+    if (g.surr_rf >= 0) rj_surr[g.surr_rf].n_groups = 0;
     if (g.surr_rf >= 0) {
         // tuples, network output, spot-check indices (seeded, distinct) and exact values
         const int64_t G = ctx->ng[2];
@@ -904,7 +965,6 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
         };
         g.s_tuples = take(sizeof(float) * 5 * (size_t)G);
         g.s_T32 = take(sizeof(float) * 12 * (size_t)G);
-        g.s_idx = take(sizeof(int32_t) * (size_t)g.surr_n_check);
         g.s_exact = take(sizeof(double) * 12 * (size_t)g.surr_n_check);
         g.s_res = take(sizeof(float));
         g.s_fb = take(sizeof(int32_t));
@@ -916,15 +976,16 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
             const int64_t j = k + (int64_t)((rs >> 33) % (uint64_t)(G - k));
             std::swap(all[k], all[j]);
         }
-        ALLOC(ctx->surr, so);
-        HIPCHK(hipMemcpy((char *)ctx->surr.p + g.s_idx, all.data(), sizeof(int32_t) * g.surr_n_check,
-                         hipMemcpyHostToDevice));
+        g.w_surr = w.take(so);
+        ALLOC(ctx->surr_idx, sizeof(int32_t) * (size_t)g.surr_n_check);
+        HIPCHK(hipMemcpy(ctx->surr_idx.p, all.data(), sizeof(int32_t) * g.surr_n_check, hipMemcpyHostToDevice));
     }
+    g.ws_bytes = w.off;
     std::vector<FoldJob> fj(folds.size());
     for (size_t i = 0; i < folds.size(); ++i) {
         const FoldPlan &f = folds[i];
-        fj[i] = FoldJob{f.axis, f.has_pre, rows_groups(f.axis), (const double *)(tb + g.rf_off[f.rf_id]),
-                        rows_table(f.axis), f.tau, f.cyc, (float4 *)(tb + f.out_off)};
+        fj[i] = FoldJob{f.axis, f.has_pre, rows_groups(f.axis), (const double *)tb(g.rf_off[f.rf_id]),
+                        rows_table(f.axis), f.tau, f.cyc, (float4 *)tb(f.out_off)};
         g.max_fold_groups = std::max(g.max_fold_groups, rows_groups(f.axis));
     }
     // readouts whose sample times and moments are arithmetic in the sample index take the
@@ -951,7 +1012,7 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
         }
         // coil p: its own block of group sums, its own row of the signal
         for (int32_t p = 0; p < ctx->n_coils; ++p) {
-            const double2 *gs = ctx->gsum.as<double2>() + g.gsum_off[i] + (size_t)p * (size_t)ctx->ng[j.axis];
+            const double2 *gs = gsum_at(g.gsum_off[i] + (size_t)p * (size_t)ctx->ng[j.axis]);
             const int64_t so = (int64_t)p * s.total_samples + b.sample_offset;
             if (lin) {
                 lj.push_back(AdcLinJob{ns, (int32_t)ctx->ng[j.axis], gs, ctx->gtab[j.axis].as<float4>(), h[0].x,
@@ -967,8 +1028,8 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
     }
 
     // ---- sweep ops: grouped ops in schedule order; consecutive ones fuse
-    auto ptr4 = [&](size_t o) { return o == kNone ? (const float4 *)nullptr : (const float4 *)(tb + o); };
-    auto ptr2 = [&](size_t o) { return o == kNone ? (const float2 *)nullptr : (const float2 *)(tb + o); };
+    auto ptr4 = [&](size_t o) { return o == kNone ? (const float4 *)nullptr : (const float4 *)tb(o); };
+    auto ptr2 = [&](size_t o) { return o == kNone ? (const float2 *)nullptr : (const float2 *)tb(o); };
     std::vector<SweepOp> sops;
     std::vector<int> op_need;       // per sweep op: arrays it needs
     std::vector<double> op_flops;   // per sweep op: algorithmic flops per isochromat
@@ -1006,7 +1067,7 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
             o.emit_ztab = ptr2(t.emit_z);
             o.emit_cy = kGammaBar * p.emit.m[1];
             o.emit_cz = g.zbuilt ? 0.0 : kGammaBar * p.emit.m[2];
-            o.gsum = ctx->gsum.as<double2>() + g.gsum_off[p.adc_job];
+            o.gsum = gsum_at(g.gsum_off[p.adc_job]);
             o.gsum_stride = (int32_t)ctx->ng[p.emit_axis];
             fl += 8.0 + 6.0 * ((o.emit_ztab != nullptr) + (o.emit_cy != 0.0) + (o.emit_cz != 0.0));
         }
@@ -1167,7 +1228,8 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
     g.n_adc = (int)aj.size();
     g.n_adclin = (int)lj.size();
     g.o_rf = 0;
-    g.o_fold = align256(sizeof(RfJobDev) * rj.size());
+    g.o_rf_surr = align256(sizeof(RfJobDev) * rj.size());
+    g.o_fold = g.o_rf_surr + align256(sizeof(RfJobDev) * rj.size());
     g.o_tab = g.o_fold + align256(sizeof(FoldJob) * fj.size());
     g.o_adc = g.o_tab + align256(sizeof(TabJob) * tjobs.size());
     g.o_adclin = g.o_adc + align256(sizeof(AdcJobDev) * aj.size());
@@ -1178,42 +1240,96 @@ static int build_grouped_plan(gbs_ctx *ctx, bool want_surr) {
         if (n) std::memcpy(ctx->host_jobs.data() + o, src, n);
     };
     put(g.o_rf, rj.data(), sizeof(RfJobDev) * rj.size());
+    put(g.o_rf_surr, rj_surr.data(), sizeof(RfJobDev) * rj_surr.size());
     put(g.o_fold, fj.data(), sizeof(FoldJob) * fj.size());
     put(g.o_tab, tjobs.data(), sizeof(TabJob) * tjobs.size());
     put(g.o_adc, aj.data(), sizeof(AdcJobDev) * aj.size());
     put(g.o_adclin, lj.data(), sizeof(AdcLinJob) * lj.size());
     put(g.o_sweep, sops.data(), sizeof(SweepOp) * sops.size());
+    // the pointer fields that hold workspace offsets
+    const std::vector<char> &img = ctx->host_jobs;
+    add_relocs<RfJobDev>(g.relocs, img, g.o_rf, rj.size(), {offsetof(RfJobDev, out)});
+    add_relocs<RfJobDev>(g.relocs, img, g.o_rf_surr, rj_surr.size(), {offsetof(RfJobDev, out)});
+    add_relocs<FoldJob>(g.relocs, img, g.o_fold, fj.size(), {offsetof(FoldJob, t64), offsetof(FoldJob, out)});
+    add_relocs<TabJob>(g.relocs, img, g.o_tab, tjobs.size(), {offsetof(TabJob, out)});
+    add_relocs<AdcJobDev>(g.relocs, img, g.o_adc, aj.size(), {offsetof(AdcJobDev, gsum)});
+    add_relocs<AdcLinJob>(g.relocs, img, g.o_adclin, lj.size(), {offsetof(AdcLinJob, gsum)});
+    add_relocs<SweepOp>(g.relocs, img, g.o_sweep, sops.size(),
+                        {offsetof(SweepOp, pre_xtab), offsetof(SweepOp, pre_ztab), offsetof(SweepOp, ttab),
+                         offsetof(SweepOp, emit_xtab), offsetof(SweepOp, emit_ztab), offsetof(SweepOp, gsum)});
     ALLOC(ctx->jobs, jbytes);
-    HIPCHK(hipMemcpy(ctx->jobs.p, ctx->host_jobs.data(), jbytes, hipMemcpyHostToDevice));
+    g.uploaded_ws = nullptr;
     if (soff) HIPCHK(hipMemcpy(ctx->samp.p, hs.data(), sizeof(double2) * soff, hipMemcpyHostToDevice));
+    // GBS_PROFILE events: a (start, stop) pair per sweep
+    while (ctx->pev.size() < 2 * (g.segs.size() + 1)) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        ctx->pev.push_back(e);
+    }
     g.valid = true;
     return GBS_OK;
 }
 
-static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *sig_out, bool profile,
+// Device copy of the grouped job descriptors with their workspace offsets
+// turned into addresses in `ws`; done again only when the workspace moves.
+static int relocate_jobs(gbs_ctx *ctx, char *ws) {
+    GroupedPlan &g = ctx->gp;
+    if (g.uploaded_ws == ws) return GBS_OK;
+    std::vector<char> &img = ctx->patched_jobs;
+    img = ctx->host_jobs;
+    for (size_t at : g.relocs) {
+        uintptr_t v = 0;
+        std::memcpy(&v, img.data() + at, sizeof(v));
+        v += reinterpret_cast<uintptr_t>(ws);
+        std::memcpy(img.data() + at, &v, sizeof(v));
+    }
+    HIPCHK(hipMemcpyAsync(ctx->jobs.p, img.data(), img.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    g.uploaded_ws = ws;
+    return GBS_OK;
+}
+
+// Group-sorted copy of the coil sensitivities (padding slots: 0).
+static int build_coil_layout(gbs_ctx *ctx) {
+    ctx->coil_l_valid = false;
+    if (!ctx->coil_re || !ctx->groups_valid) return GBS_OK;
+    const int64_t Kp = ctx->Kpad, K = ctx->K;
+    ALLOC(ctx->coil_l, sizeof(float) * 2 * (size_t)ctx->n_coils * (size_t)Kp);
+    float *cl = ctx->coil_l.as<float>();
+    for (int32_t p = 0; p < ctx->n_coils; ++p) {
+        HIPCHK(launch_gather_padded(Kp, ctx->perm.as<int32_t>(), ctx->coil_re + (size_t)p * K, cl + (size_t)(2 * p) * Kp,
+                                    ctx->stream));
+        HIPCHK(launch_gather_padded(Kp, ctx->perm.as<int32_t>(), ctx->coil_im + (size_t)p * K,
+                                    cl + (size_t)(2 * p + 1) * Kp, ctx->stream));
+    }
+    ctx->coil_l_valid = true;
+    return GBS_OK;
+}
+
+static int run_grouped(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out, double *sig_out, bool profile,
                        bool use_surr, gbs_stats *st, int *n_timed) {
     const int64_t K = ctx->K;
     const HostSeq &s = ctx->seq;
-    if (!ctx->gp.valid || ctx->gp.surr_on != use_surr) {
-        int rc = build_grouped_plan(ctx, use_surr);
-        if (rc != GBS_OK) return rc;
-    }
+    if (!ctx->gp.valid) return fail(ctx, GBS_E_STATE, "no grouped schedule (a setter failed)");
+    if (int rc = relocate_jobs(ctx, ws)) return rc;
     const GroupedPlan &g = ctx->gp;
     const Plan &plan = g.plan;
     const bool zbuilt = g.zbuilt;
     const int grid = plain_grid(ctx->Kint);
-    char *tb = ctx->tabs.as<char>();
+    const bool surr = use_surr && g.surr_rf >= 0;
+    char *tb = ws + g.w_tabs;
     char *jb = ctx->jobs.as<char>();
+    ctx->partial = g.w_partial ? (double2 *)(ws + g.w_partial) : nullptr;
 
     // ---- prepare: combined transitions (Eq. 7) and map tables --------------
-    HIPCHK(launch_fill_f64((double *)ctx->gsum.p, 2 * (int64_t)g.gsum_count, ctx->stream));
-    if (g.surr_rf >= 0) {
+    HIPCHK(launch_fill_f64((double *)(ws + g.w_gsum), 2 * (int64_t)g.gsum_count, ctx->stream));
+    if (surr) {
         // network transitions for every z group, exact ones for the checked groups,
         // then exact for all groups only if the check failed (gated on the device)
-        char *sb = ctx->surr.as<char>();
+        char *sb = ws + g.w_surr;
         const gbs_mlp *m = ctx->mlp;
         float *tuples = (float *)(sb + g.s_tuples), *T32 = (float *)(sb + g.s_T32);
-        const int32_t *cidx = (const int32_t *)(sb + g.s_idx);
+        const int32_t *cidx = ctx->surr_idx.as<int32_t>();
         int32_t *fb = (int32_t *)(sb + g.s_fb);
         double *T64 = (double *)(tb + g.rf_off[g.surr_rf]);
         HIPCHK(launch_surr_tuples(ctx->gtab[2].as<float4>(), g.surr_groups, kGammaBar * m->g_ref, tuples,
@@ -1225,7 +1341,8 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
                                  (float *)(sb + g.s_res), fb, ctx->stream));
         HIPCHK(mlp_exact_async(m, tuples, nullptr, g.surr_groups, fb, T64, ctx->stream));
     }
-    HIPCHK(launch_compose((const RfJobDev *)(jb + g.o_rf), g.n_rf, g.max_rf_groups, s.dt, ctx->stream));
+    HIPCHK(launch_compose((const RfJobDev *)(jb + (surr ? g.o_rf_surr : g.o_rf)), g.n_rf, g.max_rf_groups, s.dt,
+                          ctx->stream));
     for (const auto &pj : g.pair_jobs) {
         const RfJob &r = plan.rf[pj.second];
         HIPCHK(launch_compose_pair(ctx->n_runs, ctx->rtab.as<float4>(), ctx->rz.as<float>(),
@@ -1241,7 +1358,8 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     if (st) HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
 
     // ---- sweeps of grouped ops (plain stepping between them) ----------------
-    float *mx = ctx->ms[0].as<float>(), *my = ctx->ms[1].as<float>(), *mz = ctx->ms[2].as<float>();
+    float *mx = (float *)(ws + g.w_state), *my = mx + ctx->Kpad, *mz = my + ctx->Kpad;
+    float4 *m_final = (float4 *)(mz + ctx->Kpad);
     const int64_t Kint = ctx->Kint;
     // the default initial state (0, 0, M0) is made by the first sweep itself
     const bool fresh = !m_init && !g.exec.empty() && g.exec.front().first == 0;
@@ -1263,29 +1381,10 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     const PhantomPtrs iph{ctx->xi.as<float>(), ctx->yi.as<float>(), ctx->zi.as<float>(), ctx->t1i.as<float>(),
                           ctx->t2i.as<float>(), ctx->dfi.as<float>(), ctx->m0i.as<float>()};
     if (ctx->coil_re) {  // sensitivities in layout order (padding slots: 0)
-        const int64_t Kp = ctx->Kpad;
-        if (!ctx->coil_l_valid) {
-            ALLOC(ctx->coil_l, sizeof(float) * 2 * (size_t)ctx->n_coils * (size_t)Kp);
-            float *cl = ctx->coil_l.as<float>();
-            for (int32_t p = 0; p < ctx->n_coils; ++p) {
-                HIPCHK(launch_gather_padded(Kp, ctx->perm.as<int32_t>(), ctx->coil_re + (size_t)p * K,
-                                            cl + (size_t)(2 * p) * Kp, ctx->stream));
-                HIPCHK(launch_gather_padded(Kp, ctx->perm.as<int32_t>(), ctx->coil_im + (size_t)p * K,
-                                            cl + (size_t)(2 * p + 1) * Kp, ctx->stream));
-            }
-            ctx->coil_l_valid = true;
-        }
+        if (!ctx->coil_l_valid) return fail(ctx, GBS_E_STATE, "no group-sorted coil sensitivities (a setter failed)");
         base.coil = ctx->coil_l.as<float4>();
         base.n_coils = ctx->n_coils;
-        base.coil_plane = Kp / 4;
-    }
-    if (profile) {
-        const size_t need = 2 * (g.segs.size() + 1);
-        while (ctx->pev.size() < need) {
-            hipEvent_t e;
-            HIPCHK(hipEventCreate(&e));
-            ctx->pev.push_back(e);
-        }
+        base.coil_plane = ctx->Kpad / 4;
     }
     int timed = 0;
     double bytes = 0.0, flops = 0.0;
@@ -1301,7 +1400,7 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
             a.n_ops = sg.op_end - sg.op_begin;
             a.need = sg.need;
             a.write_m = sg.write_m ? 1 : 0;
-            a.m_final = (final4 && e + 1 == g.exec.size()) ? ctx->m_final.as<float4>() : nullptr;
+            a.m_final = (final4 && e + 1 == g.exec.size()) ? m_final : nullptr;
             a.fresh = (fresh && e == 0) ? 1 : 0;
             if (a.m_final || a.fresh) {  // the whole state is written, so all of it is held
                 a.need |= kNeedMz;
@@ -1330,7 +1429,7 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
     HIPCHK(hipEventRecord(ctx->fork, ctx->stream));
     HIPCHK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
     if (final4)
-        HIPCHK(launch_gather_state4(K, ctx->inv.as<int32_t>(), ctx->m_final.as<float4>(), m_out, m_out + K,
+        HIPCHK(launch_gather_state4(K, ctx->inv.as<int32_t>(), m_final, m_out, m_out + K,
                                     m_out + 2 * K, ctx->side));
     else
         HIPCHK(launch_gather_state(K, ctx->inv.as<int32_t>(), mx, my, mz, m_out, m_out + K, m_out + 2 * K,
@@ -1364,11 +1463,12 @@ static int run_grouped(gbs_ctx *ctx, const float *m_init, float *m_out, double *
 // The state lives in FP64 (state64) from the first operation that writes it;
 // until then operations read m_init or (0, 0, M0).  The last operation always
 // writes m_out.
-static int run_cached(gbs_ctx *ctx, const float *m_init, float *m_out, double *sig_out, bool profile,
-                      gbs_stats *st, int *n_timed) {
-    const int64_t K = ctx->K;
+// Cached schedule: host plan, per-sample tables of the direct ADC operations
+// on the device, GBS_PROFILE events.
+static int build_cached_plan(gbs_ctx *ctx) {
     const double dt = ctx->seq.dt;
-    if (!ctx->cplan_valid) {
+    ctx->cplan_valid = false;
+    {
         ctx->cplan = plan_cached(ctx->seq, ctx->cls, step_samples(ctx));
         const Plan &plan = ctx->cplan;
         // sample n of a direct ADC operation: c_n = gamma_bar (m_pre + m(s_n)),
@@ -1402,25 +1502,43 @@ static int run_cached(gbs_ctx *ctx, const float *m_init, float *m_out, double *s
         ALLOC(ctx->csamp, sizeof(double4) * std::max<size_t>(tab.size(), 1));
         if (!tab.empty())
             HIPCHK(hipMemcpy(ctx->csamp.p, tab.data(), sizeof(double4) * tab.size(), hipMemcpyHostToDevice));
-        ctx->cplan_valid = true;
     }
+    while (ctx->pev.size() < 2 * ctx->cplan.ops.size()) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        ctx->pev.push_back(e);
+    }
+    ctx->cplan_valid = true;
+    return GBS_OK;
+}
+
+// Workspace of GBS_CACHED: the FP64 state, the transition cache (3 float4
+// rows of K per distinct with-RF waveform) and per-workgroup sample sums.
+static size_t cached_ws(const gbs_ctx *ctx, size_t *o_state, size_t *o_cache, size_t *o_partial) {
+    const int64_t K = ctx->K;
+    const size_t n_entries = ctx->cplan.rf.size();
+    WsCarve w;
+    *o_state = w.take(sizeof(double) * 3 * (size_t)K);
+    *o_cache = n_entries ? w.take(sizeof(float4) * 3 * (size_t)K * n_entries) : 0;
+    const int pgrid = plain_grid(K), agrid = direct_adc_grid(K);
+    *o_partial = w.take(sizeof(double2) * (size_t)std::max(pgrid, agrid) * kMaxSamplesPerLaunch * (size_t)ctx->n_coils);
+    return w.off;
+}
+
+static int run_cached(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out, double *sig_out, bool profile,
+                      gbs_stats *st, int *n_timed) {
+    const int64_t K = ctx->K;
+    const double dt = ctx->seq.dt;
+    if (!ctx->cplan_valid) return fail(ctx, GBS_E_STATE, "no cached schedule (a setter failed)");
     const Plan &plan = ctx->cplan;
     const size_t n_entries = plan.rf.size();
-    ALLOC(ctx->state64, sizeof(double) * 3 * (size_t)K);
-    if (n_entries) ALLOC(ctx->cache, sizeof(float4) * 3 * (size_t)K * n_entries);
+    size_t o_state = 0, o_cache = 0, o_partial = 0;
+    cached_ws(ctx, &o_state, &o_cache, &o_partial);
     const int pgrid = plain_grid(K), agrid = direct_adc_grid(K);
-    ALLOC(ctx->partial,
-          sizeof(double2) * (size_t)std::max(pgrid, agrid) * kMaxSamplesPerLaunch * (size_t)ctx->n_coils);
-    if (profile) {
-        const size_t need = 2 * plan.ops.size();
-        while (ctx->pev.size() < need) {
-            hipEvent_t e;
-            HIPCHK(hipEventCreate(&e));
-            ctx->pev.push_back(e);
-        }
-    }
+    ctx->partial = (double2 *)(ws + o_partial);
+    float4 *cache = (float4 *)(ws + o_cache);
     ctx->cprof_kind.clear();
-    double *s64 = ctx->state64.as<double>();
+    double *s64 = (double *)(ws + o_state);
     const float *mi_x = m_init, *mi_y = m_init ? m_init + K : nullptr, *mi_z = m_init ? m_init + 2 * K : nullptr;
     bool from_init = true;
     int timed = 0;
@@ -1457,14 +1575,14 @@ static int run_cached(gbs_ctx *ctx, const float *m_init, float *m_out, double *s
             }
             a.samp = ctx->csamp.as<double4>() + ctx->csamp_off[oi];
             a.n_samples = c.sample_hi - c.sample_lo;
-            a.partial = ctx->partial.as<double2>();
+            a.partial = ctx->partial;
             a.coil_re = ctx->coil_re;
             a.coil_im = ctx->coil_im;
             a.n_coils = ctx->coil_re ? ctx->n_coils : 1;
             HIPCHK(launch_direct_adc(a, agrid, ctx->stream));
             for (int32_t p = 0; p < a.n_coils; ++p)  // partials of coil p: [grid][n_samples] block p
                 HIPCHK(launch_plain_finalize(
-                    ctx->partial.as<double2>() + (size_t)p * agrid * a.n_samples, agrid, a.n_samples,
+                    ctx->partial + (size_t)p * agrid * a.n_samples, agrid, a.n_samples,
                     sig_out + 2 * ((int64_t)p * ctx->seq.total_samples + b.sample_offset + c.sample_lo), ctx->stream));
         } else {  // 2: cached transition (composed at first use); 4: final map
             const CachedOp &c = op.cached;
@@ -1493,7 +1611,7 @@ static int run_cached(gbs_ctx *ctx, const float *m_init, float *m_out, double *s
             int mode = kCacheMap;
             if (op.kind == 2) {
                 const gbs_block &b = ctx->seq.blocks[c.block];
-                a.cache = ctx->cache.as<float4>() + 3 * (size_t)K * (size_t)c.entry;
+                a.cache = cache + 3 * (size_t)K * (size_t)c.entry;
                 mode = c.compose ? kCacheCompose : kCacheApply;
                 a.wave = ctx->d_wave.as<StepW>() + b.step_offset;
                 a.n_steps = (int32_t)b.n_steps;
@@ -1520,8 +1638,52 @@ static int run_cached(gbs_ctx *ctx, const float *m_init, float *m_out, double *s
     return GBS_OK;
 }
 
-extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float *m_init, float *m_out,
-                            double *sig_out, gbs_stats *stats) {
+// The schedules of every mode for the current phantom, sequence, groups,
+// coils and surrogate: built by the setters, so that gbs_simulate allocates
+// nothing.  Plain and cached schedules need a sequence; the grouped one also
+// valid groups.
+static int refresh_plans(gbs_ctx *ctx) {
+    ctx->pplan_valid = ctx->cplan_valid = false;
+    ctx->gp.valid = false;
+    if (!ctx->has_seq) return GBS_OK;
+    build_plain_plan(ctx);
+    if (int rc = build_cached_plan(ctx)) return rc;
+    if (!ctx->groups_valid) return GBS_OK;
+    if (int rc = build_coil_layout(ctx)) return rc;
+    return build_grouped_plan(ctx);
+}
+
+// Workspace bytes of `mode` for the current schedules (0 if the mode needs
+// none); -1 with the message set when the mode cannot run yet.
+static int workspace_bytes(gbs_ctx *ctx, int mode, size_t *bytes) {
+    if (!ctx->has_ph) return fail(ctx, GBS_E_STATE, "no phantom (gbs_set_phantom)");
+    if (!ctx->has_seq) return fail(ctx, GBS_E_STATE, "no sequence (gbs_set_sequence)");
+    if (mode != GBS_PLAIN && mode != GBS_GROUPED && mode != GBS_CACHED)
+        return fail(ctx, GBS_E_INVALID, "mode must be GBS_PLAIN, GBS_GROUPED or GBS_CACHED");
+    size_t a = 0, b = 0, c = 0;
+    if (mode == GBS_PLAIN) {
+        if (!ctx->pplan_valid) return fail(ctx, GBS_E_STATE, "no plain schedule (a setter failed)");
+        *bytes = plain_ws(ctx, &a, &b);
+    } else if (mode == GBS_CACHED) {
+        if (!ctx->cplan_valid) return fail(ctx, GBS_E_STATE, "no cached schedule (a setter failed)");
+        *bytes = cached_ws(ctx, &a, &b, &c);
+    } else {
+        if (!ctx->groups_valid) return fail(ctx, GBS_E_STATE, "GBS_GROUPED needs gbs_build_groups on the current phantom");
+        if (!ctx->gp.valid) return fail(ctx, GBS_E_STATE, "no grouped schedule (a setter failed)");
+        *bytes = ctx->gp.ws_bytes;
+    }
+    return GBS_OK;
+}
+
+extern "C" int gbs_workspace_size(gbs_ctx *ctx, int mode, size_t *bytes) {
+    if (!ctx) return GBS_E_INVALID;
+    if (!bytes) return fail(ctx, GBS_E_INVALID, "null bytes");
+    *bytes = 0;
+    return workspace_bytes(ctx, mode, bytes);
+}
+
+extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, void *workspace, size_t ws_bytes,
+                            const float *m_init, float *m_out, double *sig_out, gbs_stats *stats) {
     if (!ctx) return GBS_E_INVALID;
     if (!ctx->has_ph) return fail(ctx, GBS_E_STATE, "gbs_simulate before gbs_set_phantom");
     if (!ctx->has_seq) return fail(ctx, GBS_E_STATE, "gbs_simulate before gbs_set_sequence");
@@ -1535,6 +1697,15 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
     const bool use_surr = (flags & GBS_SURROGATE) != 0;
     if (use_surr && (mode != GBS_GROUPED || !ctx->mlp))
         return fail(ctx, GBS_E_INVALID, "GBS_SURROGATE needs GBS_GROUPED and gbs_set_surrogate");
+    size_t need = 0;
+    if (int rc = workspace_bytes(ctx, mode, &need)) return rc;
+    if (!workspace || ws_bytes < need)
+        return fail(ctx, GBS_E_WORKSPACE, "workspace of " + std::to_string(workspace ? ws_bytes : 0) +
+                                              " bytes; this mode needs " + std::to_string(need) +
+                                              " (gbs_workspace_size)");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255)
+        return fail(ctx, GBS_E_WORKSPACE, "workspace must be 256-byte aligned");
+    char *ws = static_cast<char *>(workspace);
     HIPCHK(hipSetDevice(ctx->device));
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
@@ -1544,9 +1715,9 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
         HIPCHK(launch_fill_f64(sig_out, 2 * (int64_t)ctx->n_coils * ctx->seq.total_samples, ctx->stream));
     const bool profile = (flags & GBS_PROFILE) != 0;
     int n_timed = 0;
-    int rc = mode == GBS_PLAIN    ? run_plain(ctx, m_init, m_out, sig_out, (flags & GBS_PLAIN_FP32) != 0, stats)
-             : mode == GBS_CACHED ? run_cached(ctx, m_init, m_out, sig_out, profile, stats, &n_timed)
-                                  : run_grouped(ctx, m_init, m_out, sig_out, profile, use_surr, stats, &n_timed);
+    int rc = mode == GBS_PLAIN ? run_plain(ctx, ws, m_init, m_out, sig_out, (flags & GBS_PLAIN_FP32) != 0, stats)
+             : mode == GBS_CACHED ? run_cached(ctx, ws, m_init, m_out, sig_out, profile, stats, &n_timed)
+                                  : run_grouped(ctx, ws, m_init, m_out, sig_out, profile, use_surr, stats, &n_timed);
     if (rc != GBS_OK) return rc;
     if (stats) HIPCHK(hipEventRecord(ctx->ev[4], ctx->stream));
     if (!(flags & GBS_ASYNC) || stats || profile) {
@@ -1583,11 +1754,13 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, const float 
             }
             stats->pass_kernel_ms = sum;
             const GroupedPlan &g = ctx->gp;
-            if (g.surr_rf >= 0) {
+            if (use_surr && g.surr_rf >= 0) {
                 float res = 0.f;
                 int32_t fb = 0;
-                HIPCHK(hipMemcpy(&res, ctx->surr.as<char>() + g.s_res, sizeof(float), hipMemcpyDeviceToHost));
-                HIPCHK(hipMemcpy(&fb, ctx->surr.as<char>() + g.s_fb, sizeof(int32_t), hipMemcpyDeviceToHost));
+                const char *sb = ws + g.w_surr;
+                HIPCHK(hipMemcpyAsync(&res, sb + g.s_res, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+                HIPCHK(hipMemcpyAsync(&fb, sb + g.s_fb, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+                HIPCHK(hipStreamSynchronize(ctx->stream));
                 stats->n_surrogate = 1;
                 stats->n_surrogate_fallback = fb ? 1 : 0;
                 stats->surrogate_residual = res;
@@ -1610,6 +1783,10 @@ extern "C" int gbs_set_surrogate(gbs_ctx *ctx, gbs_mlp *m, float tol, int32_t n_
     ctx->surr_check = n_check;
     ctx->surr_seed = seed;
     ctx->gp.valid = false;
+    if (ctx->has_seq && ctx->groups_valid) {
+        HIPCHK(hipSetDevice(ctx->device));
+        return build_grouped_plan(ctx);
+    }
     return GBS_OK;
 }
 

@@ -141,3 +141,55 @@ def test_adjoint_limits(gb):
     assert np.linalg.norm(s[:, 0] + 1j * s[:, 1] - s_o) <= 1e-4 * np.linalg.norm(s_o)
     assert np.linalg.norm(g[:, 0] + 1j * g[:, 1] - g_o) <= 2e-3 * np.linalg.norm(g_o)
     sim.close()
+
+
+def test_workspace_contract(gb):
+    """gbs_simulate takes its scratch from the caller: a workspace of
+    gbs_workspace_size bytes (256-byte aligned) works in every mode, and its
+    previous contents do not matter; a null, short or misaligned one is
+    refused with GBS_E_WORKSPACE before any work."""
+    import ctypes
+    import torch
+    ph, seq = small()
+    Mr, sr = oracle.simulate(ph, seq)
+    sim = gb.Simulator(0)
+    say("[gpu] workspace: size before a sequence")
+    sim.set_phantom(ph)
+    assert code_of(gb, lambda: sim.workspace_size(gb.GBS_PLAIN)) == gb.GBS_E_STATE
+    sim.set_sequence(seq)
+    assert code_of(gb, lambda: sim.workspace_size(gb.GBS_GROUPED)) == gb.GBS_E_STATE  # no groups yet
+    sim.build_groups()
+    m_out = torch.empty(3, ph.K, device="cuda", dtype=torch.float32)
+    sig = torch.empty(seq.total_samples, 2, device="cuda", dtype=torch.float64)
+    for mode in (gb.GBS_PLAIN, gb.GBS_GROUPED, gb.GBS_CACHED):
+        need = sim.workspace_size(mode)
+        say(f"[gpu] workspace: mode {mode} needs {need} bytes for K={ph.K}")
+        assert need > 0
+        big = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+        for fill in (0, 255):  # scratch: whatever it held before must not matter
+            big.fill_(fill)
+            ws = big[:need]
+            M, s = sim.simulate(mode, workspace=ws, m_out=m_out, sig_out=sig)
+            torch.cuda.synchronize()
+            dm = float(np.max(np.abs(M.cpu().numpy().astype(np.float64) - Mr)))
+            rel = float(np.linalg.norm(s.cpu().numpy() - sr) / np.linalg.norm(sr))
+            assert dm <= 1e-5 and rel <= 1e-4, (mode, fill, dm, rel)
+        say(f"[gpu] workspace: short, misaligned and null workspaces in mode {mode}")
+        assert code_of(gb, lambda: sim.simulate(mode, workspace=big[:need - 1])) == gb.GBS_E_WORKSPACE
+        assert code_of(gb, lambda: sim.simulate(mode, workspace=big[8:need + 8])) == gb.GBS_E_WORKSPACE
+        rc = gb.lib.gbs_simulate(sim._h, mode, 0, None, 0, None, ctypes.c_void_p(m_out.data_ptr()),
+                                 ctypes.c_void_p(sig.data_ptr()), None)
+        assert rc == gb.GBS_E_WORKSPACE
+        # straight through the C ABI with a workspace of its own
+        rc = gb.lib.gbs_simulate(sim._h, mode, 0, ctypes.c_void_p(big.data_ptr()), need, None,
+                                 ctypes.c_void_p(m_out.data_ptr()), ctypes.c_void_p(sig.data_ptr()), None)
+        assert rc == gb.GBS_OK, gb.lib.gbs_last_error(sim._h)
+        torch.cuda.synchronize()
+        assert float(np.max(np.abs(m_out.cpu().numpy().astype(np.float64) - Mr))) <= 1e-5
+    # a larger phantom needs more, and the same context still computes it right
+    ph2 = synth.tiny_phantom(nx=12, ny=9, nz=3)
+    sim.set_phantom(ph2)
+    sim.build_groups()
+    assert sim.workspace_size(gb.GBS_CACHED) > need
+    still_works(gb, sim, ph2, seq)
+    sim.close()
