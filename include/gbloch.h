@@ -271,6 +271,23 @@ int gbs_workspace_size(gbs_ctx *ctx, int mode, size_t *bytes);
 int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, void *workspace, size_t ws_bytes,
                  const float *m_init, float *m_out, double *sig_out, gbs_stats *stats);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * gbs_simulate with the workspace taken from a static device array of
+ * GBS_STATIC_WORKSPACE_BYTES that the library holds on every device it runs
+ * on until the process ends.  Same arguments, results and errors as
+ * gbs_simulate otherwise; calls no allocating routine.  A call whose
+ * gbs_workspace_size exceeds the array returns GBS_E_WORKSPACE with the two
+ * sizes in gbs_last_error.  Every context on one device shares that device's
+ * array, so calls that overlap in time on one device (from different streams
+ * or threads) race and must be serialized by the caller; nothing is kept in
+ * the array from one call to the next.
+ */
+#define GBS_STATIC_WORKSPACE_BYTES ((size_t)64 << 20)
+int gbs_simulate_static(gbs_ctx *ctx, int mode, uint32_t flags, const float *m_init, float *m_out,
+                        double *sig_out, gbs_stats *stats);
+
 /* Sizes and group counts of the current state. */
 int gbs_get_info(gbs_ctx *ctx, gbs_info *info);
 

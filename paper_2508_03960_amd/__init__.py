@@ -26,9 +26,10 @@ GBS_PLAIN_FP32 = 2
 GBS_PROFILE = 4
 GBS_SURROGATE = 8
 GBS_MLP_PARAMS = 35340
+GBS_STATIC_WORKSPACE_BYTES = 64 << 20
 
 EXPORTED = ("gbs_create", "gbs_destroy", "gbs_set_phantom", "gbs_set_sequence", "gbs_build_groups",
-            "gbs_simulate", "gbs_workspace_size", "gbs_get_info", "gbs_last_error", "gbs_strerror", "gbs_plan_summary",
+            "gbs_simulate", "gbs_workspace_size", "gbs_simulate_static", "gbs_get_info", "gbs_last_error", "gbs_strerror", "gbs_plan_summary",
             "gbs_plan_cached_summary", "gbs_set_coils",
             "gbs_mlp_create", "gbs_mlp_destroy", "gbs_mlp_last_error", "gbs_mlp_set_pulse",
             "gbs_mlp_set_norm", "gbs_mlp_get_params", "gbs_mlp_set_params", "gbs_mlp_exact",
@@ -90,6 +91,7 @@ def _load(path=LIB_PATH):
         "gbs_build_groups": ([P, U32], ctypes.c_int),
         "gbs_simulate": ([P, ctypes.c_int, U32, P, ctypes.c_size_t, P, P, P, P], ctypes.c_int),
         "gbs_workspace_size": ([P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "gbs_simulate_static": ([P, ctypes.c_int, U32, P, P, P, P], ctypes.c_int),
         "gbs_get_info": ([P, P], ctypes.c_int),
         "gbs_last_error": ([P], ctypes.c_char_p),
         "gbs_strerror": ([ctypes.c_int], ctypes.c_char_p),

@@ -22,7 +22,7 @@ ARCH = os.environ.get("GBLOCH_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "api_mlp.cpp", "plan.cpp", "k_plain.hip", "k_grouped.hip", "k_groups.hip", "k_mlp.hip",
            "k_adjoint.hip", "k_adc.hip", "k_cached.hip",
-           "k_pairs.hip", "pulseq.cpp"]
+           "k_pairs.hip", "pulseq.cpp", "noalloc.hip"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -28,6 +28,7 @@
 #include "kernels.hpp"
 #include "mlp.hpp"
 #include "mlp_api.hpp"
+#include "noalloc.hpp"
 #include "pairs.hpp"
 #include "plain_coils.hpp"
 #include "plan.hpp"
@@ -216,6 +217,9 @@ static int fail(gbs_ctx *c, int code, const std::string &msg) {
     return code;
 }
 
+int gbs::ctx_device(const gbs_ctx *ctx) { return ctx ? ctx->device : -1; }
+int gbs::ctx_fail(gbs_ctx *ctx, int code, const char *msg) { return fail(ctx, code, msg); }
+
 static int refresh_plans(gbs_ctx *ctx);
 static int build_coil_layout(gbs_ctx *ctx);
 static int build_grouped_plan(gbs_ctx *ctx);
@@ -260,6 +264,7 @@ int gbs_create(gbs_ctx **out, int device, void *stream) {
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return GBS_E_INVALID;
     if (hipSetDevice(device) != hipSuccess) return GBS_E_HIP;
+    if (noalloc_setup(device) != hipSuccess) return GBS_E_HIP;  // this device's static scratch (gbs_simulate_static)
     gbs_ctx *ctx = new (std::nothrow) gbs_ctx();
     if (!ctx) return GBS_E_NOMEM;
     ctx->device = device;
