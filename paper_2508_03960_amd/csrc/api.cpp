@@ -1140,6 +1140,17 @@ static int build_grouped_plan(gbs_ctx *ctx) {
                     piece.flops_per_iso += op_flops[q];
                 }
                 if (run) piece.need |= kEmitOnly;
+                // a lone closed-form map that ends the segment (the final
+                // relaxation) rides along with the emission run before it
+                const int t = e;
+                if (run && t + 1 == sg.op_end && (sops[t].flags & kOpPre) && !(sops[t].flags & (kOpRf | kOpEmit)) &&
+                    !(op_need[t] & (kNeedGy | kNeedZ | kNeedRun))) {
+                    piece.op_end = t + 1;
+                    piece.need |= op_need[t] | kEmitTail;
+                    piece.write_m = true;
+                    piece.flops_per_iso += op_flops[t];
+                    e = t + 1;
+                }
                 pieces[si].push_back((int)segs.size());
                 segs.push_back(piece);
                 o = e;

@@ -520,11 +520,17 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
     // y phase of the last emission per isochromat: it changes only at
     // emissions, so it waits in LDS (slot [c][thread]) rather than in registers
     // that would be copied around the op loop.  (rr, ri): its per-step factor.
+    //
+    // The emission-only sweep (EMIT) never changes the state, so it keeps the
+    // state in LDS instead and carries z_c = M_c w_c in the registers that
+    // held M: a stepped emission then costs one complex product per
+    // isochromat (z_c <- z_c r_c) and the sum of the z_c, without the LDS
+    // round trip of w_c.
     __shared__ float2 wsh[NI][256];
     float rr[NI], ri[NI];
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
-        wsh[c][threadIdx.x] = make_float2(1.f, 0.f);
+        wsh[c][threadIdx.x] = EMIT ? make_float2(mx[c], my[c]) : make_float2(1.f, 0.f);
         rr[c] = 1.f;
         ri[c] = 0.f;
     }
@@ -713,7 +719,30 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 // the factor of the x and z groups is common to the thread's
                 // isochromats: sum (M_c w_c) first, multiply once
                 float pr, pi;
-                if (yph) {
+                if (EMIT) {  // (mx, my) hold z_c = M_c w_c; M_c waits in wsh
+                    if (op.flags & kYDirect) {
+#pragma unroll
+                        for (int c = 0; c < NI; ++c) {
+                            float sn, co;
+                            sincos_rev(op.emit_cy * coord64(yv[c]), &sn, &co);
+                            const float2 m = wsh[c][threadIdx.x];
+                            mx[c] = m.x * co + m.y * sn;  // M (co - i sn)
+                            my[c] = m.y * co - m.x * sn;
+                        }
+                    } else if (op.flags & kYStep) {
+#pragma unroll
+                        for (int c = 0; c < NI; ++c) cmul(mx[c], my[c], rr[c], ri[c]);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < NI; ++c) {
+                            const float2 m = wsh[c][threadIdx.x];
+                            mx[c] = m.x;
+                            my[c] = m.y;
+                        }
+                    }
+                    pr = tree_sum<NI>(mx);
+                    pi = tree_sum<NI>(my);
+                } else if (yph) {
                     float wr[NI], wi[NI];
                     y_phase(wr, wi);
                     dot_phase<NI>(mx, my, wr, wi, pr, pi);
@@ -739,9 +768,50 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
             }
         }
     }
-    if (EMIT && act && a.write_m && (need & kNeedMz)) {  // Mz is unchanged: (0, 0, M0) or as read
+    if (EMIT && act && a.write_m) {  // the state is unchanged: M from wsh, Mz (0, 0, M0) or as read
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) ld4(a.fresh ? a.m0 : a.mz, i4 + q, mz + 4 * q);
+        for (int c = 0; c < NI; ++c) {
+            const float2 m = wsh[c][threadIdx.x];
+            mx[c] = m.x;
+            my[c] = m.y;
+        }
+        if (need & kNeedMz) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) ld4(a.fresh ? a.m0 : a.mz, i4 + q, mz + 4 * q);
+        }
+        if (need & kEmitTail) {  // the closed-form map that ends the segment (Eq. 4, 5)
+            const SweepOp op = load_op(a.ops, a.n_ops - 1);
+            float fr = 1.f, fi = 0.f, e1 = 1.f;
+            if (op.pre_xtab) {
+                const float4 v = x_row(op.pre_xtab, gx_uni, gx0, gx);
+                fr = v.x;
+                fi = v.y;
+                e1 = v.z;
+            }
+            if (op.pre_ztab) {
+                const float2 v = gather_row(op.pre_ztab, gz);
+                cmul(fr, fi, v.x, v.y);
+            }
+#pragma unroll
+            for (int c = 0; c < NI; ++c) {
+                float ar = fr, ai = fi;
+                if (op.pre_cy != 0.0) {
+                    float sn, co;
+                    sincos_rev(op.pre_cy * coord64(yv[c]), &sn, &co);
+                    cmul(ar, ai, co, -sn);
+                }
+                const float nx = mx[c] * ar - my[c] * ai;
+                const float ny = mx[c] * ai + my[c] * ar;
+                mx[c] = nx;
+                my[c] = ny;
+            }
+            if (op.flags & kPreMz) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) ld4(a.m0, i4 + q, m0 + 4 * q);
+#pragma unroll
+                for (int c = 0; c < NI; ++c) mz[c] = fmaf(e1, mz[c] - m0[c], m0[c]);
+            }
+        }
     }
     if (act && a.write_m && a.m_final) {
 #pragma unroll
@@ -904,10 +974,18 @@ __global__ void k_gather_state(int64_t K, const int32_t *__restrict__ inv, const
     }
 }
 
-__global__ __launch_bounds__(256) void k_gather_state4(int64_t K, const int32_t *__restrict__ inv,
+// Workgroups go to the 8 XCDs in turn, and each XCD has its own L2.  Caller
+// indices one grid row apart (same x and z) sit in neighbouring slots of one
+// run of the layout, i.e. in one cache line of the 16-byte rows, so each XCD
+// takes a contiguous range of caller indices: the line's four rows are then
+// read through one L2 instead of being fetched once per XCD.
+constexpr int kXcds = 8;
+
+__global__ __launch_bounds__(256) void k_gather_state4(int64_t K, int64_t per_xcd, const int32_t *__restrict__ inv,
                                                       const float4 *__restrict__ m4, float *ox, float *oy,
                                                       float *oz) {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t b = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;  // logical block
+    const int64_t k = b * 256 + threadIdx.x;
     if (k < K) {
         const float4 v = m4[inv[k]];
         ox[k] = v.x;
@@ -918,10 +996,11 @@ __global__ __launch_bounds__(256) void k_gather_state4(int64_t K, const int32_t 
 
 hipError_t launch_gather_state4(int64_t K, const int32_t *inv, const float4 *m4, float *ox, float *oy, float *oz,
                                 hipStream_t st) {
-    const int64_t g = (K + 255) / 256;  // one index per thread
-    if (g > 0x7fffffff) return hipErrorInvalidValue;
+    const int64_t g = (K + 255) / 256;  // logical blocks, one index per thread
+    const int64_t per = (g + kXcds - 1) / kXcds;
+    if (kXcds * per > 0x7fffffff) return hipErrorInvalidValue;
     if (g == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_state4, dim3((unsigned)g), dim3(256), 0, st, K, inv, m4, ox, oy, oz);
+    hipLaunchKernelGGL(k_gather_state4, dim3((unsigned)(kXcds * per)), dim3(256), 0, st, K, per, inv, m4, ox, oy, oz);
     return hipGetLastError();
 }
 

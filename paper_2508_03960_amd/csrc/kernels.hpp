@@ -83,8 +83,10 @@ struct SweepOp {
 // Per-isochromat arrays a sweep reads.
 enum { kNeedMz = 1, kNeedGx = 2, kNeedGy = 4, kNeedGz = 8, kNeedY = 16, kNeedZ = 32, kNeedRun = 64 };
 // Set in SweepArgs::need of a segment whose every op only emits (no pre map,
-// no transition): it runs in the emission-only sweep.
-enum { kEmitOnly = 128 };
+// no transition): it runs in the emission-only sweep.  kEmitTail: the last
+// op of such a segment is a B1 = 0 map without transition or emission (the
+// closed form that ends the sequence), applied after the emissions.
+enum { kEmitOnly = 128, kEmitTail = 256 };
 
 // A sweep applies ops[0 .. n_ops) in order to every isochromat while its
 // state stays in registers: one read and at most one write of M per launch.
