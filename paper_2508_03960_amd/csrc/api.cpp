@@ -1210,6 +1210,15 @@ static int build_grouped_plan(gbs_ctx *ctx) {
             prev = c;
             have_prev = true;
         }
+        // chain lengths for the emission-only sweep: stepped emissions after each direct one
+        for (size_t e = 0; e < em.size(); ++e) {
+            SweepOp &o = sops[em[e]];
+            if (!(o.flags & kYDirect)) continue;
+            int n = 0;
+            while (e + 1 + n < em.size() && em[e + 1 + n] == em[e] + 1 + n && (sops[em[e + 1 + n]].flags & kYStep)) ++n;
+            if (n > kChainMask) n = kChainMask;
+            o.flags |= n << kChainShift;
+        }
     }
     // a sweep whose emissions need no recurrence holds a repeated pre-map y
     // phase in the recurrence's factor instead of evaluating it per op.  A
@@ -1379,6 +1388,15 @@ static int run_grouped(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out
     const int64_t Kint = ctx->Kint;
     // the default initial state (0, 0, M0) is made by the first sweep itself
     const bool fresh = !m_init && !g.exec.empty() && g.exec.front().first == 0;
+    // the fast sweeps hold M / M0: an initial state that gives an isochromat
+    // with M0 = 0 a magnetization takes the general sweep instead
+    int force_general = 0;
+    if (m_init) {
+        HIPCHK(launch_fill_f64(ctx->flag.as<double>(), 1, ctx->stream));
+        HIPCHK(launch_check_zero_m0(K, ctx->ph.m0, m_init, m_init + K, m_init + 2 * K, ctx->flag.as<int>(), ctx->stream));
+        HIPCHK(hipMemcpyAsync(&force_general, ctx->flag.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
     if (!fresh)
         HIPCHK(launch_init_state(Kint, ctx->Kpad, ctx->perm.as<int32_t>(), m_init, m_init ? m_init + K : nullptr,
                                  m_init ? m_init + 2 * K : nullptr, ctx->m0i.as<float>(), mx, my, mz, ctx->stream));
@@ -1414,7 +1432,7 @@ static int run_grouped(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out
             SweepArgs a = base;
             a.ops = dev_ops + sg.op_begin;
             a.n_ops = sg.op_end - sg.op_begin;
-            a.need = sg.need;
+            a.need = sg.need | (force_general ? kForceGeneral : 0);
             a.write_m = sg.write_m ? 1 : 0;
             a.m_final = (final4 && e + 1 == g.exec.size()) ? m_final : nullptr;
             a.fresh = (fresh && e == 0) ? 1 : 0;
@@ -1445,8 +1463,7 @@ static int run_grouped(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out
     HIPCHK(hipEventRecord(ctx->fork, ctx->stream));
     HIPCHK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
     if (final4)
-        HIPCHK(launch_gather_state4(K, ctx->inv.as<int32_t>(), m_final, m_out, m_out + K,
-                                    m_out + 2 * K, ctx->side));
+        HIPCHK(launch_gather_state4(K, ctx->inv.as<int32_t>(), m_final, m_out, m_out + K, m_out + 2 * K, ctx->side));
     else
         HIPCHK(launch_gather_state(K, ctx->inv.as<int32_t>(), mx, my, mz, m_out, m_out + K, m_out + 2 * K,
                                     ctx->side));

@@ -375,6 +375,14 @@ __device__ __forceinline__ void fms_inplace(float &v, float a, float b) {
     asm("v_fma_f32 %0, %0, %1, -%2" : "+v"(v) : "v"(a), "v"(b));
 }
 
+// (ar + i ai) <- (ar + i ai)(br + i bi) with the results in ar's and ai's own
+// registers, so that a value the loop carries needs no copy.
+__device__ __forceinline__ void cmul_inplace(float &ar, float &ai, float br, float bi) {
+    const float t = ai * bi, u = ar * bi;
+    fma_inplace(ai, br, u);
+    fms_inplace(ar, br, t);
+}
+
 // M <- T (M, m0) for one isochromat.  Each output's partial sum leaves out
 // the diagonal term, so that the last step updates the component in place
 // and no copies of the state are needed.
@@ -383,6 +391,18 @@ __device__ __forceinline__ void rf_apply(const float4 &r0, const float4 &r1, con
     const float px = fmaf(r0.y, my, fmaf(r0.z, mz, r0.w * m0));
     const float py = fmaf(r1.x, mx, fmaf(r1.z, mz, r1.w * m0));
     const float pz = fmaf(r2.x, mx, fmaf(r2.y, my, r2.w * m0));
+    fma_inplace(mx, r0.x, px);
+    fma_inplace(my, r1.y, py);
+    fma_inplace(mz, r2.z, pz);
+}
+
+// rf_apply on the state divided by M0 (see sweep_body): the affine part b
+// adds as it is.
+__device__ __forceinline__ void rf_apply_ratio(const float4 &r0, const float4 &r1, const float4 &r2, float &mx,
+                                               float &my, float &mz) {
+    const float px = fmaf(r0.y, my, fmaf(r0.z, mz, r0.w));
+    const float py = fmaf(r1.x, mx, fmaf(r1.z, mz, r1.w));
+    const float pz = fmaf(r2.x, mx, fmaf(r2.y, my, r2.w));
     fma_inplace(mx, r0.x, px);
     fma_inplace(my, r1.y, py);
     fma_inplace(mz, r2.z, pz);
@@ -460,7 +480,7 @@ __device__ __forceinline__ void emit_items(const int *key, const float *vr, cons
 // share their x- and z-groups).  GENERAL = false drops what only y-group
 // transitions/emissions and direct z phases (no z groups) need, which frees
 // registers for occupancy.
-template <bool GENERAL, int NI, bool COILS = false, bool PAIRS = false, bool EMIT = false>
+template <bool GENERAL, int NI, bool COILS = false, bool PAIRS = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
     constexpr int NQ = NI / 4;  // float4 words per array and thread
     constexpr int MC = COILS ? kSweepMaxCoils : 1;
@@ -468,6 +488,15 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
     const bool act = it < a.n4 / NQ;
     const int64_t i4 = it * NQ;
     const int need = GENERAL ? a.need : (a.need & ~(kNeedGy | kNeedZ));
+    // RATIO (the fast sweeps that apply transitions): the registers hold
+    // M / M0 instead of M.  A combined transition (A, b) then maps M / M0 to
+    // A (M / M0) + b, which saves the product b M0 of every row (three per
+    // isochromat and transition); M0 is applied where M itself is needed: in
+    // the emissions (folded into the y phase factor, which the recurrence
+    // carries along) and when the state is written.  An isochromat with
+    // M0 = 0 holds 0 (its magnetization is 0 and stays 0; a launch whose
+    // initial state is not is routed to the general sweep by the host).
+    constexpr bool RATIO = !GENERAL;
     float mx[NI], my[NI], mz[NI], m0[NI], yv[NI], zv[NI];
     int gy[NI];
 #pragma unroll
@@ -483,18 +512,29 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 ld4(a.mx, i4 + q, mx + 4 * q);
                 ld4(a.my, i4 + q, my + 4 * q);
             }
-            if (!EMIT && (need & kNeedMz)) {  // (an emitting-only sweep loads Mz at the end)
+            if (RATIO || (need & kNeedMz)) {
                 ld4(a.m0, i4 + q, m0 + 4 * q);
-                if (a.fresh) {
+                if (need & kNeedMz) {
+                    if (a.fresh) {
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) mz[4 * q + c] = m0[4 * q + c];
-                } else {
-                    ld4(a.mz, i4 + q, mz + 4 * q);
+                        for (int c = 0; c < 4; ++c) mz[4 * q + c] = RATIO ? 1.f : m0[4 * q + c];
+                    } else {
+                        ld4(a.mz, i4 + q, mz + 4 * q);
+                    }
                 }
             }
             if (need & kNeedGy) ld4i(a.gid_y, i4 + q, gy + 4 * q);
             if (need & kNeedY) ld4(a.yv, i4 + q, yv + 4 * q);
             if (need & kNeedZ) ld4(a.zv, i4 + q, zv + 4 * q);
+        }
+        if (RATIO && !a.fresh) {
+#pragma unroll
+            for (int c = 0; c < NI; ++c) {
+                const float inv = m0[c] != 0.f ? 1.f / m0[c] : 0.f;
+                mx[c] *= inv;
+                my[c] *= inv;
+                if (need & kNeedMz) mz[c] *= inv;
+            }
         }
         if (need & kNeedGx) gx = a.gid_x[i4].x;
         if (need & kNeedGz) gz = a.gid_z[i4].x;
@@ -520,17 +560,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
     // y phase of the last emission per isochromat: it changes only at
     // emissions, so it waits in LDS (slot [c][thread]) rather than in registers
     // that would be copied around the op loop.  (rr, ri): its per-step factor.
-    //
-    // The emission-only sweep (EMIT) never changes the state, so it keeps the
-    // state in LDS instead and carries z_c = M_c w_c in the registers that
-    // held M: a stepped emission then costs one complex product per
-    // isochromat (z_c <- z_c r_c) and the sum of the z_c, without the LDS
-    // round trip of w_c.
     __shared__ float2 wsh[NI][256];
     float rr[NI], ri[NI];
 #pragma unroll
     for (int c = 0; c < NI; ++c) {
-        wsh[c][threadIdx.x] = EMIT ? make_float2(mx[c], my[c]) : make_float2(1.f, 0.f);
+        wsh[c][threadIdx.x] = make_float2(1.f, 0.f);
         rr[c] = 1.f;
         ri[c] = 0.f;
     }
@@ -541,7 +575,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
         // is folded into the thread's rows of T
         bool fold = false;
         float fr = 1.f, fi = 0.f;
-        if (!EMIT && (op.flags & kOpPre)) {
+        if (op.flags & kOpPre) {
             float e1 = 1.f;
             if (op.pre_xtab) {
                 const float4 v = x_row(op.pre_xtab, gx_uni, gx0, gx);
@@ -597,10 +631,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
             }
             if (op.flags & kPreMz) {
 #pragma unroll
-                for (int c = 0; c < NI; ++c) mz[c] = fmaf(e1, mz[c] - m0[c], m0[c]);
+                for (int c = 0; c < NI; ++c) mz[c] = RATIO ? fmaf(e1, mz[c] - 1.f, 1.f) : fmaf(e1, mz[c] - m0[c], m0[c]);
             }
         }
-        if (!EMIT && ((op.flags & kOpRf) || fold)) {
+        if ((op.flags & kOpRf) || fold) {
             const float4 *__restrict__ tt = op.ttab;
             if (GENERAL && (op.flags & kOpRf) && op.rf_axis == 1) {  // y groups: rows per isochromat
 #pragma unroll
@@ -636,7 +670,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     fold_row(r2, fr, fi);
                 }
 #pragma unroll
-                for (int c = 0; c < NI; ++c) rf_apply(r0, r1, r2, m0[c], mx[c], my[c], mz[c]);
+                for (int c = 0; c < NI; ++c) {
+                    if (RATIO)
+                        rf_apply_ratio(r0, r1, r2, mx[c], my[c], mz[c]);
+                    else
+                        rf_apply(r0, r1, r2, m0[c], mx[c], my[c], mz[c]);
+                }
             }
         }
         if (op.flags & kOpEmit) {
@@ -655,9 +694,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     for (int c = 0; c < NI; ++c) {
                         float s, co;
                         sincos_rev(op.emit_cy * coord64(yv[c]), &s, &co);
-                        wr[c] = co;
-                        wi[c] = -s;
-                        wsh[c][threadIdx.x] = make_float2(co, -s);
+                        wr[c] = RATIO ? co * m0[c] : co;  // RATIO: the factor carries M0
+                        wi[c] = RATIO ? -s * m0[c] : -s;
+                        wsh[c][threadIdx.x] = make_float2(wr[c], wi[c]);
                     }
                 } else {
 #pragma unroll
@@ -719,33 +758,19 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 // the factor of the x and z groups is common to the thread's
                 // isochromats: sum (M_c w_c) first, multiply once
                 float pr, pi;
-                if (EMIT) {  // (mx, my) hold z_c = M_c w_c; M_c waits in wsh
-                    if (op.flags & kYDirect) {
-#pragma unroll
-                        for (int c = 0; c < NI; ++c) {
-                            float sn, co;
-                            sincos_rev(op.emit_cy * coord64(yv[c]), &sn, &co);
-                            const float2 m = wsh[c][threadIdx.x];
-                            mx[c] = m.x * co + m.y * sn;  // M (co - i sn)
-                            my[c] = m.y * co - m.x * sn;
-                        }
-                    } else if (op.flags & kYStep) {
-#pragma unroll
-                        for (int c = 0; c < NI; ++c) cmul(mx[c], my[c], rr[c], ri[c]);
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < NI; ++c) {
-                            const float2 m = wsh[c][threadIdx.x];
-                            mx[c] = m.x;
-                            my[c] = m.y;
-                        }
-                    }
-                    pr = tree_sum<NI>(mx);
-                    pi = tree_sum<NI>(my);
-                } else if (yph) {
+                if (yph) {
                     float wr[NI], wi[NI];
                     y_phase(wr, wi);
                     dot_phase<NI>(mx, my, wr, wi, pr, pi);
+                } else if (RATIO) {
+                    float tx[NI], ty[NI];
+#pragma unroll
+                    for (int c = 0; c < NI; ++c) {
+                        tx[c] = mx[c] * m0[c];
+                        ty[c] = my[c] * m0[c];
+                    }
+                    pr = tree_sum<NI>(tx);
+                    pi = tree_sum<NI>(ty);
                 } else {
                     pr = tree_sum<NI>(mx);
                     pi = tree_sum<NI>(my);
@@ -768,49 +793,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
             }
         }
     }
-    if (EMIT && act && a.write_m) {  // the state is unchanged: M from wsh, Mz (0, 0, M0) or as read
+    if (RATIO && act && a.write_m) {  // back to M
 #pragma unroll
         for (int c = 0; c < NI; ++c) {
-            const float2 m = wsh[c][threadIdx.x];
-            mx[c] = m.x;
-            my[c] = m.y;
-        }
-        if (need & kNeedMz) {
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) ld4(a.fresh ? a.m0 : a.mz, i4 + q, mz + 4 * q);
-        }
-        if (need & kEmitTail) {  // the closed-form map that ends the segment (Eq. 4, 5)
-            const SweepOp op = load_op(a.ops, a.n_ops - 1);
-            float fr = 1.f, fi = 0.f, e1 = 1.f;
-            if (op.pre_xtab) {
-                const float4 v = x_row(op.pre_xtab, gx_uni, gx0, gx);
-                fr = v.x;
-                fi = v.y;
-                e1 = v.z;
-            }
-            if (op.pre_ztab) {
-                const float2 v = gather_row(op.pre_ztab, gz);
-                cmul(fr, fi, v.x, v.y);
-            }
-#pragma unroll
-            for (int c = 0; c < NI; ++c) {
-                float ar = fr, ai = fi;
-                if (op.pre_cy != 0.0) {
-                    float sn, co;
-                    sincos_rev(op.pre_cy * coord64(yv[c]), &sn, &co);
-                    cmul(ar, ai, co, -sn);
-                }
-                const float nx = mx[c] * ar - my[c] * ai;
-                const float ny = mx[c] * ai + my[c] * ar;
-                mx[c] = nx;
-                my[c] = ny;
-            }
-            if (op.flags & kPreMz) {
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) ld4(a.m0, i4 + q, m0 + 4 * q);
-#pragma unroll
-                for (int c = 0; c < NI; ++c) mz[c] = fmaf(e1, mz[c] - m0[c], m0[c]);
-            }
+            mx[c] *= m0[c];
+            my[c] *= m0[c];
+            mz[c] *= m0[c];
         }
     }
     if (act && a.write_m && a.m_final) {
@@ -843,12 +831,168 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     sweep_body<false, SWEEP_NI_FAST, false, true>(a);
 }
 
-// The fast sweep for segments whose ops only emit (an EPI readout train): no
-// pre maps and no transitions, so few registers stay live and more waves per
-// SIMD hide the latency of each op's descriptor and table loads.
+// The sweep for segments whose ops only emit (an EPI readout train).  The
+// state does not change between the emissions, so each thread holds its M_c
+// for the whole launch and carries z_c = M_c w_c, w_c being the y phase of
+// the current emission (Eq. 8-9 with the accumulated blip moments).  A chain
+// of evenly stepped emissions (its first op carries the count of the
+// stepped ones that follow) starts with a direct evaluation of w_c (M_c waits
+// in LDS for these chain starts, slot [c][thread]) and then
+// multiplies z_c by the step factor r_c in place, so each further emission
+// costs one complex product and the sum of the z_c per isochromat.  Each
+// emission scales the thread's sum by its x- and z-group factors.  A closed
+// form map that ends the segment (kEmitTail) is applied to the state once,
+// after the emissions.
+template <int NI>
+__device__ __forceinline__ void emit_sweep_body(const SweepArgs &a) {
+    constexpr int NQ = NI / 4;
+    const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool act = it < a.n4 / NQ;
+    const int64_t i4 = it * NQ;
+    const int need = a.need;
+    __shared__ float2 msh[NI][256];
+    float yv[NI], zr[NI], zi[NI], rr[NI], ri[NI];
+    int gx = 0, gz = 0;
+    {
+        float mx[NI], my[NI];
+#pragma unroll
+        for (int c = 0; c < NI; ++c) {
+            mx[c] = my[c] = yv[c] = zr[c] = zi[c] = ri[c] = 0.f;
+            rr[c] = 1.f;
+        }
+        if (act) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if (!a.fresh) {
+                    ld4(a.mx, i4 + q, mx + 4 * q);
+                    ld4(a.my, i4 + q, my + 4 * q);
+                }
+                if (need & kNeedY) ld4(a.yv, i4 + q, yv + 4 * q);
+            }
+            if (need & kNeedGx) gx = a.gid_x[i4].x;
+            if (need & kNeedGz) gz = a.gid_z[i4].x;
+        }
+#pragma unroll
+        for (int c = 0; c < NI; ++c) msh[c][threadIdx.x] = make_float2(mx[c], my[c]);
+    }
+    const int gx0 = __builtin_amdgcn_readfirstlane(gx);
+    const bool gx_uni = __all(!act || gx == gx0) != 0;
+    auto emit = [&](const SweepOp &op) {
+        const float4 xv = x_row(op.emit_xtab, gx_uni, gx0, gx);
+        float er = xv.x, ei = xv.y;
+        float2 zf = make_float2(1.f, 0.f);
+        if (op.emit_ztab) zf = gather_row(op.emit_ztab, gz);  // used last: its latency overlaps the sum
+        const float pr = tree_sum<NI>(zr), pi = tree_sum<NI>(zi);
+        if (op.emit_ztab) cmul(er, ei, zf.x, zf.y);
+        const float sr = er * pr - ei * pi, si = er * pi + ei * pr;
+        if (op.emit_axis == 0)
+            emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
+        else
+            emit_thread(gz, false, sr, si, act, op.gsum);
+    };
+    const int n_emit = a.n_ops - ((need & kEmitTail) ? 1 : 0);
+    for (int o = 0; o < n_emit;) {
+        const SweepOp op = load_op(a.ops, o++);
+        if (op.flags & kYDirect) {
+#pragma unroll
+            for (int c = 0; c < NI; ++c) {
+                float sn, co;
+                sincos_rev(op.emit_cy * coord64(yv[c]), &sn, &co);
+                const float2 m = msh[c][threadIdx.x];
+                zr[c] = m.x * co + m.y * sn;  // M (co - i sn)
+                zi[c] = m.y * co - m.x * sn;
+            }
+        } else if (op.flags & kYStep) {
+#pragma unroll
+            for (int c = 0; c < NI; ++c) cmul_inplace(zr[c], zi[c], rr[c], ri[c]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < NI; ++c) {
+                const float2 m = msh[c][threadIdx.x];
+                zr[c] = m.x;
+                zi[c] = m.y;
+            }
+        }
+        emit(op);
+        if (op.flags & kYSetR) {  // step factor of the chain this emission starts
+#pragma unroll
+            for (int c = 0; c < NI; ++c) {
+                float sn, co;
+                sincos_rev(op.emit_dcy * coord64(yv[c]), &sn, &co);
+                rr[c] = co;
+                ri[c] = -sn;
+            }
+        }
+        const int steps = (op.flags >> kChainShift) & kChainMask;
+        for (int j = 0; j < steps && o < n_emit; ++j) {
+            const SweepOp sop = load_op(a.ops, o++);
+#pragma unroll
+            for (int c = 0; c < NI; ++c) cmul_inplace(zr[c], zi[c], rr[c], ri[c]);
+            emit(sop);
+        }
+    }
+    if (!act || !a.write_m) return;
+    float mx[NI], my[NI], mz[NI], m0[NI];
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+        const float2 m = msh[c][threadIdx.x];
+        mx[c] = m.x;
+        my[c] = m.y;
+        mz[c] = m0[c] = 0.f;
+    }
+    if (need & kNeedMz) {  // Mz is unchanged: (0, 0, M0) or as read
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) ld4(a.fresh ? a.m0 : a.mz, i4 + q, mz + 4 * q);
+    }
+    if (need & kEmitTail) {  // the closed-form map that ends the segment (Eq. 4, 5)
+        const SweepOp op = load_op(a.ops, a.n_ops - 1);
+        float fr = 1.f, fi = 0.f, e1 = 1.f;
+        if (op.pre_xtab) {
+            const float4 v = x_row(op.pre_xtab, gx_uni, gx0, gx);
+            fr = v.x;
+            fi = v.y;
+            e1 = v.z;
+        }
+        if (op.pre_ztab) {
+            const float2 v = gather_row(op.pre_ztab, gz);
+            cmul(fr, fi, v.x, v.y);
+        }
+#pragma unroll
+        for (int c = 0; c < NI; ++c) {
+            float ar = fr, ai = fi;
+            if (op.pre_cy != 0.0) {
+                float sn, co;
+                sincos_rev(op.pre_cy * coord64(yv[c]), &sn, &co);
+                cmul(ar, ai, co, -sn);
+            }
+            const float nx = mx[c] * ar - my[c] * ai;
+            const float ny = mx[c] * ai + my[c] * ar;
+            mx[c] = nx;
+            my[c] = ny;
+        }
+        if (op.flags & kPreMz) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) ld4(a.m0, i4 + q, m0 + 4 * q);
+#pragma unroll
+            for (int c = 0; c < NI; ++c) mz[c] = fmaf(e1, mz[c] - m0[c], m0[c]);
+        }
+    }
+    if (a.m_final) {
+#pragma unroll
+        for (int c = 0; c < NI; ++c) a.m_final[4 * i4 + c] = make_float4(mx[c], my[c], mz[c], 0.f);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            a.mx[i4 + q] = make_float4(mx[4 * q], mx[4 * q + 1], mx[4 * q + 2], mx[4 * q + 3]);
+            a.my[i4 + q] = make_float4(my[4 * q], my[4 * q + 1], my[4 * q + 2], my[4 * q + 3]);
+            if (need & kNeedMz) a.mz[i4 + q] = make_float4(mz[4 * q], mz[4 * q + 1], mz[4 * q + 2], mz[4 * q + 3]);
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES_EMIT))) void k_sweep_emit(
     SweepArgs a) {
-    sweep_body<false, SWEEP_NI_FAST, false, false, true>(a);
+    emit_sweep_body<SWEEP_NI_FAST>(a);
 }
 
 // The general sweep with receive coils: the thread's sensitivities (up to
@@ -861,7 +1005,7 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
     if (a.coil) {
         if (a.n_coils < 1 || a.n_coils > kSweepMaxCoils) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_sweep_coils, dim3((unsigned)((a.n4 + 255) / 256)), dim3(256), 0, st, a);
-    } else if (a.need & (kNeedGy | kNeedZ)) {
+    } else if (a.need & (kNeedGy | kNeedZ | kForceGeneral)) {
         hipLaunchKernelGGL(k_sweep_general, dim3((unsigned)((a.n4 + 255) / 256)), dim3(256), 0, st, a);
     } else {
         const int64_t n = a.n4 / (SWEEP_NI_FAST / 4);
@@ -1001,6 +1145,23 @@ hipError_t launch_gather_state4(int64_t K, const int32_t *inv, const float4 *m4,
     if (kXcds * per > 0x7fffffff) return hipErrorInvalidValue;
     if (g == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather_state4, dim3((unsigned)(kXcds * per)), dim3(256), 0, st, K, per, inv, m4, ox, oy, oz);
+    return hipGetLastError();
+}
+
+__global__ void k_check_zero_m0(int64_t K, const float *__restrict__ m0, const float *__restrict__ mx,
+                                const float *__restrict__ my, const float *__restrict__ mz, int *flag) {
+    bool bad = false;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < K; k += (int64_t)gridDim.x * blockDim.x)
+        bad = bad || (m0[k] == 0.f && (mx[k] != 0.f || my[k] != 0.f || mz[k] != 0.f));
+    if (__any(bad) && __lane_id() == 0) *flag = 1;
+}
+
+hipError_t launch_check_zero_m0(int64_t K, const float *m0, const float *mx, const float *my, const float *mz,
+                                int *flag, hipStream_t st) {
+    int64_t g = (K + 255) / 256;
+    if (g > 4096) g = 4096;
+    if (g == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_check_zero_m0, dim3((unsigned)g), dim3(256), 0, st, K, m0, mx, my, mz, flag);
     return hipGetLastError();
 }
 

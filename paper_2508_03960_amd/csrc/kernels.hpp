@@ -63,6 +63,9 @@ enum {
     kPreYSet = 128,
     kPreYHold = 256
 };
+// An emission that starts a chain (kYDirect) also carries, in bits
+// kChainShift.., the number of kYStep emissions that follow it (at most 15).
+enum { kChainShift = 12, kChainMask = 15 };
 struct SweepOp {
     int32_t flags;
     int32_t rf_axis;
@@ -87,6 +90,10 @@ enum { kNeedMz = 1, kNeedGx = 2, kNeedGy = 4, kNeedGz = 8, kNeedY = 16, kNeedZ =
 // op of such a segment is a B1 = 0 map without transition or emission (the
 // closed form that ends the sequence), applied after the emissions.
 enum { kEmitOnly = 128, kEmitTail = 256 };
+// Run the segment in the general sweep, which keeps M itself in registers
+// (the fast sweeps hold M / M0): set for a run whose initial state gives an
+// isochromat with M0 = 0 a nonzero magnetization.
+enum { kForceGeneral = 512 };
 
 // A sweep applies ops[0 .. n_ops) in order to every isochromat while its
 // state stays in registers: one read and at most one write of M per launch.
@@ -184,6 +191,10 @@ hipError_t launch_gather_state(int64_t K, const int32_t *inv, const float *mx, c
                                float *ox, float *oy, float *oz, hipStream_t st);
 hipError_t launch_gather_state4(int64_t K, const int32_t *inv, const float4 *m4, float *ox, float *oy, float *oz,
                                 hipStream_t st);
+// *flag <- 1 if some isochromat has M0 = 0 and a nonzero initial state (*flag
+// is not cleared)
+hipError_t launch_check_zero_m0(int64_t K, const float *m0, const float *mx, const float *my, const float *mz,
+                                int *flag, hipStream_t st);
 
 // ---- grouping ---------------------------------------------------------------
 hipError_t launch_validate_phantom(int64_t K, const PhantomPtrs &ph, int *bad, hipStream_t st);

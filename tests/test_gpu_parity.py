@@ -267,3 +267,19 @@ def test_grouped_is_repeatable(gb):
     M2, s2, _ = run_gpu(gb, ph, seq, gb.GBS_GROUPED)
     assert np.array_equal(M1, M2)  # streaming passes are order-independent per isochromat
     assert np.linalg.norm(s1 - s2) <= 1e-12 * np.linalg.norm(s1)  # FP64 atomics reorder sums only
+
+
+def test_zero_m0_with_initial_state(gb):
+    """The fast sweeps hold M / M0; an isochromat with M0 = 0 and a nonzero
+    initial magnetization (its magnetization still rotates and decays) must
+    take the general sweep and match the oracle.  From (0, 0, M0) such
+    isochromats stay at zero in every sweep."""
+    ph = synth.brain_like_phantom(48, 40, 3)
+    rng = np.random.default_rng(44)
+    zero = rng.random(ph.K) < 0.1
+    ph = synth.Phantom(ph.x, ph.y, ph.z, ph.t1, ph.t2, ph.df, np.where(zero, 0.0, ph.m0).astype(np.float32),
+                       name="m0-zeros")
+    fs = synth.fse_sequence(n_shots=2, etl=3, n_read=32)
+    check_case(gb, "m0=0, fresh", ph, fs, modes=("grouped",))
+    m_init = rng.uniform(-0.5, 0.5, (3, ph.K))
+    check_case(gb, "m0=0, initial state", ph, fs, modes=("grouped", "cached", "plain"), m_init=m_init)
