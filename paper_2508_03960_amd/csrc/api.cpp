@@ -130,6 +130,9 @@ struct GroupedPlan {
     };
     std::vector<Seg> segs;
     std::vector<std::pair<int, int>> exec;  // (0, segment) or (1, index into plan.ops)
+    // kPartials segments: their reduction jobs [first, first + count) at o_part
+    std::vector<std::pair<int, int>> seg_parts;
+    size_t o_part = 0, w_part = 0;
     int64_t n_ops = 0;
     // learned surrogate for one distinct RF transition (surr_rf >= 0); the
     // RF jobs at o_rf_surr skip its exact composition.  s_* are offsets in
@@ -163,6 +166,7 @@ struct gbs_ctx {
     int64_t Kint = 0;  // isochromats in the padded group-sorted layout (multiple of 8)
     int64_t Kpad = 0;
     DevBuf perm, inv, xi, yi, zi, t1i, t2i, dfi, m0i, gid[3], gtab[3], gcount[3];
+    DevBuf xstart;  // first layout slot of every x-group, and Kint after the last
     // no-grads groups (GBS_AX_N): (0, T1, T2, df) per group, and the group of each x-group
     int64_t n_tissue = -1;
     DevBuf ttab, tmap;
@@ -293,7 +297,7 @@ int gbs_destroy(gbs_ctx *ctx) {
     DevBuf *bufs[] = {&ctx->d_wave, &ctx->d_adc, &ctx->perm, &ctx->inv, &ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i,
                       &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->jobs, &ctx->samp, &ctx->flag, &ctx->surr_idx,
                       &ctx->adj_ops, &ctx->adj_samp, &ctx->adj_ckpt, &ctx->adj_sub, &ctx->adj_sig, &ctx->adj_grf,
-                      &ctx->adj_gt, &ctx->csamp, &ctx->ttab, &ctx->tmap, &ctx->coil_l, &ctx->run_of4,
+                      &ctx->adj_gt, &ctx->csamp, &ctx->ttab, &ctx->tmap, &ctx->coil_l, &ctx->run_of4, &ctx->xstart,
                       &ctx->rtab, &ctx->rz};
     for (DevBuf *b : bufs) b->release();
     for (int a = 0; a < 3; ++a) {
@@ -502,6 +506,8 @@ int gbs_build_groups(gbs_ctx *ctx, uint32_t axes) {
         ALLOC(ctx->gid[a], sizeof(int32_t) * Kpad);
         HIPCHK(launch_gather_i32(Kpad, Kpad, src, gid_nat[a].as<int32_t>(), ctx->gid[a].as<int32_t>(), ctx->stream));
     }
+    ALLOC(ctx->xstart, sizeof(int32_t) * (size_t)(ctx->ng[0] + 1));
+    HIPCHK(launch_group_starts(kint, ctx->gid[0].as<int32_t>(), ctx->ng[0], ctx->xstart.as<int32_t>(), ctx->stream));
     DevBuf *dst[7] = {&ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i, &ctx->t2i, &ctx->dfi, &ctx->m0i};
     const float *from[7] = {ctx->ph.x, ctx->ph.y, ctx->ph.z, ctx->ph.t1, ctx->ph.t2, ctx->ph.df, ctx->ph.m0};
     for (int i = 0; i < 7; ++i) {
@@ -783,6 +789,11 @@ static double sweep_bytes_per_iso(int need, bool write_m, bool fresh, bool final
     return b;
 }
 
+// Does a sweep with these needs run in the emission-only kernel (launch_sweep)?
+static bool in_emit_kernel(int need, bool coils) {
+    return (need & kEmitOnly) && !coils && !(need & (kNeedGy | kNeedZ | kForceGeneral));
+}
+
 static int build_grouped_plan(gbs_ctx *ctx) {
     GroupedPlan &g = ctx->gp;
     const HostSeq &s = ctx->seq;
@@ -985,7 +996,6 @@ static int build_grouped_plan(gbs_ctx *ctx) {
         ALLOC(ctx->surr_idx, sizeof(int32_t) * (size_t)g.surr_n_check);
         HIPCHK(hipMemcpy(ctx->surr_idx.p, all.data(), sizeof(int32_t) * g.surr_n_check, hipMemcpyHostToDevice));
     }
-    g.ws_bytes = w.off;
     std::vector<FoldJob> fj(folds.size());
     for (size_t i = 0; i < folds.size(); ++i) {
         const FoldPlan &f = folds[i];
@@ -1244,6 +1254,37 @@ static int build_grouped_plan(gbs_ctx *ctx) {
             }
         }
     }
+    // emission-only segments: x-group sums through per-wavefront partials
+    // (kPartials) instead of memory-side atomics, one PartJob per emission
+    std::vector<PartJob> pj;
+    {
+        const int64_t n_waves = 4 * ((ctx->Kint / 8 + 255) / 256);  // k_sweep_emit: 8 isochromats per thread
+        int64_t n_part = 0;
+        const bool coils = ctx->coil_re != nullptr;
+        for (const auto &sg : g.segs)
+            if (in_emit_kernel(sg.need, coils))
+                for (int o = sg.op_begin; o < sg.op_end; ++o)
+                    if ((sops[o].flags & kOpEmit) && sops[o].emit_axis == 0) ++n_part;
+        if (n_part) g.w_part = w.take(sizeof(float4) * (size_t)n_waves * (size_t)n_part);
+        int64_t k = 0;
+        g.seg_parts.assign(g.segs.size(), {0, 0});
+        for (size_t si = 0; si < g.segs.size(); ++si) {
+            GroupedPlan::Seg &sg = g.segs[si];
+            if (!in_emit_kernel(sg.need, coils)) continue;
+            const int first = (int)pj.size();
+            for (int o = sg.op_begin; o < sg.op_end; ++o) {
+                SweepOp &op = sops[o];
+                if (!(op.flags & kOpEmit) || op.emit_axis != 0) continue;
+                op.part = ws_rel<float4>(g.w_part + sizeof(float4) * (size_t)n_waves * (size_t)k++);
+                pj.push_back(PartJob{op.part, op.gsum});
+            }
+            if ((int)pj.size() > first) {
+                sg.need |= kPartials;
+                g.seg_parts[si] = {first, (int)pj.size() - first};
+            }
+        }
+    }
+    g.ws_bytes = w.off;
     for (auto &sg : g.segs) sg.bytes_per_iso = sweep_bytes_per_iso(sg.need, sg.write_m, false, false);
     g.n_ops = (int64_t)sops.size();
 
@@ -1259,7 +1300,8 @@ static int build_grouped_plan(gbs_ctx *ctx) {
     g.o_adc = g.o_tab + align256(sizeof(TabJob) * tjobs.size());
     g.o_adclin = g.o_adc + align256(sizeof(AdcJobDev) * aj.size());
     g.o_sweep = g.o_adclin + align256(sizeof(AdcLinJob) * lj.size());
-    const size_t jbytes = g.o_sweep + sizeof(SweepOp) * sops.size();
+    g.o_part = g.o_sweep + align256(sizeof(SweepOp) * sops.size());
+    const size_t jbytes = g.o_part + sizeof(PartJob) * pj.size();
     ctx->host_jobs.assign(jbytes, 0);
     auto put = [&](size_t o, const void *src, size_t n) {
         if (n) std::memcpy(ctx->host_jobs.data() + o, src, n);
@@ -1271,6 +1313,7 @@ static int build_grouped_plan(gbs_ctx *ctx) {
     put(g.o_adc, aj.data(), sizeof(AdcJobDev) * aj.size());
     put(g.o_adclin, lj.data(), sizeof(AdcLinJob) * lj.size());
     put(g.o_sweep, sops.data(), sizeof(SweepOp) * sops.size());
+    put(g.o_part, pj.data(), sizeof(PartJob) * pj.size());
     // the pointer fields that hold workspace offsets
     const std::vector<char> &img = ctx->host_jobs;
     add_relocs<RfJobDev>(g.relocs, img, g.o_rf, rj.size(), {offsetof(RfJobDev, out)});
@@ -1282,6 +1325,7 @@ static int build_grouped_plan(gbs_ctx *ctx) {
     add_relocs<SweepOp>(g.relocs, img, g.o_sweep, sops.size(),
                         {offsetof(SweepOp, pre_xtab), offsetof(SweepOp, pre_ztab), offsetof(SweepOp, ttab),
                          offsetof(SweepOp, emit_xtab), offsetof(SweepOp, emit_ztab), offsetof(SweepOp, gsum)});
+    add_relocs<PartJob>(g.relocs, img, g.o_part, pj.size(), {offsetof(PartJob, part), offsetof(PartJob, gsum)});
     ALLOC(ctx->jobs, jbytes);
     g.uploaded_ws = nullptr;
     if (soff) HIPCHK(hipMemcpy(ctx->samp.p, hs.data(), sizeof(double2) * soff, hipMemcpyHostToDevice));
@@ -1444,6 +1488,11 @@ static int run_grouped(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out
             flops += sg.flops_per_iso * (double)K;
             if (profile) HIPCHK(hipEventRecord(ctx->pev[2 * timed], ctx->stream));
             HIPCHK(launch_sweep(a, ctx->stream));
+            if ((a.need & kPartials) && in_emit_kernel(a.need, a.coil != nullptr)) {  // (else atomics were used)
+                const auto &sp = g.seg_parts[item.second];
+                HIPCHK(launch_part_reduce((const PartJob *)(jb + g.o_part) + sp.first, sp.second, ctx->ng[0],
+                                          ctx->xstart.as<int32_t>(), ctx->stream));
+            }
             if (profile) HIPCHK(hipEventRecord(ctx->pev[2 * timed++ + 1], ctx->stream));
         } else {
             const Op &op = plan.ops[item.second];

@@ -831,6 +831,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     sweep_body<false, SWEEP_NI_FAST, false, true>(a);
 }
 
+// emit_thread for a kPartials emission: the wavefront's key sums go to its
+// float4 entry `part` (first key, other key) instead of memory-side atomics.
+__device__ __forceinline__ void emit_thread_part(int key, bool uni, float vr, float vi, bool act, float4 *part,
+                                                 double2 *__restrict__ gsum) {
+    if (uni) {
+        vr = wave_sum_lane63(vr);
+        vi = wave_sum_lane63(vi);
+        if (__lane_id() == 63) *part = make_float4(vr, vi, 0.f, 0.f);
+        return;
+    }
+    const int k = act ? key : -1;
+    const int k0 = __builtin_amdgcn_readfirstlane(k), k1 = __builtin_amdgcn_readlane(k, 63);
+    if (__all(k == k0 || k == k1)) {
+        const bool in0 = k == k0;
+        const float ar = wave_sum_lane63(in0 ? vr : 0.f), ai = wave_sum_lane63(in0 ? vi : 0.f);
+        const float br = wave_sum_lane63(in0 ? 0.f : vr), bi = wave_sum_lane63(in0 ? 0.f : vi);
+        if (__lane_id() == 63) *part = make_float4(ar, ai, br, bi);
+        return;
+    }
+    if (__lane_id() == 63) *part = make_float4(0.f, 0.f, 0.f, 0.f);
+    emit_thread(key, false, vr, vi, act, gsum);
+}
+
 // The sweep for segments whose ops only emit (an EPI readout train).  The
 // state does not change between the emissions, so each thread holds its M_c
 // for the whole launch and carries z_c = M_c w_c, w_c being the y phase of
@@ -877,6 +900,7 @@ __device__ __forceinline__ void emit_sweep_body(const SweepArgs &a) {
     }
     const int gx0 = __builtin_amdgcn_readfirstlane(gx);
     const bool gx_uni = __all(!act || gx == gx0) != 0;
+    const int64_t wave_id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // covers slots 512 wave_id ..
     auto emit = [&](const SweepOp &op) {
         const float4 xv = x_row(op.emit_xtab, gx_uni, gx0, gx);
         float er = xv.x, ei = xv.y;
@@ -885,7 +909,9 @@ __device__ __forceinline__ void emit_sweep_body(const SweepArgs &a) {
         const float pr = tree_sum<NI>(zr), pi = tree_sum<NI>(zi);
         if (op.emit_ztab) cmul(er, ei, zf.x, zf.y);
         const float sr = er * pr - ei * pi, si = er * pi + ei * pr;
-        if (op.emit_axis == 0)
+        if (op.emit_axis == 0 && (need & kPartials))
+            emit_thread_part(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.part + wave_id, op.gsum);
+        else if (op.emit_axis == 0)
             emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
         else
             emit_thread(gz, false, sr, si, act, op.gsum);
@@ -1145,6 +1171,57 @@ hipError_t launch_gather_state4(int64_t K, const int32_t *inv, const float4 *m4,
     if (kXcds * per > 0x7fffffff) return hipErrorInvalidValue;
     if (g == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather_state4, dim3((unsigned)(kXcds * per)), dim3(256), 0, st, K, per, inv, m4, ox, oy, oz);
+    return hipGetLastError();
+}
+
+// gsum[g] += sum of the partial entries of the wavefronts that span x-group g
+// (kPartials), one thread per group and emission, FP64 sums.  A wavefront's
+// entry holds its first key's sum in (x, y) and its other key's in (z, w).
+// Every wavefront after the first of the group starts inside the group, so
+// g is its first key; the first one has g first only if g starts at the
+// wavefront's first slot.
+__global__ __launch_bounds__(256) void k_part_reduce(const PartJob *__restrict__ jobs, int64_t n_groups,
+                                                    const int32_t *__restrict__ xstart) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= n_groups) return;
+    const PartJob j = jobs[blockIdx.y];
+    const int64_t s0 = xstart[g];
+    const int64_t w0 = s0 / kPartSlots, w1 = (xstart[g + 1] - 1) / kPartSlots;
+    const float4 v0 = j.part[w0];
+    const bool head = s0 % kPartSlots == 0;
+    double sr = head ? v0.x : v0.z, si = head ? v0.y : v0.w;
+    for (int64_t w = w0 + 1; w <= w1; ++w) {
+        const float4 v = j.part[w];
+        sr += v.x;
+        si += v.y;
+    }
+    j.gsum[g].x += sr;
+    j.gsum[g].y += si;
+}
+
+hipError_t launch_part_reduce(const PartJob *jobs, int n_jobs, int64_t n_groups, const int32_t *xstart,
+                              hipStream_t st) {
+    if (n_jobs <= 0 || n_groups <= 0) return hipSuccess;
+    if (n_jobs > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_part_reduce, dim3((unsigned)((n_groups + 255) / 256), (unsigned)n_jobs), dim3(256), 0, st,
+                       jobs, n_groups, xstart);
+    return hipGetLastError();
+}
+
+__global__ void k_group_starts(int64_t n, const int32_t *__restrict__ gid_x, int64_t n_groups,
+                               int32_t *__restrict__ xstart) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i == n)
+            xstart[n_groups] = (int32_t)n;
+        else if (i == 0 || gid_x[i - 1] != gid_x[i])
+            xstart[gid_x[i]] = (int32_t)i;
+    }
+}
+
+hipError_t launch_group_starts(int64_t n, const int32_t *gid_x, int64_t n_groups, int32_t *xstart, hipStream_t st) {
+    int64_t g = (n + 256) / 256;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_group_starts, dim3((unsigned)g), dim3(256), 0, st, n, gid_x, n_groups, xstart);
     return hipGetLastError();
 }
 

@@ -71,7 +71,11 @@ struct SweepOp {
     int32_t rf_axis;
     int32_t emit_axis;
     int32_t gsum_stride;     // groups of the emission axis: coil p sums at gsum + p * gsum_stride
-    const float4 *pre_xtab;  // per x-group (Re a, Im a, E1, 0); null: no x factor
+    union {
+        const float4 *pre_xtab;  // per x-group (Re a, Im a, E1, 0); null: no x factor
+        float4 *part;            // kPartials (an emission without pre map): this emission's
+                                 // per-wavefront sums, one float4 per wavefront
+    };
     const float2 *pre_ztab;  // per z-group phase; null: none
     double pre_cy, pre_cz;   // direct y / z phase coefficients (cycles per metre); 0: none
     const float4 *ttab;      // 3 float4 rows (A_r0, A_r1, A_r2, b_r) per group of rf_axis
@@ -90,6 +94,13 @@ enum { kNeedMz = 1, kNeedGx = 2, kNeedGy = 4, kNeedGz = 8, kNeedY = 16, kNeedZ =
 // op of such a segment is a B1 = 0 map without transition or emission (the
 // closed form that ends the sequence), applied after the emissions.
 enum { kEmitOnly = 128, kEmitTail = 256 };
+// kPartials: the x-group sums of the segment's emissions go to per-wavefront
+// partial sums (SweepOp::part) instead of memory-side atomics: lane 63 of a
+// wavefront of 512 isochromats (8 per thread) stores (sum of its first
+// key, sum of the other key) as one float4; k_part_reduce then adds, per
+// group, the entries of the wavefronts that span it.  A wavefront with three
+// or more keys stores zeros and adds its sums with atomics.
+enum { kPartials = 1024 };
 // Run the segment in the general sweep, which keeps M itself in registers
 // (the fast sweeps hold M / M0): set for a run whose initial state gives an
 // isochromat with M0 = 0 a nonzero magnetization.
@@ -127,6 +138,19 @@ struct SweepArgs {
     // operations whose transition rows are per such group (rf_axis 3; general sweep)
     const int32_t *run_of4;
 };
+
+// One emission of a kPartials segment: gsum[g] += the entries of part that
+// belong to group g.
+struct PartJob {
+    const float4 *part;
+    double2 *gsum;
+};
+hipError_t launch_part_reduce(const PartJob *jobs, int n_jobs, int64_t n_groups, const int32_t *xstart,
+                              hipStream_t st);
+// xstart[g] <- first slot of x-group g in the layout (slots [0, n)), xstart[G] <- n
+hipError_t launch_group_starts(int64_t n, const int32_t *gid_x, int64_t n_groups, int32_t *xstart, hipStream_t st);
+// slots of the layout one wavefront of the emission-only sweep covers
+constexpr int kPartSlots = 512;
 
 // ---- tables ---------------------------------------------------------------
 struct TabJob {

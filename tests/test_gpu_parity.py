@@ -283,3 +283,7 @@ def test_zero_m0_with_initial_state(gb):
     check_case(gb, "m0=0, fresh", ph, fs, modes=("grouped",))
     m_init = rng.uniform(-0.5, 0.5, (3, ph.K))
     check_case(gb, "m0=0, initial state", ph, fs, modes=("grouped", "cached", "plain"), m_init=m_init)
+    # an EPI: its readout train (the emission-only sweep's partial sums) in the general sweep
+    epi = synth.epi_sequence(n_lines=20, n_read=32, rf_steps=1000)
+    check_case(gb, "m0=0, epi, initial state", ph, epi, modes=("grouped",), m_init=m_init)
+    check_case(gb, "m0=0, epi", ph, epi, modes=("grouped",))
