@@ -127,6 +127,7 @@ struct GroupedPlan {
         int op_begin, op_end, need;
         bool write_m;
         double bytes_per_iso, flops_per_iso;
+        int n_head = 0;  // kEmitHead: general ops before the emission run
     };
     std::vector<Seg> segs;
     std::vector<std::pair<int, int>> exec;  // (0, segment) or (1, index into plan.ops)
@@ -1165,7 +1166,47 @@ static int build_grouped_plan(gbs_ctx *ctx) {
                 segs.push_back(piece);
                 o = e;
             }
+            // a few general ops right before an emission run (the excitation and
+            // the first readout's pre map) join it as its head (kEmitHead), so the
+            // state is not written and read once more between them
+            auto head_ok = [&](int q) {
+                const SweepOp &op = sops[q];
+                if (op_need[q] & (kNeedGy | kNeedZ | kNeedRun)) return false;
+                if ((op.flags & kOpRf) && op.rf_axis != 0 && op.rf_axis != 2) return false;
+                if ((op.flags & kOpEmit) && op.emit_axis != 0 && op.emit_axis != 2) return false;
+                return true;
+            };
+            std::vector<int> &pl = pieces[si];
+            for (size_t k = 0; k + 1 < pl.size(); ++k) {
+                GroupedPlan::Seg &h = segs[pl[k]], &r = segs[pl[k + 1]];
+                if ((h.need & kEmitOnly) || !(r.need & kEmitOnly) || (r.need & kEmitHead)) continue;
+                const int n = h.op_end - h.op_begin;
+                int n_em = 0;
+                bool ok = n <= 4;
+                for (int q = h.op_begin; ok && q < h.op_end; ++q) {
+                    ok = head_ok(q);
+                    n_em += (sops[q].flags & kOpEmit) ? 1 : 0;
+                }
+                if (!ok || n_em > 1) continue;
+                r.op_begin = h.op_begin;
+                r.n_head = n;
+                r.need |= h.need | kEmitHead;
+                r.write_m = r.write_m || h.write_m;
+                r.flops_per_iso += h.flops_per_iso;
+                pl.erase(pl.begin() + (long)k);
+            }
         }
+        // keep only the pieces still in use (a merged head's own piece is not)
+        std::vector<GroupedPlan::Seg> used;
+        std::vector<int> renum(segs.size(), -1);
+        for (auto &pl : pieces)
+            for (int &pi : pl) {
+                if (renum[pi] < 0) {
+                    renum[pi] = (int)used.size();
+                    used.push_back(segs[pi]);
+                }
+                pi = renum[pi];
+            }
         std::vector<std::pair<int, int>> exec;
         for (const auto &it : g.exec) {
             if (it.first != 0) {
@@ -1174,7 +1215,7 @@ static int build_grouped_plan(gbs_ctx *ctx) {
             }
             for (int pi : pieces[it.second]) exec.push_back({0, pi});
         }
-        g.segs.swap(segs);
+        g.segs.swap(used);
         g.exec.swap(exec);
     }
 
@@ -1182,12 +1223,23 @@ static int build_grouped_plan(gbs_ctx *ctx) {
     // a complex recurrence when the coefficients step evenly (restarted every
     // 16 emissions to bound FP32 drift).  The kernel keeps the step factor
     // between chains, so a chain with the step of the last one reuses it.
+    // (The head ops of an emission sweep keep their own chains: the emission
+    // kernel starts its recurrence after them.)
+    std::vector<std::pair<int, int>> ranges;
     for (const auto &sg : g.segs) {
+        if (sg.n_head) {
+            ranges.push_back({sg.op_begin, sg.op_begin + sg.n_head});
+            ranges.push_back({sg.op_begin + sg.n_head, sg.op_end});
+        } else {
+            ranges.push_back({sg.op_begin, sg.op_end});
+        }
+    }
+    for (const auto &rg : ranges) {
         double prev = 0.0, step = 0.0, held = 0.0;  // held: step the kernel's factor holds (starts at 1)
         bool have_prev = false, have_step = false;
         int chain = 0;
         std::vector<int> em;
-        for (int o = sg.op_begin; o < sg.op_end; ++o)
+        for (int o = rg.first; o < rg.second; ++o)
             if (sops[o].flags & kOpEmit) em.push_back(o);
         for (size_t e = 0; e < em.size(); ++e) {
             SweepOp &o = sops[em[e]];
@@ -1480,6 +1532,7 @@ static int run_grouped(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out
             a.write_m = sg.write_m ? 1 : 0;
             a.m_final = (final4 && e + 1 == g.exec.size()) ? m_final : nullptr;
             a.fresh = (fresh && e == 0) ? 1 : 0;
+            a.n_head = sg.n_head;
             if (a.m_final || a.fresh) {  // the whole state is written, so all of it is held
                 a.need |= kNeedMz;
                 a.write_m = 1;

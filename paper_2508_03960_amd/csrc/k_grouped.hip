@@ -863,9 +863,10 @@ __device__ __forceinline__ void emit_thread_part(int key, bool uni, float vr, fl
 // in LDS for these chain starts, slot [c][thread]) and then
 // multiplies z_c by the step factor r_c in place, so each further emission
 // costs one complex product and the sum of the z_c per isochromat.  Each
-// emission scales the thread's sum by its x- and z-group factors.  A closed
-// form map that ends the segment (kEmitTail) is applied to the state once,
-// after the emissions.
+// emission scales the thread's sum by its x- and z-group factors.  Ops
+// before the emissions that change the state (kEmitHead: the excitation and
+// the pre map of the first readout) are applied once, first, and a closed
+// form map that ends the segment (kEmitTail) once, after the emissions.
 template <int NI>
 __device__ __forceinline__ void emit_sweep_body(const SweepArgs &a) {
     constexpr int NQ = NI / 4;
@@ -874,15 +875,32 @@ __device__ __forceinline__ void emit_sweep_body(const SweepArgs &a) {
     const int64_t i4 = it * NQ;
     const int need = a.need;
     __shared__ float2 msh[NI][256];
-    float yv[NI], zr[NI], zi[NI], rr[NI], ri[NI];
-    int gx = 0, gz = 0;
+    __shared__ float msz[NI][256];  // Mz after the head ops (kEmitHead)
+    float yv[NI];
+    int gx = 0, gz = 0, gx0 = 0;
+    bool gx_uni = true;
+    const int64_t wave_id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // covers slots 512 wave_id ..
+    // one emission from the thread's sum (pr, pi) of M_c w_c: x- and z-group
+    // factors, then the group sums
+    auto emit_sum = [&](const SweepOp &op, float pr, float pi) {
+        const float4 xv = x_row(op.emit_xtab, gx_uni, gx0, gx);
+        float er = xv.x, ei = xv.y;
+        if (op.emit_ztab) {
+            const float2 zf = gather_row(op.emit_ztab, gz);
+            cmul(er, ei, zf.x, zf.y);
+        }
+        const float sr = er * pr - ei * pi, si = er * pi + ei * pr;
+        if (op.emit_axis == 0 && (need & kPartials))
+            emit_thread_part(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.part + wave_id, op.gsum);
+        else if (op.emit_axis == 0)
+            emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
+        else
+            emit_thread(gz, false, sr, si, act, op.gsum);
+    };
     {
         float mx[NI], my[NI];
 #pragma unroll
-        for (int c = 0; c < NI; ++c) {
-            mx[c] = my[c] = yv[c] = zr[c] = zi[c] = ri[c] = 0.f;
-            rr[c] = 1.f;
-        }
+        for (int c = 0; c < NI; ++c) mx[c] = my[c] = yv[c] = 0.f;
         if (act) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
@@ -895,29 +913,87 @@ __device__ __forceinline__ void emit_sweep_body(const SweepArgs &a) {
             if (need & kNeedGx) gx = a.gid_x[i4].x;
             if (need & kNeedGz) gz = a.gid_z[i4].x;
         }
+        gx0 = __builtin_amdgcn_readfirstlane(gx);
+        gx_uni = __all(!act || gx == gx0) != 0;
+        if (need & kEmitHead) {  // general ops before the emissions, with the whole state in registers
+            float mz[NI], m0[NI];
+#pragma unroll
+            for (int c = 0; c < NI; ++c) mz[c] = m0[c] = 0.f;
+            if (act && (need & kNeedMz)) {
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    ld4(a.m0, i4 + q, m0 + 4 * q);
+                    ld4(a.fresh ? a.m0 : a.mz, i4 + q, mz + 4 * q);
+                }
+            }
+            for (int o = 0; o < a.n_head; ++o) {
+                const SweepOp op = load_op(a.ops, o);
+                if (op.flags & kOpPre) {  // Eq. 4, 5 by group factors and the direct y phase
+                    float fr = 1.f, fi = 0.f, e1 = 1.f;
+                    if (op.pre_xtab) {
+                        const float4 v = x_row(op.pre_xtab, gx_uni, gx0, gx);
+                        fr = v.x;
+                        fi = v.y;
+                        e1 = v.z;
+                    }
+                    if (op.pre_ztab) {
+                        const float2 v = gather_row(op.pre_ztab, gz);
+                        cmul(fr, fi, v.x, v.y);
+                    }
+#pragma unroll
+                    for (int c = 0; c < NI; ++c) {
+                        float ar = fr, ai = fi;
+                        if (op.pre_cy != 0.0) {
+                            float sn, co;
+                            sincos_rev(op.pre_cy * coord64(yv[c]), &sn, &co);
+                            cmul(ar, ai, co, -sn);
+                        }
+                        cmul(mx[c], my[c], ar, ai);
+                        if (op.flags & kPreMz) mz[c] = fmaf(e1, mz[c] - m0[c], m0[c]);
+                    }
+                }
+                if (op.flags & kOpRf) {  // the group's combined transition (Eq. 7)
+                    float4 r0, r1, r2;
+                    if (op.rf_axis == 0 && gx_uni) {
+                        r0 = uniform_row(op.ttab, 3 * gx0);
+                        r1 = uniform_row(op.ttab, 3 * gx0 + 1);
+                        r2 = uniform_row(op.ttab, 3 * gx0 + 2);
+                    } else {
+                        const int g = op.rf_axis == 0 ? gx : gz;
+                        r0 = gather_row(op.ttab, 3 * g);
+                        r1 = gather_row(op.ttab, 3 * g + 1);
+                        r2 = gather_row(op.ttab, 3 * g + 2);
+                    }
+#pragma unroll
+                    for (int c = 0; c < NI; ++c) rf_apply(r0, r1, r2, m0[c], mx[c], my[c], mz[c]);
+                }
+                if (op.flags & kOpEmit) {  // (no chain crosses into the emissions that follow)
+                    float wr[NI], wi[NI];
+#pragma unroll
+                    for (int c = 0; c < NI; ++c) {
+                        float sn = 0.f, co = 1.f;
+                        if (op.flags & kYDirect) sincos_rev(op.emit_cy * coord64(yv[c]), &sn, &co);
+                        wr[c] = mx[c] * co + my[c] * sn;
+                        wi[c] = my[c] * co - mx[c] * sn;
+                    }
+                    emit_sum(op, tree_sum<NI>(wr), tree_sum<NI>(wi));
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NI; ++c) msz[c][threadIdx.x] = mz[c];
+        }
 #pragma unroll
         for (int c = 0; c < NI; ++c) msh[c][threadIdx.x] = make_float2(mx[c], my[c]);
     }
-    const int gx0 = __builtin_amdgcn_readfirstlane(gx);
-    const bool gx_uni = __all(!act || gx == gx0) != 0;
-    const int64_t wave_id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // covers slots 512 wave_id ..
-    auto emit = [&](const SweepOp &op) {
-        const float4 xv = x_row(op.emit_xtab, gx_uni, gx0, gx);
-        float er = xv.x, ei = xv.y;
-        float2 zf = make_float2(1.f, 0.f);
-        if (op.emit_ztab) zf = gather_row(op.emit_ztab, gz);  // used last: its latency overlaps the sum
-        const float pr = tree_sum<NI>(zr), pi = tree_sum<NI>(zi);
-        if (op.emit_ztab) cmul(er, ei, zf.x, zf.y);
-        const float sr = er * pr - ei * pi, si = er * pi + ei * pr;
-        if (op.emit_axis == 0 && (need & kPartials))
-            emit_thread_part(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.part + wave_id, op.gsum);
-        else if (op.emit_axis == 0)
-            emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
-        else
-            emit_thread(gz, false, sr, si, act, op.gsum);
-    };
+    float zr[NI], zi[NI], rr[NI], ri[NI];
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+        zr[c] = zi[c] = ri[c] = 0.f;
+        rr[c] = 1.f;
+    }
+    auto emit = [&](const SweepOp &op) { emit_sum(op, tree_sum<NI>(zr), tree_sum<NI>(zi)); };
     const int n_emit = a.n_ops - ((need & kEmitTail) ? 1 : 0);
-    for (int o = 0; o < n_emit;) {
+    for (int o = (need & kEmitHead) ? a.n_head : 0; o < n_emit;) {
         const SweepOp op = load_op(a.ops, o++);
         if (op.flags & kYDirect) {
 #pragma unroll
@@ -966,7 +1042,10 @@ __device__ __forceinline__ void emit_sweep_body(const SweepArgs &a) {
         my[c] = m.y;
         mz[c] = m0[c] = 0.f;
     }
-    if (need & kNeedMz) {  // Mz is unchanged: (0, 0, M0) or as read
+    if (need & kEmitHead) {  // Mz as the head ops left it
+#pragma unroll
+        for (int c = 0; c < NI; ++c) mz[c] = msz[c][threadIdx.x];
+    } else if (need & kNeedMz) {  // Mz is unchanged: (0, 0, M0) or as read
 #pragma unroll
         for (int q = 0; q < NQ; ++q) ld4(a.fresh ? a.m0 : a.mz, i4 + q, mz + 4 * q);
     }

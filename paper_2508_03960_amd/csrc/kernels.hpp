@@ -94,6 +94,10 @@ enum { kNeedMz = 1, kNeedGx = 2, kNeedGy = 4, kNeedGz = 8, kNeedY = 16, kNeedZ =
 // op of such a segment is a B1 = 0 map without transition or emission (the
 // closed form that ends the sequence), applied after the emissions.
 enum { kEmitOnly = 128, kEmitTail = 256 };
+// kEmitHead: the first SweepArgs::n_head ops of such a segment are general
+// ops (pre map, x- or z-group transition, emission without a stepped y phase)
+// applied to the state before the emissions.
+enum { kEmitHead = 2048 };
 // kPartials: the x-group sums of the segment's emissions go to per-wavefront
 // partial sums (SweepOp::part) instead of memory-side atomics: lane 63 of a
 // wavefront of 512 isochromats (8 per thread) stores (sum of its first
@@ -127,6 +131,7 @@ struct SweepArgs {
     // First sweep of a run from the default state (0, 0, M0): nothing is read
     // from mx / my / mz.
     int32_t fresh;
+    int32_t n_head;  // kEmitHead
     // Receive-coil sensitivities (Eq. 6 with S(k, p)), or null for one coil of
     // unit sensitivity: planes re, im of coil 0, re, im of coil 1, ... of
     // coil_plane float4 words each in layout order.  Every emission weights

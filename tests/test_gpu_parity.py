@@ -190,14 +190,19 @@ def test_two_axis_groups(gb):
 
 
 def test_emission_runs(gb):
-    """Runs of 16 or more emissions that leave the state alone sweep on their
-    own (the emission-only kernel): an EPI with 24 lines, and readouts before
-    any RF, from (0, 0, M0) and from a given state."""
+    """Runs of 16 or more emissions that leave the state alone sweep in the
+    emission-only kernel, with the few ops before them (the excitation, the
+    first readout's pre map) as its head and the final map as its tail: an
+    EPI with 24 lines is one sweep; an EPI with 12 lines (too short a run) and
+    readouts before any RF, from (0, 0, M0) and from a given state."""
     ph = synth.brain_like_phantom(48, 40, 3)
     epi = synth.epi_sequence(n_lines=24, n_read=32, rf_steps=1000)
     check_case(gb, "epi24", ph, epi, modes=("grouped",))
     _, _, st = run_gpu(gb, ph, epi, gb.GBS_GROUPED)
-    assert st["n_sweeps"] >= 2, st
+    assert st["n_sweeps"] == 1, st
+    check_case(gb, "epi12", ph, synth.epi_sequence(n_lines=12, n_read=32, rf_steps=1000), modes=("grouped",))
+    m_init = np.random.default_rng(13).uniform(-0.5, 0.5, (3, ph.K))
+    check_case(gb, "epi24+m_init", ph, epi, modes=("grouped",), m_init=m_init)
     sb = SeqBuilder(1e-6, "readouts-first")
     for i in range(20):
         sb.adc(32, (0.01 * (-1) ** i, 0, 0), 4 * np.arange(8) + 2)
