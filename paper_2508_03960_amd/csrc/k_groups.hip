@@ -5,12 +5,27 @@
 // 32-bit words, packed as two 64-bit halves and sorted with two stable LSD
 // radix passes (low half, then high half), carrying the isochromat index.
 // Equal neighbours share a group id; ids are dense in lexicographic key order.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "groups.hpp"
 #include "kernels.hpp"
 
 namespace gbs {
+
+// rocPRIM device primitives on int32 counts (stable LSD radix sort of 64-bit
+// keys with an int32 payload; inclusive and exclusive sums).  With tmp null
+// they report the temporary bytes they need in *bytes.
+static hipError_t sort_pairs(void *tmp, size_t *bytes, const uint64_t *kin, uint64_t *kout, const int32_t *vin,
+                             int32_t *vout, int64_t n, hipStream_t st) {
+    return rocprim::radix_sort_pairs(tmp, *bytes, kin, kout, vin, vout, (unsigned int)n, 0u, 64u, st);
+}
+static hipError_t inclusive_sum(void *tmp, size_t *bytes, const int32_t *in, int32_t *out, int64_t n, hipStream_t st) {
+    return rocprim::inclusive_scan(tmp, *bytes, in, out, (size_t)n, rocprim::plus<int32_t>(), st);
+}
+static hipError_t exclusive_sum(void *tmp, size_t *bytes, const int32_t *in, int32_t *out, int64_t n, hipStream_t st) {
+    return rocprim::exclusive_scan(tmp, *bytes, in, out, (int32_t)0, (size_t)n, rocprim::plus<int32_t>(), st);
+}
 
 __device__ __forceinline__ uint32_t ordered_bits(float f) {
     const uint32_t u = __float_as_uint(f + 0.0f);  // -0 -> +0
@@ -235,16 +250,15 @@ hipError_t build_layout(int64_t K, const int32_t *gid_x, const int32_t *gid_z, v
     hipError_t e;
     hipLaunchKernelGGL(k_pair_keys, g, dim3(256), 0, st, K, gid_x, gid_z, key, idx);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key, key2, idx, order, (int)K, 0, 64, st)) != hipSuccess)
-        return e;
+    if ((e = sort_pairs(tmp, &tmp_bytes, key, key2, idx, order, K, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_key_heads, g, dim3(256), 0, st, K, key2, flag);
-    if ((e = hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, flag, rid, (int)K, st)) != hipSuccess) return e;
+    if ((e = inclusive_sum(tmp, &tmp_bytes, flag, rid, K, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_run_start, g, dim3(256), 0, st, K, rid, rstart);
     int32_t R = 0;
     if ((e = hipMemcpyAsync(&R, rid + (K - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_run_plen, grid_for(R), dim3(256), 0, st, (int64_t)R, K, rstart, plen);
-    if ((e = hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, plen, pstart, (int)R, st)) != hipSuccess) return e;
+    if ((e = exclusive_sum(tmp, &tmp_bytes, plen, pstart, R, st)) != hipSuccess) return e;
     int32_t last[2] = {0, 0};
     if ((e = hipMemcpyAsync(&last[0], pstart + (R - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
         return e;
@@ -278,13 +292,9 @@ hipError_t launch_zero_padding(int64_t n, const int32_t *perm, float *m0, hipStr
 
 size_t group_scratch_bytes(int64_t K) {
     size_t sort_tmp = 0, scan_tmp = 0, escan_tmp = 0;
-    const bool sized =
-        hipcub::DeviceRadixSort::SortPairs(nullptr, sort_tmp, (const uint64_t *)nullptr, (uint64_t *)nullptr,
-                                           (const int32_t *)nullptr, (int32_t *)nullptr, (int)K, 0, 64) == hipSuccess &&
-        hipcub::DeviceScan::InclusiveSum(nullptr, scan_tmp, (const int32_t *)nullptr, (int32_t *)nullptr, (int)K) ==
-            hipSuccess &&
-        hipcub::DeviceScan::ExclusiveSum(nullptr, escan_tmp, (const int32_t *)nullptr, (int32_t *)nullptr, (int)K) ==
-            hipSuccess;
+    const bool sized = sort_pairs(nullptr, &sort_tmp, nullptr, nullptr, nullptr, nullptr, K, 0) == hipSuccess &&
+                       inclusive_sum(nullptr, &scan_tmp, nullptr, nullptr, K, 0) == hipSuccess &&
+                       exclusive_sum(nullptr, &escan_tmp, nullptr, nullptr, K, 0) == hipSuccess;
     size_t tmp = sort_tmp > scan_tmp ? sort_tmp : scan_tmp;
     if (escan_tmp > tmp) tmp = escan_tmp;
     // a failed size query leaves generous room; the sorts and scans report their own errors
@@ -319,17 +329,15 @@ hipError_t group_axis(int64_t K, const float *coord, const float *t1, const floa
     hipLaunchKernelGGL(k_keys, g, dim3(256), 0, st, K, coord, t1, t2, df, hi, lo, idx0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // LSD: low half first (carry indices), then the high half of the same records.
-    if ((e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, lo, k2, idx0, idx1, (int)K, 0, 64, st)) != hipSuccess)
-        return e;
+    if ((e = sort_pairs(tmp, &tmp_bytes, lo, k2, idx0, idx1, K, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather_u64, g, dim3(256), 0, st, K, hi, idx1, k3);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, k3, hi, idx1, order, (int)K, 0, 64, st)) != hipSuccess)
-        return e;
+    if ((e = sort_pairs(tmp, &tmp_bytes, k3, hi, idx1, order, K, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_gather_u64, g, dim3(256), 0, st, K, lo, order, k2);  // low half in final order
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_heads, g, dim3(256), 0, st, K, hi, k2, flag);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, flag, idx0, (int)K, st)) != hipSuccess) return e;
+    if ((e = inclusive_sum(tmp, &tmp_bytes, flag, idx0, K, st)) != hipSuccess) return e;
     int32_t *gstart = idx1;  // the first sort's payload is no longer needed
     hipLaunchKernelGGL(k_assign, g, dim3(256), 0, st, K, idx0, order, coord, t1, t2, df, gid_nat, gtab, gstart);
     if ((e = hipGetLastError()) != hipSuccess) return e;
