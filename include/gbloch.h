@@ -71,7 +71,6 @@ extern "C" {
 #define GBS_GROUPED 1
 #define GBS_CACHED 2
 #define GBS_ASYNC 1u      /* enqueue on the context stream and return; no final synchronize */
-#define GBS_PLAIN_FP32 2u /* GBS_PLAIN: step in FP32 instead of FP64 (faster to state, less exact) */
 #define GBS_PROFILE 4u    /* time every sweep launch with HIP events (gbs_stats.pass_kernel_ms) */
 #define GBS_SURROGATE 8u  /* GBS_GROUPED: transitions of RF blocks that match the attached surrogate's
                              pulse come from the network, with the spot-check fallback (gbs_set_surrogate) */
@@ -257,7 +256,10 @@ int gbs_workspace_size(gbs_ctx *ctx, int mode, size_t *bytes);
  * sig_out: device double[2*n_coils*total_samples], interleaved (re, im), Eq. (6),
  *          coil-major (row p holds coil p; n_coils = 1 without gbs_set_coils).
  * stats: host, nullable.  Without GBS_ASYNC the call synchronizes the stream.
- * GBS_PLAIN and GBS_CACHED keep the state between launches in FP64.
+ * GBS_PLAIN steps in FP64 (state and per-step coefficients; in FP32 the
+ * rounded coefficients of a constant-gradient readout err the same way at
+ * every step, far beyond 1e-5 of M over a long sequence).  GBS_PLAIN and
+ * GBS_CACHED keep the state between launches in FP64.
  * GBS_CACHED recomposes its transition cache (3 float4 rows (A_i0, A_i1,
  * A_i2, b_i) of K per distinct with-RF waveform: bit-identical B1 and
  * gradients) in every call.  With-ADC blocks that play RF are stepped per

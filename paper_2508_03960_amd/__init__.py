@@ -22,7 +22,6 @@ GBS_AX_X, GBS_AX_Y, GBS_AX_Z, GBS_AX_N, GBS_AX_XZ = 1, 2, 4, 8, 16
 GBS_AX_ALL = GBS_AX_X | GBS_AX_Y | GBS_AX_Z | GBS_AX_N | GBS_AX_XZ
 GBS_PLAIN, GBS_GROUPED, GBS_CACHED = 0, 1, 2
 GBS_ASYNC = 1
-GBS_PLAIN_FP32 = 2
 GBS_PROFILE = 4
 GBS_SURROGATE = 8
 GBS_MLP_PARAMS = 35340

@@ -680,13 +680,13 @@ static int32_t step_samples(const gbs_ctx *ctx) {
 // One stepping launch with its samples: the coil sums when the context has coil
 // maps (sensitivities of the launch's isochromats: re + p * stride), then one
 // finalize per coil into row p of the signal.
-static int launch_steps(gbs_ctx *ctx, const PlainArgs &a, bool b1, bool fp32, int grid, const float *cre,
+static int launch_steps(gbs_ctx *ctx, const PlainArgs &a, bool b1, int grid, const float *cre,
                         const float *cim, int64_t cstride, double *sig_out, int64_t first_sample) {
     const int32_t P = ctx->coil_re ? ctx->n_coils : 1;
     if (ctx->coil_re && a.n_samples > 0)
-        HIPCHK(launch_plain_coils(a, PlainCoils{cre, cim, cstride, P}, b1, fp32, grid, ctx->stream));
+        HIPCHK(launch_plain_coils(a, PlainCoils{cre, cim, cstride, P}, b1, grid, ctx->stream));
     else
-        HIPCHK(launch_plain(a, b1, fp32, grid, ctx->stream));
+        HIPCHK(launch_plain(a, b1, grid, ctx->stream));
     for (int32_t p = 0; p < P && a.n_samples > 0; ++p)
         HIPCHK(launch_plain_finalize(ctx->partial + (size_t)p * grid * a.n_samples, grid, a.n_samples,
                                      sig_out + 2 * ((int64_t)p * ctx->seq.total_samples + first_sample), ctx->stream));
@@ -714,8 +714,7 @@ static size_t plain_ws(const gbs_ctx *ctx, size_t *o_partial, size_t *o_state) {
     return w.off;
 }
 
-static int run_plain(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out, double *sig_out, bool fp32,
-                     gbs_stats *st) {
+static int run_plain(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out, double *sig_out, gbs_stats *st) {
     const int64_t K = ctx->K;
     const Plan &plan = ctx->pplan;
     const int grid = plain_grid(K);
@@ -723,10 +722,10 @@ static int run_plain(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out, 
     plain_ws(ctx, &o_partial, &o_state);
     ctx->partial = (double2 *)(ws + o_partial);
     float *ox = m_out, *oy = m_out + K, *oz = m_out + 2 * K;
-    // the FP64 stepper keeps its state in FP64 between launches and rounds
-    // to the FP32 output once, in the last launch
+    // the state stays in FP64 between launches and is rounded to the FP32
+    // output once, in the last launch
     double *sx = nullptr, *sy = nullptr, *sz = nullptr;
-    if (!fp32 && plan.ops.size() > 1) {
+    if (plan.ops.size() > 1) {
         sx = (double *)(ws + o_state);
         sy = sx + K;
         sz = sx + 2 * K;
@@ -755,7 +754,7 @@ static int run_plain(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out, 
         }
         const bool b1 = op.step.block >= 0 && ctx->cls[op.step.block].has_b1;
         const int64_t s0 = op.step.block >= 0 ? ctx->seq.blocks[op.step.block].sample_offset + op.step.sample_lo : 0;
-        if (int rc = launch_steps(ctx, a, b1, fp32, grid, ctx->coil_re, ctx->coil_im, K, sig_out, s0)) return rc;
+        if (int rc = launch_steps(ctx, a, b1, grid, ctx->coil_re, ctx->coil_im, K, sig_out, s0)) return rc;
         first = false;
     }
     if (st) st->n_fallback = 0;
@@ -1554,7 +1553,7 @@ static int run_grouped(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out
             const int64_t s0 = op.step.block >= 0 ? s.blocks[op.step.block].sample_offset + op.step.sample_lo : 0;
             const float *cl = ctx->coil_re ? ctx->coil_l.as<float>() : nullptr;  // planes re, im per coil
             const int64_t Kp = ctx->Kpad;
-            if (int rc = launch_steps(ctx, a, b1, false, grid, cl, cl ? cl + Kp : nullptr, 2 * Kp, sig_out, s0))
+            if (int rc = launch_steps(ctx, a, b1, grid, cl, cl ? cl + Kp : nullptr, 2 * Kp, sig_out, s0))
                 return rc;
         }
     }
@@ -1692,7 +1691,7 @@ static int run_cached(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out,
             a.mout64_y = s64 + K;
             a.mout64_z = s64 + 2 * K;
             const int64_t s0 = ctx->seq.blocks[op.step.block].sample_offset + op.step.sample_lo;
-            if (int rc = launch_steps(ctx, a, ctx->cls[op.step.block].has_b1, false, pgrid, ctx->coil_re, ctx->coil_im,
+            if (int rc = launch_steps(ctx, a, ctx->cls[op.step.block].has_b1, pgrid, ctx->coil_re, ctx->coil_im,
                                       K, sig_out, s0))
                 return rc;
             from_init = false;
@@ -1827,7 +1826,7 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, void *worksp
     if (!m_out || (ctx->seq.total_samples > 0 && !sig_out)) return fail(ctx, GBS_E_INVALID, "null output");
     if (mode == GBS_GROUPED && !ctx->groups_valid)
         return fail(ctx, GBS_E_STATE, "GBS_GROUPED needs gbs_build_groups on the current phantom");
-    if (flags & ~(GBS_ASYNC | GBS_PLAIN_FP32 | GBS_PROFILE | GBS_SURROGATE))
+    if (flags & ~(GBS_ASYNC | GBS_PROFILE | GBS_SURROGATE))
         return fail(ctx, GBS_E_INVALID, "unknown flags");
     const bool use_surr = (flags & GBS_SURROGATE) != 0;
     if (use_surr && (mode != GBS_GROUPED || !ctx->mlp))
@@ -1850,7 +1849,7 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, void *worksp
         HIPCHK(launch_fill_f64(sig_out, 2 * (int64_t)ctx->n_coils * ctx->seq.total_samples, ctx->stream));
     const bool profile = (flags & GBS_PROFILE) != 0;
     int n_timed = 0;
-    int rc = mode == GBS_PLAIN ? run_plain(ctx, ws, m_init, m_out, sig_out, (flags & GBS_PLAIN_FP32) != 0, stats)
+    int rc = mode == GBS_PLAIN ? run_plain(ctx, ws, m_init, m_out, sig_out, stats)
              : mode == GBS_CACHED ? run_cached(ctx, ws, m_init, m_out, sig_out, profile, stats, &n_timed)
                                   : run_grouped(ctx, ws, m_init, m_out, sig_out, profile, use_surr, stats, &n_timed);
     if (rc != GBS_OK) return rc;

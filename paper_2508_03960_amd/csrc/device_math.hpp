@@ -51,12 +51,4 @@ __device__ __forceinline__ double wave_sum_lane63_f64(double v) {
     return v;
 }
 
-// Compensated (Kahan) accumulation of x into (sum, comp).
-__device__ __forceinline__ void kahan_add(float &sum, float &comp, float x) {
-    const float y = x - comp;
-    const float t = sum + y;
-    comp = (t - sum) - y;
-    sum = t;
-}
-
 }  // namespace gbs

@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void k_compose_pair(int64_t n_runs, const floa
         const double bz = fma((double)w.gx, X, fma((double)w.gz, Z, boff));
         const double B2 = fma(bx, bx, fma(by, by, bz * bz));
         double ca, cb;  // R = (1 - cb |B|^2) I + ca [B]x + cb B B^T
-        rot_coeffs<double>(B2, gdt, k2, ca, cb);
+        rot_coeffs(B2, gdt, k2, ca, cb);
         const double c0 = fma(-cb, B2, 1.0);
         const double qx = cb * bx, qy = cb * by, qz = cb * bz;
         const double pxy = qx * by, pxz = qx * bz, pyz = qy * bz;

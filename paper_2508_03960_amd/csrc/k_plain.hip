@@ -12,15 +12,17 @@
 // R = I falls out at B = 0); relaxation as M -= (1 - E) M with
 // 1 - E = -expm1(-dt/T) computed once per isochromat.
 //
-// The arithmetic type R is double by default and float on request.  In float
-// the rounded per-step coefficients bias every step of a constant-gradient
-// readout the same way (about 1e-8 per step), which over tens of thousands of
-// steps exceeds 1e-5; the double version keeps the state exact to ~1e-12 at
-// the same FMA rate (packed FP32 is not used on this target).
+// The state and every coefficient are FP64.  In FP32 the rounded per-step
+// coefficients turn the same rounding into an angle error at every step of a
+// constant-gradient readout (about 1e-8 of the angle per step), which adds up
+// coherently over tens of thousands of steps to far more than 1e-5 of M;
+// removing that with compensated FP32 arithmetic (double-float coefficients
+// and a compensated state) costs more instructions than FP64, which issues at
+// the non-packed FP32 rate on this target.
 //
 // ADC samples (Eq. 6): at each sample boundary a wavefront sums its lanes with
-// DPP, lane 63 adds the wave total into a per-wave LDS accumulator
-// (compensated FP32, or FP64); at the end each workgroup writes one FP64
+// DPP, lane 63 adds the wave total into a per-wave FP64 LDS accumulator;
+// at the end each workgroup writes one FP64
 // partial per sample, and a finalize kernel (one workgroup per sample) adds
 // the partials in a fixed order.
 #include "device_math.hpp"
@@ -34,24 +36,8 @@ constexpr int kPlainBlock = 256;
 constexpr int kIso = 2;
 constexpr int kTile = kPlainBlock * kIso;
 
-// Per-wave ADC accumulator in LDS: compensated FP32, or plain FP64.
-template <typename R>
-struct SampleAcc;
-
-template <>
-struct SampleAcc<float> {
-    float4 v;  // (sum re, comp re, sum im, comp im)
-    static __device__ __forceinline__ void add(SampleAcc &a, float x, float y) {
-        kahan_add(a.v.x, a.v.y, x);
-        kahan_add(a.v.z, a.v.w, y);
-    }
-    __device__ __forceinline__ double re() const { return (double)v.x - (double)v.y; }
-    __device__ __forceinline__ double im() const { return (double)v.z - (double)v.w; }
-    static __device__ __forceinline__ float wave_sum(float x) { return wave_sum_lane63(x); }
-};
-
-template <>
-struct SampleAcc<double> {
+// Per-wave ADC accumulator in LDS (FP64).
+struct SampleAcc {
     double2 v;
     static __device__ __forceinline__ void add(SampleAcc &a, double x, double y) {
         a.v.x += x;
@@ -62,16 +48,10 @@ struct SampleAcc<double> {
     static __device__ __forceinline__ double wave_sum(double x) { return wave_sum_lane63_f64(x); }
 };
 
-template <typename R>
-__device__ __forceinline__ R fmaR(R a, R b, R c);
-template <>
-__device__ __forceinline__ float fmaR<float>(float a, float b, float c) { return fmaf(a, b, c); }
-template <>
-__device__ __forceinline__ double fmaR<double>(double a, double b, double c) { return fma(a, b, c); }
-
-template <typename R, bool HAS_B1, bool COILS>
+template <bool HAS_B1, bool COILS>
 __global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a, PlainCoils cl) {
-    using Acc = SampleAcc<R>;
+    using R = double;
+    using Acc = SampleAcc;
     constexpr int MC = COILS ? kPlainMaxCoils : 1;
     extern __shared__ char lds_raw[];
     Acc *acc = reinterpret_cast<Acc *>(lds_raw);  // [4 waves][n_samples][coils]
@@ -82,7 +62,7 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a, PlainCoils c
     const int P = COILS ? cl.n : 1;
     for (int i = tid; i < 4 * ns * P; i += kPlainBlock) acc[i] = Acc{};
     __syncthreads();
-    const R gdt = (R)a.gdt;
+    const R gdt = a.gdt;
     const R k2 = gdt * gdt;
     const StepW *__restrict__ wave_ptr = a.wave;
     const int32_t *__restrict__ sidx = a.sidx;
@@ -128,20 +108,20 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a, PlainCoils c
                     vy = ny;
                     vz = m0 + (vz - m0) * e1;
                 }
-                X[i] = (R)x;
-                Y[i] = (R)y;
-                Z[i] = (R)z;
-                M0[i] = (R)m0;
-                boff[i] = (R)(df / kGammaBar);
-                e1m[i] = (R)(-expm1(-a.dt / t1));
-                e2m[i] = (R)(-expm1(-a.dt / t2));
-                mx[i] = (R)vx;
-                my[i] = (R)vy;
-                mz[i] = (R)vz;
+                X[i] = x;
+                Y[i] = y;
+                Z[i] = z;
+                M0[i] = m0;
+                boff[i] = df / kGammaBar;
+                e1m[i] = -expm1(-a.dt / t1);
+                e2m[i] = -expm1(-a.dt / t2);
+                mx[i] = vx;
+                my[i] = vy;
+                mz[i] = vz;
             } else {
-                X[i] = Y[i] = Z[i] = R(0);
-                boff[i] = e1m[i] = e2m[i] = M0[i] = R(0);
-                mx[i] = my[i] = mz[i] = R(0);
+                X[i] = Y[i] = Z[i] = 0.0;
+                boff[i] = e1m[i] = e2m[i] = M0[i] = 0.0;
+                mx[i] = my[i] = mz[i] = 0.0;
             }
         }
 
@@ -151,47 +131,47 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a, PlainCoils c
 #pragma unroll 2
             for (; j < jend; ++j) {
                 const StepW w = wave_ptr[j];
-                const R b1r = (R)w.b1r, b1i = (R)w.b1i, b1sq = (R)w.b1sq;
-                const R gx = (R)w.gx, gy = (R)w.gy, gz = (R)w.gz;
+                const R b1r = w.b1r, b1i = w.b1i, b1sq = w.b1sq;
+                const R gx = w.gx, gy = w.gy, gz = w.gz;
 #pragma unroll
                 for (int i = 0; i < kIso; ++i) {
-                    const R bz = fmaR(gx, X[i], fmaR(gy, Y[i], fmaR(gz, Z[i], boff[i])));
+                    const R bz = fma(gx, X[i], fma(gy, Y[i], fma(gz, Z[i], boff[i])));
                     R ca, cb;
                     if (HAS_B1) {
-                        const R B2 = fmaR(bz, bz, b1sq);
-                        rot_coeffs<R>(B2, gdt, k2, ca, cb);
+                        const R B2 = fma(bz, bz, b1sq);
+                        rot_coeffs(B2, gdt, k2, ca, cb);
                         const R cx = b1i * mz[i] - bz * my[i];
                         const R cy = bz * mx[i] - b1r * mz[i];
                         const R cz = b1r * my[i] - b1i * mx[i];
-                        const R d = fmaR(b1r, mx[i], fmaR(b1i, my[i], bz * mz[i]));
-                        const R dx = fmaR(ca, cx, cb * fmaR(b1r, d, -B2 * mx[i]));
-                        const R dy = fmaR(ca, cy, cb * fmaR(b1i, d, -B2 * my[i]));
-                        const R dz = fmaR(ca, cz, cb * fmaR(bz, d, -B2 * mz[i]));
+                        const R d = fma(b1r, mx[i], fma(b1i, my[i], bz * mz[i]));
+                        const R dx = fma(ca, cx, cb * fma(b1r, d, -B2 * mx[i]));
+                        const R dy = fma(ca, cy, cb * fma(b1i, d, -B2 * my[i]));
+                        const R dz = fma(ca, cz, cb * fma(bz, d, -B2 * mz[i]));
                         mx[i] += dx;
                         my[i] += dy;
                         mz[i] += dz;
                     } else {  // B = (0, 0, bz): rotation about z
                         const R B2 = bz * bz;
-                        rot_coeffs<R>(B2, gdt, k2, ca, cb);
+                        rot_coeffs(B2, gdt, k2, ca, cb);
                         const R p = ca * bz, r = cb * B2;
-                        const R nx = fmaR(-p, my[i], fmaR(-r, mx[i], mx[i]));
-                        const R ny = fmaR(p, mx[i], fmaR(-r, my[i], my[i]));
+                        const R nx = fma(-p, my[i], fma(-r, mx[i], mx[i]));
+                        const R ny = fma(p, mx[i], fma(-r, my[i], my[i]));
                         mx[i] = nx;
                         my[i] = ny;
                     }
-                    mx[i] = fmaR(-e2m[i], mx[i], mx[i]);  // D: T2 decay, T1 recovery
-                    my[i] = fmaR(-e2m[i], my[i], my[i]);
-                    mz[i] = fmaR(e1m[i], M0[i] - mz[i], mz[i]);
+                    mx[i] = fma(-e2m[i], mx[i], mx[i]);  // D: T2 decay, T1 recovery
+                    my[i] = fma(-e2m[i], my[i], my[i]);
+                    mz[i] = fma(e1m[i], M0[i] - mz[i], mz[i]);
                 }
             }
             if (n < ns && COILS) {  // one sum per coil: S(k, p) (Mx + i My)
 #pragma unroll
                 for (int p = 0; p < MC; ++p) {
                     if (p >= P) break;
-                    R vx = R(0), vy = R(0);
+                    R vx = 0.0, vy = 0.0;
 #pragma unroll
                     for (int i = 0; i < kIso; ++i) {
-                        const R sr = (R)csr[p][i], si = (R)csi[p][i];
+                        const R sr = csr[p][i], si = csi[p][i];
                         vx += mx[i] * sr - my[i] * si;
                         vy += mx[i] * si + my[i] * sr;
                     }
@@ -276,38 +256,23 @@ int plain_grid(int64_t K) {
     return (int)(tiles < cap ? (tiles > 0 ? tiles : 1) : cap);
 }
 
-hipError_t launch_plain(const PlainArgs &a, bool has_b1, bool fp32, int grid, hipStream_t st) {
-    const size_t lds = 16 * 4 * (size_t)a.n_samples;  // both accumulator types are 16 bytes
+hipError_t launch_plain(const PlainArgs &a, bool has_b1, int grid, hipStream_t st) {
+    const size_t lds = sizeof(SampleAcc) * 4 * (size_t)a.n_samples;
     const PlainCoils none{nullptr, nullptr, 0, 1};
-    if (fp32) {
-        if (has_b1)
-            hipLaunchKernelGGL((k_plain<float, true, false>), dim3(grid), dim3(kPlainBlock), lds, st, a, none);
-        else
-            hipLaunchKernelGGL((k_plain<float, false, false>), dim3(grid), dim3(kPlainBlock), lds, st, a, none);
-    } else {
-        if (has_b1)
-            hipLaunchKernelGGL((k_plain<double, true, false>), dim3(grid), dim3(kPlainBlock), lds, st, a, none);
-        else
-            hipLaunchKernelGGL((k_plain<double, false, false>), dim3(grid), dim3(kPlainBlock), lds, st, a, none);
-    }
+    if (has_b1)
+        hipLaunchKernelGGL((k_plain<true, false>), dim3(grid), dim3(kPlainBlock), lds, st, a, none);
+    else
+        hipLaunchKernelGGL((k_plain<false, false>), dim3(grid), dim3(kPlainBlock), lds, st, a, none);
     return hipGetLastError();
 }
 
-hipError_t launch_plain_coils(const PlainArgs &a, const PlainCoils &c, bool has_b1, bool fp32, int grid,
-                              hipStream_t st) {
+hipError_t launch_plain_coils(const PlainArgs &a, const PlainCoils &c, bool has_b1, int grid, hipStream_t st) {
     if (!c.re || !c.im || c.n < 1 || c.n > kPlainMaxCoils || a.n_samples * c.n > 256) return hipErrorInvalidValue;
-    const size_t lds = 16 * 4 * (size_t)a.n_samples * (size_t)c.n;
-    if (fp32) {
-        if (has_b1)
-            hipLaunchKernelGGL((k_plain<float, true, true>), dim3(grid), dim3(kPlainBlock), lds, st, a, c);
-        else
-            hipLaunchKernelGGL((k_plain<float, false, true>), dim3(grid), dim3(kPlainBlock), lds, st, a, c);
-    } else {
-        if (has_b1)
-            hipLaunchKernelGGL((k_plain<double, true, true>), dim3(grid), dim3(kPlainBlock), lds, st, a, c);
-        else
-            hipLaunchKernelGGL((k_plain<double, false, true>), dim3(grid), dim3(kPlainBlock), lds, st, a, c);
-    }
+    const size_t lds = sizeof(SampleAcc) * 4 * (size_t)a.n_samples * (size_t)c.n;
+    if (has_b1)
+        hipLaunchKernelGGL((k_plain<true, true>), dim3(grid), dim3(kPlainBlock), lds, st, a, c);
+    else
+        hipLaunchKernelGGL((k_plain<false, true>), dim3(grid), dim3(kPlainBlock), lds, st, a, c);
     return hipGetLastError();
 }
 

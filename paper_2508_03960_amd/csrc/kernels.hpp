@@ -199,7 +199,7 @@ struct AdcJobDev {
 };
 
 // ---- launchers (all asynchronous on `st`) -----------------------------------
-hipError_t launch_plain(const PlainArgs &a, bool has_b1, bool fp32, int grid, hipStream_t st);
+hipError_t launch_plain(const PlainArgs &a, bool has_b1, int grid, hipStream_t st);
 hipError_t launch_plain_finalize(const double2 *partial, int nblk, int n_samples, double *sig,
                                  hipStream_t st);
 int plain_grid(int64_t K);

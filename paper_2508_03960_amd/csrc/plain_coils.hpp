@@ -19,7 +19,6 @@ struct PlainCoils {
 
 // k_plain with coil sums: every sample of the launch gets one sum per coil,
 // written as partials [coil][grid][n_samples]; needs n_samples * n <= 256.
-hipError_t launch_plain_coils(const PlainArgs &a, const PlainCoils &c, bool has_b1, bool fp32, int grid,
-                              hipStream_t st);
+hipError_t launch_plain_coils(const PlainArgs &a, const PlainCoils &c, bool has_b1, int grid, hipStream_t st);
 
 }  // namespace gbs

@@ -9,37 +9,9 @@ namespace gbs {
 // Rotation coefficients of one step:
 //   a = sin(theta)/|B| = -gdt * S(q),  b = (1 - cos theta)/|B|^2 = gdt^2 * C(q),
 //   S(q) = sum_n (-q)^n / (2n+1)!,  C(q) = sum_n (-q)^n / (2n+2)!,  q = theta^2.
-// For q <= 1 the series is truncated where the next term is below the
-// precision of R (n <= 5 for float, n <= 8 for double); larger angles use
-// sqrt and sincos.
-template <typename R>
-struct Series;
-
-template <>
-struct Series<float> {
-    static __device__ __forceinline__ void coeffs(float q, float &S, float &C) {
-        S = fmaf(q, -2.5052108385441719e-8f, 2.7557319223985891e-6f);
-        S = fmaf(q, S, -1.9841269841269841e-4f);
-        S = fmaf(q, S, 8.3333333333333333e-3f);
-        S = fmaf(q, S, -1.6666666666666667e-1f);
-        S = fmaf(q, S, 1.0f);
-        C = fmaf(q, -2.0876756987868099e-9f, 2.7557319223985891e-7f);
-        C = fmaf(q, C, -2.4801587301587302e-5f);
-        C = fmaf(q, C, 1.3888888888888889e-3f);
-        C = fmaf(q, C, -4.1666666666666667e-2f);
-        C = fmaf(q, C, 0.5f);
-    }
-    static __device__ __forceinline__ void big(float B2, float gdt, float &a, float &b) {
-        const float nb = sqrtf(B2);
-        float sh, ch;
-        sincosf(0.5f * gdt * nb, &sh, &ch);
-        a = -2.0f * sh * ch / nb;
-        b = 2.0f * sh * sh / B2;
-    }
-};
-
-template <>
-struct Series<double> {
+// For q <= 1 the series is truncated where the next term is below double
+// precision (n <= 8); larger angles use sqrt and sincos.  FP64 throughout.
+struct Series {
     static __device__ __forceinline__ void coeffs(double q, double &S, double &C) {
         S = fma(q, 8.2206352466243297e-18, -2.8114572543455208e-15);  // 1/19!, -1/17!
         S = fma(q, S, 7.6471637318198164e-13);                         // 1/15!
@@ -69,16 +41,15 @@ struct Series<double> {
     }
 };
 
-template <typename R>
-__device__ __forceinline__ void rot_coeffs(R B2, R gdt, R k2, R &a, R &b) {
-    const R q = k2 * B2;
-    if (q <= R(1)) {
-        R S, C;
-        Series<R>::coeffs(q, S, C);
+__device__ __forceinline__ void rot_coeffs(double B2, double gdt, double k2, double &a, double &b) {
+    const double q = k2 * B2;
+    if (q <= 1.0) {
+        double S, C;
+        Series::coeffs(q, S, C);
         a = -gdt * S;
         b = k2 * C;
     } else {
-        Series<R>::big(B2, gdt, a, b);
+        Series::big(B2, gdt, a, b);
     }
 }
 
