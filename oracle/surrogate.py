@@ -11,9 +11,23 @@ nothing here is shared with or imported by the GPU library.
 * ``frame`` -- K = P(-a) A P(-a), k_b = P(-a) b with P the z rotation of
   Eq. A2 and a = -2 pi (f_z + f_B0) tau / 2 (the pulse's free precession over
   each half removed), and its inverse.
+* ``reference_table`` / ``reference`` -- the reference transition K_ref that
+  the network corrects.  The table holds the relaxation-free transition of
+  the pulse at B1 scale 1 in the frame above (a rotation) on a uniform grid
+  of f = f_z + f_B0, as rotation angle theta(f) and unit axis n(f) (from its
+  unit quaternion, signs chosen continuous along f).  K_ref for a tuple
+  interpolates theta and n linearly in f, scales the angle by the B1 scale
+  (exact on resonance for a pulse of constant phase) and splits the
+  relaxation over the pulse symmetrically around the rotation:
+  A_ref = D R D, b_ref = (1 - E1) (D R e_z + e_z), D = diag(E2, E2, E1) with
+  E = exp(-(tau/2)/T).  With B1 = 0, K_ref is the exact transition.
+* ``targets`` -- what the network is trained to output:
+  RESIDUAL_SCALE * (K - K_ref).
 * ``forward`` / ``loss_grad`` -- the 5-128-128-128-12 SiLU network and the
   gradient of its mean squared error by backpropagation, written out in FP64
   with the weights rounded to BF16 as the matrix cores see them.
+* ``mlp_transition`` -- T from the network: K = K_ref + Y / RESIDUAL_SCALE,
+  mapped back by the frame.
 * ``adam`` -- one Adam step (Kingma and Ba, Algorithm 1).
 """
 from __future__ import annotations
@@ -28,6 +42,10 @@ GAMMA_BAR = 42.577478518e6
 # flat parameter layout: W1[128][5] b1[128] W2[128][128] b2[128] W3[128][128] b3[128] W4[12][128] b4[12]
 SHAPES = [(128, 5), (128,), (128, 128), (128,), (128, 128), (128,), (12, 128), (12,)]
 N_PARAMS = sum(int(np.prod(s)) for s in SHAPES)
+
+REF_GRID = 4097        # points of the reference-rotation table
+REF_FMAX = 1600.0      # the table spans f = f_z + f_B0 in [-REF_FMAX, REF_FMAX] Hz
+RESIDUAL_SCALE = 8.0   # the network outputs RESIDUAL_SCALE * (K - K_ref)
 
 
 def unpack(p):
@@ -67,7 +85,10 @@ def features(tuples, norm=None):
 
 def transition(pulse, tuples, lib=None):
     """Exact transitions (n, 12) (A row-major, then b) of ``pulse`` =
-    (complex B1 per step, Gz per step, dt) for tuples (n, 5), via the C oracle."""
+    (complex B1 per step, Gz per step, dt) for tuples (n, 5), via the C oracle.
+    Tuples with the same B1 scale run in one oracle call (four isochromats
+    per tuple: the three basis states with M0 = 0 and the zero state with
+    M0 = 1)."""
     rf, gz, dt = pulse
     # the library holds the pulse in float32: B1 = s * float32(B1), Gz = float32(Gz),
     # and f_z refers to the peak |Gz| of those values
@@ -76,20 +97,25 @@ def transition(pulse, tuples, lib=None):
     im32 = rf.imag.astype(np.float32).astype(np.float64)
     gz32 = np.asarray(gz, np.float32).astype(np.float64)
     g_ref = float(np.max(np.abs(gz32)))
-    out = np.empty((len(tuples), 12))
-    for k, (fz, df, t1, t2, s1) in enumerate(np.asarray(tuples, np.float64)):
+    t = np.asarray(tuples, np.float64).reshape(-1, 5)
+    out = np.empty((len(t), 12))
+    for s1 in np.unique(t[:, 4]):
+        sel = np.flatnonzero(t[:, 4] == s1)
+        n = len(sel)
         sb = synth.SeqBuilder(dt, "pulse")
         sb.rf(np.zeros(len(rf)), (np.zeros(len(rf)), np.zeros(len(rf)), np.zeros(len(rf))))
         seq = sb.build()
         seq.rf_re, seq.rf_im, seq.gz = s1 * re32, s1 * im32, gz32.copy()  # FP64, no further rounding
-        z = fz / (GAMMA_BAR * g_ref)
-        ph = synth.Phantom(np.zeros(4), np.zeros(4), np.full(4, z), np.full(4, t1), np.full(4, t2),
-                           np.full(4, df), np.array([0.0, 0.0, 0.0, 1.0]))
-        m_init = np.zeros((3, 4))
-        m_init[0, 0] = m_init[1, 1] = m_init[2, 2] = 1.0
+        rep = lambda v: np.repeat(v, 4)
+        z = t[sel, 0] / (GAMMA_BAR * g_ref)
+        ph = synth.Phantom(np.zeros(4 * n), np.zeros(4 * n), rep(z), rep(t[sel, 2]), rep(t[sel, 3]),
+                           rep(t[sel, 1]), np.tile([0.0, 0.0, 0.0, 1.0], n))
+        m_init = np.zeros((3, 4 * n))
+        m_init[0, 0::4] = m_init[1, 1::4] = m_init[2, 2::4] = 1.0
         M, _ = oracle.simulate(ph, seq, m_init=m_init, lib=lib)
-        out[k, :9] = M[:, :3].ravel()  # row i, column j = component i of the image of e_j
-        out[k, 9:] = M[:, 3]
+        M = M.reshape(3, n, 4)
+        out[sel, :9] = M[:, :, :3].transpose(1, 0, 2).reshape(n, 9)  # row i, column j = component i of image of e_j
+        out[sel, 9:] = M[:, :, 3].T
     return out
 
 
@@ -116,6 +142,91 @@ def frame(T, tuples, half, inverse=False):
     out[:, :9] = (P @ A @ P).reshape(-1, 9)
     out[:, 9:] = np.einsum("nij,nj->ni", P, b)
     return out
+
+
+def quaternion(R):
+    """Unit quaternion (w, x, y, z) of a 3x3 rotation matrix, from its
+    largest diagonal combination (numerically safe at every angle)."""
+    R = np.asarray(R, np.float64)
+    tr = R[0, 0] + R[1, 1] + R[2, 2]
+    k = int(np.argmax([tr, R[0, 0], R[1, 1], R[2, 2]]))
+    if k == 0:
+        w = 0.5 * np.sqrt(1.0 + tr)
+        q = [w, (R[2, 1] - R[1, 2]) / (4 * w), (R[0, 2] - R[2, 0]) / (4 * w), (R[1, 0] - R[0, 1]) / (4 * w)]
+    elif k == 1:
+        x = 0.5 * np.sqrt(1.0 + R[0, 0] - R[1, 1] - R[2, 2])
+        q = [(R[2, 1] - R[1, 2]) / (4 * x), x, (R[0, 1] + R[1, 0]) / (4 * x), (R[0, 2] + R[2, 0]) / (4 * x)]
+    elif k == 2:
+        y = 0.5 * np.sqrt(1.0 - R[0, 0] + R[1, 1] - R[2, 2])
+        q = [(R[0, 2] - R[2, 0]) / (4 * y), (R[0, 1] + R[1, 0]) / (4 * y), y, (R[1, 2] + R[2, 1]) / (4 * y)]
+    else:
+        z = 0.5 * np.sqrt(1.0 - R[0, 0] - R[1, 1] + R[2, 2])
+        q = [(R[1, 0] - R[0, 1]) / (4 * z), (R[0, 2] + R[2, 0]) / (4 * z), (R[1, 2] + R[2, 1]) / (4 * z), z]
+    return np.array(q)
+
+
+def rotation_of(q):
+    """3x3 rotation matrix of unit quaternions q (n, 4) = (w, x, y, z)."""
+    w, x, y, z = (np.asarray(q, np.float64)[:, i] for i in range(4))
+    R = np.empty((len(w), 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    R[:, 0, 1] = 2 * (x * y - z * w)
+    R[:, 0, 2] = 2 * (x * z + y * w)
+    R[:, 1, 0] = 2 * (x * y + z * w)
+    R[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    R[:, 1, 2] = 2 * (y * z - x * w)
+    R[:, 2, 0] = 2 * (x * z - y * w)
+    R[:, 2, 1] = 2 * (y * z + x * w)
+    R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def reference_table(pulse, lib=None):
+    """(f grid, theta, axis) of the relaxation-free B1-scale-1 transition of
+    ``pulse`` in the frame, on REF_GRID points over [-REF_FMAX, REF_FMAX] Hz."""
+    rf, gz, dt = pulse
+    half = dt * len(rf) / 2
+    fg = np.linspace(-REF_FMAX, REF_FMAX, REF_GRID)
+    tg = np.stack([fg, np.zeros(REF_GRID), np.full(REF_GRID, np.inf), np.full(REF_GRID, np.inf),
+                   np.ones(REF_GRID)], 1)
+    K = frame(transition(pulse, tg, lib=lib), tg, half)
+    q = np.array([quaternion(k[:9].reshape(3, 3)) for k in K])
+    for j in range(1, REF_GRID):  # q and -q are the same rotation: keep the path continuous
+        if np.dot(q[j], q[j - 1]) < 0:
+            q[j] = -q[j]
+    if q[0, 0] < 0:
+        q = -q
+    v = np.linalg.norm(q[:, 1:], axis=1)
+    theta = 2 * np.arctan2(v, q[:, 0])
+    axis = np.where(v[:, None] > 1e-300, q[:, 1:] / np.maximum(v, 1e-300)[:, None], np.array([0.0, 0.0, 1.0]))
+    return fg, theta, axis
+
+
+def reference(table, tuples, half):
+    """K_ref (n, 12) of tuples (n, 5): interpolated rotation with its angle
+    scaled by the B1 scale, relaxation split around it (see the header)."""
+    fg, theta, axis = table
+    t = np.asarray(tuples, np.float64).reshape(-1, 5)
+    u = (t[:, 0] + t[:, 1] - fg[0]) / (fg[1] - fg[0])
+    i0 = np.clip(np.floor(u).astype(np.int64), 0, len(fg) - 2)
+    w = np.clip(u - i0, 0.0, 1.0)
+    th = (1 - w) * theta[i0] + w * theta[i0 + 1]
+    n = (1 - w)[:, None] * axis[i0] + w[:, None] * axis[i0 + 1]
+    nn = np.linalg.norm(n, axis=1)
+    n = np.where(nn[:, None] > 0, n / np.maximum(nn, 1e-300)[:, None], np.array([0.0, 0.0, 1.0]))
+    h = 0.5 * t[:, 4] * th
+    R = rotation_of(np.concatenate([np.cos(h)[:, None], np.sin(h)[:, None] * n], 1))
+    e1, e2 = np.exp(-half / t[:, 2]), np.exp(-half / t[:, 3])
+    d = np.stack([e2, e2, e1], 1)
+    A = d[:, :, None] * R * d[:, None, :]
+    b = (1 - e1)[:, None] * (d * R[:, :, 2])
+    b[:, 2] += 1 - e1
+    return np.concatenate([A.reshape(-1, 9), b], 1)
+
+
+def targets(T, tuples, half, table):
+    """Training targets of exact transitions T: RESIDUAL_SCALE * (K - K_ref)."""
+    return RESIDUAL_SCALE * (frame(T, tuples, half) - reference(table, tuples, half))
 
 
 def _sig(z):
@@ -169,7 +280,8 @@ def adam(w, m, v, g, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return w - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def mlp_transition(params, tuples, half, norm=None):
-    """The surrogate's T (n, 12): network output K mapped back by the frame."""
+def mlp_transition(params, tuples, half, table, norm=None):
+    """The surrogate's T (n, 12): K = K_ref + Y / RESIDUAL_SCALE, mapped back
+    by the frame."""
     Y, _ = forward(params, features(tuples, norm))
-    return frame(Y, tuples, half, inverse=True)
+    return frame(reference(table, tuples, half) + Y / RESIDUAL_SCALE, tuples, half, inverse=True)

@@ -9,6 +9,7 @@ import torch
 import oracle
 import synth
 from oracle import surrogate as so
+from tests import surrogate_pins as spins
 
 
 @pytest.fixture(scope="module")
@@ -125,3 +126,28 @@ def test_transition_hard_pulse_and_affinity():
     m = np.array([[0.3], [-0.2], [0.5]])
     M, _ = oracle.simulate(ph, sb.build(), m_init=m)
     np.testing.assert_allclose(T[:9].reshape(3, 3) @ m[:, 0] + T[9:] * 0.7, M[:, 0], atol=1e-12)
+
+
+
+def test_quaternion_matches_scipy_at_every_angle():
+    spins.check_quaternion(so)
+
+
+def test_reference_on_resonance_scales_the_angle_exactly():
+    spins.check_on_resonance(so)
+
+
+def test_reference_between_grid_points():
+    spins.check_between_grid(so)
+
+
+def test_reference_is_exact_without_rf():
+    spins.check_zero_rf(so)
+
+
+def test_reference_split_for_a_centred_hard_pulse():
+    spins.check_centred_hard_pulse(so)
+
+
+def test_targets_and_mlp_transition_round_trip():
+    spins.check_round_trip(so)
