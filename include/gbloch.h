@@ -72,7 +72,7 @@ extern "C" {
 #define GBS_CACHED 2
 #define GBS_ASYNC 1u      /* enqueue on the context stream and return; no final synchronize */
 #define GBS_PROFILE 4u    /* time every sweep launch with HIP events (gbs_stats.pass_kernel_ms) */
-#define GBS_SURROGATE 8u  /* GBS_GROUPED: transitions of RF blocks that match the attached surrogate's
+#define GBS_SURROGATE 8u  /* GBS_GROUPED, GBS_CACHED: transitions of RF blocks that match the attached surrogate's
                              pulse come from the network, with the spot-check fallback (gbs_set_surrogate) */
 
 /*
@@ -379,12 +379,19 @@ int gbs_pulseq_load(const char *text, int64_t text_len, double dt, int64_t sizes
  * Features: f_z, f_B0, ln T1, ln T2, B1 scale, each mapped affinely by
  * (v - center) / scale.  Weights enter the matrix cores as BF16
  * (v_mfma_f32_16x16x32_bf16) with FP32 accumulation and FP32 biases;
- * activations are carried as BF16 hi + lo pairs.  The outputs are the
- * transition in a frame without the free precession of each half of the
- * pulse, K = P(-a) T P(-a) with P the z rotation of Eq. A2 and
- * a = -2 pi (f_z + f_B0) n_steps dt / 2; T = P(a) K P(a) is returned.
- * Training minimises the mean over samples and the 12 entries of
- * (K_mlp - K_exact)^2 with Adam on the GPU.
+ * activations are carried as BF16 hi + lo pairs.  The transition is taken
+ * in a frame without the free precession of each half of the pulse,
+ * K = P(-a) T P(-a) with P the z rotation of Eq. A2 and
+ * a = -2 pi (f_z + f_B0) n_steps dt / 2, and the network outputs
+ * Y = 8 (K - K_ref): the residual over a reference transition built from the
+ * pulse when it is set.  K_ref takes the pulse's relaxation-free transition
+ * at B1 scale 1 (a rotation in this frame, tabulated on 4097 points of
+ * f = f_z + f_B0 over +-1600 Hz as angle and axis, interpolated linearly),
+ * scales its angle by the B1 scale and splits the relaxation over the pulse
+ * around it: A_ref = D R D, b_ref = (1 - E1)(D R e_z + e_z),
+ * D = diag(E2, E2, E1), E = exp(-n_steps dt / 2 / T).  T = P(a) (K_ref + Y/8)
+ * P(a) is returned.  Training minimises the mean over samples and the 12
+ * entries of (Y - 8 (K_exact - K_ref))^2 with Adam on the GPU.
  *
  * Parameter vector (GBS_MLP_PARAMS floats): W1[128][5] b1[128] W2[128][128]
  * b2[128] W3[128][128] b3[128] W4[12][128] b4[12]; layer l computes
@@ -413,7 +420,8 @@ const char *gbs_mlp_last_error(const gbs_mlp *m);
 
 /* The pulse this network models: host waveforms of n_steps raster steps of
  * dt (B1 in T, gradients in T/m).  gx and gy must be zero and gz not all zero
- * (a Gz-only with-RF subsequence, Sec. 2.4).  Copied. */
+ * (a Gz-only with-RF subsequence, Sec. 2.4).  Copied.  Also builds the
+ * reference table from 4097 exact transitions of the pulse (synchronous). */
 int gbs_mlp_set_pulse(gbs_mlp *m, const float *rf_re, const float *rf_im, const float *gx,
                       const float *gy, const float *gz, int64_t n_steps, double dt);
 
@@ -447,13 +455,19 @@ int gbs_mlp_train(gbs_mlp *m, const float *tuples, const double *T_exact, int64_
                   const gbs_train_cfg *cfg, float *loss_hist, int64_t hist_len);
 
 /* Attach a surrogate to a simulator context (NULL detaches).  Used by
- * gbs_simulate(GBS_GROUPED, flags | GBS_SURROGATE) for every distinct
- * with-RF, Gz-only subsequence whose waveform equals the network's pulse
- * bit for bit: the network gives T for every z group, then the exact T is
- * composed for n_check seeded groups (all if fewer); if any entry differs by
- * more than tol, the exact T of every group is used instead.  The network
- * object must outlive its use.  Errors: GBS_E_INVALID (tol <= 0, n_check < 1,
- * device mismatch). */
+ * gbs_simulate(mode, flags | GBS_SURROGATE) for the with-RF, Gz-only
+ * subsequence whose waveform equals the network's pulse bit for bit:
+ *   GBS_GROUPED: the network gives T for every z group of the first such
+ *     distinct transition; the exact T is composed for n_check seeded
+ *     groups (all if fewer);
+ *   GBS_CACHED: the network fills the cache entry of the first such
+ *     waveform for every isochromat (tuple (f_z, f_B0, T1, T2, 1)) in place
+ *     of the per-isochromat FP64 composition (Eq. 7, Sec. 2.2); the exact T
+ *     is composed for n_check seeded isochromats.
+ * If any checked entry differs by more than tol, the exact transitions of
+ * every group or isochromat are used instead (decided on the device, no
+ * synchronization).  The network object must outlive its use.  Errors:
+ * GBS_E_INVALID (tol <= 0, n_check < 1, device mismatch). */
 int gbs_set_surrogate(gbs_ctx *ctx, gbs_mlp *m, float tol, int32_t n_check, uint64_t seed);
 
 /* ==== gradient of the signal (adjoint Bloch simulation) ===================

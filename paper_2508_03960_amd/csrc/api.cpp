@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "adc.hpp"
@@ -200,6 +201,11 @@ struct gbs_ctx {
     int32_t surr_check = 32;
     uint64_t surr_seed = 0;
     DevBuf surr_idx;  // seeded spot-check groups
+    // GBS_CACHED with the surrogate: the cache entry it fills (-1: none) and
+    // its seeded spot-check isochromats
+    int csurr_entry = -1;
+    int32_t csurr_n_check = 0;
+    DevBuf csurr_idx;
     // gradient of the signal (adjoint): flattened ops, checkpoints, partials
     DevBuf adj_ops, adj_samp, adj_ckpt, adj_sub, adj_sig, adj_grf, adj_gt;
     AdjArgs adj{};
@@ -296,7 +302,7 @@ int gbs_destroy(gbs_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->side) (void)hipStreamSynchronize(ctx->side);  // a failed call may have left work there
     DevBuf *bufs[] = {&ctx->d_wave, &ctx->d_adc, &ctx->perm, &ctx->inv, &ctx->xi, &ctx->yi, &ctx->zi, &ctx->t1i,
-                      &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->jobs, &ctx->samp, &ctx->flag, &ctx->surr_idx,
+                      &ctx->t2i, &ctx->dfi, &ctx->m0i, &ctx->jobs, &ctx->samp, &ctx->flag, &ctx->surr_idx, &ctx->csurr_idx,
                       &ctx->adj_ops, &ctx->adj_samp, &ctx->adj_ckpt, &ctx->adj_sub, &ctx->adj_sig, &ctx->adj_grf,
                       &ctx->adj_gt, &ctx->csamp, &ctx->ttab, &ctx->tmap, &ctx->coil_l, &ctx->run_of4, &ctx->xstart,
                       &ctx->rtab, &ctx->rz};
@@ -763,12 +769,13 @@ static int run_plain(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out, 
 
 // Build the cached grouped plan: schedule, arena layout, sample tables and
 // job arrays (device).  Host work only once per (sequence, groups).
-// Does distinct RF transition r have exactly the surrogate's pulse?
-static bool matches_pulse(const gbs_ctx *ctx, const RfJob &r) {
+// Do raster steps [step_offset, step_offset + n_steps) play exactly the
+// surrogate's pulse (Gz-only, bit for bit)?
+static bool matches_pulse(const gbs_ctx *ctx, int64_t step_offset, int64_t n_steps) {
     const gbs_mlp *m = ctx->mlp;
     const HostSeq &s = ctx->seq;
-    if (!m || !m->has_pulse || r.axis != 2 || r.n_steps != m->n_steps || s.dt != m->dt) return false;
-    const size_t o = (size_t)r.step_offset, n = (size_t)r.n_steps;
+    if (!m || !m->has_pulse || m->device != ctx->device || n_steps != m->n_steps || s.dt != m->dt) return false;
+    const size_t o = (size_t)step_offset, n = (size_t)n_steps;
     for (size_t i = 0; i < n; ++i)
         if (s.gx[o + i] != 0.f || s.gy[o + i] != 0.f) return false;
     return std::memcmp(&s.rf_re[o], m->rf_re.data(), n * sizeof(float)) == 0 &&
@@ -803,7 +810,7 @@ static int build_grouped_plan(gbs_ctx *ctx) {
     g.zbuilt = (ctx->axes & GBS_AX_Z) != 0;
     if (ctx->mlp && ctx->mlp->device == ctx->device) {
         for (size_t i = 0; i < plan.rf.size(); ++i)
-            if (matches_pulse(ctx, plan.rf[i])) {
+            if (plan.rf[i].axis == 2 && matches_pulse(ctx, plan.rf[i].step_offset, plan.rf[i].n_steps)) {
                 g.surr_rf = (int)i;
                 break;
             }
@@ -1599,6 +1606,8 @@ static int run_grouped(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out
 // writes m_out.
 // Cached schedule: host plan, per-sample tables of the direct ADC operations
 // on the device, GBS_PROFILE events.
+static int build_cached_surrogate(gbs_ctx *ctx);
+
 static int build_cached_plan(gbs_ctx *ctx) {
     const double dt = ctx->seq.dt;
     ctx->cplan_valid = false;
@@ -1643,36 +1652,78 @@ static int build_cached_plan(gbs_ctx *ctx) {
         ctx->pev.push_back(e);
     }
     ctx->cplan_valid = true;
+    return build_cached_surrogate(ctx);
+}
+
+// GBS_CACHED with the surrogate: the first cache entry whose waveform is the
+// network's pulse, and n_check distinct seeded isochromats for its spot check.
+static int build_cached_surrogate(gbs_ctx *ctx) {
+    ctx->csurr_entry = -1;
+    ctx->csurr_n_check = 0;
+    if (!ctx->mlp || !ctx->cplan_valid || ctx->K <= 0) return GBS_OK;
+    const Plan &plan = ctx->cplan;
+    for (size_t i = 0; i < plan.rf.size(); ++i)
+        if (matches_pulse(ctx, plan.rf[i].step_offset, plan.rf[i].n_steps)) {
+            ctx->csurr_entry = (int)i;
+            break;
+        }
+    if (ctx->csurr_entry < 0) return GBS_OK;
+    const int64_t K = ctx->K;
+    const int32_t n = (int32_t)std::min<int64_t>(ctx->surr_check, K);
+    std::vector<int32_t> idx;
+    std::unordered_set<int64_t> seen;
+    uint64_t rs = ctx->surr_seed ^ 0x2545F4914F6CDD1Dull;
+    while ((int32_t)idx.size() < n) {  // distinct draws from [0, K)
+        rs = rs * 6364136223846793005ull + 1442695040888963407ull;
+        const int64_t k = (int64_t)((rs >> 17) % (uint64_t)K);
+        if (seen.insert(k).second) idx.push_back((int32_t)k);
+    }
+    ALLOC(ctx->csurr_idx, sizeof(int32_t) * (size_t)n);
+    HIPCHK(hipMemcpy(ctx->csurr_idx.p, idx.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
+    ctx->csurr_n_check = n;
     return GBS_OK;
 }
 
 // Workspace of GBS_CACHED: the FP64 state, the transition cache (3 float4
-// rows of K per distinct with-RF waveform) and per-workgroup sample sums.
-static size_t cached_ws(const gbs_ctx *ctx, size_t *o_state, size_t *o_cache, size_t *o_partial) {
+// rows of K per distinct with-RF waveform), per-workgroup sample sums and,
+// with an attached surrogate whose pulse the sequence plays, its spot-check
+// tuples, exact transitions, residual and fallback flag.
+struct CachedWs {
+    size_t state = 0, cache = 0, partial = 0, s_tuples = 0, s_exact = 0, s_res = 0, s_fb = 0;
+};
+
+static size_t cached_ws(const gbs_ctx *ctx, CachedWs *o) {
     const int64_t K = ctx->K;
     const size_t n_entries = ctx->cplan.rf.size();
     WsCarve w;
-    *o_state = w.take(sizeof(double) * 3 * (size_t)K);
-    *o_cache = n_entries ? w.take(sizeof(float4) * 3 * (size_t)K * n_entries) : 0;
+    o->state = w.take(sizeof(double) * 3 * (size_t)K);
+    o->cache = n_entries ? w.take(sizeof(float4) * 3 * (size_t)K * n_entries) : 0;
     const int pgrid = plain_grid(K), agrid = direct_adc_grid(K);
-    *o_partial = w.take(sizeof(double2) * (size_t)std::max(pgrid, agrid) * kMaxSamplesPerLaunch * (size_t)ctx->n_coils);
+    o->partial = w.take(sizeof(double2) * (size_t)std::max(pgrid, agrid) * kMaxSamplesPerLaunch * (size_t)ctx->n_coils);
+    if (ctx->csurr_entry >= 0) {
+        o->s_tuples = w.take(sizeof(float) * 5 * (size_t)ctx->csurr_n_check);
+        o->s_exact = w.take(sizeof(double) * 12 * (size_t)ctx->csurr_n_check);
+        o->s_res = w.take(sizeof(float));
+        o->s_fb = w.take(sizeof(int32_t));
+    }
     return w.off;
 }
 
 static int run_cached(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out, double *sig_out, bool profile,
-                      gbs_stats *st, int *n_timed) {
+                      bool use_surr, gbs_stats *st, int *n_timed) {
     const int64_t K = ctx->K;
     const double dt = ctx->seq.dt;
     if (!ctx->cplan_valid) return fail(ctx, GBS_E_STATE, "no cached schedule (a setter failed)");
     const Plan &plan = ctx->cplan;
     const size_t n_entries = plan.rf.size();
-    size_t o_state = 0, o_cache = 0, o_partial = 0;
-    cached_ws(ctx, &o_state, &o_cache, &o_partial);
+    CachedWs o;
+    cached_ws(ctx, &o);
     const int pgrid = plain_grid(K), agrid = direct_adc_grid(K);
-    ctx->partial = (double2 *)(ws + o_partial);
-    float4 *cache = (float4 *)(ws + o_cache);
+    ctx->partial = (double2 *)(ws + o.partial);
+    float4 *cache = (float4 *)(ws + o.cache);
     ctx->cprof_kind.clear();
-    double *s64 = (double *)(ws + o_state);
+    double *s64 = (double *)(ws + o.state);
+    const bool surr = use_surr && ctx->csurr_entry >= 0;
     const float *mi_x = m_init, *mi_y = m_init ? m_init + K : nullptr, *mi_z = m_init ? m_init + 2 * K : nullptr;
     bool from_init = true;
     int timed = 0;
@@ -1750,7 +1801,31 @@ static int run_cached(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out,
                 a.wave = ctx->d_wave.as<StepW>() + b.step_offset;
                 a.n_steps = (int32_t)b.n_steps;
             }
-            HIPCHK(launch_cached(a, mode, ctx->stream));
+            if (mode == kCacheCompose && surr && c.entry == ctx->csurr_entry) {
+                // the network fills the entry for every isochromat; n_check of
+                // them are composed exactly and compared; past tol the exact
+                // composition runs after all (compose launch gated on the
+                // flag), else the network's entry is applied
+                const gbs_mlp *m = ctx->mlp;
+                float *tup = (float *)(ws + o.s_tuples);
+                double *ex = (double *)(ws + o.s_exact);
+                int32_t *fb = (int32_t *)(ws + o.s_fb);
+                const int32_t *cidx = ctx->csurr_idx.as<int32_t>();
+                HIPCHK(mlp_infer_rows_async(m, ctx->ph.z, ctx->ph.df, ctx->ph.t1, ctx->ph.t2, K, a.cache, K,
+                                            ctx->stream));
+                HIPCHK(launch_surr_iso_tuples(ctx->ph.z, ctx->ph.df, ctx->ph.t1, ctx->ph.t2, cidx, ctx->csurr_n_check,
+                                              kGammaBar * m->g_ref, tup, ctx->stream));
+                HIPCHK(mlp_exact_async(m, tup, nullptr, ctx->csurr_n_check, nullptr, ex, ctx->stream));
+                HIPCHK(launch_surr_check_rows(a.cache, K, cidx, ex, ctx->csurr_n_check, ctx->surr_tol,
+                                              (float *)(ws + o.s_res), fb, ctx->stream));
+                a.gate = fb;
+                a.gate_value = 1;
+                HIPCHK(launch_cached(a, kCacheCompose, ctx->stream));
+                a.gate_value = 0;
+                HIPCHK(launch_cached(a, kCacheApply, ctx->stream));
+            } else {
+                HIPCHK(launch_cached(a, mode, ctx->stream));
+            }
             from_init = false;
         }
         if (profile) {
@@ -1794,13 +1869,14 @@ static int workspace_bytes(gbs_ctx *ctx, int mode, size_t *bytes) {
     if (!ctx->has_seq) return fail(ctx, GBS_E_STATE, "no sequence (gbs_set_sequence)");
     if (mode != GBS_PLAIN && mode != GBS_GROUPED && mode != GBS_CACHED)
         return fail(ctx, GBS_E_INVALID, "mode must be GBS_PLAIN, GBS_GROUPED or GBS_CACHED");
-    size_t a = 0, b = 0, c = 0;
+    size_t a = 0, b = 0;
     if (mode == GBS_PLAIN) {
         if (!ctx->pplan_valid) return fail(ctx, GBS_E_STATE, "no plain schedule (a setter failed)");
         *bytes = plain_ws(ctx, &a, &b);
     } else if (mode == GBS_CACHED) {
         if (!ctx->cplan_valid) return fail(ctx, GBS_E_STATE, "no cached schedule (a setter failed)");
-        *bytes = cached_ws(ctx, &a, &b, &c);
+        CachedWs o;
+        *bytes = cached_ws(ctx, &o);
     } else {
         if (!ctx->groups_valid) return fail(ctx, GBS_E_STATE, "GBS_GROUPED needs gbs_build_groups on the current phantom");
         if (!ctx->gp.valid) return fail(ctx, GBS_E_STATE, "no grouped schedule (a setter failed)");
@@ -1829,8 +1905,8 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, void *worksp
     if (flags & ~(GBS_ASYNC | GBS_PROFILE | GBS_SURROGATE))
         return fail(ctx, GBS_E_INVALID, "unknown flags");
     const bool use_surr = (flags & GBS_SURROGATE) != 0;
-    if (use_surr && (mode != GBS_GROUPED || !ctx->mlp))
-        return fail(ctx, GBS_E_INVALID, "GBS_SURROGATE needs GBS_GROUPED and gbs_set_surrogate");
+    if (use_surr && (mode == GBS_PLAIN || !ctx->mlp))
+        return fail(ctx, GBS_E_INVALID, "GBS_SURROGATE needs GBS_GROUPED or GBS_CACHED and gbs_set_surrogate");
     size_t need = 0;
     if (int rc = workspace_bytes(ctx, mode, &need)) return rc;
     if (!workspace || ws_bytes < need)
@@ -1850,7 +1926,7 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, void *worksp
     const bool profile = (flags & GBS_PROFILE) != 0;
     int n_timed = 0;
     int rc = mode == GBS_PLAIN ? run_plain(ctx, ws, m_init, m_out, sig_out, stats)
-             : mode == GBS_CACHED ? run_cached(ctx, ws, m_init, m_out, sig_out, profile, stats, &n_timed)
+             : mode == GBS_CACHED ? run_cached(ctx, ws, m_init, m_out, sig_out, profile, use_surr, stats, &n_timed)
                                   : run_grouped(ctx, ws, m_init, m_out, sig_out, profile, use_surr, stats, &n_timed);
     if (rc != GBS_OK) return rc;
     if (stats) HIPCHK(hipEventRecord(ctx->ev[4], ctx->stream));
@@ -1874,6 +1950,18 @@ extern "C" int gbs_simulate(gbs_ctx *ctx, int mode, uint32_t flags, void *worksp
             stats->ms_apply = sum[1];
             stats->ms_adc_direct = sum[2];
             stats->ms_stepped = sum[3];
+            if (use_surr && ctx->csurr_entry >= 0) {
+                CachedWs o;
+                cached_ws(ctx, &o);
+                float res = 0.f;
+                int32_t fb = 0;
+                HIPCHK(hipMemcpyAsync(&res, ws + o.s_res, sizeof(float), hipMemcpyDeviceToHost, ctx->stream));
+                HIPCHK(hipMemcpyAsync(&fb, ws + o.s_fb, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+                HIPCHK(hipStreamSynchronize(ctx->stream));
+                stats->n_surrogate = 1;
+                stats->n_surrogate_fallback = fb ? 1 : 0;
+                stats->surrogate_residual = res;
+            }
         } else {
             HIPCHK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
             stats->ms_prepare = ms;
@@ -1917,10 +2005,9 @@ extern "C" int gbs_set_surrogate(gbs_ctx *ctx, gbs_mlp *m, float tol, int32_t n_
     ctx->surr_check = n_check;
     ctx->surr_seed = seed;
     ctx->gp.valid = false;
-    if (ctx->has_seq && ctx->groups_valid) {
-        HIPCHK(hipSetDevice(ctx->device));
-        return build_grouped_plan(ctx);
-    }
+    HIPCHK(hipSetDevice(ctx->device));
+    if (int rc = build_cached_surrogate(ctx)) return rc;
+    if (ctx->has_seq && ctx->groups_valid) return build_grouped_plan(ctx);
     return GBS_OK;
 }
 

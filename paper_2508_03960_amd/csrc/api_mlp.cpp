@@ -1,6 +1,7 @@
 // C ABI of the learned RF-transition surrogate (include/gbloch.h).
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -68,6 +69,96 @@ int check_tuples(gbs_mlp *m, const void *p, int64_t n) {
     return GBS_OK;
 }
 
+// Unit quaternion (w, x, y, z) of a rotation matrix R (row-major), from its
+// largest diagonal combination (safe at every angle).
+void quaternion_of(const double *R, double q[4]) {
+    const double tr = R[0] + R[4] + R[8];
+    if (tr >= R[0] && tr >= R[4] && tr >= R[8]) {
+        const double w = 0.5 * std::sqrt(1.0 + tr);
+        q[0] = w;
+        q[1] = (R[7] - R[5]) / (4.0 * w);
+        q[2] = (R[2] - R[6]) / (4.0 * w);
+        q[3] = (R[3] - R[1]) / (4.0 * w);
+    } else if (R[0] >= R[4] && R[0] >= R[8]) {
+        const double x = 0.5 * std::sqrt(1.0 + R[0] - R[4] - R[8]);
+        q[0] = (R[7] - R[5]) / (4.0 * x);
+        q[1] = x;
+        q[2] = (R[1] + R[3]) / (4.0 * x);
+        q[3] = (R[2] + R[6]) / (4.0 * x);
+    } else if (R[4] >= R[8]) {
+        const double y = 0.5 * std::sqrt(1.0 - R[0] + R[4] - R[8]);
+        q[0] = (R[2] - R[6]) / (4.0 * y);
+        q[1] = (R[1] + R[3]) / (4.0 * y);
+        q[2] = y;
+        q[3] = (R[5] + R[7]) / (4.0 * y);
+    } else {
+        const double z = 0.5 * std::sqrt(1.0 - R[0] - R[4] + R[8]);
+        q[0] = (R[3] - R[1]) / (4.0 * z);
+        q[1] = (R[2] + R[6]) / (4.0 * z);
+        q[2] = (R[5] + R[7]) / (4.0 * z);
+        q[3] = z;
+    }
+}
+
+// The reference-rotation table of the pulse just set (mlp.hpp): exact
+// relaxation-free transitions at B1 scale 1 on the f grid, taken into the
+// frame, as angle and axis of their quaternions with continuous signs.
+int build_reference(gbs_mlp *m) {
+    std::vector<float> tup(5 * (size_t)kRefGrid);
+    const double df = 2.0 * kRefFmax / (kRefGrid - 1);
+    for (int j = 0; j < kRefGrid; ++j) {
+        float *t = tup.data() + 5 * (size_t)j;
+        t[0] = (float)(-kRefFmax + j * df);  // a multiple of 1/32 Hz: exact in float
+        t[1] = 0.f;
+        t[2] = t[3] = INFINITY;
+        t[4] = 1.f;
+    }
+    Scratch s;
+    float *d_tup;
+    double *d_T;
+    MCHK(s.get((void **)&d_tup, sizeof(float) * tup.size()));
+    MCHK(s.get((void **)&d_T, sizeof(double) * 12 * (size_t)kRefGrid));
+    MCHK(hipMemcpyAsync(d_tup, tup.data(), sizeof(float) * tup.size(), hipMemcpyHostToDevice, m->stream));
+    MCHK(mlp_exact_async(m, d_tup, nullptr, kRefGrid, nullptr, d_T, m->stream));
+    std::vector<double> T(12 * (size_t)kRefGrid);
+    MCHK(hipMemcpyAsync(T.data(), d_T, sizeof(double) * T.size(), hipMemcpyDeviceToHost, m->stream));
+    MCHK(hipStreamSynchronize(m->stream));
+    std::vector<float4> tab(kRefGrid);
+    double prev[4] = {0.0, 0.0, 0.0, 0.0};
+    std::vector<std::array<double, 4>> qs(kRefGrid);
+    for (int j = 0; j < kRefGrid; ++j) {
+        // K = P(-a) A P(-a) with a = -2 pi f tau/2; P(-a) = [[c, s], [-s, c]] in x, y
+        const double a = -kTwoPi * (double)tup[5 * (size_t)j] * m->norm.half;
+        const double c = std::cos(a), sn = std::sin(a);
+        const double *A = T.data() + 12 * (size_t)j;
+        const double P[9] = {c, sn, 0.0, -sn, c, 0.0, 0.0, 0.0, 1.0};
+        double PA[9], K[9];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k)
+                PA[3 * r + k] = P[3 * r] * A[k] + P[3 * r + 1] * A[3 + k] + P[3 * r + 2] * A[6 + k];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k)
+                K[3 * r + k] = PA[3 * r] * P[k] + PA[3 * r + 1] * P[3 + k] + PA[3 * r + 2] * P[6 + k];
+        double q[4];
+        quaternion_of(K, q);
+        if (j > 0 && q[0] * prev[0] + q[1] * prev[1] + q[2] * prev[2] + q[3] * prev[3] < 0.0)
+            for (double &v : q) v = -v;  // q and -q are the same rotation: keep the path continuous
+        for (int i = 0; i < 4; ++i) prev[i] = q[i];
+        qs[j] = {q[0], q[1], q[2], q[3]};
+    }
+    const double sgn = qs[0][0] < 0.0 ? -1.0 : 1.0;
+    for (int j = 0; j < kRefGrid; ++j) {
+        const double w = sgn * qs[j][0], x = sgn * qs[j][1], y = sgn * qs[j][2], z = sgn * qs[j][3];
+        const double v = std::sqrt(x * x + y * y + z * z);
+        const double th = 2.0 * std::atan2(v, w);
+        tab[j] = v > 1e-300 ? make_float4((float)th, (float)(x / v), (float)(y / v), (float)(z / v))
+                            : make_float4((float)th, 0.f, 0.f, 1.f);
+    }
+    MCHK(hipMemcpy(m->ref, tab.data(), sizeof(float4) * kRefGrid, hipMemcpyHostToDevice));
+    m->norm.ref = m->ref;
+    return GBS_OK;
+}
+
 }  // namespace
 
 namespace gbs {
@@ -75,6 +166,23 @@ namespace gbs {
 hipError_t mlp_infer_async(const gbs_mlp *m, const float *tuples, const int32_t *idx, int64_t n, float *T32,
                            hipStream_t st) {
     MlpInferArgs a{tuples, idx, n, (const uint4 *)m->wf, m->w, m->norm, T32};
+    return launch_mlp_infer(a, st);
+}
+
+hipError_t mlp_infer_rows_async(const gbs_mlp *m, const float *z, const float *df, const float *t1, const float *t2,
+                                int64_t n, float4 *rows, int64_t stride, hipStream_t st) {
+    MlpInferArgs a{};
+    a.N = n;
+    a.wf = (const uint4 *)m->wf;
+    a.params = m->w;
+    a.norm = m->norm;
+    a.src_z = z;
+    a.src_df = df;
+    a.src_t1 = t1;
+    a.src_t2 = t2;
+    a.fz_per_m = kGammaBar * m->g_ref;
+    a.rows = rows;
+    a.row_stride = stride;
     return launch_mlp_infer(a, st);
 }
 
@@ -99,11 +207,13 @@ int gbs_mlp_create(gbs_mlp **out, int device, void *stream, uint64_t seed) {
     m->device = device;
     m->stream = (hipStream_t)stream;
     default_norm(m->norm);
+    m->norm.half = 0.0;
     const size_t pb = sizeof(float) * kMlpParams;
     if (hipMalloc((void **)&m->w, pb) != hipSuccess || hipMalloc((void **)&m->m, pb) != hipSuccess ||
         hipMalloc((void **)&m->v, pb) != hipSuccess ||
         hipMalloc((void **)&m->wf, sizeof(uint16_t) * 512 * kFragFwd) != hipSuccess ||
-        hipMalloc((void **)&m->wb, sizeof(uint16_t) * 512 * kFragBwd) != hipSuccess) {
+        hipMalloc((void **)&m->wb, sizeof(uint16_t) * 512 * kFragBwd) != hipSuccess ||
+        hipMalloc((void **)&m->ref, sizeof(float4) * kRefGrid) != hipSuccess) {
         gbs_mlp_destroy(m);
         return GBS_E_NOMEM;
     }
@@ -129,7 +239,7 @@ int gbs_mlp_destroy(gbs_mlp *m) {
     if (!m) return GBS_OK;
     (void)hipSetDevice(m->device);
     (void)hipStreamSynchronize(m->stream);
-    void *ptrs[] = {m->w, m->m, m->v, m->wf, m->wb, m->wave};
+    void *ptrs[] = {m->w, m->m, m->v, m->wf, m->wb, m->wave, m->ref};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     delete m;
@@ -153,6 +263,7 @@ int gbs_mlp_set_pulse(gbs_mlp *m, const float *rf_re, const float *rf_im, const 
     }
     if (g_ref == 0.0) return mfail(m, GBS_E_INVALID, "pulse has no slice gradient (gz all zero)");
     MCHK(hipSetDevice(m->device));
+    m->has_pulse = false;
     std::vector<float4> w(n_steps);
     for (int64_t i = 0; i < n_steps; ++i) w[i] = make_float4(rf_re[i], rf_im[i], gz[i], 0.f);
     if (m->wave) {
@@ -169,6 +280,7 @@ int gbs_mlp_set_pulse(gbs_mlp *m, const float *rf_re, const float *rf_im, const 
     m->dt = dt;
     m->g_ref = g_ref;
     m->norm.half = 0.5 * (double)n_steps * dt;
+    if (int rc = build_reference(m)) return rc;
     m->has_pulse = true;
     return GBS_OK;
 }
@@ -290,7 +402,7 @@ int gbs_mlp_loss_grad(gbs_mlp *m, const float *tuples, const double *T_exact, in
     float *dloss;
     MCHK(tb.s.get((void **)&dloss, sizeof(float)));
     MCHK(launch_fill_f32(dloss, 1, 0.f, m->stream));
-    MCHK(launch_mlp_targets(tuples, T_exact, n, m->norm.half, tb.K, m->stream));
+    MCHK(launch_mlp_targets(tuples, T_exact, n, m->norm, tb.K, m->stream));
     MCHK(launch_mlp_train_fb(tb.train_args(m, tuples, n, (int)n, dloss), m->stream));
     const int slice = n % 256 == 0 ? 256 : 64;
     MCHK(launch_mlp_wgrad(MlpGradArgs{tb.act_h, tb.act_l, tb.dz_h, tb.dz_l, (int32_t)n, slice, tb.part}, m->stream));
@@ -325,7 +437,7 @@ int gbs_mlp_train(gbs_mlp *m, const float *tuples, const double *T_exact, int64_
     float *dloss;
     MCHK(tb.s.get((void **)&dloss, sizeof(float) * total));
     MCHK(launch_fill_f32(dloss, total, 0.f, m->stream));
-    MCHK(launch_mlp_targets(tuples, T_exact, n, m->norm.half, tb.K, m->stream));
+    MCHK(launch_mlp_targets(tuples, T_exact, n, m->norm, tb.K, m->stream));
     uint64_t rs = cfg->seed;
     int64_t k = 0;
     for (int e = 0; e < cfg->epochs; ++e) {

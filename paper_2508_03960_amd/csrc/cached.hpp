@@ -40,6 +40,10 @@ struct CachedArgs {
     int32_t n_steps;    // compose
     double dt;
     double gdt;  // gamma * dt (rad / T)
+    // optional: the launch does nothing unless *gate == gate_value (a device
+    // flag set by an earlier kernel on the stream, e.g. a surrogate's spot check)
+    const int32_t *gate;
+    int32_t gate_value;
 };
 
 // Samples of one with-ADC block without RF.  Sample n sees the block-start

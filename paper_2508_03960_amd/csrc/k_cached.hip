@@ -33,6 +33,7 @@ template <int MODE>
 __global__ __launch_bounds__(kCachedBlock) void k_cached(CachedArgs a) {
     const int64_t k = (int64_t)blockIdx.x * kCachedBlock + threadIdx.x;
     if (k >= a.K) return;
+    if (a.gate && *a.gate != a.gate_value) return;
     const int64_t K = a.K;
     const double m0 = a.ph.m0[k];
     double vx, vy, vz;

@@ -4,7 +4,9 @@
 //                   for a batch of parameter tuples, FP64, one wavefront per
 //                   tuple: the training data, the spot check and the exact
 //                   fallback.
-//  k_mlp_targets    T -> K (free precession of each half pulse removed).
+//  k_mlp_targets    T -> kResidualScale (K - K_ref): the frame (free
+//                   precession of each half pulse removed), less the
+//                   reference transition.
 //  k_mlp_train_fb   forward and backward pass of one batch, 16 samples per
 //                   wavefront, on v_mfma_f32_16x16x32_bf16; activations stay
 //                   in registers between layers (see the k order below).
@@ -12,7 +14,8 @@
 //  k_mlp_adam       Adam update of the FP32 master weights, then the BF16
 //                   MFMA fragments are repacked.
 //  k_mlp_infer      forward pass only, weights staged in LDS, 32 samples per
-//                   wavefront and iteration, then T = P(a) K P(a).
+//                   wavefront and iteration, then K = K_ref + Y / scale and
+//                   T = P(a) K P(a).
 //
 // MFMA 16x16x32 lane layout (lane l, g = l / 16): A holds row l % 16 and
 // k = 8g..8g+7; B holds column l % 16 and the same k; D holds column l % 16
@@ -241,22 +244,61 @@ __device__ __forceinline__ void frame_angle(const float *tp, double half, double
     sincos(kTwoPi * rev, &s, &c);
 }
 
-__global__ __launch_bounds__(256) void k_mlp_targets(const float *tuples, const double *T, int64_t N,
-                                                     double half, float *K) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N) return;
-    double c, s, k[12];
-    frame_angle(tuples + 5 * t, half, c, s);
-    frame(T + 12 * t, c, s, true, k);
+// Reference transition K_ref (frame coordinates, FP64) of tuple tp: the
+// tabulated rotation interpolated at f = f_z + f_B0, its angle scaled by the
+// B1 scale, relaxation over each half of the pulse on either side.
+__device__ void ref_transition(const float *tp, const MlpNorm &n, double *k) {
+    const double f = (double)tp[0] + (double)tp[1];
+    double u = (f + kRefFmax) * ((kRefGrid - 1) / (2.0 * kRefFmax));
+    u = u >= 0.0 ? (u <= kRefGrid - 1 ? u : (double)(kRefGrid - 1)) : 0.0;  // NaN -> 0
+    int i0 = (int)u;
+    i0 = i0 < kRefGrid - 2 ? i0 : kRefGrid - 2;
+    const double w = u - i0;
+    const float4 r0 = n.ref[i0], r1 = n.ref[i0 + 1];
+    const double th = (1.0 - w) * r0.x + w * r1.x;
+    double ax = (1.0 - w) * r0.y + w * r1.y, ay = (1.0 - w) * r0.z + w * r1.z, az = (1.0 - w) * r0.w + w * r1.w;
+    const double nn = sqrt(ax * ax + ay * ay + az * az);
+    if (nn > 0.0) {
+        ax /= nn;
+        ay /= nn;
+        az /= nn;
+    } else {
+        ax = ay = 0.0;
+        az = 1.0;
+    }
+    double sh, ch;
+    sincos(0.5 * (double)tp[4] * th, &sh, &ch);
+    const double qw = ch, qx = sh * ax, qy = sh * ay, qz = sh * az;
+    const double R[9] = {1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qz * qw),     2 * (qx * qz + qy * qw),
+                         2 * (qx * qy + qz * qw),     1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qx * qw),
+                         2 * (qx * qz - qy * qw),     2 * (qy * qz + qx * qw),     1 - 2 * (qx * qx + qy * qy)};
+    const double e1 = exp(-n.half / (double)tp[2]), e2 = exp(-n.half / (double)tp[3]);
+    const double d[3] = {e2, e2, e1};
 #pragma unroll
-    for (int i = 0; i < 12; ++i) K[12 * t + i] = (float)k[i];
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) k[3 * i + j] = d[i] * R[3 * i + j] * d[j];
+        k[9 + i] = (1.0 - e1) * (d[i] * R[3 * i + 2] + (i == 2 ? 1.0 : 0.0));
+    }
 }
 
-hipError_t launch_mlp_targets(const float *tuples, const double *T, int64_t N, double half, float *K,
+__global__ __launch_bounds__(256) void k_mlp_targets(const float *tuples, const double *T, int64_t N, MlpNorm norm,
+                                                     float *K) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    double c, s, k[12], kr[12];
+    frame_angle(tuples + 5 * t, norm.half, c, s);
+    frame(T + 12 * t, c, s, true, k);
+    ref_transition(tuples + 5 * t, norm, kr);
+#pragma unroll
+    for (int i = 0; i < 12; ++i) K[12 * t + i] = (float)(kResidualScale * (k[i] - kr[i]));
+}
+
+hipError_t launch_mlp_targets(const float *tuples, const double *T, int64_t N, const MlpNorm &norm, float *K,
                               hipStream_t st) {
     if (N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mlp_targets, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, tuples, T, N,
-                       half, K);
+    if (!norm.ref) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mlp_targets, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, tuples, T, N, norm, K);
     return hipGetLastError();
 }
 
@@ -601,6 +643,21 @@ hipError_t launch_mlp_adam(const MlpAdamArgs &a, hipStream_t st) {
 // -------------------------------------------------------------- k_mlp_infer
 constexpr int kInferWG = 512;  // 8 wavefronts share one LDS copy of the weights
 
+// Tuple s of an inference launch (s < N).
+__device__ __forceinline__ void infer_tuple(const MlpInferArgs &a, int64_t s, float tp[5]) {
+    if (a.src_z) {
+        tp[0] = (float)(a.fz_per_m * (double)a.src_z[s]);
+        tp[1] = a.src_df[s];
+        tp[2] = a.src_t1[s];
+        tp[3] = a.src_t2[s];
+        tp[4] = 1.f;
+    } else {
+        const float *p = a.tuples + 5 * (a.idx ? (int64_t)a.idx[s] : s);
+#pragma unroll
+        for (int i = 0; i < 5; ++i) tp[i] = p[i];
+    }
+}
+
 __global__ __launch_bounds__(kInferWG) void k_mlp_infer(MlpInferArgs a) {
     __shared__ uint4 sw[kFragFwd * 64];
     __shared__ float sk[kInferWG / 64][32][12];
@@ -618,7 +675,11 @@ __global__ __launch_bounds__(kInferWG) void k_mlp_infer(MlpInferArgs a) {
         for (int nt = 0; nt < 2; ++nt) {
             const int64_t s = tile * 32 + nt * 16 + col;
             float u[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-            if (s < a.N) features(a.tuples + 5 * (a.idx ? (int64_t)a.idx[s] : s), a.norm, u);
+            if (s < a.N) {
+                float tp[5];
+                infer_tuple(a, s, tp);
+                features(tp, a.norm, u);
+            }
             input_frag(u, g, fh[nt][0], fl[nt][0]);
             bias_init(acc[nt], a.params + kOffB1, g);
         }
@@ -697,13 +758,23 @@ __global__ __launch_bounds__(kInferWG) void k_mlp_infer(MlpInferArgs a) {
         const int64_t s = tile * 32 + lane;
         if (lane < 32 && s < a.N) {
             double k[12], T[12], c, sn;
+            float tp[5];
+            infer_tuple(a, s, tp);
+            ref_transition(tp, a.norm, k);
 #pragma unroll
-            for (int i = 0; i < 12; ++i) k[i] = sk[wave][lane][i];
-            frame_angle(a.tuples + 5 * (a.idx ? (int64_t)a.idx[s] : s), a.norm.half, c, sn);
+            for (int i = 0; i < 12; ++i) k[i] += (double)sk[wave][lane][i] * (1.0 / kResidualScale);
+            frame_angle(tp, a.norm.half, c, sn);
             frame(k, c, sn, false, T);
-            float *o = a.out + 12 * s;
+            if (a.rows) {
 #pragma unroll
-            for (int i = 0; i < 12; ++i) o[i] = (float)T[i];
+                for (int i = 0; i < 3; ++i)
+                    a.rows[i * a.row_stride + s] =
+                        make_float4((float)T[3 * i], (float)T[3 * i + 1], (float)T[3 * i + 2], (float)T[9 + i]);
+            } else {
+                float *o = a.out + 12 * s;
+#pragma unroll
+                for (int i = 0; i < 12; ++i) o[i] = (float)T[i];
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -713,6 +784,7 @@ __global__ __launch_bounds__(kInferWG) void k_mlp_infer(MlpInferArgs a) {
 
 hipError_t launch_mlp_infer(const MlpInferArgs &a, hipStream_t st) {
     if (a.N <= 0) return hipSuccess;
+    if (!a.norm.ref || (!a.rows && !a.out) || (!a.src_z && !a.tuples)) return hipErrorInvalidValue;
     const int64_t tiles = (a.N + 31) / 32;
     const int64_t wgs = (tiles + kInferWG / 64 - 1) / (kInferWG / 64);
     const unsigned grid = (unsigned)(wgs < 256 ? wgs : 256);  // one resident workgroup per CU
@@ -753,15 +825,50 @@ hipError_t launch_surr_store(const float *T32, int64_t n, double *T64, hipStream
     return hipGetLastError();
 }
 
-// max |T_mlp - T_exact| over the checked groups; sets *fallback when it
-// exceeds tol.  One workgroup.
-__global__ __launch_bounds__(256) void k_surr_check(const float *T32, const int32_t *idx, const double *exact,
-                                                    int n_check, float tol, float *residual, int32_t *fallback) {
+// Tuples of phantom isochromats idx[0 .. n) for B1 scale 1:
+// (fz_per_m z, df, t1, t2, 1).
+__global__ __launch_bounds__(256) void k_surr_iso_tuples(const float *z, const float *df, const float *t1,
+                                                         const float *t2, const int32_t *idx, int n, double fz_per_m,
+                                                         float *tuples) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int64_t k = idx[t];
+    float *o = tuples + 5 * (int64_t)t;
+    o[0] = (float)(fz_per_m * (double)z[k]);
+    o[1] = df[k];
+    o[2] = t1[k];
+    o[3] = t2[k];
+    o[4] = 1.f;
+}
+
+hipError_t launch_surr_iso_tuples(const float *z, const float *df, const float *t1, const float *t2,
+                                  const int32_t *idx, int n, double fz_per_m, float *tuples, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_surr_iso_tuples, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, z, df, t1, t2, idx, n,
+                       fz_per_m, tuples);
+    return hipGetLastError();
+}
+
+// Entry c of network transition k: T32[12 idx[k] + c], or from the row planes
+// (rows[i * stride + idx[k]] = (A_i0, A_i1, A_i2, b_i)).
+__device__ __forceinline__ float checked_entry(const float *T32, const float4 *rows, int64_t stride, int64_t k,
+                                               int c) {
+    if (!rows) return T32[12 * k + c];
+    const int i = c < 9 ? c / 3 : c - 9, j = c < 9 ? c % 3 : 3;
+    const float4 r = rows[i * stride + k];
+    return j == 0 ? r.x : j == 1 ? r.y : j == 2 ? r.z : r.w;
+}
+
+// max |T_mlp - T_exact| over the checked transitions; sets *fallback when it
+// exceeds tol (or is NaN).  One workgroup.
+__global__ __launch_bounds__(256) void k_surr_check(const float *T32, const float4 *rows, int64_t stride,
+                                                    const int32_t *idx, const double *exact, int n_check, float tol,
+                                                    float *residual, int32_t *fallback) {
     __shared__ float red[256];
     float mx = 0.f;
     for (int e = threadIdx.x; e < 12 * n_check; e += 256) {
         const int k = e / 12, c = e % 12;
-        const float d = fabsf((float)(exact[e] - (double)T32[12 * (int64_t)idx[k] + c]));
+        const float d = fabsf((float)(exact[e] - (double)checked_entry(T32, rows, stride, idx[k], c)));
         mx = (d > mx || d != d) ? d : mx;
     }
     red[threadIdx.x] = mx;
@@ -782,7 +889,15 @@ __global__ __launch_bounds__(256) void k_surr_check(const float *T32, const int3
 
 hipError_t launch_surr_check(const float *T32, const int32_t *idx, const double *exact, int n_check, float tol,
                              float *residual, int32_t *fallback, hipStream_t st) {
-    hipLaunchKernelGGL(k_surr_check, dim3(1), dim3(256), 0, st, T32, idx, exact, n_check, tol, residual, fallback);
+    hipLaunchKernelGGL(k_surr_check, dim3(1), dim3(256), 0, st, T32, (const float4 *)nullptr, (int64_t)0, idx, exact,
+                       n_check, tol, residual, fallback);
+    return hipGetLastError();
+}
+
+hipError_t launch_surr_check_rows(const float4 *rows, int64_t stride, const int32_t *idx, const double *exact,
+                                  int n_check, float tol, float *residual, int32_t *fallback, hipStream_t st) {
+    hipLaunchKernelGGL(k_surr_check, dim3(1), dim3(256), 0, st, (const float *)nullptr, rows, stride, idx, exact,
+                       n_check, tol, residual, fallback);
     return hipGetLastError();
 }
 

@@ -9,10 +9,21 @@
 // Activations are carried as a BF16 pair (hi + lo) so that only the weights
 // are rounded to BF16.
 //
-// The network predicts K = P(-a) T P(-a), the transition with the free
-// precession of each half of the pulse removed; P(a) is the z rotation of
-// Eq. A2 and a = -2 pi (f_z + f_B0) tau/2.  T is recovered exactly as
-// P(a) K P(a) (b column: P(a) k_b).
+// Frame: K = P(-a) T P(-a), the transition with the free precession of each
+// half of the pulse removed; P(a) is the z rotation of Eq. A2 and
+// a = -2 pi (f_z + f_B0) tau/2.  T is recovered exactly as P(a) K P(a)
+// (b column: P(a) k_b).
+//
+// The network predicts the scaled residual kResidualScale (K - K_ref) over a
+// reference transition built from the pulse itself: its relaxation-free
+// transition at B1 scale 1 in the frame (a rotation), tabulated on
+// kRefGrid points of f = f_z + f_B0 over [-kRefFmax, kRefFmax] as rotation
+// angle and unit axis (from the unit quaternion, signs continuous along f).
+// For a tuple, angle and axis are interpolated linearly in f, the angle is
+// scaled by the B1 scale, and the relaxation over the pulse is split around
+// the rotation: A_ref = D R D, b_ref = (1 - E1) (D R e_z + e_z),
+// D = diag(E2, E2, E1), E = exp(-(tau/2)/T).  The residual is 3-60x smaller
+// than K, and so is the error floor that BF16 weights leave on it.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -39,10 +50,15 @@ constexpr int kActRows = 400;  // H0 (16: 5 inputs + zeros), H1, H2, H3
 constexpr int kDzRows = 400;   // dZ1, dZ2, dZ3, dZ4 (16: 12 outputs + zeros)
 constexpr int kSpRows = 384;   // SiLU'(Z1..Z3)
 
+constexpr int kRefGrid = 4097;          // reference-rotation table points
+constexpr double kRefFmax = 1600.0;     // table span of f = f_z + f_B0 [Hz]
+constexpr double kResidualScale = 8.0;  // network output = kResidualScale (K - K_ref)
+
 struct MlpNorm {
     float center[5];     // features: f_z [Hz], f_B0 [Hz], ln T1, ln T2, B1 scale
     float inv_scale[5];  // u_k = (feature_k - center_k) * inv_scale_k
     double half;         // tau/2 of the modelled pulse [s]
+    const float4 *ref;   // [kRefGrid] (angle, axis x, y, z) of the reference rotation
 };
 
 struct MlpTrainArgs {
@@ -77,13 +93,21 @@ struct MlpAdamArgs {
 };
 
 struct MlpInferArgs {
-    const float *tuples;
-    const int32_t *idx;  // optional gather
+    const float *tuples;  // [.][5], gathered through idx when set
+    const int32_t *idx;
     int64_t N;
     const uint4 *wf;
     const float *params;
     MlpNorm norm;
     float *out;  // [N][12] transition T (A row-major, b)
+    // Optional tuple source instead of `tuples`: phantom arrays, tuple k =
+    // (fz_per_m z[k], df[k], t1[k], t2[k], 1).
+    const float *src_z, *src_df, *src_t1, *src_t2;
+    double fz_per_m;
+    // Optional output instead of `out`: three float4 row planes,
+    // rows[i * row_stride + k] = (A_i0, A_i1, A_i2, b_i).
+    float4 *rows;
+    int64_t row_stride;
 };
 
 struct MlpExactArgs {
@@ -105,12 +129,16 @@ hipError_t launch_mlp_pack(const float *w, uint16_t *wf, uint16_t *wb, hipStream
 hipError_t launch_mlp_infer(const MlpInferArgs &a, hipStream_t st);
 hipError_t launch_mlp_exact(const MlpExactArgs &a, hipStream_t st);
 hipError_t launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
-hipError_t launch_mlp_targets(const float *tuples, const double *T, int64_t N, double half,
+hipError_t launch_mlp_targets(const float *tuples, const double *T, int64_t N, const MlpNorm &norm,
                               float *K, hipStream_t st);
 hipError_t launch_surr_tuples(const float4 *gtab, int64_t n, double fz_per_m, float *tuples,
                               hipStream_t st);
 hipError_t launch_surr_store(const float *T32, int64_t n, double *T64, hipStream_t st);
 hipError_t launch_surr_check(const float *T32, const int32_t *idx, const double *exact, int n_check,
                              float tol, float *residual, int32_t *fallback, hipStream_t st);
+hipError_t launch_surr_check_rows(const float4 *rows, int64_t stride, const int32_t *idx, const double *exact,
+                                  int n_check, float tol, float *residual, int32_t *fallback, hipStream_t st);
+hipError_t launch_surr_iso_tuples(const float *z, const float *df, const float *t1, const float *t2,
+                                  const int32_t *idx, int n, double fz_per_m, float *tuples, hipStream_t st);
 
 }  // namespace gbs

@@ -24,12 +24,17 @@ struct gbs_mlp {
     double dt = 0.0, g_ref = 0.0;
     std::vector<float> rf_re, rf_im, gz;  // host copy for matching sequence blocks
     float4 *wave = nullptr;               // device: B1 re, B1 im, Gz, 0
+    float4 *ref = nullptr;                // device: reference-rotation table (norm.ref)
 };
 
 namespace gbs {
 // Enqueue MLP transitions for n tuples (device) into T32 (device float[n][12]).
 hipError_t mlp_infer_async(const gbs_mlp *m, const float *tuples, const int32_t *idx, int64_t n, float *T32,
                            hipStream_t st);
+// Enqueue MLP transitions of phantom isochromats 0 .. n (tuples (g_ref-scaled z,
+// df, t1, t2, B1 scale 1)) into three float4 row planes rows[i * stride + k].
+hipError_t mlp_infer_rows_async(const gbs_mlp *m, const float *z, const float *df, const float *t1, const float *t2,
+                                int64_t n, float4 *rows, int64_t stride, hipStream_t st);
 // Enqueue exact transitions (FP64) of the pulse; gate as in MlpExactArgs.
 hipError_t mlp_exact_async(const gbs_mlp *m, const float *tuples, const int32_t *idx, int64_t n,
                            const int32_t *gate, double *T64, hipStream_t st);
