@@ -304,7 +304,7 @@ def adjoint_leg(gb, steps):
             "forward_ms": f * 1e3, "backward_ms": b * 1e3, "backward_over_forward": b / f,
             "forward_iso_steps_per_s": ph.K * S / f, "backward_iso_steps_per_s": ph.K * S / b,
             "checkpoint_every": 256, "checkpoint_bytes": 12 * ph.K * -(-n_ops // 256),
-            "precision": "FP32 state, FP64 sums over isochromats"}
+            "precision": "compensated FP32 state (hi + lo pairs), FP64 sums over isochromats"}
 
 
 def main():

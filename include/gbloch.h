@@ -475,15 +475,21 @@ int gbs_set_surrogate(gbs_ctx *ctx, gbs_mlp *m, float tol, int32_t n_check, uint
  * Reverse-mode differentiation of the plain simulation (Eq. 2 with U = D R
  * of Eq. A1, A2 per raster step; Eq. 4, 5 for relaxation blocks; Eq. 6) of
  * the context's phantom and sequence, in FP32 with FP64 sums over
- * isochromats.  Parameters: a complex "parameter pulse" of n_rf samples,
+ * isochromats.  The magnetization and the adjoint state are compensated
+ * FP32 pairs (hi + lo, each op's increment added by a two-sum), so that the
+ * small per-step changes are not rounded away coherently.  Parameters: a
+ * complex "parameter pulse" of n_rf samples,
  * played by every listed RF block in place of its own B1, and per-class T1
  * and T2 (isochromat k has class cls[k]; the phantom's own T1/T2 arrays are
  * not used).  For a cotangent w of the signal the backward pass returns the
  * gradient of L = sum_n (w_re[n] Re A_n + w_im[n] Im A_n).
  *
- * The forward pass stores the state every `every` ops (one op = one raster
- * step or one relaxation block; 3 * K floats per checkpoint, owned by the
- * context); the backward pass steps each segment again from its checkpoint,
+ * The sequence is flattened into ops: a relaxation block, a raster step of
+ * a parameter block or with B1 != 0, or a run of raster steps without RF
+ * between two sample boundaries (the closed form of Eq. 4, 5 with the run's
+ * gradient moment; exact, since all its rotations are about z).  The
+ * forward pass stores the state (hi) every `every` ops (3 * K floats per
+ * checkpoint, owned by the context); the backward pass steps each segment again from its checkpoint,
  * keeping the state every 8 ops of the segment (3 * K * every / 8 floats,
  * also owned by the context).
  */

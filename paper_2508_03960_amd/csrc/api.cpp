@@ -2037,39 +2037,68 @@ extern "C" int gbs_adj_forward(gbs_ctx *ctx, const int32_t *cls, int32_t n_class
             return fail(ctx, GBS_E_INVALID, "parameter blocks must be RF blocks of n_rf steps");
         is_par[b] = 1;
     }
-    // flatten the sequence: one op per raster step or relaxation block; samples by boundary
-    int64_t n_ops = 0;
-    for (const gbs_block &b : s.blocks) n_ops += b.type == GBS_BLOCK_RELAX ? 1 : b.n_steps;
-    if (n_ops > (int64_t)INT32_MAX - 2) return fail(ctx, GBS_E_INVALID, "sequence too long for the adjoint");
-    std::vector<AdjOp> ops((size_t)n_ops);
+    // Flatten the sequence into ops: a relaxation block is one op (Eq. 4, 5);
+    // raster steps of a parameter block, or with B1 != 0, are one op each
+    // (Eq. 2, A1, A2); every other run of raster steps without RF between
+    // two sample boundaries is one op too, the closed form of Eq. 4, 5 with
+    // the run's gradient moment summed in FP64 (with B1 = 0 every step is a
+    // z rotation, so the run's product is exactly that closed form, and its
+    // phase is formed in FP64 once instead of rounded at every step).
+    std::vector<AdjOp> ops;
     std::vector<int32_t> spos((size_t)s.total_samples);
-    int64_t o = 0;
+    std::vector<int64_t> bop;  // op boundary of each raster boundary of the current block
     for (int64_t b = 0; b < nb; ++b) {
         const gbs_block &bk = s.blocks[b];
         if (bk.type == GBS_BLOCK_RELAX) {
-            AdjOp &op = ops[o++];
-            op = AdjOp{};
+            AdjOp op{};
             op.kind = 1;
             op.param = -1;
             op.tau = bk.tau;
             for (int i = 0; i < 3; ++i) op.cyc[i] = kGammaBar * bk.moment[i];
+            ops.push_back(op);
             continue;
         }
-        for (int32_t n = 0; n < bk.n_samples; ++n)
-            spos[bk.sample_offset + n] = (int32_t)(o + s.adc_idx[bk.sample_offset + n]);
-        for (int64_t j = 0; j < bk.n_steps; ++j) {
-            const size_t w = (size_t)(bk.step_offset + j);
-            AdjOp &op = ops[o++];
-            op = AdjOp{};
-            op.kind = 0;
-            op.b1r = s.rf_re[w];
-            op.b1i = s.rf_im[w];
-            op.gx = s.gx[w];
-            op.gy = s.gy[w];
-            op.gz = s.gz[w];
-            op.param = is_par[b] ? (int32_t)j : -1;
+        std::vector<char> cut((size_t)bk.n_steps + 1, 0);  // a sample is taken at this raster boundary
+        for (int32_t n = 0; n < bk.n_samples; ++n) cut[(size_t)s.adc_idx[bk.sample_offset + n]] = 1;
+        bop.assign((size_t)bk.n_steps + 1, -1);
+        int64_t j = 0;
+        while (j < bk.n_steps) {
+            const size_t w0 = (size_t)(bk.step_offset + j);
+            bop[(size_t)j] = (int64_t)ops.size();
+            AdjOp op{};
+            op.param = -1;
+            if (!is_par[b] && s.rf_re[w0] == 0.f && s.rf_im[w0] == 0.f) {
+                double mom[3] = {0.0, 0.0, 0.0};
+                const int64_t j0 = j;
+                do {
+                    const size_t w = (size_t)(bk.step_offset + j);
+                    mom[0] += (double)s.gx[w] * s.dt;
+                    mom[1] += (double)s.gy[w] * s.dt;
+                    mom[2] += (double)s.gz[w] * s.dt;
+                    ++j;
+                } while (j < bk.n_steps && !cut[(size_t)j] && s.rf_re[bk.step_offset + j] == 0.f &&
+                         s.rf_im[bk.step_offset + j] == 0.f);
+                op.kind = 1;
+                op.tau = (double)(j - j0) * s.dt;
+                for (int i = 0; i < 3; ++i) op.cyc[i] = kGammaBar * mom[i];
+            } else {
+                op.kind = 0;
+                op.b1r = s.rf_re[w0];
+                op.b1i = s.rf_im[w0];
+                op.gx = s.gx[w0];
+                op.gy = s.gy[w0];
+                op.gz = s.gz[w0];
+                op.param = is_par[b] ? (int32_t)j : -1;
+                ++j;
+            }
+            ops.push_back(op);
         }
+        bop[(size_t)bk.n_steps] = (int64_t)ops.size();
+        for (int32_t n = 0; n < bk.n_samples; ++n)
+            spos[bk.sample_offset + n] = (int32_t)bop[(size_t)s.adc_idx[bk.sample_offset + n]];
     }
+    const int64_t n_ops = (int64_t)ops.size();
+    if (n_ops > (int64_t)INT32_MAX - 2) return fail(ctx, GBS_E_INVALID, "sequence too long for the adjoint");
     const int64_t N = s.total_samples;
     std::vector<int32_t> samp((size_t)(n_ops + 2 + N), 0);  // sstart[n_ops + 2], then sid[N]
     for (int64_t n = 0; n < N; ++n) samp[spos[n] + 1]++;

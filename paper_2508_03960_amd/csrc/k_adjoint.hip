@@ -3,6 +3,17 @@
 // a parameter RF pulse and per-class T1, T2.  One isochromat per thread,
 // FP32 state, FP64 accumulation of sums over isochromats.
 //
+// Compensated FP32 state.  A raster step changes M by a small increment
+// (relaxation by dt/T of M, rotation by |w| ~ 1e-2); added to M in FP32,
+// most of such an increment is rounded away, and the same way at every step
+// while M changes slowly: a coherent bias that reached 4e-4 of M over the
+// 8-TR workload.  So M and the adjoint state lambda are carried as FP32
+// pairs (hi, lo): each op forms its increment from hi, and a two-sum adds
+// increment + lo to hi, keeping the rounding error in lo.  Relaxation blocks
+// form cos as 1 - c1 and sin as s + sl from an FP64 sincos, and E2 as 1 - om2,
+// so their coefficients carry no rounding that repeats across identical
+// blocks.  Checkpoints hold hi; a recomputed segment starts with lo = 0.
+//
 //  k_adj_forward   plain stepping (Eq. 2 with U = D R of Eq. A1, A2; Eq. 4, 5
 //                  for relaxation blocks), the samples of Eq. 6, and the state
 //                  at every `every`-th op boundary (checkpoints, SoA in HBM).
@@ -144,46 +155,63 @@ __device__ __forceinline__ StepCoef raster_coef(const AdjOp &op, const AdjArgs &
     return r;
 }
 
-// out = v + S (w x v) + sgn... : R v = v + S (w x v) + C (w x (w x v));
-// the transpose uses -S.
-__device__ __forceinline__ void rotate(const StepCoef &c, float S, const float *v, float *out) {
-    const float ax = c.wy * v[2] - c.wz * v[1], ay = c.wz * v[0] - c.wx * v[2], az = c.wx * v[1] - c.wy * v[0];
-    const float bx = c.wy * az - c.wz * ay, by = c.wz * ax - c.wx * az, bz = c.wx * ay - c.wy * ax;
-    out[0] = v[0] + S * ax + c.C * bx;
-    out[1] = v[1] + S * ay + c.C * by;
-    out[2] = v[2] + S * az + c.C * bz;
-}
-
+// Rotation by -phi about z (the phase of Eq. 4, phi = 2 pi cyc), then
+// decay over tau: cos phi = 1 - c1, sin phi = sn + sl (FP64 rounded to an
+// FP32 pair), E2 = 1 - om2.
 struct RelaxCoef {
-    float c, s, e2, om1;
+    float c1, sn, sl, om2, om1;
 };
 
 __device__ __forceinline__ RelaxCoef relax_coef(const AdjOp &op, const Iso &s) {
     RelaxCoef r;
     const double cyc = op.cyc[0] * s.x + op.cyc[1] * s.y + op.cyc[2] * s.z + s.df * op.tau;
-    sincos_rev(cyc, &r.s, &r.c);
-    r.e2 = (float)exp(-op.tau / s.t2);
+    double sh, ch;
+    sincos(kPi * (cyc - rint(cyc)), &sh, &ch);  // half angle
+    const double sn = 2.0 * sh * ch;
+    r.sn = (float)sn;
+    r.sl = (float)(sn - (double)r.sn);
+    r.c1 = (float)(2.0 * sh * sh);
+    r.om2 = (float)(-expm1(-op.tau / s.t2));
     r.om1 = (float)(-expm1(-op.tau / s.t1));
     return r;
 }
 
-// One op on M; v receives the rotated state before relaxation.
-__device__ __forceinline__ void step(const AdjOp &op, const AdjArgs &a, const Iso &s, float *M, float *v) {
+// hi + lo <- hi + lo + d, exactly up to the rounding of d + lo.
+__device__ __forceinline__ void acc_add(float &hi, float &lo, float d) {
+    const float b = d + lo;
+    const float t = hi + b;
+    const float bb = t - hi;
+    lo = (hi - (t - bb)) + (b - bb);
+    hi = t;
+}
+
+// One op on the state (H, L); v receives the rotated state before relaxation
+// (from H).
+__device__ __forceinline__ void step(const AdjOp &op, const AdjArgs &a, const Iso &s, float *H, float *L, float *v) {
+    float d[3];
     if (op.kind == 0) {
         const StepCoef c = raster_coef(op, a, s, false);
-        rotate(c, c.S, M, v);
-        M[0] = v[0] - s.om2 * v[0];
-        M[1] = v[1] - s.om2 * v[1];
-        M[2] = v[2] + s.om1 * (s.m0 - v[2]);
+        const float ax = c.wy * H[2] - c.wz * H[1], ay = c.wz * H[0] - c.wx * H[2], az = c.wx * H[1] - c.wy * H[0];
+        const float bx = c.wy * az - c.wz * ay, by = c.wz * ax - c.wx * az, bz = c.wx * ay - c.wy * ax;
+        const float r[3] = {c.S * ax + c.C * bx, c.S * ay + c.C * by, c.S * az + c.C * bz};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) v[i] = H[i] + r[i];
+        d[0] = r[0] - s.om2 * v[0];
+        d[1] = r[1] - s.om2 * v[1];
+        d[2] = r[2] + s.om1 * (s.m0 - v[2]);
     } else {
         const RelaxCoef r = relax_coef(op, s);
-        v[0] = M[0] * r.c + M[1] * r.s;  // (Mx + i My) e^{-i phase}
-        v[1] = M[1] * r.c - M[0] * r.s;
-        v[2] = M[2];
-        M[0] = r.e2 * v[0];
-        M[1] = r.e2 * v[1];
-        M[2] = v[2] + r.om1 * (s.m0 - v[2]);
+        const float rx = (-r.c1 * H[0] + (r.sn * H[1] + r.sl * H[1])) + (-r.c1 * L[0] + r.sn * L[1]);
+        const float ry = (-r.c1 * H[1] - (r.sn * H[0] + r.sl * H[0])) + (-r.c1 * L[1] - r.sn * L[0]);
+        v[0] = H[0] + rx;
+        v[1] = H[1] + ry;
+        v[2] = H[2];
+        d[0] = rx - r.om2 * v[0];
+        d[1] = ry - r.om2 * v[1];
+        d[2] = r.om1 * (s.m0 - (H[2] + L[2]));
     }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc_add(H[i], L[i], d[i]);
 }
 
 // --------------------------------------------------------------- forward
@@ -193,17 +221,17 @@ __global__ __launch_bounds__(kAdjWG) void k_adj_forward(AdjArgs a) {
     const bool act = k < a.K;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const Iso s = load_iso(a, k, act);
-    float M[3] = {0.f, 0.f, s.m0}, v[3];
+    float H[3] = {0.f, 0.f, s.m0}, L[3] = {0.f, 0.f, 0.f}, v[3];
     for (int p = 0;; ++p) {
         if (p % a.every == 0 && p < a.n_ops && act) {
             float *c = a.ckpt + (int64_t)(p / a.every) * 3 * a.K + k;
-            c[0] = M[0];
-            c[a.K] = M[1];
-            c[2 * a.K] = M[2];
+            c[0] = H[0];
+            c[a.K] = H[1];
+            c[2 * a.K] = H[2];
         }
         const int q1 = uniform_load(a.sstart, p + 1);
         for (int q = uniform_load(a.sstart, p); q < q1; ++q) {  // samples at this boundary (Eq. 6)
-            const float sx = wave_sum_lane63(M[0]), sy = wave_sum_lane63(M[1]);
+            const float sx = wave_sum_lane63(H[0] + L[0]), sy = wave_sum_lane63(H[1] + L[1]);
             if (lane == 63) {
                 ws[wave][0] = sx;
                 ws[wave][1] = sy;
@@ -221,17 +249,19 @@ __global__ __launch_bounds__(kAdjWG) void k_adj_forward(AdjArgs a) {
             __syncthreads();
         }
         if (p == a.n_ops) break;
-        step(load_op(a.ops, p), a, s, M, v);
+        step(load_op(a.ops, p), a, s, H, L, v);
     }
 }
 
 // -------------------------------------------------------------- backward
-__device__ __forceinline__ void add_cotangent(const AdjArgs &a, int p, float *lam) {
+// lambda += the signal cotangent of the samples taken at boundary p.
+__device__ __forceinline__ void add_cotangent(const AdjArgs &a, int p, float *LH, float *LL) {
     const int q1 = uniform_load(a.sstart, p + 1);
     for (int q = uniform_load(a.sstart, p); q < q1; ++q) {
         const double2 w = uniform_load(a.w, uniform_load(a.sid, q));
-        lam[0] += (float)w.x;
-        lam[1] += (float)w.y;
+        const float wx = (float)w.x, wy = (float)w.y;
+        acc_add(LH[0], LL[0], wx + (float)(w.x - (double)wx));
+        acc_add(LH[1], LL[1], wy + (float)(w.y - (double)wy));
     }
 }
 
@@ -240,15 +270,17 @@ struct TAcc {
     double x1, x2;  // relaxation blocks: the same terms times tau
 };
 
-// Back through op `op` whose rotated state is v; lam = lambda' on entry, lambda on exit.
-__device__ __forceinline__ void back_step(const AdjOp &op, const AdjArgs &a, const Iso &s, const float *v, float *lam,
-                                          TAcc &t, float2 *rfg, int lane) {
+// Back through op `op` whose rotated state is v: lambda' = (LH, LL) on entry,
+// lambda = (D R)^T lambda' on exit, formed as an increment and two-summed.
+__device__ __forceinline__ void back_step(const AdjOp &op, const AdjArgs &a, const Iso &s, const float *v, float *LH,
+                                          float *LL, TAcc &t, float2 *rfg, int lane) {
+    float d[3];
     if (op.kind == 0) {
         const float Mx = v[0] - s.om2 * v[0], My = v[1] - s.om2 * v[1], Mz = v[2] + s.om1 * (s.m0 - v[2]);
-        t.r2 += (double)(lam[0] * Mx + lam[1] * My);
-        t.r1 += (double)(lam[2] * (Mz - s.m0));
-        const float e2 = 1.f - s.om2, e1 = 1.f - s.om1;
-        const float mu[3] = {e2 * lam[0], e2 * lam[1], e1 * lam[2]};
+        t.r2 += (double)(LH[0] * Mx + LH[1] * My);
+        t.r1 += (double)(LH[2] * (Mz - s.m0));
+        const float d1[3] = {-s.om2 * LH[0], -s.om2 * LH[1], -s.om1 * LH[2]};  // D lambda' - lambda'
+        const float mu[3] = {LH[0] + d1[0], LH[1] + d1[1], LH[2] + d1[2]};
         const StepCoef c = raster_coef(op, a, s, true);
         if (op.param >= 0) {  // wave-uniform
             const float wv[3] = {v[1] * mu[2] - v[2] * mu[1], v[2] * mu[0] - v[0] * mu[2], v[0] * mu[1] - v[1] * mu[0]};
@@ -263,21 +295,32 @@ __device__ __forceinline__ void back_step(const AdjOp &op, const AdjArgs &a, con
                 atomicAdd(&rfg[op.param].y, sy);
             }
         }
-        rotate(c, -c.S, mu, lam);  // R^T mu
+        // R^T mu - mu = -S (w x mu) + C (w x (w x mu))
+        const float ax = c.wy * mu[2] - c.wz * mu[1], ay = c.wz * mu[0] - c.wx * mu[2], az = c.wx * mu[1] - c.wy * mu[0];
+        const float bx = c.wy * az - c.wz * ay, by = c.wz * ax - c.wx * az, bz = c.wx * ay - c.wy * ax;
+        d[0] = d1[0] + (-c.S * ax + c.C * bx);
+        d[1] = d1[1] + (-c.S * ay + c.C * by);
+        d[2] = d1[2] + (-c.S * az + c.C * bz);
     } else {
         const RelaxCoef r = relax_coef(op, s);
-        const float Mx = r.e2 * v[0], My = r.e2 * v[1], Mz = v[2] + r.om1 * (s.m0 - v[2]);
-        t.x2 += (double)(lam[0] * Mx + lam[1] * My) * op.tau;
-        t.x1 += (double)(lam[2] * (Mz - s.m0)) * op.tau;
-        const float mux = r.e2 * lam[0], muy = r.e2 * lam[1];
-        lam[0] = r.c * mux - r.s * muy;
-        lam[1] = r.s * mux + r.c * muy;
-        lam[2] = (1.f - r.om1) * lam[2];
+        const float e2v0 = v[0] - r.om2 * v[0], e2v1 = v[1] - r.om2 * v[1];
+        const float Mz = v[2] + r.om1 * (s.m0 - v[2]);
+        t.x2 += (double)(LH[0] * e2v0 + LH[1] * e2v1) * op.tau;
+        t.x1 += (double)(LH[2] * (Mz - s.m0)) * op.tau;
+        // mu = E2 lambda'_xy; lambda_xy = P(phi) mu (the transpose of the forward's rotation by -phi)
+        const float mx = LH[0] - r.om2 * LH[0], my = LH[1] - r.om2 * LH[1];
+        const float rx = -r.c1 * mx - (r.sn * my + r.sl * my);
+        const float ry = -r.c1 * my + (r.sn * mx + r.sl * mx);
+        d[0] = (mx - LH[0]) + rx;
+        d[1] = (my - LH[1]) + ry;
+        d[2] = -r.om1 * LH[2];
     }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) acc_add(LH[i], LL[i], d[i]);
 }
 
-// 4 waves per SIMD: 128 VGPRs (a few spills outside the op loops).  LDS holds
-// 25 KiB of accumulators per workgroup, so registers set the occupancy.
+// 4 waves per SIMD: 128 VGPRs.  LDS holds 25 KiB of accumulators per
+// workgroup, so registers set the occupancy.
 __global__ __launch_bounds__(kAdjWG) __attribute__((amdgpu_waves_per_eu(4))) void k_adj_backward(AdjArgs a) {
     __shared__ double tg[kAdjMaxClasses][2];
     __shared__ float2 rfg[kAdjMaxRf];
@@ -288,18 +331,18 @@ __global__ __launch_bounds__(kAdjWG) __attribute__((amdgpu_waves_per_eu(4))) voi
     for (int j = tid; j < kAdjMaxClasses * 2; j += kAdjWG) tg[j >> 1][j & 1] = 0.0;
     __syncthreads();
     const Iso s = load_iso(a, k, act);
-    float lam[3] = {0.f, 0.f, 0.f};
+    float LH[3] = {0.f, 0.f, 0.f}, LL[3] = {0.f, 0.f, 0.f};
     TAcc t = {0.0, 0.0, 0.0, 0.0};
-    add_cotangent(a, a.n_ops, lam);
+    add_cotangent(a, a.n_ops, LH, LL);
     const int n_seg = (a.n_ops + a.every - 1) / a.every;
     for (int seg = n_seg - 1; seg >= 0; --seg) {
         const int p0 = seg * a.every, p1 = min(p0 + a.every, a.n_ops);
-        float M[3] = {0.f, 0.f, 0.f}, v[3];
+        float H[3] = {0.f, 0.f, 0.f}, L[3] = {0.f, 0.f, 0.f}, v[3];
         if (act) {
             const float *c = a.ckpt + (int64_t)seg * 3 * a.K + k;
-            M[0] = c[0];
-            M[1] = c[a.K];
-            M[2] = c[2 * a.K];
+            H[0] = c[0];
+            H[1] = c[a.K];
+            H[2] = c[2 * a.K];
         }
         // sub-checkpoints in HBM, one column per thread (coalesced), so that
         // LDS holds only the gradient accumulators and occupancy is set by
@@ -307,30 +350,31 @@ __global__ __launch_bounds__(kAdjWG) __attribute__((amdgpu_waves_per_eu(4))) voi
         for (int p = p0; p < p1; ++p) {
             if (act && ((p - p0) & (kAdjSub - 1)) == 0) {
                 float *c = a.sub + (int64_t)((p - p0) / kAdjSub) * 3 * a.K + k;
-                c[0] = M[0];
-                c[a.K] = M[1];
-                c[2 * a.K] = M[2];
+                c[0] = H[0];
+                c[a.K] = H[1];
+                c[2 * a.K] = H[2];
             }
-            step(load_op(a.ops, p), a, s, M, v);
+            step(load_op(a.ops, p), a, s, H, L, v);
         }
         const int n_sub = (p1 - p0 + kAdjSub - 1) / kAdjSub;
         for (int sb = n_sub - 1; sb >= 0; --sb) {
             const int q0 = p0 + sb * kAdjSub, cnt = min(kAdjSub, p1 - q0);
+            float SL[3] = {0.f, 0.f, 0.f};
             if (act) {
                 const float *c = a.sub + (int64_t)sb * 3 * a.K + k;
-                M[0] = c[0];
-                M[1] = c[a.K];
-                M[2] = c[2 * a.K];
+                H[0] = c[0];
+                H[1] = c[a.K];
+                H[2] = c[2 * a.K];
             }
             float V[kAdjSub][3];
 #pragma unroll
             for (int i = 0; i < kAdjSub; ++i)
-                if (i < cnt) step(load_op(a.ops, q0 + i), a, s, M, V[i]);
+                if (i < cnt) step(load_op(a.ops, q0 + i), a, s, H, SL, V[i]);
 #pragma unroll
             for (int i = kAdjSub - 1; i >= 0; --i) {
                 if (i < cnt) {
-                    back_step(load_op(a.ops, q0 + i), a, s, V[i], lam, t, rfg, lane);
-                    add_cotangent(a, q0 + i, lam);
+                    back_step(load_op(a.ops, q0 + i), a, s, V[i], LH, LL, t, rfg, lane);
+                    add_cotangent(a, q0 + i, LH, LL);
                 }
             }
         }

@@ -5,17 +5,20 @@ samples with Gz, 8 phase lines x 64 samples, TR 10 ms) on the 256x256x16
 six-class phantom (1,048,576 isochromats).  Checks:
 
 * against the FP64 oracle adjoint (oracle/bloch_adjoint.c) on a seeded
-  4096-isochromat subset: the signal within the usual 1e-4 relative bar; the
-  gradients within 2e-3 relative (L2 for the RF gradient), a bar derived from
-  the FP32 stepping error, which grows to ~1e-4 of M over the 29k ops and
-  enters the gradient both through M and through the adjoint state;
+  4096-isochromat subset, for the 8-TR workload and for a sequence four
+  times longer (32 TRs): the signal within the usual 1e-4 relative bar; the
+  RF gradient within 1e-4 (relative L2) and every class T1 and T2 derivative
+  within 5e-4 relative.  The kernels carry M and the adjoint state as
+  compensated FP32 pairs, so that the small per-step increments are not
+  rounded away the same way at every step; measured errors are 3e-6 to
+  1e-4 and barely grow from 8 to 32 TRs;
 * against central finite differences (relative step 1e-4) of the FP64 plain
   GPU path at full size, along seeded random directions of the pulse and for
-  every class T1 and T2: the same 2e-3 bar, norm-wise over the vector of the
-  12 T1/T2 derivatives (a class sum that cancels to a small value keeps only
-  the absolute FP32 accuracy of its terms).  Differences of FP32 forward
-  passes cannot serve: their rounding noise at this step is several per
-  cent;
+  every class T1 and T2: 1e-4 for the pulse directions and 2e-4 norm-wise
+  over the vector of the 12 T1/T2 derivatives (a class sum that cancels to a
+  small value keeps only the absolute accuracy of its terms).  Differences
+  of FP32 forward passes cannot serve: their rounding noise at this step is
+  several per cent;
 * the torch.autograd.Function wrapper returns exactly the C ABI's gradient;
 * the checkpoint interval (256, 16, 8) does not change the result.
 """
@@ -74,10 +77,16 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def test_subset_vs_oracle_gradient(env):
+@pytest.mark.parametrize("n_lines", [8, 32])
+def test_subset_vs_oracle_gradient(env, n_lines):
+    """8 TRs (the workload) and 32 TRs (four times longer)."""
     gb, torch, ph, t1c, t2c, seq, rf, pb, w = env
+    if n_lines != 8:
+        ph, t1c, t2c, seq, rf, pb = synth.adjoint_workload(n_lines=n_lines)
+        rng = np.random.default_rng(12)
+        w = rng.standard_normal(seq.total_samples) + 1j * rng.standard_normal(seq.total_samples)
     sub = ph.subset(synth.random_subset_indices(ph.K, 4096, seed=7))
-    say(f"[gpu] adjoint: 4096-isochromat subset, {seq.stepped_count()} stepped steps")
+    say(f"[gpu] adjoint: 4096-isochromat subset, {n_lines} TRs, {seq.stepped_count()} stepped steps")
     sim, adj = make(gb, torch, sub, seq, pb)
     sig, g_rf, g1, g2 = run(adj, torch, rf, t1c, t2c, w)
     sim.close()
@@ -90,7 +99,7 @@ def test_subset_vs_oracle_gradient(env):
     say(f"[gpu] adjoint vs oracle: signal rel {r_sig:.2e}; dL/dB1 rel L2 {r_rf:.2e}; "
         f"dL/dT1 max rel {r1:.2e}; dL/dT2 max rel {r2:.2e}")
     assert r_sig <= 1e-4
-    assert r_rf <= 2e-3 and r1 <= 2e-3 and r2 <= 2e-3
+    assert r_rf <= 1e-4 and r1 <= 5e-4 and r2 <= 5e-4
 
 
 def _played(seq, rf, pb):
@@ -159,8 +168,8 @@ def test_fullsize_vs_finite_differences(env):
     say(f"[gpu] adjoint FD: RF directions worst rel {worst_rf:.2e}; T1/T2 vector rel L2 {r_t:.2e}, "
         f"max component error / largest component {r_inf:.2e}")
     # norm-wise bars: a class sum that cancels to a small value keeps only the
-    # absolute FP32 accuracy of its terms
-    assert worst_rf <= 2e-3 and r_t <= 2e-3 and r_inf <= 2e-3
+    # absolute accuracy of its terms
+    assert worst_rf <= 1e-4 and r_t <= 2e-4 and r_inf <= 2e-4
 
 
 def test_autograd_function_and_checkpoint_interval(env):
@@ -204,5 +213,5 @@ def test_no_parameter_blocks(env):
     r1, r2 = rel(g1, g1_o), rel(g2, g2_o)  # norm-wise: some class sums nearly cancel
     say(f"[gpu] adjoint, no parameter blocks: signal rel {rel(sig, s_o):.2e}; T1 {r1:.2e}; T2 {r2:.2e}")
     assert not np.any(g_rf)
-    assert rel(sig, s_o) <= 1e-4 and r1 <= 2e-3 and r2 <= 2e-3
+    assert rel(sig, s_o) <= 1e-4 and r1 <= 5e-4 and r2 <= 5e-4
 
