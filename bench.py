@@ -119,6 +119,39 @@ def subset_errors(gb, ph, seq, M_full, idx, M_ref, sig_ref):
             "rel_signal": float(np.linalg.norm(s - sig_ref) / np.linalg.norm(sig_ref))}
 
 
+# Algorithmic flops per isochromat and raster step of the plain and adjoint
+# kernels, counted from their source (an FMA counts 2):
+# k_plain (FP64): field 6, |B|^2 2, rotation series and coefficients 39, the
+#   increment of the rotation 35 (cross products 9, B.M 5, three increments
+#   18, adds 3), relaxation 7 -> 89 with B1; without B1 the rotation about z
+#   costs 10 and |B|^2 1 -> 63.
+PLAIN_FLOPS_B1, PLAIN_FLOPS_NO_B1 = 89, 63
+# k_adj_forward (FP32), per raster op: w and |w|^2 14, series S, C, D3 48,
+#   rotation increment 27, rotated state 3, relaxation increment 7, three
+#   compensated adds 21 -> 120.  k_adj_backward per raster op: the op is
+#   stepped twice (segment and sub-segment, 240), then its transpose: T1/T2
+#   terms 14, D lambda 6, coefficients 62, RF gradient (parameter steps) 46,
+#   rotation increment 27, compensated adds 21 -> 416.
+ADJ_FWD_FLOPS, ADJ_BWD_FLOPS = 120, 416
+
+
+def adjoint_raster_ops(seq, param_blocks):
+    """Raster ops of the adjoint's flattened sequence: steps of parameter
+    blocks and steps with B1 != 0 (runs without RF become closed-form ops)."""
+    import numpy as np
+    pb = set(int(b) for b in param_blocks)
+    n = 0
+    for b in range(seq.n_blocks):
+        if seq.btype[b] == 3:
+            continue
+        o, k = int(seq.step_offset[b]), int(seq.n_steps[b])
+        if b in pb:
+            n += k
+        else:
+            n += int(np.count_nonzero((np.asarray(seq.rf_re[o:o + k]) != 0) | (np.asarray(seq.rf_im[o:o + k]) != 0)))
+    return n
+
+
 # FP64 flops of one raster step of the per-isochromat composition [A | b] <- D R [A | b]
 # (k_cached, compose mode; FMA = 2): field and |B|^2 11, rotation coefficients 39,
 # rows of D R 32, the 3x3 by 3x4 product 60, T1 recovery 1.
@@ -296,15 +329,23 @@ def adjoint_leg(gb, steps):
             fwd.append(t_f)
             bwd.append(t_b)
     S = seq.stepped_count()
-    n_ops = S + int(np.sum(np.asarray(seq.btype) == synth.BLOCK_RELAX))
+    n_raster = adjoint_raster_ops(seq, pb)
     f, b = float(np.mean(fwd)), float(np.mean(bwd))
     sim.close()
+    fl_f, fl_b = ADJ_FWD_FLOPS * n_raster * ph.K, ADJ_BWD_FLOPS * n_raster * ph.K
+    rl = lambda kernel, fl, t: {"kernel": kernel, "bound": "alu", "flops": fl,
+                                "achieved": fl / t / 1e12, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                "frac": fl / t / 1e12 / FP32_PEAK_TFLOPS,
+                                "frac_of_nonpacked_fp32": fl / t / 1e12 / FP32_NONPACKED_TFLOPS,
+                                "time": "whole call (kernel dominated)"}
     return {"workload": f"GRE {ph.K} isochromats (256x256x16), {len(pb)} TRs of a 3000-sample complex sinc RF, "
                         f"{seq.total_samples} samples; gradient wrt 3000 complex RF samples + 6 (T1, T2) pairs",
             "forward_ms": f * 1e3, "backward_ms": b * 1e3, "backward_over_forward": b / f,
             "forward_iso_steps_per_s": ph.K * S / f, "backward_iso_steps_per_s": ph.K * S / b,
-            "checkpoint_every": 256, "checkpoint_bytes": 12 * ph.K * -(-n_ops // 256),
-            "precision": "compensated FP32 state (hi + lo pairs), FP64 sums over isochromats"}
+            "checkpoint_every": 256, "raster_ops": n_raster,
+            "precision": "compensated FP32 state (hi + lo pairs), FP64 sums over isochromats",
+            "roofline_forward": rl("k_adj_forward", fl_f, f),
+            "roofline_backward": rl("k_adj_backward", fl_b, b)}
 
 
 def main():
@@ -328,7 +369,7 @@ def main():
     ap.add_argument("--no-table2", action="store_true",
                     help="skip the four sequences of the paper's Table 2 (grouped vs cached) and the EPI read from a Pulseq file")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a 1 GiB device copy (for counter calibration under rocprofv3)")
+                    help="accepted for older command lines: the 1 GiB device copies always run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the simulator has no "
@@ -342,14 +383,20 @@ def main():
     import paper_2508_03960_amd as gb
 
     dev = torch.device("cuda", 0)
-    if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-        log("copy calibration: 3 x 1 GiB device copy done")
+    # measured device-copy bandwidth next to the 8 TB/s nominal: 1 GiB read and
+    # 1 GiB written per copy (also the calibration kernel of the counter runs)
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(3):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 3 * 2 * (1 << 30) / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del a, b
+    log(f"device copy: {copy_gbs:.0f} GB/s (1 GiB read + 1 GiB written per copy)")
 
     t = time.perf_counter()
     ph = synth.brain_like_phantom()
@@ -398,7 +445,8 @@ def main():
                      "avg_launch_ms": sweep_ms, "launches_per_step": n_sw,
                      "hbm_GBs": bytes_launch / (sweep_ms * 1e-3) / 1e9,
                      "frac_of_nonpacked_fp32": achieved / FP32_NONPACKED_TFLOPS,
-                     "grouped_ops_per_launch": stats[-1]["n_passes"] / n_sw},
+                     "grouped_ops_per_launch": stats[-1]["n_passes"] / n_sw,
+                     "copy_GBs_measured": copy_gbs},
         "fse": {"grouped_ms": sec * 1e3, "phases_ms": {k: stats[-1][k] for k in
                                                       ("ms_prepare", "ms_passes", "ms_adc_eval")},
                 "build_groups_s": t_groups},
@@ -552,11 +600,19 @@ def main():
         sig_shot = torch.empty(shot.total_samples, 2, device=dev, dtype=torch.float64)
         sec_p, _ = timed_runs(sim, gb, gb.GBS_PLAIN, 1, 1, m_out, sig_shot)
         rate_p = K * shot.stepped_count() / sec_p
+        rf_blocks = [b for b in range(shot.n_blocks) if shot.btype[b] != 3 and
+                     np.any(np.asarray(shot.rf_re[shot.step_offset[b]:shot.step_offset[b] + shot.n_steps[b]]) != 0)]
+        s_b1 = int(sum(int(shot.n_steps[b]) for b in rf_blocks))
+        fl_p = K * (PLAIN_FLOPS_B1 * s_b1 + PLAIN_FLOPS_NO_B1 * (shot.stepped_count() - s_b1))
         out["plain"] = {"workload": "FSE first shot (17 RF + 16 ADC blocks, 67,384 stepped steps) at full K, FP64",
                         "ms": sec_p * 1e3, "iso_steps_per_s": rate_p,
                         "precision": "FP64 state and coefficients (the only plain stepper: FP32 stepping "
                                      "misses the 1e-5 bar by ~30x)",
-                        "fse_full_s_extrapolated": K * S_fse / rate_p}
+                        "fse_full_s_extrapolated": K * S_fse / rate_p,
+                        "roofline": {"kernel": "k_plain", "bound": "alu", "flops": fl_p,
+                                     "achieved": fl_p / sec_p / 1e12, "peak": FP64_PEAK_TFLOPS,
+                                     "unit": "TFLOP/s (FP64)", "frac": fl_p / sec_p / 1e12 / FP64_PEAK_TFLOPS,
+                                     "time": "whole call (kernel dominated)"}}
         out["fse"]["speedup_grouped_fp32_vs_plain_fp64"] = value / rate_p
         log(f"FSE plain shot: {sec_p * 1e3:.1f} ms, {rate_p:.3e} iso-steps/s")
 

@@ -801,6 +801,13 @@ static bool in_emit_kernel(int need, bool coils) {
     return (need & kEmitOnly) && !coils && !(need & (kNeedGy | kNeedZ | kForceGeneral));
 }
 
+// Does a sweep with these needs run in a kernel of 8 isochromats per thread
+// that can write per-wavefront partial sums (k_sweep, k_sweep_pairs,
+// k_sweep_emit), i.e. not the general or the coil sweep?
+static bool in_partial_kernel(int need, bool coils) {
+    return !coils && !(need & (kNeedGy | kNeedZ | kForceGeneral));
+}
+
 static int build_grouped_plan(gbs_ctx *ctx) {
     GroupedPlan &g = ctx->gp;
     const HostSeq &s = ctx->seq;
@@ -1312,15 +1319,16 @@ static int build_grouped_plan(gbs_ctx *ctx) {
             }
         }
     }
-    // emission-only segments: x-group sums through per-wavefront partials
-    // (kPartials) instead of memory-side atomics, one PartJob per emission
+    // x-group sums of the emissions through per-wavefront partials
+    // (kPartials) instead of memory-side atomics, one PartJob per emission,
+    // in every segment that runs in a kernel of 8 isochromats per thread
     std::vector<PartJob> pj;
     {
-        const int64_t n_waves = 4 * ((ctx->Kint / 8 + 255) / 256);  // k_sweep_emit: 8 isochromats per thread
+        const int64_t n_waves = 4 * ((ctx->Kint / 8 + 255) / 256);  // 8 isochromats per thread
         int64_t n_part = 0;
         const bool coils = ctx->coil_re != nullptr;
         for (const auto &sg : g.segs)
-            if (in_emit_kernel(sg.need, coils))
+            if (in_partial_kernel(sg.need, coils))
                 for (int o = sg.op_begin; o < sg.op_end; ++o)
                     if ((sops[o].flags & kOpEmit) && sops[o].emit_axis == 0) ++n_part;
         if (n_part) g.w_part = w.take(sizeof(float4) * (size_t)n_waves * (size_t)n_part);
@@ -1328,7 +1336,7 @@ static int build_grouped_plan(gbs_ctx *ctx) {
         g.seg_parts.assign(g.segs.size(), {0, 0});
         for (size_t si = 0; si < g.segs.size(); ++si) {
             GroupedPlan::Seg &sg = g.segs[si];
-            if (!in_emit_kernel(sg.need, coils)) continue;
+            if (!in_partial_kernel(sg.need, coils)) continue;
             const int first = (int)pj.size();
             for (int o = sg.op_begin; o < sg.op_end; ++o) {
                 SweepOp &op = sops[o];
@@ -1381,8 +1389,9 @@ static int build_grouped_plan(gbs_ctx *ctx) {
     add_relocs<AdcJobDev>(g.relocs, img, g.o_adc, aj.size(), {offsetof(AdcJobDev, gsum)});
     add_relocs<AdcLinJob>(g.relocs, img, g.o_adclin, lj.size(), {offsetof(AdcLinJob, gsum)});
     add_relocs<SweepOp>(g.relocs, img, g.o_sweep, sops.size(),
-                        {offsetof(SweepOp, pre_xtab), offsetof(SweepOp, pre_ztab), offsetof(SweepOp, ttab),
-                         offsetof(SweepOp, emit_xtab), offsetof(SweepOp, emit_ztab), offsetof(SweepOp, gsum)});
+                        {offsetof(SweepOp, pre_xtab), offsetof(SweepOp, part), offsetof(SweepOp, pre_ztab),
+                         offsetof(SweepOp, ttab), offsetof(SweepOp, emit_xtab), offsetof(SweepOp, emit_ztab),
+                         offsetof(SweepOp, gsum)});
     add_relocs<PartJob>(g.relocs, img, g.o_part, pj.size(), {offsetof(PartJob, part), offsetof(PartJob, gsum)});
     ALLOC(ctx->jobs, jbytes);
     g.uploaded_ws = nullptr;
@@ -1547,7 +1556,7 @@ static int run_grouped(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out
             flops += sg.flops_per_iso * (double)K;
             if (profile) HIPCHK(hipEventRecord(ctx->pev[2 * timed], ctx->stream));
             HIPCHK(launch_sweep(a, ctx->stream));
-            if ((a.need & kPartials) && in_emit_kernel(a.need, a.coil != nullptr)) {  // (else atomics were used)
+            if ((a.need & kPartials) && in_partial_kernel(a.need, a.coil != nullptr)) {  // (else atomics were used)
                 const auto &sp = g.seg_parts[item.second];
                 HIPCHK(launch_part_reduce((const PartJob *)(jb + g.o_part) + sp.first, sp.second, ctx->ng[0],
                                           ctx->xstart.as<int32_t>(), ctx->stream));

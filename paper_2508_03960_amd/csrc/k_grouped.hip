@@ -363,6 +363,30 @@ __device__ __forceinline__ void emit_thread(int key, bool uni, float vr, float v
     }
 }
 
+// emit_thread for a kPartials emission: the wavefront's key sums go to its
+// float4 entry `part` (first key, other key) instead of memory-side atomics.
+__device__ __forceinline__ void emit_thread_part(int key, bool uni, float vr, float vi, bool act, float4 *part,
+                                                 double2 *__restrict__ gsum) {
+    if (uni) {
+        vr = wave_sum_lane63(vr);
+        vi = wave_sum_lane63(vi);
+        if (__lane_id() == 63) *part = make_float4(vr, vi, 0.f, 0.f);
+        return;
+    }
+    const int k = act ? key : -1;
+    const int k0 = __builtin_amdgcn_readfirstlane(k), k1 = __builtin_amdgcn_readlane(k, 63);
+    if (__all(k == k0 || k == k1)) {
+        const bool in0 = k == k0;
+        const float ar = wave_sum_lane63(in0 ? vr : 0.f), ai = wave_sum_lane63(in0 ? vi : 0.f);
+        const float br = wave_sum_lane63(in0 ? 0.f : vr), bi = wave_sum_lane63(in0 ? 0.f : vi);
+        if (__lane_id() == 63) *part = make_float4(ar, ai, br, bi);
+        return;
+    }
+    if (__lane_id() == 63) *part = make_float4(0.f, 0.f, 0.f, 0.f);
+    emit_thread(key, false, vr, vi, act, gsum);
+}
+
+
 // v = v * a + b, the result in v's own register.  The compiler's accumulating
 // FMA form would land it in b's register instead, and the state then needs a
 // copy back on every pass of the op loop.
@@ -488,6 +512,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
     const bool act = it < a.n4 / NQ;
     const int64_t i4 = it * NQ;
     const int need = GENERAL ? a.need : (a.need & ~(kNeedGy | kNeedZ));
+    // kPartials: x-emissions write the wavefront's key sums (its 64 threads
+    // hold slots 64 NI wave_id ..) instead of memory-side atomics
+    constexpr bool PART = !GENERAL && !COILS && NI == SWEEP_NI_FAST;
+    const int64_t wave_id = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     // RATIO (the fast sweeps that apply transitions): the registers hold
     // M / M0 instead of M.  A combined transition (A, b) then maps M / M0 to
     // A (M / M0) + b, which saves the product b M0 of every row (three per
@@ -749,7 +777,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                     emit_items<NI>(gy, vr, vi, act, op.gsum);
                 } else {
                     const float sr = tree_sum<NI>(vr), si = tree_sum<NI>(vi);
-                    if (op.emit_axis == 0)
+                    if (op.emit_axis == 0 && PART && (need & kPartials))
+                        emit_thread_part(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.part + wave_id, op.gsum);
+                    else if (op.emit_axis == 0)
                         emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
                     else
                         emit_thread(gz, false, sr, si, act, op.gsum);
@@ -777,7 +807,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
                 }
                 if (!GENERAL && op.emit_ztab) cmul(er, ei, zf.x, zf.y);
                 const float sr = er * pr - ei * pi, si = er * pi + ei * pr;
-                if (op.emit_axis == 0)
+                if (op.emit_axis == 0 && PART && (need & kPartials))
+                    emit_thread_part(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.part + wave_id, op.gsum);
+                else if (op.emit_axis == 0)
                     emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
                 else
                     emit_thread(gz, false, sr, si, act, op.gsum);
@@ -829,29 +861,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SWEEP_WAVES
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_sweep_pairs(
     SweepArgs a) {
     sweep_body<false, SWEEP_NI_FAST, false, true>(a);
-}
-
-// emit_thread for a kPartials emission: the wavefront's key sums go to its
-// float4 entry `part` (first key, other key) instead of memory-side atomics.
-__device__ __forceinline__ void emit_thread_part(int key, bool uni, float vr, float vi, bool act, float4 *part,
-                                                 double2 *__restrict__ gsum) {
-    if (uni) {
-        vr = wave_sum_lane63(vr);
-        vi = wave_sum_lane63(vi);
-        if (__lane_id() == 63) *part = make_float4(vr, vi, 0.f, 0.f);
-        return;
-    }
-    const int k = act ? key : -1;
-    const int k0 = __builtin_amdgcn_readfirstlane(k), k1 = __builtin_amdgcn_readlane(k, 63);
-    if (__all(k == k0 || k == k1)) {
-        const bool in0 = k == k0;
-        const float ar = wave_sum_lane63(in0 ? vr : 0.f), ai = wave_sum_lane63(in0 ? vi : 0.f);
-        const float br = wave_sum_lane63(in0 ? 0.f : vr), bi = wave_sum_lane63(in0 ? 0.f : vi);
-        if (__lane_id() == 63) *part = make_float4(ar, ai, br, bi);
-        return;
-    }
-    if (__lane_id() == 63) *part = make_float4(0.f, 0.f, 0.f, 0.f);
-    emit_thread(key, false, vr, vi, act, gsum);
 }
 
 // The sweep for segments whose ops only emit (an EPI readout train).  The

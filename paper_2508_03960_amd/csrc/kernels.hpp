@@ -71,11 +71,9 @@ struct SweepOp {
     int32_t rf_axis;
     int32_t emit_axis;
     int32_t gsum_stride;     // groups of the emission axis: coil p sums at gsum + p * gsum_stride
-    union {
-        const float4 *pre_xtab;  // per x-group (Re a, Im a, E1, 0); null: no x factor
-        float4 *part;            // kPartials (an emission without pre map): this emission's
-                                 // per-wavefront sums, one float4 per wavefront
-    };
+    const float4 *pre_xtab;  // per x-group (Re a, Im a, E1, 0); null: no x factor
+    float4 *part;            // kPartials: this x-emission's per-wavefront sums, one float4 per
+                             // wavefront of 512 slots (fast and emission-only sweeps)
     const float2 *pre_ztab;  // per z-group phase; null: none
     double pre_cy, pre_cz;   // direct y / z phase coefficients (cycles per metre); 0: none
     const float4 *ttab;      // 3 float4 rows (A_r0, A_r1, A_r2, b_r) per group of rf_axis
