@@ -231,6 +231,30 @@ hipError_t launch_tables(const TabJob *jobs, int n_jobs, int max_n, const float4
 #ifndef SWEEP_NI_FAST
 #define SWEEP_NI_FAST 8  // isochromats per thread in the fast sweep
 #endif
+
+// The workgroups of a dispatch go to the 8 XCDs round robin (workgroup i to
+// XCD i % 8), and each XCD has its own L2.  The sweeps read, at every
+// operation, one table row per group of the wavefront (x-group factors,
+// transitions); with consecutive slots on different XCDs every XCD fetches
+// rows from the whole table, about 1.1 GB per FSE launch.  A sweep grid is
+// therefore padded to a multiple of 8 kXcdChunk and the logical blocks are
+// dealt to the XCDs in chunks of kXcdChunk consecutive ones: the 16 blocks
+// (about 22 x-groups) of a chunk share their rows in one L2, while the
+// chunks of one XCD still come from the whole layout, so that regions of
+// costlier waves (many small groups) spread over all XCDs.  Logical blocks
+// past the end exit at once.
+constexpr int kXcds = 8;
+constexpr int kXcdChunk = 16;
+
+__device__ __forceinline__ int64_t xcd_block() {
+    const int64_t j = blockIdx.x / kXcds, x = blockIdx.x % kXcds;  // j-th workgroup of XCD x
+    return ((j / kXcdChunk) * kXcds + x) * kXcdChunk + j % kXcdChunk;
+}
+
+static inline unsigned xcd_grid(int64_t blocks) {
+    constexpr int64_t q = (int64_t)kXcds * kXcdChunk;
+    return (unsigned)(q * ((blocks + q - 1) / q));
+}
 #ifndef SWEEP_WAVES_FAST
 #define SWEEP_WAVES_FAST 5
 #endif
@@ -508,14 +532,16 @@ template <bool GENERAL, int NI, bool COILS = false, bool PAIRS = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs &a) {
     constexpr int NQ = NI / 4;  // float4 words per array and thread
     constexpr int MC = COILS ? kSweepMaxCoils : 1;
-    const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t blk = xcd_block();
+    if (blk * 256 >= a.n4 / NQ) return;  // padding of the XCD grid
+    const int64_t it = blk * 256 + threadIdx.x;
     const bool act = it < a.n4 / NQ;
     const int64_t i4 = it * NQ;
     const int need = GENERAL ? a.need : (a.need & ~(kNeedGy | kNeedZ));
     // kPartials: x-emissions write the wavefront's key sums (its 64 threads
     // hold slots 64 NI wave_id ..) instead of memory-side atomics
     constexpr bool PART = !GENERAL && !COILS && NI == SWEEP_NI_FAST;
-    const int64_t wave_id = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t wave_id = blk * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     // RATIO (the fast sweeps that apply transitions): the registers hold
     // M / M0 instead of M.  A combined transition (A, b) then maps M / M0 to
     // A (M / M0) + b, which saves the product b M0 of every row (three per
@@ -879,7 +905,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 template <int NI>
 __device__ __forceinline__ void emit_sweep_body(const SweepArgs &a) {
     constexpr int NQ = NI / 4;
-    const int64_t it = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t blk = xcd_block();
+    if (blk * 256 >= a.n4 / NQ) return;  // padding of the XCD grid
+    const int64_t it = blk * 256 + threadIdx.x;
     const bool act = it < a.n4 / NQ;
     const int64_t i4 = it * NQ;
     const int need = a.need;
@@ -888,7 +916,7 @@ __device__ __forceinline__ void emit_sweep_body(const SweepArgs &a) {
     float yv[NI];
     int gx = 0, gz = 0, gx0 = 0;
     bool gx_uni = true;
-    const int64_t wave_id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // covers slots 512 wave_id ..
+    const int64_t wave_id = blk * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // slots 512 wave_id ..
     // one emission from the thread's sum (pr, pi) of M_c w_c: x- and z-group
     // factors, then the group sums
     auto emit_sum = [&](const SweepOp &op, float pr, float pi) {
@@ -1118,17 +1146,17 @@ hipError_t launch_sweep(const SweepArgs &a, hipStream_t st) {
     if (a.n4 % (SWEEP_NI_FAST / 4)) return hipErrorInvalidValue;  // the layout pads runs to multiples of 8
     if (a.coil) {
         if (a.n_coils < 1 || a.n_coils > kSweepMaxCoils) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_sweep_coils, dim3((unsigned)((a.n4 + 255) / 256)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_sweep_coils, dim3(xcd_grid((a.n4 + 255) / 256)), dim3(256), 0, st, a);
     } else if (a.need & (kNeedGy | kNeedZ | kForceGeneral)) {
-        hipLaunchKernelGGL(k_sweep_general, dim3((unsigned)((a.n4 + 255) / 256)), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(k_sweep_general, dim3(xcd_grid((a.n4 + 255) / 256)), dim3(256), 0, st, a);
     } else {
         const int64_t n = a.n4 / (SWEEP_NI_FAST / 4);
         if (a.need & kEmitOnly)
-            hipLaunchKernelGGL(k_sweep_emit, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+            hipLaunchKernelGGL(k_sweep_emit, dim3(xcd_grid((n + 255) / 256)), dim3(256), 0, st, a);
         else if (a.need & kNeedRun)
-            hipLaunchKernelGGL(k_sweep_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+            hipLaunchKernelGGL(k_sweep_pairs, dim3(xcd_grid((n + 255) / 256)), dim3(256), 0, st, a);
         else
-            hipLaunchKernelGGL(k_sweep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+            hipLaunchKernelGGL(k_sweep, dim3(xcd_grid((n + 255) / 256)), dim3(256), 0, st, a);
     }
     return hipGetLastError();
 }
@@ -1237,7 +1265,6 @@ __global__ void k_gather_state(int64_t K, const int32_t *__restrict__ inv, const
 // run of the layout, i.e. in one cache line of the 16-byte rows, so each XCD
 // takes a contiguous range of caller indices: the line's four rows are then
 // read through one L2 instead of being fetched once per XCD.
-constexpr int kXcds = 8;
 
 __global__ __launch_bounds__(256) void k_gather_state4(int64_t K, int64_t per_xcd, const int32_t *__restrict__ inv,
                                                       const float4 *__restrict__ m4, float *ox, float *oy,
