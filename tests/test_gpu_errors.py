@@ -73,9 +73,13 @@ def test_call_order(gb):
     assert code_of(gb, lambda: sim.build_groups(gb.GBS_AX_Y)) == gb.GBS_E_INVALID  # x axis is required
     assert code_of(gb, lambda: sim.build_groups(gb.GBS_AX_X | gb.GBS_AX_XZ)) == gb.GBS_E_INVALID  # needs z
     assert code_of(gb, lambda: sim.build_groups(gb.GBS_AX_ALL | 32)) == gb.GBS_E_INVALID  # unknown bit
-    # GBS_SURROGATE without a network
+    # GBS_SURROGATE without a network, or with the plain mode; flag 2 (a removed FP32 plain
+    # option) is unknown
     sim.build_groups()
     assert code_of(gb, lambda: sim.simulate(gb.GBS_GROUPED, flags=gb.GBS_SURROGATE)) == gb.GBS_E_INVALID
+    assert code_of(gb, lambda: sim.simulate(gb.GBS_CACHED, flags=gb.GBS_SURROGATE)) == gb.GBS_E_INVALID
+    assert code_of(gb, lambda: sim.simulate(gb.GBS_PLAIN, flags=gb.GBS_SURROGATE)) == gb.GBS_E_INVALID
+    assert code_of(gb, lambda: sim.simulate(gb.GBS_PLAIN, flags=2)) == gb.GBS_E_INVALID
     still_works(gb, sim, ph, seq)
     sim.close()
 
