@@ -452,17 +452,6 @@ def main():
                 "build_groups_s": t_groups},
     }
 
-    # ---- learned RF-transition surrogate (FSE 180-degree pulse) --------------------
-    if not args.no_surrogate:
-        sim.set_sequence(fse)
-        out["surrogate"] = surrogate_leg(sim, gb, ph, fse, sig_fse_exact, m_out, args.steps)
-        log(f"surrogate: {out['surrogate']}")
-
-    # ---- gradient of the signal (adjoint) -------------------------------------------
-    if not args.no_adjoint:
-        out["adjoint"] = adjoint_leg(gb, max(1, min(args.steps, 3)))
-        log(f"adjoint: {out['adjoint']}")
-
     # ---- EPI grouped --------------------------------------------------------------
     if not args.no_epi:
         sim.set_sequence(epi)
@@ -484,6 +473,17 @@ def main():
                                    "max_abs_dM": float(np.max(np.abs(M_epi - m_out.cpu().numpy()))),
                                    "rel_signal": float(np.linalg.norm(s_epi - s_pl) / np.linalg.norm(s_pl))}})
             log(f"EPI plain: {sec_p * 1e3:.1f} ms; grouped vs plain {out['epi']['grouped_vs_plain_fp64']}")
+
+    # ---- learned RF-transition surrogate (FSE 180-degree pulse) --------------------
+    if not args.no_surrogate:
+        sim.set_sequence(fse)
+        out["surrogate"] = surrogate_leg(sim, gb, ph, fse, sig_fse_exact, m_out, args.steps)
+        log(f"surrogate: {out['surrogate']}")
+
+    # ---- gradient of the signal (adjoint) -------------------------------------------
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(gb, max(1, min(args.steps, 3)))
+        log(f"adjoint: {out['adjoint']}")
 
     # ---- conventional method with per-isochromat transition caching (Sec. 2.2) -------------
     if not args.no_cached:
