@@ -9,7 +9,10 @@
 // multiplication with z_g.  Thread layout: 16 consecutive samples per thread
 // ("chunk"), threads with the same chunk split the workgroup's groups
 // ("slices"); slice partials are combined in LDS, one FP64 atomic pair per
-// sample and workgroup.
+// sample and workgroup.  A thread adds its groups' terms (at most
+// kAdcLinGroups / slices, 64 for a 256-sample readout) in FP32, the terms
+// themselves being FP32 products; the slices, workgroups and samples are
+// combined in FP64.
 #include "adc.hpp"
 #include "device_math.hpp"
 
@@ -38,9 +41,9 @@ __global__ __launch_bounds__(kAdcLinWG) void k_adc_lin(const AdcLinJob *__restri
         const int n0 = base + chunk * kAdcLinChunk;
         const int cnt = max(0, min(kAdcLinChunk, j.n_samples - n0));
         const double tau_n0 = j.tau0 + n0 * j.dtau, cyc_n0 = j.cyc0 + n0 * j.dcyc;
-        double ar[kAdcLinChunk], ai[kAdcLinChunk];
+        float ar[kAdcLinChunk], ai[kAdcLinChunk];
 #pragma unroll
-        for (int k = 0; k < kAdcLinChunk; ++k) ar[k] = ai[k] = 0.0;
+        for (int k = 0; k < kAdcLinChunk; ++k) ar[k] = ai[k] = 0.f;
         if (cnt > 0 && g0 + slice < g1) {
             // the next group's table row and sum are loaded one iteration ahead
             float4 p_next = j.gtab[g0 + slice];  // (coord, T1, T2, df)
@@ -64,8 +67,8 @@ __global__ __launch_bounds__(kAdcLinWG) void k_adc_lin(const AdcLinJob *__restri
                 const float zr = ed * cd, zi = -ed * sd;
 #pragma unroll
                 for (int k = 0; k < kAdcLinChunk; ++k) {
-                    ar[k] += (double)fr;
-                    ai[k] += (double)fi;
+                    ar[k] += fr;
+                    ai[k] += fi;
                     const float nr = fr * zr - fi * zi;
                     fi = fr * zi + fi * zr;
                     fr = nr;
@@ -76,14 +79,14 @@ __global__ __launch_bounds__(kAdcLinWG) void k_adc_lin(const AdcLinJob *__restri
         double2 *mine = red + (slice % half) * per_pass + chunk * kAdcLinChunk;
         if (slice < half) {
 #pragma unroll
-            for (int k = 0; k < kAdcLinChunk; ++k) mine[k] = make_double2(ar[k], ai[k]);
+            for (int k = 0; k < kAdcLinChunk; ++k) mine[k] = make_double2((double)ar[k], (double)ai[k]);
         }
         __syncthreads();
         if (slice >= half) {  // each slot has exactly one adding thread
 #pragma unroll
             for (int k = 0; k < kAdcLinChunk; ++k) {
                 const double2 v = mine[k];
-                mine[k] = make_double2(v.x + ar[k], v.y + ai[k]);
+                mine[k] = make_double2(v.x + (double)ar[k], v.y + (double)ai[k]);
             }
         }
         __syncthreads();
