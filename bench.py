@@ -210,6 +210,9 @@ def cached_leg(sim, gb, seq, m_out, sig, steps, ref_M=None, ref_sig=None):
 
 
 MLP_MACS = 5 * 128 + 128 * 128 * 2 + 128 * 12  # multiply-adds per network evaluation
+# per training sample: forward, hidden-layer data gradients (none for the inputs), weight gradients
+TRAIN_FLOPS = 2 * (MLP_MACS + (MLP_MACS - 5 * 128) + MLP_MACS)
+TRAIN_BATCH, TRAIN_LR = 1024, 3e-3
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 
 
@@ -235,7 +238,7 @@ def surrogate_leg(sim, gb, ph, fse, sig_exact, m_out, steps):
     t_data = time.perf_counter() - t0
     epochs = 64
     t0 = time.perf_counter()
-    hist = m.train(tup, T, epochs=epochs, batch=1024, lr_max=3e-3, lr_min=1e-6, seed=2)
+    hist = m.train(tup, T, epochs=epochs, batch=TRAIN_BATCH, lr_max=TRAIN_LR, lr_min=1e-6, seed=2)
     t_train = time.perf_counter() - t0
     del tup, T
     # per-isochromat transitions of the whole phantom (what a per-isochromat method needs)
@@ -254,8 +257,11 @@ def surrogate_leg(sim, gb, ph, fse, sig_exact, m_out, steps):
     ms_inf, ms_ex = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
     err = (Tm.double() - Te).abs().max(dim=1).values
     err_q = torch.quantile(err[:: -(-ph.K // (1 << 24))].float(), torch.tensor([0.5, 0.99], device=err.device))
-    res = {"training": {"samples": 1 << 21, "exact_data_s": t_data, "epochs": epochs, "batch": 1024,
-                        "steps": int(hist.size), "train_s": t_train, "us_per_step": t_train / hist.size * 1e6,
+    res = {"training": {"samples": 1 << 21, "exact_data_s": t_data, "epochs": epochs, "batch": TRAIN_BATCH,
+                        "lr_max": TRAIN_LR, "steps": int(hist.size), "train_s": t_train,
+                        "us_per_step": t_train / hist.size * 1e6,
+                        "samples_per_s": hist.size * TRAIN_BATCH / t_train,
+                        "algorithmic_TFLOPs": TRAIN_FLOPS * hist.size * TRAIN_BATCH / t_train / 1e12,
                         "final_loss": float(hist[-1]),
                         "target": "8 (K - K_ref): residual over the pulse's own B1-scaled rotation table"},
            "per_isochromat_transitions": {

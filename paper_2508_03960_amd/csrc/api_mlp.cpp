@@ -354,16 +354,23 @@ namespace {
 struct TrainBufs {
     Scratch s;
     uint16_t *act_h, *act_l, *dz_h, *dz_l;
-    float *sp, *part, *K;
+    float *K;
     hipError_t alloc(int64_t n, int B) {
         hipError_t e;
         if ((e = s.get((void **)&act_h, sizeof(uint16_t) * kActRows * (size_t)B)) != hipSuccess) return e;
         if ((e = s.get((void **)&act_l, sizeof(uint16_t) * kActRows * (size_t)B)) != hipSuccess) return e;
         if ((e = s.get((void **)&dz_h, sizeof(uint16_t) * kDzRows * (size_t)B)) != hipSuccess) return e;
         if ((e = s.get((void **)&dz_l, sizeof(uint16_t) * kDzRows * (size_t)B)) != hipSuccess) return e;
-        if ((e = s.get((void **)&sp, sizeof(float) * kSpRows * (size_t)B)) != hipSuccess) return e;
-        if ((e = s.get((void **)&part, sizeof(float) * 256 * kGradTiles * (size_t)(B / 32))) != hipSuccess) return e;
         return s.get((void **)&K, sizeof(float) * 12 * (size_t)n);
+    }
+    MlpGradAdamArgs grad_args(int32_t B) const {
+        MlpGradAdamArgs g{};
+        g.act_h = act_h;
+        g.act_l = act_l;
+        g.dz_h = dz_h;
+        g.dz_l = dz_l;
+        g.B = B;
+        return g;
     }
     MlpTrainArgs train_args(const gbs_mlp *m, const float *tuples, int64_t n, int B, float *loss) const {
         MlpTrainArgs a{};
@@ -382,7 +389,6 @@ struct TrainBufs {
         a.act_l = act_l;
         a.dz_h = dz_h;
         a.dz_l = dz_l;
-        a.sp = sp;
         a.loss = loss;
         return a;
     }
@@ -404,13 +410,9 @@ int gbs_mlp_loss_grad(gbs_mlp *m, const float *tuples, const double *T_exact, in
     MCHK(launch_fill_f32(dloss, 1, 0.f, m->stream));
     MCHK(launch_mlp_targets(tuples, T_exact, n, m->norm, tb.K, m->stream));
     MCHK(launch_mlp_train_fb(tb.train_args(m, tuples, n, (int)n, dloss), m->stream));
-    const int slice = n % 256 == 0 ? 256 : 64;
-    MCHK(launch_mlp_wgrad(MlpGradArgs{tb.act_h, tb.act_l, tb.dz_h, tb.dz_l, (int32_t)n, slice, tb.part}, m->stream));
-    MlpAdamArgs ad{};
-    ad.part = tb.part;
-    ad.n_slices = (int32_t)(n / slice);
-    ad.grad_out = grad;
-    MCHK(launch_mlp_adam(ad, m->stream));
+    MlpGradAdamArgs ga = tb.grad_args((int32_t)n);
+    ga.grad_out = grad;
+    MCHK(launch_mlp_grad_adam(ga, m->stream));
     MCHK(hipMemcpyAsync(loss, dloss, sizeof(float), hipMemcpyDeviceToHost, m->stream));
     MCHK(hipStreamSynchronize(m->stream));
     return GBS_OK;
@@ -430,7 +432,7 @@ int gbs_mlp_train(gbs_mlp *m, const float *tuples, const double *T_exact, int64_
         return mfail(m, GBS_E_INVALID, "bad optimizer settings");
     if (!m->has_pulse) return mfail(m, GBS_E_STATE, "no pulse set (the target frame needs its duration)");
     MCHK(hipSetDevice(m->device));
-    const int B = cfg->batch, slice = 256;
+    const int B = cfg->batch;
     const int64_t per_epoch = n / B, total = per_epoch * cfg->epochs;
     TrainBufs tb;
     MCHK(tb.alloc(n, B));
@@ -457,13 +459,10 @@ int gbs_mlp_train(gbs_mlp *m, const float *tuples, const double *T_exact, int64_
             a.pc = pc;
             a.j0 = b * B;
             MCHK(launch_mlp_train_fb(a, m->stream));
-            MCHK(launch_mlp_wgrad(MlpGradArgs{tb.act_h, tb.act_l, tb.dz_h, tb.dz_l, B, slice, tb.part}, m->stream));
             m->t += 1;
             const double frac = (double)k / (double)total;  // first step at lr_max
             const double lr = cfg->lr_min + 0.5 * (cfg->lr_max - cfg->lr_min) * (1.0 + std::cos(kTwoPi * 0.5 * frac));
-            MlpAdamArgs ad{};
-            ad.part = tb.part;
-            ad.n_slices = B / slice;
+            MlpGradAdamArgs ad = tb.grad_args(B);
             ad.w = m->w;
             ad.m = m->m;
             ad.v = m->v;
@@ -476,7 +475,7 @@ int gbs_mlp_train(gbs_mlp *m, const float *tuples, const double *T_exact, int64_
             ad.corr1 = (float)(1.0 / (1.0 - std::pow((double)cfg->beta1, (double)m->t)));
             ad.corr2 = (float)(1.0 / (1.0 - std::pow((double)cfg->beta2, (double)m->t)));
             ad.grad_out = nullptr;
-            MCHK(launch_mlp_adam(ad, m->stream));
+            MCHK(launch_mlp_grad_adam(ad, m->stream));
         }
     }
     if (loss_hist && hist_len > 0) {

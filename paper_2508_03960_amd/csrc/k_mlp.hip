@@ -7,12 +7,14 @@
 //  k_mlp_targets    T -> kResidualScale (K - K_ref): the frame (free
 //                   precession of each half pulse removed), less the
 //                   reference transition.
-//  k_mlp_train_fb   forward and backward pass of one batch, 16 samples per
-//                   wavefront, on v_mfma_f32_16x16x32_bf16; activations stay
-//                   in registers between layers (see the k order below).
-//  k_mlp_wgrad      weight and bias gradients, split-K over the batch.
-//  k_mlp_adam       Adam update of the FP32 master weights, then the BF16
-//                   MFMA fragments are repacked.
+//  k_mlp_train_fb   forward and backward pass of one batch on
+//                   v_mfma_f32_16x16x32_bf16, 16 samples per workgroup, one
+//                   16-neuron tile per wavefront; tiles pass between layers
+//                   through LDS in the B-operand order (see the k order below).
+//  k_mlp_grad_adam  weight and bias gradients (contraction over the batch),
+//                   then the Adam update of the FP32 master weights and the
+//                   repacked BF16 MFMA fragments, one gradient tile per
+//                   workgroup.
 //  k_mlp_infer      forward pass only, weights staged in LDS, 32 samples per
 //                   wavefront and iteration, then K = K_ref + Y / scale and
 //                   T = P(a) K P(a).
@@ -75,7 +77,11 @@ __device__ __forceinline__ void make_frag(const float *lo4, const float *hi4, bf
     }
 }
 
-__device__ __forceinline__ float sigmoid(float z) { return 1.f / (1.f + __expf(-z)); }
+// Logistic function with the hardware reciprocal (v_rcp_f32, within 1 ulp):
+// the IEEE-exact quotient costs nine VALU instructions per activation, a
+// large share of the forward pass, for an error far below the BF16 weight
+// rounding the network already carries.
+__device__ __forceinline__ float sigmoid(float z) { return __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
 
 __device__ __forceinline__ void features(const float *t, const MlpNorm &n, float u[5]) {
     const float v[5] = {t[0], t[1], __logf(t[2]), __logf(t[3]), t[4]};
@@ -303,89 +309,130 @@ hipError_t launch_mlp_targets(const float *tuples, const double *T, int64_t N, c
 }
 
 // ---------------------------------------------------------- k_mlp_train_fb
-// Hidden-layer epilogue: z -> SiLU(z); stores SiLU'(z) and the activation
-// (hi, lo) for the weight gradients; leaves SiLU(z) in h.
-__device__ __forceinline__ void hidden_out(const f32x4 *acc, float (*h)[4], const MlpTrainArgs &a,
-                                           int sp_base, int act_base, int g, int s) {
+// One workgroup per 16 samples, kTrainWaves wavefronts: wavefront w computes
+// neuron tile w (rows 16w..16w+15) of every 128-wide layer.  The next layer's
+// B operand for chunk c is tiles 2c and 2c+1 at the same lane positions (see
+// kperm), so each wavefront publishes its tile's BF16 (hi, lo) halves in LDS
+// and reads the four chunks back after one barrier; the two exchange buffers
+// alternate, so a write can only follow the barrier that ended the previous
+// reads of its buffer.  The 12-output layer and the loss are computed by
+// every wavefront (one tile, 8 MFMAs), which hands each of them dZ4 without
+// another exchange; wavefront 0 alone stores them.
+constexpr int kTrainWaves = 8;
+
+struct TileHL {
+    uint2 h, l;  // rows 4g..4g+3 of a tile, BF16 hi and lo halves
+};
+
+__device__ __forceinline__ uint2 pack4(const uint16_t *v) {
+    return make_uint2((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16));
+}
+
+__device__ __forceinline__ bf16x8 frag_of(uint2 a, uint2 b) {
+    const uint4 u = make_uint4(a.x, a.y, b.x, b.y);
+    bf16x8 r;
+    __builtin_memcpy(&r, &u, 16);
+    return r;
+}
+
+// B operands of the next layer from the exchange buffer.
+__device__ __forceinline__ void frags_from_lds(const TileHL (*x)[64], int lane, bf16x8 *fh, bf16x8 *fl) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const TileHL t0 = x[2 * c][lane], t1 = x[2 * c + 1][lane];
+        fh[c] = frag_of(t0.h, t1.h);
+        fl[c] = frag_of(t0.l, t1.l);
+    }
+}
+
+// Hidden-layer epilogue of one tile: z -> SiLU(z); keeps SiLU'(z) in sp for
+// the backward pass and stores the activation (hi, lo) for the weight
+// gradients.  row = first neuron of the lane (16w + 4g).
+__device__ __forceinline__ TileHL hidden_tile(const f32x4 &acc, const MlpTrainArgs &a, int act_base, int row, int s,
+                                              float *sp) {
     const int64_t B = a.B;
-    // per-lane bases; the row offsets (16m + r) * B are wave-uniform
-    float *sp = a.sp + (sp_base + 4 * g) * B + s;
-    uint16_t *ah = a.act_h + (act_base + 4 * g) * B + s;
-    uint16_t *al = a.act_l + (act_base + 4 * g) * B + s;
+    uint16_t *ah = a.act_h + (act_base + row) * B + s;
+    uint16_t *al = a.act_l + (act_base + row) * B + s;
+    uint16_t hb[4], lb[4];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t off = (16 * m + r) * B;
-            const float z = acc[m][r];
-            const float sg = sigmoid(z);
-            const float y = z * sg;
-            h[m][r] = y;
-            sp[off] = sg * (1.f + z * (1.f - sg));
-            const uint16_t hb = bf16_bits(y);
-            ah[off] = hb;
-            al[off] = bf16_bits(y - bf16_float(hb));
-        }
+    for (int r = 0; r < 4; ++r) {
+        const float z = acc[r];
+        const float sg = sigmoid(z);
+        const float y = z * sg;
+        sp[r] = sg * (1.f + z * (1.f - sg));
+        hb[r] = bf16_bits(y);
+        lb[r] = bf16_bits(y - bf16_float(hb[r]));
+        ah[r * B] = hb[r];
+        al[r * B] = lb[r];
     }
+    return TileHL{pack4(hb), pack4(lb)};
 }
 
-__device__ __forceinline__ void frags_from(const float (*h)[4], bf16x8 *fh, bf16x8 *fl) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) make_frag(h[2 * c], h[2 * c + 1], fh[c], fl[c]);
-}
-
-__device__ __forceinline__ void bias_init(f32x4 *acc, const float *b, int g) {
-#pragma unroll
-    for (int m = 0; m < 8; ++m)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[m][r] = b[16 * m + 4 * g + r];
-}
-
-__device__ __forceinline__ void dense128(f32x4 *acc, const uint4 *wf, int fbase, const bf16x8 *fh,
-                                        const bf16x8 *fl, int lane) {
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const bf16x8 A = ld_frag(wf, fbase + 4 * m + c, lane);
-            acc[m] = mfma(A, fh[c], acc[m]);
-            acc[m] = mfma(A, fl[c], acc[m]);
-        }
-        __builtin_amdgcn_sched_barrier(0);  // keeps fragment loads from piling up in registers
-    }
-}
-
-// dZ = dH * SiLU'(Z); stores dZ (hi, lo); leaves dZ in h.
-__device__ __forceinline__ void backward_out(const f32x4 *acc, float (*h)[4], const MlpTrainArgs &a,
-                                             int sp_base, int dz_base, int g, int s) {
+// dZ = dH * SiLU'(Z) for one tile; stores dZ (hi, lo).
+__device__ __forceinline__ TileHL backward_tile(const f32x4 &acc, const MlpTrainArgs &a, const float *sp, int dz_base,
+                                                int row, int s) {
     const int64_t B = a.B;
-    const float *sp = a.sp + (sp_base + 4 * g) * B + s;
-    uint16_t *dh = a.dz_h + (dz_base + 4 * g) * B + s;
-    uint16_t *dl = a.dz_l + (dz_base + 4 * g) * B + s;
+    uint16_t *dh = a.dz_h + (dz_base + row) * B + s;
+    uint16_t *dl = a.dz_l + (dz_base + row) * B + s;
+    uint16_t hb[4], lb[4];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t off = (16 * m + r) * B;
-            const float d = acc[m][r] * sp[off];
-            h[m][r] = d;
-            const uint16_t hb = bf16_bits(d);
-            dh[off] = hb;
-            dl[off] = bf16_bits(d - bf16_float(hb));
-        }
+    for (int r = 0; r < 4; ++r) {
+        const float d = acc[r] * sp[r];
+        hb[r] = bf16_bits(d);
+        lb[r] = bf16_bits(d - bf16_float(hb[r]));
+        dh[r * B] = hb[r];
+        dl[r * B] = lb[r];
     }
+    return TileHL{pack4(hb), pack4(lb)};
 }
 
-__global__ __launch_bounds__(64) void k_mlp_train_fb(MlpTrainArgs a) {
-    const int lane = threadIdx.x;
+// acc += W(tile w) X over the four 32-neuron chunks, hi then lo per chunk.
+__device__ __forceinline__ f32x4 dense_tile(f32x4 acc, const bf16x8 *A, const bf16x8 *fh, const bf16x8 *fl) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        acc = mfma(A[c], fh[c], acc);
+        acc = mfma(A[c], fl[c], acc);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ void load_a4(const uint4 *frags, int F, int lane, bf16x8 *A) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) A[c] = ld_frag(frags, F + c, lane);
+}
+
+__global__ __launch_bounds__(64 * kTrainWaves) void k_mlp_train_fb(MlpTrainArgs a) {
+    __shared__ TileHL xch[2][kTrainWaves][64];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, col = lane & 15;
+    const int row = 16 * w + 4 * g;  // first neuron of the lane's rows in tile w
     const int B = a.B;
     const int s = blockIdx.x * 16 + col;  // < B by the launch
     const int64_t j = (a.j0 + s) % a.N;
     const int64_t idx = (int64_t)(((uint64_t)a.pa * (uint64_t)j + a.pc) % (uint64_t)a.N);
-    float u[5];
+    // Every global load of the pass is issued here: only the LDS exchanges
+    // then separate the layers.
+    float u[5], tgt[4];
     features(a.tuples + 5 * idx, a.norm, u);
-    if (g == 0) {  // H0 rows: the 5 inputs, then zeros
+    f32x4 b1, b2, b3, b4;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int o = 4 * g + r;
+        tgt[r] = o < 12 ? a.targets[12 * idx + o] : 0.f;
+        b1[r] = a.params[kOffB1 + row + r];
+        b2[r] = a.params[kOffB2 + row + r];
+        b3[r] = a.params[kOffB3 + row + r];
+        b4[r] = o < 12 ? a.params[kOffB4 + o] : 0.f;
+    }
+    const bf16x8 A1 = ld_frag(a.wf, kFragFwdL1 + w, lane), A4b = ld_frag(a.wb, kFragBwdL4 + w, lane);
+    bf16x8 A2[4], A3[4], A4[4], A3b[4], A2b[4];
+    load_a4(a.wf, kFragFwdL2 + 4 * w, lane, A2);
+    load_a4(a.wf, kFragFwdL3 + 4 * w, lane, A3);
+    load_a4(a.wf, kFragFwdL4, lane, A4);
+    load_a4(a.wb, kFragBwdL3 + 4 * w, lane, A3b);
+    load_a4(a.wb, kFragBwdL2 + 4 * w, lane, A2b);
+    if (w == 0 && g == 0) {  // H0 rows: the 5 inputs, then zeros
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const float v = r < 5 ? u[r < 5 ? r : 0] : 0.f;
@@ -394,154 +441,76 @@ __global__ __launch_bounds__(64) void k_mlp_train_fb(MlpTrainArgs a) {
             a.act_l[(int64_t)r * B + s] = bf16_bits(v - bf16_float(hb));
         }
     }
-    f32x4 acc[8];
-    float h[8][4];
     bf16x8 fh[4], fl[4];
+    f32x4 acc;
+    float sp1[4], sp2[4], sp3[4];  // SiLU'(Z1..Z3) of the lane's rows
     // layer 1
     {
         bf16x8 xh, xl;
         input_frag(u, g, xh, xl);
-        bias_init(acc, a.params + kOffB1, g);
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const bf16x8 A = ld_frag(a.wf, kFragFwdL1 + m, lane);
-            acc[m] = mfma(A, xh, acc[m]);
-            acc[m] = mfma(A, xl, acc[m]);
-        }
-        hidden_out(acc, h, a, 0, 16, g, s);
+        acc = mfma(A1, xh, b1);
+        acc = mfma(A1, xl, acc);
+        xch[0][w][lane] = hidden_tile(acc, a, 16, row, s, sp1);
     }
     // layers 2 and 3
-    frags_from(h, fh, fl);
-    bias_init(acc, a.params + kOffB2, g);
-    dense128(acc, a.wf, kFragFwdL2, fh, fl, lane);
-    hidden_out(acc, h, a, 128, 144, g, s);
-    frags_from(h, fh, fl);
-    bias_init(acc, a.params + kOffB3, g);
-    dense128(acc, a.wf, kFragFwdL3, fh, fl, lane);
-    hidden_out(acc, h, a, 256, 272, g, s);
-    // layer 4 and the loss
-    frags_from(h, fh, fl);
-    f32x4 y;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) y[r] = (4 * g + r < 12) ? a.params[kOffB4 + ((4 * g + r) % 12)] : 0.f;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const bf16x8 A = ld_frag(a.wf, kFragFwdL4 + c, lane);
-        y = mfma(A, fh[c], y);
-        y = mfma(A, fl[c], y);
-    }
+    __syncthreads();
+    frags_from_lds(xch[0], lane, fh, fl);
+    acc = dense_tile(b2, A2, fh, fl);
+    xch[1][w][lane] = hidden_tile(acc, a, 144, row, s, sp2);
+    __syncthreads();
+    frags_from_lds(xch[1], lane, fh, fl);
+    acc = dense_tile(b3, A3, fh, fl);
+    xch[0][w][lane] = hidden_tile(acc, a, 272, row, s, sp3);
+    // layer 4 and the loss, in every wavefront
+    __syncthreads();
+    frags_from_lds(xch[0], lane, fh, fl);
+    const f32x4 y = dense_tile(b4, A4, fh, fl);
     float dz[4], lsum = 0.f;
     const float scale = 2.f / (float)(B * 12);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int o = 4 * g + r;
-        float d = 0.f;
-        if (o < 12) d = y[r] - a.targets[12 * idx + o];
+        const float d = o < 12 ? y[r] - tgt[r] : 0.f;
         lsum += d * d;
         dz[r] = d * scale;
-        const uint16_t hb = bf16_bits(dz[r]);
-        a.dz_h[(int64_t)(384 + o) * B + s] = hb;
-        a.dz_l[(int64_t)(384 + o) * B + s] = bf16_bits(dz[r] - bf16_float(hb));
+        if (w == 0) {
+            const uint16_t hb = bf16_bits(dz[r]);
+            a.dz_h[(int64_t)(384 + o) * B + s] = hb;
+            a.dz_l[(int64_t)(384 + o) * B + s] = bf16_bits(dz[r] - bf16_float(hb));
+        }
     }
-    // dH3 = W4^T dZ4
+    // dH3 = W4^T dZ4 (tile w), then dZ3
     {
         const float zero4[4] = {0.f, 0.f, 0.f, 0.f};
         bf16x8 dh, dl;
         make_frag(dz, zero4, dh, dl);
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const bf16x8 A = ld_frag(a.wb, kFragBwdL4 + m, lane);
-            acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
-            acc[m] = mfma(A, dh, acc[m]);
-            acc[m] = mfma(A, dl, acc[m]);
-        }
+        acc = mfma(A4b, dh, f32x4{0.f, 0.f, 0.f, 0.f});
+        acc = mfma(A4b, dl, acc);
     }
-    backward_out(acc, h, a, 256, 256, g, s);  // dZ3
-    frags_from(h, fh, fl);
-#pragma unroll
-    for (int m = 0; m < 8; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
-    dense128(acc, a.wb, kFragBwdL3, fh, fl, lane);  // dH2 = W3^T dZ3
-    backward_out(acc, h, a, 128, 128, g, s);        // dZ2
-    frags_from(h, fh, fl);
-#pragma unroll
-    for (int m = 0; m < 8; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
-    dense128(acc, a.wb, kFragBwdL2, fh, fl, lane);  // dH1 = W2^T dZ2
-    backward_out(acc, h, a, 0, 0, g, s);            // dZ1
-    lsum = wave_sum_lane63(lsum);
-    if (lane == 63) atomicAdd(a.loss, lsum / (float)(B * 12));
+    xch[1][w][lane] = backward_tile(acc, a, sp3, 256, row, s);
+    // dH2 = W3^T dZ3, then dZ2
+    __syncthreads();
+    frags_from_lds(xch[1], lane, fh, fl);
+    acc = dense_tile(f32x4{0.f, 0.f, 0.f, 0.f}, A3b, fh, fl);
+    xch[0][w][lane] = backward_tile(acc, a, sp2, 128, row, s);
+    // dH1 = W2^T dZ2, then dZ1
+    __syncthreads();
+    frags_from_lds(xch[0], lane, fh, fl);
+    acc = dense_tile(f32x4{0.f, 0.f, 0.f, 0.f}, A2b, fh, fl);
+    backward_tile(acc, a, sp1, 0, row, s);
+    if (w == 0) {
+        lsum = wave_sum_lane63(lsum);
+        if (lane == 63) atomicAdd(a.loss, lsum / (float)(B * 12));
+    }
 }
 
 hipError_t launch_mlp_train_fb(const MlpTrainArgs &a, hipStream_t st) {
     if (a.B <= 0 || a.B % 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_mlp_train_fb, dim3((unsigned)(a.B / 16)), dim3(64), 0, st, a);  // 16 samples per wavefront
+    hipLaunchKernelGGL(k_mlp_train_fb, dim3((unsigned)(a.B / 16)), dim3(64 * kTrainWaves), 0, st, a);
     return hipGetLastError();
 }
 
-// -------------------------------------------------------------- k_mlp_wgrad
-__device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
-    const uint4 u = *(const uint4 *)p;
-    bf16x8 r;
-    __builtin_memcpy(&r, &u, 16);
-    return r;
-}
-
-__global__ __launch_bounds__(64) void k_mlp_wgrad(MlpGradArgs a) {
-    const int tile = blockIdx.x, sl = blockIdx.y;
-    const int lane = threadIdx.x, g = lane >> 4, col = lane & 15;
-    int arow, brow, it;
-    if (tile < 16) {
-        it = tile % 2;
-        arow = 16 * (tile / 2);
-        brow = 0;
-        it = it == 1 ? 8 : 0;
-    } else if (tile < 88) {
-        const int t = tile - 16;
-        it = t % 9;
-        arow = 128 + 16 * (t / 9);
-        brow = 16 + 16 * it;
-    } else if (tile < 160) {
-        const int t = tile - 88;
-        it = t % 9;
-        arow = 256 + 16 * (t / 9);
-        brow = 144 + 16 * it;
-    } else {
-        it = tile - 160;
-        arow = 384;
-        brow = 272 + 16 * it;
-    }
-    const bool bias = it == 8;
-    const int64_t B = a.B;
-    const int s0 = sl * a.slice;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    bf16x8 ones;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) ones[i] = (__bf16)(col == 0 ? 1.f : 0.f);
-    for (int k = 0; k < a.slice; k += 32) {
-        const int64_t oa = (arow + col) * B + s0 + k + 8 * g;
-        const bf16x8 ah = ld8(a.dz_h + oa), al = ld8(a.dz_l + oa);
-        if (bias) {
-            acc = mfma(ah, ones, acc);
-            acc = mfma(al, ones, acc);
-        } else {
-            const int64_t ob = (brow + col) * B + s0 + k + 8 * g;
-            const bf16x8 bh = ld8(a.act_h + ob), bl = ld8(a.act_l + ob);
-            acc = mfma(ah, bh, acc);
-            acc = mfma(ah, bl, acc);
-            acc = mfma(al, bh, acc);
-        }
-    }
-    float *o = a.part + ((int64_t)sl * kGradTiles + tile) * 256;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) o[(4 * g + r) * 16 + col] = acc[r];
-}
-
-hipError_t launch_mlp_wgrad(const MlpGradArgs &a, hipStream_t st) {
-    if (a.B <= 0 || a.slice <= 0 || a.slice % 32 || a.B % a.slice) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3(kGradTiles, a.B / a.slice), dim3(64), 0, st, a);
-    return hipGetLastError();
-}
-
-// --------------------------------------------------------- packing, Adam
+// ------------------------------------------------ packing, gradients, Adam
 struct ParamPos {
     int layer;  // 1..4
     bool bias;
@@ -559,17 +528,6 @@ __device__ __forceinline__ ParamPos decode_param(int p) {
     else if (p < kOffB4) q = {4, false, (p - kOffW4) / 128, (p - kOffW4) % 128};
     else q = {4, true, p - kOffB4, 0};
     return q;
-}
-
-// Gradient tile, row and column of a parameter (see k_mlp_wgrad).
-__device__ __forceinline__ void grad_pos(const ParamPos &q, int &tile, int &row, int &col) {
-    const int it = q.bias ? 8 : q.i / 16;
-    col = q.bias ? 0 : q.i % 16;
-    row = q.o % 16;
-    if (q.layer == 1) tile = (q.o / 16) * 2 + (q.bias ? 1 : 0);
-    else if (q.layer == 2) tile = 16 + (q.o / 16) * 9 + it;
-    else if (q.layer == 3) tile = 88 + (q.o / 16) * 9 + it;
-    else tile = 160 + it;
 }
 
 // Inverse of kperm within a 32-chunk: k % 32 -> (g, i).
@@ -614,30 +572,157 @@ hipError_t launch_mlp_pack(const float *w, uint16_t *wf, uint16_t *wb, hipStream
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_mlp_adam(MlpAdamArgs a) {
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= kMlpParams) return;
-    const ParamPos q = decode_param(p);
-    int tile, row, col;
-    grad_pos(q, tile, row, col);
+// ------------------------------------------------------- k_mlp_grad_adam
+// Weight and bias gradients, 16 x 16 tiles: dW = dZ H^T, a contraction over
+// the batch (D rows = output neurons, D columns = input neurons).  Layer 1
+// has 8 x 2 tiles (weights over the 16 padded inputs, bias), layers 2 and 3
+// 8 x 9 and layer 4 1 x 9; the ninth input tile of a layer is its bias,
+// contracted against a ones column.  A workgroup takes one tile; its
+// kGradWaves wavefronts split the batch's 32-sample chunks into contiguous
+// ranges, their sums are added in wavefront order in LDS, and each of the
+// 256 threads then owns one tile entry: it either writes the gradient or
+// applies Adam to the parameter and repacks its BF16 fragments.
+constexpr int kGradWaves = 8;
+constexpr int kGradGroup = 4;
+
+__device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
+    const uint4 u = *(const uint4 *)p;
+    bf16x8 r;
+    __builtin_memcpy(&r, &u, 16);
+    return r;
+}
+
+// Parameter index of entry (row, col) of gradient tile `tile`, -1 for padding.
+__device__ __forceinline__ int param_of(int tile, int row, int col) {
+    if (tile < 16) {
+        const int o = 16 * (tile / 2) + row;
+        if (tile & 1) return col == 0 ? kOffB1 + o : -1;
+        return col < kMlpIn ? kOffW1 + kMlpIn * o + col : -1;
+    }
+    if (tile >= 160) {
+        const int it = tile - 160;
+        if (row >= kMlpOut) return -1;
+        if (it == 8) return col == 0 ? kOffB4 + row : -1;
+        return kOffW4 + kMlpH * row + 16 * it + col;
+    }
+    const bool l2 = tile < 88;
+    const int t = tile - (l2 ? 16 : 88);
+    const int o = 16 * (t / 9) + row, it = t % 9;
+    if (it == 8) return col == 0 ? (l2 ? kOffB2 : kOffB3) + o : -1;
+    return (l2 ? kOffW2 : kOffW3) + kMlpH * o + 16 * it + col;
+}
+
+__global__ __launch_bounds__(64 * kGradWaves) void k_mlp_grad_adam(MlpGradAdamArgs a) {
+    __shared__ float part[kGradWaves][256];
+    const int tile = blockIdx.x;
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    int arow, brow, it;
+    if (tile < 16) {
+        it = tile % 2 == 1 ? 8 : 0;
+        arow = 16 * (tile / 2);
+        brow = 0;
+    } else if (tile < 88) {
+        const int t = tile - 16;
+        it = t % 9;
+        arow = 128 + 16 * (t / 9);
+        brow = 16 + 16 * it;
+    } else if (tile < 160) {
+        const int t = tile - 88;
+        it = t % 9;
+        arow = 256 + 16 * (t / 9);
+        brow = 144 + 16 * it;
+    } else {
+        it = tile - 160;
+        arow = 384;
+        brow = 272 + 16 * it;
+    }
+    const bool bias = it == 8;
+    const int64_t B = a.B;
+    const int e = threadIdx.x;  // tile entry of the update (row e / 16, column e % 16)
+    const int p = e < 256 ? param_of(tile, e / 16, e % 16) : -1;
+    float m0 = 0.f, v0 = 0.f, w0 = 0.f;  // Adam state, loaded ahead of the contraction
+    if (p >= 0 && !a.grad_out) {
+        m0 = a.m[p];
+        v0 = a.v[p];
+        w0 = a.w[p];
+    }
+    const int nc = a.B / 32, c0 = q * nc / kGradWaves, c1 = (q + 1) * nc / kGradWaves;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    bf16x8 ones;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) ones[i] = (__bf16)(col == 0 ? 1.f : 0.f);
+    const uint16_t *pa_h = a.dz_h + (arow + col) * B + 8 * g, *pa_l = a.dz_l + (arow + col) * B + 8 * g;
+    const uint16_t *pb_h = a.act_h + (brow + col) * B + 8 * g, *pb_l = a.act_l + (brow + col) * B + 8 * g;
+    // chunks in groups of kGradGroup, every load of a group issued before its MFMAs
+    int c = c0;
+    for (; c < c1; c += kGradGroup) {
+        const int n = c1 - c < kGradGroup ? c1 - c : kGradGroup;
+        bf16x8 ah[kGradGroup], al[kGradGroup], bh[kGradGroup], bl[kGradGroup];
+#pragma unroll
+        for (int u = 0; u < kGradGroup; ++u) {
+            if (u < n) {
+                ah[u] = ld8(pa_h + 32 * (c + u));
+                al[u] = ld8(pa_l + 32 * (c + u));
+                if (!bias) {
+                    bh[u] = ld8(pb_h + 32 * (c + u));
+                    bl[u] = ld8(pb_l + 32 * (c + u));
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGradGroup; ++u) {
+            if (u < n) {
+                if (bias) {
+                    acc = mfma(ah[u], ones, acc);
+                    acc = mfma(al[u], ones, acc);
+                } else {
+                    acc = mfma(ah[u], bh[u], acc);
+                    acc = mfma(ah[u], bl[u], acc);
+                    acc = mfma(al[u], bh[u], acc);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[q][(4 * g + r) * 16 + col] = acc[r];
+    __syncthreads();
+    if (p < 0) return;
     float gsum = 0.f;
-    for (int sl = 0; sl < a.n_slices; ++sl) gsum += a.part[((int64_t)sl * kGradTiles + tile) * 256 + row * 16 + col];
+#pragma unroll
+    for (int k = 0; k < kGradWaves; ++k) gsum += part[k][e];
     if (a.grad_out) {
         a.grad_out[p] = gsum;
         return;
     }
-    const float m = a.beta1 * a.m[p] + (1.f - a.beta1) * gsum;
-    const float v = a.beta2 * a.v[p] + (1.f - a.beta2) * gsum * gsum;
+    const float m = a.beta1 * m0 + (1.f - a.beta1) * gsum;
+    const float v = a.beta2 * v0 + (1.f - a.beta2) * gsum * gsum;
     a.m[p] = m;
     a.v[p] = v;
-    const float w = a.w[p] - a.lr * (m * a.corr1) / (sqrtf(v * a.corr2) + a.eps);
+    const float w = w0 - a.lr * (m * a.corr1) / (sqrtf(v * a.corr2) + a.eps);
     a.w[p] = w;
-    if (!q.bias) pack_weight(q, bf16_bits(w), a.wf, a.wb);
+    const ParamPos pp = decode_param(p);
+    if (!pp.bias) pack_weight(pp, bf16_bits(w), a.wf, a.wb);
 }
 
-hipError_t launch_mlp_adam(const MlpAdamArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, a);
+hipError_t launch_mlp_grad_adam(const MlpGradAdamArgs &a, hipStream_t st) {
+    if (a.B <= 0 || a.B % 32) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mlp_grad_adam, dim3(kGradTiles), dim3(64 * kGradWaves), 0, st, a);
     return hipGetLastError();
+}
+
+// Hidden-layer bias into the eight accumulator tiles (rows 16m + 4g + r).
+__device__ __forceinline__ void bias_init(f32x4 *acc, const float *b, int g) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[m][r] = b[16 * m + 4 * g + r];
+}
+
+// B operands of the next layer: chunk c is D tiles 2c and 2c+1 (see kperm).
+__device__ __forceinline__ void frags_from(const float (*h)[4], bf16x8 *fh, bf16x8 *fl) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) make_frag(h[2 * c], h[2 * c + 1], fh[c], fl[c]);
 }
 
 // -------------------------------------------------------------- k_mlp_infer

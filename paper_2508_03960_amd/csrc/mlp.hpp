@@ -48,7 +48,6 @@ constexpr int kGradTiles = 169;
 // Training activations, one row per neuron, B samples per row.
 constexpr int kActRows = 400;  // H0 (16: 5 inputs + zeros), H1, H2, H3
 constexpr int kDzRows = 400;   // dZ1, dZ2, dZ3, dZ4 (16: 12 outputs + zeros)
-constexpr int kSpRows = 384;   // SiLU'(Z1..Z3)
 
 constexpr int kRefGrid = 4097;          // reference-rotation table points
 constexpr double kRefFmax = 1600.0;     // table span of f = f_z + f_B0 [Hz]
@@ -72,20 +71,13 @@ struct MlpTrainArgs {
     const float *params;
     MlpNorm norm;
     uint16_t *act_h, *act_l, *dz_h, *dz_l;
-    float *sp;
     float *loss;  // += mean squared error of this batch
 };
 
-struct MlpGradArgs {
+// Weight gradients of the batch written by k_mlp_train_fb, then Adam.
+struct MlpGradAdamArgs {
     const uint16_t *act_h, *act_l, *dz_h, *dz_l;
-    int32_t B;
-    int32_t slice;  // samples per split-K slice (multiple of 32)
-    float *part;    // [B / slice][kGradTiles][16][16]
-};
-
-struct MlpAdamArgs {
-    const float *part;
-    int32_t n_slices;
+    int32_t B;  // batch size (multiple of 32)
     float *w, *m, *v;
     uint16_t *wf, *wb;
     float lr, beta1, beta2, eps, corr1, corr2;  // corr = 1 / (1 - beta^t)
@@ -123,8 +115,7 @@ struct MlpExactArgs {
 };
 
 hipError_t launch_mlp_train_fb(const MlpTrainArgs &a, hipStream_t st);
-hipError_t launch_mlp_wgrad(const MlpGradArgs &a, hipStream_t st);
-hipError_t launch_mlp_adam(const MlpAdamArgs &a, hipStream_t st);
+hipError_t launch_mlp_grad_adam(const MlpGradAdamArgs &a, hipStream_t st);
 hipError_t launch_mlp_pack(const float *w, uint16_t *wf, uint16_t *wb, hipStream_t st);
 hipError_t launch_mlp_infer(const MlpInferArgs &a, hipStream_t st);
 hipError_t launch_mlp_exact(const MlpExactArgs &a, hipStream_t st);
