@@ -128,7 +128,8 @@ __global__ __launch_bounds__(kPlainBlock) void k_plain(PlainArgs a, PlainCoils c
         int j = 0;
         for (int n = 0; n <= ns; ++n) {
             const int jend = n < ns ? sidx[n] - a.step_base : a.n_steps;
-#pragma unroll 2
+            // not unrolled: the Horner steps are inline asm, which the compiler
+            // treats as convergent; at 124-126 VGPRs four waves share a SIMD
             for (; j < jend; ++j) {
                 const StepW w = wave_ptr[j];
                 const R b1r = w.b1r, b1i = w.b1i, b1sq = w.b1sq;

@@ -11,25 +11,35 @@ namespace gbs {
 //   S(q) = sum_n (-q)^n / (2n+1)!,  C(q) = sum_n (-q)^n / (2n+2)!,  q = theta^2.
 // For q <= 1 the series is truncated where the next term is below double
 // precision (n <= 8); larger angles use sqrt and sincos.  FP64 throughout.
+// One Horner step r = q S + c as a single VOP3 FMA with the coefficient c in
+// a scalar register pair.  Left to itself the compiler picks the two-address
+// v_fmac_f64, whose addend is its destination, and then copies the constant
+// into that register at every step: two instructions per term.
+__device__ __forceinline__ double horner(double q, double S, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(q), "v"(S), "s"(c));
+    return r;
+}
+
 struct Series {
     static __device__ __forceinline__ void coeffs(double q, double &S, double &C) {
-        S = fma(q, 8.2206352466243297e-18, -2.8114572543455208e-15);  // 1/19!, -1/17!
-        S = fma(q, S, 7.6471637318198164e-13);                         // 1/15!
-        S = fma(q, S, -1.6059043836821613e-10);                        // -1/13!
-        S = fma(q, S, 2.5052108385441719e-8);                          // 1/11!
-        S = fma(q, S, -2.7557319223985891e-6);                         // -1/9!
-        S = fma(q, S, 1.9841269841269841e-4);                          // 1/7!
-        S = fma(q, S, -8.3333333333333333e-3);                         // -1/5!
-        S = fma(q, S, 1.6666666666666667e-1);                          // 1/3!
+        S = horner(q, 8.2206352466243297e-18, -2.8114572543455208e-15);  // 1/19!, -1/17!
+        S = horner(q, S, 7.6471637318198164e-13);                      // 1/15!
+        S = horner(q, S, -1.6059043836821613e-10);                     // -1/13!
+        S = horner(q, S, 2.5052108385441719e-8);                       // 1/11!
+        S = horner(q, S, -2.7557319223985891e-6);                      // -1/9!
+        S = horner(q, S, 1.9841269841269841e-4);                       // 1/7!
+        S = horner(q, S, -8.3333333333333333e-3);                      // -1/5!
+        S = horner(q, S, 1.6666666666666667e-1);                       // 1/3!
         S = fma(-q, S, 1.0);
-        C = fma(q, 4.1103176233121648e-19, -1.5619206968586226e-16);   // 1/20!, -1/18!
-        C = fma(q, C, 4.7794773323873853e-14);                         // 1/16!
-        C = fma(q, C, -1.1470745597729725e-11);                        // -1/14!
-        C = fma(q, C, 2.0876756987868099e-9);                          // 1/12!
-        C = fma(q, C, -2.7557319223985891e-7);                         // -1/10!
-        C = fma(q, C, 2.4801587301587302e-5);                          // 1/8!
-        C = fma(q, C, -1.3888888888888889e-3);                         // -1/6!
-        C = fma(q, C, 4.1666666666666667e-2);                          // 1/4!
+        C = horner(q, 4.1103176233121648e-19, -1.5619206968586226e-16);  // 1/20!, -1/18!
+        C = horner(q, C, 4.7794773323873853e-14);                      // 1/16!
+        C = horner(q, C, -1.1470745597729725e-11);                     // -1/14!
+        C = horner(q, C, 2.0876756987868099e-9);                       // 1/12!
+        C = horner(q, C, -2.7557319223985891e-7);                      // -1/10!
+        C = horner(q, C, 2.4801587301587302e-5);                       // 1/8!
+        C = horner(q, C, -1.3888888888888889e-3);                      // -1/6!
+        C = horner(q, C, 4.1666666666666667e-2);                       // 1/4!
         C = fma(-q, C, 0.5);
     }
     static __device__ __forceinline__ void big(double B2, double gdt, double &a, double &b) {
