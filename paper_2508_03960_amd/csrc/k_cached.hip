@@ -78,10 +78,10 @@ __global__ __launch_bounds__(kCachedBlock) void k_cached(CachedArgs a) {
         const double e1 = exp(-a.dt / t1), e2 = exp(-a.dt / t2), e1m = -expm1(-a.dt / t1);
         const double gdt = a.gdt, k2 = gdt * gdt;
         // T = [A | b], starting from the identity map
-        double T[3][4] = {{1.0, 0.0, 0.0, 0.0}, {0.0, 1.0, 0.0, 0.0}, {0.0, 0.0, 1.0, 0.0}};
+        double T[3][4] = {{1.0, 0.0, 0.0, 0.0}, {0.0, 1.0, 0.0, 0.0}, {0.0, 0.0, 1.0, 0.0}}, U[3][4];
         const StepW *__restrict__ wave = a.wave;
-#pragma unroll 2
-        for (int j = 0; j < a.n_steps; ++j) {
+        // V = (D R)_j V0 for raster step j, then the T1 recovery toward M0
+        auto step = [&](const double (&V0)[3][4], double (&V)[3][4], int j) {
             const StepW w = wave[j];
             const double bx = w.b1r, by = w.b1i;
             const double bz = fma((double)w.gx, X, fma((double)w.gy, Y, fma((double)w.gz, Z, boff)));
@@ -98,12 +98,26 @@ __global__ __launch_bounds__(kCachedBlock) void k_cached(CachedArgs a) {
             const double r20 = e1 * (pxz - sy), r21 = e1 * (pyz + sx), r22 = e1 * fma(qz, bz, c0);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const double u0 = T[0][c], u1 = T[1][c], u2 = T[2][c];
-                T[0][c] = fma(r00, u0, fma(r01, u1, r02 * u2));
-                T[1][c] = fma(r10, u0, fma(r11, u1, r12 * u2));
-                T[2][c] = fma(r20, u0, fma(r21, u1, r22 * u2));
+                const double u0 = V0[0][c], u1 = V0[1][c], u2 = V0[2][c];
+                V[0][c] = fma(r00, u0, fma(r01, u1, r02 * u2));
+                V[1][c] = fma(r10, u0, fma(r11, u1, r12 * u2));
+                V[2][c] = fma(r20, u0, fma(r21, u1, r22 * u2));
             }
-            T[2][3] += e1m;  // T1 recovery toward M0
+            V[2][3] += e1m;
+        };
+        // two steps per iteration, T -> U -> T, so that the loop carries no
+        // register copies of the twelve entries
+        int j = 0;
+        for (; j + 1 < a.n_steps; j += 2) {
+            step(T, U, j);
+            step(U, T, j + 1);
+        }
+        if (j < a.n_steps) {
+            step(T, U, j);
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) T[r][c] = U[r][c];
         }
         a.cache[k] = make_float4((float)T[0][0], (float)T[0][1], (float)T[0][2], (float)T[0][3]);
         a.cache[K + k] = make_float4((float)T[1][0], (float)T[1][1], (float)T[1][2], (float)T[1][3]);
