@@ -40,28 +40,42 @@
 
 namespace gbs {
 
-// S, C, D3 of t = sqrt(q).  Taylor series below q = 4: the first dropped
-// terms are 4^9 / 19!, 4^9 / 20!, 4^9 / 21! (< 3e-12).
-__device__ __forceinline__ void rot_coeffs(float q, float &S, float &C, float &D3) {
-    if (q < 4.f) {
-        // 1/k! for k = 1 .. 21
-        constexpr float f[22] = {1.f, 1.f, 5.0e-1f, 1.6666666666666666e-1f, 4.1666666666666664e-2f,
-                                 8.3333333333333332e-3f, 1.3888888888888889e-3f, 1.9841269841269841e-4f,
-                                 2.4801587301587302e-5f, 2.7557319223985893e-6f, 2.7557319223985888e-7f,
-                                 2.5052108385441720e-8f, 2.0876756987868100e-9f, 1.6059043836821613e-10f,
-                                 1.1470745597729725e-11f, 7.6471637318198164e-13f, 4.7794773323873853e-14f,
-                                 2.8114572543455206e-15f, 1.5619206968586225e-16f, 8.2206352466243295e-18f,
-                                 4.1103176233121648e-19f, 1.9572941063391263e-20f};
-        float s = f[19], c = f[20], d = f[21];
+// S, C, D3 of t = sqrt(q) from their Taylor series, terms k = 0 .. N:
+//   S = sum_k (-q)^k / (2k+1)!,  C = sum_k (-q)^k / (2k+2)!,
+//   D3 = sum_k (-q)^k / (2k+3)!.
+template <int N>
+__device__ __forceinline__ void rot_series(float q, float &S, float &C, float &D3) {
+    // 1/k! for k = 0 .. 21
+    constexpr float f[22] = {1.f, 1.f, 5.0e-1f, 1.6666666666666666e-1f, 4.1666666666666664e-2f,
+                             8.3333333333333332e-3f, 1.3888888888888889e-3f, 1.9841269841269841e-4f,
+                             2.4801587301587302e-5f, 2.7557319223985893e-6f, 2.7557319223985888e-7f,
+                             2.5052108385441720e-8f, 2.0876756987868100e-9f, 1.6059043836821613e-10f,
+                             1.1470745597729725e-11f, 7.6471637318198164e-13f, 4.7794773323873853e-14f,
+                             2.8114572543455206e-15f, 1.5619206968586225e-16f, 8.2206352466243295e-18f,
+                             4.1103176233121648e-19f, 1.9572941063391263e-20f};
+    static_assert(2 * N + 3 < 22, "series length");
+    float s = f[2 * N + 1], c = f[2 * N + 2], d = f[2 * N + 3];
 #pragma unroll
-        for (int n = 8; n >= 1; --n) {
-            s = f[2 * n - 1] - q * s;
-            c = f[2 * n] - q * c;
-            d = f[2 * n + 1] - q * d;
-        }
-        S = s;
-        C = c;
-        D3 = d;
+    for (int k = N - 1; k >= 0; --k) {
+        s = f[2 * k + 1] - q * s;
+        c = f[2 * k + 2] - q * c;
+        d = f[2 * k + 3] - q * d;
+    }
+    S = s;
+    C = c;
+    D3 = d;
+}
+
+// The series' length follows q: below q = 1/16 five terms leave out at most
+// q^5 / 11! < 2.4e-14 (relative), below q = 4 nine terms at most
+// 4^9 / 19! < 3e-12; larger angles take sqrt and sincos.  Raster steps
+// rotate by far less than a quarter radian, so the short branch is the one
+// taken.
+__device__ __forceinline__ void rot_coeffs(float q, float &S, float &C, float &D3) {
+    if (q < 0.0625f) {
+        rot_series<4>(q, S, C, D3);
+    } else if (q < 4.f) {
+        rot_series<8>(q, S, C, D3);
     } else {
         const float t = sqrtf(q);
         float sn, cs;
