@@ -120,19 +120,23 @@ def subset_errors(gb, ph, seq, M_full, idx, M_ref, sig_ref):
 
 
 # Algorithmic flops per isochromat and raster step of the plain and adjoint
-# kernels, counted from their source (an FMA counts 2):
-# k_plain (FP64): field 6, |B|^2 2, rotation series and coefficients 39, the
+# kernels, counted from their source (an FMA counts 2).  The rotation series
+# are counted at the length a step under a quarter radian needs (q <= 1/16:
+# six FP64 terms per series, five FP32 terms), the case of nearly every
+# raster step; a step with a larger angle executes the longer series, which
+# these figures do not count.
+# k_plain (FP64): field 6, |B|^2 2, rotation series and coefficients 23, the
 #   increment of the rotation 35 (cross products 9, B.M 5, three increments
-#   18, adds 3), relaxation 7 -> 89 with B1; without B1 the rotation about z
-#   costs 10 and |B|^2 1 -> 63.
-PLAIN_FLOPS_B1, PLAIN_FLOPS_NO_B1 = 89, 63
-# k_adj_forward (FP32), per raster op: w and |w|^2 14, series S, C, D3 48,
+#   18, adds 3), relaxation 7 -> 73 with B1; without B1 the rotation about z
+#   costs 10 and |B|^2 1 -> 47.
+PLAIN_FLOPS_B1, PLAIN_FLOPS_NO_B1 = 73, 47
+# k_adj_forward (FP32), per raster op: w and |w|^2 14, series S, C, D3 24,
 #   rotation increment 27, rotated state 3, relaxation increment 7, three
-#   compensated adds 21 -> 120.  k_adj_backward per raster op: the op is
-#   stepped twice (segment and sub-segment, 240), then its transpose: T1/T2
-#   terms 14, D lambda 6, coefficients 62, RF gradient (parameter steps) 46,
-#   rotation increment 27, compensated adds 21 -> 416.
-ADJ_FWD_FLOPS, ADJ_BWD_FLOPS = 120, 416
+#   compensated adds 21 -> 96.  k_adj_backward per raster op: the op is
+#   stepped twice (segment and sub-segment, 192), then its transpose: T1/T2
+#   terms 14, D lambda 6, coefficients 38, RF gradient (parameter steps) 46,
+#   rotation increment 27, compensated adds 21 -> 344.
+ADJ_FWD_FLOPS, ADJ_BWD_FLOPS = 96, 344
 
 
 def adjoint_raster_ops(seq, param_blocks):
@@ -153,9 +157,10 @@ def adjoint_raster_ops(seq, param_blocks):
 
 
 # FP64 flops of one raster step of the per-isochromat composition [A | b] <- D R [A | b]
-# (k_cached, compose mode; FMA = 2): field and |B|^2 11, rotation coefficients 39,
-# rows of D R 32, the 3x3 by 3x4 product 60, T1 recovery 1.
-COMPOSE_FLOPS_PER_ISO_STEP = 143
+# (k_cached, compose mode; FMA = 2): field and |B|^2 11, rotation coefficients 23
+# (the six-term series, as for k_plain), rows of D R 32, the 3x3 by 3x4 product 60,
+# T1 recovery 1.
+COMPOSE_FLOPS_PER_ISO_STEP = 127
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 
 
