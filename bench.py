@@ -13,7 +13,7 @@ the grouped-vs-plain speedup, the roofline of the dominant kernel (the
 fused grouped sweep k_sweep: algorithmic FP32 flops per launch over its
 HIP-event-timed duration) and the FP64 CPU oracle timed on the host cores.
 
-Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1]
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 3]
 """
 import argparse
 import hashlib
@@ -362,8 +362,8 @@ def adjoint_leg(gb, steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-method runs")
     ap.add_argument("--no-epi", action="store_true")
