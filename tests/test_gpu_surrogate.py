@@ -118,11 +118,16 @@ def batch512():
     return _targets(512, 33)
 
 
-def test_loss_grad_vs_oracle(env, batch512, table):
+@pytest.mark.parametrize("n", [64, 192, 512])
+def test_loss_grad_vs_oracle(env, batch512, table, n):
+    """Loss and weight gradient against the FP64 oracle.  The gradient
+    kernel splits the batch's 32-sample chunks over 8 wavefronts: 64 samples
+    leave six of them empty, 192 split unevenly."""
     gb, torch, pulse = env
     m = make_mlp(gb, pulse)
     tup, T = batch512
-    say("[gpu] surrogate: loss and gradient, 512 samples")
+    tup, T = tup[:n], T[:n]
+    say(f"[gpu] surrogate: loss and gradient, {n} samples")
     loss, g = m.loss_grad(torch.from_numpy(tup), torch.from_numpy(T))
     g = g.cpu().numpy().astype(np.float64)
     half = pulse[2] * len(pulse[0]) / 2
