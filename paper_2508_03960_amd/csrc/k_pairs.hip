@@ -39,9 +39,9 @@ __global__ __launch_bounds__(256) void k_compose_pair(int64_t n_runs, const floa
     const double boff = (double)g.w / kGammaBar;
     const double e1 = exp(-dt / t1), e2 = exp(-dt / t2), e1m = -expm1(-dt / t1);
     const double gdt = kTwoPi * kGammaBar * dt, k2 = gdt * gdt;
-    double T[3][4] = {{1.0, 0.0, 0.0, 0.0}, {0.0, 1.0, 0.0, 0.0}, {0.0, 0.0, 1.0, 0.0}};
-#pragma unroll 2
-    for (int j = 0; j < n_steps; ++j) {
+    double T[3][4] = {{1.0, 0.0, 0.0, 0.0}, {0.0, 1.0, 0.0, 0.0}, {0.0, 0.0, 1.0, 0.0}}, U[3][4];
+    // V = (D R)_j V0 for raster step j, then the T1 recovery toward M0
+    auto step = [&](const double (&V0)[3][4], double (&V)[3][4], int j) {
         const StepW w = wave[j];
         const double bx = w.b1r, by = w.b1i;
         const double bz = fma((double)w.gx, X, fma((double)w.gz, Z, boff));
@@ -58,12 +58,26 @@ __global__ __launch_bounds__(256) void k_compose_pair(int64_t n_runs, const floa
         const double r20 = e1 * (pxz - sy), r21 = e1 * (pyz + sx), r22 = e1 * fma(qz, bz, c0);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const double u0 = T[0][c], u1 = T[1][c], u2 = T[2][c];
-            T[0][c] = fma(r00, u0, fma(r01, u1, r02 * u2));
-            T[1][c] = fma(r10, u0, fma(r11, u1, r12 * u2));
-            T[2][c] = fma(r20, u0, fma(r21, u1, r22 * u2));
+            const double u0 = V0[0][c], u1 = V0[1][c], u2 = V0[2][c];
+            V[0][c] = fma(r00, u0, fma(r01, u1, r02 * u2));
+            V[1][c] = fma(r10, u0, fma(r11, u1, r12 * u2));
+            V[2][c] = fma(r20, u0, fma(r21, u1, r22 * u2));
         }
-        T[2][3] += e1m;  // T1 recovery toward M0
+        V[2][3] += e1m;
+    };
+    // two steps per iteration, T -> U -> T: the loop carries no register
+    // copies of the twelve entries
+    int j = 0;
+    for (; j + 1 < n_steps; j += 2) {
+        step(T, U, j);
+        step(U, T, j + 1);
+    }
+    if (j < n_steps) {
+        step(T, U, j);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) T[i][c] = U[i][c];
     }
     double *o = out + 12 * r;
 #pragma unroll
