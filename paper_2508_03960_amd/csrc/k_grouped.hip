@@ -23,6 +23,7 @@
 //              per-component arrays after plain stepping).
 #include "device_math.hpp"
 #include "kernels.hpp"
+#include "rotation.hpp"
 
 namespace gbs {
 
@@ -61,6 +62,7 @@ __global__ __launch_bounds__(256) void k_compose(const RfJobDev *__restrict__ jo
     const double coord = p.x, t1 = p.y, t2 = p.z;
     const double boff = (double)p.w / kGammaBar;
     const double e1 = exp(-dt / t1), e2 = exp(-dt / t2);
+    const double gdt = kTwoPi * kGammaBar * dt, k2 = gdt * gdt;
     const int n = j.n_steps;
     const int lo = (int)(((int64_t)n * lane) >> 6), hi = (int)(((int64_t)n * (lane + 1)) >> 6);
     Aff T;
@@ -69,27 +71,27 @@ __global__ __launch_bounds__(256) void k_compose(const RfJobDev *__restrict__ jo
         const StepW w = j.wave[s];
         const double gv = j.axis == 0 ? w.gx : (j.axis == 1 ? w.gy : w.gz);
         const double bx = w.b1r, by = w.b1i, bz = gv * coord + boff;
-        const double nb = sqrt(bx * bx + by * by + bz * bz);
-        Aff U;  // U = D R (Eq. A1, Eq. A2)
-        if (nb == 0.0) {
-            aff_identity(U);
-        } else {
-            const double ux = bx / nb, uy = by / nb, uz = bz / nb;
-            const double th = -kTwoPi * kGammaBar * nb * dt;
-            double sn, cs;
-            sincos(th, &sn, &cs);
-            const double v = 1.0 - cs;
-            U.a[0] = cs + ux * ux * v;
-            U.a[1] = -uz * sn + ux * uy * v;
-            U.a[2] = uy * sn + ux * uz * v;
-            U.a[3] = uz * sn + ux * uy * v;
-            U.a[4] = cs + uy * uy * v;
-            U.a[5] = -ux * sn + uy * uz * v;
-            U.a[6] = -uy * sn + ux * uz * v;
-            U.a[7] = ux * sn + uy * uz * v;
-            U.a[8] = cs + uz * uz * v;
-            U.b[0] = U.b[1] = U.b[2] = 0.0;
-        }
+        // U = D R (Eq. A1, Eq. A2) with R = (1 - cb |B|^2) I + ca [B]x + cb B B^T,
+        // ca = sin(theta) / |B| and cb = (1 - cos theta) / |B|^2 from their series
+        // (no square root or division; B = 0 gives the identity)
+        const double B2 = fma(bx, bx, fma(by, by, bz * bz));
+        double ca, cb;
+        rot_coeffs(B2, gdt, k2, ca, cb);
+        const double c0 = fma(-cb, B2, 1.0);
+        const double qx = cb * bx, qy = cb * by, qz = cb * bz;
+        const double pxy = qx * by, pxz = qx * bz, pyz = qy * bz;
+        const double sx = ca * bx, sy = ca * by, sz = ca * bz;
+        Aff U;
+        U.a[0] = fma(qx, bx, c0);
+        U.a[1] = pxy - sz;
+        U.a[2] = pxz + sy;
+        U.a[3] = pxy + sz;
+        U.a[4] = fma(qy, by, c0);
+        U.a[5] = pyz - sx;
+        U.a[6] = pxz - sy;
+        U.a[7] = pyz + sx;
+        U.a[8] = fma(qz, bz, c0);
+        U.b[0] = U.b[1] = U.b[2] = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             U.a[c] *= e2;
