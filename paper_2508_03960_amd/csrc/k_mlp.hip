@@ -32,6 +32,7 @@
 #include "consts.hpp"
 #include "device_math.hpp"
 #include "mlp.hpp"
+#include "rotation.hpp"
 
 namespace gbs {
 
@@ -137,27 +138,31 @@ __global__ __launch_bounds__(256) void k_mlp_exact(MlpExactArgs a) {
     const double s1 = act ? (double)tp[4] : 0.0;
     const int n = a.n_steps;
     const int lo = (int)(((int64_t)n * lane) >> 6), hi = (int)(((int64_t)n * (lane + 1)) >> 6);
+    const double gdt = kTwoPi * kGammaBar * a.dt, k2 = gdt * gdt;
     Aff64 T = {{1, 0, 0, 0, 1, 0, 0, 0, 1}, {0, 0, 0}};
     for (int s = lo; s < hi; ++s) {
         const float4 w = a.wave[s];
         const double bx = s1 * w.x, by = s1 * w.y, bz = (double)w.z * z + boff;
-        const double nb = sqrt(bx * bx + by * by + bz * bz);
-        Aff64 U = {{1, 0, 0, 0, 1, 0, 0, 0, 1}, {0, 0, 0}};
-        if (nb > 0.0) {  // Eq. A2
-            const double ux = bx / nb, uy = by / nb, uz = bz / nb;
-            double sn, cs;
-            sincos(-kTwoPi * kGammaBar * nb * a.dt, &sn, &cs);
-            const double v = 1.0 - cs;
-            U.a[0] = cs + ux * ux * v;
-            U.a[1] = -uz * sn + ux * uy * v;
-            U.a[2] = uy * sn + ux * uz * v;
-            U.a[3] = uz * sn + ux * uy * v;
-            U.a[4] = cs + uy * uy * v;
-            U.a[5] = -ux * sn + uy * uz * v;
-            U.a[6] = -uy * sn + ux * uz * v;
-            U.a[7] = ux * sn + uy * uz * v;
-            U.a[8] = cs + uz * uz * v;
-        }
+        // Eq. A2 as R = (1 - cb |B|^2) I + ca [B]x + cb B B^T, with
+        // ca = sin(theta) / |B| and cb = (1 - cos theta) / |B|^2 from their series
+        const double B2 = fma(bx, bx, fma(by, by, bz * bz));
+        double ca, cb;
+        rot_coeffs(B2, gdt, k2, ca, cb);
+        const double c0 = fma(-cb, B2, 1.0);
+        const double qx = cb * bx, qy = cb * by, qz = cb * bz;
+        const double pxy = qx * by, pxz = qx * bz, pyz = qy * bz;
+        const double sx = ca * bx, sy = ca * by, sz = ca * bz;
+        Aff64 U;
+        U.a[0] = fma(qx, bx, c0);
+        U.a[1] = pxy - sz;
+        U.a[2] = pxz + sy;
+        U.a[3] = pxy + sz;
+        U.a[4] = fma(qy, by, c0);
+        U.a[5] = pyz - sx;
+        U.a[6] = pxz - sy;
+        U.a[7] = pyz + sx;
+        U.a[8] = fma(qz, bz, c0);
+        U.b[0] = U.b[1] = U.b[2] = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {  // Eq. A1
             U.a[c] *= e2;
