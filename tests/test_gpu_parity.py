@@ -82,6 +82,27 @@ def test_epi_small(gb):
     check_case(gb, "epi-small", ph, seq)
 
 
+def test_rotation_series_branches(gb):
+    """Raster-step rotations from 0 to about 1.5 rad within every wavefront.
+    The rotation coefficients switch per isochromat between a six-term series
+    (under a quarter radian), a ten-term series (up to one radian) and sqrt
+    plus sincos beyond; a strong Gx on x in [-0.1, 0.1] m at dt = 10 us puts
+    consecutive isochromats, and so every wavefront, on all three, in an RF
+    block (B1 and Gx) and in a readout (Gx alone)."""
+    ph = synth.gre_phantom(64, 8, 2, seed=23)  # x fastest: a wavefront spans the field of view
+    dt = 1e-5
+    g = 1.5 / (2 * np.pi * synth.GAMMA_BAR * dt * 0.1)  # 1.5 rad per step at |x| = 0.1 m
+    n_rf, n_ro = 200, 256
+    b1 = (np.pi / 2) / (2 * np.pi * synth.GAMMA_BAR * n_rf * dt)  # 90 degrees with no gradient
+    sb = synth.SeqBuilder(dt, name="series-branches")
+    sb.rf(np.full(n_rf, b1, dtype=np.complex128) * np.exp(0.3j), g=(g, 0.0, 0.0))
+    sb.relax(2e-3, moment=(-g * n_rf * dt / 2, 0.0, 0.0))
+    sb.adc(n_ro, (g, 0.0, 0.0), np.arange(0, n_ro, 4))
+    sb.relax(5e-3)
+    seq = sb.build()
+    check_case(gb, "series-branches", ph, seq, modes=("plain", "grouped", "cached"))
+
+
 def test_ragged_k_and_initial_state(gb):
     ph = synth.gre_phantom(33, 31, 3, seed=21)  # K = 3069: not a multiple of 4 or of a tile
     seq = synth.gre_sequence(n_lines=3, n_read=24, dwell_steps=4, rf_steps=600, te=2.5e-3, tr=7e-3)
