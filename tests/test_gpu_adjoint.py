@@ -19,6 +19,8 @@ six-class phantom (1,048,576 isochromats).  Checks:
   small value keeps only the absolute accuracy of its terms).  Differences
   of FP32 forward passes cannot serve: their rounding noise at this step is
   several per cent;
+* the three branches of the rotation series (five terms, nine terms, sqrt
+  and sincos) inside every wavefront, against the oracle adjoint;
 * the torch.autograd.Function wrapper returns exactly the C ABI's gradient;
 * the checkpoint interval (256, 16, 8) does not change the result.
 """
@@ -98,6 +100,49 @@ def test_subset_vs_oracle_gradient(env, n_lines):
     r2 = float(np.max(np.abs(g2 - g2_o)[present] / np.abs(g2_o[present])))
     say(f"[gpu] adjoint vs oracle: signal rel {r_sig:.2e}; dL/dB1 rel L2 {r_rf:.2e}; "
         f"dL/dT1 max rel {r1:.2e}; dL/dT2 max rel {r2:.2e}")
+    assert r_sig <= 1e-4
+    assert r_rf <= 1e-4 and r1 <= 5e-4 and r2 <= 5e-4
+
+
+def test_adjoint_series_branches(env):
+    """The adjoint's rotation coefficients switch per isochromat between a
+    five-term series (q < 1/16), a nine-term series (q < 4) and sqrt plus
+    sincos.  Each TR excites with the parameter pulse (no gradient), then plays
+    a weak RF under a strong Gx with x the fastest phantom index, so that
+    every wavefront has raster steps on all three branches: 0.1 rad per step
+    at |x| = 4 mm up to 3.1 rad at the edge (MR raster steps rotate by far
+    less).  A relaxation block rephases the Gx moment, so the echo and its
+    gradients stay large.  Against the FP64 oracle adjoint: signal and RF
+    gradient within 1e-4, T1 and T2 derivatives within 5e-4 (relative L2 over
+    the classes)."""
+    gb, torch = env[0], env[1]
+    ph = synth.ellipse_phantom(32, 32, 2, (0.256, 0.256, 0.010), synth.SIX_T1, synth.SIX_T2, synth.SIX_PD,
+                               df_range=50.0, df_levels=8, seed=77, name="adjoint-branches")
+    dt, n_rf, n_g = 1e-5, 400, 200
+    g = 0.1 / (2 * np.pi * synth.GAMMA_BAR * dt * 0.004)
+    rf = synth.sinc_pulse(n_rf, dt, np.deg2rad(30.0), 4.0).astype(np.complex128) * np.exp(0.4j)
+    weak = np.full(n_g, 2e-8 + 1e-8j)
+    sb = synth.SeqBuilder(dt, name="adjoint-branches")
+    for _ in range(2):
+        sb.rf(rf)
+        sb.rf(weak, g=(g, 0.0, 0.0))
+        sb.relax(1e-3, moment=(-g * n_g * dt, 0.0, 0.0))
+        sb.adc(64, (2e-3, 0.0, 0.0), np.arange(0, 64, 2))
+        sb.relax(5e-3)
+    seq = sb.build()
+    pb = np.nonzero(np.asarray(seq.btype) == synth.BLOCK_RF)[0][::2].astype(np.int32)  # the excitations
+    t1c, t2c = np.array(synth.SIX_T1), np.array(synth.SIX_T2)
+    rng = np.random.default_rng(13)
+    w = rng.standard_normal(seq.total_samples) + 1j * rng.standard_normal(seq.total_samples)
+    say(f"[gpu] adjoint: series branches, K={ph.K}, {seq.stepped_count()} stepped steps")
+    sim, adj = make(gb, torch, ph, seq, pb)
+    sig, g_rf, g1, g2 = run(adj, torch, rf, t1c, t2c, w)
+    sim.close()
+    rf32 = rf.real.astype(np.float32) + 1j * rf.imag.astype(np.float32)
+    s_o, g_o, g1_o, g2_o = oracle.adjoint(ph, ph.labels, np.float32(t1c), np.float32(t2c), seq, rf32, pb, w)
+    r_sig, r_rf, r1, r2 = rel(sig, s_o), rel(g_rf, g_o), rel(g1, g1_o), rel(g2, g2_o)
+    say(f"[gpu] adjoint, series branches: signal rel {r_sig:.2e}; dL/dB1 rel L2 {r_rf:.2e}; "
+        f"dL/dT1 rel L2 {r1:.2e}; dL/dT2 rel L2 {r2:.2e}")
     assert r_sig <= 1e-4
     assert r_rf <= 1e-4 and r1 <= 5e-4 and r2 <= 5e-4
 
