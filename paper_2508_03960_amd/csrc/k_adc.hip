@@ -5,33 +5,87 @@
 //     e^{-tau_n/T2} e^{-i phi_g(n)} = f_g z_g^n,
 //     phi_g(n) = 2 pi (cyc_n x_g + df_g tau_n),
 // so a thread evaluates f_g z_g^{n0} directly (FP64 phase reduced modulo one
-// turn, hardware sin/cos) and steps 15 further samples by complex
-// multiplication with z_g.  Thread layout: 16 consecutive samples per thread
-// ("chunk"), threads with the same chunk split the workgroup's groups
-// ("slices"); slice partials are combined in LDS, one FP64 atomic pair per
-// sample and workgroup.  A thread adds its groups' terms (at most
-// kAdcLinGroups / slices, 64 for a 256-sample readout) in FP32, the terms
-// themselves being FP32 products; the slices, workgroups and samples are
-// combined in FP64.
+// turn, hardware sin/cos), steps 15 further samples by complex multiplication
+// with z_g, restarts at n0 + 16 from f_g z_g^{n0} times z_g^16 (itself made
+// directly, not by repeated products) and steps 15 more.  The FP32 rounding
+// of z_g thus compounds over at most 15 products.
+// The workgroup first stages what its groups need in LDS: coordinate, df and
+// the group sum, and z_g, z_g^16 and 1/T2, made once per group.  The group
+// loop then touches no global memory, so its pace does not depend on the
+// memory latency (the final-state gather runs beside it).
+// Thread layout: 32 consecutive samples per thread ("chunk"), threads with the
+// same chunk split the workgroup's groups ("slices").  A thread adds its
+// groups' terms (at most kAdcLinGroups / slices, 28 for a 256-sample
+// readout) in FP32, the terms themselves being FP32 products; the eight
+// slices of a wavefront that share a chunk add in FP32 through lane shuffles;
+// those sums go through LDS, and the workgroup's rows and the workgroups add
+// in FP64 (one FP64 atomic pair per sample and workgroup).
 #include "adc.hpp"
 #include "device_math.hpp"
 
 namespace gbs {
 
 constexpr int kAdcLinWG = 256;
-constexpr int kAdcLinChunk = 16;      // samples per thread
-constexpr int kAdcLinGroups = 1024;   // groups per workgroup
+constexpr int kAdcLinChunk = 32;      // samples per thread
+constexpr int kAdcLinGroups = 896;    // groups per workgroup: 40 KiB of LDS, 4 workgroups per CU
+constexpr int kAdcLinHalf = kAdcLinChunk / 2;
+
+// Group-table rows and group sums through the global address space (the
+// pointers come out of the job descriptor and would otherwise be flat loads).
+typedef const __attribute__((address_space(1))) float *adc_gf32;
+typedef const __attribute__((address_space(1))) double *adc_gf64;
+__device__ __forceinline__ float4 adc_row(const float4 *tab, int g) {
+    adc_gf32 p = (adc_gf32)(tab + g);
+    return make_float4(p[0], p[1], p[2], p[3]);
+}
+__device__ __forceinline__ double2 adc_sum(const double2 *gs, int g) {
+    adc_gf64 p = (adc_gf64)(gs + g);
+    return make_double2(p[0], p[1]);
+}
 
 __global__ __launch_bounds__(kAdcLinWG) void k_adc_lin(const AdcLinJob *__restrict__ jobs, double *__restrict__ sig_base) {
-    // [slice][sample] for the lower half of the slices (32 KiB): the upper
-    // half adds into it, so that the LDS allows 4 workgroups per CU
-    __shared__ double2 red[kAdcLinWG * kAdcLinChunk / 2];
+    // [slice / 8][sample]: the eight-slice sums (8 KiB); per group of the
+    // workgroup (coord, df, Re S, Im S), (z, z^16) and 1/T2 (31.5 KiB)
+    __shared__ float2 red[kAdcLinWG * kAdcLinChunk / 8];
+    __shared__ float4 ga[kAdcLinGroups];
+    __shared__ float4 gb[kAdcLinGroups];
+    __shared__ float gr[kAdcLinGroups];
     const AdcLinJob j = jobs[blockIdx.y];
     const int g0 = blockIdx.x * kAdcLinGroups;
     if (g0 >= j.n_groups) return;  // uniform over the workgroup
-    const int g1 = min(g0 + kAdcLinGroups, j.n_groups);
+    const int ng = min(kAdcLinGroups, j.n_groups - g0);
     double *sig = sig_base + 2 * j.sig_offset;
-    // chunks per pass: power of two covering the samples, at most 16
+    // all loads first (indices clamped into the workgroup's groups), then the
+    // arithmetic and the LDS writes of the groups that exist
+    constexpr int kRounds = (kAdcLinGroups + kAdcLinWG - 1) / kAdcLinWG;
+    float4 pr[kRounds];
+    double2 Sr[kRounds];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int i = min((int)threadIdx.x + r * kAdcLinWG, ng - 1);
+        pr[r] = adc_row(j.gtab, g0 + i);  // (coord, T1, T2, df)
+        Sr[r] = adc_sum(j.gsum, g0 + i);
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const int i = threadIdx.x + r * kAdcLinWG;
+        if (i < ng) {
+            const float4 p = pr[r];
+            const double2 S = Sr[r];
+            const double dphi = j.dcyc * (double)p.x + (double)p.w * j.dtau;  // turns per sample
+            float sd, cd, sh, ch;
+            sincos_rev(dphi, &sd, &cd);
+            sincos_rev(kAdcLinHalf * dphi, &sh, &ch);
+            const float r2 = __builtin_amdgcn_rcpf(p.z);
+            const float ed = __expf(-(float)j.dtau * r2), eh = __expf(-(float)(kAdcLinHalf * j.dtau) * r2);
+            ga[i] = make_float4(p.x, p.w, (float)S.x, (float)S.y);
+            gb[i] = make_float4(ed * cd, -ed * sd, eh * ch, -eh * sh);  // z = ed e^{-i dphi}, z^16
+            gr[i] = r2;
+        }
+    }
+    __syncthreads();
+    // chunks per pass: power of two covering the samples, at most 8, so
+    // that 8 slices sharing a chunk sit in one wavefront
     int n_chunks = 1;
     while (n_chunks < kAdcLinWG / kAdcLinChunk && n_chunks * kAdcLinChunk < j.n_samples) n_chunks <<= 1;
     const int n_slices = kAdcLinWG / n_chunks;
@@ -41,62 +95,82 @@ __global__ __launch_bounds__(kAdcLinWG) void k_adc_lin(const AdcLinJob *__restri
         const int n0 = base + chunk * kAdcLinChunk;
         const int cnt = max(0, min(kAdcLinChunk, j.n_samples - n0));
         const double tau_n0 = j.tau0 + n0 * j.dtau, cyc_n0 = j.cyc0 + n0 * j.dcyc;
+        const float mtau_n0 = -(float)tau_n0;
         float ar[kAdcLinChunk], ai[kAdcLinChunk];
 #pragma unroll
         for (int k = 0; k < kAdcLinChunk; ++k) ar[k] = ai[k] = 0.f;
-        if (cnt > 0 && g0 + slice < g1) {
-            // the next group's table row and sum are loaded one iteration ahead
-            float4 p_next = j.gtab[g0 + slice];  // (coord, T1, T2, df)
-            double2 S_next = j.gsum[g0 + slice];
-            for (int g = g0 + slice; g < g1; g += n_slices) {
-                const float4 p = p_next;
-                const double2 S = S_next;
-                if (g + n_slices < g1) {
-                    p_next = j.gtab[g + n_slices];
-                    S_next = j.gsum[g + n_slices];
+        if (cnt > 0 && slice < ng) {
+            // the next group's rows are read one iteration ahead
+            float4 a_next = ga[slice], b_next = gb[slice];
+            float r2_next = gr[slice];
+            for (int i = slice; i < ng; i += n_slices) {
+                const float4 a = a_next, b = b_next;
+                const float r2 = r2_next;
+                if (i + n_slices < ng) {
+                    a_next = ga[i + n_slices];
+                    b_next = gb[i + n_slices];
+                    r2_next = gr[i + n_slices];
                 }
-                float s0, c0, sd, cd;
-                sincos_rev(cyc_n0 * (double)p.x + (double)p.w * tau_n0, &s0, &c0);
-                sincos_rev(j.dcyc * (double)p.x + (double)p.w * j.dtau, &sd, &cd);
-                const float r2 = __builtin_amdgcn_rcpf(p.z);
-                const float e0 = __expf(-(float)tau_n0 * r2), ed = __expf(-(float)j.dtau * r2);
-                // f = S e0 e^{-i phi(n0)},  z = ed e^{-i dphi}
+                float s0, c0;
+                sincos_rev(cyc_n0 * (double)a.x + (double)a.y * tau_n0, &s0, &c0);
+                const float e0 = __expf(mtau_n0 * r2);
+                // f = S e0 e^{-i phi(n0)}
                 const float tr = e0 * c0, ti = -e0 * s0;
-                float fr = (float)S.x * tr - (float)S.y * ti;
-                float fi = (float)S.x * ti + (float)S.y * tr;
-                const float zr = ed * cd, zi = -ed * sd;
+                const float f0r = a.z * tr - a.w * ti;
+                const float f0i = a.z * ti + a.w * tr;
+                float fr = f0r, fi = f0i;
 #pragma unroll
-                for (int k = 0; k < kAdcLinChunk; ++k) {
+                for (int k = 0; k < kAdcLinHalf; ++k) {
                     ar[k] += fr;
                     ai[k] += fi;
-                    const float nr = fr * zr - fi * zi;
-                    fi = fr * zi + fi * zr;
+                    const float nr = fr * b.x - fi * b.y;
+                    fi = fr * b.y + fi * b.x;
+                    fr = nr;
+                }
+                fr = f0r * b.z - f0i * b.w;  // f_g z_g^{n0 + 16}: f_g z_g^{n0} times z_g^16
+                fi = f0r * b.w + f0i * b.z;
+#pragma unroll
+                for (int k = kAdcLinHalf; k < kAdcLinChunk; ++k) {
+                    ar[k] += fr;
+                    ai[k] += fi;
+                    const float nr = fr * b.x - fi * b.y;
+                    fi = fr * b.y + fi * b.x;
                     fr = nr;
                 }
             }
         }
-        const int half = n_slices / 2;
-        double2 *mine = red + (slice % half) * per_pass + chunk * kAdcLinChunk;
-        if (slice < half) {
+        // lanes l ^ (m n_chunks), m < 8: one chunk, eight slices of a
+        // wavefront; the slices that are multiples of 8 then hold the sums and
+        // write them, one row each.  Four samples at a time: the scheduling
+        // barrier keeps the compiler from putting every shuffle in flight at
+        // once, which would take as many registers again as the sums.
+        const int rows = n_slices / 8;
+        const bool leader = slice % 8 == 0;
+        float2 *mine = red + (slice / 8) * per_pass + chunk * kAdcLinChunk;
 #pragma unroll
-            for (int k = 0; k < kAdcLinChunk; ++k) mine[k] = make_double2((double)ar[k], (double)ai[k]);
-        }
-        __syncthreads();
-        if (slice >= half) {  // each slot has exactly one adding thread
+        for (int k0 = 0; k0 < kAdcLinChunk; k0 += 4) {
 #pragma unroll
-            for (int k = 0; k < kAdcLinChunk; ++k) {
-                const double2 v = mine[k];
-                mine[k] = make_double2(v.x + (double)ar[k], v.y + (double)ai[k]);
+            for (int m = 1; m < 8; m <<= 1) {
+#pragma unroll
+                for (int k = k0; k < k0 + 4; ++k) {
+                    ar[k] += __shfl_xor(ar[k], m * n_chunks);
+                    ai[k] += __shfl_xor(ai[k], m * n_chunks);
+                }
             }
+            if (leader) {
+#pragma unroll
+                for (int k = k0; k < k0 + 4; ++k) mine[k] = make_float2(ar[k], ai[k]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
         for (int n = threadIdx.x; n < per_pass; n += kAdcLinWG) {
             if (base + n < j.n_samples) {
                 double sr = 0.0, si = 0.0;
-                for (int sl = 0; sl < half; ++sl) {
-                    const double2 v = red[sl * per_pass + n];
-                    sr += v.x;
-                    si += v.y;
+                for (int r = 0; r < rows; ++r) {
+                    const float2 v = red[r * per_pass + n];
+                    sr += (double)v.x;
+                    si += (double)v.y;
                 }
                 atomicAdd(&sig[2 * (base + n)], sr);
                 atomicAdd(&sig[2 * (base + n) + 1], si);

@@ -16,7 +16,7 @@
 //              FP64 atomics.
 //  k_adc_eval  every ADC sample from the group sums (Eq. 8 with Eq. 10), FP64
 //              phase reduced modulo one turn, FP64 accumulation.
-//  k_init_state, k_gather_state4, k_gather_state
+//  k_init_state, k_gather_state4, k_gather_state4x4, k_gather_state
 //              the state into the group-sorted layout (when the first sweep
 //              does not start it from (0, 0, M0) itself) and back into the
 //              caller's order (from the last sweep's 16-byte rows, or from the
@@ -1281,13 +1281,37 @@ __global__ __launch_bounds__(256) void k_gather_state4(int64_t K, int64_t per_xc
     }
 }
 
+// Four caller indices per thread: one 16-byte index load, four independent
+// row gathers in flight, 16-byte stores.  Needs K % 4 == 0 and 16-byte
+// aligned planes.
+__global__ __launch_bounds__(256) void k_gather_state4x4(int64_t K4, int64_t per_xcd, const int4 *__restrict__ inv4,
+                                                        const float4 *__restrict__ m4, float4 *ox, float4 *oy,
+                                                        float4 *oz) {
+    const int64_t b = (int64_t)(blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;  // logical block
+    const int64_t k = b * 256 + threadIdx.x;
+    if (k < K4) {
+        const int4 r = inv4[k];
+        const float4 a = m4[r.x], c = m4[r.y], d = m4[r.z], e = m4[r.w];
+        ox[k] = make_float4(a.x, c.x, d.x, e.x);
+        oy[k] = make_float4(a.y, c.y, d.y, e.y);
+        oz[k] = make_float4(a.z, c.z, d.z, e.z);
+    }
+}
+
 hipError_t launch_gather_state4(int64_t K, const int32_t *inv, const float4 *m4, float *ox, float *oy, float *oz,
                                 hipStream_t st) {
-    const int64_t g = (K + 255) / 256;  // logical blocks, one index per thread
+    const bool by4 = K % 4 == 0 && ((uintptr_t)ox | (uintptr_t)inv) % 16 == 0;  // oy, oz = ox + K, + 2K
+    const int64_t n = by4 ? K / 4 : K;   // threads
+    const int64_t g = (n + 255) / 256;   // logical blocks
     const int64_t per = (g + kXcds - 1) / kXcds;
     if (kXcds * per > 0x7fffffff) return hipErrorInvalidValue;
     if (g == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_state4, dim3((unsigned)(kXcds * per)), dim3(256), 0, st, K, per, inv, m4, ox, oy, oz);
+    if (by4)
+        hipLaunchKernelGGL(k_gather_state4x4, dim3((unsigned)(kXcds * per)), dim3(256), 0, st, n, per,
+                           (const int4 *)inv, m4, (float4 *)ox, (float4 *)oy, (float4 *)oz);
+    else
+        hipLaunchKernelGGL(k_gather_state4, dim3((unsigned)(kXcds * per)), dim3(256), 0, st, K, per, inv, m4, ox, oy,
+                           oz);
     return hipGetLastError();
 }
 
