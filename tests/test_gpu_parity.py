@@ -103,6 +103,34 @@ def test_rotation_series_branches(gb):
     check_case(gb, "series-branches", ph, seq, modes=("plain", "grouped", "cached"))
 
 
+def test_adc_lin_passes_and_tails(gb):
+    """Readouts at constant Gx with contiguous samples go to the
+    geometric-sequence ADC evaluation (Eq. 10 with f_g z_g^n).  Its layout
+    splits on the sample count: 600 samples take three passes of 256, and 1,
+    15, 17 and 33 samples end inside a 32-sample chunk, before and after the
+    restart of the recursion at the chunk's sixteenth sample.  The phantom has
+    3895 x-groups, so each readout spans four full workgroups of groups and a
+    ragged fifth.  One dwell per raster step, with the readout gradient giving
+    up to half a turn per sample at the edge of the field of view."""
+    ph = synth.ellipse_phantom(256, 8, 2, (0.256, 0.256, 0.01), synth.SIX_T1, synth.SIX_T2, synth.SIX_PD,
+                               df_range=100.0, df_levels=64, seed=5, name="adc-lin")
+    keys = np.stack([ph.x, ph.t1, ph.t2, ph.df], 1)
+    assert len(np.unique(keys, axis=0)) == 3895
+    dt = 1e-5
+    g_ro = synth.readout_gradient(dt, 0.256)
+    sb = SeqBuilder(dt, name="adc-lin")
+    sb.rf(synth.sinc_pulse(200, dt, np.deg2rad(90.0), 4.0).astype(np.complex128) * np.exp(0.2j))
+    lengths = (600, 1, 15, 17, 33)
+    for n in lengths:
+        sb.relax(2e-4, moment=(-g_ro * n * dt / 2, 0.0, 0.0))
+        sb.adc(n, (g_ro, 0.0, 0.0), np.arange(n))
+        sb.relax(2e-4, moment=(-g_ro * n * dt / 2, 0.0, 0.0))
+    seq = sb.build()
+    plan = gb.gbs_plan_summary(seq)
+    assert plan["adc_grouped"] == len(lengths) and plan["fallback"] == 0, plan
+    check_case(gb, "adc-lin", ph, seq, modes=("grouped",))
+
+
 def test_ragged_k_and_initial_state(gb):
     ph = synth.gre_phantom(33, 31, 3, seed=21)  # K = 3069: not a multiple of 4 or of a tile
     seq = synth.gre_sequence(n_lines=3, n_read=24, dwell_steps=4, rf_steps=600, te=2.5e-3, tr=7e-3)
