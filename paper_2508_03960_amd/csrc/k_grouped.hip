@@ -919,15 +919,16 @@ __device__ __forceinline__ void emit_sweep_body(const SweepArgs &a) {
     int gx = 0, gz = 0, gx0 = 0;
     bool gx_uni = true;
     const int64_t wave_id = blk * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // slots 512 wave_id ..
+    // the x- and z-group factor rows of an emission
+    auto emit_rows = [&](const SweepOp &op, float4 &xv, float2 &zf) {
+        xv = x_row(op.emit_xtab, gx_uni, gx0, gx);
+        zf = op.emit_ztab ? gather_row(op.emit_ztab, gz) : make_float2(1.f, 0.f);
+    };
     // one emission from the thread's sum (pr, pi) of M_c w_c: x- and z-group
-    // factors, then the group sums
-    auto emit_sum = [&](const SweepOp &op, float pr, float pi) {
-        const float4 xv = x_row(op.emit_xtab, gx_uni, gx0, gx);
+    // factors (rows already loaded), then the group sums
+    auto emit_sum_rows = [&](const SweepOp &op, const float4 &xv, const float2 &zf, float pr, float pi) {
         float er = xv.x, ei = xv.y;
-        if (op.emit_ztab) {
-            const float2 zf = gather_row(op.emit_ztab, gz);
-            cmul(er, ei, zf.x, zf.y);
-        }
+        if (op.emit_ztab) cmul(er, ei, zf.x, zf.y);
         const float sr = er * pr - ei * pi, si = er * pi + ei * pr;
         if (op.emit_axis == 0 && (need & kPartials))
             emit_thread_part(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.part + wave_id, op.gsum);
@@ -935,6 +936,12 @@ __device__ __forceinline__ void emit_sweep_body(const SweepArgs &a) {
             emit_thread(gx_uni ? gx0 : gx, gx_uni, sr, si, act, op.gsum);
         else
             emit_thread(gz, false, sr, si, act, op.gsum);
+    };
+    auto emit_sum = [&](const SweepOp &op, float pr, float pi) {
+        float4 xv;
+        float2 zf;
+        emit_rows(op, xv, zf);
+        emit_sum_rows(op, xv, zf, pr, pi);
     };
     {
         float mx[NI], my[NI];
@@ -1064,12 +1071,26 @@ __device__ __forceinline__ void emit_sweep_body(const SweepArgs &a) {
                 ri[c] = -sn;
             }
         }
-        const int steps = (op.flags >> kChainShift) & kChainMask;
-        for (int j = 0; j < steps && o < n_emit; ++j) {
-            const SweepOp sop = load_op(a.ops, o++);
+        // the evenly stepped emissions of the chain, software-pipelined: the
+        // next op's descriptor is loaded before this emission's arithmetic and
+        // its factor rows right after this emission, so neither latency sits
+        // in front of the work that needs it (indices are clamped into the
+        // segment; the loads past the chain's end are never used)
+        const int steps = min((op.flags >> kChainShift) & kChainMask, n_emit - o);
+        if (steps > 0) {
+            SweepOp sop = load_op(a.ops, o);
+            float4 xv;
+            float2 zf;
+            emit_rows(sop, xv, zf);
+            for (int j = 0; j < steps; ++j) {
+                const SweepOp nxt = load_op(a.ops, min(o + 1, n_emit - 1));
 #pragma unroll
-            for (int c = 0; c < NI; ++c) cmul_inplace(zr[c], zi[c], rr[c], ri[c]);
-            emit(sop);
+                for (int c = 0; c < NI; ++c) cmul_inplace(zr[c], zi[c], rr[c], ri[c]);
+                emit_sum_rows(sop, xv, zf, tree_sum<NI>(zr), tree_sum<NI>(zi));
+                ++o;
+                emit_rows(nxt, xv, zf);
+                sop = nxt;
+            }
         }
     }
     if (!act || !a.write_m) return;
