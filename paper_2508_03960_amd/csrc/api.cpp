@@ -1458,7 +1458,13 @@ static int run_grouped(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out
     ctx->partial = g.w_partial ? (double2 *)(ws + g.w_partial) : nullptr;
 
     // ---- prepare: combined transitions (Eq. 7) and map tables --------------
-    HIPCHK(launch_fill_f64((double *)(ws + g.w_gsum), 2 * (int64_t)g.gsum_count, ctx->stream));
+    // The compositions and folds run on this stream.  The group sums' clearing
+    // and the map tables (which depend on the group table alone) run beside
+    // them on the side stream, which first waits for everything enqueued here
+    // before this point (a previous call's sweeps read the same buffers).  The
+    // side stream's kernels are submitted after the compositions, so that the
+    // compositions' few workgroups are placed first.
+    HIPCHK(hipEventRecord(ctx->fork, ctx->stream));
     if (surr) {
         // network transitions for every z group, exact ones for the checked groups,
         // then exact for all groups only if the check failed (gated on the device)
@@ -1479,6 +1485,11 @@ static int run_grouped(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out
     }
     HIPCHK(launch_compose((const RfJobDev *)(jb + (surr ? g.o_rf_surr : g.o_rf)), g.n_rf, g.max_rf_groups, s.dt,
                           ctx->stream));
+    HIPCHK(hipStreamWaitEvent(ctx->side, ctx->fork, 0));
+    HIPCHK(launch_fill_f64((double *)(ws + g.w_gsum), 2 * (int64_t)g.gsum_count, ctx->side));
+    HIPCHK(launch_tables((const TabJob *)(jb + g.o_tab), g.n_tab, (int)g.max_tab, ctx->gtab[0].as<float4>(),
+                         zbuilt ? ctx->gtab[2].as<float4>() : nullptr, ctx->side));
+    HIPCHK(hipEventRecord(ctx->join, ctx->side));
     for (const auto &pj : g.pair_jobs) {
         const RfJob &r = plan.rf[pj.second];
         HIPCHK(launch_compose_pair(ctx->n_runs, ctx->rtab.as<float4>(), ctx->rz.as<float>(),
@@ -1489,8 +1500,7 @@ static int run_grouped(gbs_ctx *ctx, char *ws, const float *m_init, float *m_out
         HIPCHK(launch_expand_rows((const double *)(tb + e.first), ctx->tmap.as<int32_t>(), ctx->ng[0],
                                   (double *)(tb + e.second), ctx->stream));
     HIPCHK(launch_fold((const FoldJob *)(jb + g.o_fold), g.n_fold, g.max_fold_groups, ctx->stream));
-    HIPCHK(launch_tables((const TabJob *)(jb + g.o_tab), g.n_tab, (int)g.max_tab, ctx->gtab[0].as<float4>(),
-                         zbuilt ? ctx->gtab[2].as<float4>() : nullptr, ctx->stream));
+    HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->join, 0));  // cleared group sums, map tables
     if (st) HIPCHK(hipEventRecord(ctx->ev[1], ctx->stream));
 
     // ---- sweeps of grouped ops (plain stepping between them) ----------------

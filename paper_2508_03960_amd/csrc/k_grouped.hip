@@ -29,6 +29,7 @@ namespace gbs {
 
 // ---------------------------------------------------------------- k_compose
 constexpr int kComposeGroupsPerWG = 4;
+typedef const __attribute__((address_space(1))) float *compose_gf32;
 
 struct Aff {
     double a[9];  // row-major 3x3
@@ -65,15 +66,18 @@ __global__ __launch_bounds__(256) void k_compose(const RfJobDev *__restrict__ jo
     const double gdt = kTwoPi * kGammaBar * dt, k2 = gdt * gdt;
     const int n = j.n_steps;
     const int lo = (int)(((int64_t)n * lane) >> 6), hi = (int)(((int64_t)n * (lane + 1)) >> 6);
-    Aff T;
-    aff_identity(T);
-    for (int s = lo; s < hi; ++s) {
-        const StepW w = j.wave[s];
-        const double gv = j.axis == 0 ? w.gx : (j.axis == 1 ? w.gy : w.gz);
-        const double bx = w.b1r, by = w.b1i, bz = gv * coord + boff;
-        // U = D R (Eq. A1, Eq. A2) with R = (1 - cb |B|^2) I + ca [B]x + cb B B^T,
-        // ca = sin(theta) / |B| and cb = (1 - cos theta) / |B|^2 from their series
-        // (no square root or division; B = 0 gives the identity)
+    // (B1 re, B1 im, gradient on the job's axis) of step s, through the
+    // global address space, the index clamped into the waveform
+    const int gcol = 3 + j.axis;  // gx, gy, gz follow b1r, b1i, b1sq in StepW
+    auto step_in = [&](int s) {
+        const compose_gf32 w = (compose_gf32)(j.wave + min(s, n - 1));
+        return make_float3(w[0], w[1], w[gcol]);
+    };
+    // U = D R (Eq. A1, Eq. A2) with R = (1 - cb |B|^2) I + ca [B]x + cb B B^T,
+    // ca = sin(theta) / |B| and cb = (1 - cos theta) / |B|^2 from their series
+    // (no square root or division; B = 0 gives the identity)
+    auto step_u = [&](const float3 &w, Aff &U) {
+        const double bx = w.x, by = w.y, bz = (double)w.z * coord + boff;
         const double B2 = fma(bx, bx, fma(by, by, bz * bz));
         double ca, cb;
         rot_coeffs(B2, gdt, k2, ca, cb);
@@ -81,27 +85,50 @@ __global__ __launch_bounds__(256) void k_compose(const RfJobDev *__restrict__ jo
         const double qx = cb * bx, qy = cb * by, qz = cb * bz;
         const double pxy = qx * by, pxz = qx * bz, pyz = qy * bz;
         const double sx = ca * bx, sy = ca * by, sz = ca * bz;
-        Aff U;
-        U.a[0] = fma(qx, bx, c0);
-        U.a[1] = pxy - sz;
-        U.a[2] = pxz + sy;
-        U.a[3] = pxy + sz;
-        U.a[4] = fma(qy, by, c0);
-        U.a[5] = pyz - sx;
-        U.a[6] = pxz - sy;
-        U.a[7] = pyz + sx;
-        U.a[8] = fma(qz, bz, c0);
-        U.b[0] = U.b[1] = U.b[2] = 0.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            U.a[c] *= e2;
-            U.a[3 + c] *= e2;
-            U.a[6 + c] *= e1;
-        }
+        U.a[0] = fma(qx, bx, c0) * e2;
+        U.a[1] = (pxy - sz) * e2;
+        U.a[2] = (pxz + sy) * e2;
+        U.a[3] = (pxy + sz) * e2;
+        U.a[4] = fma(qy, by, c0) * e2;
+        U.a[5] = (pyz - sx) * e2;
+        U.a[6] = (pxz - sy) * e1;
+        U.a[7] = (pyz + sx) * e1;
+        U.a[8] = fma(qz, bz, c0) * e1;
+        U.b[0] = U.b[1] = 0.0;
         U.b[2] = 1.0 - e1;
-        Aff Tn;
-        aff_compose(U, T, Tn);
-        T = Tn;
+    };
+    // The lane's steps in fours: each of w0..w3 is consumed, then reloaded
+    // four steps ahead, so no register holding a load in flight is copied
+    // (a copy would wait for it); the running product alternates between T
+    // and T2 for the same reason.
+    Aff T, T2, U;
+    aff_identity(T);
+    float3 w0, w1, w2, w3;
+    if (lo < hi) {
+        w0 = step_in(lo);
+        w1 = step_in(lo + 1);
+        w2 = step_in(lo + 2);
+        w3 = step_in(lo + 3);
+    }
+    int s = lo;
+    for (; s + 4 <= hi; s += 4) {
+        step_u(w0, U);
+        w0 = step_in(s + 4);
+        aff_compose(U, T, T2);
+        step_u(w1, U);
+        w1 = step_in(s + 5);
+        aff_compose(U, T2, T);
+        step_u(w2, U);
+        w2 = step_in(s + 6);
+        aff_compose(U, T, T2);
+        step_u(w3, U);
+        w3 = step_in(s + 7);
+        aff_compose(U, T2, T);
+    }
+    for (int k = 0; s < hi; ++s, ++k) {  // the last one to three steps
+        step_u(k == 0 ? w0 : (k == 1 ? w1 : w2), U);
+        aff_compose(U, T, T2);
+        T = T2;
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i) lds[wave][lane][i] = T.a[i];
