@@ -847,19 +847,21 @@ static int build_grouped_plan(gbs_ctx *ctx) {
             g.expand.emplace_back(comp_off[i], g.rf_off[i]);
         }
     }
+    // Map-factor tables.  Ops whose factors have the same kind, duration and
+    // moment (the echoes and shots of a repeated timing) share one table:
+    // equal inputs give equal entries.  (`out` holds the arena offset until
+    // the offsets are made workspace-relative below.)
     std::vector<TabJob> tjobs;
-    auto x_table = [&](int kind, double tau, double cyc) {
+    auto table = [&](int kind, int64_t n, double tau, double cyc, size_t row_bytes) {
+        for (const TabJob &t : tjobs)
+            if (t.kind == kind && t.n == (int32_t)n && t.tau == tau && t.cyc == cyc) return (size_t)t.out;
         const size_t o = off;
-        off = align256(off + sizeof(float4) * (size_t)Gx);
-        tjobs.push_back(TabJob{kind, (int32_t)Gx, tau, cyc, (void *)o});
+        off = align256(off + row_bytes * (size_t)n);
+        tjobs.push_back(TabJob{kind, (int32_t)n, tau, cyc, (void *)o});
         return o;
     };
-    auto z_table = [&](double cyc) {
-        const size_t o = off;
-        off = align256(off + sizeof(float2) * (size_t)Gz);
-        tjobs.push_back(TabJob{1, (int32_t)Gz, 0.0, cyc, (void *)o});
-        return o;
-    };
+    auto x_table = [&](int kind, double tau, double cyc) { return table(kind, Gx, tau, cyc, sizeof(float4)); };
+    auto z_table = [&](double cyc) { return table(1, Gz, 0.0, cyc, sizeof(float2)); };
     struct FoldPlan {
         size_t out_off;
         int axis, rf_id, has_pre;
