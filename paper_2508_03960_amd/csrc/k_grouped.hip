@@ -1364,36 +1364,57 @@ hipError_t launch_gather_state4(int64_t K, const int32_t *inv, const float4 *m4,
 }
 
 // gsum[g] += sum of the partial entries of the wavefronts that span x-group g
-// (kPartials), one thread per group and emission, FP64 sums.  A wavefront's
-// entry holds its first key's sum in (x, y) and its other key's in (z, w).
-// Every wavefront after the first of the group starts inside the group, so
-// g is its first key; the first one has g first only if g starts at the
-// wavefront's first slot.
-__global__ __launch_bounds__(256) void k_part_reduce(const PartJob *__restrict__ jobs, int64_t n_groups,
+// (kPartials), one thread per group and kPartJobsPerThread emissions, FP64
+// sums.  A wavefront's entry holds its first key's sum in (x, y) and its other
+// key's in (z, w).  Every wavefront after the first of the group starts
+// inside the group, so g is its first key; the first one has g first only if
+// g starts at the wavefront's first slot.  The group's bounds are read once;
+// the emissions' first entries are all loaded before any is added (job
+// indices clamped into the launch; a clamped duplicate is never written back).
+constexpr int kPartJobsPerThread = 4;
+typedef const __attribute__((address_space(1))) float4 *part_gptr;
+typedef __attribute__((address_space(1))) double2 *gsum_gptr;
+
+__global__ __launch_bounds__(256) void k_part_reduce(const PartJob *__restrict__ jobs, int n_jobs, int64_t n_groups,
                                                     const int32_t *__restrict__ xstart) {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g >= n_groups) return;
-    const PartJob j = jobs[blockIdx.y];
     const int64_t s0 = xstart[g];
     const int64_t w0 = s0 / kPartSlots, w1 = (xstart[g + 1] - 1) / kPartSlots;
-    const float4 v0 = j.part[w0];
     const bool head = s0 % kPartSlots == 0;
-    double sr = head ? v0.x : v0.z, si = head ? v0.y : v0.w;
-    for (int64_t w = w0 + 1; w <= w1; ++w) {
-        const float4 v = j.part[w];
-        sr += v.x;
-        si += v.y;
+    const int j0 = blockIdx.y * kPartJobsPerThread;
+    part_gptr part[kPartJobsPerThread];
+    float4 v0[kPartJobsPerThread];
+#pragma unroll
+    for (int q = 0; q < kPartJobsPerThread; ++q) {
+        part[q] = (part_gptr)jobs[min(j0 + q, n_jobs - 1)].part;
+        v0[q] = part[q][w0];
     }
-    j.gsum[g].x += sr;
-    j.gsum[g].y += si;
+#pragma unroll
+    for (int q = 0; q < kPartJobsPerThread; ++q) {
+        double sr = head ? v0[q].x : v0[q].z, si = head ? v0[q].y : v0[q].w;
+        for (int64_t w = w0 + 1; w <= w1; ++w) {
+            const float4 v = part[q][w];
+            sr += v.x;
+            si += v.y;
+        }
+        if (j0 + q < n_jobs) {
+            gsum_gptr gs = (gsum_gptr)jobs[j0 + q].gsum + g;
+            double2 t = *gs;
+            t.x += sr;
+            t.y += si;
+            *gs = t;
+        }
+    }
 }
 
 hipError_t launch_part_reduce(const PartJob *jobs, int n_jobs, int64_t n_groups, const int32_t *xstart,
                               hipStream_t st) {
     if (n_jobs <= 0 || n_groups <= 0) return hipSuccess;
-    if (n_jobs > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_part_reduce, dim3((unsigned)((n_groups + 255) / 256), (unsigned)n_jobs), dim3(256), 0, st,
-                       jobs, n_groups, xstart);
+    const int gy = (n_jobs + kPartJobsPerThread - 1) / kPartJobsPerThread;
+    if (gy > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_part_reduce, dim3((unsigned)((n_groups + 255) / 256), (unsigned)gy), dim3(256), 0, st, jobs,
+                       n_jobs, n_groups, xstart);
     return hipGetLastError();
 }
 
